@@ -1,0 +1,191 @@
+/*
+ * tlda.h -- C ABI of the MI355X (gfx950) online tensor-LDA hot path.
+ *
+ * The method (arXiv 2511.07809, "Scalable Tensor LDA") streams batches of
+ * bag-of-words documents through
+ *   1. the first moment M1 and the centred second moment M2~ (section
+ *      "Computing the Centered Cumulants"),
+ *   2. a whitening matrix W with W^T M2~ W = I (section "Online Decomposition
+ *      of the Second Moment"),
+ *   3. the centred, whitened batch X = (F_B - 1 M1^T) W, and
+ *   4. a stochastic gradient step on the CP factors Phi of the whitened third
+ *      moment, eq. vec_deriv, without forming any D x D x D or V x V x V tensor
+ *      (section "Online Learning of the Third Moment"),
+ * and finally unwhitens and re-centres the factors into topics (section
+ * "Recovering the Topic Model Parameters", Theorem 1).
+ *
+ * Conventions for every call
+ *  - Every function returns a tlda_status; nothing throws, aborts or prints.
+ *    tlda_last_error() returns a message for the last failed call on a context.
+ *  - Argument and shape errors are detected on the host before any work is
+ *    enqueued, so a failed call leaves the context unchanged.
+ *  - Device pointers are HIP device (HBM) addresses; host pointers are plain
+ *    process memory.  The caller owns every pointer it passes; the library keeps
+ *    none of them after the call returns.  The context owns its own device
+ *    state (moment accumulators, W, scratch).
+ *  - Work is enqueued on the context's HIP stream (given at creation) and is
+ *    asynchronous unless a call says otherwise: outputs are valid once that
+ *    stream has been synchronised.
+ *  - Arrays are row-major.  A context is not thread-safe: use one per stream.
+ *  - Documents with fewer than three tokens are dropped (the paper's
+ *    pre-processing rule): they are not counted in N, contribute nothing to the
+ *    moments, and their rows of a whitened batch are written as zeros.
+ *  - The frequency vector of a document is f = c / L, its counts over its
+ *    length L (the paper's notation table).
+ */
+#ifndef TLDA_H
+#define TLDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tlda_ctx tlda_ctx;
+
+typedef enum {
+  TLDA_OK = 0,
+  TLDA_ERR_ARG = 1,      /* a NULL pointer, a bad flag or an out-of-range scalar   */
+  TLDA_ERR_SHAPE = 2,    /* sizes that do not fit the context's V, K, D or limits  */
+  TLDA_ERR_CSR = 3,      /* CSR content rejected by validation                     */
+  TLDA_ERR_STATE = 4,    /* call order: e.g. whitening before any W exists         */
+  TLDA_ERR_NUMERIC = 5,  /* M2~ has fewer than D positive eigenvalues, N == 0 ...  */
+  TLDA_ERR_OOM = 6,      /* device allocation failed                               */
+  TLDA_ERR_DEVICE = 7    /* a HIP runtime error                                    */
+} tlda_status;
+
+/* Limits of this build. */
+#define TLDA_MAX_D 256
+#define TLDA_MAX_K 256
+#define TLDA_MAX_DK 16384   /* D * K: Phi must fit in a 64 KiB LDS tile */
+
+/* tlda_config.flags */
+#define TLDA_VALIDATE_CSR 0x1u  /* check every batch's CSR content (synchronous) */
+
+typedef struct {
+  int32_t V;            /* vocabulary size, 3 <= V <= 131072                       */
+  int32_t K;            /* number of topics, 1 <= K <= TLDA_MAX_K                   */
+  int32_t D;            /* whitening size, 1 <= D <= min(V, TLDA_MAX_D), D*K bound  */
+  int32_t flags;        /* TLDA_VALIDATE_CSR                                       */
+  double alpha0;        /* topic mixing parameter, > 0                             */
+  double theta;         /* orthogonality penalty of eq. full_vec_pb, >= 0          */
+  int32_t eig_iters;    /* subspace iterations of a refresh, 0 = default (60)      */
+  int32_t eig_block;    /* subspace width p >= D, 0 = default                      */
+  uint64_t eig_seed;    /* seed of the refresh's start block                       */
+} tlda_config;
+
+/* One CSR batch of documents (rows) over the vocabulary (columns).  Counts are
+ * positive integer-valued floats <= 2^24; column indices are strictly
+ * increasing within a row.  row_ptr[0] == 0, row_ptr[n_rows] == nnz.
+ * slot < 0: the arrays are caller-owned device memory.  slot >= 0: the arrays
+ * are a staging slot filled by tlda_stage_batch; consuming calls then wait for
+ * that copy and release the slot when their work is done. */
+typedef struct {
+  int32_t n_rows;
+  int32_t nnz;
+  const int32_t* row_ptr;   /* [n_rows + 1] */
+  const int32_t* col_idx;   /* [nnz]        */
+  const float* val;         /* [nnz]        */
+  int32_t slot;
+} tlda_csr_batch;
+
+/* Create a context whose work runs on `hip_stream` (a hipStream_t; NULL = the
+ * null stream).  Validates the configuration (TLDA_ERR_ARG / TLDA_ERR_SHAPE).
+ * Device memory for the second moment (V*V doubles) is allocated on the first
+ * tlda_update_moments call. */
+tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out);
+void tlda_destroy(tlda_ctx* ctx);
+const char* tlda_status_str(tlda_status s);
+const char* tlda_last_error(const tlda_ctx* ctx);
+
+/* tlda_update_moments flags */
+#define TLDA_REFRESH_W 0x1u   /* after accumulating, recompute M1, M2~ and W       */
+#define TLDA_RESET 0x2u       /* clear the accumulators before accumulating        */
+
+/* Section "Computing the Centered Cumulants" and the batched implementation:
+ * accumulates, over the kept documents of `batch` (may be NULL when only
+ * refreshing), the document count N, the dropped-document count, exact int64
+ * token totals per word, sum f (FP64) and the upper triangle of sum f f^T
+ * (FP64).  With TLDA_REFRESH_W it then forms M1 = sum f / N and
+ * M2~ = (alpha0 + 1)(sum f f^T / N - M1 M1^T) and recomputes
+ * W = U diag(lambda)^(-1/2) from the top-D eigenpairs of M2~ by FP64 block
+ * subspace iteration with Rayleigh-Ritz (section "Online Decomposition of the
+ * Second Moment": W^T M2~ W = I).  Eigenvectors are ordered by decreasing
+ * eigenvalue and signed so that their largest-magnitude entry is positive.
+ * A refresh synchronises the stream; it returns TLDA_ERR_NUMERIC if N == 0 or
+ * the D-th eigenvalue is not positive (the previous W is then kept).
+ * Accumulation uses FP64 atomics: sums are exact up to FP64 rounding order. */
+tlda_status tlda_update_moments(tlda_ctx* ctx, const tlda_csr_batch* batch, uint32_t flags);
+
+/* Whitened counts of the centred data (online second-moment section):
+ * X[d, :] = W^T (f_d - M1) for kept rows, 0 for dropped rows.
+ * X: device float [n_rows][D].  n_kept: device int32 (may be NULL) that
+ * receives the number of kept rows of the batch (overwritten, not added).
+ * Requires a W (TLDA_ERR_STATE otherwise). */
+tlda_status tlda_whiten_batch(tlda_ctx* ctx, const tlda_csr_batch* batch, float* X, int32_t* n_kept);
+
+/* Batched stochastic tensor gradient step, eq. vec_deriv and the update rule:
+ *   G = 3(1+theta) Phi (Phi^T Phi * Phi^T Phi)
+ *       - 3 (alpha0+1)(alpha0+2) / (2 n) X^T (X Phi * X Phi)
+ *   Phi <- Phi - beta G
+ * X: device float [n_rows][D] (dropped rows are zero and add nothing).
+ * n_kept: device int32 with the batch's kept-row count n (as written by
+ * tlda_whiten_batch), or NULL for n = n_rows.  When n == 0 the step is skipped.
+ * Phi: device float [D][K], updated in place.  grad: device float [D][K] or
+ * NULL.  The reduction order is fixed: results are bit-reproducible. */
+tlda_status tlda_cp_step(tlda_ctx* ctx, const float* X, int32_t n_rows, const int32_t* n_kept,
+                         float beta, float* Phi, float* grad);
+
+/* tlda_unwhiten flags */
+#define TLDA_PROJECT_SIMPLEX 0x1u  /* clip negative entries of mu and renormalise */
+
+/* Section "Recovering the Topic Model Parameters" with Theorem 1, in this
+ * reading for centred moments: E[M2~] = sum a_i nu_i nu_i^T with
+ * sum a_i nu_i = 0 makes the whitened factors a tight frame,
+ * a_i |W^T nu_i|^2 = 1 - a_i.  With w_i = (1+theta)^(1/3) phi_i, a_i is the
+ * root in (0, 1] of a^(1/3) |w_i|^2 + a = 1, nu_i = (W^T)^+ a_i^(-1/3) w_i,
+ * mu_i = nu_i + M1, alpha_i = a_i / sum_j a_j.
+ * Phi: device float [D][K].  mu: device double [V][K].  alpha: device double
+ * [K].  lambda: device double [K] or NULL, receives (1+theta)|phi_i|^3. */
+tlda_status tlda_unwhiten(tlda_ctx* ctx, const float* Phi, double* mu, double* alpha,
+                          double* lambda, uint32_t flags);
+
+/* Document-topic proportions (the package's document-topic output), as the
+ * minimiser over the probability simplex of |x_d - A theta|^2 with
+ * A = W^T (mu - M1 1^T): projected gradient from theta = 1/K with step
+ * 1 / lambda_max(A^T A), at most max_iter steps, stopping early when the L1
+ * change of an iterate is below tol (tol = 0: exactly max_iter steps).
+ * X: device float [n_rows][D] from tlda_whiten_batch.  mu: device double
+ * [V][K].  theta_out: device float [n_rows][K], rows on the simplex. */
+tlda_status tlda_infer_doc_topics(tlda_ctx* ctx, const float* X, int32_t n_rows, const double* mu,
+                                  int32_t max_iter, float tol, float* theta_out);
+
+/* Streaming (batched implementation over data larger than device memory):
+ * copy a CSR batch from pinned host memory (hipHostMalloc) into staging slot
+ * `slot` (0 or 1) on the context's copy stream and return a device view of it
+ * in *dev_out (dev_out->slot == slot).  The copy waits until every earlier
+ * consumer of that slot has finished, and consumers of *dev_out wait for the
+ * copy, so staging batch i+1 before consuming batch i overlaps the copy with
+ * compute.  Slots grow on demand (TLDA_ERR_OOM on failure). */
+tlda_status tlda_stage_batch(tlda_ctx* ctx, const tlda_csr_batch* host_batch, int32_t slot,
+                             tlda_csr_batch* dev_out);
+
+/* Inspection and test hooks (all synchronous). */
+/* N, dropped documents and the int64 token totals [V] (token_totals may be NULL). */
+tlda_status tlda_get_stats(tlda_ctx* ctx, int64_t* N, int64_t* n_skipped, int64_t* token_totals);
+/* Host copies: W [V][D], eigenvalues [D], M1 [V]; any may be NULL. */
+tlda_status tlda_get_whitening(tlda_ctx* ctx, double* W, double* eig, double* M1);
+/* Install a whitening matrix W [V][D] (mutually orthogonal columns, as any
+ * U diag(lambda)^(-1/2) has) and M1 [V] from host memory, e.g. computed by an
+ * independent implementation; the eigenvalues are taken as 1/|w_d|^2. */
+tlda_status tlda_set_whitening(tlda_ctx* ctx, const double* W, const double* M1);
+/* Checkpoint of the moment state and W.  buf == NULL: *len receives the size. */
+tlda_status tlda_save_state(tlda_ctx* ctx, void* buf, size_t* len);
+tlda_status tlda_load_state(tlda_ctx* ctx, const void* buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TLDA_H */

@@ -1,0 +1,482 @@
+// FP64 building blocks of the whitening refresh: the top-D eigenpairs of
+// M2~ = (alpha0 + 1)(S2 / N - M1 M1^T) by block subspace iteration with
+// Cholesky-QR orthonormalisation and a final Rayleigh-Ritz step solved by
+// parallel-order cyclic Jacobi (section "Online Decomposition of the Second
+// Moment": W = U diag(lambda)^(-1/2) so that W^T M2~ W = I).
+#include "tlda_internal.h"
+
+namespace tlda {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Dense FP64 GEMM: C = alpha * op(A) * B (+ C when accumulating through
+// atomics for split-K).  op(A) is A (M x Kd, row-major, lda) or A^T where A is
+// stored Kd x M.  B is Kd x N row-major (ldb), C is M x N row-major (ldc).
+// 64 x 64 output tile per 256-thread block, 4 x 4 register tile per thread,
+// K step 16 staged through LDS.  grid.z splits Kd into chunks of k_chunk
+// rows; with more than one chunk the tile is added to C with FP64 atomics.
+// ---------------------------------------------------------------------------
+template <bool TRANS_A>
+__global__ void __launch_bounds__(256) k_gemm64(int M, int N, int Kd, const double* __restrict__ A,
+                                                int lda, const double* __restrict__ B, int ldb,
+                                                double* __restrict__ C, int ldc, double alpha,
+                                                int k_chunk, int atomic_out) {
+  __shared__ double As[16][64 + 2];
+  __shared__ double Bs[16][64 + 2];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
+  const int kbeg = blockIdx.z * k_chunk;
+  const int kend = min(Kd, kbeg + k_chunk);
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
+    // A tile: 64 rows x 16 k  ->  As[k][row]
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * 256;
+      int r, kk;
+      if (TRANS_A) { kk = idx >> 6; r = idx & 63; }   // consecutive threads along M
+      else { r = idx >> 4; kk = idx & 15; }           // consecutive threads along K
+      const int gr = row0 + r, gk = k0 + kk;
+      double v = 0.0;
+      if (gr < M && gk < kend) v = TRANS_A ? A[(size_t)gk * lda + gr] : A[(size_t)gr * lda + gk];
+      As[kk][r] = v;
+    }
+    // B tile: 16 k x 64 cols
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx >> 6, c = idx & 63;
+      const int gk = k0 + kk, gc = col0 + c;
+      Bs[kk][c] = (gk < kend && gc < N) ? B[(size_t)gk * ldb + gc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int gr = row0 + ty + 16 * i;
+    if (gr >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gc = col0 + tx + 16 * j;
+      if (gc >= N) continue;
+      if (atomic_out) unsafeAtomicAdd(&C[(size_t)gr * ldc + gc], alpha * acc[i][j]);
+      else C[(size_t)gr * ldc + gc] = alpha * acc[i][j];
+    }
+  }
+}
+
+hipError_t gemm(bool transA, int M, int N, int Kd, const double* A, int lda, const double* B,
+                int ldb, double* C, int ldc, double alpha, int splits, hipStream_t s) {
+  if (splits < 1) splits = 1;
+  int chunk = (Kd + splits - 1) / splits;
+  chunk = (chunk + 15) / 16 * 16;
+  splits = (Kd + chunk - 1) / chunk;
+  dim3 grid((N + 63) / 64, (M + 63) / 64, splits);
+  const int atomic_out = splits > 1 ? 1 : 0;
+  if (atomic_out) {
+    hipError_t e = launch_zero(C, (size_t)M * ldc * sizeof(double), s);
+    if (e != hipSuccess) return e;
+  }
+  if (transA)
+    hipLaunchKernelGGL(k_gemm64<true>, grid, dim3(256), 0, s, M, N, Kd, A, lda, B, ldb, C, ldc,
+                       alpha, chunk, atomic_out);
+  else
+    hipLaunchKernelGGL(k_gemm64<false>, grid, dim3(256), 0, s, M, N, Kd, A, lda, B, ldb, C, ldc,
+                       alpha, chunk, atomic_out);
+  return hipGetLastError();
+}
+
+// splitmix64 (Steele, Lea & Flood 2014) as a counter-based generator for the
+// refresh's start block: entry (i, c) is uniform in [-1, 1).
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__global__ void k_random_block(double* __restrict__ Q, int V, int p, uint64_t seed) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)V * p) return;
+  const uint64_t r = splitmix64(seed * 0x100000001B3ull + idx);
+  Q[idx] = (double)(r >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+}
+
+// Y[i][c] -= scale_m * m[i] * t[c]   (the -M1 M1^T part of M2~ applied to Q)
+__global__ void k_rank1_update(double* __restrict__ Y, const double* __restrict__ m,
+                               const double* __restrict__ t, int V, int p, double scale_m) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)V * p) return;
+  const int i = (int)(idx / p), c = (int)(idx % p);
+  Y[idx] -= scale_m * m[i] * t[c];
+}
+
+// Right-looking Cholesky of the p x p matrix G + shift * max(diag) * I in
+// place (lower triangle); one block.  info[0] != 0 on a non-positive pivot.
+__global__ void __launch_bounds__(1024) k_cholesky(double* __restrict__ G, int p, double shift_rel,
+                                                   int* __restrict__ info) {
+  __shared__ double sh_shift;
+  __shared__ int sh_fail;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < p; ++i) mx = fmax(mx, G[(size_t)i * p + i]);
+    sh_shift = shift_rel * mx;
+    sh_fail = 0;
+  }
+  __syncthreads();
+  for (int i = tid; i < p; i += nt) G[(size_t)i * p + i] += sh_shift;
+  __threadfence_block();
+  __syncthreads();
+  for (int j = 0; j < p; ++j) {
+    if (tid == 0) {
+      const double d = G[(size_t)j * p + j];
+      if (!(d > 0.0)) {
+        sh_fail = 1;
+        G[(size_t)j * p + j] = 1.0;
+      } else {
+        G[(size_t)j * p + j] = sqrt(d);
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    const double djj = G[(size_t)j * p + j];
+    for (int i = j + 1 + tid; i < p; i += nt) G[(size_t)i * p + j] /= djj;
+    __threadfence_block();
+    __syncthreads();
+    const int rem = p - j - 1;
+    for (int idx = tid; idx < rem * rem; idx += nt) {
+      const int i = j + 1 + idx / rem, k = j + 1 + idx % rem;
+      if (k <= i) G[(size_t)i * p + k] -= G[(size_t)i * p + j] * G[(size_t)k * p + j];
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  if (tid == 0 && sh_fail) atomicOr(info, 1);
+}
+
+// Binv = (L^-1)^T for the lower-triangular L held in G; thread c solves
+// L x = e_c by forward substitution and stores x as row c of Binv.
+__global__ void __launch_bounds__(256) k_tri_inverse_t(const double* __restrict__ G, int p,
+                                                       double* __restrict__ Binv) {
+  for (int c = threadIdx.x; c < p; c += blockDim.x) {
+    double* x = Binv + (size_t)c * p;
+    for (int i = 0; i < p; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= G[(size_t)i * p + k] * x[k];
+      x[i] = (i < c) ? 0.0 : s / G[(size_t)i * p + i];
+    }
+  }
+}
+
+// Cyclic Jacobi with the round-robin parallel ordering: in each round the
+// m/2 disjoint pairs (circle method) are rotated at once, so every pair of
+// indices is visited once per sweep.  A (p x p, symmetric) is diagonalised in
+// place; Z accumulates the rotations; ev receives the diagonal.
+__global__ void __launch_bounds__(1024) k_jacobi(double* __restrict__ A, double* __restrict__ Z,
+                                                 double* __restrict__ ev, int p,
+                                                 int* __restrict__ info) {
+  extern __shared__ double sh[];   // c[m/2], s[m/2], then reduction scratch
+  __shared__ int sh_done;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int m = (p + 1) & ~1;
+  const int half = m / 2;
+  double* cs = sh;
+  double* sn = sh + half;
+  int* pi = reinterpret_cast<int*>(sh + 2 * half);
+  int* pj = pi + half;
+  double* red = sh + 3 * half;     // nt doubles
+  for (int idx = tid; idx < p * p; idx += nt) Z[idx] = (idx / p == idx % p) ? 1.0 : 0.0;
+  __threadfence_block();
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    // convergence test: off-diagonal mass against total mass
+    double off = 0.0, tot = 0.0;
+    for (int idx = tid; idx < p * p; idx += nt) {
+      const double v = A[idx];
+      tot += v * v;
+      if (idx / p != idx % p) off += v * v;
+    }
+    red[tid] = off;
+    red[nt + tid] = tot;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        red[tid] += red[tid + w];
+        red[nt + tid] += red[nt + tid + w];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) sh_done = (red[0] <= 1e-30 * red[nt] || red[nt] == 0.0) ? 1 : 0;
+    __syncthreads();
+    if (sh_done) break;
+    for (int r = 0; r < m - 1; ++r) {
+      for (int k = tid; k < half; k += nt) {
+        int i, j;
+        if (k == 0) { i = 0; j = 1 + r; }
+        else {
+          i = 1 + (r + k) % (m - 1);
+          j = 1 + (r - k + (m - 1)) % (m - 1);
+        }
+        if (i > j) { const int t = i; i = j; j = t; }
+        double c = 1.0, s = 0.0;
+        if (j < p) {
+          const double aij = A[(size_t)i * p + j];
+          if (aij != 0.0) {
+            const double tau = (A[(size_t)j * p + j] - A[(size_t)i * p + i]) / (2.0 * aij);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        pi[k] = i;
+        pj[k] = j;
+        cs[k] = c;
+        sn[k] = s;
+      }
+      __syncthreads();
+      // columns i, j of A and Z
+      for (int idx = tid; idx < half * p; idx += nt) {
+        const int k = idx / p, row = idx % p;
+        const int i = pi[k], j = pj[k];
+        if (j >= p) continue;
+        const double c = cs[k], s = sn[k];
+        const double ai = A[(size_t)row * p + i], aj = A[(size_t)row * p + j];
+        A[(size_t)row * p + i] = c * ai - s * aj;
+        A[(size_t)row * p + j] = s * ai + c * aj;
+        const double zi = Z[(size_t)row * p + i], zj = Z[(size_t)row * p + j];
+        Z[(size_t)row * p + i] = c * zi - s * zj;
+        Z[(size_t)row * p + j] = s * zi + c * zj;
+      }
+      __threadfence_block();
+      __syncthreads();
+      // rows i, j of A
+      for (int idx = tid; idx < half * p; idx += nt) {
+        const int k = idx / p, col = idx % p;
+        const int i = pi[k], j = pj[k];
+        if (j >= p) continue;
+        const double c = cs[k], s = sn[k];
+        const double ai = A[(size_t)i * p + col], aj = A[(size_t)j * p + col];
+        A[(size_t)i * p + col] = c * ai - s * aj;
+        A[(size_t)j * p + col] = s * ai + c * aj;
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+    if (sweep == 39 && tid == 0) atomicOr(info, 2);
+  }
+  for (int i = tid; i < p; i += nt) ev[i] = A[(size_t)i * p + i];
+}
+
+// Sorts the Ritz values in decreasing order (ties: lower index first), keeps
+// the top D, and gathers the matching eigenvector columns into Zs [p][D].
+__global__ void __launch_bounds__(256) k_select_top(const double* __restrict__ Z,
+                                                    const double* __restrict__ ev, int p, int D,
+                                                    double* __restrict__ Zs,
+                                                    double* __restrict__ eigD) {
+  for (int c = threadIdx.x; c < p; c += blockDim.x) {
+    int rank = 0;
+    const double v = ev[c];
+    for (int k = 0; k < p; ++k) {
+      const double w = ev[k];
+      if (w > v || (w == v && k < c)) ++rank;
+    }
+    if (rank < D) {
+      eigD[rank] = v;
+      for (int r = 0; r < p; ++r) Zs[(size_t)r * D + rank] = Z[(size_t)r * p + c];
+    }
+  }
+}
+
+// Sign rule: the entry of largest magnitude of every column of U (V x D) is
+// made positive (lowest row index on ties).  One block per column.
+__global__ void __launch_bounds__(256) k_sign_fix(double* __restrict__ U, int V, int D) {
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  const int col = blockIdx.x, tid = threadIdx.x;
+  double best = -1.0;
+  int besti = V;
+  for (int i = tid; i < V; i += blockDim.x) {
+    const double a = fabs(U[(size_t)i * D + col]);
+    if (a > best) { best = a; besti = i; }
+  }
+  bv[tid] = best;
+  bi[tid] = besti;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      if (bv[tid + w] > bv[tid] || (bv[tid + w] == bv[tid] && bi[tid + w] < bi[tid])) {
+        bv[tid] = bv[tid + w];
+        bi[tid] = bi[tid + w];
+      }
+    }
+    __syncthreads();
+  }
+  const bool flip = bi[0] < V && U[(size_t)bi[0] * D + col] < 0.0;
+  __syncthreads();
+  if (flip)
+    for (int i = tid; i < V; i += blockDim.x) U[(size_t)i * D + col] = -U[(size_t)i * D + col];
+}
+
+// W = U diag(eig)^(-1/2) in FP64 and its FP32 copy with row stride Dp (zero
+// padding beyond D).
+__global__ void k_form_w(const double* __restrict__ U, const double* __restrict__ eig, int V, int D,
+                         int Dp, double* __restrict__ W, float* __restrict__ W32) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)V * Dp) return;
+  const int i = (int)(idx / Dp), d = (int)(idx % Dp);
+  if (d < D) {
+    const double w = U[(size_t)i * D + d] / sqrt(eig[d]);
+    W[(size_t)i * D + d] = w;
+    W32[idx] = (float)w;
+  } else {
+    W32[idx] = 0.0f;
+  }
+}
+
+// mw32[d] = sum_i W[i][d] m[i] (FP64 sum, one block per column); padding zero.
+__global__ void __launch_bounds__(256) k_mw(const double* __restrict__ W, const double* __restrict__ m,
+                                            int V, int D, int Dp, float* __restrict__ mw32) {
+  __shared__ double red[256];
+  const int d = blockIdx.x, tid = threadIdx.x;
+  if (d >= D) {
+    if (tid == 0) mw32[d] = 0.0f;
+    return;
+  }
+  double s = 0.0;
+  for (int i = tid; i < V; i += blockDim.x) s += W[(size_t)i * D + d] * m[i];
+  red[tid] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) mw32[d] = (float)red[0];
+}
+
+// For an injected W: eig[d] = 1 / |w_d|^2 and U = W diag(eig)^(1/2).
+__global__ void __launch_bounds__(256) k_from_injected(const double* __restrict__ W, int V, int D,
+                                                       double* __restrict__ U,
+                                                       double* __restrict__ eig) {
+  __shared__ double red[256];
+  const int d = blockIdx.x, tid = threadIdx.x;
+  double s = 0.0;
+  for (int i = tid; i < V; i += blockDim.x) {
+    const double w = W[(size_t)i * D + d];
+    s += w * w;
+  }
+  red[tid] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const double nrm2 = red[0];
+  if (tid == 0) eig[d] = nrm2 > 0.0 ? 1.0 / nrm2 : 0.0;
+  const double sc = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+  for (int i = tid; i < V; i += blockDim.x) U[(size_t)i * D + d] = W[(size_t)i * D + d] * sc;
+}
+
+inline int blocks_for(size_t n, int bs) { return (int)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_random_block(double* Q, int V, int p, uint64_t seed, hipStream_t s) {
+  hipLaunchKernelGGL(k_random_block, dim3(blocks_for((size_t)V * p, 256)), dim3(256), 0, s, Q, V,
+                     p, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_vecT_mat(const double* m, const double* Q, double* t, int V, int p,
+                           hipStream_t s) {
+  // t (1 x p) = m^T Q as a GEMM with op(A) = m^T
+  const int splits = (V + 4095) / 4096;
+  return gemm(true, 1, p, V, m, 1, Q, p, t, p, 1.0, splits, s);
+}
+
+hipError_t launch_m2_apply(const double* S2, const double* m, const double* t, const double* Q,
+                           double* Y, int V, int p, double scale_s, double scale_m,
+                           hipStream_t s) {
+  hipError_t e = gemm(false, V, p, V, S2, V, Q, p, Y, p, scale_s, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rank1_update, dim3(blocks_for((size_t)V * p, 256)), dim3(256), 0, s, Y, m,
+                     t, V, p, scale_m);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(const double* A, const double* B, double* G, int V, int p, hipStream_t s) {
+  const int splits = (V + 2047) / 2048;
+  return gemm(true, p, p, V, A, p, B, p, G, p, 1.0, splits, s);
+}
+
+hipError_t launch_cholesky(double* G, int p, double shift_rel, int* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, G, p, shift_rel, info);
+  return hipGetLastError();
+}
+
+// Y (V x p) <- Y L^-T, written to Out; Binv is p x p scratch.
+hipError_t launch_trsm_right_into(const double* Y, const double* G, double* Binv, double* Out, int V,
+                                  int p, hipStream_t s) {
+  hipLaunchKernelGGL(k_tri_inverse_t, dim3(1), dim3(256), 0, s, G, p, Binv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return gemm(false, V, p, p, Y, p, Binv, p, Out, p, 1.0, 1, s);
+}
+
+hipError_t launch_jacobi(double* A, double* Z, double* ev, int p, int* info, hipStream_t s) {
+  const int m = (p + 1) & ~1;
+  const int nt = 1024;
+  const size_t shmem = sizeof(double) * (3 * (m / 2) + 2 * nt) + sizeof(int) * m;
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(nt), shmem, s, A, Z, ev, p, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_ritz_vectors(const double* Q, const double* Z, const double* ev, int V, int p,
+                               int D, double* U, double* eigD, hipStream_t s) {
+  // Zs is placed right after eigD's D entries in caller scratch: eigD [D], Zs [p][D]
+  double* Zs = eigD + D;
+  hipLaunchKernelGGL(k_select_top, dim3(1), dim3(256), 0, s, Z, ev, p, D, Zs, eigD);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = gemm(false, V, D, p, Q, p, Zs, D, U, D, 1.0, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sign_fix, dim3(D), dim3(256), 0, s, U, V, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_form_whitening(const double* U, const double* eig, const double* m, int V, int D,
+                                 int Dp, double* W, float* W32, float* mw32, hipStream_t s) {
+  hipLaunchKernelGGL(k_form_w, dim3(blocks_for((size_t)V * Dp, 256)), dim3(256), 0, s, U, eig, V,
+                     D, Dp, W, W32);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mw, dim3(Dp), dim3(256), 0, s, W, m, V, D, Dp, mw32);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_injected(const double* W, int V, int D, double* U, double* eig,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_from_injected, dim3(D), dim3(256), 0, s, W, V, D, U, eig);
+  return hipGetLastError();
+}
+
+}  // namespace tlda

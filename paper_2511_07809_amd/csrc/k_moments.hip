@@ -1,0 +1,154 @@
+// Moment accumulation: document statistics, sum f and the upper triangle of
+// sum f f^T over the kept documents of a CSR batch (section "Computing the
+// Centered Cumulants"; documents with fewer than three tokens are dropped).
+#include "tlda_internal.h"
+
+namespace tlda {
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ inline long long wave_sum_ll(long long v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ inline int wave_sum_i(int v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Each wave checks one row: bounds of row_ptr, column range and order, and
+// that counts are positive integers <= 2^24.  Any failure sets *err.
+__global__ void __launch_bounds__(256) k_validate_csr(const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col_idx,
+                                                     const float* __restrict__ val, int n_rows,
+                                                     int nnz, int V, int* __restrict__ err) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (row >= n_rows) return;
+  const int b = row_ptr[row], e = row_ptr[row + 1];
+  int bad = 0;
+  if (row == 0 && b != 0) bad = 1;
+  if (row == n_rows - 1 && e != nnz) bad = 1;
+  if (b < 0 || e < b || e > nnz) {
+    bad = 1;
+  } else {
+    for (int j = b + lane; j < e; j += kWave) {
+      const int c = col_idx[j];
+      const float v = val[j];
+      if (c < 0 || c >= V) bad = 1;
+      if (j > b && col_idx[j - 1] >= c) bad = 1;
+      if (!(v >= 1.0f) || v > 16777216.0f || v != rintf(v)) bad = 1;
+    }
+  }
+  if (wave_sum_i(bad) != 0 && lane == 0) atomicOr(err, 1);
+}
+
+// One wave per document.  Integer statistics use 64-bit integer atomics
+// (exact, order-independent); the frequency sums use FP64 atomics.  The pair
+// loop enumerates the upper triangle (j <= k) of the row's nnz positions; as
+// columns are strictly increasing, col_j <= col_k and the pair lands in the
+// upper triangle of S2.
+__global__ void __launch_bounds__(256) k_accumulate(const int32_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col_idx,
+                                                    const float* __restrict__ val, int n_rows,
+                                                    int V, unsigned long long* __restrict__ counts,
+                                                    unsigned long long* __restrict__ totals,
+                                                    double* __restrict__ fsum,
+                                                    double* __restrict__ S2) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (row >= n_rows) return;
+  const int b = row_ptr[row], e = row_ptr[row + 1];
+  const int n = e - b;
+  long long part = 0;
+  for (int j = lane; j < n; j += kWave) part += (long long)val[b + j];
+  const long long L = wave_sum_ll(part);
+  if (L < 3) {
+    if (lane == 0) atomicAdd(&counts[1], 1ull);
+    return;
+  }
+  if (lane == 0) atomicAdd(&counts[0], 1ull);
+  const double invL = 1.0 / (double)L;
+  for (int j = lane; j < n; j += kWave) {
+    const int c = col_idx[b + j];
+    const float v = val[b + j];
+    atomicAdd(&totals[c], (unsigned long long)v);
+    unsafeAtomicAdd(&fsum[c], (double)v * invL);
+  }
+  const long long P = (long long)n * (n + 1) / 2;
+  const double tn = 2.0 * n + 1.0;
+  for (long long p = lane; p < P; p += kWave) {
+    // row j of the packed triangle starts at base(j) = j*n - j*(j-1)/2
+    int j = (int)((tn - sqrt(tn * tn - 8.0 * (double)p)) * 0.5);
+    if (j < 0) j = 0;
+    if (j > n - 1) j = n - 1;
+    while (j + 1 < n && (long long)(j + 1) * n - (long long)(j + 1) * j / 2 <= p) ++j;
+    while (j > 0 && (long long)j * n - (long long)j * (j - 1) / 2 > p) --j;
+    const long long base = (long long)j * n - (long long)j * (j - 1) / 2;
+    const int k = j + (int)(p - base);
+    const int cj = col_idx[b + j], ck = col_idx[b + k];
+    const double fj = (double)val[b + j] * invL, fk = (double)val[b + k] * invL;
+    unsafeAtomicAdd(&S2[(size_t)cj * V + ck], fj * fk);
+  }
+}
+
+// Copies the upper triangle onto the lower one, so S2 is a full symmetric
+// matrix for the eigen-solver's products.  A 32 x 32 tile of the upper
+// triangle is read row-wise into LDS and written transposed, so both the read
+// and the write are coalesced.
+__global__ void __launch_bounds__(256) k_mirror_upper(double* __restrict__ S2, int V) {
+  __shared__ double tile[32][33];
+  const int bi = blockIdx.y, bj = blockIdx.x;     // destination tile (bi, bj), bi >= bj
+  if (bj > bi) return;
+  const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8
+  // source tile (bj, bi) of the upper triangle
+  for (int r = ty; r < 32; r += 8) {
+    const int gi = bj * 32 + r, gj = bi * 32 + tx;
+    tile[r][tx] = (gi < V && gj < V) ? S2[(size_t)gi * V + gj] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int gi = bi * 32 + r, gj = bj * 32 + tx;   // destination (gi, gj), gi > gj
+    if (gi < V && gj < V && gj < gi) S2[(size_t)gi * V + gj] = tile[tx][r];
+  }
+}
+
+__global__ void k_mean(const double* __restrict__ fsum, const unsigned long long* __restrict__ counts,
+                       double* __restrict__ m, int V) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < V) m[i] = fsum[i] / (double)counts[0];
+}
+
+}  // namespace
+
+hipError_t launch_validate_csr(const tlda_csr_batch& b, int V, int* err, hipStream_t s) {
+  const int rows_per_block = 256 / kWave;
+  const int grid = (b.n_rows + rows_per_block - 1) / rows_per_block;
+  hipLaunchKernelGGL(k_validate_csr, dim3(grid), dim3(256), 0, s, b.row_ptr, b.col_idx, b.val,
+                     b.n_rows, b.nnz, V, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const tlda_csr_batch& b, int V, const Moments& m, hipStream_t s) {
+  const int rows_per_block = 256 / kWave;
+  const int grid = (b.n_rows + rows_per_block - 1) / rows_per_block;
+  hipLaunchKernelGGL(k_accumulate, dim3(grid), dim3(256), 0, s, b.row_ptr, b.col_idx, b.val,
+                     b.n_rows, V, m.counts, m.totals, m.fsum, m.S2);
+  return hipGetLastError();
+}
+
+hipError_t launch_mirror_upper(double* S2, int V, hipStream_t s) {
+  const int nt = (V + 31) / 32;
+  hipLaunchKernelGGL(k_mirror_upper, dim3(nt, nt), dim3(32, 8), 0, s, S2, V);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean(const double* fsum, const unsigned long long* counts, double* m, int V,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_mean, dim3((V + 255) / 256), dim3(256), 0, s, fsum, counts, m, V);
+  return hipGetLastError();
+}
+
+}  // namespace tlda

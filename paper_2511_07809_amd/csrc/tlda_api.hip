@@ -1,0 +1,586 @@
+// Host side of the C ABI declared in include/tlda.h: argument checks, device
+// state, stream ordering, the whitening refresh driver and checkpoints.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "tlda_internal.h"
+
+using tlda::launch_zero;
+
+namespace {
+
+struct Fail {
+  tlda_status code;
+};
+
+void set_err(tlda_ctx* c, const std::string& msg) {
+  if (c) c->last_error = msg;
+}
+
+#define HIP_OK(ctx, expr)                                                          \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      set_err(ctx, std::string(#expr) + ": " + hipGetErrorString(e_));             \
+      return e_ == hipErrorOutOfMemory ? TLDA_ERR_OOM : TLDA_ERR_DEVICE;           \
+    }                                                                              \
+  } while (0)
+
+#define CHECK_ARG(ctx, cond, code, msg) \
+  do {                                  \
+    if (!(cond)) {                      \
+      set_err(ctx, msg);                \
+      return code;                      \
+    }                                   \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+int default_block(const tlda_config& c) {
+  int p = 2 * c.D;
+  if (p < c.D + 16) p = c.D + 16;
+  if (p > c.V) p = c.V;
+  return p;
+}
+
+tlda_status check_batch(tlda_ctx* c, const tlda_csr_batch* b) {
+  CHECK_ARG(c, b != nullptr, TLDA_ERR_ARG, "batch is NULL");
+  CHECK_ARG(c, b->n_rows >= 0 && b->nnz >= 0, TLDA_ERR_SHAPE, "negative n_rows or nnz");
+  CHECK_ARG(c, b->slot >= -1 && b->slot <= 1, TLDA_ERR_ARG, "slot must be -1, 0 or 1");
+  if (b->n_rows > 0) CHECK_ARG(c, b->row_ptr != nullptr, TLDA_ERR_ARG, "row_ptr is NULL");
+  if (b->nnz > 0)
+    CHECK_ARG(c, b->col_idx != nullptr && b->val != nullptr, TLDA_ERR_ARG,
+              "col_idx or val is NULL");
+  if (b->slot >= 0) {
+    CHECK_ARG(c, c->slots[b->slot].used, TLDA_ERR_STATE, "staging slot was never filled");
+    CHECK_ARG(c, b->row_ptr == c->slots[b->slot].row_ptr, TLDA_ERR_ARG,
+              "batch does not view its staging slot");
+  }
+  return TLDA_OK;
+}
+
+// Optional CSR content validation: synchronous, before any state changes.
+tlda_status validate_content(tlda_ctx* c, const tlda_csr_batch* b) {
+  if (!(c->cfg.flags & TLDA_VALIDATE_CSR) || b->n_rows == 0) return TLDA_OK;
+  if (b->slot >= 0) HIP_OK(c, hipStreamWaitEvent(c->stream, c->slots[b->slot].ready, 0));
+  HIP_OK(c, launch_zero(c->dev_flags, sizeof(int), c->stream));
+  HIP_OK(c, tlda::launch_validate_csr(*b, c->cfg.V, c->dev_flags, c->stream));
+  int bad = 0;
+  HIP_OK(c, hipMemcpyAsync(&bad, c->dev_flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  CHECK_ARG(c, bad == 0, TLDA_ERR_CSR, "CSR content rejected (row_ptr, column order/range or counts)");
+  return TLDA_OK;
+}
+
+tlda_status begin_use(tlda_ctx* c, const tlda_csr_batch* b) {
+  if (b->slot >= 0) HIP_OK(c, hipStreamWaitEvent(c->stream, c->slots[b->slot].ready, 0));
+  return TLDA_OK;
+}
+
+tlda_status end_use(tlda_ctx* c, const tlda_csr_batch* b) {
+  if (b->slot >= 0) HIP_OK(c, hipEventRecord(c->slots[b->slot].free_, c->stream));
+  return TLDA_OK;
+}
+
+tlda_status ensure_s2(tlda_ctx* c) {
+  if (c->mom.S2) return TLDA_OK;
+  const size_t n = (size_t)c->cfg.V * c->cfg.V;
+  HIP_OK(c, dalloc(&c->mom.S2, n));
+  HIP_OK(c, launch_zero(c->mom.S2, n * sizeof(double), c->stream));
+  return TLDA_OK;
+}
+
+tlda_status ensure_eig(tlda_ctx* c, int p) {
+  tlda::EigScratch& e = c->eig;
+  if (e.p == p && e.Q) return TLDA_OK;
+  dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
+  dfree(e.sel); dfree(e.mcand); dfree(e.info);
+  e.p = 0;
+  const size_t V = c->cfg.V, D = c->cfg.D;
+  HIP_OK(c, dalloc(&e.Q, V * p));
+  HIP_OK(c, dalloc(&e.Y, V * p));
+  HIP_OK(c, dalloc(&e.G, (size_t)p * p));
+  HIP_OK(c, dalloc(&e.Z, (size_t)p * p));
+  HIP_OK(c, dalloc(&e.Binv, (size_t)p * p));
+  HIP_OK(c, dalloc(&e.ev, (size_t)p));
+  HIP_OK(c, dalloc(&e.t, (size_t)p));
+  HIP_OK(c, dalloc(&e.sel, D + (size_t)p * D));
+  HIP_OK(c, dalloc(&e.mcand, V));
+  HIP_OK(c, dalloc(&e.info, 4));
+  e.p = p;
+  return TLDA_OK;
+}
+
+// Two Cholesky-QR passes (the first with a small diagonal shift so that a
+// rank-deficient block still factors): in -> out, using tmp as scratch.
+tlda_status orthonormalise(tlda_ctx* c, const double* in, double* tmp, double* out) {
+  tlda::EigScratch& e = c->eig;
+  const int V = c->cfg.V, p = e.p;
+  HIP_OK(c, tlda::launch_gram(in, in, e.G, V, p, c->stream));
+  HIP_OK(c, tlda::launch_cholesky(e.G, p, 1e-12, e.info, c->stream));
+  HIP_OK(c, tlda::launch_trsm_right_into(in, e.G, e.Binv, tmp, V, p, c->stream));
+  HIP_OK(c, tlda::launch_gram(tmp, tmp, e.G, V, p, c->stream));
+  HIP_OK(c, tlda::launch_cholesky(e.G, p, 0.0, e.info, c->stream));
+  HIP_OK(c, tlda::launch_trsm_right_into(tmp, e.G, e.Binv, out, V, p, c->stream));
+  return TLDA_OK;
+}
+
+// M2~ Q = (alpha0+1)(S2 Q / N - M1 (M1^T Q)) into Y.
+tlda_status apply_m2(tlda_ctx* c, const double* Q, double* Y, double N) {
+  tlda::EigScratch& e = c->eig;
+  const int V = c->cfg.V, p = e.p;
+  const double a1 = c->cfg.alpha0 + 1.0;
+  HIP_OK(c, tlda::launch_vecT_mat(e.mcand, Q, e.t, V, p, c->stream));
+  HIP_OK(c, tlda::launch_m2_apply(c->mom.S2, e.mcand, e.t, Q, Y, V, p, a1 / N, a1, c->stream));
+  return TLDA_OK;
+}
+
+tlda_status refresh(tlda_ctx* c) {
+  const int V = c->cfg.V, D = c->cfg.D;
+  unsigned long long counts[2] = {0, 0};
+  HIP_OK(c, hipMemcpyAsync(counts, c->mom.counts, sizeof(counts), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  CHECK_ARG(c, counts[0] > 0, TLDA_ERR_NUMERIC, "no kept documents: M1 and M2 are undefined");
+  const int p = c->cfg.eig_block > 0 ? c->cfg.eig_block : default_block(c->cfg);
+  const int iters = c->cfg.eig_iters > 0 ? c->cfg.eig_iters : 60;
+  tlda_status st = ensure_eig(c, p);
+  if (st != TLDA_OK) return st;
+  tlda::EigScratch& e = c->eig;
+  const double N = (double)counts[0];
+  HIP_OK(c, launch_zero(e.info, 4 * sizeof(int), c->stream));
+  HIP_OK(c, tlda::launch_mean(c->mom.fsum, c->mom.counts, e.mcand, V, c->stream));
+  HIP_OK(c, tlda::launch_mirror_upper(c->mom.S2, V, c->stream));
+  // start block: seeded uniform entries, orthonormalised (y -> tmp q -> y)
+  double* q = e.Q;
+  double* y = e.Y;
+  HIP_OK(c, tlda::launch_random_block(y, V, p, c->cfg.eig_seed, c->stream));
+  st = orthonormalise(c, y, q, y);
+  if (st != TLDA_OK) return st;
+  std::swap(q, y);   // q: orthonormal block
+  for (int it = 0; it < iters; ++it) {
+    st = apply_m2(c, q, y, N);
+    if (st != TLDA_OK) return st;
+    st = orthonormalise(c, y, q, y);   // y -> tmp q -> y
+    if (st != TLDA_OK) return st;
+    std::swap(q, y);
+  }
+  // Rayleigh-Ritz: H = Q^T M2~ Q, eigenpairs by Jacobi, U = Q Z_top
+  st = apply_m2(c, q, y, N);
+  if (st != TLDA_OK) return st;
+  HIP_OK(c, tlda::launch_gram(q, y, e.G, V, p, c->stream));
+  HIP_OK(c, tlda::launch_jacobi(e.G, e.Z, e.ev, p, e.info, c->stream));
+  HIP_OK(c, tlda::launch_ritz_vectors(q, e.Z, e.ev, V, p, D, y, e.sel, c->stream));
+  int info[4] = {0, 0, 0, 0};
+  std::vector<double> eigD(D);
+  HIP_OK(c, hipMemcpyAsync(info, e.info, sizeof(info), hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipMemcpyAsync(eigD.data(), e.sel, sizeof(double) * D, hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  CHECK_ARG(c, info[0] == 0, TLDA_ERR_NUMERIC, "eigen-solver did not converge or factorisation failed");
+  for (int d = 0; d < D; ++d)
+    CHECK_ARG(c, std::isfinite(eigD[d]) && eigD[d] > 0.0, TLDA_ERR_NUMERIC,
+              "M2~ has fewer than D positive eigenvalues; lower D");
+  // commit
+  HIP_OK(c, hipMemcpyAsync(c->wh.U, y, sizeof(double) * (size_t)V * D, hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->wh.eig, e.sel, sizeof(double) * D, hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->wh.m, e.mcand, sizeof(double) * V, hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(c, tlda::launch_form_whitening(c->wh.U, c->wh.eig, c->wh.m, V, D, c->Dp, c->wh.W,
+                                        c->wh.W32, c->wh.mw32, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  c->wh.ready = true;
+  return TLDA_OK;
+}
+
+void destroy_all(tlda_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  dfree(c->mom.counts); dfree(c->mom.totals); dfree(c->mom.fsum); dfree(c->mom.S2);
+  dfree(c->wh.W); dfree(c->wh.U); dfree(c->wh.eig); dfree(c->wh.m); dfree(c->wh.W32);
+  dfree(c->wh.mw32);
+  tlda::EigScratch& e = c->eig;
+  dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
+  dfree(e.sel); dfree(e.mcand); dfree(e.info);
+  dfree(c->cp.partial); dfree(c->cp.R1); dfree(c->cp.grad);
+  dfree(c->post); dfree(c->postA); dfree(c->postG); dfree(c->postZ); dfree(c->postEv);
+  dfree(c->A32); dfree(c->G32); dfree(c->step32); dfree(c->dev_flags); dfree(c->sync);
+  for (auto& s : c->slots) {
+    if (s.free_) (void)hipEventSynchronize(s.free_);
+    dfree(s.row_ptr); dfree(s.col_idx); dfree(s.val);
+    if (s.ready) (void)hipEventDestroy(s.ready);
+    if (s.free_) (void)hipEventDestroy(s.free_);
+  }
+  if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+  delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tlda_status_str(tlda_status s) {
+  switch (s) {
+    case TLDA_OK: return "ok";
+    case TLDA_ERR_ARG: return "invalid argument";
+    case TLDA_ERR_SHAPE: return "invalid shape";
+    case TLDA_ERR_CSR: return "invalid CSR content";
+    case TLDA_ERR_STATE: return "invalid call order";
+    case TLDA_ERR_NUMERIC: return "numerical failure";
+    case TLDA_ERR_OOM: return "device out of memory";
+    case TLDA_ERR_DEVICE: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* tlda_last_error(const tlda_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out) {
+  if (out == nullptr || cfg == nullptr) return TLDA_ERR_ARG;
+  *out = nullptr;
+  const tlda_config& c = *cfg;
+  if (!(c.alpha0 > 0.0) || !std::isfinite(c.alpha0)) return TLDA_ERR_ARG;
+  if (!(c.theta >= 0.0) || !std::isfinite(c.theta)) return TLDA_ERR_ARG;
+  if (c.flags & ~TLDA_VALIDATE_CSR) return TLDA_ERR_ARG;
+  if (c.eig_iters < 0 || c.eig_block < 0) return TLDA_ERR_ARG;
+  if (c.V < 3 || c.V > 131072) return TLDA_ERR_SHAPE;
+  if (c.K < 1 || c.K > TLDA_MAX_K || c.D < 1 || c.D > TLDA_MAX_D || c.D > c.V) return TLDA_ERR_SHAPE;
+  if (c.D * c.K > TLDA_MAX_DK) return TLDA_ERR_SHAPE;
+  if (((c.D + 3) / 4) * ((c.K + 3) / 4) > 1024 || tlda::cp_tile_rows(c.D, c.K) == 0)
+    return TLDA_ERR_SHAPE;
+  if (c.eig_block != 0 && (c.eig_block < c.D || c.eig_block > c.V)) return TLDA_ERR_SHAPE;
+  tlda_ctx* ctx = new (std::nothrow) tlda_ctx();
+  if (!ctx) return TLDA_ERR_OOM;
+  ctx->cfg = c;
+  ctx->Dp = tlda::padded_d(c.D);
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  auto fail = [&](tlda_status s) {
+    destroy_all(ctx);
+    return s;
+  };
+  if (hipGetDevice(&ctx->device) != hipSuccess) return fail(TLDA_ERR_DEVICE);
+  if (hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) !=
+      hipSuccess)
+    return fail(TLDA_ERR_DEVICE);
+  if (hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(TLDA_ERR_DEVICE);
+  for (auto& s : ctx->slots) {
+    if (hipEventCreateWithFlags(&s.ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s.free_, hipEventDisableTiming) != hipSuccess)
+      return fail(TLDA_ERR_DEVICE);
+  }
+  const size_t V = c.V, D = c.D, K = c.K;
+  bool ok = dalloc(&ctx->mom.counts, 2) == hipSuccess && dalloc(&ctx->mom.totals, V) == hipSuccess &&
+            dalloc(&ctx->mom.fsum, V) == hipSuccess && dalloc(&ctx->wh.W, V * D) == hipSuccess &&
+            dalloc(&ctx->wh.U, V * D) == hipSuccess && dalloc(&ctx->wh.eig, D) == hipSuccess &&
+            dalloc(&ctx->wh.m, V) == hipSuccess &&
+            dalloc(&ctx->wh.W32, V * (size_t)ctx->Dp) == hipSuccess &&
+            dalloc(&ctx->wh.mw32, (size_t)ctx->Dp) == hipSuccess &&
+            dalloc(&ctx->cp.R1, D * K) == hipSuccess &&
+            dalloc(&ctx->cp.grad, D * K) == hipSuccess && dalloc(&ctx->post, K) == hipSuccess &&
+            dalloc(&ctx->postA, D * K) == hipSuccess && dalloc(&ctx->postG, K * K) == hipSuccess &&
+            dalloc(&ctx->postZ, K * K) == hipSuccess && dalloc(&ctx->postEv, K) == hipSuccess &&
+            dalloc(&ctx->A32, D * K) == hipSuccess && dalloc(&ctx->G32, K * K) == hipSuccess &&
+            dalloc(&ctx->step32, 1) == hipSuccess && dalloc(&ctx->dev_flags, 4) == hipSuccess &&
+            dalloc(&ctx->sync, 4) == hipSuccess;
+  if (!ok) return fail(TLDA_ERR_OOM);
+  if (launch_zero(ctx->mom.counts, 2 * sizeof(unsigned long long), ctx->stream) != hipSuccess ||
+      launch_zero(ctx->mom.totals, V * sizeof(unsigned long long), ctx->stream) != hipSuccess ||
+      launch_zero(ctx->mom.fsum, V * sizeof(double), ctx->stream) != hipSuccess ||
+      launch_zero(ctx->sync, 4 * sizeof(int), ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess)
+    return fail(TLDA_ERR_DEVICE);
+  *out = ctx;
+  return TLDA_OK;
+}
+
+void tlda_destroy(tlda_ctx* ctx) { destroy_all(ctx); }
+
+tlda_status tlda_update_moments(tlda_ctx* c, const tlda_csr_batch* b, uint32_t flags) {
+  if (!c) return TLDA_ERR_ARG;
+  CHECK_ARG(c, (flags & ~(TLDA_REFRESH_W | TLDA_RESET)) == 0, TLDA_ERR_ARG, "unknown flags");
+  CHECK_ARG(c, b != nullptr || (flags & (TLDA_REFRESH_W | TLDA_RESET)), TLDA_ERR_ARG,
+            "batch is NULL and no refresh or reset was requested");
+  if (b) {
+    tlda_status st = check_batch(c, b);
+    if (st != TLDA_OK) return st;
+    st = validate_content(c, b);
+    if (st != TLDA_OK) return st;
+  }
+  tlda_status st = ensure_s2(c);
+  if (st != TLDA_OK) return st;
+  const size_t V = c->cfg.V;
+  if (flags & TLDA_RESET) {
+    HIP_OK(c, launch_zero(c->mom.counts, 2 * sizeof(unsigned long long), c->stream));
+    HIP_OK(c, launch_zero(c->mom.totals, V * sizeof(unsigned long long), c->stream));
+    HIP_OK(c, launch_zero(c->mom.fsum, V * sizeof(double), c->stream));
+    HIP_OK(c, launch_zero(c->mom.S2, V * V * sizeof(double), c->stream));
+  }
+  if (b && b->n_rows > 0) {
+    st = begin_use(c, b);
+    if (st != TLDA_OK) return st;
+    HIP_OK(c, tlda::launch_accumulate(*b, c->cfg.V, c->mom, c->stream));
+    st = end_use(c, b);
+    if (st != TLDA_OK) return st;
+  }
+  if (flags & TLDA_REFRESH_W) return refresh(c);
+  return TLDA_OK;
+}
+
+tlda_status tlda_whiten_batch(tlda_ctx* c, const tlda_csr_batch* b, float* X, int32_t* n_kept) {
+  if (!c) return TLDA_ERR_ARG;
+  tlda_status st = check_batch(c, b);
+  if (st != TLDA_OK) return st;
+  CHECK_ARG(c, c->wh.ready, TLDA_ERR_STATE, "no whitening matrix yet: refresh or set one first");
+  CHECK_ARG(c, X != nullptr || b->n_rows == 0, TLDA_ERR_ARG, "X is NULL");
+  st = validate_content(c, b);
+  if (st != TLDA_OK) return st;
+  st = begin_use(c, b);
+  if (st != TLDA_OK) return st;
+  HIP_OK(c, tlda::launch_whiten(*b, c->wh.W32, c->wh.mw32, c->cfg.D, c->Dp, X, n_kept, c->sync,
+                                c->stream));
+  return end_use(c, b);
+}
+
+tlda_status tlda_cp_step(tlda_ctx* c, const float* X, int32_t n_rows, const int32_t* n_kept,
+                         float beta, float* Phi, float* grad) {
+  if (!c) return TLDA_ERR_ARG;
+  CHECK_ARG(c, n_rows >= 0, TLDA_ERR_SHAPE, "negative n_rows");
+  CHECK_ARG(c, Phi != nullptr, TLDA_ERR_ARG, "Phi is NULL");
+  CHECK_ARG(c, X != nullptr || n_rows == 0, TLDA_ERR_ARG, "X is NULL");
+  CHECK_ARG(c, std::isfinite(beta), TLDA_ERR_ARG, "beta is not finite");
+  if (n_rows == 0) return TLDA_OK;
+  const int D = c->cfg.D, K = c->cfg.K;
+  const int nblk = tlda::cp_num_blocks(n_rows, D, K);
+  const size_t need = (size_t)nblk * D * K;
+  if (c->cp.cap < need) {
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    dfree(c->cp.partial);
+    c->cp.cap = 0;
+    HIP_OK(c, dalloc(&c->cp.partial, need));
+    c->cp.cap = need;
+  }
+  float* g = grad ? grad : c->cp.grad;
+  HIP_OK(c, tlda::launch_cp_reduce(X, n_rows, Phi, D, K, nblk, c->cp.partial, c->stream));
+  HIP_OK(c, tlda::launch_cp_finalize(c->cp.partial, nblk, n_kept, n_rows, Phi, g, D, K,
+                                     c->cfg.alpha0, c->cfg.theta, beta, c->cp.R1, c->sync + 2,
+                                     c->stream));
+  return TLDA_OK;
+}
+
+tlda_status tlda_unwhiten(tlda_ctx* c, const float* Phi, double* mu, double* alpha, double* lambda,
+                          uint32_t flags) {
+  if (!c) return TLDA_ERR_ARG;
+  CHECK_ARG(c, Phi && mu && alpha, TLDA_ERR_ARG, "Phi, mu or alpha is NULL");
+  CHECK_ARG(c, (flags & ~TLDA_PROJECT_SIMPLEX) == 0, TLDA_ERR_ARG, "unknown flags");
+  CHECK_ARG(c, c->wh.ready, TLDA_ERR_STATE, "no whitening matrix yet");
+  HIP_OK(c, tlda::launch_unwhiten(Phi, c->wh.U, c->wh.eig, c->wh.m, c->cfg.V, c->cfg.D, c->cfg.K,
+                                  c->cfg.theta, flags, mu, alpha, lambda, c->post, c->stream));
+  return TLDA_OK;
+}
+
+tlda_status tlda_infer_doc_topics(tlda_ctx* c, const float* X, int32_t n_rows, const double* mu,
+                                  int32_t max_iter, float tol, float* theta_out) {
+  if (!c) return TLDA_ERR_ARG;
+  CHECK_ARG(c, n_rows >= 0 && max_iter >= 0, TLDA_ERR_ARG, "negative n_rows or max_iter");
+  CHECK_ARG(c, tol >= 0.0f && std::isfinite(tol), TLDA_ERR_ARG, "tol must be finite and >= 0");
+  CHECK_ARG(c, mu != nullptr, TLDA_ERR_ARG, "mu is NULL");
+  CHECK_ARG(c, (X && theta_out) || n_rows == 0, TLDA_ERR_ARG, "X or theta is NULL");
+  CHECK_ARG(c, c->wh.ready, TLDA_ERR_STATE, "no whitening matrix yet");
+  if (n_rows == 0) return TLDA_OK;
+  const int V = c->cfg.V, D = c->cfg.D, K = c->cfg.K;
+  HIP_OK(c, launch_zero(c->dev_flags, 4 * sizeof(int), c->stream));
+  HIP_OK(c, tlda::launch_inference_setup(c->wh.W, c->wh.m, mu, V, D, K, c->postA, c->postG,
+                                         c->postZ, c->postEv, c->A32, c->G32, c->step32,
+                                         c->dev_flags + 1, c->stream));
+  HIP_OK(c, tlda::launch_infer(X, n_rows, c->A32, c->G32, c->step32, D, K, max_iter, tol,
+                               theta_out, c->stream));
+  return TLDA_OK;
+}
+
+tlda_status tlda_stage_batch(tlda_ctx* c, const tlda_csr_batch* h, int32_t slot,
+                             tlda_csr_batch* dev_out) {
+  if (!c) return TLDA_ERR_ARG;
+  CHECK_ARG(c, h && dev_out, TLDA_ERR_ARG, "host batch or output is NULL");
+  CHECK_ARG(c, slot == 0 || slot == 1, TLDA_ERR_ARG, "slot must be 0 or 1");
+  CHECK_ARG(c, h->n_rows >= 0 && h->nnz >= 0, TLDA_ERR_SHAPE, "negative n_rows or nnz");
+  CHECK_ARG(c, h->row_ptr != nullptr, TLDA_ERR_ARG, "row_ptr is NULL");
+  if (h->nnz > 0) CHECK_ARG(c, h->col_idx && h->val, TLDA_ERR_ARG, "col_idx or val is NULL");
+  tlda::StageSlot& s = c->slots[slot];
+  const size_t rows = (size_t)h->n_rows + 1, nnz = (size_t)h->nnz;
+  if (s.cap_rows < rows || s.cap_nnz < nnz) {
+    if (s.used) HIP_OK(c, hipEventSynchronize(s.free_));
+    dfree(s.row_ptr); dfree(s.col_idx); dfree(s.val);
+    s.cap_rows = s.cap_nnz = 0;
+    s.used = false;
+    HIP_OK(c, dalloc(&s.row_ptr, rows));
+    HIP_OK(c, dalloc(&s.col_idx, nnz));
+    HIP_OK(c, dalloc(&s.val, nnz));
+    s.cap_rows = rows;
+    s.cap_nnz = nnz;
+  }
+  if (s.used) HIP_OK(c, hipStreamWaitEvent(c->copy_stream, s.free_, 0));
+  HIP_OK(c, hipMemcpyAsync(s.row_ptr, h->row_ptr, rows * sizeof(int32_t), hipMemcpyHostToDevice,
+                           c->copy_stream));
+  if (nnz) {
+    HIP_OK(c, hipMemcpyAsync(s.col_idx, h->col_idx, nnz * sizeof(int32_t), hipMemcpyHostToDevice,
+                             c->copy_stream));
+    HIP_OK(c, hipMemcpyAsync(s.val, h->val, nnz * sizeof(float), hipMemcpyHostToDevice,
+                             c->copy_stream));
+  }
+  HIP_OK(c, hipEventRecord(s.ready, c->copy_stream));
+  // until a consumer records its own release, the slot is free once copied
+  HIP_OK(c, hipEventRecord(s.free_, c->copy_stream));
+  s.used = true;
+  dev_out->n_rows = h->n_rows;
+  dev_out->nnz = h->nnz;
+  dev_out->row_ptr = s.row_ptr;
+  dev_out->col_idx = s.col_idx;
+  dev_out->val = s.val;
+  dev_out->slot = slot;
+  return TLDA_OK;
+}
+
+tlda_status tlda_get_stats(tlda_ctx* c, int64_t* N, int64_t* n_skipped, int64_t* totals) {
+  if (!c) return TLDA_ERR_ARG;
+  unsigned long long counts[2];
+  HIP_OK(c, hipMemcpyAsync(counts, c->mom.counts, sizeof(counts), hipMemcpyDeviceToHost, c->stream));
+  if (totals)
+    HIP_OK(c, hipMemcpyAsync(totals, c->mom.totals, sizeof(int64_t) * c->cfg.V,
+                             hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  if (N) *N = (int64_t)counts[0];
+  if (n_skipped) *n_skipped = (int64_t)counts[1];
+  return TLDA_OK;
+}
+
+tlda_status tlda_get_whitening(tlda_ctx* c, double* W, double* eig, double* M1) {
+  if (!c) return TLDA_ERR_ARG;
+  CHECK_ARG(c, c->wh.ready, TLDA_ERR_STATE, "no whitening matrix yet");
+  const size_t V = c->cfg.V, D = c->cfg.D;
+  if (W) HIP_OK(c, hipMemcpyAsync(W, c->wh.W, sizeof(double) * V * D, hipMemcpyDeviceToHost, c->stream));
+  if (eig) HIP_OK(c, hipMemcpyAsync(eig, c->wh.eig, sizeof(double) * D, hipMemcpyDeviceToHost, c->stream));
+  if (M1) HIP_OK(c, hipMemcpyAsync(M1, c->wh.m, sizeof(double) * V, hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  return TLDA_OK;
+}
+
+tlda_status tlda_set_whitening(tlda_ctx* c, const double* W, const double* M1) {
+  if (!c) return TLDA_ERR_ARG;
+  CHECK_ARG(c, W && M1, TLDA_ERR_ARG, "W or M1 is NULL");
+  const int V = c->cfg.V, D = c->cfg.D;
+  for (int i = 0; i < V * D; ++i)
+    CHECK_ARG(c, std::isfinite(W[i]), TLDA_ERR_ARG, "W has a non-finite entry");
+  for (int d = 0; d < D; ++d) {
+    double s = 0.0;
+    for (int i = 0; i < V; ++i) s += W[(size_t)i * D + d] * W[(size_t)i * D + d];
+    CHECK_ARG(c, s > 0.0, TLDA_ERR_NUMERIC, "W has a zero column");
+  }
+  HIP_OK(c, hipMemcpyAsync(c->wh.W, W, sizeof(double) * (size_t)V * D, hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->wh.m, M1, sizeof(double) * V, hipMemcpyHostToDevice, c->stream));
+  HIP_OK(c, tlda::launch_from_injected(c->wh.W, V, D, c->wh.U, c->wh.eig, c->stream));
+  HIP_OK(c, tlda::launch_form_whitening(c->wh.U, c->wh.eig, c->wh.m, V, D, c->Dp, c->wh.W,
+                                        c->wh.W32, c->wh.mw32, c->stream));
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  c->wh.ready = true;
+  return TLDA_OK;
+}
+
+// Checkpoint layout: header (magic, version, V, K, D, flags), the counts,
+// token totals, sum f, S2 (when allocated), then W, U, eig and M1 (when ready).
+namespace {
+constexpr uint32_t kMagic = 0x41444c54u;   // "TLDA"
+struct Header {
+  uint32_t magic, version;
+  int32_t V, K, D, has_s2, ready, pad;
+};
+}  // namespace
+
+tlda_status tlda_save_state(tlda_ctx* c, void* buf, size_t* len) {
+  if (!c || !len) return TLDA_ERR_ARG;
+  const size_t V = c->cfg.V, D = c->cfg.D;
+  const bool has_s2 = c->mom.S2 != nullptr;
+  size_t need = sizeof(Header) + 2 * 8 + V * 8 + V * 8;
+  if (has_s2) need += V * V * 8;
+  if (c->wh.ready) need += 2 * V * D * 8 + D * 8 + V * 8;
+  if (!buf) {
+    *len = need;
+    return TLDA_OK;
+  }
+  CHECK_ARG(c, *len >= need, TLDA_ERR_SHAPE, "checkpoint buffer too small");
+  char* p = static_cast<char*>(buf);
+  Header h{kMagic, 1u, (int32_t)V, c->cfg.K, (int32_t)D, has_s2 ? 1 : 0, c->wh.ready ? 1 : 0, 0};
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  auto d2h = [&](const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(p, src, bytes, hipMemcpyDeviceToHost, c->stream);
+    p += bytes;
+    return e;
+  };
+  HIP_OK(c, d2h(c->mom.counts, 16));
+  HIP_OK(c, d2h(c->mom.totals, V * 8));
+  HIP_OK(c, d2h(c->mom.fsum, V * 8));
+  if (has_s2) HIP_OK(c, d2h(c->mom.S2, V * V * 8));
+  if (c->wh.ready) {
+    HIP_OK(c, d2h(c->wh.W, V * D * 8));
+    HIP_OK(c, d2h(c->wh.U, V * D * 8));
+    HIP_OK(c, d2h(c->wh.eig, D * 8));
+    HIP_OK(c, d2h(c->wh.m, V * 8));
+  }
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  *len = need;
+  return TLDA_OK;
+}
+
+tlda_status tlda_load_state(tlda_ctx* c, const void* buf, size_t len) {
+  if (!c || !buf) return TLDA_ERR_ARG;
+  CHECK_ARG(c, len >= sizeof(Header), TLDA_ERR_SHAPE, "checkpoint too short");
+  Header h;
+  std::memcpy(&h, buf, sizeof(h));
+  CHECK_ARG(c, h.magic == kMagic && h.version == 1u, TLDA_ERR_ARG, "not a checkpoint of this format");
+  CHECK_ARG(c, h.V == c->cfg.V && h.K == c->cfg.K && h.D == c->cfg.D, TLDA_ERR_SHAPE,
+            "checkpoint shape does not match the context");
+  const size_t V = c->cfg.V, D = c->cfg.D;
+  size_t need = sizeof(Header) + 16 + V * 16;
+  if (h.has_s2) need += V * V * 8;
+  if (h.ready) need += 2 * V * D * 8 + D * 8 + V * 8;
+  CHECK_ARG(c, len >= need, TLDA_ERR_SHAPE, "checkpoint truncated");
+  if (h.has_s2) {
+    tlda_status st = ensure_s2(c);
+    if (st != TLDA_OK) return st;
+  }
+  const char* p = static_cast<const char*>(buf) + sizeof(Header);
+  auto h2d = [&](void* dst, size_t bytes) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, c->stream);
+    p += bytes;
+    return e;
+  };
+  HIP_OK(c, h2d(c->mom.counts, 16));
+  HIP_OK(c, h2d(c->mom.totals, V * 8));
+  HIP_OK(c, h2d(c->mom.fsum, V * 8));
+  if (h.has_s2) HIP_OK(c, h2d(c->mom.S2, V * V * 8));
+  else if (c->mom.S2) HIP_OK(c, launch_zero(c->mom.S2, V * V * 8, c->stream));
+  if (h.ready) {
+    HIP_OK(c, h2d(c->wh.W, V * D * 8));
+    HIP_OK(c, h2d(c->wh.U, V * D * 8));
+    HIP_OK(c, h2d(c->wh.eig, D * 8));
+    HIP_OK(c, h2d(c->wh.m, V * 8));
+    HIP_OK(c, tlda::launch_form_whitening(c->wh.U, c->wh.eig, c->wh.m, (int)V, (int)D, c->Dp,
+                                          c->wh.W, c->wh.W32, c->wh.mw32, c->stream));
+  }
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  c->wh.ready = h.ready != 0;
+  return TLDA_OK;
+}
+
+}  // extern "C"

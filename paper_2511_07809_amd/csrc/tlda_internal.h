@@ -1,0 +1,151 @@
+// Internal declarations shared by the translation units of libtlda.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/tlda.h"
+
+namespace tlda {
+
+// Row stride (floats) of the FP32 whitening copy used for the gathers of the
+// whitening SpMM: rows are aligned to a 128-byte cache line once D >= 32, and
+// to a power of two of at least one float4 below that.
+inline int padded_d(int D) {
+  if (D >= 32) return (D + 31) / 32 * 32;
+  int p = 4;
+  while (p < D) p <<= 1;
+  return p;
+}
+
+struct StageSlot {
+  int32_t* row_ptr = nullptr;
+  int32_t* col_idx = nullptr;
+  float* val = nullptr;
+  size_t cap_rows = 0, cap_nnz = 0;
+  hipEvent_t ready = nullptr;   // recorded on the copy stream after the copy
+  hipEvent_t free_ = nullptr;   // recorded on the compute stream after consumers
+  bool used = false;
+};
+
+struct Moments {
+  unsigned long long* counts = nullptr;  // [0] N kept, [1] dropped
+  unsigned long long* totals = nullptr;  // [V] token totals of kept documents
+  double* fsum = nullptr;                // [V] sum of f over kept documents
+  double* S2 = nullptr;                  // [V][V] upper triangle of sum f f^T
+};
+
+struct Whitening {
+  bool ready = false;
+  double* W = nullptr;     // [V][D]
+  double* U = nullptr;     // [V][D]
+  double* eig = nullptr;   // [D]
+  double* m = nullptr;     // [V]
+  float* W32 = nullptr;    // [V][Dp]
+  float* mw32 = nullptr;   // [Dp], W^T M1
+};
+
+struct EigScratch {
+  int p = 0;
+  double* Q = nullptr;     // [V][p]
+  double* Y = nullptr;     // [V][p]
+  double* G = nullptr;     // [p][p]  Gram / projected matrix
+  double* Z = nullptr;     // [p][p]  eigenvectors of the projected matrix
+  double* ev = nullptr;    // [p]
+  double* t = nullptr;     // [p]     M1^T Q
+  double* Binv = nullptr;  // [p][p]  inverse-transpose Cholesky factor
+  double* sel = nullptr;   // [D + p*D] selected Ritz values and vectors
+  double* mcand = nullptr; // [V]     M1 of the refresh in progress
+  int* info = nullptr;     // [4]     device status words
+};
+
+struct CpScratch {
+  size_t cap = 0;             // floats available in partial
+  float* partial = nullptr;   // [nblk][D][K]
+  double* R1 = nullptr;       // [D][K]
+  float* grad = nullptr;      // [D][K] used when the caller passes no gradient buffer
+};
+
+}  // namespace tlda
+
+struct tlda_ctx {
+  tlda_config cfg;
+  int Dp = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t copy_stream = nullptr;
+  int device = 0;
+  int num_cu = 0;
+  tlda::Moments mom;
+  tlda::Whitening wh;
+  tlda::EigScratch eig;
+  tlda::CpScratch cp;
+  tlda::StageSlot slots[2];
+  double* post = nullptr;     // [K] scratch for unwhiten
+  double* postA = nullptr;    // [D][K] inference matrix
+  double* postG = nullptr;    // [K][K]
+  double* postZ = nullptr;    // [K][K]
+  double* postEv = nullptr;   // [K]
+  float* A32 = nullptr;       // [D][K]
+  float* G32 = nullptr;       // [K][K]
+  float* step32 = nullptr;    // [1]
+  int* dev_flags = nullptr;   // [4] CSR validation and inference status words
+  int* sync = nullptr;        // [4] last-block counters: whiten (0, 1), cp step (2)
+  std::string last_error;
+};
+
+namespace tlda {
+
+// ---- kernel launchers (one translation unit each) ----
+// zero-fill with a kernel (no memset nodes, so callers may capture the work)
+hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s);
+// moments
+hipError_t launch_validate_csr(const tlda_csr_batch& b, int V, int* err, hipStream_t s);
+hipError_t launch_accumulate(const tlda_csr_batch& b, int V, const Moments& m, hipStream_t s);
+hipError_t launch_mirror_upper(double* S2, int V, hipStream_t s);
+hipError_t launch_mean(const double* fsum, const unsigned long long* counts, double* m, int V,
+                       hipStream_t s);
+// eigen-solver building blocks (FP64)
+hipError_t launch_random_block(double* Q, int V, int p, uint64_t seed, hipStream_t s);
+hipError_t launch_m2_apply(const double* S2, const double* m, const double* t, const double* Q,
+                           double* Y, int V, int p, double scale_s, double scale_m,
+                           hipStream_t s);
+hipError_t launch_gram(const double* A, const double* B, double* G, int V, int p, hipStream_t s);
+hipError_t launch_vecT_mat(const double* m, const double* Q, double* t, int V, int p,
+                           hipStream_t s);
+hipError_t launch_cholesky(double* G, int p, double shift_rel, int* info, hipStream_t s);
+hipError_t launch_trsm_right_into(const double* Y, const double* G, double* Binv, double* Out, int V,
+                                  int p, hipStream_t s);
+hipError_t launch_jacobi(double* A, double* Z, double* ev, int p, int* info, hipStream_t s);
+hipError_t launch_ritz_vectors(const double* Q, const double* Z, const double* ev, int V, int p,
+                               int D, double* U, double* eigD, hipStream_t s);
+hipError_t launch_form_whitening(const double* U, const double* eig, const double* m, int V, int D,
+                                 int Dp, double* W, float* W32, float* mw32, hipStream_t s);
+hipError_t launch_from_injected(const double* W, int V, int D, double* U, double* eig,
+                                hipStream_t s);
+// whitening SpMM
+hipError_t launch_whiten(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
+                         int Dp, float* X, int* n_kept, int* sync, hipStream_t s);
+// CP step
+hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D, int K, int nblk,
+                            float* partial, hipStream_t s);
+hipError_t launch_cp_finalize(const float* partial, int nblk, const int* n_kept, int n_rows,
+                              float* Phi, float* grad, int D, int K, double alpha0, double theta,
+                              float beta, double* R1, int* sync, hipStream_t s);
+int cp_tile_rows(int D, int K);
+int cp_num_blocks(int n_rows, int D, int K);
+// post-processing
+hipError_t launch_unwhiten(const float* Phi, const double* U, const double* eig, const double* m,
+                           int V, int D, int K, double theta, uint32_t flags, double* mu,
+                           double* alpha, double* lambda, double* scratch, hipStream_t s);
+hipError_t launch_inference_setup(const double* W, const double* m, const double* mu, int V,
+                                  int D, int K, double* A, double* G, double* Z, double* ev,
+                                  float* A32, float* G32, float* step32, int* info,
+                                  hipStream_t s);
+hipError_t launch_infer(const float* X, int n_rows, const float* A32, const float* G32,
+                        const float* step32, int D, int K, int max_iter, float tol,
+                        float* theta, hipStream_t s);
+
+}  // namespace tlda

@@ -1,0 +1,270 @@
+"""Thin ctypes binding of libtlda (include/tlda.h), function for function.
+
+Argument marshalling only: every call goes straight to the HIP library; there
+is no CPU implementation behind any of these names.  PyTorch supplies device
+memory and the current HIP stream.  Importing this module without a built
+libtlda.so raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch  # loads the HIP runtime libtlda.so binds to (same soname)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtlda.so")
+
+TLDA_OK = 0
+STATUS_NAMES = {0: "TLDA_OK", 1: "TLDA_ERR_ARG", 2: "TLDA_ERR_SHAPE", 3: "TLDA_ERR_CSR",
+                4: "TLDA_ERR_STATE", 5: "TLDA_ERR_NUMERIC", 6: "TLDA_ERR_OOM",
+                7: "TLDA_ERR_DEVICE"}
+TLDA_VALIDATE_CSR = 0x1
+TLDA_REFRESH_W = 0x1
+TLDA_RESET = 0x2
+TLDA_PROJECT_SIMPLEX = 0x1
+TLDA_MAX_D = 256
+TLDA_MAX_K = 256
+TLDA_MAX_DK = 16384
+
+EXPORTED = ("tlda_create", "tlda_destroy", "tlda_status_str", "tlda_last_error",
+            "tlda_update_moments", "tlda_whiten_batch", "tlda_cp_step", "tlda_unwhiten",
+            "tlda_infer_doc_topics", "tlda_stage_batch", "tlda_get_stats",
+            "tlda_get_whitening", "tlda_set_whitening", "tlda_save_state", "tlda_load_state")
+
+
+class tlda_config(ctypes.Structure):
+    _fields_ = [("V", ctypes.c_int32), ("K", ctypes.c_int32), ("D", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("alpha0", ctypes.c_double),
+                ("theta", ctypes.c_double), ("eig_iters", ctypes.c_int32),
+                ("eig_block", ctypes.c_int32), ("eig_seed", ctypes.c_uint64)]
+
+
+class tlda_csr_batch(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("nnz", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("slot", ctypes.c_int32)]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libtlda.so is not built at {path}; run "
+                          "`python -m paper_2511_07809_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
+    sig = {
+        "tlda_create": ([ctypes.POINTER(tlda_config), vp, ctypes.POINTER(vp)], i32),
+        "tlda_destroy": ([vp], None),
+        "tlda_status_str": ([i32], ctypes.c_char_p),
+        "tlda_last_error": ([vp], ctypes.c_char_p),
+        "tlda_update_moments": ([vp, ctypes.POINTER(tlda_csr_batch), u32], i32),
+        "tlda_whiten_batch": ([vp, ctypes.POINTER(tlda_csr_batch), vp, vp], i32),
+        "tlda_cp_step": ([vp, vp, i32, vp, ctypes.c_float, vp, vp], i32),
+        "tlda_unwhiten": ([vp, vp, vp, vp, vp, u32], i32),
+        "tlda_infer_doc_topics": ([vp, vp, i32, vp, i32, ctypes.c_float, vp], i32),
+        "tlda_stage_batch": ([vp, ctypes.POINTER(tlda_csr_batch), i32,
+                              ctypes.POINTER(tlda_csr_batch)], i32),
+        "tlda_get_stats": ([vp, vp, vp, vp], i32),
+        "tlda_get_whitening": ([vp, vp, vp, vp], i32),
+        "tlda_set_whitening": ([vp, vp, vp], i32),
+        "tlda_save_state": ([vp, vp, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "tlda_load_state": ([vp, vp, ctypes.c_size_t], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_LIB = load_library()
+
+
+class TldaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Context:
+    """Owns a tlda_ctx* created on a HIP stream."""
+
+    def __init__(self, handle: int, cfg: tlda_config, stream: torch.cuda.Stream):
+        self.handle = handle
+        self.cfg = cfg
+        self.stream = stream
+
+    @property
+    def V(self) -> int:
+        return self.cfg.V
+
+    @property
+    def K(self) -> int:
+        return self.cfg.K
+
+    @property
+    def D(self) -> int:
+        return self.cfg.D
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h:
+            _LIB.tlda_destroy(h)
+
+
+def _check(ctx: Optional[Context], status: int) -> None:
+    if status != TLDA_OK:
+        msg = _LIB.tlda_last_error(ctx.handle if ctx else None) or b""
+        raise TldaError(status, msg.decode() or _LIB.tlda_status_str(status).decode())
+
+
+class CsrBatch:
+    """A CSR batch whose arrays live in device (or pinned host) memory."""
+
+    def __init__(self, row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor,
+                 slot: int = -1):
+        assert row_ptr.dtype == torch.int32 and col_idx.dtype == torch.int32
+        assert val.dtype == torch.float32
+        assert row_ptr.is_contiguous() and col_idx.is_contiguous() and val.is_contiguous()
+        self.row_ptr, self.col_idx, self.val = row_ptr, col_idx, val
+        self.n_rows = row_ptr.numel() - 1
+        self.nnz = col_idx.numel()
+        self.slot = slot
+
+    @classmethod
+    def from_numpy(cls, row_ptr, col_idx, val, device="cuda", pin=False):
+        rp = torch.from_numpy(row_ptr.astype("int32", copy=False))
+        ci = torch.from_numpy(col_idx.astype("int32", copy=False))
+        va = torch.from_numpy(val.astype("float32", copy=False))
+        if pin:
+            return cls(rp.pin_memory(), ci.pin_memory(), va.pin_memory())
+        return cls(rp.to(device), ci.to(device), va.to(device))
+
+    def struct(self) -> tlda_csr_batch:
+        return tlda_csr_batch(self.n_rows, self.nnz, self.row_ptr.data_ptr(),
+                              self.col_idx.data_ptr() if self.nnz else None,
+                              self.val.data_ptr() if self.nnz else None, self.slot)
+
+
+class _StagedBatch(CsrBatch):
+    def __init__(self, s: tlda_csr_batch, owner: CsrBatch):
+        self._s = s
+        self._owner = owner          # keeps the pinned host arrays alive
+        self.n_rows, self.nnz, self.slot = s.n_rows, s.nnz, s.slot
+
+    def struct(self) -> tlda_csr_batch:
+        return self._s
+
+
+# ---------------------------------------------------------------------------
+# The C ABI, one Python function per C function.
+# ---------------------------------------------------------------------------
+def tlda_create(V: int, K: int, D: int, alpha0: float, theta: float = 0.0, *,
+                validate_csr: bool = False, eig_iters: int = 0, eig_block: int = 0,
+                eig_seed: int = 0, stream: Optional[torch.cuda.Stream] = None) -> Context:
+    if not torch.cuda.is_available():
+        raise RuntimeError("libtlda needs a ROCm GPU; none is visible")
+    stream = stream or torch.cuda.current_stream()
+    cfg = tlda_config(V, K, D, TLDA_VALIDATE_CSR if validate_csr else 0, float(alpha0),
+                      float(theta), eig_iters, eig_block, eig_seed)
+    h = ctypes.c_void_p()
+    _check(None, _LIB.tlda_create(ctypes.byref(cfg), ctypes.c_void_p(stream.cuda_stream),
+                                  ctypes.byref(h)))
+    return Context(h.value, cfg, stream)
+
+
+def tlda_update_moments(ctx: Context, batch: Optional[CsrBatch], flags: int = 0) -> None:
+    s = batch.struct() if batch is not None else None
+    _check(ctx, _LIB.tlda_update_moments(ctx.handle, ctypes.byref(s) if s else None, flags))
+
+
+def tlda_whiten_batch(ctx: Context, batch: CsrBatch, X: Optional[torch.Tensor] = None,
+                      n_kept: Optional[torch.Tensor] = None):
+    if X is None:
+        X = torch.empty((batch.n_rows, ctx.D), dtype=torch.float32, device="cuda")
+    if n_kept is None:
+        n_kept = torch.empty(1, dtype=torch.int32, device="cuda")
+    assert X.dtype == torch.float32 and X.is_contiguous() and X.numel() >= batch.n_rows * ctx.D
+    s = batch.struct()
+    _check(ctx, _LIB.tlda_whiten_batch(ctx.handle, ctypes.byref(s), _ptr(X), _ptr(n_kept)))
+    return X, n_kept
+
+
+def tlda_cp_step(ctx: Context, X: torch.Tensor, n_rows: int, n_kept: Optional[torch.Tensor],
+                 beta: float, Phi: torch.Tensor, grad: Optional[torch.Tensor] = None) -> None:
+    assert Phi.dtype == torch.float32 and Phi.is_contiguous() and Phi.numel() == ctx.D * ctx.K
+    assert X.dtype == torch.float32 and X.is_contiguous() and X.numel() >= n_rows * ctx.D
+    _check(ctx, _LIB.tlda_cp_step(ctx.handle, _ptr(X), n_rows, _ptr(n_kept), float(beta),
+                                  _ptr(Phi), _ptr(grad)))
+
+
+def tlda_unwhiten(ctx: Context, Phi: torch.Tensor, flags: int = 0):
+    mu = torch.empty((ctx.V, ctx.K), dtype=torch.float64, device="cuda")
+    alpha = torch.empty(ctx.K, dtype=torch.float64, device="cuda")
+    lam = torch.empty(ctx.K, dtype=torch.float64, device="cuda")
+    _check(ctx, _LIB.tlda_unwhiten(ctx.handle, _ptr(Phi), _ptr(mu), _ptr(alpha), _ptr(lam),
+                                   flags))
+    return mu, alpha, lam
+
+
+def tlda_infer_doc_topics(ctx: Context, X: torch.Tensor, n_rows: int, mu: torch.Tensor,
+                          max_iter: int, tol: float = 0.0,
+                          theta: Optional[torch.Tensor] = None) -> torch.Tensor:
+    if theta is None:
+        theta = torch.empty((n_rows, ctx.K), dtype=torch.float32, device="cuda")
+    assert mu.dtype == torch.float64 and mu.is_contiguous()
+    _check(ctx, _LIB.tlda_infer_doc_topics(ctx.handle, _ptr(X), n_rows, _ptr(mu), max_iter,
+                                           float(tol), _ptr(theta)))
+    return theta
+
+
+def tlda_stage_batch(ctx: Context, host_batch: CsrBatch, slot: int) -> CsrBatch:
+    h = host_batch.struct()
+    out = tlda_csr_batch()
+    _check(ctx, _LIB.tlda_stage_batch(ctx.handle, ctypes.byref(h), slot, ctypes.byref(out)))
+    return _StagedBatch(out, host_batch)
+
+
+def tlda_get_stats(ctx: Context):
+    import numpy as np
+    N = ctypes.c_int64()
+    sk = ctypes.c_int64()
+    tot = np.zeros(ctx.V, dtype=np.int64)
+    _check(ctx, _LIB.tlda_get_stats(ctx.handle, ctypes.addressof(N), ctypes.addressof(sk),
+                                    tot.ctypes.data))
+    return int(N.value), int(sk.value), tot
+
+
+def tlda_get_whitening(ctx: Context):
+    import numpy as np
+    W = np.zeros((ctx.V, ctx.D))
+    eig = np.zeros(ctx.D)
+    m = np.zeros(ctx.V)
+    _check(ctx, _LIB.tlda_get_whitening(ctx.handle, W.ctypes.data, eig.ctypes.data, m.ctypes.data))
+    return W, eig, m
+
+
+def tlda_set_whitening(ctx: Context, W, M1) -> None:
+    import numpy as np
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    M1 = np.ascontiguousarray(M1, dtype=np.float64)
+    assert W.shape == (ctx.V, ctx.D) and M1.shape == (ctx.V,)
+    _check(ctx, _LIB.tlda_set_whitening(ctx.handle, W.ctypes.data, M1.ctypes.data))
+
+
+def tlda_save_state(ctx: Context) -> bytes:
+    n = ctypes.c_size_t(0)
+    _check(ctx, _LIB.tlda_save_state(ctx.handle, None, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(ctx, _LIB.tlda_save_state(ctx.handle, buf, ctypes.byref(n)))
+    return buf.raw[:n.value]
+
+
+def tlda_load_state(ctx: Context, data: bytes) -> None:
+    buf = ctypes.create_string_buffer(data, len(data))
+    _check(ctx, _LIB.tlda_load_state(ctx.handle, buf, len(data)))

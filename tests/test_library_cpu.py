@@ -1,0 +1,80 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+the header declares, and its structs have the header's layout.  No call here
+touches a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tlda.h")
+LIB = os.path.join(ROOT, "paper_2511_07809_amd", "libtlda.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tlda_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2511_07809_amd.build import build
+        build()
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_function_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2511_07809_amd import tlda
+    assert sorted(tlda.EXPORTED) == names
+
+
+def test_status_strings(lib):
+    lib.tlda_status_str.restype = ctypes.c_char_p
+    lib.tlda_status_str.argtypes = [ctypes.c_int]
+    assert lib.tlda_status_str(0) == b"ok"
+    assert lib.tlda_status_str(3) == b"invalid CSR content"
+    assert lib.tlda_status_str(99) == b"unknown status"
+    lib.tlda_last_error.restype = ctypes.c_char_p
+    lib.tlda_last_error.argtypes = [ctypes.c_void_p]
+    assert lib.tlda_last_error(None) == b""
+
+
+def test_create_rejects_null_arguments_before_touching_a_device(lib):
+    lib.tlda_create.restype = ctypes.c_int
+    lib.tlda_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.tlda_create(None, None, None) == 1   # TLDA_ERR_ARG
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "tlda.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(tlda_config),"
+        " offsetof(tlda_config, alpha0), offsetof(tlda_config, eig_iters),"
+        " offsetof(tlda_config, eig_seed), sizeof(tlda_csr_batch),"
+        " offsetof(tlda_csr_batch, row_ptr), offsetof(tlda_csr_batch, slot));return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    from paper_2511_07809_amd import tlda
+    cfg, b = tlda.tlda_config, tlda.tlda_csr_batch
+    assert got == [ctypes.sizeof(cfg), cfg.alpha0.offset, cfg.eig_iters.offset,
+                   cfg.eig_seed.offset, ctypes.sizeof(b), b.row_ptr.offset, b.slot.offset]
+
+
+def test_header_compiles_as_c_and_cxx(tmp_path):
+    for comp, ext in (("gcc", "c"), ("g++", "cpp")):
+        src = tmp_path / f"h.{ext}"
+        src.write_text('#include "tlda.h"\nint main(void){return TLDA_OK;}\n')
+        subprocess.run([comp, "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                        str(src), "-o", str(tmp_path / f"h_{ext}")], check=True)
