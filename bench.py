@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, TFLOP/s
+FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector / FP32 matrix, TFLOP/s
 
 
 def log(msg: str) -> None:
@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--beta", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the run, copy a device buffer of this many MiB (a plain copy "
+                         "kernel of known size that scales the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -80,6 +83,25 @@ def cpu_baseline(corpus, spec, batches, seconds: float) -> dict:
     return {"value": docs / dt, "unit": "docs/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{docs} documents of batch 0 ({spec.name}) in 1024-document slices, "
                       f"{dt:.1f} s: dense FP64 whitening plus the eq. vec_deriv gradient"}
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if there is none for this workload or the kernel's source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    entry = json.load(open(path)).get("kernels", {}).get(kernel)
+    if not entry:
+        return None
+    src = os.path.join(ROOT, entry["source"])
+    if not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != entry["source_sha256"]:
+        return None
+    return entry["bytes_per_launch"]
 
 
 def main():
@@ -167,14 +189,16 @@ def main():
     if wh_avg >= cp_avg:
         ach = wh_bytes / wh_avg / 1e9
         roof = {"kernel": "k_whiten", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                "avg_launch_us": wh_avg * 1e6}
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": measured_traffic("k_whiten", spec.name),
+                "algorithmic_bytes": wh_bytes, "avg_launch_us": wh_avg * 1e6}
     else:
         ach = cp_flops / cp_avg / 1e12
-        roof = {"kernel": "k_cp_reduce+k_cp_finalize", "bound": "alu", "achieved": ach,
+        roof = {"kernel": "k_cp_reduce+k_cp_finalize", "bound": "mfma", "achieved": ach,
                 "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": None,
-                "avg_launch_us": cp_avg * 1e6}
+                "frac": ach / FP32_VALU_PEAK_TFLOPS,
+                "traffic": measured_traffic("k_cp_reduce+k_cp_finalize", spec.name),
+                "algorithmic_flops": cp_flops, "avg_launch_us": cp_avg * 1e6}
     mom_docs_s = corpus.n_docs / (moments_ms / 1e3)
     # recovered topics: error to the planted ones after the timed steps
     mu, alpha, lam = tl.tlda_unwhiten(ctx, Phi, tl.TLDA_PROJECT_SIMPLEX)
@@ -202,6 +226,14 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(corpus, spec, batches, args.cpu_seconds)
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 4 * n
     print(json.dumps(out), flush=True)
 
 

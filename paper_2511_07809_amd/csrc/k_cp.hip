@@ -124,87 +124,334 @@ __global__ void __launch_bounds__(kThreads) k_cp_reduce(const float* __restrict_
   }
 }
 
-// Gradient and update.  Thread (d, k) sums the partials of R1[d][k] in block
-// order (FP64), forms its row of the penalty term
-// 3(1+theta) sum_j Phi[d][j] (phi_j . phi_k)^2 from Phi (a few KB, cached),
-// and writes grad[d][k].  Phi cannot be updated in place by the same threads
-// (others still read it), so every block counts itself done and the last one
-// applies Phi <- Phi - beta grad to all entries and re-arms the counter.
+// ---------------------------------------------------------------------------
+// FP32 matrix-core variant of the reduction (D, K <= 128 after padding to
+// 16).  Per row tile (T rows of X staged in LDS):
+//   S = X_t Phi      with v_mfma_f32_16x16x4_f32; each wave owns S column
+//                    tiles ct = wave, wave + 4, ... and keeps the Phi
+//                    fragments of those columns in registers for the whole
+//                    kernel (Phi is read from memory once per block);
+//   S^2 -> LDS;
+//   R1 += X_t^T S^2  with the same instruction, each wave owning R1 tiles
+//                    t = wave, wave + 4, ... accumulated in registers over
+//                    every tile of the block.
+// Operand layout of the 16x16x4 instruction: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; it receives D[4*(l/16) + r][l%16], r = 0..3.
+// The next row tile is prefetched into registers while the current one is
+// multiplied.
+// ---------------------------------------------------------------------------
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+
+// Penalty term P = Phi (Phi^T Phi * Phi^T Phi), column k = blockIdx.x
+// (FP64 sums): g_j = (phi_j . phi_k)^2, then P[d][k] = sum_j Phi[d][j] g_j.
+// Phi is staged in LDS when it fits (IN_LDS), else read from memory.
+template <bool IN_LDS>
+__global__ void __launch_bounds__(kThreads) k_cp_penalty(const float* __restrict__ Phi, int D,
+                                                         int K, double* __restrict__ P) {
+  extern __shared__ double psm[];
+  double* g = psm;                                         // [K]
+  float* Ps = reinterpret_cast<float*>(psm + K);           // [D][K] when IN_LDS
+  const float* src = Phi;
+  if (IN_LDS) {
+    for (int e = threadIdx.x; e < D * K; e += kThreads) Ps[e] = Phi[e];
+    __syncthreads();
+    src = Ps;
+  }
+  const int k = blockIdx.x;
+  for (int j = threadIdx.x; j < K; j += kThreads) {
+    double dot = 0.0;
+    for (int d = 0; d < D; ++d) dot += (double)src[d * K + j] * (double)src[d * K + k];
+    g[j] = dot * dot;
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < D; d += kThreads) {
+    double pen = 0.0;
+    for (int j = 0; j < K; ++j) pen += (double)src[d * K + j] * g[j];
+    P[d * K + k] = pen;
+  }
+}
+
+// The padded shape (DQ x KQ, multiples of 16) and the row tile T are
+// compile-time constants, so every loop is fully unrolled, accumulators stay
+// in place across the matrix instructions and only the row bound is checked
+// at run time.
+template <int DQ, int KQ, int T>
+__global__ void __launch_bounds__(kThreads) k_cp_reduce_mfma(const float* __restrict__ X,
+                                                             int n_rows,
+                                                             const float* __restrict__ Phi,
+                                                             int D, int K, int nblk,
+                                                             float* __restrict__ partial) {
+  constexpr int LDX = DQ + 4, LDS = KQ + 4;
+  constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = DQ / 4;
+  constexpr int NRT = NDT * NCT;
+  constexpr int ST = (NCT + 3) / 4;              // S column tiles per wave (max)
+  constexpr int RT = (NRT + 3) / 4;              // R1 tiles per wave (max)
+  // X tile staging: thread t owns column t % CP of rows t / CP + i * RPI,
+  // CP = DQ rounded up to a power of two; rows past the batch and padding
+  // columns load a clamped, in-bounds address and are zeroed by a select.
+  constexpr int CP = DQ <= 16 ? 16 : (DQ <= 32 ? 32 : (DQ <= 64 ? 64 : 128));
+  constexpr int RPI = kThreads / CP;
+  constexpr int PER = T / RPI;
+  static_assert(T % RPI == 0, "tile must split evenly over the block");
+  __shared__ float Xs[T * LDX];
+  __shared__ float Ss[T * LDS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+
+  // Phi fragments of this wave's S column tiles: bf[q][ks] = Phi[4 ks + l4][16 ct + l16]
+  float bf[ST][NKS];
+#pragma unroll
+  for (int q = 0; q < ST; ++q) {
+    const int ct = wave + 4 * q;
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int d = 4 * ks + l4, k = 16 * ct + l16;
+      bf[q][ks] = (ct < NCT && d < D && k < K) ? Phi[d * K + k] : 0.f;
+    }
+  }
+  floatx4 acc[RT];
+#pragma unroll
+  for (int q = 0; q < RT; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int sd = tid % CP, sr = tid / CP;
+  const bool dval = sd < D;
+  const int dcl = dval ? sd : 0;
+  float pre[PER];
+  const int ntiles = (n_rows + T - 1) / T;
+  auto fetch = [&](int tile) {
+    const int r0 = tile * T;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int r = r0 + sr + i * RPI;
+      const int rc = r < n_rows ? r : n_rows - 1;
+      const float v = X[(size_t)rc * D + dcl];
+      pre[i] = (dval && r < n_rows) ? v : 0.f;
+    }
+  };
+  if (blockIdx.x < ntiles) fetch(blockIdx.x);
+  for (int tile = blockIdx.x; tile < ntiles; tile += nblk) {
+    __syncthreads();
+    if (sd < DQ)
+#pragma unroll
+      for (int i = 0; i < PER; ++i) Xs[(sr + i * RPI) * LDX + sd] = pre[i];
+    __syncthreads();
+    if (tile + nblk < ntiles) fetch(tile + nblk);
+    // S = X_t Phi, squared into LDS (four independent 16-row chains at a time)
+#pragma unroll
+    for (int q = 0; q < ST; ++q) {
+      const int ct = wave + 4 * q;
+      if (ct < NCT) {
+#pragma unroll
+        for (int rt0 = 0; rt0 < T / 16; rt0 += 4) {
+          floatx4 sacc[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) sacc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+          const float* xa = Xs + (rt0 * 16 + l16) * LDX + l4;
+#pragma unroll
+          for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (rt0 + u < T / 16)
+                sacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u * 16 * LDX + 4 * ks],
+                                                               bf[q][ks], sacc[u], 0, 0, 0);
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (rt0 + u < T / 16)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                Ss[((rt0 + u) * 16 + 4 * l4 + r) * LDS + ct * 16 + l16] = sacc[u][r] * sacc[u][r];
+        }
+      }
+    }
+    __syncthreads();
+    // R1 += X_t^T S^2: for every 4-row step, one instruction per owned tile
+#pragma unroll
+    for (int rs = 0; rs < T / 4; ++rs) {
+      const float* xa = Xs + (rs * 4 + l4) * LDX + l16;
+      const float* sb = Ss + (rs * 4 + l4) * LDS + l16;
+#pragma unroll
+      for (int q = 0; q < RT; ++q) {
+        const int t = wave + 4 * q;
+        if (t < NRT)
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[(t / NCT) * 16], sb[(t % NCT) * 16],
+                                                        acc[q], 0, 0, 0);
+      }
+    }
+  }
+  float* out = partial + (size_t)blockIdx.x * D * K;
+#pragma unroll
+  for (int q = 0; q < RT; ++q) {
+    const int t = wave + 4 * q;
+    if (t < NRT) {
+      const int k = (t % NCT) * 16 + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int d = (t / NCT) * 16 + 4 * l4 + r;
+        if (d < D && k < K) out[d * K + k] = acc[q][r];
+      }
+    }
+  }
+}
+
+// Gradient and update.  Block b owns 64 consecutive entries e = d*K + k of
+// the D x K result; its 16 waves add the partials of blocks w, w + 16, ...
+// (one lane per entry, FP64, four independent chains) and the 16 wave sums
+// are combined in wave order, giving R1.  Then
+//   grad = 3(1+theta) P - 3 c3 / n R1,   Phi <- Phi - beta grad
+// entry by entry (P = Phi (Phi^T Phi * Phi^T Phi) comes from k_cp_penalty,
+// which ran before, so no entry of Phi is read after it is updated).
 // n == 0 gives a zero gradient and leaves Phi unchanged.
-__global__ void __launch_bounds__(256) k_cp_finalize(const float* __restrict__ partial, int nblk,
-                                                     const int* __restrict__ n_kept, int n_rows,
-                                                     float* __restrict__ Phi, int D, int K,
-                                                     double alpha0, double theta, float beta,
-                                                     float* __restrict__ grad,
-                                                     double* __restrict__ R1,
-                                                     int* __restrict__ sync) {
-  __shared__ int is_last;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = n_kept != nullptr ? *n_kept : n_rows;
-  if (e < D * K) {
-    const int d = e / K, k = e % K;
-    double r = 0.0;
-    for (int b = 0; b < nblk; ++b) r += (double)partial[(size_t)b * D * K + e];
-    R1[e] = r;
+__global__ void __launch_bounds__(1024) k_cp_finalize(const float* __restrict__ partial, int nblk,
+                                                      const int* __restrict__ n_kept, int n_rows,
+                                                      float* __restrict__ Phi,
+                                                      const double* __restrict__ P, int D, int K,
+                                                      double alpha0, double theta, float beta,
+                                                      float* __restrict__ grad,
+                                                      double* __restrict__ R1) {
+  __shared__ double red[16][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int DK = D * K;
+  const int e = blockIdx.x * 64 + lane;
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+  if (e < DK) {
+    int b = wave;
+    for (; b + 48 < nblk; b += 64) {
+      r0 += (double)partial[(size_t)b * DK + e];
+      r1 += (double)partial[(size_t)(b + 16) * DK + e];
+      r2 += (double)partial[(size_t)(b + 32) * DK + e];
+      r3 += (double)partial[(size_t)(b + 48) * DK + e];
+    }
+    for (; b < nblk; b += 16) r0 += (double)partial[(size_t)b * DK + e];
+  }
+  red[wave][lane] = (r0 + r1) + (r2 + r3);
+  __syncthreads();
+  if (wave == 0 && e < DK) {
+    double tot = 0.0;
+    for (int w = 0; w < 16; ++w) tot += red[w][lane];
+    R1[e] = tot;
+    const int n = n_kept != nullptr ? *n_kept : n_rows;
     if (n <= 0) {
       grad[e] = 0.f;
     } else {
-      double pen = 0.0;
-      for (int j = 0; j < K; ++j) {
-        double g = 0.0;
-        for (int q = 0; q < D; ++q) g += (double)Phi[q * K + j] * (double)Phi[q * K + k];
-        pen += (double)Phi[d * K + j] * g * g;
-      }
       const double c3 = (alpha0 + 1.0) * (alpha0 + 2.0) / 2.0;
-      grad[e] = (float)(3.0 * (1.0 + theta) * pen - 3.0 * c3 / (double)n * r);
+      const float g = (float)(3.0 * (1.0 + theta) * P[e] - 3.0 * c3 / (double)n * tot);
+      grad[e] = g;
+      Phi[e] = fmaf(-beta, g, Phi[e]);
     }
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) is_last = (atomicAdd(sync, 1) == (int)gridDim.x - 1) ? 1 : 0;
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  if (n > 0)
-    for (int i = threadIdx.x; i < D * K; i += blockDim.x)
-      Phi[i] = fmaf(-beta, __builtin_nontemporal_load(grad + i), Phi[i]);
-  if (threadIdx.x == 0) atomicExch(sync, 0);
 }
 
 }  // namespace
 
-// Row-tile height for the reduction: the largest of 64, 32, 16, 8, 4 whose
-// LDS footprint (Phi + X tile + S tile) stays within 64 KiB.
-int cp_tile_rows(int D, int K) {
+// LDS bytes of the reduction kernel for a row tile of T rows: Phi and the X
+// and S tiles.
+size_t cp_lds_bytes(int D, int K, int T) {
   const int Dq = (D + 3) & ~3, Kq = (K + 3) & ~3;
-  for (int T = 64; T >= 4; T >>= 1) {
-    const size_t bytes = sizeof(float) * ((size_t)Dq * Kq + (size_t)T * (Dq + Kq));
-    if (bytes <= 65536) return T;
-  }
+  return sizeof(float) * ((size_t)Dq * Kq + (size_t)T * (Dq + Kq));
+}
+
+// Row-tile height for the reduction: the largest of 64, 32, 16, 8, 4 whose
+// LDS footprint stays within 64 KiB.
+int cp_tile_rows(int D, int K) {
+  for (int T = 64; T >= 4; T >>= 1)
+    if (cp_lds_bytes(D, K, T) <= 65536) return T;
   return 0;
 }
 
-int cp_num_blocks(int n_rows, int D, int K) {
-  const int T = cp_tile_rows(D, K);
+// Padded size of a dimension for the matrix-core reduction: the smallest of
+// 16, 32, 64, 112, 128 that holds it (0: too large).
+int mfma_bucket(int n) {
+  const int q = (n + 15) & ~15;
+  if (q <= 16) return 16;
+  if (q <= 32) return 32;
+  if (q <= 64) return 64;
+  if (q <= 112) return 112;
+  if (q <= 128) return 128;
+  return 0;
+}
+
+// Row tile of the matrix-core reduction for padded shape (dq, kq): 64 rows
+// unless the X and S tiles would pass 48 KiB of LDS, then 32 (0: shape not
+// supported by it).
+int cp_mfma_tile_rows(int D, int K) {
+  const int dq = mfma_bucket(D), kq = mfma_bucket(K);
+  if (dq == 0 || kq == 0) return 0;
+  return (size_t)64 * (dq + kq + 8) * sizeof(float) <= 49152 ? 64 : 32;
+}
+
+int cp_resident_blocks(int D, int K, int num_cu) {
+  const int Tm = cp_mfma_tile_rows(D, K);
+  int per_cu = 0;
+  hipError_t e = hipSuccess;
+  if (Tm > 0) {
+    const int dq = mfma_bucket(D), kq = mfma_bucket(K);
+#define TLDA_OCC(DQ_, KQ_)                                                                      \
+  if (dq == DQ_ && kq == KQ_)                                                                   \
+    e = Tm == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
+                       &per_cu, k_cp_reduce_mfma<DQ_, KQ_, 64>, kThreads, 0)                    \
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
+                       &per_cu, k_cp_reduce_mfma<DQ_, KQ_, 32>, kThreads, 0);
+#define TLDA_OCC_ROW(DQ_) \
+  TLDA_OCC(DQ_, 16) TLDA_OCC(DQ_, 32) TLDA_OCC(DQ_, 64) TLDA_OCC(DQ_, 112) TLDA_OCC(DQ_, 128)
+    TLDA_OCC_ROW(16) TLDA_OCC_ROW(32) TLDA_OCC_ROW(64) TLDA_OCC_ROW(112) TLDA_OCC_ROW(128)
+#undef TLDA_OCC_ROW
+#undef TLDA_OCC
+  } else {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cp_reduce, kThreads,
+                                                      cp_lds_bytes(D, K, cp_tile_rows(D, K)));
+  }
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  return per_cu * num_cu;
+}
+
+int cp_num_blocks(int n_rows, int D, int K, int max_blocks) {
+  if (max_blocks <= 0) max_blocks = 1024;
+  const int Tm = cp_mfma_tile_rows(D, K);
+  const int T = Tm > 0 ? Tm : cp_tile_rows(D, K);
   const int ntiles = (n_rows + T - 1) / T;
-  return ntiles < 1024 ? (ntiles < 1 ? 1 : ntiles) : 1024;
+  return ntiles < max_blocks ? (ntiles < 1 ? 1 : ntiles) : max_blocks;
 }
 
 hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D, int K, int nblk,
-                            float* partial, hipStream_t s) {
-  const int T = cp_tile_rows(D, K);
-  const int Dq = (D + 3) & ~3, Kq = (K + 3) & ~3;
-  const size_t bytes = sizeof(float) * ((size_t)Dq * Kq + (size_t)T * (Dq + Kq));
-  hipLaunchKernelGGL(k_cp_reduce, dim3(nblk), dim3(kThreads), bytes, s, X, n_rows, Phi, D, K, T,
-                     nblk, partial);
+                            float* partial, double* P, hipStream_t s) {
+  const int Tm = cp_mfma_tile_rows(D, K);
+  if (Tm > 0) {
+    const int dq = mfma_bucket(D), kq = mfma_bucket(K);
+#define TLDA_MFMA(DQ_, KQ_)                                                                   \
+  if (dq == DQ_ && kq == KQ_) {                                                               \
+    if (Tm == 64)                                                                             \
+      hipLaunchKernelGGL((k_cp_reduce_mfma<DQ_, KQ_, 64>), dim3(nblk), dim3(kThreads), 0, s, X, \
+                         n_rows, Phi, D, K, nblk, partial);                                   \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_cp_reduce_mfma<DQ_, KQ_, 32>), dim3(nblk), dim3(kThreads), 0, s, X, \
+                         n_rows, Phi, D, K, nblk, partial);                                   \
+  }
+#define TLDA_MFMA_ROW(DQ_) \
+  TLDA_MFMA(DQ_, 16) TLDA_MFMA(DQ_, 32) TLDA_MFMA(DQ_, 64) TLDA_MFMA(DQ_, 112) TLDA_MFMA(DQ_, 128)
+    TLDA_MFMA_ROW(16) TLDA_MFMA_ROW(32) TLDA_MFMA_ROW(64) TLDA_MFMA_ROW(112) TLDA_MFMA_ROW(128)
+#undef TLDA_MFMA_ROW
+#undef TLDA_MFMA
+  } else {
+    const int T = cp_tile_rows(D, K);
+    hipLaunchKernelGGL(k_cp_reduce, dim3(nblk), dim3(kThreads), cp_lds_bytes(D, K, T), s, X,
+                       n_rows, Phi, D, K, T, nblk, partial);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t pbytes = sizeof(double) * K + sizeof(float) * (size_t)D * K;
+  if (pbytes <= 65536)
+    hipLaunchKernelGGL(k_cp_penalty<true>, dim3(K), dim3(kThreads), pbytes, s, Phi, D, K, P);
+  else
+    hipLaunchKernelGGL(k_cp_penalty<false>, dim3(K), dim3(kThreads), sizeof(double) * K, s, Phi,
+                       D, K, P);
   return hipGetLastError();
 }
-
 hipError_t launch_cp_finalize(const float* partial, int nblk, const int* n_kept, int n_rows,
                               float* Phi, float* grad, int D, int K, double alpha0, double theta,
-                              float beta, double* R1, int* sync, hipStream_t s) {
-  hipLaunchKernelGGL(k_cp_finalize, dim3((D * K + 255) / 256), dim3(256), 0, s, partial, nblk,
-                     n_kept, n_rows, Phi, D, K, alpha0, theta, beta, grad, R1, sync);
+                              float beta, double* R1, const double* P, hipStream_t s) {
+  hipLaunchKernelGGL(k_cp_finalize, dim3((D * K + 63) / 64), dim3(1024), 0, s, partial, nblk,
+                     n_kept, n_rows, Phi, P, D, K, alpha0, theta, beta, grad, R1);
   return hipGetLastError();
 }
 

@@ -190,13 +190,18 @@ __global__ void __launch_bounds__(256) k_tri_inverse_t(const double* __restrict_
 
 // Cyclic Jacobi with the round-robin parallel ordering: in each round the
 // m/2 disjoint pairs (circle method) are rotated at once, so every pair of
-// indices is visited once per sweep.  A (p x p, symmetric) is diagonalised in
-// place; Z accumulates the rotations; ev receives the diagonal.
+// indices is visited once per sweep.  A pair is rotated only while its
+// off-diagonal entry is significant relative to its diagonal entries
+// (|a_ij| > 1e-15 sqrt|a_ii a_jj|) and to the matrix (|a_ij| > 1e-20 |A|_F);
+// a sweep without rotations ends the iteration.  A (p x p, symmetric) is
+// diagonalised in place, Z accumulates the rotations, ev gets the diagonal.
+// info |= 2 if 60 sweeps leave an off-diagonal mass above 1e-10 |A|_F.
 __global__ void __launch_bounds__(1024) k_jacobi(double* __restrict__ A, double* __restrict__ Z,
                                                  double* __restrict__ ev, int p,
                                                  int* __restrict__ info) {
-  extern __shared__ double sh[];   // c[m/2], s[m/2], then reduction scratch
-  __shared__ int sh_done;
+  extern __shared__ double sh[];   // c[m/2], s[m/2], pair indices, reduction scratch
+  __shared__ int sh_rot;
+  __shared__ double sh_norm;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int m = (p + 1) & ~1;
   const int half = m / 2;
@@ -204,31 +209,24 @@ __global__ void __launch_bounds__(1024) k_jacobi(double* __restrict__ A, double*
   double* sn = sh + half;
   int* pi = reinterpret_cast<int*>(sh + 2 * half);
   int* pj = pi + half;
-  double* red = sh + 3 * half;     // nt doubles
+  double* red = sh + 3 * half;     // 2 * nt doubles
   for (int idx = tid; idx < p * p; idx += nt) Z[idx] = (idx / p == idx % p) ? 1.0 : 0.0;
+  // Frobenius norm (invariant under the rotations)
+  double tot = 0.0;
+  for (int idx = tid; idx < p * p; idx += nt) tot += A[idx] * A[idx];
+  red[tid] = tot;
+  __syncthreads();
+  for (int w = nt / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) sh_norm = sqrt(red[0]);
   __threadfence_block();
   __syncthreads();
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    // convergence test: off-diagonal mass against total mass
-    double off = 0.0, tot = 0.0;
-    for (int idx = tid; idx < p * p; idx += nt) {
-      const double v = A[idx];
-      tot += v * v;
-      if (idx / p != idx % p) off += v * v;
-    }
-    red[tid] = off;
-    red[nt + tid] = tot;
+  const double tiny = 1e-20 * sh_norm;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) sh_rot = 0;
     __syncthreads();
-    for (int w = nt / 2; w > 0; w >>= 1) {
-      if (tid < w) {
-        red[tid] += red[tid + w];
-        red[nt + tid] += red[nt + tid + w];
-      }
-      __syncthreads();
-    }
-    if (tid == 0) sh_done = (red[0] <= 1e-30 * red[nt] || red[nt] == 0.0) ? 1 : 0;
-    __syncthreads();
-    if (sh_done) break;
     for (int r = 0; r < m - 1; ++r) {
       for (int k = tid; k < half; k += nt) {
         int i, j;
@@ -241,11 +239,13 @@ __global__ void __launch_bounds__(1024) k_jacobi(double* __restrict__ A, double*
         double c = 1.0, s = 0.0;
         if (j < p) {
           const double aij = A[(size_t)i * p + j];
-          if (aij != 0.0) {
-            const double tau = (A[(size_t)j * p + j] - A[(size_t)i * p + i]) / (2.0 * aij);
+          const double aii = A[(size_t)i * p + i], ajj = A[(size_t)j * p + j];
+          if (fabs(aij) > tiny && fabs(aij) > 1e-15 * sqrt(fabs(aii * ajj))) {
+            const double tau = (ajj - aii) / (2.0 * aij);
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
+            sh_rot = 1;
           }
         }
         pi[k] = i;
@@ -258,8 +258,9 @@ __global__ void __launch_bounds__(1024) k_jacobi(double* __restrict__ A, double*
       for (int idx = tid; idx < half * p; idx += nt) {
         const int k = idx / p, row = idx % p;
         const int i = pi[k], j = pj[k];
-        if (j >= p) continue;
-        const double c = cs[k], s = sn[k];
+        const double s = sn[k];
+        if (j >= p || s == 0.0) continue;
+        const double c = cs[k];
         const double ai = A[(size_t)row * p + i], aj = A[(size_t)row * p + j];
         A[(size_t)row * p + i] = c * ai - s * aj;
         A[(size_t)row * p + j] = s * ai + c * aj;
@@ -273,8 +274,9 @@ __global__ void __launch_bounds__(1024) k_jacobi(double* __restrict__ A, double*
       for (int idx = tid; idx < half * p; idx += nt) {
         const int k = idx / p, col = idx % p;
         const int i = pi[k], j = pj[k];
-        if (j >= p) continue;
-        const double c = cs[k], s = sn[k];
+        const double s = sn[k];
+        if (j >= p || s == 0.0) continue;
+        const double c = cs[k];
         const double ai = A[(size_t)i * p + col], aj = A[(size_t)j * p + col];
         A[(size_t)i * p + col] = c * ai - s * aj;
         A[(size_t)j * p + col] = s * ai + c * aj;
@@ -282,8 +284,20 @@ __global__ void __launch_bounds__(1024) k_jacobi(double* __restrict__ A, double*
       __threadfence_block();
       __syncthreads();
     }
-    if (sweep == 39 && tid == 0) atomicOr(info, 2);
+    if (sh_rot == 0) break;
+    __syncthreads();
   }
+  // final check of the remaining off-diagonal mass
+  double off = 0.0;
+  for (int idx = tid; idx < p * p; idx += nt)
+    if (idx / p != idx % p) off += A[idx] * A[idx];
+  red[tid] = off;
+  __syncthreads();
+  for (int w = nt / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0 && sqrt(red[0]) > 1e-10 * sh_norm) atomicOr(info, 2);
   for (int i = tid; i < p; i += nt) ev[i] = A[(size_t)i * p + i];
 }
 

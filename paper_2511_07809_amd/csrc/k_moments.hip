@@ -45,52 +45,92 @@ __global__ void __launch_bounds__(256) k_validate_csr(const int32_t* __restrict_
   if (wave_sum_i(bad) != 0 && lane == 0) atomicOr(err, 1);
 }
 
-// One wave per document.  Integer statistics use 64-bit integer atomics
-// (exact, order-independent); the frequency sums use FP64 atomics.  The pair
-// loop enumerates the upper triangle (j <= k) of the row's nnz positions; as
-// columns are strictly increasing, col_j <= col_k and the pair lands in the
-// upper triangle of S2.
+// One wave per document, grid-stride over the batch.  Token totals use 64-bit
+// integer atomics (exact, order-independent) and the frequency sums FP64
+// atomics.  The pair loop enumerates the upper triangle (j <= k) of the row's
+// nnz positions; as columns are strictly increasing, col_j <= col_k and the
+// pair lands in the upper triangle of S2.  Kept/dropped document counts are
+// kept per block and added by k_add_counts, so no address is hit by every row.
+constexpr int kAccMaxBlocks = kWhitenBlockCounts;
+
 __global__ void __launch_bounds__(256) k_accumulate(const int32_t* __restrict__ row_ptr,
                                                     const int32_t* __restrict__ col_idx,
                                                     const float* __restrict__ val, int n_rows,
-                                                    int V, unsigned long long* __restrict__ counts,
+                                                    int V, int* __restrict__ block_counts,
                                                     unsigned long long* __restrict__ totals,
                                                     double* __restrict__ fsum,
                                                     double* __restrict__ S2) {
+  __shared__ int kept_s[4], drop_s[4];
   const int lane = threadIdx.x & (kWave - 1);
-  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (row >= n_rows) return;
-  const int b = row_ptr[row], e = row_ptr[row + 1];
-  const int n = e - b;
-  long long part = 0;
-  for (int j = lane; j < n; j += kWave) part += (long long)val[b + j];
-  const long long L = wave_sum_ll(part);
-  if (L < 3) {
-    if (lane == 0) atomicAdd(&counts[1], 1ull);
-    return;
+  const int wave = threadIdx.x / kWave;
+  int kept = 0, dropped = 0;
+  for (int row = blockIdx.x * 4 + wave; row < n_rows; row += gridDim.x * 4) {
+    const int b = row_ptr[row], e = row_ptr[row + 1];
+    const int n = e - b;
+    long long part = 0;
+    for (int j = lane; j < n; j += kWave) part += (long long)val[b + j];
+    const long long L = wave_sum_ll(part);
+    if (L < 3) {
+      ++dropped;
+      continue;
+    }
+    ++kept;
+    const double invL = 1.0 / (double)L;
+    for (int j = lane; j < n; j += kWave) {
+      const int c = col_idx[b + j];
+      const float v = val[b + j];
+      atomicAdd(&totals[c], (unsigned long long)v);
+      unsafeAtomicAdd(&fsum[c], (double)v * invL);
+    }
+    const long long P = (long long)n * (n + 1) / 2;
+    const double tn = 2.0 * n + 1.0;
+    for (long long p = lane; p < P; p += kWave) {
+      // row j of the packed triangle starts at base(j) = j*n - j*(j-1)/2
+      int j = (int)((tn - sqrt(tn * tn - 8.0 * (double)p)) * 0.5);
+      if (j < 0) j = 0;
+      if (j > n - 1) j = n - 1;
+      while (j + 1 < n && (long long)(j + 1) * n - (long long)(j + 1) * j / 2 <= p) ++j;
+      while (j > 0 && (long long)j * n - (long long)j * (j - 1) / 2 > p) --j;
+      const long long base = (long long)j * n - (long long)j * (j - 1) / 2;
+      const int k = j + (int)(p - base);
+      const int cj = col_idx[b + j], ck = col_idx[b + k];
+      const double fj = (double)val[b + j] * invL, fk = (double)val[b + k] * invL;
+      unsafeAtomicAdd(&S2[(size_t)cj * V + ck], fj * fk);
+    }
   }
-  if (lane == 0) atomicAdd(&counts[0], 1ull);
-  const double invL = 1.0 / (double)L;
-  for (int j = lane; j < n; j += kWave) {
-    const int c = col_idx[b + j];
-    const float v = val[b + j];
-    atomicAdd(&totals[c], (unsigned long long)v);
-    unsafeAtomicAdd(&fsum[c], (double)v * invL);
+  if (lane == 0) {
+    kept_s[wave] = kept;
+    drop_s[wave] = dropped;
   }
-  const long long P = (long long)n * (n + 1) / 2;
-  const double tn = 2.0 * n + 1.0;
-  for (long long p = lane; p < P; p += kWave) {
-    // row j of the packed triangle starts at base(j) = j*n - j*(j-1)/2
-    int j = (int)((tn - sqrt(tn * tn - 8.0 * (double)p)) * 0.5);
-    if (j < 0) j = 0;
-    if (j > n - 1) j = n - 1;
-    while (j + 1 < n && (long long)(j + 1) * n - (long long)(j + 1) * j / 2 <= p) ++j;
-    while (j > 0 && (long long)j * n - (long long)j * (j - 1) / 2 > p) --j;
-    const long long base = (long long)j * n - (long long)j * (j - 1) / 2;
-    const int k = j + (int)(p - base);
-    const int cj = col_idx[b + j], ck = col_idx[b + k];
-    const double fj = (double)val[b + j] * invL, fk = (double)val[b + k] * invL;
-    unsafeAtomicAdd(&S2[(size_t)cj * V + ck], fj * fk);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    block_counts[2 * blockIdx.x] = kept_s[0] + kept_s[1] + kept_s[2] + kept_s[3];
+    block_counts[2 * blockIdx.x + 1] = drop_s[0] + drop_s[1] + drop_s[2] + drop_s[3];
+  }
+}
+
+// counts[0] += kept, counts[1] += dropped over the per-block counts (one block).
+__global__ void __launch_bounds__(256) k_add_counts(const int* __restrict__ block_counts, int nb,
+                                                    unsigned long long* __restrict__ counts) {
+  __shared__ long long rk[256], rd[256];
+  long long k = 0, d = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    k += block_counts[2 * i];
+    d += block_counts[2 * i + 1];
+  }
+  rk[threadIdx.x] = k;
+  rd[threadIdx.x] = d;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      rk[threadIdx.x] += rk[threadIdx.x + w];
+      rd[threadIdx.x] += rd[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    counts[0] += (unsigned long long)rk[0];
+    counts[1] += (unsigned long long)rd[0];
   }
 }
 
@@ -131,11 +171,16 @@ hipError_t launch_validate_csr(const tlda_csr_batch& b, int V, int* err, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_accumulate(const tlda_csr_batch& b, int V, const Moments& m, hipStream_t s) {
+hipError_t launch_accumulate(const tlda_csr_batch& b, int V, const Moments& m, int* block_counts,
+                             hipStream_t s) {
   const int rows_per_block = 256 / kWave;
-  const int grid = (b.n_rows + rows_per_block - 1) / rows_per_block;
+  int grid = (b.n_rows + rows_per_block - 1) / rows_per_block;
+  if (grid > kAccMaxBlocks) grid = kAccMaxBlocks;
   hipLaunchKernelGGL(k_accumulate, dim3(grid), dim3(256), 0, s, b.row_ptr, b.col_idx, b.val,
-                     b.n_rows, V, m.counts, m.totals, m.fsum, m.S2);
+                     b.n_rows, V, block_counts, m.totals, m.fsum, m.S2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_add_counts, dim3(1), dim3(256), 0, s, block_counts, grid, m.counts);
   return hipGetLastError();
 }
 

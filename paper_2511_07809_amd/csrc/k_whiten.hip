@@ -15,94 +15,140 @@
 namespace tlda {
 namespace {
 
-template <int G>
+// Kernel-wide count of kept rows without same-address device atomics (which
+// serialise across the XCDs): every block stores its own count, and a
+// one-block kernel adds the counts in block order.
+constexpr int kWhitenMaxBlocks = kWhitenBlockCounts;
+
+// 16-byte gather of W32 at a 32-bit byte offset (W32 is far below 4 GiB).
+__device__ inline float4 ld_b128(const float* __restrict__ base, int byte_off) {
+  return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+// G lanes per document, V4 float4 columns per lane.
+template <int G, int V4>
 __global__ void __launch_bounds__(256) k_whiten(const int32_t* __restrict__ row_ptr,
                                                 const int32_t* __restrict__ col_idx,
                                                 const float* __restrict__ val, int n_rows,
-                                                const float* __restrict__ W32,
+                                                const float* __restrict__ W32, int V,
                                                 const float* __restrict__ mw32, int D, int Dp,
-                                                float* __restrict__ X, int* __restrict__ n_kept,
-                                                int* __restrict__ sync) {
+                                                int S, float* __restrict__ X,
+                                                int* __restrict__ block_counts) {
   constexpr int RPW = 64 / G;
-  __shared__ int block_kept;
-  if (threadIdx.x == 0) block_kept = 0;
-  __syncthreads();
+  constexpr int RPB = 4 * RPW;                  // rows per block per sweep
+  constexpr int NB = 16 / V4;                   // nonzeros per step of a row
+  constexpr int SLOTS = G >= NB ? 1 : NB / G;   // nonzeros each lane fetches per step
+  __shared__ int wave_kept[4];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int gl = lane % G;
-  const int row = (blockIdx.x * 4 + wave) * RPW + lane / G;
-  const int c4 = gl * 4;                       // first of this lane's four columns
-  const bool active = c4 < Dp;
-  int kept = 0;
-  if (row < n_rows) {
-    const int b = row_ptr[row], e = row_ptr[row + 1];
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    float L = 0.f;
-    int j = b;
-    for (; j + 4 <= e; j += 4) {
-      const int i0 = col_idx[j], i1 = col_idx[j + 1], i2 = col_idx[j + 2], i3 = col_idx[j + 3];
-      const float v0 = val[j], v1 = val[j + 1], v2 = val[j + 2], v3 = val[j + 3];
-      float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f), w1 = w0, w2 = w0, w3 = w0;
-      if (active) {
-        w0 = *reinterpret_cast<const float4*>(W32 + (size_t)i0 * Dp + c4);
-        w1 = *reinterpret_cast<const float4*>(W32 + (size_t)i1 * Dp + c4);
-        w2 = *reinterpret_cast<const float4*>(W32 + (size_t)i2 * Dp + c4);
-        w3 = *reinterpret_cast<const float4*>(W32 + (size_t)i3 * Dp + c4);
+  // Column chunk of this block: workgroups go round-robin to the 8 XCDs, so
+  // block b runs on XCD b % 8 and chunk b % S keeps every XCD on one slice of
+  // W (Dp / S columns), which then stays in that XCD's L2.
+  const int chunk = blockIdx.x % S;
+  const int c0 = chunk * (Dp / S) + gl * 4 * V4;   // first of this lane's columns
+  const bool active = gl * 4 * V4 < Dp / S;
+  const int nblk_chunk = gridDim.x / S;
+  int kept_total = 0;
+  for (int base = (blockIdx.x / S) * RPB; base < n_rows; base += nblk_chunk * RPB) {
+    const int row = base + wave * RPW + lane / G;
+    const bool valid = row < n_rows;
+    int b = 0, e = 0;
+    if (valid) {
+      b = row_ptr[row];
+      e = row_ptr[row + 1];
+    }
+    float4 acc[V4];
+#pragma unroll
+    for (int v = 0; v < V4; ++v) acc[v] = make_float4(0.f, 0.f, 0.f, 0.f);
+    float Lp = 0.f;
+    // Step through the row NB nonzeros at a time: the G lanes of the row fetch
+    // the step's (column, count) pairs together (one memory round trip), pass
+    // them around with lane shuffles, and issue all of the step's W-row
+    // gathers before using any of them.
+    for (int jb = b; jb < e; jb += NB) {
+      int cidx[SLOTS];
+      float cval[SLOTS];
+#pragma unroll
+      for (int q = 0; q < SLOTS; ++q) {
+        const int j = jb + q * G + gl;
+        const bool in = (q * G + gl) < NB && j < e;
+        cidx[q] = in ? col_idx[j] : 0;
+        cval[q] = in ? val[j] : 0.f;
+        Lp += cval[q];
       }
-      acc.x = fmaf(v0, w0.x, acc.x); acc.y = fmaf(v0, w0.y, acc.y);
-      acc.z = fmaf(v0, w0.z, acc.z); acc.w = fmaf(v0, w0.w, acc.w);
-      acc.x = fmaf(v1, w1.x, acc.x); acc.y = fmaf(v1, w1.y, acc.y);
-      acc.z = fmaf(v1, w1.z, acc.z); acc.w = fmaf(v1, w1.w, acc.w);
-      acc.x = fmaf(v2, w2.x, acc.x); acc.y = fmaf(v2, w2.y, acc.y);
-      acc.z = fmaf(v2, w2.z, acc.z); acc.w = fmaf(v2, w2.w, acc.w);
-      acc.x = fmaf(v3, w3.x, acc.x); acc.y = fmaf(v3, w3.y, acc.y);
-      acc.z = fmaf(v3, w3.z, acc.z); acc.w = fmaf(v3, w3.w, acc.w);
-      L += (v0 + v1) + (v2 + v3);
+      float4 w[NB][V4];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        const int c = G == 1 ? cidx[t] : __shfl(cidx[t / G < SLOTS ? t / G : 0], t % G, G);
+        const int off = (c * Dp + c0) * (int)sizeof(float);
+#pragma unroll
+        for (int v = 0; v < V4; ++v) {
+          w[t][v] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (active && jb + t < e) w[t][v] = ld_b128(W32, off + 16 * v);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        const float x = G == 1 ? cval[t] : __shfl(cval[t / G < SLOTS ? t / G : 0], t % G, G);
+#pragma unroll
+        for (int v = 0; v < V4; ++v) {
+          acc[v].x = fmaf(x, w[t][v].x, acc[v].x);
+          acc[v].y = fmaf(x, w[t][v].y, acc[v].y);
+          acc[v].z = fmaf(x, w[t][v].z, acc[v].z);
+          acc[v].w = fmaf(x, w[t][v].w, acc[v].w);
+        }
+      }
     }
-    for (; j < e; ++j) {
-      const int i0 = col_idx[j];
-      const float v0 = val[j];
-      float4 w0 = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (active) w0 = *reinterpret_cast<const float4*>(W32 + (size_t)i0 * Dp + c4);
-      acc.x = fmaf(v0, w0.x, acc.x); acc.y = fmaf(v0, w0.y, acc.y);
-      acc.z = fmaf(v0, w0.z, acc.z); acc.w = fmaf(v0, w0.w, acc.w);
-      L += v0;
-    }
-    float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (L >= 3.f) {
-      kept = 1;
+    // document length: sum of the lanes' partial counts within the group
+    float L = Lp;
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) L += __shfl_xor(L, off, G);
+    int kept = 0;
+    if (valid) {
+      if (L >= 3.f) kept = 1;
       if (active) {
         const float invL = 1.0f / L;
-        const float4 mw = *reinterpret_cast<const float4*>(mw32 + c4);
-        x.x = fmaf(acc.x, invL, -mw.x);
-        x.y = fmaf(acc.y, invL, -mw.y);
-        x.z = fmaf(acc.z, invL, -mw.z);
-        x.w = fmaf(acc.w, invL, -mw.w);
+        float* out = X + (size_t)row * D;
+#pragma unroll
+        for (int v = 0; v < V4; ++v) {
+          const int c4 = c0 + 4 * v;
+          float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (kept) {
+            const float4 mw = *reinterpret_cast<const float4*>(mw32 + c4);
+            x.x = fmaf(acc[v].x, invL, -mw.x);
+            x.y = fmaf(acc[v].y, invL, -mw.y);
+            x.z = fmaf(acc[v].z, invL, -mw.z);
+            x.w = fmaf(acc[v].w, invL, -mw.w);
+          }
+          if (c4 + 0 < D) out[c4 + 0] = x.x;
+          if (c4 + 1 < D) out[c4 + 1] = x.y;
+          if (c4 + 2 < D) out[c4 + 2] = x.z;
+          if (c4 + 3 < D) out[c4 + 3] = x.w;
+        }
       }
     }
-    float* out = X + (size_t)row * D;
-    if (c4 + 0 < D) out[c4 + 0] = x.x;
-    if (c4 + 1 < D) out[c4 + 1] = x.y;
-    if (c4 + 2 < D) out[c4 + 2] = x.z;
-    if (c4 + 3 < D) out[c4 + 3] = x.w;
+    kept_total += __popcll(__ballot(kept && gl == 0));
   }
-  if (n_kept == nullptr) return;
-  // kept-row count: per-block sum, then one device atomic per block; the last
-  // block to finish publishes the total and re-arms the counters (sync[0]:
-  // running sum, sync[1]: finished blocks) for the next call on this context
-  const unsigned long long mask = __ballot(kept && gl == 0);
-  if (lane == 0 && mask != 0ull) atomicAdd(&block_kept, (int)__popcll(mask));
+  if (lane == 0) wave_kept[wave] = kept_total;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    atomicAdd(&sync[0], block_kept);
-    __threadfence();
-    const int done = atomicAdd(&sync[1], 1);
-    if (done == (int)gridDim.x - 1) {
-      __threadfence();
-      *n_kept = atomicExch(&sync[0], 0);
-      atomicExch(&sync[1], 0);
-    }
+  if (threadIdx.x == 0)
+    block_counts[blockIdx.x] =
+        chunk == 0 ? wave_kept[0] + wave_kept[1] + wave_kept[2] + wave_kept[3] : 0;
+}
+
+__global__ void __launch_bounds__(256) k_sum_counts(const int* __restrict__ block_counts, int n,
+                                                    int* __restrict__ out) {
+  __shared__ int red[256];
+  int s = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += block_counts[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *out = red[0];
 }
 
 __global__ void k_zero(uint32_t* __restrict__ p, size_t n) {
@@ -115,13 +161,18 @@ __global__ void k_zero_bytes(unsigned char* __restrict__ p, size_t n) {
   if (i < n) p[i] = 0u;
 }
 
-template <int G>
-hipError_t launch_g(const tlda_csr_batch& b, const float* W32, const float* mw32, int D, int Dp,
-                    float* X, int* n_kept, int* sync, hipStream_t s) {
+template <int G, int V4>
+hipError_t launch_g(const tlda_csr_batch& b, const float* W32, int V, const float* mw32, int D,
+                    int Dp, int S, float* X, int* n_kept, int* block_counts, hipStream_t s) {
   const int rows_per_block = 4 * (64 / G);
-  const int grid = (b.n_rows + rows_per_block - 1) / rows_per_block;
-  hipLaunchKernelGGL(k_whiten<G>, dim3(grid), dim3(256), 0, s, b.row_ptr, b.col_idx, b.val,
-                     b.n_rows, W32, mw32, D, Dp, X, n_kept, sync);
+  int per_chunk = (b.n_rows + rows_per_block - 1) / rows_per_block;
+  if (per_chunk * S > kWhitenMaxBlocks) per_chunk = kWhitenMaxBlocks / S;
+  const int grid = per_chunk * S;
+  hipLaunchKernelGGL((k_whiten<G, V4>), dim3(grid), dim3(256), 0, s, b.row_ptr, b.col_idx, b.val,
+                     b.n_rows, W32, V, mw32, D, Dp, S, X, block_counts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n_kept == nullptr) return e;
+  hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(256), 0, s, block_counts, grid, n_kept);
   return hipGetLastError();
 }
 
@@ -140,16 +191,46 @@ hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_whiten(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
-                         int Dp, float* X, int* n_kept, int* sync, hipStream_t s) {
+// Number of column chunks of the whitening: the smallest of 1, 2, 4, 8 that
+// makes one chunk of the FP32 W copy (V x Dp/S floats) fit in 3 MiB, the L2
+// share an XCD can spare beside the streaming CSR and X traffic, with at least
+// four columns per chunk.
+int whiten_chunks(int V, int Dp) {
+  int S = 1;
+  while (S < 8 && (size_t)V * (Dp / S) * sizeof(float) > (3u << 20) && (Dp / (2 * S)) % 4 == 0)
+    S *= 2;
+  return S;
+}
+
+hipError_t launch_whiten(const tlda_csr_batch& b, const float* W32, const float* mw32, int V, int D,
+                         int Dp, float* X, int* n_kept, int* block_counts, const Tuning& t,
+                         hipStream_t s) {
   if (b.n_rows == 0) return n_kept != nullptr ? launch_zero(n_kept, sizeof(int), s) : hipSuccess;
-  const int q = Dp / 4;   // float4 columns per row, Dp is a multiple of 4 and <= 256
-  if (q <= 2) return launch_g<2>(b, W32, mw32, D, Dp, X, n_kept, sync, s);
-  if (q <= 4) return launch_g<4>(b, W32, mw32, D, Dp, X, n_kept, sync, s);
-  if (q <= 8) return launch_g<8>(b, W32, mw32, D, Dp, X, n_kept, sync, s);
-  if (q <= 16) return launch_g<16>(b, W32, mw32, D, Dp, X, n_kept, sync, s);
-  if (q <= 32) return launch_g<32>(b, W32, mw32, D, Dp, X, n_kept, sync, s);
-  return launch_g<64>(b, W32, mw32, D, Dp, X, n_kept, sync, s);
+  // Measured on MI355X at V = 20 000, D = 50: one chunk and one float4 per
+  // lane is fastest; the XCD column split and two float4 per lane are kept as
+  // tuning options.
+  int S = 1;
+  if (t.whiten_chunks < 0) S = whiten_chunks(V, Dp);
+  if (t.whiten_chunks == 2 || t.whiten_chunks == 4 || t.whiten_chunks == 8)
+    if ((Dp / t.whiten_chunks) % 4 == 0) S = t.whiten_chunks;
+  const int wc = Dp / S;   // columns per chunk, a multiple of 4
+  if (wc % 8 == 0 && t.whiten_v4 == 2) {
+    const int g = wc / 8;
+    if (g <= 1) return launch_g<1, 2>(b, W32, V, mw32, D, Dp, S, X, n_kept, block_counts, s);
+    if (g <= 2) return launch_g<2, 2>(b, W32, V, mw32, D, Dp, S, X, n_kept, block_counts, s);
+    if (g <= 4) return launch_g<4, 2>(b, W32, V, mw32, D, Dp, S, X, n_kept, block_counts, s);
+    if (g <= 8) return launch_g<8, 2>(b, W32, V, mw32, D, Dp, S, X, n_kept, block_counts, s);
+    if (g <= 16) return launch_g<16, 2>(b, W32, V, mw32, D, Dp, S, X, n_kept, block_counts, s);
+    return launch_g<32, 2>(b, W32, V, mw32, D, Dp, S, X, n_kept, block_counts, s);
+  }
+  const int g = wc / 4;
+  if (g <= 1) return launch_g<1, 1>(b, W32, V, mw32, D, Dp, S, X, n_kept, block_counts, s);
+  if (g <= 2) return launch_g<2, 1>(b, W32, V, mw32, D, Dp, S, X, n_kept, block_counts, s);
+  if (g <= 4) return launch_g<4, 1>(b, W32, V, mw32, D, Dp, S, X, n_kept, block_counts, s);
+  if (g <= 8) return launch_g<8, 1>(b, W32, V, mw32, D, Dp, S, X, n_kept, block_counts, s);
+  if (g <= 16) return launch_g<16, 1>(b, W32, V, mw32, D, Dp, S, X, n_kept, block_counts, s);
+  if (g <= 32) return launch_g<32, 1>(b, W32, V, mw32, D, Dp, S, X, n_kept, block_counts, s);
+  return launch_g<64, 1>(b, W32, V, mw32, D, Dp, S, X, n_kept, block_counts, s);
 }
 
 }  // namespace tlda

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/tlda.h: argument checks, device
 // state, stream ordering, the whitening refresh driver and checkpoints.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -188,7 +189,9 @@ tlda_status refresh(tlda_ctx* c) {
   HIP_OK(c, hipMemcpyAsync(info, e.info, sizeof(info), hipMemcpyDeviceToHost, c->stream));
   HIP_OK(c, hipMemcpyAsync(eigD.data(), e.sel, sizeof(double) * D, hipMemcpyDeviceToHost, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
-  CHECK_ARG(c, info[0] == 0, TLDA_ERR_NUMERIC, "eigen-solver did not converge or factorisation failed");
+  CHECK_ARG(c, (info[0] & 1) == 0, TLDA_ERR_NUMERIC,
+            "Cholesky-QR of the subspace block failed (non-positive pivot)");
+  CHECK_ARG(c, (info[0] & 2) == 0, TLDA_ERR_NUMERIC, "Jacobi eigen-solver did not converge");
   for (int d = 0; d < D; ++d)
     CHECK_ARG(c, std::isfinite(eigD[d]) && eigD[d] > 0.0, TLDA_ERR_NUMERIC,
               "M2~ has fewer than D positive eigenvalues; lower D");
@@ -212,9 +215,9 @@ void destroy_all(tlda_ctx* c) {
   tlda::EigScratch& e = c->eig;
   dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
   dfree(e.sel); dfree(e.mcand); dfree(e.info);
-  dfree(c->cp.partial); dfree(c->cp.R1); dfree(c->cp.grad);
+  dfree(c->cp.partial); dfree(c->cp.R1); dfree(c->cp.P); dfree(c->cp.grad);
   dfree(c->post); dfree(c->postA); dfree(c->postG); dfree(c->postZ); dfree(c->postEv);
-  dfree(c->A32); dfree(c->G32); dfree(c->step32); dfree(c->dev_flags); dfree(c->sync);
+  dfree(c->A32); dfree(c->G32); dfree(c->step32); dfree(c->dev_flags); dfree(c->block_counts);
   for (auto& s : c->slots) {
     if (s.free_) (void)hipEventSynchronize(s.free_);
     dfree(s.row_ptr); dfree(s.col_idx); dfree(s.val);
@@ -263,6 +266,13 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
   if (!ctx) return TLDA_ERR_OOM;
   ctx->cfg = c;
   ctx->Dp = tlda::padded_d(c.D);
+  auto env_int = [](const char* name) {
+    const char* v = std::getenv(name);
+    return v ? std::atoi(v) : 0;
+  };
+  ctx->tune.cp_max_blocks = env_int("TLDA_TUNE_CP_BLOCKS");
+  ctx->tune.whiten_v4 = env_int("TLDA_TUNE_WHITEN_V4");
+  ctx->tune.whiten_chunks = env_int("TLDA_TUNE_WHITEN_CHUNKS");
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   auto fail = [&](tlda_status s) {
     destroy_all(ctx);
@@ -286,18 +296,17 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
             dalloc(&ctx->wh.m, V) == hipSuccess &&
             dalloc(&ctx->wh.W32, V * (size_t)ctx->Dp) == hipSuccess &&
             dalloc(&ctx->wh.mw32, (size_t)ctx->Dp) == hipSuccess &&
-            dalloc(&ctx->cp.R1, D * K) == hipSuccess &&
+            dalloc(&ctx->cp.R1, D * K) == hipSuccess && dalloc(&ctx->cp.P, D * K) == hipSuccess &&
             dalloc(&ctx->cp.grad, D * K) == hipSuccess && dalloc(&ctx->post, K) == hipSuccess &&
             dalloc(&ctx->postA, D * K) == hipSuccess && dalloc(&ctx->postG, K * K) == hipSuccess &&
             dalloc(&ctx->postZ, K * K) == hipSuccess && dalloc(&ctx->postEv, K) == hipSuccess &&
             dalloc(&ctx->A32, D * K) == hipSuccess && dalloc(&ctx->G32, K * K) == hipSuccess &&
             dalloc(&ctx->step32, 1) == hipSuccess && dalloc(&ctx->dev_flags, 4) == hipSuccess &&
-            dalloc(&ctx->sync, 4) == hipSuccess;
+            dalloc(&ctx->block_counts, 2 * tlda::kWhitenBlockCounts) == hipSuccess;
   if (!ok) return fail(TLDA_ERR_OOM);
   if (launch_zero(ctx->mom.counts, 2 * sizeof(unsigned long long), ctx->stream) != hipSuccess ||
       launch_zero(ctx->mom.totals, V * sizeof(unsigned long long), ctx->stream) != hipSuccess ||
       launch_zero(ctx->mom.fsum, V * sizeof(double), ctx->stream) != hipSuccess ||
-      launch_zero(ctx->sync, 4 * sizeof(int), ctx->stream) != hipSuccess ||
       hipStreamSynchronize(ctx->stream) != hipSuccess)
     return fail(TLDA_ERR_DEVICE);
   *out = ctx;
@@ -329,7 +338,7 @@ tlda_status tlda_update_moments(tlda_ctx* c, const tlda_csr_batch* b, uint32_t f
   if (b && b->n_rows > 0) {
     st = begin_use(c, b);
     if (st != TLDA_OK) return st;
-    HIP_OK(c, tlda::launch_accumulate(*b, c->cfg.V, c->mom, c->stream));
+    HIP_OK(c, tlda::launch_accumulate(*b, c->cfg.V, c->mom, c->block_counts, c->stream));
     st = end_use(c, b);
     if (st != TLDA_OK) return st;
   }
@@ -347,8 +356,8 @@ tlda_status tlda_whiten_batch(tlda_ctx* c, const tlda_csr_batch* b, float* X, in
   if (st != TLDA_OK) return st;
   st = begin_use(c, b);
   if (st != TLDA_OK) return st;
-  HIP_OK(c, tlda::launch_whiten(*b, c->wh.W32, c->wh.mw32, c->cfg.D, c->Dp, X, n_kept, c->sync,
-                                c->stream));
+  HIP_OK(c, tlda::launch_whiten(*b, c->wh.W32, c->wh.mw32, c->cfg.V, c->cfg.D, c->Dp, X, n_kept,
+                                c->block_counts, c->tune, c->stream));
   return end_use(c, b);
 }
 
@@ -361,7 +370,8 @@ tlda_status tlda_cp_step(tlda_ctx* c, const float* X, int32_t n_rows, const int3
   CHECK_ARG(c, std::isfinite(beta), TLDA_ERR_ARG, "beta is not finite");
   if (n_rows == 0) return TLDA_OK;
   const int D = c->cfg.D, K = c->cfg.K;
-  const int nblk = tlda::cp_num_blocks(n_rows, D, K);
+  if (c->tune.cp_max_blocks <= 0) c->tune.cp_max_blocks = tlda::cp_resident_blocks(D, K, c->num_cu);
+  const int nblk = tlda::cp_num_blocks(n_rows, D, K, c->tune.cp_max_blocks);
   const size_t need = (size_t)nblk * D * K;
   if (c->cp.cap < need) {
     HIP_OK(c, hipStreamSynchronize(c->stream));
@@ -371,9 +381,10 @@ tlda_status tlda_cp_step(tlda_ctx* c, const float* X, int32_t n_rows, const int3
     c->cp.cap = need;
   }
   float* g = grad ? grad : c->cp.grad;
-  HIP_OK(c, tlda::launch_cp_reduce(X, n_rows, Phi, D, K, nblk, c->cp.partial, c->stream));
+  HIP_OK(c, tlda::launch_cp_reduce(X, n_rows, Phi, D, K, nblk, c->cp.partial, c->cp.P,
+                                   c->stream));
   HIP_OK(c, tlda::launch_cp_finalize(c->cp.partial, nblk, n_kept, n_rows, Phi, g, D, K,
-                                     c->cfg.alpha0, c->cfg.theta, beta, c->cp.R1, c->sync + 2,
+                                     c->cfg.alpha0, c->cfg.theta, beta, c->cp.R1, c->cp.P,
                                      c->stream));
   return TLDA_OK;
 }

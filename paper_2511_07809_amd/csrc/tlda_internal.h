@@ -11,6 +11,10 @@
 
 namespace tlda {
 
+// Per-block count scratch: the whitening and the moment kernels cap their
+// grids at this many blocks (the moment kernel stores two counts per block).
+constexpr int kWhitenBlockCounts = 2048;
+
 // Row stride (floats) of the FP32 whitening copy used for the gathers of the
 // whitening SpMM: rows are aligned to a 128-byte cache line once D >= 32, and
 // to a power of two of at least one float4 below that.
@@ -62,10 +66,23 @@ struct EigScratch {
   int* info = nullptr;     // [4]     device status words
 };
 
+// Launch-shape knobs (0 = built-in choice).  Initialised from the
+// environment (TLDA_TUNE_CP_BLOCKS, TLDA_TUNE_WHITEN_V4, TLDA_TUNE_WHITEN_CHUNKS)
+// when a context is created.  cp_max_blocks: grid of the CP reduction
+// (default: one full round of resident blocks); whiten_v4: float4 columns
+// per lane (1 or 2); whiten_chunks: XCD column chunks (1, 2, 4, 8; -1 = by
+// W size).
+struct Tuning {
+  int cp_max_blocks = 0;
+  int whiten_v4 = 0;
+  int whiten_chunks = 0;
+};
+
 struct CpScratch {
   size_t cap = 0;             // floats available in partial
   float* partial = nullptr;   // [nblk][D][K]
   double* R1 = nullptr;       // [D][K]
+  double* P = nullptr;        // [D][K] penalty Phi (Phi^T Phi * Phi^T Phi)
   float* grad = nullptr;      // [D][K] used when the caller passes no gradient buffer
 };
 
@@ -82,6 +99,7 @@ struct tlda_ctx {
   tlda::Whitening wh;
   tlda::EigScratch eig;
   tlda::CpScratch cp;
+  tlda::Tuning tune;
   tlda::StageSlot slots[2];
   double* post = nullptr;     // [K] scratch for unwhiten
   double* postA = nullptr;    // [D][K] inference matrix
@@ -92,7 +110,7 @@ struct tlda_ctx {
   float* G32 = nullptr;       // [K][K]
   float* step32 = nullptr;    // [1]
   int* dev_flags = nullptr;   // [4] CSR validation and inference status words
-  int* sync = nullptr;        // [4] last-block counters: whiten (0, 1), cp step (2)
+  int* block_counts = nullptr;  // [2 * kWhitenBlockCounts] per-block document counts
   std::string last_error;
 };
 
@@ -103,7 +121,9 @@ namespace tlda {
 hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s);
 // moments
 hipError_t launch_validate_csr(const tlda_csr_batch& b, int V, int* err, hipStream_t s);
-hipError_t launch_accumulate(const tlda_csr_batch& b, int V, const Moments& m, hipStream_t s);
+// block_counts: scratch for 2 * kWhitenBlockCounts ints
+hipError_t launch_accumulate(const tlda_csr_batch& b, int V, const Moments& m, int* block_counts,
+                             hipStream_t s);
 hipError_t launch_mirror_upper(double* S2, int V, hipStream_t s);
 hipError_t launch_mean(const double* fsum, const unsigned long long* counts, double* m, int V,
                        hipStream_t s);
@@ -126,16 +146,21 @@ hipError_t launch_form_whitening(const double* U, const double* eig, const doubl
 hipError_t launch_from_injected(const double* W, int V, int D, double* U, double* eig,
                                 hipStream_t s);
 // whitening SpMM
-hipError_t launch_whiten(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
-                         int Dp, float* X, int* n_kept, int* sync, hipStream_t s);
+// block_counts: scratch for kWhitenBlockCounts ints
+hipError_t launch_whiten(const tlda_csr_batch& b, const float* W32, const float* mw32, int V, int D,
+                         int Dp, float* X, int* n_kept, int* block_counts, const Tuning& t,
+                         hipStream_t s);
+int whiten_chunks(int V, int Dp);
 // CP step
 hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D, int K, int nblk,
-                            float* partial, hipStream_t s);
+                            float* partial, double* P, hipStream_t s);
 hipError_t launch_cp_finalize(const float* partial, int nblk, const int* n_kept, int n_rows,
                               float* Phi, float* grad, int D, int K, double alpha0, double theta,
-                              float beta, double* R1, int* sync, hipStream_t s);
+                              float beta, double* R1, const double* P, hipStream_t s);
 int cp_tile_rows(int D, int K);
-int cp_num_blocks(int n_rows, int D, int K);
+int cp_num_blocks(int n_rows, int D, int K, int max_blocks);
+// One full round of resident CP-reduction blocks on this device.
+int cp_resident_blocks(int D, int K, int num_cu);
 // post-processing
 hipError_t launch_unwhiten(const float* Phi, const double* U, const double* eig, const double* m,
                            int V, int D, int K, double theta, uint32_t flags, double* mu,

@@ -300,7 +300,7 @@ def test_infer_doc_topics_matches_oracle(c1):
     spec = c1["spec"]
     ctx = make_ctx(spec.V, spec.K, spec.K, spec.alpha0)
     tl.tlda_set_whitening(ctx, c1["W"], c1["m"])
-    mu = c1["corpus"].mu
+    mu = np.ascontiguousarray(c1["corpus"].mu)
     rp, ci, va = c1["batches"][0]
     X, nk = tl.tlda_whiten_batch(ctx, dev_batch(rp, ci, va))
     Xo = O.whiten(rp, ci, va, spec.V, c1["m"], c1["W"])
