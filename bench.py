@@ -2,8 +2,9 @@
 """Throughput of the online tensor-LDA hot path on one MI355X.
 
 A step is one batch through the hot path of the batched method: the whitened
-batch X = (F_B - 1 M1^T) W (tlda_whiten_batch) followed by one CP gradient
-step on Phi (tlda_cp_step).  The moment pass and the whitening refresh that
+batch X = (F_B - 1 M1^T) W and one CP gradient step on Phi, either fused in
+one call (tlda_whiten_cp_step, the default) or as tlda_whiten_batch followed
+by tlda_cp_step (--path split).  The moment pass and the whitening refresh that
 precede the CP passes are run and timed in the same process and reported
 beside the steps.  Inputs are resident in HBM before timing starts.
 
@@ -37,6 +38,8 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--docs", type=int, default=0, help="limit the corpus size (0 = full)")
     ap.add_argument("--beta", type=float, default=None)
+    ap.add_argument("--path", default="fused", choices=["fused", "split"],
+                    help="fused: tlda_whiten_cp_step; split: tlda_whiten_batch + tlda_cp_step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -149,56 +152,84 @@ def main():
     Xbuf = torch.empty((max(b.n_rows for b in dev), D), dtype=torch.float32, device="cuda")
     nk = torch.empty(1, dtype=torch.int32, device="cuda")
 
-    def step(i):
+    fused = args.path == "fused"
+
+    def step(i, evs=None):
         b = dev[i % len(dev)]
-        tl.tlda_whiten_batch(ctx, b, Xbuf, nk)
-        tl.tlda_cp_step(ctx, Xbuf, b.n_rows, nk, beta, Phi)
+        if fused:
+            tl.tlda_whiten_cp_step(ctx, b, beta, Phi, None, None, nk)
+            if evs is not None:
+                evs[1].record(stream)
+                evs[2].record(stream)
+        else:
+            tl.tlda_whiten_batch(ctx, b, Xbuf, nk)
+            if evs is not None:
+                evs[1].record(stream)
+            tl.tlda_cp_step(ctx, Xbuf, b.n_rows, nk, beta, Phi)
+            if evs is not None:
+                evs[2].record(stream)
+        return b
 
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
     K_steps = args.steps
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * K_steps + 1)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K_steps)]
     docs = 0
+    nnz_tot = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    evs[0].record(stream)
     for i in range(K_steps):
-        b = dev[(args.warmup + i) % len(dev)]
-        tl.tlda_whiten_batch(ctx, b, Xbuf, nk)
-        evs[2 * i + 1].record(stream)
-        tl.tlda_cp_step(ctx, Xbuf, b.n_rows, nk, beta, Phi)
-        evs[2 * i + 2].record(stream)
+        evs[i][0].record(stream)
+        b = step(args.warmup + i, evs[i])
         docs += b.n_rows
+        nnz_tot += b.nnz
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    total_ms = evs[0].elapsed_time(evs[-1])
-    wh_ms = [evs[2 * i].elapsed_time(evs[2 * i + 1]) for i in range(K_steps)]
-    cp_ms = [evs[2 * i + 1].elapsed_time(evs[2 * i + 2]) for i in range(K_steps)]
+    total_ms = evs[0][0].elapsed_time(evs[-1][2])
+    wh_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    cp_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    st_ms = [e[0].elapsed_time(e[2]) for e in evs]
     value = docs / (total_ms / 1e3)
-    log(f"[bench] {K_steps} steps: {total_ms:.3f} ms (wall {wall * 1e3:.1f} ms), "
-        f"whiten {np.mean(wh_ms) * 1e3:.1f} us, cp {np.mean(cp_ms) * 1e3:.1f} us per batch")
+    if fused:
+        log(f"[bench] {K_steps} steps: {total_ms:.3f} ms (wall {wall * 1e3:.1f} ms), "
+            f"fused step {np.mean(st_ms) * 1e3:.1f} us per batch")
+    else:
+        log(f"[bench] {K_steps} steps: {total_ms:.3f} ms (wall {wall * 1e3:.1f} ms), "
+            f"whiten {np.mean(wh_ms) * 1e3:.1f} us, cp {np.mean(cp_ms) * 1e3:.1f} us per batch")
 
     # roofline of the dominant call
-    nnz_tot = sum(dev[(args.warmup + i) % len(dev)].nnz for i in range(K_steps))
-    rows_tot = docs
-    wh_bytes = (4 * (rows_tot + K_steps) + 8 * nnz_tot + 4 * D * rows_tot
-                + K_steps * 4 * (spec.V * D + D)) / K_steps
-    cp_flops = rows_tot * (4.0 * D * K + K) / K_steps
-    wh_avg, cp_avg = float(np.mean(wh_ms)) / 1e3, float(np.mean(cp_ms)) / 1e3
-    if wh_avg >= cp_avg:
-        ach = wh_bytes / wh_avg / 1e9
-        roof = {"kernel": "k_whiten", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": measured_traffic("k_whiten", spec.name),
-                "algorithmic_bytes": wh_bytes, "avg_launch_us": wh_avg * 1e6}
+    rows_per = docs / K_steps
+    csr_bytes = (4 * (docs + K_steps) + 8 * nnz_tot) / K_steps      # row_ptr, col_idx, val
+    w_bytes = 4 * (spec.V * D + D)                                    # W and W^T M1, once
+    cp_flops = rows_per * (4.0 * D * K + K)
+    if fused:
+        st_avg = float(np.mean(st_ms)) / 1e3
+        ach = cp_flops / st_avg / 1e12
+        roof = {"kernel": "k_whiten_cp (fused step: k_cp_penalty + k_whiten_cp + k_fused_finalize)",
+                "bound": "mfma", "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS,
+                "traffic": measured_traffic("k_whiten_cp", spec.name),
+                "algorithmic_flops": cp_flops, "algorithmic_bytes": csr_bytes + w_bytes,
+                "hbm_frac_on_algorithmic_bytes": (csr_bytes + w_bytes) / st_avg / 1e9 / HBM_PEAK_GBS,
+                "avg_launch_us": st_avg * 1e6}
+        wh_avg, cp_avg = float("nan"), float("nan")
     else:
-        ach = cp_flops / cp_avg / 1e12
-        roof = {"kernel": "k_cp_reduce+k_cp_finalize", "bound": "mfma", "achieved": ach,
-                "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP32_VALU_PEAK_TFLOPS,
-                "traffic": measured_traffic("k_cp_reduce+k_cp_finalize", spec.name),
-                "algorithmic_flops": cp_flops, "avg_launch_us": cp_avg * 1e6}
+        wh_bytes = csr_bytes + 4 * D * rows_per + w_bytes
+        wh_avg, cp_avg = float(np.mean(wh_ms)) / 1e3, float(np.mean(cp_ms)) / 1e3
+        if wh_avg >= cp_avg:
+            ach = wh_bytes / wh_avg / 1e9
+            roof = {"kernel": "k_whiten", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                    "traffic": measured_traffic("k_whiten", spec.name),
+                    "algorithmic_bytes": wh_bytes, "avg_launch_us": wh_avg * 1e6}
+        else:
+            ach = cp_flops / cp_avg / 1e12
+            roof = {"kernel": "k_cp_reduce+k_cp_finalize", "bound": "mfma", "achieved": ach,
+                    "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": ach / FP32_VALU_PEAK_TFLOPS,
+                    "traffic": measured_traffic("k_cp_reduce+k_cp_finalize", spec.name),
+                    "algorithmic_flops": cp_flops, "avg_launch_us": cp_avg * 1e6}
     mom_docs_s = corpus.n_docs / (moments_ms / 1e3)
     # recovered topics: error to the planted ones after the timed steps
     mu, alpha, lam = tl.tlda_unwhiten(ctx, Phi, tl.TLDA_PROJECT_SIMPLEX)
@@ -216,9 +247,10 @@ def main():
         "config": {"workload": f"{spec.name}: V={spec.V}, K=D={K}, alpha0={spec.alpha0}, "
                                f"{corpus.n_docs} docs of length 1+Poisson({spec.doc_len_lambda:g}), "
                                f"batch {spec.batch}, resident in HBM",
-                   "global_batch": spec.batch, "beta": beta},
+                   "global_batch": spec.batch, "beta": beta, "path": args.path},
         "roofline": roof,
-        "breakdown": {"whiten_us": wh_avg * 1e6, "cp_step_us": cp_avg * 1e6,
+        "breakdown": {"path": args.path, "step_us": float(np.mean(st_ms)) * 1e3,
+                      "whiten_us": wh_avg * 1e6, "cp_step_us": cp_avg * 1e6,
                       "moment_pass_ms": moments_ms, "moments_docs_per_s": mom_docs_s,
                       "refresh_ms": refresh_ms,
                       "topic_l1_to_planted_after_steps": topic_l1},

@@ -138,6 +138,18 @@ tlda_status tlda_whiten_batch(tlda_ctx* ctx, const tlda_csr_batch* batch, float*
 tlda_status tlda_cp_step(tlda_ctx* ctx, const float* X, int32_t n_rows, const int32_t* n_kept,
                          float beta, float* Phi, float* grad);
 
+/* The two calls above as one step, for the CP passes of the batched method:
+ * the whitened rows of `batch` are formed in on-chip memory and used at once
+ * by the gradient step (same definitions and results, up to FP32 rounding,
+ * as tlda_whiten_batch followed by tlda_cp_step with the batch's kept-row
+ * count), so X does not travel through HBM.  Phi: device float [D][K],
+ * updated in place.  grad: device float [D][K] or NULL.  X_out: device float
+ * [n_rows][D] or NULL (written only if given).  n_kept_out: device int32 or
+ * NULL.  Requires a W (TLDA_ERR_STATE).  Shapes outside the fused kernel's
+ * range (padded D or K above 128) run the two calls in sequence. */
+tlda_status tlda_whiten_cp_step(tlda_ctx* ctx, const tlda_csr_batch* batch, float beta, float* Phi,
+                                float* grad, float* X_out, int32_t* n_kept_out);
+
 /* tlda_unwhiten flags */
 #define TLDA_PROJECT_SIMPLEX 0x1u  /* clip negative entries of mu and renormalise */
 

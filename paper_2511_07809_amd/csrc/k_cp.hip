@@ -439,6 +439,10 @@ hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D,
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  return launch_cp_penalty(Phi, D, K, P, s);
+}
+
+hipError_t launch_cp_penalty(const float* Phi, int D, int K, double* P, hipStream_t s) {
   const size_t pbytes = sizeof(double) * K + sizeof(float) * (size_t)D * K;
   if (pbytes <= 65536)
     hipLaunchKernelGGL(k_cp_penalty<true>, dim3(K), dim3(kThreads), pbytes, s, Phi, D, K, P);

@@ -215,7 +215,7 @@ void destroy_all(tlda_ctx* c) {
   tlda::EigScratch& e = c->eig;
   dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
   dfree(e.sel); dfree(e.mcand); dfree(e.info);
-  dfree(c->cp.partial); dfree(c->cp.R1); dfree(c->cp.P); dfree(c->cp.grad);
+  dfree(c->cp.partial); dfree(c->cp.R1); dfree(c->cp.P); dfree(c->cp.grad); dfree(c->cp.X);
   dfree(c->post); dfree(c->postA); dfree(c->postG); dfree(c->postZ); dfree(c->postEv);
   dfree(c->A32); dfree(c->G32); dfree(c->step32); dfree(c->dev_flags); dfree(c->block_counts);
   for (auto& s : c->slots) {
@@ -273,6 +273,7 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
   ctx->tune.cp_max_blocks = env_int("TLDA_TUNE_CP_BLOCKS");
   ctx->tune.whiten_v4 = env_int("TLDA_TUNE_WHITEN_V4");
   ctx->tune.whiten_chunks = env_int("TLDA_TUNE_WHITEN_CHUNKS");
+  ctx->tune.fused_blocks = env_int("TLDA_TUNE_FUSED_BLOCKS");
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   auto fail = [&](tlda_status s) {
     destroy_all(ctx);
@@ -386,6 +387,72 @@ tlda_status tlda_cp_step(tlda_ctx* c, const float* X, int32_t n_rows, const int3
   HIP_OK(c, tlda::launch_cp_finalize(c->cp.partial, nblk, n_kept, n_rows, Phi, g, D, K,
                                      c->cfg.alpha0, c->cfg.theta, beta, c->cp.R1, c->cp.P,
                                      c->stream));
+  return TLDA_OK;
+}
+
+tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float* Phi,
+                                float* grad, float* X_out, int32_t* n_kept_out) {
+  if (!c) return TLDA_ERR_ARG;
+  tlda_status st = check_batch(c, b);
+  if (st != TLDA_OK) return st;
+  CHECK_ARG(c, c->wh.ready, TLDA_ERR_STATE, "no whitening matrix yet: refresh or set one first");
+  CHECK_ARG(c, Phi != nullptr, TLDA_ERR_ARG, "Phi is NULL");
+  CHECK_ARG(c, std::isfinite(beta), TLDA_ERR_ARG, "beta is not finite");
+  const int D = c->cfg.D, K = c->cfg.K;
+  if (!tlda::fused_supported(D, K, c->Dp)) {
+    // two calls in sequence through the context's own X buffer
+    const size_t need = (size_t)b->n_rows * D;
+    float* X = X_out;
+    if (X == nullptr) {
+      if (c->cp.cap_x < need) {
+        HIP_OK(c, hipStreamSynchronize(c->stream));
+        dfree(c->cp.X);
+        c->cp.cap_x = 0;
+        HIP_OK(c, dalloc(&c->cp.X, need));
+        c->cp.cap_x = need;
+      }
+      X = c->cp.X;
+    }
+    int32_t* nk = n_kept_out ? n_kept_out : c->dev_flags + 2;
+    st = tlda_whiten_batch(c, b, X, nk);
+    if (st != TLDA_OK) return st;
+    return tlda_cp_step(c, X, b->n_rows, nk, beta, Phi, grad);
+  }
+  st = validate_content(c, b);
+  if (st != TLDA_OK) return st;
+  if (b->n_rows == 0) {
+    if (n_kept_out) HIP_OK(c, launch_zero(n_kept_out, sizeof(int32_t), c->stream));
+    return TLDA_OK;
+  }
+  const int T = tlda::cp_mfma_tile_rows(D, K);
+  const int ntiles = (b->n_rows + T - 1) / T;
+  if (c->tune.fused_blocks <= 0) {
+    int per_cu = 0;
+    HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, Phi, K, 0, nullptr,
+                                     &per_cu, nullptr, c->stream));
+    c->tune.fused_blocks = (per_cu > 0 ? per_cu : 1) * c->num_cu;
+  }
+  int nblk = ntiles < c->tune.fused_blocks ? ntiles : c->tune.fused_blocks;
+  if (nblk > 2 * tlda::kWhitenBlockCounts) nblk = 2 * tlda::kWhitenBlockCounts;
+  const size_t need = (size_t)nblk * D * K;
+  if (c->cp.cap < need) {
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    dfree(c->cp.partial);
+    c->cp.cap = 0;
+    HIP_OK(c, dalloc(&c->cp.partial, need));
+    c->cp.cap = need;
+  }
+  float* g = grad ? grad : c->cp.grad;
+  st = begin_use(c, b);
+  if (st != TLDA_OK) return st;
+  HIP_OK(c, tlda::launch_cp_penalty(Phi, D, K, c->cp.P, c->stream));
+  HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, Phi, K, nblk,
+                                   c->cp.partial, c->block_counts, X_out, c->stream));
+  st = end_use(c, b);
+  if (st != TLDA_OK) return st;
+  HIP_OK(c, tlda::launch_fused_finalize(c->cp.partial, c->block_counts, nblk, Phi, c->cp.P, D, K,
+                                        c->cfg.alpha0, c->cfg.theta, beta, g, c->cp.R1,
+                                        n_kept_out, c->stream));
   return TLDA_OK;
 }
 

@@ -68,12 +68,14 @@ struct EigScratch {
 
 // Launch-shape knobs (0 = built-in choice).  Initialised from the
 // environment (TLDA_TUNE_CP_BLOCKS, TLDA_TUNE_WHITEN_V4, TLDA_TUNE_WHITEN_CHUNKS)
-// when a context is created.  cp_max_blocks: grid of the CP reduction
+// when a context is created (and TLDA_TUNE_FUSED_BLOCKS: grid of the fused
+// whitening + CP kernel, default three blocks per CU).  cp_max_blocks: grid of the CP reduction
 // (default: one full round of resident blocks); whiten_v4: float4 columns
 // per lane (1 or 2); whiten_chunks: XCD column chunks (1, 2, 4, 8; -1 = by
 // W size).
 struct Tuning {
   int cp_max_blocks = 0;
+  int fused_blocks = 0;
   int whiten_v4 = 0;
   int whiten_chunks = 0;
 };
@@ -84,6 +86,8 @@ struct CpScratch {
   double* R1 = nullptr;       // [D][K]
   double* P = nullptr;        // [D][K] penalty Phi (Phi^T Phi * Phi^T Phi)
   float* grad = nullptr;      // [D][K] used when the caller passes no gradient buffer
+  float* X = nullptr;         // [cap_x] whitened batch for the unfused fallback
+  size_t cap_x = 0;
 };
 
 }  // namespace tlda
@@ -158,6 +162,20 @@ hipError_t launch_cp_finalize(const float* partial, int nblk, const int* n_kept,
                               float* Phi, float* grad, int D, int K, double alpha0, double theta,
                               float beta, double* R1, const double* P, hipStream_t s);
 int cp_tile_rows(int D, int K);
+int mfma_bucket(int n);
+int cp_mfma_tile_rows(int D, int K);
+hipError_t launch_cp_penalty(const float* Phi, int D, int K, double* P, hipStream_t s);
+// fused whitening + CP reduction
+bool fused_supported(int D, int K, int Dp);
+// With partial == nullptr, launch_whiten_cp only stores in *block_counts how
+// many blocks of the kernel it would launch can be resident on one CU.
+hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
+                            int Dp, const float* Phi, int K, int nblk, float* partial,
+                            int* block_counts, float* Xout, hipStream_t s);
+hipError_t launch_fused_finalize(const float* partial, const int* block_counts, int nblk, float* Phi,
+                                 const double* P, int D, int K, double alpha0, double theta,
+                                 float beta, float* grad, double* R1, int* n_kept_out,
+                                 hipStream_t s);
 int cp_num_blocks(int n_rows, int D, int K, int max_blocks);
 // One full round of resident CP-reduction blocks on this device.
 int cp_resident_blocks(int D, int K, int num_cu);

@@ -29,7 +29,8 @@ TLDA_MAX_K = 256
 TLDA_MAX_DK = 16384
 
 EXPORTED = ("tlda_create", "tlda_destroy", "tlda_status_str", "tlda_last_error",
-            "tlda_update_moments", "tlda_whiten_batch", "tlda_cp_step", "tlda_unwhiten",
+            "tlda_update_moments", "tlda_whiten_batch", "tlda_cp_step", "tlda_whiten_cp_step",
+            "tlda_unwhiten",
             "tlda_infer_doc_topics", "tlda_stage_batch", "tlda_get_stats",
             "tlda_get_whitening", "tlda_set_whitening", "tlda_save_state", "tlda_load_state")
 
@@ -61,6 +62,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tlda_update_moments": ([vp, ctypes.POINTER(tlda_csr_batch), u32], i32),
         "tlda_whiten_batch": ([vp, ctypes.POINTER(tlda_csr_batch), vp, vp], i32),
         "tlda_cp_step": ([vp, vp, i32, vp, ctypes.c_float, vp, vp], i32),
+        "tlda_whiten_cp_step": ([vp, ctypes.POINTER(tlda_csr_batch), ctypes.c_float, vp, vp, vp,
+                                 vp], i32),
         "tlda_unwhiten": ([vp, vp, vp, vp, vp, u32], i32),
         "tlda_infer_doc_topics": ([vp, vp, i32, vp, i32, ctypes.c_float, vp], i32),
         "tlda_stage_batch": ([vp, ctypes.POINTER(tlda_csr_batch), i32,
@@ -201,6 +204,17 @@ def tlda_cp_step(ctx: Context, X: torch.Tensor, n_rows: int, n_kept: Optional[to
     assert X.dtype == torch.float32 and X.is_contiguous() and X.numel() >= n_rows * ctx.D
     _check(ctx, _LIB.tlda_cp_step(ctx.handle, _ptr(X), n_rows, _ptr(n_kept), float(beta),
                                   _ptr(Phi), _ptr(grad)))
+
+
+def tlda_whiten_cp_step(ctx: Context, batch: CsrBatch, beta: float, Phi: torch.Tensor,
+                        grad: Optional[torch.Tensor] = None, X_out: Optional[torch.Tensor] = None,
+                        n_kept: Optional[torch.Tensor] = None) -> None:
+    assert Phi.dtype == torch.float32 and Phi.is_contiguous() and Phi.numel() == ctx.D * ctx.K
+    if X_out is not None:
+        assert X_out.dtype == torch.float32 and X_out.numel() >= batch.n_rows * ctx.D
+    s = batch.struct()
+    _check(ctx, _LIB.tlda_whiten_cp_step(ctx.handle, ctypes.byref(s), float(beta), _ptr(Phi),
+                                         _ptr(grad), _ptr(X_out), _ptr(n_kept)))
 
 
 def tlda_unwhiten(ctx: Context, Phi: torch.Tensor, flags: int = 0):

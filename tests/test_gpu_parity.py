@@ -279,6 +279,72 @@ def test_cp_step_full_size_streaming_shape():
 
 
 # ----------------------------------------------------------------------------
+# fused whitening + CP step
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("D,K", [(5, 5), (10, 7), (20, 20), (33, 40), (50, 50), (64, 64),
+                                 (100, 100), (128, 96), (150, 40)])
+def test_fused_step_matches_oracle(D, K):
+    """tlda_whiten_cp_step against the oracle's whitening and gradient on the
+    same batch (rows with dropped and empty documents included)."""
+    V = 400
+    rng = np.random.default_rng(D * 7 + K)
+    rows = [{}, {3: 1, 9: 1}]
+    for _ in range(1500):
+        words = rng.choice(V, size=rng.integers(1, 45), replace=False)
+        rows.append({int(w): int(rng.integers(1, 4)) for w in words})
+    rp, ci, va = make_csr_rows(rows, V)
+    Q, _ = np.linalg.qr(rng.standard_normal((V, D)))
+    W = Q * rng.uniform(5, 30, size=D)[None, :]
+    m = rng.dirichlet(np.ones(V))
+    a0, theta, beta = 1.5, 0.5, 2e-3
+    ctx = make_ctx(V, K, D, a0, theta)
+    tl.tlda_set_whitening(ctx, W, m)
+    Phi0 = (init_phi(D, K, 2) * 0.8).astype(np.float32)
+    Pd = torch.from_numpy(Phi0).cuda()
+    g = torch.empty_like(Pd)
+    Xo = torch.empty((len(rows), D), dtype=torch.float32, device="cuda")
+    nk = torch.empty(1, dtype=torch.int32, device="cuda")
+    tl.tlda_whiten_cp_step(ctx, dev_batch(rp, ci, va), beta, Pd, g, Xo, nk)
+    X_ref = O.whiten(rp, ci, va, V, m, W)
+    n_ref = O.batch_stats(rp, ci, va, V)["n_kept"]
+    g_ref = O.cp_gradient(X_ref, Phi0.astype(np.float64), n_ref, a0, theta)
+    assert int(nk.item()) == n_ref
+    assert rel(Xo.cpu().numpy(), X_ref) < REL32
+    assert rel(g.cpu().numpy(), g_ref) < REL32
+    assert rel(Pd.cpu().numpy(), Phi0 - beta * g_ref) < REL32
+
+
+def test_fused_step_equals_split_steps_at_full_size():
+    """At the benchmark's batch shape the fused step and whiten + cp_step
+    agree to FP32 rounding, and the fused step is bit-reproducible."""
+    spec = SPECS["c2"]
+    c = generate(spec, n_docs=spec.batch)
+    rp, ci, va, _ = next(iter_batches(c))
+    D = K = spec.K
+    rng = np.random.default_rng(11)
+    Q, _ = np.linalg.qr(rng.standard_normal((spec.V, D)))
+    W = Q * rng.uniform(20, 200, size=D)[None, :]
+    m = np.bincount(ci, weights=va, minlength=spec.V)
+    m /= m.sum()
+    ctx = make_ctx(spec.V, K, D, spec.alpha0)
+    tl.tlda_set_whitening(ctx, W, m)
+    b = dev_batch(rp, ci, va)
+    Phi0 = torch.from_numpy(init_phi(D, K, 5).astype(np.float32)).cuda()
+    outs = []
+    for _ in range(2):
+        P = Phi0.clone()
+        for _ in range(3):
+            tl.tlda_whiten_cp_step(ctx, b, 1e-4, P)
+        outs.append(P.cpu())
+    assert torch.equal(outs[0], outs[1])
+    P2 = Phi0.clone()
+    for _ in range(3):
+        X, nk = tl.tlda_whiten_batch(ctx, b)
+        tl.tlda_cp_step(ctx, X, b.n_rows, nk, 1e-4, P2)
+    assert rel(outs[0].numpy(), P2.cpu().numpy()) < REL32
+
+
+# ----------------------------------------------------------------------------
 # boundary: unwhitening and inference
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("theta", [0.0, 1.0])
