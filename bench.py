@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--docs", type=int, default=0, help="limit the corpus size (0 = full)")
     ap.add_argument("--beta", type=float, default=None)
+    ap.add_argument("--streamed", action="store_true",
+                    help="stream every step's batch from pinned host memory (tlda_stage_batch, "
+                         "copy of batch i+1 overlapping the compute of batch i)")
     ap.add_argument("--path", default="fused", choices=["fused", "split"],
                     help="fused: tlda_whiten_cp_step; split: tlda_whiten_batch + tlda_cp_step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -154,8 +157,22 @@ def main():
 
     fused = args.path == "fused"
 
+    if args.streamed:
+        host = [tl.CsrBatch.from_numpy(rp, ci, va, pin=True) for rp, ci, va, _ in batches]
+        staged = {}
+
+        def batch_for(i):
+            # stage batch i+1 before computing batch i, so the copy overlaps the compute
+            if i not in staged:
+                staged[i] = tl.tlda_stage_batch(ctx, host[i % len(host)], i % 2)
+            staged[i + 1] = tl.tlda_stage_batch(ctx, host[(i + 1) % len(host)], (i + 1) % 2)
+            return staged.pop(i)
+    else:
+        def batch_for(i):
+            return dev[i % len(dev)]
+
     def step(i, evs=None):
-        b = dev[i % len(dev)]
+        b = batch_for(i)
         if fused:
             tl.tlda_whiten_cp_step(ctx, b, beta, Phi, None, None, nk)
             if evs is not None:
@@ -246,7 +263,10 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{spec.name}: V={spec.V}, K=D={K}, alpha0={spec.alpha0}, "
                                f"{corpus.n_docs} docs of length 1+Poisson({spec.doc_len_lambda:g}), "
-                               f"batch {spec.batch}, resident in HBM",
+                               f"batch {spec.batch}, "
+                               + ("streamed from pinned host memory" if args.streamed
+                                  else "resident in HBM"),
+                   "streamed": bool(args.streamed),
                    "global_batch": spec.batch, "beta": beta, "path": args.path},
         "roofline": roof,
         "breakdown": {"path": args.path, "step_us": float(np.mean(st_ms)) * 1e3,

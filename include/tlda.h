@@ -146,7 +146,8 @@ tlda_status tlda_cp_step(tlda_ctx* ctx, const float* X, int32_t n_rows, const in
  * updated in place.  grad: device float [D][K] or NULL.  X_out: device float
  * [n_rows][D] or NULL (written only if given).  n_kept_out: device int32 or
  * NULL.  Requires a W (TLDA_ERR_STATE).  Shapes outside the fused kernel's
- * range (padded D or K above 128) run the two calls in sequence. */
+ * range (D or K above 64, where its registers would spill) run the two
+ * calls in sequence. */
 tlda_status tlda_whiten_cp_step(tlda_ctx* ctx, const tlda_csr_batch* batch, float beta, float* Phi,
                                 float* grad, float* X_out, int32_t* n_kept_out);
 
