@@ -63,12 +63,21 @@ typedef enum {
 
 /* tlda_config.flags */
 #define TLDA_VALIDATE_CSR 0x1u  /* check every batch's CSR content (synchronous) */
+/* BF16 precision for the per-document work (requires D, K <= 128, else
+ * TLDA_ERR_SHAPE): the whitening gathers read a BF16 copy W16 = bf16(fp32(W))
+ * with its own mean projection W16^T M1 (FP64), so X = (F - 1 M1^T) W16 is
+ * formed and centred in FP32; the CP contractions X Phi and X^T (X Phi)^2
+ * take BF16 operands (X, Phi, S^2, round to nearest even) with FP32
+ * accumulation.  The eigensolver, W, the penalty term, the 3 c3 / n scaling,
+ * the update, unwhitening and inference stay FP64/FP32.  tlda_whiten_batch,
+ * tlda_cp_step and tlda_whiten_cp_step switch; their interfaces do not. */
+#define TLDA_BF16 0x2u
 
 typedef struct {
   int32_t V;            /* vocabulary size, 3 <= V <= 131072                       */
   int32_t K;            /* number of topics, 1 <= K <= TLDA_MAX_K                   */
   int32_t D;            /* whitening size, 1 <= D <= min(V, TLDA_MAX_D), D*K bound  */
-  int32_t flags;        /* TLDA_VALIDATE_CSR                                       */
+  int32_t flags;        /* TLDA_VALIDATE_CSR | TLDA_BF16                           */
   double alpha0;        /* topic mixing parameter, > 0                             */
   double theta;         /* orthogonality penalty of eq. full_vec_pb, >= 0          */
   int32_t eig_iters;    /* subspace iterations of a refresh, 0 = default (60)      */
@@ -194,6 +203,15 @@ tlda_status tlda_get_whitening(tlda_ctx* ctx, double* W, double* eig, double* M1
  * U diag(lambda)^(-1/2) has) and M1 [V] from host memory, e.g. computed by an
  * independent implementation; the eigenvalues are taken as 1/|w_d|^2. */
 tlda_status tlda_set_whitening(tlda_ctx* ctx, const double* W, const double* M1);
+/* Timing hook for profilers and benchmarks: `start` and `stop` are arrays of
+ * n hipEvent_t (created by the caller, which keeps ownership).  While set,
+ * each tlda_whiten_batch, tlda_cp_step and tlda_whiten_cp_step call records
+ * the next pair (round robin) on the context's stream immediately before and
+ * after its main kernel (the whitening, the CP reduction or the fused
+ * kernel), so hipEventElapsedTime gives that kernel's duration alone.
+ * n == 0 (arrays may be NULL) turns the hook off.  Not synchronous. */
+tlda_status tlda_set_timing_events(tlda_ctx* ctx, void* const* start, void* const* stop,
+                                   int32_t n);
 /* Checkpoint of the moment state and W.  buf == NULL: *len receives the size. */
 tlda_status tlda_save_state(tlda_ctx* ctx, void* buf, size_t* len);
 tlda_status tlda_load_state(tlda_ctx* ctx, const void* buf, size_t len);

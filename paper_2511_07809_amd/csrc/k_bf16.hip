@@ -1,0 +1,444 @@
+// BF16 precision path of the whitening SpMM and the CP-gradient reduction
+// (the data term R1 = X^T (X Phi)^2 of eq. vec_deriv).
+//
+// What is rounded to BF16 (round to nearest even), and nothing else:
+//   * the whitening copy: W16 = bf16(fp32(W)); its mean projection
+//     mw16 = W16^T M1 is formed in FP64 from the rounded values, so the
+//     whitened rows are exactly (F - 1 M1^T) W16 up to FP32 accumulation: a
+//     whitening by a slightly perturbed W, centred in FP32 before any
+//     rounding of X (no mean-correction terms are needed afterwards);
+//   * the MFMA operands: X, Phi and the squared scores S^2 = (X Phi)^2.
+// Accumulation is FP32 on the matrix cores; the penalty term, the 3 c3 / n
+// scaling and the update stay in the FP32/FP64 finalize kernels shared with
+// the FP32 path.
+//
+// One kernel template, three modes:
+//   kFused      CSR batch -> whitened tile in LDS -> S^2 -> R1 partials
+//   kFromX      FP32 X rows from HBM -> same contractions (tlda_cp_step)
+//   kWhitenOnly CSR batch -> FP32 X rows in HBM (tlda_whiten_batch)
+//
+// Per tile of 64 documents (256 threads = 4 waves):
+//   1. G lanes own a document, 8 columns (16 bytes of W16) per lane; 8
+//      nonzeros per step are fetched cooperatively, broadcast by shuffles,
+//      and all their W16-row gathers are issued before use.  The centred row
+//      goes to LDS twice in BF16: row-major (operand of X Phi) and
+//      column-major (operand of X^T S^2).
+//   2. S = X Phi with v_mfma_f32_16x16x32_bf16 (Phi fragments in registers),
+//      S^2 rounded to BF16 into LDS column-major.
+//   3. R1 += X^T S^2 with the same instruction, accumulators in registers.
+// A K-permutation applied equally to both operands of an MFMA leaves the
+// product unchanged, so only the row/column lane mapping (shared with the
+// FP32 16x16x4 instruction) is relied on.
+#include "tlda_internal.h"
+
+namespace tlda {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTile = 64;       // documents per tile
+constexpr int kNB = 8;          // nonzeros per gather step
+
+enum { kFused = 0, kFromX = 1, kWhitenOnly = 2 };
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16, round to nearest even on the upper 16 bits; NaN stays NaN.
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+__device__ __forceinline__ floatx4 mfma_bf16(u32x4 a, u32x4 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+__global__ void k_form_w16(const double* __restrict__ W, int V, int D, int Dh,
+                           uint16_t* __restrict__ W16) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)V * Dh) return;
+  const int i = (int)(idx / Dh), d = (int)(idx % Dh);
+  W16[idx] = d < D ? (uint16_t)bf16_rne((float)W[(size_t)i * D + d]) : (uint16_t)0;
+}
+
+// mw16[d] = sum_i W16[i][d] m[i] in FP64 (one block per column); padding zero.
+__global__ void __launch_bounds__(256) k_mw16(const uint16_t* __restrict__ W16,
+                                              const double* __restrict__ m, int V, int D, int Dh,
+                                              float* __restrict__ mw16) {
+  __shared__ double red[256];
+  const int d = blockIdx.x, tid = threadIdx.x;
+  if (d >= D) {
+    if (tid == 0) mw16[d] = 0.0f;
+    return;
+  }
+  double s = 0.0;
+  for (int i = tid; i < V; i += blockDim.x) s += (double)bf16_lo(W16[(size_t)i * Dh + d]) * m[i];
+  red[tid] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) mw16[d] = (float)red[0];
+}
+
+template <int DQ, int KQ>
+struct Bf16Shape {
+  static constexpr int LDA = DQ + 8;        // row-major X tile stride (bf16)
+  static constexpr int LDT = kTile + 8;     // column-major tiles stride (bf16)
+  static constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = DQ / 32;
+  static constexpr int ST = (NCT + 3) / 4;  // column tiles of S per wave
+  static constexpr int WD = NDT >= 4 ? 4 : NDT;
+  static constexpr int WK = 4 / WD;
+  static constexpr int TDW = NDT / WD;                 // R1 row tiles per wave
+  static constexpr int TKW = (NCT + WK - 1) / WK;      // R1 column tiles per wave
+};
+
+template <int DQ, int KQ, int G, int MODE>
+__global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp_bf16(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+    const float* __restrict__ val, int n_rows, const uint16_t* __restrict__ W16,
+    const float* __restrict__ mw16, int Dh, const float* __restrict__ Xin, int D,
+    const float* __restrict__ Phi, int K, int nblk, float* __restrict__ partial,
+    int* __restrict__ block_counts, float* __restrict__ Xout) {
+  typedef Bf16Shape<DQ, KQ> Sh;
+  constexpr bool kCp = MODE != kWhitenOnly;
+  constexpr int RPW = 64 / G;
+  constexpr int RPB = 4 * RPW;
+  constexpr int PASSES = (kTile + RPB - 1) / RPB;
+  constexpr int SLOTS = G >= kNB ? 1 : kNB / G;
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[kCp ? kTile * Sh::LDA : 8];
+  __shared__ __attribute__((aligned(16))) uint16_t XsT[kCp ? DQ * Sh::LDT : 8];
+  __shared__ __attribute__((aligned(16))) uint16_t SsT[kCp ? KQ * Sh::LDT : 8];
+  __shared__ int wave_kept[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int gl = lane % G;
+  const int c8 = gl * 8;               // first column of this lane (c8 < Dh <= DQ)
+  const bool pair_lo = ((lane / G) & 1) == 0;
+
+  if (kCp) {
+    for (int e = tid; e < kTile * Sh::LDA; e += kThreads) Xs[e] = 0;
+    for (int e = tid; e < DQ * Sh::LDT; e += kThreads) XsT[e] = 0;
+  }
+  // Phi fragments: bphi[q][ks] holds Phi[32 ks + 8 l4 + i][16 ct + l16], i = 0..7
+  u32x4 bphi[Sh::ST][Sh::NKS];
+#pragma unroll
+  for (int q = 0; q < Sh::ST; ++q) {
+    const int ct = wave + 4 * q;
+    const int k = 16 * ct + l16;
+#pragma unroll
+    for (int ks = 0; ks < Sh::NKS; ++ks) {
+      uint32_t h[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int d = 32 * ks + 8 * l4 + i;
+        h[i] = (kCp && ct < Sh::NCT && d < D && k < K) ? bf16_rne(Phi[d * K + k]) : 0u;
+      }
+      bphi[q][ks] = u32x4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                          h[6] | (h[7] << 16)};
+    }
+  }
+  floatx4 acc[Sh::TDW][Sh::TKW];
+#pragma unroll
+  for (int a = 0; a < Sh::TDW; ++a)
+#pragma unroll
+    for (int b = 0; b < Sh::TKW; ++b) acc[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float mw[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) mw[i] = MODE == kFromX ? 0.f : mw16[c8 + i];
+  int kept_total = 0;
+
+  const int ntiles = (n_rows + kTile - 1) / kTile;
+  for (int tile = blockIdx.x; tile < ntiles; tile += nblk) {
+    if (kCp) __syncthreads();
+    // ---- 1. rows of the tile ----
+#pragma unroll 1
+    for (int pass = 0; pass < PASSES; ++pass) {
+      const int lr = pass * RPB + wave * RPW + lane / G;
+      const int row = tile * kTile + lr;
+      const bool valid = lr < kTile && row < n_rows;
+      float x[8];
+      int kept = 0;
+      if (MODE == kFromX) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          x[i] = (valid && c8 + i < D) ? Xin[(size_t)row * D + c8 + i] : 0.f;
+      } else {
+        int b = 0, e = 0;
+        if (valid) {
+          b = row_ptr[row];
+          e = row_ptr[row + 1];
+        }
+        float a[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = 0.f;
+        float Lp = 0.f;
+        for (int jb = b; jb < e; jb += kNB) {
+          int cidx[SLOTS];
+          float cval[SLOTS];
+#pragma unroll
+          for (int q = 0; q < SLOTS; ++q) {
+            const int j = jb + q * G + gl;
+            const bool in = (q * G + gl) < kNB && j < e;
+            cidx[q] = in ? col_idx[j] : 0;
+            cval[q] = in ? val[j] : 0.f;
+            Lp += cval[q];
+          }
+          u32x4 w[kNB];
+#pragma unroll
+          for (int t = 0; t < kNB; ++t) {
+            const int c = __shfl(cidx[t / G < SLOTS ? t / G : 0], t % G, G);
+            w[t] = u32x4{0u, 0u, 0u, 0u};
+            if (jb + t < e) w[t] = *reinterpret_cast<const u32x4*>(W16 + (size_t)c * Dh + c8);
+          }
+#pragma unroll
+          for (int t = 0; t < kNB; ++t) {
+            const float v = __shfl(cval[t / G < SLOTS ? t / G : 0], t % G, G);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              a[2 * i] = fmaf(v, bf16_lo(w[t][i]), a[2 * i]);
+              a[2 * i + 1] = fmaf(v, bf16_hi(w[t][i]), a[2 * i + 1]);
+            }
+          }
+        }
+        float L = Lp;
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) L += __shfl_xor(L, off, G);
+        kept = (valid && L >= 3.f) ? 1 : 0;
+        const float invL = kept ? 1.0f / L : 0.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[i] = kept ? fmaf(a[i], invL, -mw[i]) : 0.f;
+        if (Xout != nullptr && valid) {
+          float* out = Xout + (size_t)row * D;
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if (c8 + i < D) out[c8 + i] = x[i];
+        }
+        kept_total += __popcll(__ballot(kept && gl == 0));
+      }
+      if (kCp) {
+        uint32_t h[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) h[i] = bf16_rne(x[i]);
+        if (lr < kTile)
+          *reinterpret_cast<u32x4*>(Xs + lr * Sh::LDA + c8) =
+              u32x4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                    h[6] | (h[7] << 16)};
+        // column-major copy: the even document of each pair writes both
+        // documents' values of a column as one 32-bit word
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const uint32_t other = __shfl_down(h[i], G, 64);
+          if (pair_lo && lr < kTile)
+            *reinterpret_cast<uint32_t*>(XsT + (c8 + i) * Sh::LDT + lr) = h[i] | (other << 16);
+        }
+      }
+    }
+    if (!kCp) continue;
+    __syncthreads();
+    // ---- 2. S = X Phi; S^2 to LDS, column-major ----
+#pragma unroll
+    for (int q = 0; q < Sh::ST; ++q) {
+      const int ct = wave + 4 * q;
+      if (ct < Sh::NCT) {
+#pragma unroll
+        for (int rt = 0; rt < kTile / 16; ++rt) {
+          floatx4 s = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int ks = 0; ks < Sh::NKS; ++ks) {
+            const u32x4 av =
+                *reinterpret_cast<const u32x4*>(Xs + (16 * rt + l16) * Sh::LDA + 32 * ks + 8 * l4);
+            s = mfma_bf16(av, bphi[q][ks], s);
+          }
+          const uint32_t h0 = bf16_rne(s[0] * s[0]), h1 = bf16_rne(s[1] * s[1]);
+          const uint32_t h2 = bf16_rne(s[2] * s[2]), h3 = bf16_rne(s[3] * s[3]);
+          *reinterpret_cast<u32x2*>(SsT + (16 * ct + l16) * Sh::LDT + 16 * rt + 4 * l4) =
+              u32x2{h0 | (h1 << 16), h2 | (h3 << 16)};
+        }
+      }
+    }
+    __syncthreads();
+    // ---- 3. R1 += X^T S^2 ----
+    const int wd = wave % Sh::WD, wk = wave / Sh::WD;
+#pragma unroll
+    for (int kk = 0; kk < kTile / 32; ++kk) {
+      u32x4 av[Sh::TDW];
+#pragma unroll
+      for (int a = 0; a < Sh::TDW; ++a)
+        av[a] = *reinterpret_cast<const u32x4*>(XsT + (16 * (wd + Sh::WD * a) + l16) * Sh::LDT +
+                                                32 * kk + 8 * l4);
+#pragma unroll
+      for (int b = 0; b < Sh::TKW; ++b) {
+        const int ct = wk + Sh::WK * b;
+        if (ct < Sh::NCT) {
+          const u32x4 bv =
+              *reinterpret_cast<const u32x4*>(SsT + (16 * ct + l16) * Sh::LDT + 32 * kk + 8 * l4);
+#pragma unroll
+          for (int a = 0; a < Sh::TDW; ++a) acc[a][b] = mfma_bf16(av[a], bv, acc[a][b]);
+        }
+      }
+    }
+  }
+  if (kCp) {
+    const int wd = wave % Sh::WD, wk = wave / Sh::WD;
+    float* out = partial + (size_t)blockIdx.x * D * K;
+#pragma unroll
+    for (int a = 0; a < Sh::TDW; ++a)
+#pragma unroll
+      for (int b = 0; b < Sh::TKW; ++b) {
+        const int ct = wk + Sh::WK * b;
+        const int k = 16 * ct + l16;
+        if (ct < Sh::NCT && k < K) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int d = 16 * (wd + Sh::WD * a) + 4 * l4 + r;
+            if (d < D) out[d * K + k] = acc[a][b][r];
+          }
+        }
+      }
+  }
+  if (MODE != kFromX) {
+    if (lane == 0) wave_kept[wave] = kept_total;
+    __syncthreads();
+    if (tid == 0)
+      block_counts[blockIdx.x] = wave_kept[0] + wave_kept[1] + wave_kept[2] + wave_kept[3];
+  }
+}
+
+struct Bf16Args {
+  const tlda_csr_batch* b;
+  int n_rows;
+  const uint16_t* W16;
+  const float* mw16;
+  int Dh;
+  const float* Xin;
+  int D;
+  const float* Phi;
+  int K;
+  int nblk;
+  float* partial;
+  int* block_counts;
+  float* Xout;
+};
+
+template <int DQ, int KQ, int G, int MODE>
+hipError_t launch_t(const Bf16Args& a, int* per_cu, hipStream_t s) {
+  if (per_cu != nullptr)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_cp_bf16<DQ, KQ, G, MODE>,
+                                                        kThreads, 0);
+  const int32_t* rp = a.b ? a.b->row_ptr : nullptr;
+  const int32_t* ci = a.b ? a.b->col_idx : nullptr;
+  const float* va = a.b ? a.b->val : nullptr;
+  hipLaunchKernelGGL((k_cp_bf16<DQ, KQ, G, MODE>), dim3(a.nblk), dim3(kThreads), 0, s, rp, ci, va,
+                     a.n_rows, a.W16, a.mw16, a.Dh, a.Xin, a.D, a.Phi, a.K, a.nblk, a.partial,
+                     a.block_counts, a.Xout);
+  return hipGetLastError();
+}
+
+// Lanes per document G = Dh / 8: 1, 2 or 4 below 33 columns (DQ = 32), then
+// 8 (DQ = 64) and 16 (DQ = 128).
+template <int DQ, int KQ, int MODE>
+hipError_t launch_g(int G, const Bf16Args& a, int* per_cu, hipStream_t s) {
+  if constexpr (DQ == 32) {
+    switch (G) {
+      case 1: return launch_t<DQ, KQ, 1, MODE>(a, per_cu, s);
+      case 2: return launch_t<DQ, KQ, 2, MODE>(a, per_cu, s);
+      case 4: return launch_t<DQ, KQ, 4, MODE>(a, per_cu, s);
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    if (G != DQ / 8) return hipErrorInvalidValue;
+    return launch_t<DQ, KQ, DQ / 8, MODE>(a, per_cu, s);
+  }
+}
+
+int dq_bucket(int D) { return D <= 32 ? 32 : D <= 64 ? 64 : 128; }
+int kq_bucket(int K) { return K <= 16 ? 16 : K <= 32 ? 32 : K <= 64 ? 64 : 128; }
+
+int bf16_cols_(int D) {
+  int c = 8;
+  while (c < D) c <<= 1;
+  return c;
+}
+
+hipError_t dispatch(int mode, const Bf16Args& a, int* per_cu, hipStream_t s) {
+  const int dq = dq_bucket(a.D), kq = kq_bucket(a.K);
+  const int G = a.Dh / 8;
+  if (mode == kWhitenOnly) {
+    // the contraction shapes do not matter without the CP phases
+    switch (G) {
+      case 1: return launch_t<32, 16, 1, kWhitenOnly>(a, per_cu, s);
+      case 2: return launch_t<32, 16, 2, kWhitenOnly>(a, per_cu, s);
+      case 4: return launch_t<32, 16, 4, kWhitenOnly>(a, per_cu, s);
+      case 8: return launch_t<32, 16, 8, kWhitenOnly>(a, per_cu, s);
+      default: return launch_t<32, 16, 16, kWhitenOnly>(a, per_cu, s);
+    }
+  }
+#define TLDA_BF16(DQ_, KQ_)                                                        \
+  if (dq == DQ_ && kq == KQ_)                                                      \
+    return mode == kFused ? launch_g<DQ_, KQ_, kFused>(G, a, per_cu, s)            \
+                          : launch_g<DQ_, KQ_, kFromX>(G, a, per_cu, s);
+#define TLDA_BF16_ROW(DQ_) TLDA_BF16(DQ_, 16) TLDA_BF16(DQ_, 32) TLDA_BF16(DQ_, 64) TLDA_BF16(DQ_, 128)
+  TLDA_BF16_ROW(32) TLDA_BF16_ROW(64) TLDA_BF16_ROW(128)
+#undef TLDA_BF16_ROW
+#undef TLDA_BF16
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int bf16_cols(int D) { return bf16_cols_(D); }
+
+bool bf16_supported(int D, int K) { return D >= 1 && D <= 128 && K >= 1 && K <= 128; }
+
+hipError_t launch_form_w16(const double* W, const double* m, int V, int D, int Dh, uint16_t* W16,
+                           float* mw16, hipStream_t s) {
+  const size_t n = (size_t)V * Dh;
+  hipLaunchKernelGGL(k_form_w16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, V, D, Dh,
+                     W16);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mw16, dim3(Dh), dim3(256), 0, s, W16, m, V, D, Dh, mw16);
+  return hipGetLastError();
+}
+
+int bf16_resident_blocks(int mode, int D, int K, int Dh, int num_cu) {
+  Bf16Args a{};
+  a.D = D;
+  a.K = K;
+  a.Dh = Dh;
+  int per_cu = 0;
+  if (dispatch(mode, a, &per_cu, nullptr) != hipSuccess || per_cu < 1) per_cu = 1;
+  return per_cu * num_cu;
+}
+
+hipError_t launch_whiten_cp_bf16(const tlda_csr_batch& b, const uint16_t* W16, const float* mw16,
+                                 int Dh, int D, const float* Phi, int K, int nblk, float* partial,
+                                 int* block_counts, float* Xout, hipStream_t s) {
+  Bf16Args a{&b, b.n_rows, W16, mw16, Dh, nullptr, D, Phi, K, nblk, partial, block_counts, Xout};
+  return dispatch(kFused, a, nullptr, s);
+}
+
+hipError_t launch_cp_reduce_bf16(const float* X, int n_rows, const float* Phi, int D, int K,
+                                 int nblk, float* partial, hipStream_t s) {
+  Bf16Args a{nullptr, n_rows, nullptr, nullptr, bf16_cols(D), X, D, Phi, K, nblk, partial,
+             nullptr, nullptr};
+  return dispatch(kFromX, a, nullptr, s);
+}
+
+hipError_t launch_whiten_bf16(const tlda_csr_batch& b, const uint16_t* W16, const float* mw16,
+                              int Dh, int D, int nblk, float* X, int* block_counts,
+                              hipStream_t s) {
+  Bf16Args a{&b, b.n_rows, W16, mw16, Dh, nullptr, D, nullptr, 1, nblk, nullptr, block_counts, X};
+  return dispatch(kWhitenOnly, a, nullptr, s);
+}
+
+}  // namespace tlda

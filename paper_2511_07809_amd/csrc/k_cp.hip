@@ -414,7 +414,7 @@ int cp_num_blocks(int n_rows, int D, int K, int max_blocks) {
 }
 
 hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D, int K, int nblk,
-                            float* partial, double* P, hipStream_t s) {
+                            float* partial, hipStream_t s) {
   const int Tm = cp_mfma_tile_rows(D, K);
   if (Tm > 0) {
     const int dq = mfma_bucket(D), kq = mfma_bucket(K);
@@ -437,9 +437,7 @@ hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D,
     hipLaunchKernelGGL(k_cp_reduce, dim3(nblk), dim3(kThreads), cp_lds_bytes(D, K, T), s, X,
                        n_rows, Phi, D, K, T, nblk, partial);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_cp_penalty(Phi, D, K, P, s);
+  return hipGetLastError();
 }
 
 hipError_t launch_cp_penalty(const float* Phi, int D, int K, double* P, hipStream_t s) {

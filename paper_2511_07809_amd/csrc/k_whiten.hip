@@ -191,6 +191,11 @@ hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_sum_counts(const int* block_counts, int n, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(256), 0, s, block_counts, n, out);
+  return hipGetLastError();
+}
+
 // Number of column chunks of the whitening: the smallest of 1, 2, 4, 8 that
 // makes one chunk of the FP32 W copy (V x Dp/S floats) fit in 3 MiB, the L2
 // share an XCD can spare beside the streaming CSR and X traffic, with at least

@@ -50,6 +50,57 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+bool is_bf16(const tlda_ctx* c) { return (c->cfg.flags & TLDA_BF16) != 0; }
+
+// FP32 (and, in BF16 contexts, BF16) gather copies of W and their mean
+// projections, from U, eig and M1.
+hipError_t form_whitening(tlda_ctx* c) {
+  const int V = c->cfg.V, D = c->cfg.D;
+  hipError_t e = tlda::launch_form_whitening(c->wh.U, c->wh.eig, c->wh.m, V, D, c->Dp, c->wh.W,
+                                             c->wh.W32, c->wh.mw32, c->stream);
+  if (e != hipSuccess || !is_bf16(c)) return e;
+  return tlda::launch_form_w16(c->wh.W, c->wh.m, V, D, c->Dh, c->wh.W16, c->wh.mw16, c->stream);
+}
+
+hipError_t timing_start(tlda_ctx* c) {
+  if (c->t_n <= 0) return hipSuccess;
+  return hipEventRecord(c->t_start[c->t_next], c->stream);
+}
+
+hipError_t timing_stop(tlda_ctx* c) {
+  if (c->t_n <= 0) return hipSuccess;
+  hipError_t e = hipEventRecord(c->t_stop[c->t_next], c->stream);
+  c->t_next = (c->t_next + 1) % c->t_n;
+  return e;
+}
+
+// Grid of the BF16 kernels: one full round of resident blocks (or the tuned
+// size), at most one block per 64-document tile and per block-count slot.
+int bf16_grid(tlda_ctx* c, int mode, int n_rows) {
+  int cap = c->tune.bf16_blocks;
+  if (cap <= 0) {
+    if (c->tune.bf16_resident[mode] <= 0)
+      c->tune.bf16_resident[mode] =
+          tlda::bf16_resident_blocks(mode, c->cfg.D, c->cfg.K, c->Dh, c->num_cu);
+    cap = c->tune.bf16_resident[mode];
+  }
+  const int ntiles = (n_rows + 63) / 64;
+  int nblk = ntiles < cap ? ntiles : cap;
+  if (nblk > 2 * tlda::kWhitenBlockCounts) nblk = 2 * tlda::kWhitenBlockCounts;
+  return nblk < 1 ? 1 : nblk;
+}
+
+tlda_status ensure_partial(tlda_ctx* c, size_t need) {
+  if (c->cp.cap < need) {
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    dfree(c->cp.partial);
+    c->cp.cap = 0;
+    HIP_OK(c, dalloc(&c->cp.partial, need));
+    c->cp.cap = need;
+  }
+  return TLDA_OK;
+}
+
 int default_block(const tlda_config& c) {
   int p = 2 * c.D;
   if (p < c.D + 16) p = c.D + 16;
@@ -199,8 +250,7 @@ tlda_status refresh(tlda_ctx* c) {
   HIP_OK(c, hipMemcpyAsync(c->wh.U, y, sizeof(double) * (size_t)V * D, hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(c, hipMemcpyAsync(c->wh.eig, e.sel, sizeof(double) * D, hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(c, hipMemcpyAsync(c->wh.m, e.mcand, sizeof(double) * V, hipMemcpyDeviceToDevice, c->stream));
-  HIP_OK(c, tlda::launch_form_whitening(c->wh.U, c->wh.eig, c->wh.m, V, D, c->Dp, c->wh.W,
-                                        c->wh.W32, c->wh.mw32, c->stream));
+  HIP_OK(c, form_whitening(c));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   c->wh.ready = true;
   return TLDA_OK;
@@ -211,7 +261,9 @@ void destroy_all(tlda_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   dfree(c->mom.counts); dfree(c->mom.totals); dfree(c->mom.fsum); dfree(c->mom.S2);
   dfree(c->wh.W); dfree(c->wh.U); dfree(c->wh.eig); dfree(c->wh.m); dfree(c->wh.W32);
-  dfree(c->wh.mw32);
+  dfree(c->wh.mw32); dfree(c->wh.W16); dfree(c->wh.mw16);
+  delete[] c->t_start;
+  delete[] c->t_stop;
   tlda::EigScratch& e = c->eig;
   dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
   dfree(e.sel); dfree(e.mcand); dfree(e.info);
@@ -254,18 +306,21 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
   const tlda_config& c = *cfg;
   if (!(c.alpha0 > 0.0) || !std::isfinite(c.alpha0)) return TLDA_ERR_ARG;
   if (!(c.theta >= 0.0) || !std::isfinite(c.theta)) return TLDA_ERR_ARG;
-  if (c.flags & ~TLDA_VALIDATE_CSR) return TLDA_ERR_ARG;
+  if (c.flags & ~(TLDA_VALIDATE_CSR | TLDA_BF16)) return TLDA_ERR_ARG;
   if (c.eig_iters < 0 || c.eig_block < 0) return TLDA_ERR_ARG;
   if (c.V < 3 || c.V > 131072) return TLDA_ERR_SHAPE;
   if (c.K < 1 || c.K > TLDA_MAX_K || c.D < 1 || c.D > TLDA_MAX_D || c.D > c.V) return TLDA_ERR_SHAPE;
   if (c.D * c.K > TLDA_MAX_DK) return TLDA_ERR_SHAPE;
-  if (((c.D + 3) / 4) * ((c.K + 3) / 4) > 1024 || tlda::cp_tile_rows(c.D, c.K) == 0)
-    return TLDA_ERR_SHAPE;
+  if (!(c.flags & TLDA_BF16) &&
+      (((c.D + 3) / 4) * ((c.K + 3) / 4) > 1024 || tlda::cp_tile_rows(c.D, c.K) == 0))
+    return TLDA_ERR_SHAPE;   // the FP32 reduction's shape limits
   if (c.eig_block != 0 && (c.eig_block < c.D || c.eig_block > c.V)) return TLDA_ERR_SHAPE;
+  if ((c.flags & TLDA_BF16) && !tlda::bf16_supported(c.D, c.K)) return TLDA_ERR_SHAPE;
   tlda_ctx* ctx = new (std::nothrow) tlda_ctx();
   if (!ctx) return TLDA_ERR_OOM;
   ctx->cfg = c;
   ctx->Dp = tlda::padded_d(c.D);
+  ctx->Dh = tlda::bf16_cols(c.D);
   auto env_int = [](const char* name) {
     const char* v = std::getenv(name);
     return v ? std::atoi(v) : 0;
@@ -274,6 +329,7 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
   ctx->tune.whiten_v4 = env_int("TLDA_TUNE_WHITEN_V4");
   ctx->tune.whiten_chunks = env_int("TLDA_TUNE_WHITEN_CHUNKS");
   ctx->tune.fused_blocks = env_int("TLDA_TUNE_FUSED_BLOCKS");
+  ctx->tune.bf16_blocks = env_int("TLDA_TUNE_BF16_BLOCKS");
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   auto fail = [&](tlda_status s) {
     destroy_all(ctx);
@@ -304,6 +360,9 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
             dalloc(&ctx->A32, D * K) == hipSuccess && dalloc(&ctx->G32, K * K) == hipSuccess &&
             dalloc(&ctx->step32, 1) == hipSuccess && dalloc(&ctx->dev_flags, 4) == hipSuccess &&
             dalloc(&ctx->block_counts, 2 * tlda::kWhitenBlockCounts) == hipSuccess;
+  if (ok && (c.flags & TLDA_BF16))
+    ok = dalloc(&ctx->wh.W16, V * (size_t)ctx->Dh) == hipSuccess &&
+         dalloc(&ctx->wh.mw16, (size_t)ctx->Dh) == hipSuccess;
   if (!ok) return fail(TLDA_ERR_OOM);
   if (launch_zero(ctx->mom.counts, 2 * sizeof(unsigned long long), ctx->stream) != hipSuccess ||
       launch_zero(ctx->mom.totals, V * sizeof(unsigned long long), ctx->stream) != hipSuccess ||
@@ -357,8 +416,20 @@ tlda_status tlda_whiten_batch(tlda_ctx* c, const tlda_csr_batch* b, float* X, in
   if (st != TLDA_OK) return st;
   st = begin_use(c, b);
   if (st != TLDA_OK) return st;
-  HIP_OK(c, tlda::launch_whiten(*b, c->wh.W32, c->wh.mw32, c->cfg.V, c->cfg.D, c->Dp, X, n_kept,
-                                c->block_counts, c->tune, c->stream));
+  if (is_bf16(c) && b->n_rows > 0) {
+    int nblk = bf16_grid(c, 2, b->n_rows);
+    if (nblk > tlda::kWhitenBlockCounts) nblk = tlda::kWhitenBlockCounts;
+    HIP_OK(c, timing_start(c));
+    HIP_OK(c, tlda::launch_whiten_bf16(*b, c->wh.W16, c->wh.mw16, c->Dh, c->cfg.D, nblk, X,
+                                       c->block_counts, c->stream));
+    HIP_OK(c, timing_stop(c));
+    if (n_kept) HIP_OK(c, tlda::launch_sum_counts(c->block_counts, nblk, n_kept, c->stream));
+  } else {
+    HIP_OK(c, timing_start(c));
+    HIP_OK(c, tlda::launch_whiten(*b, c->wh.W32, c->wh.mw32, c->cfg.V, c->cfg.D, c->Dp, X, n_kept,
+                                  c->block_counts, c->tune, c->stream));
+    HIP_OK(c, timing_stop(c));
+  }
   return end_use(c, b);
 }
 
@@ -371,19 +442,24 @@ tlda_status tlda_cp_step(tlda_ctx* c, const float* X, int32_t n_rows, const int3
   CHECK_ARG(c, std::isfinite(beta), TLDA_ERR_ARG, "beta is not finite");
   if (n_rows == 0) return TLDA_OK;
   const int D = c->cfg.D, K = c->cfg.K;
-  if (c->tune.cp_max_blocks <= 0) c->tune.cp_max_blocks = tlda::cp_resident_blocks(D, K, c->num_cu);
-  const int nblk = tlda::cp_num_blocks(n_rows, D, K, c->tune.cp_max_blocks);
-  const size_t need = (size_t)nblk * D * K;
-  if (c->cp.cap < need) {
-    HIP_OK(c, hipStreamSynchronize(c->stream));
-    dfree(c->cp.partial);
-    c->cp.cap = 0;
-    HIP_OK(c, dalloc(&c->cp.partial, need));
-    c->cp.cap = need;
+  int nblk;
+  if (is_bf16(c)) {
+    nblk = bf16_grid(c, 1, n_rows);
+  } else {
+    if (c->tune.cp_max_blocks <= 0)
+      c->tune.cp_max_blocks = tlda::cp_resident_blocks(D, K, c->num_cu);
+    nblk = tlda::cp_num_blocks(n_rows, D, K, c->tune.cp_max_blocks);
   }
+  tlda_status st = ensure_partial(c, (size_t)nblk * D * K);
+  if (st != TLDA_OK) return st;
   float* g = grad ? grad : c->cp.grad;
-  HIP_OK(c, tlda::launch_cp_reduce(X, n_rows, Phi, D, K, nblk, c->cp.partial, c->cp.P,
-                                   c->stream));
+  HIP_OK(c, tlda::launch_cp_penalty(Phi, D, K, c->cp.P, c->stream));
+  HIP_OK(c, timing_start(c));
+  if (is_bf16(c))
+    HIP_OK(c, tlda::launch_cp_reduce_bf16(X, n_rows, Phi, D, K, nblk, c->cp.partial, c->stream));
+  else
+    HIP_OK(c, tlda::launch_cp_reduce(X, n_rows, Phi, D, K, nblk, c->cp.partial, c->stream));
+  HIP_OK(c, timing_stop(c));
   HIP_OK(c, tlda::launch_cp_finalize(c->cp.partial, nblk, n_kept, n_rows, Phi, g, D, K,
                                      c->cfg.alpha0, c->cfg.theta, beta, c->cp.R1, c->cp.P,
                                      c->stream));
@@ -399,7 +475,7 @@ tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta
   CHECK_ARG(c, Phi != nullptr, TLDA_ERR_ARG, "Phi is NULL");
   CHECK_ARG(c, std::isfinite(beta), TLDA_ERR_ARG, "beta is not finite");
   const int D = c->cfg.D, K = c->cfg.K;
-  if (!tlda::fused_supported(D, K, c->Dp)) {
+  if (!is_bf16(c) && !tlda::fused_supported(D, K, c->Dp)) {
     // two calls in sequence through the context's own X buffer
     const size_t need = (size_t)b->n_rows * D;
     float* X = X_out;
@@ -424,6 +500,25 @@ tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta
     if (n_kept_out) HIP_OK(c, launch_zero(n_kept_out, sizeof(int32_t), c->stream));
     return TLDA_OK;
   }
+  if (is_bf16(c)) {
+    const int nblk = bf16_grid(c, 0, b->n_rows);
+    st = ensure_partial(c, (size_t)nblk * D * K);
+    if (st != TLDA_OK) return st;
+    float* g = grad ? grad : c->cp.grad;
+    st = begin_use(c, b);
+    if (st != TLDA_OK) return st;
+    HIP_OK(c, tlda::launch_cp_penalty(Phi, D, K, c->cp.P, c->stream));
+    HIP_OK(c, timing_start(c));
+    HIP_OK(c, tlda::launch_whiten_cp_bf16(*b, c->wh.W16, c->wh.mw16, c->Dh, D, Phi, K, nblk,
+                                          c->cp.partial, c->block_counts, X_out, c->stream));
+    HIP_OK(c, timing_stop(c));
+    st = end_use(c, b);
+    if (st != TLDA_OK) return st;
+    HIP_OK(c, tlda::launch_fused_finalize(c->cp.partial, c->block_counts, nblk, Phi, c->cp.P, D,
+                                          K, c->cfg.alpha0, c->cfg.theta, beta, g, c->cp.R1,
+                                          n_kept_out, c->stream));
+    return TLDA_OK;
+  }
   const int T = tlda::cp_mfma_tile_rows(D, K);
   const int ntiles = (b->n_rows + T - 1) / T;
   if (c->tune.fused_blocks <= 0) {
@@ -434,20 +529,16 @@ tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta
   }
   int nblk = ntiles < c->tune.fused_blocks ? ntiles : c->tune.fused_blocks;
   if (nblk > 2 * tlda::kWhitenBlockCounts) nblk = 2 * tlda::kWhitenBlockCounts;
-  const size_t need = (size_t)nblk * D * K;
-  if (c->cp.cap < need) {
-    HIP_OK(c, hipStreamSynchronize(c->stream));
-    dfree(c->cp.partial);
-    c->cp.cap = 0;
-    HIP_OK(c, dalloc(&c->cp.partial, need));
-    c->cp.cap = need;
-  }
+  st = ensure_partial(c, (size_t)nblk * D * K);
+  if (st != TLDA_OK) return st;
   float* g = grad ? grad : c->cp.grad;
   st = begin_use(c, b);
   if (st != TLDA_OK) return st;
   HIP_OK(c, tlda::launch_cp_penalty(Phi, D, K, c->cp.P, c->stream));
+  HIP_OK(c, timing_start(c));
   HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, Phi, K, nblk,
                                    c->cp.partial, c->block_counts, X_out, c->stream));
+  HIP_OK(c, timing_stop(c));
   st = end_use(c, b);
   if (st != TLDA_OK) return st;
   HIP_OK(c, tlda::launch_fused_finalize(c->cp.partial, c->block_counts, nblk, Phi, c->cp.P, D, K,
@@ -567,10 +658,37 @@ tlda_status tlda_set_whitening(tlda_ctx* c, const double* W, const double* M1) {
   HIP_OK(c, hipMemcpyAsync(c->wh.W, W, sizeof(double) * (size_t)V * D, hipMemcpyHostToDevice, c->stream));
   HIP_OK(c, hipMemcpyAsync(c->wh.m, M1, sizeof(double) * V, hipMemcpyHostToDevice, c->stream));
   HIP_OK(c, tlda::launch_from_injected(c->wh.W, V, D, c->wh.U, c->wh.eig, c->stream));
-  HIP_OK(c, tlda::launch_form_whitening(c->wh.U, c->wh.eig, c->wh.m, V, D, c->Dp, c->wh.W,
-                                        c->wh.W32, c->wh.mw32, c->stream));
+  HIP_OK(c, form_whitening(c));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   c->wh.ready = true;
+  return TLDA_OK;
+}
+
+tlda_status tlda_set_timing_events(tlda_ctx* c, void* const* start, void* const* stop,
+                                   int32_t n) {
+  if (!c) return TLDA_ERR_ARG;
+  CHECK_ARG(c, n >= 0, TLDA_ERR_ARG, "negative event count");
+  CHECK_ARG(c, n == 0 || (start && stop), TLDA_ERR_ARG, "event arrays are NULL");
+  for (int i = 0; i < n; ++i)
+    CHECK_ARG(c, start[i] && stop[i], TLDA_ERR_ARG, "an event is NULL");
+  delete[] c->t_start;
+  delete[] c->t_stop;
+  c->t_start = c->t_stop = nullptr;
+  c->t_n = c->t_next = 0;
+  if (n == 0) return TLDA_OK;
+  c->t_start = new (std::nothrow) hipEvent_t[n];
+  c->t_stop = new (std::nothrow) hipEvent_t[n];
+  if (!c->t_start || !c->t_stop) {
+    delete[] c->t_start;
+    delete[] c->t_stop;
+    c->t_start = c->t_stop = nullptr;
+    return TLDA_ERR_OOM;
+  }
+  for (int i = 0; i < n; ++i) {
+    c->t_start[i] = static_cast<hipEvent_t>(start[i]);
+    c->t_stop[i] = static_cast<hipEvent_t>(stop[i]);
+  }
+  c->t_n = n;
   return TLDA_OK;
 }
 
@@ -653,8 +771,7 @@ tlda_status tlda_load_state(tlda_ctx* c, const void* buf, size_t len) {
     HIP_OK(c, h2d(c->wh.U, V * D * 8));
     HIP_OK(c, h2d(c->wh.eig, D * 8));
     HIP_OK(c, h2d(c->wh.m, V * 8));
-    HIP_OK(c, tlda::launch_form_whitening(c->wh.U, c->wh.eig, c->wh.m, (int)V, (int)D, c->Dp,
-                                          c->wh.W, c->wh.W32, c->wh.mw32, c->stream));
+    HIP_OK(c, form_whitening(c));
   }
   HIP_OK(c, hipStreamSynchronize(c->stream));
   c->wh.ready = h.ready != 0;

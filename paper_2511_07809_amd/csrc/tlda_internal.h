@@ -50,6 +50,8 @@ struct Whitening {
   double* m = nullptr;     // [V]
   float* W32 = nullptr;    // [V][Dp]
   float* mw32 = nullptr;   // [Dp], W^T M1
+  uint16_t* W16 = nullptr; // [V][Dh] BF16 bits of fp32(W) (BF16 contexts only)
+  float* mw16 = nullptr;   // [Dh], W16^T M1 from the rounded values
 };
 
 struct EigScratch {
@@ -69,13 +71,16 @@ struct EigScratch {
 // Launch-shape knobs (0 = built-in choice).  Initialised from the
 // environment (TLDA_TUNE_CP_BLOCKS, TLDA_TUNE_WHITEN_V4, TLDA_TUNE_WHITEN_CHUNKS)
 // when a context is created (and TLDA_TUNE_FUSED_BLOCKS: grid of the fused
-// whitening + CP kernel, default three blocks per CU).  cp_max_blocks: grid of the CP reduction
+// whitening + CP kernel, default one full round of resident blocks;
+// TLDA_TUNE_BF16_BLOCKS: the same for the BF16 kernels).  cp_max_blocks: grid of the CP reduction
 // (default: one full round of resident blocks); whiten_v4: float4 columns
 // per lane (1 or 2); whiten_chunks: XCD column chunks (1, 2, 4, 8; -1 = by
 // W size).
 struct Tuning {
   int cp_max_blocks = 0;
   int fused_blocks = 0;
+  int bf16_blocks = 0;
+  int bf16_resident[3] = {0, 0, 0};   // cached occupancy rounds of the BF16 kernels
   int whiten_v4 = 0;
   int whiten_chunks = 0;
 };
@@ -95,6 +100,7 @@ struct CpScratch {
 struct tlda_ctx {
   tlda_config cfg;
   int Dp = 0;
+  int Dh = 0;                 // row stride of the BF16 whitening copy
   hipStream_t stream = nullptr;
   hipStream_t copy_stream = nullptr;
   int device = 0;
@@ -115,6 +121,10 @@ struct tlda_ctx {
   float* step32 = nullptr;    // [1]
   int* dev_flags = nullptr;   // [4] CSR validation and inference status words
   int* block_counts = nullptr;  // [2 * kWhitenBlockCounts] per-block document counts
+  // timing hook: event pairs recorded around the main kernel of each hot-path call
+  hipEvent_t* t_start = nullptr;
+  hipEvent_t* t_stop = nullptr;
+  int t_n = 0, t_next = 0;
   std::string last_error;
 };
 
@@ -157,7 +167,7 @@ hipError_t launch_whiten(const tlda_csr_batch& b, const float* W32, const float*
 int whiten_chunks(int V, int Dp);
 // CP step
 hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D, int K, int nblk,
-                            float* partial, double* P, hipStream_t s);
+                            float* partial, hipStream_t s);
 hipError_t launch_cp_finalize(const float* partial, int nblk, const int* n_kept, int n_rows,
                               float* Phi, float* grad, int D, int K, double alpha0, double theta,
                               float beta, double* R1, const double* P, hipStream_t s);
@@ -177,6 +187,21 @@ hipError_t launch_fused_finalize(const float* partial, const int* block_counts, 
                                  float beta, float* grad, double* R1, int* n_kept_out,
                                  hipStream_t s);
 int cp_num_blocks(int n_rows, int D, int K, int max_blocks);
+hipError_t launch_sum_counts(const int* block_counts, int n, int* out, hipStream_t s);
+// BF16 path (D, K <= 128)
+int bf16_cols(int D);
+bool bf16_supported(int D, int K);
+hipError_t launch_form_w16(const double* W, const double* m, int V, int D, int Dh, uint16_t* W16,
+                           float* mw16, hipStream_t s);
+// resident blocks of one round on the device; mode 0 fused, 1 from X, 2 whitening only
+int bf16_resident_blocks(int mode, int D, int K, int Dh, int num_cu);
+hipError_t launch_whiten_cp_bf16(const tlda_csr_batch& b, const uint16_t* W16, const float* mw16,
+                                 int Dh, int D, const float* Phi, int K, int nblk, float* partial,
+                                 int* block_counts, float* Xout, hipStream_t s);
+hipError_t launch_cp_reduce_bf16(const float* X, int n_rows, const float* Phi, int D, int K,
+                                 int nblk, float* partial, hipStream_t s);
+hipError_t launch_whiten_bf16(const tlda_csr_batch& b, const uint16_t* W16, const float* mw16,
+                              int Dh, int D, int nblk, float* X, int* block_counts, hipStream_t s);
 // One full round of resident CP-reduction blocks on this device.
 int cp_resident_blocks(int D, int K, int num_cu);
 // post-processing

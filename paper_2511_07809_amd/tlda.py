@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "TLDA_OK", 1: "TLDA_ERR_ARG", 2: "TLDA_ERR_SHAPE", 3: "TLDA_E
                 4: "TLDA_ERR_STATE", 5: "TLDA_ERR_NUMERIC", 6: "TLDA_ERR_OOM",
                 7: "TLDA_ERR_DEVICE"}
 TLDA_VALIDATE_CSR = 0x1
+TLDA_BF16 = 0x2
 TLDA_REFRESH_W = 0x1
 TLDA_RESET = 0x2
 TLDA_PROJECT_SIMPLEX = 0x1
@@ -32,7 +33,8 @@ EXPORTED = ("tlda_create", "tlda_destroy", "tlda_status_str", "tlda_last_error",
             "tlda_update_moments", "tlda_whiten_batch", "tlda_cp_step", "tlda_whiten_cp_step",
             "tlda_unwhiten",
             "tlda_infer_doc_topics", "tlda_stage_batch", "tlda_get_stats",
-            "tlda_get_whitening", "tlda_set_whitening", "tlda_save_state", "tlda_load_state")
+            "tlda_get_whitening", "tlda_set_whitening", "tlda_set_timing_events",
+            "tlda_save_state", "tlda_load_state")
 
 
 class tlda_config(ctypes.Structure):
@@ -71,6 +73,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tlda_get_stats": ([vp, vp, vp, vp], i32),
         "tlda_get_whitening": ([vp, vp, vp, vp], i32),
         "tlda_set_whitening": ([vp, vp, vp], i32),
+        "tlda_set_timing_events": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32], i32),
         "tlda_save_state": ([vp, vp, ctypes.POINTER(ctypes.c_size_t)], i32),
         "tlda_load_state": ([vp, vp, ctypes.c_size_t], i32),
     }
@@ -168,13 +171,14 @@ class _StagedBatch(CsrBatch):
 # The C ABI, one Python function per C function.
 # ---------------------------------------------------------------------------
 def tlda_create(V: int, K: int, D: int, alpha0: float, theta: float = 0.0, *,
-                validate_csr: bool = False, eig_iters: int = 0, eig_block: int = 0,
-                eig_seed: int = 0, stream: Optional[torch.cuda.Stream] = None) -> Context:
+                validate_csr: bool = False, bf16: bool = False, eig_iters: int = 0,
+                eig_block: int = 0, eig_seed: int = 0,
+                stream: Optional[torch.cuda.Stream] = None) -> Context:
     if not torch.cuda.is_available():
         raise RuntimeError("libtlda needs a ROCm GPU; none is visible")
     stream = stream or torch.cuda.current_stream()
-    cfg = tlda_config(V, K, D, TLDA_VALIDATE_CSR if validate_csr else 0, float(alpha0),
-                      float(theta), eig_iters, eig_block, eig_seed)
+    flags = (TLDA_VALIDATE_CSR if validate_csr else 0) | (TLDA_BF16 if bf16 else 0)
+    cfg = tlda_config(V, K, D, flags, float(alpha0), float(theta), eig_iters, eig_block, eig_seed)
     h = ctypes.c_void_p()
     _check(None, _LIB.tlda_create(ctypes.byref(cfg), ctypes.c_void_p(stream.cuda_stream),
                                   ctypes.byref(h)))
@@ -269,6 +273,19 @@ def tlda_set_whitening(ctx: Context, W, M1) -> None:
     M1 = np.ascontiguousarray(M1, dtype=np.float64)
     assert W.shape == (ctx.V, ctx.D) and M1.shape == (ctx.V,)
     _check(ctx, _LIB.tlda_set_whitening(ctx.handle, W.ctypes.data, M1.ctypes.data))
+
+
+def tlda_set_timing_events(ctx: Context, starts, stops) -> None:
+    """starts/stops: equal-length lists of torch.cuda.Event(enable_timing=True),
+    each already recorded once (torch creates an event on its first record).
+    Empty lists turn the hook off.  The events must outlive the hook."""
+    assert len(starts) == len(stops)
+    n = len(starts)
+    arr = ctypes.c_void_p * max(n, 1)
+    a = arr(*[ctypes.c_void_p(e.cuda_event) for e in starts])
+    b = arr(*[ctypes.c_void_p(e.cuda_event) for e in stops])
+    ctx._timing_refs = (list(starts), list(stops))
+    _check(ctx, _LIB.tlda_set_timing_events(ctx.handle, a, b, n))
 
 
 def tlda_save_state(ctx: Context) -> bytes:

@@ -53,6 +53,32 @@ def test_create_rejects_null_arguments_before_touching_a_device(lib):
     assert lib.tlda_create(None, None, None) == 1   # TLDA_ERR_ARG
 
 
+def test_create_validates_config_before_touching_a_device(lib):
+    from paper_2511_07809_amd import tlda
+    lib.tlda_create.restype = ctypes.c_int
+    lib.tlda_create.argtypes = [ctypes.POINTER(tlda.tlda_config), ctypes.c_void_p,
+                                ctypes.POINTER(ctypes.c_void_p)]
+    out = ctypes.c_void_p()
+
+    def create(V, K, D, flags, alpha0=1.0, theta=0.0):
+        cfg = tlda.tlda_config(V, K, D, flags, alpha0, theta, 0, 0, 0)
+        return lib.tlda_create(ctypes.byref(cfg), None, ctypes.byref(out))
+
+    assert create(100, 10, 10, 0x4) == 1                       # unknown flag
+    assert create(100, 10, 10, 0, alpha0=0.0) == 1             # alpha0 must be > 0
+    assert create(100, 10, 10, 0, theta=-1.0) == 1             # theta must be >= 0
+    assert create(2, 1, 1, 0) == 2                             # V < 3
+    assert create(100, 10, 101, 0) == 2                        # D > V
+    assert create(300, 257, 10, 0) == 2                        # K above the limit
+    assert create(300, 10, 129, tlda.TLDA_BF16) == 2           # BF16 path: D <= 128
+    assert create(300, 129, 10, tlda.TLDA_BF16) == 2           # BF16 path: K <= 128
+    assert out.value is None
+    lib.tlda_set_timing_events.restype = ctypes.c_int
+    lib.tlda_set_timing_events.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int]
+    assert lib.tlda_set_timing_events(None, None, None, 0) == 1
+
+
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
