@@ -4,9 +4,13 @@
 A step is one batch through the hot path of the batched method: the whitened
 batch X = (F_B - 1 M1^T) W and one CP gradient step on Phi, either fused in
 one call (tlda_whiten_cp_step, the default) or as tlda_whiten_batch followed
-by tlda_cp_step (--path split).  The moment pass and the whitening refresh that
-precede the CP passes are run and timed in the same process and reported
-beside the steps.  Inputs are resident in HBM before timing starts.
+by tlda_cp_step (--path split), in BF16 (default) or FP32 per-document
+arithmetic; the other precision is timed beside it on the same whitening.
+The moment pass and the whitening refresh that precede the CP passes are run
+and timed in the same process and reported beside the steps.  Inputs are
+resident in HBM before timing starts (--streamed: staged from pinned host
+memory inside the timed region).  An untimed fit of both precisions from the
+same start reports their topic-recovery errors after the same passes.
 
 Prints one JSON line (see the keys below).  --gpus > 1 is not supported: this
 build runs on one GPU.
@@ -24,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector / FP32 matrix, TFLOP/s
+BF16_MFMA_PEAK_TFLOPS = 2500.0 # MI355X dense BF16 matrix, TFLOP/s
 
 
 def log(msg: str) -> None:
@@ -43,6 +48,13 @@ def parse():
                          "copy of batch i+1 overlapping the compute of batch i)")
     ap.add_argument("--path", default="fused", choices=["fused", "split"],
                     help="fused: tlda_whiten_cp_step; split: tlda_whiten_batch + tlda_cp_step")
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"],
+                    help="precision of the timed path (the other one is timed beside it)")
+    ap.add_argument("--fit-passes", type=int, default=20,
+                    help="passes of the untimed fit that compares the topic-recovery error of "
+                         "the two precisions")
+    ap.add_argument("--fit-beta", type=float, default=None,
+                    help="step size of that fit (default 0.03 for c1, 0.01 for c2, 0.001 for c3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -110,6 +122,61 @@ def measured_traffic(kernel: str, workload: str):
     return entry["bytes_per_launch"]
 
 
+def run_steps(tl, ctx, batch_for, fused, beta, Phi, Xbuf, nk, steps, warmup, stream):
+    """Untimed warm-up, then `steps` timed steps.  Events: per step around the
+    whole step, and (through the library's timing hook) around its main
+    kernel(s).  Returns per-step and per-kernel times in ms."""
+    import numpy as np
+    import torch
+
+    def step(i):
+        b = batch_for(i)
+        if fused:
+            tl.tlda_whiten_cp_step(ctx, b, beta, Phi, None, None, nk)
+        else:
+            tl.tlda_whiten_batch(ctx, b, Xbuf, nk)
+            tl.tlda_cp_step(ctx, Xbuf, b.n_rows, nk, beta, Phi)
+        return b
+
+    for i in range(warmup):
+        step(i)
+    per = 1 if fused else 2
+    ks = [torch.cuda.Event(enable_timing=True) for _ in range(per * steps)]
+    ke = [torch.cuda.Event(enable_timing=True) for _ in range(per * steps)]
+    for e in ks + ke:
+        e.record(stream)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    tl.tlda_set_timing_events(ctx, ks, ke)
+    docs = nnz = 0
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record(stream)
+        b = step(warmup + i)
+        evs[i][1].record(stream)
+        docs += b.n_rows
+        nnz += b.nnz
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tl.tlda_set_timing_events(ctx, [], [])
+    total_ms = evs[0][0].elapsed_time(evs[-1][1])
+    step_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    kern_ms = np.array([a.elapsed_time(b) for a, b in zip(ks, ke)]).reshape(steps, per)
+    return {"docs": docs, "nnz": nnz, "total_ms": total_ms, "wall_ms": wall * 1e3,
+            "step_ms": step_ms, "kern_ms": kern_ms}
+
+
+def topic_error(tl, ctx, Phi, mu_true):
+    import numpy as np
+    from scipy.optimize import linear_sum_assignment
+    mu, alpha, lam = tl.tlda_unwhiten(ctx, Phi, tl.TLDA_PROJECT_SIMPLEX)
+    mu = mu.cpu().numpy()
+    cost = np.abs(mu[:, :, None] - mu_true[:, None, :]).sum(axis=0)
+    r, c = linear_sum_assignment(cost)
+    return float(cost[r, c].mean()), mu
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -132,12 +199,13 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    ctx = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, eig_iters=60)
+    bf16 = args.precision == "bf16"
+    ctx = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, bf16=bf16, eig_iters=60)
     dev = [tl.CsrBatch.from_numpy(rp, ci, va) for rp, ci, va, _ in batches]
     torch.cuda.synchronize()
 
     # ---- moment pass (a1) and refresh, timed on the context's stream ----
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev[0].record(stream)
     for b in dev:
         tl.tlda_update_moments(ctx, b)
@@ -148,132 +216,135 @@ def main():
     refresh_ms = (time.perf_counter() - t_ref) * 1e3
     moments_ms = ev[0].elapsed_time(ev[1])
     log(f"[bench] moment pass {moments_ms:.2f} ms, refresh {refresh_ms:.1f} ms")
+    # the other precision on the same whitening, for the side-by-side figures
+    W, _, m = tl.tlda_get_whitening(ctx)
+    other = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, bf16=not bf16)
+    tl.tlda_set_whitening(other, W, m)
+    del W
 
     # ---- CP steps (a2 + a3) ----
-    Phi = torch.from_numpy(init_phi(D, K, 1).astype(np.float32)).cuda()
     beta = args.beta if args.beta is not None else (0.03 if spec.name == "c1" else 1e-3)
     Xbuf = torch.empty((max(b.n_rows for b in dev), D), dtype=torch.float32, device="cuda")
     nk = torch.empty(1, dtype=torch.int32, device="cuda")
-
     fused = args.path == "fused"
 
     if args.streamed:
         host = [tl.CsrBatch.from_numpy(rp, ci, va, pin=True) for rp, ci, va, _ in batches]
-        staged = {}
 
-        def batch_for(i):
-            # stage batch i+1 before computing batch i, so the copy overlaps the compute
-            if i not in staged:
-                staged[i] = tl.tlda_stage_batch(ctx, host[i % len(host)], i % 2)
-            staged[i + 1] = tl.tlda_stage_batch(ctx, host[(i + 1) % len(host)], (i + 1) % 2)
-            return staged.pop(i)
+        def make_batch_for(cx):
+            staged = {}
+
+            def batch_for(i):
+                # stage batch i+1 before computing batch i, so the copy overlaps the compute
+                if i not in staged:
+                    staged.clear()
+                    staged[i] = tl.tlda_stage_batch(cx, host[i % len(host)], i % 2)
+                staged[i + 1] = tl.tlda_stage_batch(cx, host[(i + 1) % len(host)], (i + 1) % 2)
+                return staged.pop(i)
+            return batch_for
     else:
-        def batch_for(i):
-            return dev[i % len(dev)]
+        def make_batch_for(cx):
+            return lambda i: dev[i % len(dev)]
 
-    def step(i, evs=None):
-        b = batch_for(i)
-        if fused:
-            tl.tlda_whiten_cp_step(ctx, b, beta, Phi, None, None, nk)
-            if evs is not None:
-                evs[1].record(stream)
-                evs[2].record(stream)
-        else:
-            tl.tlda_whiten_batch(ctx, b, Xbuf, nk)
-            if evs is not None:
-                evs[1].record(stream)
-            tl.tlda_cp_step(ctx, Xbuf, b.n_rows, nk, beta, Phi)
-            if evs is not None:
-                evs[2].record(stream)
-        return b
-
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
+    runs = {}
+    for name, cx in ((args.precision, ctx), ("fp32" if bf16 else "bf16", other)):
+        Phi = torch.from_numpy(init_phi(D, K, 1).astype(np.float32)).cuda()
+        r = run_steps(tl, cx, make_batch_for(cx), fused, beta, Phi, Xbuf, nk, args.steps,
+                      args.warmup, stream)
+        r["docs_per_s"] = r["docs"] / (r["total_ms"] / 1e3)
+        runs[name] = r
+        km = r["kern_ms"].mean(axis=0) * 1e3
+        log(f"[bench] {name} {args.path}: {args.steps} steps {r['total_ms']:.3f} ms "
+            f"(wall {r['wall_ms']:.1f} ms), step {r['step_ms'].mean() * 1e3:.1f} us, main "
+            f"kernel(s) {' + '.join(f'{x:.1f}' for x in km)} us, {r['docs_per_s']:.4g} docs/s")
+    main_run = runs[args.precision]
     K_steps = args.steps
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K_steps)]
-    docs = 0
-    nnz_tot = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(K_steps):
-        evs[i][0].record(stream)
-        b = step(args.warmup + i, evs[i])
-        docs += b.n_rows
-        nnz_tot += b.nnz
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    total_ms = evs[0][0].elapsed_time(evs[-1][2])
-    wh_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    cp_ms = [e[1].elapsed_time(e[2]) for e in evs]
-    st_ms = [e[0].elapsed_time(e[2]) for e in evs]
-    value = docs / (total_ms / 1e3)
-    if fused:
-        log(f"[bench] {K_steps} steps: {total_ms:.3f} ms (wall {wall * 1e3:.1f} ms), "
-            f"fused step {np.mean(st_ms) * 1e3:.1f} us per batch")
-    else:
-        log(f"[bench] {K_steps} steps: {total_ms:.3f} ms (wall {wall * 1e3:.1f} ms), "
-            f"whiten {np.mean(wh_ms) * 1e3:.1f} us, cp {np.mean(cp_ms) * 1e3:.1f} us per batch")
 
-    # roofline of the dominant call
+    # ---- roofline of the dominant kernel, on its own launch duration ----
+    docs, nnz_tot = main_run["docs"], main_run["nnz"]
     rows_per = docs / K_steps
     csr_bytes = (4 * (docs + K_steps) + 8 * nnz_tot) / K_steps      # row_ptr, col_idx, val
-    w_bytes = 4 * (spec.V * D + D)                                    # W and W^T M1, once
+    w_elem = 2 if bf16 else 4
+    w_bytes = w_elem * spec.V * D + 4 * D                             # W copy and W^T M1, once
     cp_flops = rows_per * (4.0 * D * K + K)
+    mm_peak = BF16_MFMA_PEAK_TFLOPS if bf16 else FP32_VALU_PEAK_TFLOPS
+    kern_us = main_run["kern_ms"].mean(axis=0) * 1e3
     if fused:
-        st_avg = float(np.mean(st_ms)) / 1e3
-        ach = cp_flops / st_avg / 1e12
-        roof = {"kernel": "k_whiten_cp (fused step: k_cp_penalty + k_whiten_cp + k_fused_finalize)",
-                "bound": "mfma", "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS,
-                "traffic": measured_traffic("k_whiten_cp", spec.name),
-                "algorithmic_flops": cp_flops, "algorithmic_bytes": csr_bytes + w_bytes,
-                "hbm_frac_on_algorithmic_bytes": (csr_bytes + w_bytes) / st_avg / 1e9 / HBM_PEAK_GBS,
-                "avg_launch_us": st_avg * 1e6}
-        wh_avg, cp_avg = float("nan"), float("nan")
+        t_k = kern_us[0] / 1e6
+        name = "k_cp_bf16 (fused mode)" if bf16 else "k_whiten_cp"
+        key = "k_cp_bf16/fused" if bf16 else "k_whiten_cp"
+        hbm_frac = (csr_bytes + w_bytes) / t_k / 1e9 / HBM_PEAK_GBS
+        mm_frac = cp_flops / t_k / 1e12 / mm_peak
+        if hbm_frac >= mm_frac:
+            ach = (csr_bytes + w_bytes) / t_k / 1e9
+            roof = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+        else:
+            ach = cp_flops / t_k / 1e12
+            roof = {"kernel": name, "bound": "mfma", "achieved": ach, "peak": mm_peak,
+                    "unit": "TFLOP/s", "frac": ach / mm_peak}
+        roof.update({"traffic": measured_traffic(key, spec.name),
+                     "algorithmic_bytes": csr_bytes + w_bytes, "algorithmic_flops": cp_flops,
+                     "hbm_frac": hbm_frac, "mfma_frac": mm_frac,
+                     "avg_launch_us": float(kern_us[0])})
     else:
         wh_bytes = csr_bytes + 4 * D * rows_per + w_bytes
-        wh_avg, cp_avg = float(np.mean(wh_ms)) / 1e3, float(np.mean(cp_ms)) / 1e3
-        if wh_avg >= cp_avg:
-            ach = wh_bytes / wh_avg / 1e9
-            roof = {"kernel": "k_whiten", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+        wh_s, cp_s = kern_us[0] / 1e6, kern_us[1] / 1e6
+        if wh_s >= cp_s:
+            name = "k_cp_bf16 (whitening mode)" if bf16 else "k_whiten"
+            key = "k_cp_bf16/whiten" if bf16 else "k_whiten"
+            ach = wh_bytes / wh_s / 1e9
+            roof = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                    "traffic": measured_traffic("k_whiten", spec.name),
-                    "algorithmic_bytes": wh_bytes, "avg_launch_us": wh_avg * 1e6}
+                    "traffic": measured_traffic(key, spec.name),
+                    "algorithmic_bytes": wh_bytes, "avg_launch_us": float(kern_us[0])}
         else:
-            ach = cp_flops / cp_avg / 1e12
-            roof = {"kernel": "k_cp_reduce+k_cp_finalize", "bound": "mfma", "achieved": ach,
-                    "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": ach / FP32_VALU_PEAK_TFLOPS,
-                    "traffic": measured_traffic("k_cp_reduce+k_cp_finalize", spec.name),
-                    "algorithmic_flops": cp_flops, "avg_launch_us": cp_avg * 1e6}
-    mom_docs_s = corpus.n_docs / (moments_ms / 1e3)
-    # recovered topics: error to the planted ones after the timed steps
-    mu, alpha, lam = tl.tlda_unwhiten(ctx, Phi, tl.TLDA_PROJECT_SIMPLEX)
-    mu_h = mu.cpu().numpy()
-    from scipy.optimize import linear_sum_assignment
-    cost = np.abs(mu_h[:, :, None] - corpus.mu[:, None, :]).sum(axis=0)
-    r, cidx = linear_sum_assignment(cost)
-    topic_l1 = float(cost[r, cidx].mean())
+            name = "k_cp_bf16 (from-X mode)" if bf16 else "k_cp_reduce_mfma"
+            key = "k_cp_bf16/from_x" if bf16 else "k_cp_reduce_mfma"
+            ach = cp_flops / cp_s / 1e12
+            roof = {"kernel": name, "bound": "mfma", "achieved": ach, "peak": mm_peak,
+                    "unit": "TFLOP/s", "frac": ach / mm_peak,
+                    "traffic": measured_traffic(key, spec.name),
+                    "algorithmic_flops": cp_flops, "avg_launch_us": float(kern_us[1])}
 
+    # ---- topic-recovery error of both precisions after the same passes ----
+    fit_beta = args.fit_beta
+    if fit_beta is None:
+        fit_beta = {"c1": 0.03, "c2": 0.01}.get(spec.name, 1e-3)
+    acc = {"passes": args.fit_passes, "beta": fit_beta}
+    mus = {}
+    for name, cx in ((args.precision, ctx), ("fp32" if bf16 else "bf16", other)):
+        Phi = torch.from_numpy(init_phi(D, K, 1).astype(np.float32)).cuda()
+        for _ in range(args.fit_passes):
+            for b in dev:
+                tl.tlda_whiten_cp_step(cx, b, fit_beta, Phi)
+        acc[f"{name}_topic_l1_to_planted"], mus[name] = topic_error(tl, cx, Phi, corpus.mu)
+    acc["fp32_vs_bf16_topic_l1"] = float(np.abs(mus["fp32"] - mus["bf16"]).sum(axis=0).mean())
+    log(f"[bench] topic error after {args.fit_passes} passes: {acc}")
+
+    mom_docs_s = corpus.n_docs / (moments_ms / 1e3)
+    other_name = "fp32" if bf16 else "bf16"
     out = {
         "metric": "docs/sec (whiten+CP step) at fixed topic-recovery error; % HBM roofline",
-        "value": value, "unit": "docs/s", "n_gpus": 1, "steps": K_steps,
-        "warmup": args.warmup, "ms_per_step": total_ms / K_steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "value": main_run["docs_per_s"], "unit": "docs/s", "n_gpus": 1, "steps": K_steps,
+        "warmup": args.warmup, "ms_per_step": main_run["total_ms"] / K_steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if bf16 else "f32", "data": "synthetic",
         "config": {"workload": f"{spec.name}: V={spec.V}, K=D={K}, alpha0={spec.alpha0}, "
                                f"{corpus.n_docs} docs of length 1+Poisson({spec.doc_len_lambda:g}), "
                                f"batch {spec.batch}, "
                                + ("streamed from pinned host memory" if args.streamed
                                   else "resident in HBM"),
-                   "streamed": bool(args.streamed),
+                   "streamed": bool(args.streamed), "precision": args.precision,
                    "global_batch": spec.batch, "beta": beta, "path": args.path},
         "roofline": roof,
-        "breakdown": {"path": args.path, "step_us": float(np.mean(st_ms)) * 1e3,
-                      "whiten_us": wh_avg * 1e6, "cp_step_us": cp_avg * 1e6,
+        "breakdown": {"path": args.path, "step_us": float(main_run["step_ms"].mean()) * 1e3,
+                      "main_kernel_us": [float(x) for x in kern_us],
+                      f"{other_name}_docs_per_s": runs[other_name]["docs_per_s"],
+                      f"{other_name}_step_us": float(runs[other_name]["step_ms"].mean()) * 1e3,
                       "moment_pass_ms": moments_ms, "moments_docs_per_s": mom_docs_s,
-                      "refresh_ms": refresh_ms,
-                      "topic_l1_to_planted_after_steps": topic_l1},
+                      "refresh_ms": refresh_ms},
+        "accuracy": acc,
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")

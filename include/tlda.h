@@ -204,12 +204,13 @@ tlda_status tlda_get_whitening(tlda_ctx* ctx, double* W, double* eig, double* M1
  * independent implementation; the eigenvalues are taken as 1/|w_d|^2. */
 tlda_status tlda_set_whitening(tlda_ctx* ctx, const double* W, const double* M1);
 /* Timing hook for profilers and benchmarks: `start` and `stop` are arrays of
- * n hipEvent_t (created by the caller, which keeps ownership).  While set,
- * each tlda_whiten_batch, tlda_cp_step and tlda_whiten_cp_step call records
- * the next pair (round robin) on the context's stream immediately before and
- * after its main kernel (the whitening, the CP reduction or the fused
- * kernel), so hipEventElapsedTime gives that kernel's duration alone.
- * n == 0 (arrays may be NULL) turns the hook off.  Not synchronous. */
+ * n hipEvent_t (created by the caller with timing enabled; the caller keeps
+ * ownership).  While set, each tlda_whiten_batch, tlda_cp_step and
+ * tlda_whiten_cp_step call attaches the next pair (round robin) to the
+ * dispatch of its main kernel (the whitening, the CP reduction or the fused
+ * kernel), which records them when that kernel starts and ends, so
+ * hipEventElapsedTime gives the kernel's own execution time.  n == 0
+ * (arrays may be NULL) turns the hook off.  Not synchronous. */
 tlda_status tlda_set_timing_events(tlda_ctx* ctx, void* const* start, void* const* stop,
                                    int32_t n);
 /* Checkpoint of the moment state and W.  buf == NULL: *len receives the size. */

@@ -9,8 +9,8 @@
 //     rounding of X (no mean-correction terms are needed afterwards);
 //   * the MFMA operands: X, Phi and the squared scores S^2 = (X Phi)^2.
 // Accumulation is FP32 on the matrix cores; the penalty term, the 3 c3 / n
-// scaling and the update stay in the FP32/FP64 finalize kernels shared with
-// the FP32 path.
+// scaling and the update stay in the FP64/FP32 finish kernel shared with the
+// FP32 path.
 //
 // One kernel template, three modes:
 //   kFused      CSR batch -> whitened tile in LDS -> S^2 -> R1 partials
@@ -19,10 +19,14 @@
 //
 // Per tile of 64 documents (256 threads = 4 waves):
 //   1. G lanes own a document, 8 columns (16 bytes of W16) per lane; 8
-//      nonzeros per step are fetched cooperatively, broadcast by shuffles,
-//      and all their W16-row gathers are issued before use.  The centred row
-//      goes to LDS twice in BF16: row-major (operand of X Phi) and
-//      column-major (operand of X^T S^2).
+//      nonzeros per step are fetched cooperatively one step ahead, broadcast
+//      by shuffles, and all their W16-row gathers are issued before use.
+//      Counts that are exact in BF16 (integers up to 256, every count of a
+//      short document in practice) accumulate with v_dot2_f32_bf16 (one
+//      instruction per column, the BF16 x BF16 product being exact in FP32),
+//      any other step with plain FMAs.  The centred row goes to LDS twice in
+//      BF16: row-major (operand of X Phi) and column-major (operand of
+//      X^T S^2).
 //   2. S = X Phi with v_mfma_f32_16x16x32_bf16 (Phi fragments in registers),
 //      S^2 rounded to BF16 into LDS column-major.
 //   3. R1 += X^T S^2 with the same instruction, accumulators in registers.
@@ -42,6 +46,7 @@ enum { kFused = 0, kFromX = 1, kWhitenOnly = 2 };
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
@@ -51,6 +56,14 @@ __device__ __forceinline__ uint32_t bf16_rne(float f) {
   if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
   u += 0x7fffu + ((u >> 16) & 1u);
   return u >> 16;
+}
+// Two FP32 values to packed BF16 (a in the low half), round to nearest even
+// (one v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 b16x2 __attribute__((ext_vector_type(2)));
+  const b16x2 h = __builtin_convertvector((f32x2{a, b}), b16x2);
+  return __builtin_bit_cast(uint32_t, h);
 }
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
@@ -107,7 +120,7 @@ __global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp
     const float* __restrict__ val, int n_rows, const uint16_t* __restrict__ W16,
     const float* __restrict__ mw16, int Dh, const float* __restrict__ Xin, int D,
     const float* __restrict__ Phi, int K, int nblk, float* __restrict__ partial,
-    int* __restrict__ block_counts, float* __restrict__ Xout) {
+    int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy) {
   typedef Bf16Shape<DQ, KQ> Sh;
   constexpr bool kCp = MODE != kWhitenOnly;
   constexpr int RPW = 64 / G;
@@ -123,8 +136,11 @@ __global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp
   const int gl = lane % G;
   const int c8 = gl * 8;               // first column of this lane (c8 < Dh <= DQ)
   const bool pair_lo = ((lane / G) & 1) == 0;
+  const unsigned char* W16b = reinterpret_cast<const unsigned char*>(W16);
 
   if (kCp) {
+    for (int e = blockIdx.x * kThreads + tid; e < D * K; e += nblk * kThreads)
+      phi_copy[e] = Phi[e];
     for (int e = tid; e < kTile * Sh::LDA; e += kThreads) Xs[e] = 0;
     for (int e = tid; e < DQ * Sh::LDT; e += kThreads) XsT[e] = 0;
   }
@@ -136,14 +152,14 @@ __global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp
     const int k = 16 * ct + l16;
 #pragma unroll
     for (int ks = 0; ks < Sh::NKS; ++ks) {
-      uint32_t h[8];
+      float f[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int d = 32 * ks + 8 * l4 + i;
-        h[i] = (kCp && ct < Sh::NCT && d < D && k < K) ? bf16_rne(Phi[d * K + k]) : 0u;
+        f[i] = (kCp && ct < Sh::NCT && d < D && k < K) ? Phi[d * K + k] : 0.f;
       }
-      bphi[q][ks] = u32x4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
-                          h[6] | (h[7] << 16)};
+      bphi[q][ks] = u32x4{pack_bf16(f[0], f[1]), pack_bf16(f[2], f[3]), pack_bf16(f[4], f[5]),
+                          pack_bf16(f[6], f[7])};
     }
   }
   floatx4 acc[Sh::TDW][Sh::TKW];
@@ -181,32 +197,75 @@ __global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp
 #pragma unroll
         for (int i = 0; i < 8; ++i) a[i] = 0.f;
         float Lp = 0.f;
-        for (int jb = b; jb < e; jb += kNB) {
-          int cidx[SLOTS];
-          float cval[SLOTS];
+        // nonzeros jb .. jb + 7 of the row, fetched cooperatively (lane gl
+        // of the group loads entries gl, gl + G, ...); indices are clamped
+        // to the row, and entries past it become (column 0, count 0)
+        int cn[SLOTS];
+        float vn[SLOTS];
+        auto fetch = [&](int jb) {
 #pragma unroll
           for (int q = 0; q < SLOTS; ++q) {
             const int j = jb + q * G + gl;
             const bool in = (q * G + gl) < kNB && j < e;
-            cidx[q] = in ? col_idx[j] : 0;
-            cval[q] = in ? val[j] : 0.f;
-            Lp += cval[q];
+            const int jc = j < e ? j : e - 1;
+            const int cc = col_idx[jc];
+            const float vv = val[jc];
+            cn[q] = in ? cc : 0;
+            vn[q] = in ? vv : 0.f;
           }
+        };
+        if (b < e) fetch(b);
+        for (int jb = b; jb < e; jb += kNB) {
+          int cidx[SLOTS];
+          float cval[SLOTS];
+          bool inexact = false;
+#pragma unroll
+          for (int q = 0; q < SLOTS; ++q) {
+            cidx[q] = cn[q];
+            cval[q] = vn[q];
+            Lp += cval[q];
+            inexact |= (__float_as_uint(cval[q]) & 0xffffu) != 0u;
+          }
+          if (jb + kNB < e) fetch(jb + kNB);      // next step's entries, in flight meanwhile
+          // all gathers first: 16 bytes of row c of W16 per lane, 32-bit offsets
           u32x4 w[kNB];
 #pragma unroll
           for (int t = 0; t < kNB; ++t) {
-            const int c = __shfl(cidx[t / G < SLOTS ? t / G : 0], t % G, G);
-            w[t] = u32x4{0u, 0u, 0u, 0u};
-            if (jb + t < e) w[t] = *reinterpret_cast<const u32x4*>(W16 + (size_t)c * Dh + c8);
+            const uint32_t c = (uint32_t)__shfl(cidx[t / G < SLOTS ? t / G : 0], t % G, G);
+            w[t] = *reinterpret_cast<const u32x4*>(W16b + (c * (uint32_t)Dh + (uint32_t)c8) * 2u);
           }
+          float v[kNB];
 #pragma unroll
-          for (int t = 0; t < kNB; ++t) {
-            const float v = __shfl(cval[t / G < SLOTS ? t / G : 0], t % G, G);
+          for (int t = 0; t < kNB; ++t) v[t] = __shfl(cval[t / G < SLOTS ? t / G : 0], t % G, G);
+          if (!__any(inexact)) {
+            // every count of the step is exact in BF16 (integers <= 256): one
+            // dot-2 per column, w.lo * v + w.hi * 0 + a (products exact in FP32)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              a[2 * i] = fmaf(v, bf16_lo(w[t][i]), a[2 * i]);
-              a[2 * i + 1] = fmaf(v, bf16_hi(w[t][i]), a[2 * i + 1]);
+            for (int t = 0; t < kNB; ++t) {
+              // an exact count has zero low 16 bits: its FP32 pattern is
+              // (0, v) as a BF16 pair, and shifted right it is (v, 0)
+              const uint32_t vb = __float_as_uint(v[t]);
+              const uint32_t vb_lo = vb >> 16;
+              const bf16x2 vlo = __builtin_bit_cast(bf16x2, vb_lo);
+              const bf16x2 vhi = __builtin_bit_cast(bf16x2, vb);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                // (bit-cast a named scalar: this compiler folds a bit-cast of a
+                // vector subscript to element 0)
+                const uint32_t wi = w[t][i];
+                const bf16x2 wp = __builtin_bit_cast(bf16x2, wi);
+                a[2 * i] = __builtin_amdgcn_fdot2_f32_bf16(wp, vlo, a[2 * i], false);
+                a[2 * i + 1] = __builtin_amdgcn_fdot2_f32_bf16(wp, vhi, a[2 * i + 1], false);
+              }
             }
+          } else {
+#pragma unroll
+            for (int t = 0; t < kNB; ++t)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                a[2 * i] = fmaf(v[t], bf16_lo(w[t][i]), a[2 * i]);
+                a[2 * i + 1] = fmaf(v[t], bf16_hi(w[t][i]), a[2 * i + 1]);
+              }
           }
         }
         float L = Lp;
@@ -225,20 +284,21 @@ __global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp
         kept_total += __popcll(__ballot(kept && gl == 0));
       }
       if (kCp) {
-        uint32_t h[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) h[i] = bf16_rne(x[i]);
-        if (lr < kTile)
-          *reinterpret_cast<u32x4*>(Xs + lr * Sh::LDA + c8) =
-              u32x4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
-                    h[6] | (h[7] << 16)};
+        const u32x4 hp = u32x4{pack_bf16(x[0], x[1]), pack_bf16(x[2], x[3]),
+                               pack_bf16(x[4], x[5]), pack_bf16(x[6], x[7])};
+        if (lr < kTile) *reinterpret_cast<u32x4*>(Xs + lr * Sh::LDA + c8) = hp;
         // column-major copy: the even document of each pair writes both
         // documents' values of a column as one 32-bit word
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const uint32_t other = __shfl_down(h[i], G, 64);
-          if (pair_lo && lr < kTile)
-            *reinterpret_cast<uint32_t*>(XsT + (c8 + i) * Sh::LDT + lr) = h[i] | (other << 16);
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t mine = hp[i];
+          const uint32_t other = __shfl_down(mine, G, 64);
+          if (pair_lo && lr < kTile) {
+            *reinterpret_cast<uint32_t*>(XsT + (c8 + 2 * i) * Sh::LDT + lr) =
+                (mine & 0xffffu) | (other << 16);
+            *reinterpret_cast<uint32_t*>(XsT + (c8 + 2 * i + 1) * Sh::LDT + lr) =
+                (mine >> 16) | (other & 0xffff0000u);
+          }
         }
       }
     }
@@ -258,10 +318,8 @@ __global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp
                 *reinterpret_cast<const u32x4*>(Xs + (16 * rt + l16) * Sh::LDA + 32 * ks + 8 * l4);
             s = mfma_bf16(av, bphi[q][ks], s);
           }
-          const uint32_t h0 = bf16_rne(s[0] * s[0]), h1 = bf16_rne(s[1] * s[1]);
-          const uint32_t h2 = bf16_rne(s[2] * s[2]), h3 = bf16_rne(s[3] * s[3]);
           *reinterpret_cast<u32x2*>(SsT + (16 * ct + l16) * Sh::LDT + 16 * rt + 4 * l4) =
-              u32x2{h0 | (h1 << 16), h2 | (h3 << 16)};
+              u32x2{pack_bf16(s[0] * s[0], s[1] * s[1]), pack_bf16(s[2] * s[2], s[3] * s[3])};
         }
       }
     }
@@ -327,6 +385,7 @@ struct Bf16Args {
   float* partial;
   int* block_counts;
   float* Xout;
+  float* phi_copy;
 };
 
 template <int DQ, int KQ, int G, int MODE>
@@ -337,9 +396,9 @@ hipError_t launch_t(const Bf16Args& a, int* per_cu, hipStream_t s) {
   const int32_t* rp = a.b ? a.b->row_ptr : nullptr;
   const int32_t* ci = a.b ? a.b->col_idx : nullptr;
   const float* va = a.b ? a.b->val : nullptr;
-  hipLaunchKernelGGL((k_cp_bf16<DQ, KQ, G, MODE>), dim3(a.nblk), dim3(kThreads), 0, s, rp, ci, va,
-                     a.n_rows, a.W16, a.mw16, a.Dh, a.Xin, a.D, a.Phi, a.K, a.nblk, a.partial,
-                     a.block_counts, a.Xout);
+  launch_main(k_cp_bf16<DQ, KQ, G, MODE>, dim3(a.nblk), dim3(kThreads), 0, s, rp, ci, va,
+              a.n_rows, a.W16, a.mw16, a.Dh, a.Xin, a.D, a.Phi, a.K, a.nblk, a.partial,
+              a.block_counts, a.Xout, a.phi_copy);
   return hipGetLastError();
 }
 
@@ -422,22 +481,24 @@ int bf16_resident_blocks(int mode, int D, int K, int Dh, int num_cu) {
 
 hipError_t launch_whiten_cp_bf16(const tlda_csr_batch& b, const uint16_t* W16, const float* mw16,
                                  int Dh, int D, const float* Phi, int K, int nblk, float* partial,
-                                 int* block_counts, float* Xout, hipStream_t s) {
-  Bf16Args a{&b, b.n_rows, W16, mw16, Dh, nullptr, D, Phi, K, nblk, partial, block_counts, Xout};
+                                 int* block_counts, float* Xout, float* phi_copy, hipStream_t s) {
+  Bf16Args a{&b,   b.n_rows, W16,          mw16, Dh,  nullptr, D, Phi, K,
+             nblk, partial,  block_counts, Xout, phi_copy};
   return dispatch(kFused, a, nullptr, s);
 }
 
 hipError_t launch_cp_reduce_bf16(const float* X, int n_rows, const float* Phi, int D, int K,
-                                 int nblk, float* partial, hipStream_t s) {
-  Bf16Args a{nullptr, n_rows, nullptr, nullptr, bf16_cols(D), X, D, Phi, K, nblk, partial,
-             nullptr, nullptr};
+                                 int nblk, float* partial, float* phi_copy, hipStream_t s) {
+  Bf16Args a{nullptr, n_rows,  nullptr, nullptr, bf16_cols(D), X,       D,
+             Phi,     K,       nblk,    partial, nullptr,      nullptr, phi_copy};
   return dispatch(kFromX, a, nullptr, s);
 }
 
 hipError_t launch_whiten_bf16(const tlda_csr_batch& b, const uint16_t* W16, const float* mw16,
                               int Dh, int D, int nblk, float* X, int* block_counts,
                               hipStream_t s) {
-  Bf16Args a{&b, b.n_rows, W16, mw16, Dh, nullptr, D, nullptr, 1, nblk, nullptr, block_counts, X};
+  Bf16Args a{&b,   b.n_rows, W16,          mw16, Dh,     nullptr, D, nullptr, 1,
+             nblk, nullptr,  block_counts, X,    nullptr};
   return dispatch(kWhitenOnly, a, nullptr, s);
 }
 

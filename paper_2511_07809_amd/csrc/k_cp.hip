@@ -22,13 +22,15 @@ constexpr int kMaxRBlocks = 4;   // (D/4)*(K/4) <= 1024 for D*K <= 16384
 __global__ void __launch_bounds__(kThreads) k_cp_reduce(const float* __restrict__ X, int n_rows,
                                                         const float* __restrict__ Phi, int D,
                                                         int K, int T, int nblk,
-                                                        float* __restrict__ partial) {
+                                                        float* __restrict__ partial,
+                                                        float* __restrict__ phi_copy) {
   extern __shared__ float smem[];
   const int Dq = (D + 3) & ~3, Kq = (K + 3) & ~3;
   float* Ps = smem;                 // [Dq][Kq]
   float* Xs = Ps + Dq * Kq;         // [T][Dq]
   float* Ss = Xs + T * Dq;          // [T][Kq]
   const int tid = threadIdx.x;
+  for (int e = blockIdx.x * kThreads + tid; e < D * K; e += nblk * kThreads) phi_copy[e] = Phi[e];
   for (int e = tid; e < Dq * Kq; e += kThreads) {
     const int d = e / Kq, k = e % Kq;
     Ps[e] = (d < D && k < K) ? Phi[d * K + k] : 0.f;
@@ -143,35 +145,6 @@ __global__ void __launch_bounds__(kThreads) k_cp_reduce(const float* __restrict_
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 
-// Penalty term P = Phi (Phi^T Phi * Phi^T Phi), column k = blockIdx.x
-// (FP64 sums): g_j = (phi_j . phi_k)^2, then P[d][k] = sum_j Phi[d][j] g_j.
-// Phi is staged in LDS when it fits (IN_LDS), else read from memory.
-template <bool IN_LDS>
-__global__ void __launch_bounds__(kThreads) k_cp_penalty(const float* __restrict__ Phi, int D,
-                                                         int K, double* __restrict__ P) {
-  extern __shared__ double psm[];
-  double* g = psm;                                         // [K]
-  float* Ps = reinterpret_cast<float*>(psm + K);           // [D][K] when IN_LDS
-  const float* src = Phi;
-  if (IN_LDS) {
-    for (int e = threadIdx.x; e < D * K; e += kThreads) Ps[e] = Phi[e];
-    __syncthreads();
-    src = Ps;
-  }
-  const int k = blockIdx.x;
-  for (int j = threadIdx.x; j < K; j += kThreads) {
-    double dot = 0.0;
-    for (int d = 0; d < D; ++d) dot += (double)src[d * K + j] * (double)src[d * K + k];
-    g[j] = dot * dot;
-  }
-  __syncthreads();
-  for (int d = threadIdx.x; d < D; d += kThreads) {
-    double pen = 0.0;
-    for (int j = 0; j < K; ++j) pen += (double)src[d * K + j] * g[j];
-    P[d * K + k] = pen;
-  }
-}
-
 // The padded shape (DQ x KQ, multiples of 16) and the row tile T are
 // compile-time constants, so every loop is fully unrolled, accumulators stay
 // in place across the matrix instructions and only the row bound is checked
@@ -181,7 +154,8 @@ __global__ void __launch_bounds__(kThreads) k_cp_reduce_mfma(const float* __rest
                                                              int n_rows,
                                                              const float* __restrict__ Phi,
                                                              int D, int K, int nblk,
-                                                             float* __restrict__ partial) {
+                                                             float* __restrict__ partial,
+                                                             float* __restrict__ phi_copy) {
   constexpr int LDX = DQ + 4, LDS = KQ + 4;
   constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = DQ / 4;
   constexpr int NRT = NDT * NCT;
@@ -198,6 +172,7 @@ __global__ void __launch_bounds__(kThreads) k_cp_reduce_mfma(const float* __rest
   __shared__ float Ss[T * LDS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
+  for (int e = blockIdx.x * kThreads + tid; e < D * K; e += nblk * kThreads) phi_copy[e] = Phi[e];
 
   // Phi fragments of this wave's S column tiles: bf[q][ks] = Phi[4 ks + l4][16 ct + l16]
   float bf[ST][NKS];
@@ -294,52 +269,95 @@ __global__ void __launch_bounds__(kThreads) k_cp_reduce_mfma(const float* __rest
   }
 }
 
-// Gradient and update.  Block b owns 64 consecutive entries e = d*K + k of
-// the D x K result; its 16 waves add the partials of blocks w, w + 16, ...
-// (one lane per entry, FP64, four independent chains) and the 16 wave sums
-// are combined in wave order, giving R1.  Then
-//   grad = 3(1+theta) P - 3 c3 / n R1,   Phi <- Phi - beta grad
-// entry by entry (P = Phi (Phi^T Phi * Phi^T Phi) comes from k_cp_penalty,
-// which ran before, so no entry of Phi is read after it is updated).
-// n == 0 gives a zero gradient and leaves Phi unchanged.
-__global__ void __launch_bounds__(1024) k_cp_finalize(const float* __restrict__ partial, int nblk,
-                                                      const int* __restrict__ n_kept, int n_rows,
-                                                      float* __restrict__ Phi,
-                                                      const double* __restrict__ P, int D, int K,
-                                                      double alpha0, double theta, float beta,
-                                                      float* __restrict__ grad,
-                                                      double* __restrict__ R1) {
-  __shared__ double red[16][64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// Gradient and update, after a reduction kernel has written its per-block R1
+// partials and a copy Phi0 of the Phi it read.  Block b (1024 threads) owns
+// 16 consecutive entries e = d*K + k of the D x K result:
+//   1. its 64 lane groups of 16 add the partials of blocks g, g + 64, ...
+//      (one lane per entry, FP64, four independent chains, so each lane
+//      waits on few dependent loads); the group sums are combined in group
+//      order, giving R1 with a fixed summation order;
+//   2. with Phi0 in LDS, the 64 lanes of wave w form the penalty of entry w,
+//      P[d][k] = sum_j Phi0[d][j] (phi0_j . phi0_k)^2 (FP64), lane l taking
+//      j = l, l + 64, ...;
+//   3. grad = 3(1+theta) P - 3 c3 / n R1 and Phi = Phi0 - beta grad.
+// n is the sum of counts[0 .. ncounts) (per-block kept-row counts, or one
+// caller-supplied count) or n_default when counts is NULL; n <= 0 gives a
+// zero gradient and leaves Phi unchanged.  Phi is only written, Phi0 only
+// read, so no block sees another block's update.
+constexpr int kFinEntries = 16;
+constexpr int kFinThreads = 1024;
+constexpr int kFinGroups = kFinThreads / kFinEntries;   // 64
+
+__global__ void __launch_bounds__(kFinThreads) k_cp_finish(
+    const float* __restrict__ partial, int nblk, const int* __restrict__ counts, int ncounts,
+    int n_default, const float* __restrict__ Phi0, int D, int K, double alpha0, double theta,
+    float beta, float* __restrict__ Phi, float* __restrict__ grad, double* __restrict__ R1,
+    int* __restrict__ n_out) {
+  extern __shared__ float ph[];                 // [D][K] copy of Phi0
+  __shared__ double red[kFinGroups][kFinEntries + 1];
+  __shared__ double pen_s[kFinEntries];
+  __shared__ int nred[kFinThreads / 64];
+  const int tid = threadIdx.x, el = tid & 15, grp = tid >> 4;
+  const int lane = tid & 63, wave = tid >> 6;
   const int DK = D * K;
-  const int e = blockIdx.x * 64 + lane;
+  const int e = blockIdx.x * kFinEntries + el;
   double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
   if (e < DK) {
-    int b = wave;
-    for (; b + 48 < nblk; b += 64) {
+    int b = grp;
+    for (; b + 3 * kFinGroups < nblk; b += 4 * kFinGroups) {
       r0 += (double)partial[(size_t)b * DK + e];
-      r1 += (double)partial[(size_t)(b + 16) * DK + e];
-      r2 += (double)partial[(size_t)(b + 32) * DK + e];
-      r3 += (double)partial[(size_t)(b + 48) * DK + e];
+      r1 += (double)partial[(size_t)(b + kFinGroups) * DK + e];
+      r2 += (double)partial[(size_t)(b + 2 * kFinGroups) * DK + e];
+      r3 += (double)partial[(size_t)(b + 3 * kFinGroups) * DK + e];
     }
-    for (; b < nblk; b += 16) r0 += (double)partial[(size_t)b * DK + e];
+    for (; b < nblk; b += kFinGroups) r0 += (double)partial[(size_t)b * DK + e];
   }
-  red[wave][lane] = (r0 + r1) + (r2 + r3);
+  int cnt = 0;
+  if (counts != nullptr)
+    for (int i = tid; i < ncounts; i += kFinThreads) cnt += counts[i];
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+  if (lane == 0) nred[wave] = cnt;
+  for (int i = tid; i < DK; i += kFinThreads) ph[i] = Phi0[i];
+  red[grp][el] = (r0 + r1) + (r2 + r3);
   __syncthreads();
-  if (wave == 0 && e < DK) {
+  const int me = blockIdx.x * kFinEntries + wave;   // wave w: penalty of entry w
+  if (me < DK) {
+    const int d = me / K, k = me % K;
+    double pen = 0.0;
+    for (int j = lane; j < K; j += 64) {
+      double dot0 = 0.0, dot1 = 0.0;
+      int i = 0;
+      for (; i + 1 < D; i += 2) {
+        dot0 += (double)ph[i * K + j] * (double)ph[i * K + k];
+        dot1 += (double)ph[(i + 1) * K + j] * (double)ph[(i + 1) * K + k];
+      }
+      if (i < D) dot0 += (double)ph[i * K + j] * (double)ph[i * K + k];
+      const double dot = dot0 + dot1;
+      pen += (double)ph[d * K + j] * (dot * dot);
+    }
+    for (int off = 32; off > 0; off >>= 1) pen += __shfl_xor(pen, off, 64);
+    if (lane == 0) pen_s[wave] = pen;
+  }
+  __syncthreads();
+  int n = n_default;
+  if (counts != nullptr) {
+    n = 0;
+    for (int w = 0; w < kFinThreads / 64; ++w) n += nred[w];
+  }
+  if (tid < kFinEntries && e < DK) {
     double tot = 0.0;
-    for (int w = 0; w < 16; ++w) tot += red[w][lane];
+    for (int g = 0; g < kFinGroups; ++g) tot += red[g][el];
     R1[e] = tot;
-    const int n = n_kept != nullptr ? *n_kept : n_rows;
     if (n <= 0) {
       grad[e] = 0.f;
     } else {
       const double c3 = (alpha0 + 1.0) * (alpha0 + 2.0) / 2.0;
-      const float g = (float)(3.0 * (1.0 + theta) * P[e] - 3.0 * c3 / (double)n * tot);
+      const float g = (float)(3.0 * (1.0 + theta) * pen_s[el] - 3.0 * c3 / (double)n * tot);
       grad[e] = g;
-      Phi[e] = fmaf(-beta, g, Phi[e]);
+      Phi[e] = fmaf(-beta, g, ph[e]);
     }
   }
+  if (blockIdx.x == 0 && tid == 0 && n_out != nullptr) *n_out = n;
 }
 
 }  // namespace
@@ -414,18 +432,18 @@ int cp_num_blocks(int n_rows, int D, int K, int max_blocks) {
 }
 
 hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D, int K, int nblk,
-                            float* partial, hipStream_t s) {
+                            float* partial, float* phi_copy, hipStream_t s) {
   const int Tm = cp_mfma_tile_rows(D, K);
   if (Tm > 0) {
     const int dq = mfma_bucket(D), kq = mfma_bucket(K);
 #define TLDA_MFMA(DQ_, KQ_)                                                                   \
   if (dq == DQ_ && kq == KQ_) {                                                               \
     if (Tm == 64)                                                                             \
-      hipLaunchKernelGGL((k_cp_reduce_mfma<DQ_, KQ_, 64>), dim3(nblk), dim3(kThreads), 0, s, X, \
-                         n_rows, Phi, D, K, nblk, partial);                                   \
+      launch_main(k_cp_reduce_mfma<DQ_, KQ_, 64>, dim3(nblk), dim3(kThreads), 0, s, X, n_rows, \
+                  Phi, D, K, nblk, partial, phi_copy);                                        \
     else                                                                                      \
-      hipLaunchKernelGGL((k_cp_reduce_mfma<DQ_, KQ_, 32>), dim3(nblk), dim3(kThreads), 0, s, X, \
-                         n_rows, Phi, D, K, nblk, partial);                                   \
+      launch_main(k_cp_reduce_mfma<DQ_, KQ_, 32>, dim3(nblk), dim3(kThreads), 0, s, X, n_rows, \
+                  Phi, D, K, nblk, partial, phi_copy);                                        \
   }
 #define TLDA_MFMA_ROW(DQ_) \
   TLDA_MFMA(DQ_, 16) TLDA_MFMA(DQ_, 32) TLDA_MFMA(DQ_, 64) TLDA_MFMA(DQ_, 112) TLDA_MFMA(DQ_, 128)
@@ -434,26 +452,20 @@ hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D,
 #undef TLDA_MFMA
   } else {
     const int T = cp_tile_rows(D, K);
-    hipLaunchKernelGGL(k_cp_reduce, dim3(nblk), dim3(kThreads), cp_lds_bytes(D, K, T), s, X,
-                       n_rows, Phi, D, K, T, nblk, partial);
+    launch_main(k_cp_reduce, dim3(nblk), dim3(kThreads), (unsigned)cp_lds_bytes(D, K, T), s, X,
+                n_rows, Phi, D, K, T, nblk, partial, phi_copy);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_cp_penalty(const float* Phi, int D, int K, double* P, hipStream_t s) {
-  const size_t pbytes = sizeof(double) * K + sizeof(float) * (size_t)D * K;
-  if (pbytes <= 65536)
-    hipLaunchKernelGGL(k_cp_penalty<true>, dim3(K), dim3(kThreads), pbytes, s, Phi, D, K, P);
-  else
-    hipLaunchKernelGGL(k_cp_penalty<false>, dim3(K), dim3(kThreads), sizeof(double) * K, s, Phi,
-                       D, K, P);
-  return hipGetLastError();
-}
-hipError_t launch_cp_finalize(const float* partial, int nblk, const int* n_kept, int n_rows,
-                              float* Phi, float* grad, int D, int K, double alpha0, double theta,
-                              float beta, double* R1, const double* P, hipStream_t s) {
-  hipLaunchKernelGGL(k_cp_finalize, dim3((D * K + 63) / 64), dim3(1024), 0, s, partial, nblk,
-                     n_kept, n_rows, Phi, P, D, K, alpha0, theta, beta, grad, R1);
+hipError_t launch_cp_finish(const float* partial, int nblk, const int* counts, int ncounts,
+                            int n_default, const float* Phi0, int D, int K, double alpha0,
+                            double theta, float beta, float* Phi, float* grad, double* R1,
+                            int* n_out, hipStream_t s) {
+  const int DK = D * K;
+  hipLaunchKernelGGL(k_cp_finish, dim3((DK + kFinEntries - 1) / kFinEntries), dim3(kFinThreads),
+                     sizeof(float) * DK, s, partial, nblk, counts, ncounts, n_default, Phi0, D, K,
+                     alpha0, theta, beta, Phi, grad, R1, n_out);
   return hipGetLastError();
 }
 

@@ -13,7 +13,8 @@
 //   3. R1 += X_t^T S^2 on FP32 matrix cores, accumulated in registers.
 // Blocks resident on the same CU overlap one block's gathers with another
 // block's matrix work.  Each block writes its R1 partial and its kept-row
-// count; the finalize kernel adds them in block order.
+// count (and its share of a copy of Phi); the finish kernel adds them in
+// block order, forms the gradient and updates Phi.
 #include "tlda_internal.h"
 
 namespace tlda {
@@ -28,7 +29,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_whiten_cp(
     const float* __restrict__ val, int n_rows, const float* __restrict__ W32,
     const float* __restrict__ mw32, int D, int Dp, const float* __restrict__ Phi, int K,
     int nblk, float* __restrict__ partial, int* __restrict__ block_counts,
-    float* __restrict__ Xout) {
+    float* __restrict__ Xout, float* __restrict__ phi_copy) {
   constexpr int LDX = DQ + 4, LDS = KQ + 4;
   constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = DQ / 4;
   constexpr int NRT = NDT * NCT;
@@ -49,6 +50,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_whiten_cp(
   const bool active = c4 < Dp;             // lane holds real (or zero-padded) W columns
   const bool in_lds = c4 < DQ;             // its columns exist in the LDS tile
 
+  for (int e = blockIdx.x * kThreads + tid; e < D * K; e += nblk * kThreads) phi_copy[e] = Phi[e];
   for (int e = tid; e < T * LDX; e += kThreads) Xs[e] = 0.f;
   float bf[ST][NKS];
 #pragma unroll
@@ -193,60 +195,10 @@ __global__ void __launch_bounds__(kThreads, 3) k_whiten_cp(
   if (tid == 0) block_counts[blockIdx.x] = wave_kept[0] + wave_kept[1] + wave_kept[2] + wave_kept[3];
 }
 
-// Finalize of the fused step: n = sum of the per-block kept counts (block
-// order), then the same fixed-order partial sum, gradient and update as the
-// unfused finalize.
-__global__ void __launch_bounds__(1024) k_fused_finalize(
-    const float* __restrict__ partial, const int* __restrict__ block_counts, int nblk,
-    float* __restrict__ Phi, const double* __restrict__ P, int D, int K, double alpha0,
-    double theta, float beta, float* __restrict__ grad, double* __restrict__ R1,
-    int* __restrict__ n_kept_out) {
-  __shared__ double red[16][64];
-  __shared__ int nsum[16];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int DK = D * K;
-  const int e = blockIdx.x * 64 + lane;
-  int cnt = 0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) cnt += block_counts[b];
-  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
-  if (lane == 0) nsum[wave] = cnt;
-  double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
-  if (e < DK) {
-    int b = wave;
-    for (; b + 48 < nblk; b += 64) {
-      r0 += (double)partial[(size_t)b * DK + e];
-      r1 += (double)partial[(size_t)(b + 16) * DK + e];
-      r2 += (double)partial[(size_t)(b + 32) * DK + e];
-      r3 += (double)partial[(size_t)(b + 48) * DK + e];
-    }
-    for (; b < nblk; b += 16) r0 += (double)partial[(size_t)b * DK + e];
-  }
-  red[wave][lane] = (r0 + r1) + (r2 + r3);
-  __syncthreads();
-  if (wave == 0) {
-    int n = 0;
-    for (int w = 0; w < 16; ++w) n += nsum[w];
-    if (blockIdx.x == 0 && lane == 0 && n_kept_out != nullptr) *n_kept_out = n;
-    if (e < DK) {
-      double tot = 0.0;
-      for (int w = 0; w < 16; ++w) tot += red[w][lane];
-      R1[e] = tot;
-      if (n <= 0) {
-        grad[e] = 0.f;
-      } else {
-        const double c3 = (alpha0 + 1.0) * (alpha0 + 2.0) / 2.0;
-        const float g = (float)(3.0 * (1.0 + theta) * P[e] - 3.0 * c3 / (double)n * tot);
-        grad[e] = g;
-        Phi[e] = fmaf(-beta, g, Phi[e]);
-      }
-    }
-  }
-}
-
 template <int DQ, int KQ, int T, int G>
 hipError_t launch_fused_t(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
                           int Dp, const float* Phi, int K, int nblk, float* partial,
-                          int* block_counts, float* Xout, hipStream_t s) {
+                          int* block_counts, float* Xout, float* phi_copy, hipStream_t s) {
   if (partial == nullptr) {   // occupancy query: resident blocks per CU in nblk's place
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_whiten_cp<DQ, KQ, T, G>,
@@ -254,22 +206,22 @@ hipError_t launch_fused_t(const tlda_csr_batch& b, const float* W32, const float
     *block_counts = per_cu;
     return e;
   }
-  hipLaunchKernelGGL((k_whiten_cp<DQ, KQ, T, G>), dim3(nblk), dim3(kThreads), 0, s, b.row_ptr,
-                     b.col_idx, b.val, b.n_rows, W32, mw32, D, Dp, Phi, K, nblk, partial,
-                     block_counts, Xout);
+  launch_main(k_whiten_cp<DQ, KQ, T, G>, dim3(nblk), dim3(kThreads), 0, s, b.row_ptr, b.col_idx,
+              b.val, b.n_rows, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout,
+              phi_copy);
   return hipGetLastError();
 }
 
 template <int DQ, int KQ, int T>
 hipError_t launch_fused_g(int G, const tlda_csr_batch& b, const float* W32, const float* mw32,
                           int D, int Dp, const float* Phi, int K, int nblk, float* partial,
-                          int* block_counts, float* Xout, hipStream_t s) {
+                          int* block_counts, float* Xout, float* phi_copy, hipStream_t s) {
   switch (G) {
-    case 1: return launch_fused_t<DQ, KQ, T, 1>(b, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout, s);
-    case 2: return launch_fused_t<DQ, KQ, T, 2>(b, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout, s);
-    case 4: return launch_fused_t<DQ, KQ, T, 4>(b, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout, s);
-    case 8: return launch_fused_t<DQ, KQ, T, 8>(b, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout, s);
-    default: return launch_fused_t<DQ, KQ, T, 16>(b, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout, s);
+    case 1: return launch_fused_t<DQ, KQ, T, 1>(b, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout, phi_copy, s);
+    case 2: return launch_fused_t<DQ, KQ, T, 2>(b, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout, phi_copy, s);
+    case 4: return launch_fused_t<DQ, KQ, T, 4>(b, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout, phi_copy, s);
+    case 8: return launch_fused_t<DQ, KQ, T, 8>(b, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout, phi_copy, s);
+    default: return launch_fused_t<DQ, KQ, T, 16>(b, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout, phi_copy, s);
   }
 }
 
@@ -289,7 +241,7 @@ int fused_tile_rows(int D, int K) {
 
 hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
                             int Dp, const float* Phi, int K, int nblk, float* partial,
-                            int* block_counts, float* Xout, hipStream_t s) {
+                            int* block_counts, float* Xout, float* phi_copy, hipStream_t s) {
   const int dq = mfma_bucket(D), kq = mfma_bucket(K);
   const int T = fused_tile_rows(D, K);
   int G = Dp / 4;   // lanes per document: Dp is 4, 8, 16, 32 or 64 here
@@ -298,23 +250,14 @@ hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const flo
 #define TLDA_FUSED(DQ_, KQ_)                                                                   \
   if (dq == DQ_ && kq == KQ_)                                                                  \
     return T == 64 ? launch_fused_g<DQ_, KQ_, 64>(G, b, W32, mw32, D, Dp, Phi, K, nblk, partial, \
-                                                  block_counts, Xout, s)                       \
+                                                  block_counts, Xout, phi_copy, s)             \
                    : launch_fused_g<DQ_, KQ_, 32>(G, b, W32, mw32, D, Dp, Phi, K, nblk, partial, \
-                                                  block_counts, Xout, s);
+                                                  block_counts, Xout, phi_copy, s);
 #define TLDA_FUSED_ROW(DQ_) TLDA_FUSED(DQ_, 16) TLDA_FUSED(DQ_, 32) TLDA_FUSED(DQ_, 64)
   TLDA_FUSED_ROW(16) TLDA_FUSED_ROW(32) TLDA_FUSED_ROW(64)
 #undef TLDA_FUSED_ROW
 #undef TLDA_FUSED
   return hipErrorInvalidValue;
-}
-
-hipError_t launch_fused_finalize(const float* partial, const int* block_counts, int nblk, float* Phi,
-                                 const double* P, int D, int K, double alpha0, double theta,
-                                 float beta, float* grad, double* R1, int* n_kept_out,
-                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_fused_finalize, dim3((D * K + 63) / 64), dim3(1024), 0, s, partial,
-                     block_counts, nblk, Phi, P, D, K, alpha0, theta, beta, grad, R1, n_kept_out);
-  return hipGetLastError();
 }
 
 }  // namespace tlda

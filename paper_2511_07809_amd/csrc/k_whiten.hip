@@ -168,8 +168,8 @@ hipError_t launch_g(const tlda_csr_batch& b, const float* W32, int V, const floa
   int per_chunk = (b.n_rows + rows_per_block - 1) / rows_per_block;
   if (per_chunk * S > kWhitenMaxBlocks) per_chunk = kWhitenMaxBlocks / S;
   const int grid = per_chunk * S;
-  hipLaunchKernelGGL((k_whiten<G, V4>), dim3(grid), dim3(256), 0, s, b.row_ptr, b.col_idx, b.val,
-                     b.n_rows, W32, V, mw32, D, Dp, S, X, block_counts);
+  launch_main(k_whiten<G, V4>, dim3(grid), dim3(256), 0, s, b.row_ptr, b.col_idx, b.val, b.n_rows,
+              W32, V, mw32, D, Dp, S, X, block_counts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n_kept == nullptr) return e;
   hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(256), 0, s, block_counts, grid, n_kept);

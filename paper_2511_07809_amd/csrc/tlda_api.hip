@@ -50,6 +50,14 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+}  // namespace
+
+namespace tlda {
+thread_local KernelTimer g_main_timer;
+}  // namespace tlda
+
+namespace {
+
 bool is_bf16(const tlda_ctx* c) { return (c->cfg.flags & TLDA_BF16) != 0; }
 
 // FP32 (and, in BF16 contexts, BF16) gather copies of W and their mean
@@ -62,16 +70,20 @@ hipError_t form_whitening(tlda_ctx* c) {
   return tlda::launch_form_w16(c->wh.W, c->wh.m, V, D, c->Dh, c->wh.W16, c->wh.mw16, c->stream);
 }
 
+// The next event pair of the timing hook goes to the next main-kernel launch.
 hipError_t timing_start(tlda_ctx* c) {
+  tlda::g_main_timer = tlda::KernelTimer{};
   if (c->t_n <= 0) return hipSuccess;
-  return hipEventRecord(c->t_start[c->t_next], c->stream);
+  tlda::g_main_timer.start = c->t_start[c->t_next];
+  tlda::g_main_timer.stop = c->t_stop[c->t_next];
+  return hipSuccess;
 }
 
 hipError_t timing_stop(tlda_ctx* c) {
+  tlda::g_main_timer = tlda::KernelTimer{};
   if (c->t_n <= 0) return hipSuccess;
-  hipError_t e = hipEventRecord(c->t_stop[c->t_next], c->stream);
   c->t_next = (c->t_next + 1) % c->t_n;
-  return e;
+  return hipSuccess;
 }
 
 // Grid of the BF16 kernels: one full round of resident blocks (or the tuned
@@ -267,7 +279,7 @@ void destroy_all(tlda_ctx* c) {
   tlda::EigScratch& e = c->eig;
   dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
   dfree(e.sel); dfree(e.mcand); dfree(e.info);
-  dfree(c->cp.partial); dfree(c->cp.R1); dfree(c->cp.P); dfree(c->cp.grad); dfree(c->cp.X);
+  dfree(c->cp.partial); dfree(c->cp.R1); dfree(c->cp.phi0); dfree(c->cp.grad); dfree(c->cp.X);
   dfree(c->post); dfree(c->postA); dfree(c->postG); dfree(c->postZ); dfree(c->postEv);
   dfree(c->A32); dfree(c->G32); dfree(c->step32); dfree(c->dev_flags); dfree(c->block_counts);
   for (auto& s : c->slots) {
@@ -353,7 +365,7 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
             dalloc(&ctx->wh.m, V) == hipSuccess &&
             dalloc(&ctx->wh.W32, V * (size_t)ctx->Dp) == hipSuccess &&
             dalloc(&ctx->wh.mw32, (size_t)ctx->Dp) == hipSuccess &&
-            dalloc(&ctx->cp.R1, D * K) == hipSuccess && dalloc(&ctx->cp.P, D * K) == hipSuccess &&
+            dalloc(&ctx->cp.R1, D * K) == hipSuccess && dalloc(&ctx->cp.phi0, D * K) == hipSuccess &&
             dalloc(&ctx->cp.grad, D * K) == hipSuccess && dalloc(&ctx->post, K) == hipSuccess &&
             dalloc(&ctx->postA, D * K) == hipSuccess && dalloc(&ctx->postG, K * K) == hipSuccess &&
             dalloc(&ctx->postZ, K * K) == hipSuccess && dalloc(&ctx->postEv, K) == hipSuccess &&
@@ -453,16 +465,17 @@ tlda_status tlda_cp_step(tlda_ctx* c, const float* X, int32_t n_rows, const int3
   tlda_status st = ensure_partial(c, (size_t)nblk * D * K);
   if (st != TLDA_OK) return st;
   float* g = grad ? grad : c->cp.grad;
-  HIP_OK(c, tlda::launch_cp_penalty(Phi, D, K, c->cp.P, c->stream));
   HIP_OK(c, timing_start(c));
   if (is_bf16(c))
-    HIP_OK(c, tlda::launch_cp_reduce_bf16(X, n_rows, Phi, D, K, nblk, c->cp.partial, c->stream));
+    HIP_OK(c, tlda::launch_cp_reduce_bf16(X, n_rows, Phi, D, K, nblk, c->cp.partial, c->cp.phi0,
+                                          c->stream));
   else
-    HIP_OK(c, tlda::launch_cp_reduce(X, n_rows, Phi, D, K, nblk, c->cp.partial, c->stream));
-  HIP_OK(c, timing_stop(c));
-  HIP_OK(c, tlda::launch_cp_finalize(c->cp.partial, nblk, n_kept, n_rows, Phi, g, D, K,
-                                     c->cfg.alpha0, c->cfg.theta, beta, c->cp.R1, c->cp.P,
+    HIP_OK(c, tlda::launch_cp_reduce(X, n_rows, Phi, D, K, nblk, c->cp.partial, c->cp.phi0,
                                      c->stream));
+  HIP_OK(c, timing_stop(c));
+  HIP_OK(c, tlda::launch_cp_finish(c->cp.partial, nblk, n_kept, n_kept ? 1 : 0, n_rows,
+                                   c->cp.phi0, D, K, c->cfg.alpha0, c->cfg.theta, beta, Phi, g,
+                                   c->cp.R1, nullptr, c->stream));
   return TLDA_OK;
 }
 
@@ -507,16 +520,16 @@ tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta
     float* g = grad ? grad : c->cp.grad;
     st = begin_use(c, b);
     if (st != TLDA_OK) return st;
-    HIP_OK(c, tlda::launch_cp_penalty(Phi, D, K, c->cp.P, c->stream));
     HIP_OK(c, timing_start(c));
     HIP_OK(c, tlda::launch_whiten_cp_bf16(*b, c->wh.W16, c->wh.mw16, c->Dh, D, Phi, K, nblk,
-                                          c->cp.partial, c->block_counts, X_out, c->stream));
+                                          c->cp.partial, c->block_counts, X_out, c->cp.phi0,
+                                          c->stream));
     HIP_OK(c, timing_stop(c));
     st = end_use(c, b);
     if (st != TLDA_OK) return st;
-    HIP_OK(c, tlda::launch_fused_finalize(c->cp.partial, c->block_counts, nblk, Phi, c->cp.P, D,
-                                          K, c->cfg.alpha0, c->cfg.theta, beta, g, c->cp.R1,
-                                          n_kept_out, c->stream));
+    HIP_OK(c, tlda::launch_cp_finish(c->cp.partial, nblk, c->block_counts, nblk, 0, c->cp.phi0, D,
+                                     K, c->cfg.alpha0, c->cfg.theta, beta, Phi, g, c->cp.R1,
+                                     n_kept_out, c->stream));
     return TLDA_OK;
   }
   const int T = tlda::cp_mfma_tile_rows(D, K);
@@ -524,7 +537,7 @@ tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta
   if (c->tune.fused_blocks <= 0) {
     int per_cu = 0;
     HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, Phi, K, 0, nullptr,
-                                     &per_cu, nullptr, c->stream));
+                                     &per_cu, nullptr, nullptr, c->stream));
     c->tune.fused_blocks = (per_cu > 0 ? per_cu : 1) * c->num_cu;
   }
   int nblk = ntiles < c->tune.fused_blocks ? ntiles : c->tune.fused_blocks;
@@ -534,16 +547,15 @@ tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta
   float* g = grad ? grad : c->cp.grad;
   st = begin_use(c, b);
   if (st != TLDA_OK) return st;
-  HIP_OK(c, tlda::launch_cp_penalty(Phi, D, K, c->cp.P, c->stream));
   HIP_OK(c, timing_start(c));
   HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, Phi, K, nblk,
-                                   c->cp.partial, c->block_counts, X_out, c->stream));
+                                   c->cp.partial, c->block_counts, X_out, c->cp.phi0, c->stream));
   HIP_OK(c, timing_stop(c));
   st = end_use(c, b);
   if (st != TLDA_OK) return st;
-  HIP_OK(c, tlda::launch_fused_finalize(c->cp.partial, c->block_counts, nblk, Phi, c->cp.P, D, K,
-                                        c->cfg.alpha0, c->cfg.theta, beta, g, c->cp.R1,
-                                        n_kept_out, c->stream));
+  HIP_OK(c, tlda::launch_cp_finish(c->cp.partial, nblk, c->block_counts, nblk, 0, c->cp.phi0, D, K,
+                                   c->cfg.alpha0, c->cfg.theta, beta, Phi, g, c->cp.R1,
+                                   n_kept_out, c->stream));
   return TLDA_OK;
 }
 

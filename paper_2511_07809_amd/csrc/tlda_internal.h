@@ -1,6 +1,7 @@
 // Internal declarations shared by the translation units of libtlda.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -89,7 +90,7 @@ struct CpScratch {
   size_t cap = 0;             // floats available in partial
   float* partial = nullptr;   // [nblk][D][K]
   double* R1 = nullptr;       // [D][K]
-  double* P = nullptr;        // [D][K] penalty Phi (Phi^T Phi * Phi^T Phi)
+  float* phi0 = nullptr;      // [D][K] copy of Phi taken by the reduction kernels
   float* grad = nullptr;      // [D][K] used when the caller passes no gradient buffer
   float* X = nullptr;         // [cap_x] whitened batch for the unfused fallback
   size_t cap_x = 0;
@@ -130,6 +131,25 @@ struct tlda_ctx {
 
 namespace tlda {
 
+// Timing hook of the main kernel of a hot-path call: the API stores a pair
+// of events here right before launching it, and launch_main records them as
+// part of that kernel's dispatch (hipExtLaunchKernelGGL), so their interval
+// is the kernel's own execution.  The first launch_main consumes the pair.
+struct KernelTimer {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+extern thread_local KernelTimer g_main_timer;
+
+template <typename... Params, typename... Args>
+inline void launch_main(void (*kernel)(Params...), dim3 grid, dim3 block, unsigned shmem,
+                        hipStream_t s, Args... args) {
+  const KernelTimer t = g_main_timer;
+  g_main_timer = KernelTimer{};
+  hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t.start, t.stop, 0u,
+                        static_cast<Params>(args)...);
+}
+
 // ---- kernel launchers (one translation unit each) ----
 // zero-fill with a kernel (no memset nodes, so callers may capture the work)
 hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s);
@@ -166,26 +186,25 @@ hipError_t launch_whiten(const tlda_csr_batch& b, const float* W32, const float*
                          hipStream_t s);
 int whiten_chunks(int V, int Dp);
 // CP step
+// The reduction kernels also copy Phi into phi_copy (D*K floats), which the
+// finish kernel reads while it writes Phi.
 hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D, int K, int nblk,
-                            float* partial, hipStream_t s);
-hipError_t launch_cp_finalize(const float* partial, int nblk, const int* n_kept, int n_rows,
-                              float* Phi, float* grad, int D, int K, double alpha0, double theta,
-                              float beta, double* R1, const double* P, hipStream_t s);
+                            float* partial, float* phi_copy, hipStream_t s);
+// n = sum of counts[0 .. ncounts), or n_default when counts is NULL
+hipError_t launch_cp_finish(const float* partial, int nblk, const int* counts, int ncounts,
+                            int n_default, const float* Phi0, int D, int K, double alpha0,
+                            double theta, float beta, float* Phi, float* grad, double* R1,
+                            int* n_out, hipStream_t s);
 int cp_tile_rows(int D, int K);
 int mfma_bucket(int n);
 int cp_mfma_tile_rows(int D, int K);
-hipError_t launch_cp_penalty(const float* Phi, int D, int K, double* P, hipStream_t s);
 // fused whitening + CP reduction
 bool fused_supported(int D, int K, int Dp);
 // With partial == nullptr, launch_whiten_cp only stores in *block_counts how
 // many blocks of the kernel it would launch can be resident on one CU.
 hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
                             int Dp, const float* Phi, int K, int nblk, float* partial,
-                            int* block_counts, float* Xout, hipStream_t s);
-hipError_t launch_fused_finalize(const float* partial, const int* block_counts, int nblk, float* Phi,
-                                 const double* P, int D, int K, double alpha0, double theta,
-                                 float beta, float* grad, double* R1, int* n_kept_out,
-                                 hipStream_t s);
+                            int* block_counts, float* Xout, float* phi_copy, hipStream_t s);
 int cp_num_blocks(int n_rows, int D, int K, int max_blocks);
 hipError_t launch_sum_counts(const int* block_counts, int n, int* out, hipStream_t s);
 // BF16 path (D, K <= 128)
@@ -197,9 +216,9 @@ hipError_t launch_form_w16(const double* W, const double* m, int V, int D, int D
 int bf16_resident_blocks(int mode, int D, int K, int Dh, int num_cu);
 hipError_t launch_whiten_cp_bf16(const tlda_csr_batch& b, const uint16_t* W16, const float* mw16,
                                  int Dh, int D, const float* Phi, int K, int nblk, float* partial,
-                                 int* block_counts, float* Xout, hipStream_t s);
+                                 int* block_counts, float* Xout, float* phi_copy, hipStream_t s);
 hipError_t launch_cp_reduce_bf16(const float* X, int n_rows, const float* Phi, int D, int K,
-                                 int nblk, float* partial, hipStream_t s);
+                                 int nblk, float* partial, float* phi_copy, hipStream_t s);
 hipError_t launch_whiten_bf16(const tlda_csr_batch& b, const uint16_t* W16, const float* mw16,
                               int Dh, int D, int nblk, float* X, int* block_counts, hipStream_t s);
 // One full round of resident CP-reduction blocks on this device.
