@@ -203,6 +203,69 @@ tlda_status tlda_get_whitening(tlda_ctx* ctx, double* W, double* eig, double* M1
  * U diag(lambda)^(-1/2) has) and M1 [V] from host memory, e.g. computed by an
  * independent implementation; the eigenvalues are taken as 1/|w_d|^2. */
 tlda_status tlda_set_whitening(tlda_ctx* ctx, const double* W, const double* M1);
+/* ------------------------------------------------------------------------
+ * Document-topic encoder: a d_in -> hidden -> hidden -> k_out perceptron
+ * (GELU hidden layers, softmax output) that maps a whitened document x to
+ * topic proportions on the simplex, standing in for the per-document solve of
+ * tlda_infer_doc_topics, which stays as its judge and fallback
+ * (tlda_infer_doc_topics_mlp).  Layers are X W + b with W stored input-major;
+ * the matrix products run on BF16 matrix cores with FP32 accumulation (BF16
+ * copies of FP32 master weights, BF16 activations, FP32 pre-activations);
+ * gelu(z) = z Phi(z) with the standard normal distribution function Phi.
+ * Training minimises the mean row cross-entropy -sum_k t_k log p_k against
+ * target proportions t (e.g. solve outputs) with Adam (beta1 0.9, beta2
+ * 0.999, eps 1e-8).  Parameters are packed as W1 [d_in][hidden], b1 [hidden],
+ * W2 [hidden][hidden], b2 [hidden], W3 [hidden][k_out], b3 [k_out] (FP32).
+ * An encoder is bound to one HIP stream; it is not thread-safe.
+ * ------------------------------------------------------------------------ */
+#define TLDA_MLP_MAX_WIDTH 1024
+typedef struct tlda_mlp tlda_mlp;
+
+/* Number of packed parameters, or 0 for a non-positive width. */
+int64_t tlda_mlp_param_count(int32_t d_in, int32_t hidden, int32_t k_out);
+/* Create an encoder whose work runs on `hip_stream`; max_batch bounds the rows
+ * of one training step (device scratch grows with it).  Parameters start at
+ * zero: set them with tlda_mlp_set_params (the caller draws the
+ * initialisation).  TLDA_ERR_SHAPE for widths outside 1 .. TLDA_MLP_MAX_WIDTH
+ * (k_out <= TLDA_MAX_K). */
+tlda_status tlda_mlp_create(int32_t d_in, int32_t hidden, int32_t k_out, int32_t max_batch,
+                            void* hip_stream, tlda_mlp** out);
+void tlda_mlp_destroy(tlda_mlp* mlp);
+const char* tlda_mlp_last_error(const tlda_mlp* mlp);
+/* Host copies of the packed FP32 parameters (synchronous).  Setting them
+ * refreshes the BF16 copies and resets Adam's state. */
+tlda_status tlda_mlp_set_params(tlda_mlp* mlp, const float* host_params);
+tlda_status tlda_mlp_get_params(tlda_mlp* mlp, float* host_params);
+/* theta_out [n_rows][k_out] = softmax(...) of X [n_rows][d_in] (device
+ * float), in chunks of max_batch rows. */
+tlda_status tlda_mlp_forward(tlda_mlp* mlp, const float* X, int64_t n_rows, float* theta_out);
+/* Gradients of the mean cross-entropy of X against T [n_rows][k_out] (device
+ * float, rows on the simplex), 1 <= n_rows <= max_batch: grads_out (device
+ * float, packed like the parameters) and loss_out (device float); either may
+ * be NULL. */
+tlda_status tlda_mlp_gradients(tlda_mlp* mlp, const float* X, const float* T, int32_t n_rows,
+                               float* grads_out, float* loss_out);
+/* One Adam step with step size lr on the gradients of (X, T). */
+tlda_status tlda_mlp_train_step(tlda_mlp* mlp, const float* X, const float* T, int32_t n_rows,
+                                float lr, float* loss_out);
+/* Document-topic proportions through the encoder, judged by the solve of
+ * tlda_infer_doc_topics: each row starts at the encoder's output t (or at
+ * 1/K when mlp is NULL: the plain solve under the same rule), takes
+ * min_steps projected-gradient steps (each sets the smallest entries of the
+ * softmax output to zero), then continues until the duality gap of
+ * h(t) = |x - A t|^2 / 2 over the simplex, g.t - min_k g_k with
+ * g = A^T (A t - x), which bounds h(t) - min h, is at most gap_tol, or
+ * max_iter steps have been taken.  Rows that needed more than min_steps
+ * steps (their refined encoder output failed the judge) are counted in
+ * *n_stepped_out (device int32, or NULL).  The encoder must have d_in == D
+ * and k_out == K and share the context's stream.  X: device float
+ * [n_rows][D]; mu: device double [V][K]; theta_out: device float
+ * [n_rows][K]. */
+tlda_status tlda_infer_doc_topics_mlp(tlda_ctx* ctx, tlda_mlp* mlp, const float* X, int32_t n_rows,
+                                      const double* mu, float gap_tol, int32_t min_steps,
+                                      int32_t max_iter, float* theta_out,
+                                      int32_t* n_stepped_out);
+
 /* Timing hook for profilers and benchmarks: `start` and `stop` are arrays of
  * n hipEvent_t (created by the caller with timing enabled; the caller keeps
  * ownership).  While set, each tlda_whiten_batch, tlda_cp_step and

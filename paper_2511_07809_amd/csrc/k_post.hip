@@ -124,12 +124,22 @@ __global__ void k_infer_step(const double* __restrict__ ev, int K, float* __rest
 // The simplex projection finds, for each topic, its rank in decreasing order
 // (ties by index) and the sum of all values ranked at or above it; the
 // largest rank r whose value exceeds (prefix_r - 1) / r sets the threshold.
-template <int TPL>
+//
+// GIVEN: the start point is read from `out` (e.g. an encoder's output on the
+// simplex) instead of the uniform 1/K.
+// GAP_RULE: instead of stopping when the L1 change of an iterate falls below
+// tol, stop at the first iterate after min_steps steps whose duality gap for
+// h(t) = |x - A t|^2 / 2, g.t - min_k g_k with g = A^T (A t - x) = G t - b, is
+// at most gap_tol (it bounds h(t) - min h); rows that need more than
+// min_steps steps are counted in *n_stepped.
+template <int TPL, bool GIVEN, bool GAP_RULE>
 __global__ void __launch_bounds__(256) k_infer(const float* __restrict__ X, int n_rows,
                                                const float* __restrict__ A32,
                                                const float* __restrict__ G32,
                                                const float* __restrict__ step32, int D, int K,
-                                               int max_iter, float tol, float* __restrict__ out) {
+                                               int max_iter, float tol, float* __restrict__ out,
+                                               float gap_tol, int min_steps,
+                                               int* __restrict__ n_stepped) {
   __shared__ float xs[4][TLDA_MAX_D];
   __shared__ float ys[4][64 * TPL];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -146,13 +156,17 @@ __global__ void __launch_bounds__(256) k_infer(const float* __restrict__ X, int 
     if (k < K)
       for (int d = 0; d < D; ++d) s = fmaf(A32[d * K + k], xs[wave][d], s);
     b[q] = s;
-    t[q] = k < K ? 1.0f / (float)K : 0.f;
+    if (GIVEN)
+      t[q] = k < K ? out[(size_t)row * K + k] : 0.f;
+    else
+      t[q] = k < K ? 1.0f / (float)K : 0.f;
   }
   for (int it = 0; it < max_iter; ++it) {
 #pragma unroll
     for (int q = 0; q < TPL; ++q) ys[wave][lane + 64 * q] = t[q];
     wave_sync();
     float y[TPL];
+    float gt = 0.f, gmin = INFINITY;
 #pragma unroll
     for (int q = 0; q < TPL; ++q) {
       const int k = lane + 64 * q;
@@ -160,8 +174,18 @@ __global__ void __launch_bounds__(256) k_infer(const float* __restrict__ X, int 
       if (k < K) {
         for (int j = 0; j < K; ++j) g = fmaf(G32[k * K + j], ys[wave][j], g);
         g -= b[q];
+        gt = fmaf(g, t[q], gt);
+        gmin = fminf(gmin, g);
       }
       y[q] = t[q] - step * g;
+    }
+    if (GAP_RULE) {
+      for (int off = 32; off > 0; off >>= 1) {
+        gt += __shfl_xor(gt, off, 64);
+        gmin = fminf(gmin, __shfl_xor(gmin, off, 64));
+      }
+      if (it >= min_steps && gt - gmin <= gap_tol) break;   // within gap_tol of the minimum
+      if (it == min_steps && lane == 0) atomicAdd(n_stepped, 1);
     }
     wave_sync();
 #pragma unroll
@@ -206,7 +230,7 @@ __global__ void __launch_bounds__(256) k_infer(const float* __restrict__ X, int 
     }
     for (int off = 32; off > 0; off >>= 1) change += __shfl_xor(change, off, 64);
     wave_sync();
-    if (change < tol) break;
+    if (!GAP_RULE && change < tol) break;
   }
 #pragma unroll
   for (int q = 0; q < TPL; ++q) {
@@ -253,21 +277,43 @@ hipError_t launch_inference_setup(const double* W, const double* m, const double
   return hipGetLastError();
 }
 
-hipError_t launch_infer(const float* X, int n_rows, const float* A32, const float* G32,
-                        const float* step32, int D, int K, int max_iter, float tol,
-                        float* theta, hipStream_t s) {
+template <bool GIVEN, bool GAP_RULE>
+hipError_t launch_infer_t(const float* X, int n_rows, const float* A32, const float* G32,
+                          const float* step32, int D, int K, int max_iter, float tol, float* theta,
+                          float gap_tol, int min_steps, int* n_stepped, hipStream_t s) {
   if (n_rows == 0) return hipSuccess;
   const dim3 grid((n_rows + 3) / 4);
   if (K <= 64)
-    hipLaunchKernelGGL(k_infer<1>, grid, dim3(256), 0, s, X, n_rows, A32, G32, step32, D, K,
-                       max_iter, tol, theta);
+    hipLaunchKernelGGL((k_infer<1, GIVEN, GAP_RULE>), grid, dim3(256), 0, s, X, n_rows, A32, G32,
+                       step32, D, K, max_iter, tol, theta, gap_tol, min_steps,
+                       n_stepped);
   else if (K <= 128)
-    hipLaunchKernelGGL(k_infer<2>, grid, dim3(256), 0, s, X, n_rows, A32, G32, step32, D, K,
-                       max_iter, tol, theta);
+    hipLaunchKernelGGL((k_infer<2, GIVEN, GAP_RULE>), grid, dim3(256), 0, s, X, n_rows, A32, G32,
+                       step32, D, K, max_iter, tol, theta, gap_tol, min_steps,
+                       n_stepped);
   else
-    hipLaunchKernelGGL(k_infer<4>, grid, dim3(256), 0, s, X, n_rows, A32, G32, step32, D, K,
-                       max_iter, tol, theta);
+    hipLaunchKernelGGL((k_infer<4, GIVEN, GAP_RULE>), grid, dim3(256), 0, s, X, n_rows, A32, G32,
+                       step32, D, K, max_iter, tol, theta, gap_tol, min_steps,
+                       n_stepped);
   return hipGetLastError();
+}
+
+hipError_t launch_infer(const float* X, int n_rows, const float* A32, const float* G32,
+                        const float* step32, int D, int K, int max_iter, float tol,
+                        float* theta, hipStream_t s) {
+  return launch_infer_t<false, false>(X, n_rows, A32, G32, step32, D, K, max_iter, tol, theta,
+                                      0.f, 0, nullptr, s);
+}
+
+hipError_t launch_infer_gap(const float* X, int n_rows, const float* A32, const float* G32,
+                            const float* step32, int D, int K, bool given_start, float gap_tol,
+                            int min_steps, int max_iter, float* theta, int* n_stepped,
+                            hipStream_t s) {
+  return given_start
+             ? launch_infer_t<true, true>(X, n_rows, A32, G32, step32, D, K, max_iter, 0.f, theta,
+                                          gap_tol, min_steps, n_stepped, s)
+             : launch_infer_t<false, true>(X, n_rows, A32, G32, step32, D, K, max_iter, 0.f,
+                                           theta, gap_tol, min_steps, n_stepped, s);
 }
 
 }  // namespace tlda

@@ -1,5 +1,6 @@
 // Host side of the C ABI declared in include/tlda.h: argument checks, device
 // state, stream ordering, the whitening refresh driver and checkpoints.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -7,6 +8,9 @@
 #include <vector>
 
 #include "tlda_internal.h"
+
+#include <algorithm>
+#include <cmath>
 
 using tlda::launch_zero;
 
@@ -701,6 +705,184 @@ tlda_status tlda_set_timing_events(tlda_ctx* c, void* const* start, void* const*
     c->t_stop[i] = static_cast<hipEvent_t>(stop[i]);
   }
   c->t_n = n;
+  return TLDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Document-topic encoder
+// ---------------------------------------------------------------------------
+namespace {
+
+void mlp_free(tlda_mlp* m) {
+  if (!m) return;
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  dfree(m->params); dfree(m->wb); dfree(m->grads); dfree(m->adam_m); dfree(m->adam_v);
+  dfree(m->Z1); dfree(m->Z2); dfree(m->H1); dfree(m->H2); dfree(m->logits); dfree(m->dZ3);
+  dfree(m->dZa); dfree(m->dZb); dfree(m->row_loss);
+  delete m;
+}
+
+#define MLP_OK(m, expr)                                                            \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      (m)->last_error = std::string(#expr) + ": " + hipGetErrorString(e_);         \
+      return e_ == hipErrorOutOfMemory ? TLDA_ERR_OOM : TLDA_ERR_DEVICE;           \
+    }                                                                              \
+  } while (0)
+
+#define MLP_CHECK(m, cond, code, msg) \
+  do {                                \
+    if (!(cond)) {                    \
+      (m)->last_error = msg;          \
+      return code;                    \
+    }                                 \
+  } while (0)
+
+}  // namespace
+
+int64_t tlda_mlp_param_count(int32_t d_in, int32_t hidden, int32_t k_out) {
+  if (d_in < 1 || hidden < 1 || k_out < 1) return 0;
+  return (int64_t)tlda::mlp_param_count(d_in, hidden, k_out);
+}
+
+tlda_status tlda_mlp_create(int32_t d_in, int32_t hidden, int32_t k_out, int32_t max_batch,
+                            void* hip_stream, tlda_mlp** out) {
+  if (out == nullptr) return TLDA_ERR_ARG;
+  *out = nullptr;
+  if (d_in < 1 || d_in > TLDA_MLP_MAX_WIDTH || hidden < 1 || hidden > TLDA_MLP_MAX_WIDTH ||
+      k_out < 1 || k_out > TLDA_MAX_K || max_batch < 1)
+    return TLDA_ERR_SHAPE;
+  tlda_mlp* m = new (std::nothrow) tlda_mlp();
+  if (!m) return TLDA_ERR_OOM;
+  m->d_in = d_in;
+  m->hidden = hidden;
+  m->k_out = k_out;
+  m->max_batch = max_batch;
+  m->n_params = tlda::mlp_param_count(d_in, hidden, k_out);
+  m->stream = static_cast<hipStream_t>(hip_stream);
+  const size_t P = m->n_params, B = (size_t)max_batch, H = hidden, K = k_out;
+  bool ok = dalloc(&m->params, P) == hipSuccess && dalloc(&m->wb, P) == hipSuccess &&
+            dalloc(&m->grads, P) == hipSuccess && dalloc(&m->adam_m, P) == hipSuccess &&
+            dalloc(&m->adam_v, P) == hipSuccess && dalloc(&m->Z1, B * H) == hipSuccess &&
+            dalloc(&m->Z2, B * H) == hipSuccess && dalloc(&m->H1, B * H) == hipSuccess &&
+            dalloc(&m->H2, B * H) == hipSuccess && dalloc(&m->logits, B * K) == hipSuccess &&
+            dalloc(&m->dZ3, B * K) == hipSuccess && dalloc(&m->dZa, B * H) == hipSuccess &&
+            dalloc(&m->dZb, B * H) == hipSuccess && dalloc(&m->row_loss, B) == hipSuccess;
+  if (!ok) {
+    mlp_free(m);
+    return TLDA_ERR_OOM;
+  }
+  if (launch_zero(m->params, P * sizeof(float), m->stream) != hipSuccess ||
+      launch_zero(m->wb, P * sizeof(uint16_t), m->stream) != hipSuccess ||
+      launch_zero(m->adam_m, P * sizeof(float), m->stream) != hipSuccess ||
+      launch_zero(m->adam_v, P * sizeof(float), m->stream) != hipSuccess ||
+      hipStreamSynchronize(m->stream) != hipSuccess) {
+    mlp_free(m);
+    return TLDA_ERR_DEVICE;
+  }
+  *out = m;
+  return TLDA_OK;
+}
+
+void tlda_mlp_destroy(tlda_mlp* mlp) { mlp_free(mlp); }
+
+const char* tlda_mlp_last_error(const tlda_mlp* mlp) { return mlp ? mlp->last_error.c_str() : ""; }
+
+tlda_status tlda_mlp_set_params(tlda_mlp* m, const float* host_params) {
+  if (!m) return TLDA_ERR_ARG;
+  MLP_CHECK(m, host_params != nullptr, TLDA_ERR_ARG, "params is NULL");
+  for (size_t i = 0; i < m->n_params; ++i)
+    MLP_CHECK(m, std::isfinite(host_params[i]), TLDA_ERR_ARG, "a parameter is not finite");
+  MLP_OK(m, hipMemcpyAsync(m->params, host_params, m->n_params * sizeof(float),
+                           hipMemcpyHostToDevice, m->stream));
+  MLP_OK(m, tlda::mlp_refresh_bf16(*m));
+  MLP_OK(m, launch_zero(m->adam_m, m->n_params * sizeof(float), m->stream));
+  MLP_OK(m, launch_zero(m->adam_v, m->n_params * sizeof(float), m->stream));
+  MLP_OK(m, hipStreamSynchronize(m->stream));
+  m->adam_t = 0;
+  return TLDA_OK;
+}
+
+tlda_status tlda_mlp_get_params(tlda_mlp* m, float* host_params) {
+  if (!m) return TLDA_ERR_ARG;
+  MLP_CHECK(m, host_params != nullptr, TLDA_ERR_ARG, "params is NULL");
+  MLP_OK(m, hipMemcpyAsync(host_params, m->params, m->n_params * sizeof(float),
+                           hipMemcpyDeviceToHost, m->stream));
+  MLP_OK(m, hipStreamSynchronize(m->stream));
+  return TLDA_OK;
+}
+
+tlda_status tlda_mlp_forward(tlda_mlp* m, const float* X, int64_t n_rows, float* theta_out) {
+  if (!m) return TLDA_ERR_ARG;
+  MLP_CHECK(m, n_rows >= 0, TLDA_ERR_SHAPE, "negative n_rows");
+  MLP_CHECK(m, (X && theta_out) || n_rows == 0, TLDA_ERR_ARG, "X or theta is NULL");
+  for (int64_t r0 = 0; r0 < n_rows; r0 += m->max_batch) {
+    const int n = (int)std::min<int64_t>(m->max_batch, n_rows - r0);
+    MLP_OK(m, tlda::mlp_forward(*m, X + r0 * m->d_in, n, theta_out + r0 * m->k_out, false));
+  }
+  return TLDA_OK;
+}
+
+tlda_status tlda_mlp_gradients(tlda_mlp* m, const float* X, const float* T, int32_t n_rows,
+                               float* grads_out, float* loss_out) {
+  if (!m) return TLDA_ERR_ARG;
+  MLP_CHECK(m, n_rows >= 1 && n_rows <= m->max_batch, TLDA_ERR_SHAPE,
+            "n_rows must be in 1 .. max_batch");
+  MLP_CHECK(m, X && T, TLDA_ERR_ARG, "X or T is NULL");
+  MLP_OK(m, tlda::mlp_forward(*m, X, n_rows, nullptr, true));
+  MLP_OK(m, tlda::mlp_backward(*m, X, T, n_rows, loss_out));
+  if (grads_out)
+    MLP_OK(m, hipMemcpyAsync(grads_out, m->grads, m->n_params * sizeof(float),
+                             hipMemcpyDeviceToDevice, m->stream));
+  return TLDA_OK;
+}
+
+tlda_status tlda_mlp_train_step(tlda_mlp* m, const float* X, const float* T, int32_t n_rows,
+                                float lr, float* loss_out) {
+  if (!m) return TLDA_ERR_ARG;
+  MLP_CHECK(m, std::isfinite(lr) && lr > 0.f, TLDA_ERR_ARG, "lr must be finite and > 0");
+  tlda_status st = tlda_mlp_gradients(m, X, T, n_rows, nullptr, loss_out);
+  if (st != TLDA_OK) return st;
+  MLP_OK(m, tlda::mlp_adam(*m, lr, 0.9f, 0.999f, 1e-8f));
+  return TLDA_OK;
+}
+
+tlda_status tlda_infer_doc_topics_mlp(tlda_ctx* c, tlda_mlp* m, const float* X, int32_t n_rows,
+                                      const double* mu, float gap_tol, int32_t min_steps,
+                                      int32_t max_iter, float* theta_out,
+                                      int32_t* n_stepped_out) {
+  if (!c) return TLDA_ERR_ARG;
+  if (m != nullptr) {
+    CHECK_ARG(c, m->d_in == c->cfg.D && m->k_out == c->cfg.K, TLDA_ERR_SHAPE,
+              "encoder widths do not match the context's D and K");
+    CHECK_ARG(c, m->stream == c->stream, TLDA_ERR_ARG,
+              "the encoder and the context must share a stream");
+  }
+  CHECK_ARG(c, n_rows >= 0 && max_iter >= 0 && min_steps >= 0, TLDA_ERR_ARG,
+            "negative n_rows, min_steps or max_iter");
+  CHECK_ARG(c, gap_tol >= 0.0f && std::isfinite(gap_tol), TLDA_ERR_ARG,
+            "gap_tol must be finite and >= 0");
+  CHECK_ARG(c, mu != nullptr, TLDA_ERR_ARG, "mu is NULL");
+  CHECK_ARG(c, (X && theta_out) || n_rows == 0, TLDA_ERR_ARG, "X or theta is NULL");
+  CHECK_ARG(c, c->wh.ready, TLDA_ERR_STATE, "no whitening matrix yet");
+  int32_t* ns = n_stepped_out ? n_stepped_out : c->dev_flags + 3;
+  HIP_OK(c, launch_zero(ns, sizeof(int32_t), c->stream));
+  if (n_rows == 0) return TLDA_OK;
+  const int V = c->cfg.V, D = c->cfg.D, K = c->cfg.K;
+  HIP_OK(c, launch_zero(c->dev_flags + 1, sizeof(int), c->stream));
+  HIP_OK(c, tlda::launch_inference_setup(c->wh.W, c->wh.m, mu, V, D, K, c->postA, c->postG,
+                                         c->postZ, c->postEv, c->A32, c->G32, c->step32,
+                                         c->dev_flags + 1, c->stream));
+  if (m != nullptr) {
+    tlda_status st = tlda_mlp_forward(m, X, n_rows, theta_out);
+    if (st != TLDA_OK) {
+      set_err(c, m->last_error);
+      return st;
+    }
+  }
+  HIP_OK(c, tlda::launch_infer_gap(X, n_rows, c->A32, c->G32, c->step32, D, K, m != nullptr,
+                                   gap_tol, min_steps, max_iter, theta_out, ns, c->stream));
   return TLDA_OK;
 }
 

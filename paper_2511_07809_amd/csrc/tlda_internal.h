@@ -129,6 +129,30 @@ struct tlda_ctx {
   std::string last_error;
 };
 
+// Document-topic encoder: d_in -> hidden -> hidden -> k_out MLP (GELU,
+// softmax), FP32 master parameters with BF16 copies for the matrix cores.
+struct tlda_mlp {
+  int d_in = 0, hidden = 0, k_out = 0, max_batch = 0;
+  size_t n_params = 0;
+  hipStream_t stream = nullptr;
+  float* params = nullptr;     // [n_params] FP32 master, packed W1 b1 W2 b2 W3 b3
+  uint16_t* wb = nullptr;      // BF16 copies of W1, W2, W3 (same offsets as in params)
+  float* grads = nullptr;      // [n_params]
+  float* adam_m = nullptr;     // [n_params]
+  float* adam_v = nullptr;     // [n_params]
+  long long adam_t = 0;
+  float* Z1 = nullptr;         // [max_batch][hidden] FP32 pre-activations
+  float* Z2 = nullptr;
+  uint16_t* H1 = nullptr;      // [max_batch][hidden] BF16 activations
+  uint16_t* H2 = nullptr;
+  float* logits = nullptr;     // [max_batch][k_out]
+  uint16_t* dZ3 = nullptr;     // [max_batch][k_out] BF16
+  uint16_t* dZa = nullptr;     // [max_batch][hidden] BF16 (dZ2, then dZ1)
+  uint16_t* dZb = nullptr;
+  float* row_loss = nullptr;   // [max_batch]
+  std::string last_error;
+};
+
 namespace tlda {
 
 // Timing hook of the main kernel of a hot-path call: the API stores a pair
@@ -223,6 +247,18 @@ hipError_t launch_whiten_bf16(const tlda_csr_batch& b, const uint16_t* W16, cons
                               int Dh, int D, int nblk, float* X, int* block_counts, hipStream_t s);
 // One full round of resident CP-reduction blocks on this device.
 int cp_resident_blocks(int D, int K, int num_cu);
+// document-topic encoder (MLP)
+size_t mlp_param_count(int d_in, int hidden, int k_out);
+// offsets of W1, b1, W2, b2, W3, b3 in the packed parameter vector
+void mlp_offsets(int d_in, int hidden, int k_out, size_t off[6]);
+// forward pass of n <= max_batch rows: theta = softmax(...) (FP32 [n][k_out]);
+// with train, also keeps the intermediates for mlp_backward
+hipError_t mlp_forward(tlda_mlp& m, const float* X, int n, float* theta, bool train);
+// loss and gradients of the mean cross-entropy against targets T [n][k_out]
+// (needs a preceding mlp_forward(train) of the same rows); loss_out: device float or NULL
+hipError_t mlp_backward(tlda_mlp& m, const float* X, const float* T, int n, float* loss_out);
+hipError_t mlp_adam(tlda_mlp& m, float lr, float beta1, float beta2, float eps);
+hipError_t mlp_refresh_bf16(tlda_mlp& m);
 // post-processing
 hipError_t launch_unwhiten(const float* Phi, const double* U, const double* eig, const double* m,
                            int V, int D, int K, double theta, uint32_t flags, double* mu,
@@ -234,5 +270,14 @@ hipError_t launch_inference_setup(const double* W, const double* m, const double
 hipError_t launch_infer(const float* X, int n_rows, const float* A32, const float* G32,
                         const float* step32, int D, int K, int max_iter, float tol,
                         float* theta, hipStream_t s);
+// Projected gradient with a duality-gap stopping rule: from the start point
+// held in theta (given_start) or from 1/K, at least min_steps steps, then
+// until the gap of the iterate is at most gap_tol or max_iter steps; rows
+// that need more than min_steps steps are counted in *n_stepped (which the
+// caller zeroes).
+hipError_t launch_infer_gap(const float* X, int n_rows, const float* A32, const float* G32,
+                            const float* step32, int D, int K, bool given_start, float gap_tol,
+                            int min_steps, int max_iter, float* theta, int* n_stepped,
+                            hipStream_t s);
 
 }  // namespace tlda

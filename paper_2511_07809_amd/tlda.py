@@ -28,13 +28,17 @@ TLDA_PROJECT_SIMPLEX = 0x1
 TLDA_MAX_D = 256
 TLDA_MAX_K = 256
 TLDA_MAX_DK = 16384
+TLDA_MLP_MAX_WIDTH = 1024
 
 EXPORTED = ("tlda_create", "tlda_destroy", "tlda_status_str", "tlda_last_error",
             "tlda_update_moments", "tlda_whiten_batch", "tlda_cp_step", "tlda_whiten_cp_step",
             "tlda_unwhiten",
             "tlda_infer_doc_topics", "tlda_stage_batch", "tlda_get_stats",
             "tlda_get_whitening", "tlda_set_whitening", "tlda_set_timing_events",
-            "tlda_save_state", "tlda_load_state")
+            "tlda_save_state", "tlda_load_state",
+            "tlda_mlp_param_count", "tlda_mlp_create", "tlda_mlp_destroy", "tlda_mlp_last_error",
+            "tlda_mlp_set_params", "tlda_mlp_get_params", "tlda_mlp_forward",
+            "tlda_mlp_gradients", "tlda_mlp_train_step", "tlda_infer_doc_topics_mlp")
 
 
 class tlda_config(ctypes.Structure):
@@ -75,6 +79,17 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tlda_set_whitening": ([vp, vp, vp], i32),
         "tlda_set_timing_events": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32], i32),
         "tlda_save_state": ([vp, vp, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "tlda_mlp_param_count": ([i32, i32, i32], ctypes.c_int64),
+        "tlda_mlp_create": ([i32, i32, i32, i32, vp, ctypes.POINTER(vp)], i32),
+        "tlda_mlp_destroy": ([vp], None),
+        "tlda_mlp_last_error": ([vp], ctypes.c_char_p),
+        "tlda_mlp_set_params": ([vp, vp], i32),
+        "tlda_mlp_get_params": ([vp, vp], i32),
+        "tlda_mlp_forward": ([vp, vp, ctypes.c_int64, vp], i32),
+        "tlda_mlp_gradients": ([vp, vp, vp, i32, vp, vp], i32),
+        "tlda_mlp_train_step": ([vp, vp, vp, i32, ctypes.c_float, vp], i32),
+        "tlda_infer_doc_topics_mlp": ([vp, vp, vp, i32, vp, ctypes.c_float, i32, i32, vp, vp],
+                                      i32),
         "tlda_load_state": ([vp, vp, ctypes.c_size_t], i32),
     }
     for name, (args, res) in sig.items():
@@ -299,3 +314,100 @@ def tlda_save_state(ctx: Context) -> bytes:
 def tlda_load_state(ctx: Context, data: bytes) -> None:
     buf = ctypes.create_string_buffer(data, len(data))
     _check(ctx, _LIB.tlda_load_state(ctx.handle, buf, len(data)))
+
+
+# ---------------------------------------------------------------------------
+# Document-topic encoder
+# ---------------------------------------------------------------------------
+class Mlp:
+    """Owns a tlda_mlp* created on a HIP stream."""
+
+    def __init__(self, handle: int, d_in: int, hidden: int, k_out: int, max_batch: int,
+                 stream: torch.cuda.Stream):
+        self.handle = handle
+        self.d_in, self.hidden, self.k_out, self.max_batch = d_in, hidden, k_out, max_batch
+        self.stream = stream
+        self.n_params = int(_LIB.tlda_mlp_param_count(d_in, hidden, k_out))
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _LIB.tlda_mlp_destroy(self.handle)
+            self.handle = None
+
+
+def _check_mlp(m: Mlp, status: int) -> None:
+    if status != TLDA_OK:
+        msg = _LIB.tlda_mlp_last_error(m.handle) or b""
+        raise TldaError(status, msg.decode() or _LIB.tlda_status_str(status).decode())
+
+
+def tlda_mlp_param_count(d_in: int, hidden: int, k_out: int) -> int:
+    return int(_LIB.tlda_mlp_param_count(d_in, hidden, k_out))
+
+
+def tlda_mlp_create(d_in: int, hidden: int, k_out: int, max_batch: int,
+                    stream: Optional[torch.cuda.Stream] = None) -> Mlp:
+    if not torch.cuda.is_available():
+        raise RuntimeError("libtlda needs a ROCm GPU; none is visible")
+    stream = stream or torch.cuda.current_stream()
+    h = ctypes.c_void_p()
+    st = _LIB.tlda_mlp_create(d_in, hidden, k_out, max_batch, ctypes.c_void_p(stream.cuda_stream),
+                              ctypes.byref(h))
+    if st != TLDA_OK:
+        raise TldaError(st, _LIB.tlda_status_str(st).decode())
+    return Mlp(h.value, d_in, hidden, k_out, max_batch, stream)
+
+
+def tlda_mlp_set_params(m: Mlp, params) -> None:
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.shape == (m.n_params,)
+    _check_mlp(m, _LIB.tlda_mlp_set_params(m.handle, p.ctypes.data))
+
+
+def tlda_mlp_get_params(m: Mlp):
+    import numpy as np
+    p = np.empty(m.n_params, dtype=np.float32)
+    _check_mlp(m, _LIB.tlda_mlp_get_params(m.handle, p.ctypes.data))
+    return p
+
+
+def tlda_mlp_forward(m: Mlp, X: torch.Tensor, theta: Optional[torch.Tensor] = None) -> torch.Tensor:
+    n = X.shape[0]
+    assert X.dtype == torch.float32 and X.is_contiguous() and X.shape[1] == m.d_in
+    if theta is None:
+        theta = torch.empty((n, m.k_out), dtype=torch.float32, device="cuda")
+    _check_mlp(m, _LIB.tlda_mlp_forward(m.handle, _ptr(X), n, _ptr(theta)))
+    return theta
+
+
+def tlda_mlp_gradients(m: Mlp, X: torch.Tensor, T: torch.Tensor):
+    n = X.shape[0]
+    assert X.is_contiguous() and T.is_contiguous() and T.shape == (n, m.k_out)
+    g = torch.empty(m.n_params, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check_mlp(m, _LIB.tlda_mlp_gradients(m.handle, _ptr(X), _ptr(T), n, _ptr(g), _ptr(loss)))
+    return g, loss
+
+
+def tlda_mlp_train_step(m: Mlp, X: torch.Tensor, T: torch.Tensor, lr: float,
+                        loss: Optional[torch.Tensor] = None) -> None:
+    n = X.shape[0]
+    assert X.is_contiguous() and T.is_contiguous() and T.shape == (n, m.k_out)
+    _check_mlp(m, _LIB.tlda_mlp_train_step(m.handle, _ptr(X), _ptr(T), n, float(lr), _ptr(loss)))
+
+
+def tlda_infer_doc_topics_mlp(ctx: Context, m: Optional[Mlp], X: torch.Tensor, n_rows: int,
+                              mu: torch.Tensor, gap_tol: float, max_iter: int,
+                              theta: Optional[torch.Tensor] = None,
+                              n_stepped: Optional[torch.Tensor] = None, min_steps: int = 0):
+    if theta is None:
+        theta = torch.empty((n_rows, ctx.K), dtype=torch.float32, device="cuda")
+    if n_stepped is None:
+        n_stepped = torch.zeros(1, dtype=torch.int32, device="cuda")
+    assert mu.dtype == torch.float64 and mu.is_contiguous()
+    _check(ctx, _LIB.tlda_infer_doc_topics_mlp(ctx.handle, m.handle if m is not None else None,
+                                               _ptr(X), n_rows, _ptr(mu), float(gap_tol),
+                                               min_steps, max_iter, _ptr(theta),
+                                               _ptr(n_stepped)))
+    return theta, n_stepped
