@@ -266,6 +266,51 @@ tlda_status tlda_infer_doc_topics_mlp(tlda_ctx* ctx, tlda_mlp* mlp, const float*
                                       int32_t max_iter, float* theta_out,
                                       int32_t* n_stepped_out);
 
+/* ------------------------------------------------------------------------
+ * Batched time slices: many independent corpora (slices), each with its own
+ * context (its own moments, whitening, K and Phi), stepped together.  A plan
+ * fixes one CSR batch per slice; tlda_multi_step runs the same work as
+ * tlda_whiten_cp_step on every slice's batch with two launches in all: one
+ * persistent reduction launch whose blocks are laid out over the slices in
+ * proportion to their row tiles, and one finish launch.  A sequence of steps
+ * (e.g. a pass over every batch index) can be captured once in a HIP graph
+ * and replayed.
+ * ------------------------------------------------------------------------ */
+typedef struct tlda_multi tlda_multi;
+typedef struct tlda_graph tlda_graph;
+/* ctxs: n_slices distinct BF16 contexts (TLDA_BF16) with D, K <= 64, a
+ * whitening matrix, and one shared non-null stream.  batches: one device
+ * batch per slice (caller-owned arrays that must stay valid while the plan
+ * is used; staging slots are not accepted; n_rows may be 0, which leaves
+ * that slice's Phi unchanged and its gradient zero).  Phis: distinct device
+ * float [D_i][K_i], updated in place by each step.  betas: host [n_slices]
+ * step sizes.  n_kept_out: device int32 [n_slices] or NULL, receives the
+ * kept-row counts at each step.  Batches of contexts created with
+ * TLDA_VALIDATE_CSR are validated once, here.  TLDA_ERR_SHAPE for a context
+ * that is not BF16 or has D or K above 64; TLDA_ERR_STATE without a
+ * whitening matrix. */
+tlda_status tlda_multi_create(int32_t n_slices, tlda_ctx* const* ctxs,
+                              const tlda_csr_batch* batches, float* const* Phis,
+                              const float* betas, int32_t* n_kept_out, tlda_multi** out);
+void tlda_multi_destroy(tlda_multi* plan);
+const char* tlda_multi_last_error(const tlda_multi* plan);
+/* Launch shape: total reduction blocks over all slices (0 = one round of
+ * resident blocks on the device, the default).  Synchronous. */
+tlda_status tlda_multi_set_blocks(tlda_multi* plan, int32_t total_blocks);
+tlda_status tlda_multi_get_blocks(const tlda_multi* plan, int32_t* total_blocks);
+/* One step of every slice (asynchronous on the contexts' stream). */
+tlda_status tlda_multi_step(tlda_multi* plan);
+/* Autotuner: times `reps` steps for each candidate launch shape (1, 2, ...
+ * resident blocks per CU, and two rounds), keeps the fastest and restores
+ * every Phi to its value at entry.  Synchronous. */
+tlda_status tlda_multi_autotune(tlda_multi* plan, int32_t reps, int32_t* total_blocks_out);
+/* Capture the steps of n_plans plans, in order, as one HIP graph on their
+ * shared stream; tlda_graph_launch replays it (asynchronous).  A plan's
+ * launch shape is frozen into the graph when it is captured. */
+tlda_status tlda_graph_capture(tlda_multi* const* plans, int32_t n_plans, tlda_graph** out);
+tlda_status tlda_graph_launch(tlda_graph* graph);
+void tlda_graph_destroy(tlda_graph* graph);
+
 /* Timing hook for profilers and benchmarks: `start` and `stop` are arrays of
  * n hipEvent_t (created by the caller with timing enabled; the caller keeps
  * ownership).  While set, each tlda_whiten_batch, tlda_cp_step and

@@ -114,23 +114,24 @@ struct Bf16Shape {
   static constexpr int TKW = (NCT + WK - 1) / WK;      // R1 column tiles per wave
 };
 
+// The work of one block: block `blk` of `nblk` blocks that share one batch.
+// LDS comes from the caller (Xs: kTile x LDA, XsT: DQ x LDT, SsT: KQ x LDT
+// BF16 values, wave_kept: 4 ints), so one kernel can serve several shapes.
 template <int DQ, int KQ, int G, int MODE>
-__global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp_bf16(
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+__device__ __forceinline__ void cp_bf16_block(
+    int blk, int nblk, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const float* __restrict__ val, int n_rows, const uint16_t* __restrict__ W16,
     const float* __restrict__ mw16, int Dh, const float* __restrict__ Xin, int D,
-    const float* __restrict__ Phi, int K, int nblk, float* __restrict__ partial,
-    int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy) {
+    const float* __restrict__ Phi, int K, float* __restrict__ partial,
+    int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy,
+    uint16_t* __restrict__ Xs, uint16_t* __restrict__ XsT, uint16_t* __restrict__ SsT,
+    int* __restrict__ wave_kept) {
   typedef Bf16Shape<DQ, KQ> Sh;
   constexpr bool kCp = MODE != kWhitenOnly;
   constexpr int RPW = 64 / G;
   constexpr int RPB = 4 * RPW;
   constexpr int PASSES = (kTile + RPB - 1) / RPB;
   constexpr int SLOTS = G >= kNB ? 1 : kNB / G;
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[kCp ? kTile * Sh::LDA : 8];
-  __shared__ __attribute__((aligned(16))) uint16_t XsT[kCp ? DQ * Sh::LDT : 8];
-  __shared__ __attribute__((aligned(16))) uint16_t SsT[kCp ? KQ * Sh::LDT : 8];
-  __shared__ int wave_kept[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
   const int gl = lane % G;
@@ -139,7 +140,7 @@ __global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp
   const unsigned char* W16b = reinterpret_cast<const unsigned char*>(W16);
 
   if (kCp) {
-    for (int e = blockIdx.x * kThreads + tid; e < D * K; e += nblk * kThreads)
+    for (int e = blk * kThreads + tid; e < D * K; e += nblk * kThreads)
       phi_copy[e] = Phi[e];
     for (int e = tid; e < kTile * Sh::LDA; e += kThreads) Xs[e] = 0;
     for (int e = tid; e < DQ * Sh::LDT; e += kThreads) XsT[e] = 0;
@@ -173,7 +174,7 @@ __global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp
   int kept_total = 0;
 
   const int ntiles = (n_rows + kTile - 1) / kTile;
-  for (int tile = blockIdx.x; tile < ntiles; tile += nblk) {
+  for (int tile = blk; tile < ntiles; tile += nblk) {
     if (kCp) __syncthreads();
     // ---- 1. rows of the tile ----
 #pragma unroll 1
@@ -347,7 +348,7 @@ __global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp
   }
   if (kCp) {
     const int wd = wave % Sh::WD, wk = wave / Sh::WD;
-    float* out = partial + (size_t)blockIdx.x * D * K;
+    float* out = partial + (size_t)blk * D * K;
 #pragma unroll
     for (int a = 0; a < Sh::TDW; ++a)
 #pragma unroll
@@ -367,8 +368,57 @@ __global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp
     if (lane == 0) wave_kept[wave] = kept_total;
     __syncthreads();
     if (tid == 0)
-      block_counts[blockIdx.x] = wave_kept[0] + wave_kept[1] + wave_kept[2] + wave_kept[3];
+      block_counts[blk] = wave_kept[0] + wave_kept[1] + wave_kept[2] + wave_kept[3];
   }
+}
+
+
+template <int DQ, int KQ, int G, int MODE>
+__global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp_bf16(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+    const float* __restrict__ val, int n_rows, const uint16_t* __restrict__ W16,
+    const float* __restrict__ mw16, int Dh, const float* __restrict__ Xin, int D,
+    const float* __restrict__ Phi, int K, int nblk, float* __restrict__ partial,
+    int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy) {
+  typedef Bf16Shape<DQ, KQ> Sh;
+  constexpr bool kCp = MODE != kWhitenOnly;
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[kCp ? kTile * Sh::LDA : 8];
+  __shared__ __attribute__((aligned(16))) uint16_t XsT[kCp ? DQ * Sh::LDT : 8];
+  __shared__ __attribute__((aligned(16))) uint16_t SsT[kCp ? KQ * Sh::LDT : 8];
+  __shared__ int wave_kept[4];
+  cp_bf16_block<DQ, KQ, G, MODE>(blockIdx.x, nblk, row_ptr, col_idx, val, n_rows, W16, mw16, Dh,
+                                 Xin, D, Phi, K, partial, block_counts, Xout, phi_copy, Xs, XsT,
+                                 SsT, wave_kept);
+}
+
+// Several batches (the slices of a batched run, each with its own
+// whitening, D, K and Phi) in one launch: block b serves slice blk_slice[b],
+// as block b - blk0 of that slice's nblk blocks.  One LDS allocation of the
+// largest shape (D, K <= 64) serves every slice.
+__global__ void __launch_bounds__(kThreads, 3) k_cp_bf16_multi(const SliceStep* __restrict__ sl,
+                                                               const int* __restrict__ blk_slice) {
+  constexpr int LDA = 64 + 8, LDT = kTile + 8;
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[kTile * LDA];
+  __shared__ __attribute__((aligned(16))) uint16_t XsT[64 * LDT];
+  __shared__ __attribute__((aligned(16))) uint16_t SsT[64 * LDT];
+  __shared__ int wave_kept[4];
+  const SliceStep& d = sl[blk_slice[blockIdx.x]];
+  const int blk = blockIdx.x - d.blk0;
+#define TLDA_MULTI(DQ_, KQ_, G_)                                                               \
+  case multi_shape_id(DQ_, KQ_, G_):                                                           \
+    cp_bf16_block<DQ_, KQ_, G_, kFused>(blk, d.nblk, d.row_ptr, d.col_idx, d.val, d.n_rows,    \
+                                        d.W16, d.mw16, d.Dh, nullptr, d.D, d.Phi, d.K,         \
+                                        d.partial, d.block_counts, nullptr, d.phi_copy, Xs,    \
+                                        XsT, SsT, wave_kept);                                  \
+    break;
+  switch (d.shape) {
+    TLDA_MULTI(32, 16, 1) TLDA_MULTI(32, 16, 2) TLDA_MULTI(32, 16, 4)
+    TLDA_MULTI(32, 32, 1) TLDA_MULTI(32, 32, 2) TLDA_MULTI(32, 32, 4)
+    TLDA_MULTI(32, 64, 1) TLDA_MULTI(32, 64, 2) TLDA_MULTI(32, 64, 4)
+    TLDA_MULTI(64, 16, 8) TLDA_MULTI(64, 32, 8) TLDA_MULTI(64, 64, 8)
+    default: break;
+  }
+#undef TLDA_MULTI
 }
 
 struct Bf16Args {
@@ -455,6 +505,28 @@ hipError_t dispatch(int mode, const Bf16Args& a, int* per_cu, hipStream_t s) {
 }  // namespace
 
 int bf16_cols(int D) { return bf16_cols_(D); }
+
+int multi_shape(int D, int K) {
+  if (D < 1 || D > 64 || K < 1 || K > 64) return -1;
+  const int dq = D <= 32 ? 32 : 64, kq = K <= 16 ? 16 : K <= 32 ? 32 : 64;
+  return multi_shape_id(dq, kq, bf16_cols_(D) / 8);
+}
+
+int cp_bf16_multi_per_cu() {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cp_bf16_multi, kThreads, 0) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return per_cu;
+}
+
+hipError_t launch_cp_bf16_multi(const SliceStep* sl, const int* blk_slice, int n_blocks,
+                                hipStream_t s) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cp_bf16_multi, dim3(n_blocks), dim3(kThreads), 0, s, sl, blk_slice);
+  return hipGetLastError();
+}
 
 bool bf16_supported(int D, int K) { return D >= 1 && D <= 128 && K >= 1 && K <= 128; }
 

@@ -284,23 +284,22 @@ __global__ void __launch_bounds__(kThreads) k_cp_reduce_mfma(const float* __rest
 // caller-supplied count) or n_default when counts is NULL; n <= 0 gives a
 // zero gradient and leaves Phi unchanged.  Phi is only written, Phi0 only
 // read, so no block sees another block's update.
-constexpr int kFinEntries = 16;
+constexpr int kFinEntries = kFinishEntries;
 constexpr int kFinThreads = 1024;
 constexpr int kFinGroups = kFinThreads / kFinEntries;   // 64
 
-__global__ void __launch_bounds__(kFinThreads) k_cp_finish(
-    const float* __restrict__ partial, int nblk, const int* __restrict__ counts, int ncounts,
-    int n_default, const float* __restrict__ Phi0, int D, int K, double alpha0, double theta,
-    float beta, float* __restrict__ Phi, float* __restrict__ grad, double* __restrict__ R1,
-    int* __restrict__ n_out) {
-  extern __shared__ float ph[];                 // [D][K] copy of Phi0
+__device__ __forceinline__ void cp_finish_block(
+    int blk, const float* __restrict__ partial, int nblk, const int* __restrict__ counts,
+    int ncounts, int n_default, const float* __restrict__ Phi0, int D, int K, double alpha0,
+    double theta, float beta, float* __restrict__ Phi, float* __restrict__ grad,
+    double* __restrict__ R1, int* __restrict__ n_out, float* __restrict__ ph) {
   __shared__ double red[kFinGroups][kFinEntries + 1];
   __shared__ double pen_s[kFinEntries];
   __shared__ int nred[kFinThreads / 64];
   const int tid = threadIdx.x, el = tid & 15, grp = tid >> 4;
   const int lane = tid & 63, wave = tid >> 6;
   const int DK = D * K;
-  const int e = blockIdx.x * kFinEntries + el;
+  const int e = blk * kFinEntries + el;
   double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
   if (e < DK) {
     int b = grp;
@@ -320,7 +319,7 @@ __global__ void __launch_bounds__(kFinThreads) k_cp_finish(
   for (int i = tid; i < DK; i += kFinThreads) ph[i] = Phi0[i];
   red[grp][el] = (r0 + r1) + (r2 + r3);
   __syncthreads();
-  const int me = blockIdx.x * kFinEntries + wave;   // wave w: penalty of entry w
+  const int me = blk * kFinEntries + wave;   // wave w: penalty of entry w
   if (me < DK) {
     const int d = me / K, k = me % K;
     double pen = 0.0;
@@ -357,7 +356,27 @@ __global__ void __launch_bounds__(kFinThreads) k_cp_finish(
       Phi[e] = fmaf(-beta, g, ph[e]);
     }
   }
-  if (blockIdx.x == 0 && tid == 0 && n_out != nullptr) *n_out = n;
+  if (blk == 0 && tid == 0 && n_out != nullptr) *n_out = n;
+}
+
+__global__ void __launch_bounds__(kFinThreads) k_cp_finish(
+    const float* __restrict__ partial, int nblk, const int* __restrict__ counts, int ncounts,
+    int n_default, const float* __restrict__ Phi0, int D, int K, double alpha0, double theta,
+    float beta, float* __restrict__ Phi, float* __restrict__ grad, double* __restrict__ R1,
+    int* __restrict__ n_out) {
+  extern __shared__ float ph[];                 // [D][K] copy of Phi0
+  cp_finish_block(blockIdx.x, partial, nblk, counts, ncounts, n_default, Phi0, D, K, alpha0, theta,
+                  beta, Phi, grad, R1, n_out, ph);
+}
+
+// The finish of every slice of a multi-slice step in one launch: block b
+// serves slice fin_slice[b] as its finish block b - fin0.
+__global__ void __launch_bounds__(kFinThreads) k_cp_finish_multi(const SliceStep* __restrict__ sl,
+                                                                 const int* __restrict__ fin_slice) {
+  extern __shared__ float ph[];
+  const SliceStep& d = sl[fin_slice[blockIdx.x]];
+  cp_finish_block(blockIdx.x - d.fin0, d.partial, d.nblk, d.block_counts, d.nblk, 0, d.phi_copy,
+                  d.D, d.K, d.alpha0, d.theta, d.beta, d.Phi, d.grad, d.R1, d.n_kept_out, ph);
 }
 
 }  // namespace
@@ -455,6 +474,13 @@ hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D,
     launch_main(k_cp_reduce, dim3(nblk), dim3(kThreads), (unsigned)cp_lds_bytes(D, K, T), s, X,
                 n_rows, Phi, D, K, T, nblk, partial, phi_copy);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_cp_finish_multi(const SliceStep* sl, const int* fin_slice, int n_fin,
+                                  int max_dk, hipStream_t s) {
+  hipLaunchKernelGGL(k_cp_finish_multi, dim3(n_fin), dim3(kFinThreads), sizeof(float) * max_dk, s,
+                     sl, fin_slice);
   return hipGetLastError();
 }
 

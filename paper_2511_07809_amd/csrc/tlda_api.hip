@@ -886,6 +886,322 @@ tlda_status tlda_infer_doc_topics_mlp(tlda_ctx* c, tlda_mlp* m, const float* X, 
   return TLDA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched time slices: one launch per step over many slices
+// ---------------------------------------------------------------------------
+struct tlda_multi {
+  int n = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 0;
+  std::vector<tlda_ctx*> ctxs;
+  std::vector<tlda::SliceStep> host;   // table without the block layout
+  std::vector<int> tiles;
+  tlda::SliceStep* d_table = nullptr;
+  int* d_blk_slice = nullptr;
+  int* d_fin_slice = nullptr;
+  int n_blocks = 0, n_fin = 0, max_dk = 0, total_blocks = 0;
+  float* partial = nullptr;
+  int* counts = nullptr;
+  size_t cap_partial = 0, cap_counts = 0, cap_blk = 0, cap_fin = 0;
+  std::string last_error;
+};
+
+struct tlda_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;
+};
+
+namespace {
+
+void multi_free(tlda_multi* m) {
+  if (!m) return;
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  dfree(m->d_table); dfree(m->d_blk_slice); dfree(m->d_fin_slice); dfree(m->partial);
+  dfree(m->counts);
+  delete m;
+}
+
+// Lay out total_blocks reduction blocks over the slices in proportion to
+// their row tiles (at least one each, at most one per tile), and the finish
+// blocks; upload the tables (synchronous, never inside a capture).
+tlda_status multi_layout(tlda_multi* m, int total_blocks) {
+  long long all_tiles = 0;
+  for (int t : m->tiles) all_tiles += t;
+  if (total_blocks <= 0) total_blocks = tlda::cp_bf16_multi_per_cu() * m->num_cu;
+  std::vector<tlda::SliceStep> tab = m->host;
+  std::vector<int> blk_slice, fin_slice;
+  size_t need_p = 0, need_c = 0;
+  int max_dk = 1;
+  for (int i = 0; i < m->n; ++i) {
+    tlda::SliceStep& d = tab[i];
+    long long want = all_tiles > 0 ? (long long)((double)total_blocks * m->tiles[i] / all_tiles + 0.5) : 1;
+    int nb = (int)std::max<long long>(1, std::min<long long>(want, std::max(1, m->tiles[i])));
+    d.nblk = nb;
+    d.blk0 = (int)blk_slice.size();
+    for (int b = 0; b < nb; ++b) blk_slice.push_back(i);
+    d.fin0 = (int)fin_slice.size();
+    const int nf = (d.D * d.K + tlda::kFinishEntries - 1) / tlda::kFinishEntries;
+    for (int b = 0; b < nf; ++b) fin_slice.push_back(i);
+    need_p += (size_t)nb * d.D * d.K;
+    need_c += (size_t)nb;
+    max_dk = std::max(max_dk, d.D * d.K);
+  }
+  MLP_OK(m, hipStreamSynchronize(m->stream));
+  if (m->cap_partial < need_p) {
+    dfree(m->partial);
+    m->cap_partial = 0;
+    MLP_OK(m, dalloc(&m->partial, need_p));
+    m->cap_partial = need_p;
+  }
+  if (m->cap_counts < need_c) {
+    dfree(m->counts);
+    m->cap_counts = 0;
+    MLP_OK(m, dalloc(&m->counts, need_c));
+    m->cap_counts = need_c;
+  }
+  if (m->cap_blk < blk_slice.size()) {
+    dfree(m->d_blk_slice);
+    m->cap_blk = 0;
+    MLP_OK(m, dalloc(&m->d_blk_slice, blk_slice.size()));
+    m->cap_blk = blk_slice.size();
+  }
+  if (m->cap_fin < fin_slice.size()) {
+    dfree(m->d_fin_slice);
+    m->cap_fin = 0;
+    MLP_OK(m, dalloc(&m->d_fin_slice, fin_slice.size()));
+    m->cap_fin = fin_slice.size();
+  }
+  size_t op = 0, oc = 0;
+  for (auto& d : tab) {
+    d.partial = m->partial + op;
+    d.block_counts = m->counts + oc;
+    op += (size_t)d.nblk * d.D * d.K;
+    oc += (size_t)d.nblk;
+  }
+  MLP_OK(m, hipMemcpy(m->d_table, tab.data(), sizeof(tlda::SliceStep) * m->n,
+                      hipMemcpyHostToDevice));
+  MLP_OK(m, hipMemcpy(m->d_blk_slice, blk_slice.data(), sizeof(int) * blk_slice.size(),
+                      hipMemcpyHostToDevice));
+  MLP_OK(m, hipMemcpy(m->d_fin_slice, fin_slice.data(), sizeof(int) * fin_slice.size(),
+                      hipMemcpyHostToDevice));
+  m->n_blocks = (int)blk_slice.size();
+  m->n_fin = (int)fin_slice.size();
+  m->max_dk = max_dk;
+  m->total_blocks = total_blocks;
+  return TLDA_OK;
+}
+
+}  // namespace
+
+tlda_status tlda_multi_create(int32_t n_slices, tlda_ctx* const* ctxs,
+                              const tlda_csr_batch* batches, float* const* Phis,
+                              const float* betas, int32_t* n_kept_out, tlda_multi** out) {
+  if (out == nullptr) return TLDA_ERR_ARG;
+  *out = nullptr;
+  if (n_slices < 1 || !ctxs || !batches || !Phis || !betas) return TLDA_ERR_ARG;
+  for (int i = 0; i < n_slices; ++i) {
+    tlda_ctx* c = ctxs[i];
+    if (!c || !Phis[i] || !std::isfinite(betas[i])) return TLDA_ERR_ARG;
+    if (!is_bf16(c) || tlda::multi_shape(c->cfg.D, c->cfg.K) < 0) return TLDA_ERR_SHAPE;
+    if (!c->wh.ready) return TLDA_ERR_STATE;
+    if (c->stream != ctxs[0]->stream) return TLDA_ERR_ARG;
+    const tlda_csr_batch& b = batches[i];
+    if (b.slot >= 0 || b.n_rows < 0 || b.nnz < 0) return TLDA_ERR_ARG;
+    if (b.n_rows > 0 && !b.row_ptr) return TLDA_ERR_ARG;
+    if (b.nnz > 0 && (!b.col_idx || !b.val)) return TLDA_ERR_ARG;
+  }
+  tlda_multi* m = new (std::nothrow) tlda_multi();
+  if (!m) return TLDA_ERR_OOM;
+  m->n = n_slices;
+  m->stream = ctxs[0]->stream;
+  m->num_cu = ctxs[0]->num_cu;
+  m->ctxs.assign(ctxs, ctxs + n_slices);
+  for (int i = 0; i < n_slices; ++i) {
+    tlda_ctx* c = ctxs[i];
+    const tlda_csr_batch& b = batches[i];
+    if (c->cfg.flags & TLDA_VALIDATE_CSR) {
+      tlda_status st = validate_content(c, &b);
+      if (st != TLDA_OK) {
+        multi_free(m);
+        return st;
+      }
+    }
+    tlda::SliceStep d{};
+    d.row_ptr = b.row_ptr;
+    d.col_idx = b.col_idx;
+    d.val = b.val;
+    d.n_rows = b.n_rows;
+    d.W16 = c->wh.W16;
+    d.mw16 = c->wh.mw16;
+    d.Dh = c->Dh;
+    d.D = c->cfg.D;
+    d.K = c->cfg.K;
+    d.shape = tlda::multi_shape(d.D, d.K);
+    d.Phi = Phis[i];
+    d.phi_copy = c->cp.phi0;
+    d.grad = c->cp.grad;
+    d.R1 = c->cp.R1;
+    d.n_kept_out = n_kept_out ? n_kept_out + i : nullptr;
+    d.alpha0 = c->cfg.alpha0;
+    d.theta = c->cfg.theta;
+    d.beta = betas[i];
+    m->host.push_back(d);
+    m->tiles.push_back((b.n_rows + 63) / 64);
+  }
+  if (dalloc(&m->d_table, (size_t)n_slices) != hipSuccess) {
+    multi_free(m);
+    return TLDA_ERR_OOM;
+  }
+  tlda_status st = multi_layout(m, 0);
+  if (st != TLDA_OK) {
+    multi_free(m);
+    return st;
+  }
+  *out = m;
+  return TLDA_OK;
+}
+
+void tlda_multi_destroy(tlda_multi* plan) { multi_free(plan); }
+
+const char* tlda_multi_last_error(const tlda_multi* plan) {
+  return plan ? plan->last_error.c_str() : "";
+}
+
+tlda_status tlda_multi_set_blocks(tlda_multi* m, int32_t total_blocks) {
+  if (!m) return TLDA_ERR_ARG;
+  MLP_CHECK(m, total_blocks >= 0 && total_blocks <= (1 << 20), TLDA_ERR_ARG,
+            "total_blocks out of range");
+  return multi_layout(m, total_blocks);
+}
+
+tlda_status tlda_multi_get_blocks(const tlda_multi* m, int32_t* total_blocks) {
+  if (!m || !total_blocks) return TLDA_ERR_ARG;
+  *total_blocks = m->total_blocks;
+  return TLDA_OK;
+}
+
+tlda_status tlda_multi_step(tlda_multi* m) {
+  if (!m) return TLDA_ERR_ARG;
+  MLP_OK(m, tlda::launch_cp_bf16_multi(m->d_table, m->d_blk_slice, m->n_blocks, m->stream));
+  MLP_OK(m, tlda::launch_cp_finish_multi(m->d_table, m->d_fin_slice, m->n_fin, m->max_dk,
+                                         m->stream));
+  return TLDA_OK;
+}
+
+tlda_status tlda_multi_autotune(tlda_multi* m, int32_t reps, int32_t* total_blocks_out) {
+  if (!m) return TLDA_ERR_ARG;
+  MLP_CHECK(m, reps >= 1 && reps <= 1000, TLDA_ERR_ARG, "reps must be in 1 .. 1000");
+  // steps change Phi: keep each slice's Phi and restore it after every trial
+  std::vector<float*> saved(m->n, nullptr);
+  auto release = [&]() {
+    for (auto& p : saved) dfree(p);
+  };
+  for (int i = 0; i < m->n; ++i) {
+    const size_t dk = (size_t)m->host[i].D * m->host[i].K;
+    if (dalloc(&saved[i], dk) != hipSuccess ||
+        hipMemcpyAsync(saved[i], m->host[i].Phi, dk * sizeof(float), hipMemcpyDeviceToDevice,
+                       m->stream) != hipSuccess) {
+      release();
+      m->last_error = "could not keep a copy of Phi";
+      return TLDA_ERR_OOM;
+    }
+  }
+  auto restore = [&]() -> hipError_t {
+    for (int i = 0; i < m->n; ++i) {
+      const size_t dk = (size_t)m->host[i].D * m->host[i].K;
+      hipError_t e = hipMemcpyAsync(m->host[i].Phi, saved[i], dk * sizeof(float),
+                                    hipMemcpyDeviceToDevice, m->stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  const int per_cu = tlda::cp_bf16_multi_per_cu();
+  std::vector<int> cands;
+  for (int b = 1; b <= per_cu; ++b) cands.push_back(b * m->num_cu);
+  cands.push_back(2 * per_cu * m->num_cu);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  tlda_status st = TLDA_OK;
+  int best = cands.back();
+  float best_ms = 0.f;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    st = TLDA_ERR_DEVICE;
+  } else {
+    for (int cand : cands) {
+      st = multi_layout(m, cand);
+      if (st != TLDA_OK) break;
+      if ((st = tlda_multi_step(m)) != TLDA_OK) break;   // warm-up
+      hipEventRecord(e0, m->stream);
+      for (int r = 0; r < reps && st == TLDA_OK; ++r) st = tlda_multi_step(m);
+      hipEventRecord(e1, m->stream);
+      if (st != TLDA_OK || hipEventSynchronize(e1) != hipSuccess) {
+        if (st == TLDA_OK) st = TLDA_ERR_DEVICE;
+        break;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (best_ms == 0.f || ms < best_ms) {
+        best_ms = ms;
+        best = cand;
+      }
+      if (restore() != hipSuccess) {
+        st = TLDA_ERR_DEVICE;
+        break;
+      }
+    }
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (st == TLDA_OK) st = multi_layout(m, best);
+  if (restore() != hipSuccess || hipStreamSynchronize(m->stream) != hipSuccess)
+    st = st == TLDA_OK ? TLDA_ERR_DEVICE : st;
+  release();
+  if (st == TLDA_OK && total_blocks_out) *total_blocks_out = best;
+  return st;
+}
+
+tlda_status tlda_graph_capture(tlda_multi* const* plans, int32_t n_plans, tlda_graph** out) {
+  if (!out) return TLDA_ERR_ARG;
+  *out = nullptr;
+  if (n_plans < 1 || !plans) return TLDA_ERR_ARG;
+  for (int i = 0; i < n_plans; ++i)
+    if (!plans[i] || plans[i]->stream != plans[0]->stream) return TLDA_ERR_ARG;
+  hipStream_t s = plans[0]->stream;
+  if (s == nullptr) return TLDA_ERR_ARG;      // the null stream cannot be captured
+  if (hipStreamSynchronize(s) != hipSuccess) return TLDA_ERR_DEVICE;
+  tlda_graph* g = new (std::nothrow) tlda_graph();
+  if (!g) return TLDA_ERR_OOM;
+  g->stream = s;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    delete g;
+    return TLDA_ERR_DEVICE;
+  }
+  tlda_status st = TLDA_OK;
+  for (int i = 0; i < n_plans && st == TLDA_OK; ++i) st = tlda_multi_step(plans[i]);
+  hipError_t e = hipStreamEndCapture(s, &g->graph);
+  if (st != TLDA_OK || e != hipSuccess ||
+      hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+    if (g->graph) hipGraphDestroy(g->graph);
+    delete g;
+    return st != TLDA_OK ? st : TLDA_ERR_DEVICE;
+  }
+  *out = g;
+  return TLDA_OK;
+}
+
+tlda_status tlda_graph_launch(tlda_graph* g) {
+  if (!g) return TLDA_ERR_ARG;
+  return hipGraphLaunch(g->exec, g->stream) == hipSuccess ? TLDA_OK : TLDA_ERR_DEVICE;
+}
+
+void tlda_graph_destroy(tlda_graph* g) {
+  if (!g) return;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  delete g;
+}
+
 // Checkpoint layout: header (magic, version, V, K, D, flags), the counts,
 // token totals, sum f, S2 (when allocated), then W, U, eig and M1 (when ready).
 namespace {

@@ -155,6 +155,31 @@ struct tlda_mlp {
 
 namespace tlda {
 
+// One slice's share of a multi-slice step (device-side table entry): its
+// batch, BF16 whitening copy, shapes, Phi, scratch, and which blocks of the
+// reduction launch (blk0 .. blk0 + nblk - 1) and of the finish launch
+// (fin0 ..) serve it.
+struct SliceStep {
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const float* val;
+  int n_rows;
+  const uint16_t* W16;
+  const float* mw16;
+  int Dh, D, K, shape;
+  float* Phi;            // read by the reduction (copied to phi_copy), written by the finish
+  float* phi_copy;
+  float* partial;        // [nblk][D][K]
+  int* block_counts;     // [nblk]
+  int nblk, blk0, fin0;
+  float* grad;           // [D][K]
+  double* R1;            // [D][K]
+  int* n_kept_out;       // or null
+  double alpha0, theta;
+  float beta;
+};
+constexpr int multi_shape_id(int dq, int kq, int g) { return dq * 10000 + kq * 100 + g; }
+
 // Timing hook of the main kernel of a hot-path call: the API stores a pair
 // of events here right before launching it, and launch_main records them as
 // part of that kernel's dispatch (hipExtLaunchKernelGGL), so their interval
@@ -231,6 +256,15 @@ hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const flo
                             int* block_counts, float* Xout, float* phi_copy, hipStream_t s);
 int cp_num_blocks(int n_rows, int D, int K, int max_blocks);
 hipError_t launch_sum_counts(const int* block_counts, int n, int* out, hipStream_t s);
+// multi-slice step: reduction over every slice's batch, then every slice's finish
+// (sl: device table; blk_slice [n_blocks], fin_slice [n_fin]: slice of each block)
+hipError_t launch_cp_bf16_multi(const SliceStep* sl, const int* blk_slice, int n_blocks,
+                                hipStream_t s);
+hipError_t launch_cp_finish_multi(const SliceStep* sl, const int* fin_slice, int n_fin,
+                                  int max_dk, hipStream_t s);
+int multi_shape(int D, int K);            // shape id of the multi kernel for D, K <= 64, else -1
+int cp_bf16_multi_per_cu();               // resident blocks of the multi kernel per CU
+constexpr int kFinishEntries = 16;        // entries of D x K per finish block
 // BF16 path (D, K <= 128)
 int bf16_cols(int D);
 bool bf16_supported(int D, int K);

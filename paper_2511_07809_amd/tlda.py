@@ -38,7 +38,11 @@ EXPORTED = ("tlda_create", "tlda_destroy", "tlda_status_str", "tlda_last_error",
             "tlda_save_state", "tlda_load_state",
             "tlda_mlp_param_count", "tlda_mlp_create", "tlda_mlp_destroy", "tlda_mlp_last_error",
             "tlda_mlp_set_params", "tlda_mlp_get_params", "tlda_mlp_forward",
-            "tlda_mlp_gradients", "tlda_mlp_train_step", "tlda_infer_doc_topics_mlp")
+            "tlda_mlp_gradients", "tlda_mlp_train_step", "tlda_infer_doc_topics_mlp",
+            "tlda_multi_create", "tlda_multi_destroy", "tlda_multi_last_error",
+            "tlda_multi_set_blocks", "tlda_multi_get_blocks", "tlda_multi_step",
+            "tlda_multi_autotune", "tlda_graph_capture", "tlda_graph_launch",
+            "tlda_graph_destroy")
 
 
 class tlda_config(ctypes.Structure):
@@ -80,6 +84,18 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tlda_set_timing_events": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32], i32),
         "tlda_save_state": ([vp, vp, ctypes.POINTER(ctypes.c_size_t)], i32),
         "tlda_mlp_param_count": ([i32, i32, i32], ctypes.c_int64),
+        "tlda_multi_create": ([i32, ctypes.POINTER(vp), ctypes.POINTER(tlda_csr_batch),
+                               ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_float), vp,
+                               ctypes.POINTER(vp)], i32),
+        "tlda_multi_destroy": ([vp], None),
+        "tlda_multi_last_error": ([vp], ctypes.c_char_p),
+        "tlda_multi_set_blocks": ([vp, i32], i32),
+        "tlda_multi_get_blocks": ([vp, ctypes.POINTER(i32)], i32),
+        "tlda_multi_step": ([vp], i32),
+        "tlda_multi_autotune": ([vp, i32, ctypes.POINTER(i32)], i32),
+        "tlda_graph_capture": ([ctypes.POINTER(vp), i32, ctypes.POINTER(vp)], i32),
+        "tlda_graph_launch": ([vp], i32),
+        "tlda_graph_destroy": ([vp], None),
         "tlda_mlp_create": ([i32, i32, i32, i32, vp, ctypes.POINTER(vp)], i32),
         "tlda_mlp_destroy": ([vp], None),
         "tlda_mlp_last_error": ([vp], ctypes.c_char_p),
@@ -411,3 +427,87 @@ def tlda_infer_doc_topics_mlp(ctx: Context, m: Optional[Mlp], X: torch.Tensor, n
                                                min_steps, max_iter, _ptr(theta),
                                                _ptr(n_stepped)))
     return theta, n_stepped
+
+
+# ---------------------------------------------------------------------------
+# Batched time slices
+# ---------------------------------------------------------------------------
+class Multi:
+    """Owns a tlda_multi* (a step plan over several slices).  Keeps the
+    contexts, batches and Phi tensors it refers to alive."""
+
+    def __init__(self, handle: int, refs):
+        self.handle = handle
+        self._refs = refs
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _LIB.tlda_multi_destroy(self.handle)
+            self.handle = None
+
+
+class Graph:
+    def __init__(self, handle: int, refs):
+        self.handle = handle
+        self._refs = refs
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _LIB.tlda_graph_destroy(self.handle)
+            self.handle = None
+
+
+def _check_multi(p: Multi, status: int) -> None:
+    if status != TLDA_OK:
+        msg = _LIB.tlda_multi_last_error(p.handle) or b""
+        raise TldaError(status, msg.decode() or _LIB.tlda_status_str(status).decode())
+
+
+def tlda_multi_create(ctxs, batches, Phis, betas, n_kept: Optional[torch.Tensor] = None) -> Multi:
+    n = len(ctxs)
+    assert len(batches) == n and len(Phis) == n and len(betas) == n
+    c_ctx = (ctypes.c_void_p * n)(*[c.handle for c in ctxs])
+    c_b = (tlda_csr_batch * n)(*[b.struct() for b in batches])
+    c_p = (ctypes.c_void_p * n)(*[P.data_ptr() for P in Phis])
+    c_beta = (ctypes.c_float * n)(*[float(x) for x in betas])
+    h = ctypes.c_void_p()
+    st = _LIB.tlda_multi_create(n, c_ctx, c_b, c_p, c_beta, _ptr(n_kept), ctypes.byref(h))
+    if st != TLDA_OK:
+        raise TldaError(st, _LIB.tlda_status_str(st).decode())
+    return Multi(h.value, (list(ctxs), list(batches), list(Phis), n_kept))
+
+
+def tlda_multi_set_blocks(p: Multi, total_blocks: int) -> None:
+    _check_multi(p, _LIB.tlda_multi_set_blocks(p.handle, total_blocks))
+
+
+def tlda_multi_get_blocks(p: Multi) -> int:
+    v = ctypes.c_int32(0)
+    _check_multi(p, _LIB.tlda_multi_get_blocks(p.handle, ctypes.byref(v)))
+    return int(v.value)
+
+
+def tlda_multi_step(p: Multi) -> None:
+    _check_multi(p, _LIB.tlda_multi_step(p.handle))
+
+
+def tlda_multi_autotune(p: Multi, reps: int = 3) -> int:
+    v = ctypes.c_int32(0)
+    _check_multi(p, _LIB.tlda_multi_autotune(p.handle, reps, ctypes.byref(v)))
+    return int(v.value)
+
+
+def tlda_graph_capture(plans) -> Graph:
+    n = len(plans)
+    arr = (ctypes.c_void_p * n)(*[p.handle for p in plans])
+    h = ctypes.c_void_p()
+    st = _LIB.tlda_graph_capture(arr, n, ctypes.byref(h))
+    if st != TLDA_OK:
+        raise TldaError(st, _LIB.tlda_status_str(st).decode())
+    return Graph(h.value, list(plans))
+
+
+def tlda_graph_launch(g: Graph) -> None:
+    st = _LIB.tlda_graph_launch(g.handle)
+    if st != TLDA_OK:
+        raise TldaError(st, _LIB.tlda_status_str(st).decode())

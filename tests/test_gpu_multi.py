@@ -1,0 +1,189 @@
+"""Batched time slices through the C ABI: one multi-slice step (a persistent
+reduction launch over every slice plus one finish launch) against the
+single-slice fused step of each slice, the autotuner, and replays of a
+captured HIP graph against eager execution.
+
+The single-slice BF16 step is itself checked against the FP64 oracle
+(tests/test_gpu_bf16.py); here the multi-slice step must reproduce it up to
+the order of its FP32 partial sums (the two launches split a slice's rows
+over different numbers of blocks): 1e-5 relative.  Replays of a graph run
+the same kernels with the same launch shapes as eager steps and must match
+them bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+from synth import init_phi, make_csr_rows
+
+pytestmark = pytest.mark.gpu
+
+tl = pytest.importorskip("paper_2511_07809_amd.tlda")
+
+V = 300
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _rows(n, seed):
+    rng = np.random.default_rng(seed)
+    rows = [{}, {3: 1, 9: 1}] if n >= 2 else []
+    for _ in range(max(n - len(rows), 0)):
+        words = rng.choice(V, size=rng.integers(1, 40), replace=False)
+        rows.append({int(w): int(rng.integers(1, 4)) for w in words})
+    return make_csr_rows(rows[:n], V)
+
+
+def _slice(D, K, n_rows, seed, stream):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((V, D)))
+    W = Q * rng.uniform(5, 30, size=D)[None, :]
+    m = rng.dirichlet(np.ones(V))
+    ctx = tl.tlda_create(V, K, D, 1.0 + 0.5 * (seed % 3), 0.25 * (seed % 2), bf16=True,
+                         stream=stream)
+    tl.tlda_set_whitening(ctx, W, m)
+    rp, ci, va = _rows(n_rows, seed + 100)
+    return ctx, tl.CsrBatch.from_numpy(rp, ci, va), (init_phi(D, K, seed) * 0.9).astype(np.float32)
+
+
+SLICES = [(10, 10, 3000), (20, 20, 1500), (50, 50, 4100), (7, 7, 1), (64, 64, 700),
+          (20, 10, 2300), (33, 40, 0), (50, 50, 130)]
+
+
+@pytest.fixture()
+def side_stream():
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    return s
+
+
+def _build(stream, slices=SLICES, seed0=1):
+    ctxs, batches, phis0 = [], [], []
+    for i, (D, K, n) in enumerate(slices):
+        c, b, p = _slice(D, K, n, seed0 + i, stream)
+        ctxs.append(c)
+        batches.append(b)
+        phis0.append(p)
+    torch.cuda.synchronize()
+    return ctxs, batches, phis0
+
+
+def test_multi_step_matches_single_slice_steps(side_stream):
+    ctxs, batches, phis0 = _build(side_stream)
+    betas = [1e-3 * (1 + i) for i in range(len(ctxs))]
+    Ps = [torch.from_numpy(p).cuda() for p in phis0]
+    nk = torch.zeros(len(ctxs), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    plan = tl.tlda_multi_create(ctxs, batches, Ps, betas, nk)
+    for _ in range(3):
+        tl.tlda_multi_step(plan)
+    side_stream.synchronize()
+    for i, (c, b, p0) in enumerate(zip(ctxs, batches, phis0)):
+        P = torch.from_numpy(p0).cuda()
+        n1 = torch.zeros(1, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        for _ in range(3):
+            tl.tlda_whiten_cp_step(c, b, betas[i], P, None, None, n1)
+        side_stream.synchronize()
+        if b.n_rows == 0:
+            assert torch.equal(Ps[i].cpu(), torch.from_numpy(p0))
+            assert int(nk[i].item()) == 0
+        else:
+            assert rel(Ps[i].cpu().numpy(), P.cpu().numpy()) < 1e-5, SLICES[i]
+            assert int(nk[i].item()) == int(n1.item())
+
+
+def test_autotune_restores_phi_and_chooses_a_valid_shape(side_stream):
+    ctxs, batches, phis0 = _build(side_stream, seed0=11)
+    Ps = [torch.from_numpy(p).cuda() for p in phis0]
+    torch.cuda.synchronize()
+    plan = tl.tlda_multi_create(ctxs, batches, Ps, [2e-3] * len(ctxs))
+    default = tl.tlda_multi_get_blocks(plan)
+    best = tl.tlda_multi_autotune(plan, 2)
+    assert best > 0 and tl.tlda_multi_get_blocks(plan) == best
+    for P, p0 in zip(Ps, phis0):
+        assert torch.equal(P.cpu(), torch.from_numpy(p0))
+    # every launch shape gives the same step up to the partial-sum order
+    outs = []
+    for blocks in (default, best, 37):
+        for P, p0 in zip(Ps, phis0):
+            P.copy_(torch.from_numpy(p0).cuda())
+        torch.cuda.synchronize()
+        tl.tlda_multi_set_blocks(plan, blocks)
+        tl.tlda_multi_step(plan)
+        side_stream.synchronize()
+        outs.append([P.cpu().numpy().copy() for P in Ps])
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert rel(a, b) < 1e-5
+
+
+def test_graph_replays_match_eager_steps(side_stream):
+    slices_a = SLICES[:5]
+    ctxs, batches, phis0 = _build(side_stream, slices_a, seed0=21)
+    # two batch indices: a second set of batches for the same slices
+    batches2 = [_rows(n // 2 + 1, 500 + i) for i, (_, _, n) in enumerate(slices_a)]
+    batches2 = [tl.CsrBatch.from_numpy(*r) for r in batches2]
+    betas = [1e-3] * len(ctxs)
+
+    def fresh():
+        return [torch.from_numpy(p).cuda() for p in phis0]
+
+    # eager
+    Pe = fresh()
+    torch.cuda.synchronize()
+    p1 = tl.tlda_multi_create(ctxs, batches, Pe, betas)
+    p2 = tl.tlda_multi_create(ctxs, batches2, Pe, betas)
+    eager = []
+    for _ in range(3):
+        tl.tlda_multi_step(p1)
+        tl.tlda_multi_step(p2)
+        side_stream.synchronize()
+        eager.append([P.cpu().numpy().copy() for P in Pe])
+    # graph of one pass (both batch indices), replayed three times with
+    # unrelated eager work and synchronisations in between
+    Pg = fresh()
+    torch.cuda.synchronize()
+    g1 = tl.tlda_multi_create(ctxs, batches, Pg, betas)
+    g2 = tl.tlda_multi_create(ctxs, batches2, Pg, betas)
+    graph = tl.tlda_graph_capture([g1, g2])
+    for r in range(3):
+        tl.tlda_graph_launch(graph)
+        side_stream.synchronize()
+        junk = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for a, b in zip([P.cpu().numpy() for P in Pg], eager[r]):
+            assert np.array_equal(a, b)
+
+
+def test_multi_rejects_bad_plans(side_stream):
+    ctxs, batches, phis0 = _build(side_stream, SLICES[:2], seed0=31)
+    Ps = [torch.from_numpy(p).cuda() for p in phis0]
+    torch.cuda.synchronize()
+    fp32 = tl.tlda_create(V, 10, 10, 1.0, stream=side_stream)
+    with pytest.raises(tl.TldaError) as e:
+        tl.tlda_multi_create([ctxs[0], fp32], batches, Ps, [1e-3, 1e-3])
+    assert e.value.status == 2
+    big = tl.tlda_create(V, 100, 100, 1.0, bf16=True, stream=side_stream)
+    with pytest.raises(tl.TldaError) as e:
+        tl.tlda_multi_create([ctxs[0], big], batches, Ps, [1e-3, 1e-3])
+    assert e.value.status == 2
+    nowhite = tl.tlda_create(V, 20, 20, 1.0, bf16=True, stream=side_stream)
+    with pytest.raises(tl.TldaError) as e:
+        tl.tlda_multi_create([ctxs[0], nowhite], batches, Ps, [1e-3, 1e-3])
+    assert e.value.status == 4
+    # contexts on the null stream cannot be captured
+    c0 = tl.tlda_create(V, 10, 10, 1.0, bf16=True, stream=torch.cuda.default_stream())
+    rng = np.random.default_rng(0)
+    tl.tlda_set_whitening(c0, np.linalg.qr(rng.standard_normal((V, 10)))[0] * 10,
+                          rng.dirichlet(np.ones(V)))
+    P0 = torch.from_numpy(init_phi(10, 10, 1).astype(np.float32)).cuda()
+    plan = tl.tlda_multi_create([c0], [batches[0]], [P0], [1e-3])
+    with pytest.raises(tl.TldaError) as e:
+        tl.tlda_graph_capture([plan])
+    assert e.value.status == 1
