@@ -112,6 +112,7 @@ const char* tlda_last_error(const tlda_ctx* ctx);
 /* tlda_update_moments flags */
 #define TLDA_REFRESH_W 0x1u   /* after accumulating, recompute M1, M2~ and W       */
 #define TLDA_RESET 0x2u       /* clear the accumulators before accumulating        */
+#define TLDA_RELEASE 0x4u     /* last: free the V x V accumulator, clear the counts */
 
 /* Section "Computing the Centered Cumulants" and the batched implementation:
  * accumulates, over the kept documents of `batch` (may be NULL when only
@@ -125,6 +126,10 @@ const char* tlda_last_error(const tlda_ctx* ctx);
  * eigenvalue and signed so that their largest-magnitude entry is positive.
  * A refresh synchronises the stream; it returns TLDA_ERR_NUMERIC if N == 0 or
  * the D-th eigenvalue is not positive (the previous W is then kept).
+ * TLDA_RELEASE (last, synchronous) frees the V x V accumulator and clears N,
+ * the totals and sum f, keeping W: for contexts that only step after their
+ * refresh (e.g. many time slices, whose accumulators could not all stay
+ * resident).  A later update allocates the accumulator again.
  * Accumulation uses FP64 atomics: sums are exact up to FP64 rounding order. */
 tlda_status tlda_update_moments(tlda_ctx* ctx, const tlda_csr_batch* batch, uint32_t flags);
 

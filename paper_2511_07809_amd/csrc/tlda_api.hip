@@ -393,8 +393,10 @@ void tlda_destroy(tlda_ctx* ctx) { destroy_all(ctx); }
 
 tlda_status tlda_update_moments(tlda_ctx* c, const tlda_csr_batch* b, uint32_t flags) {
   if (!c) return TLDA_ERR_ARG;
-  CHECK_ARG(c, (flags & ~(TLDA_REFRESH_W | TLDA_RESET)) == 0, TLDA_ERR_ARG, "unknown flags");
-  CHECK_ARG(c, b != nullptr || (flags & (TLDA_REFRESH_W | TLDA_RESET)), TLDA_ERR_ARG,
+  CHECK_ARG(c, (flags & ~(TLDA_REFRESH_W | TLDA_RESET | TLDA_RELEASE)) == 0, TLDA_ERR_ARG,
+            "unknown flags");
+  CHECK_ARG(c, b != nullptr || (flags & (TLDA_REFRESH_W | TLDA_RESET | TLDA_RELEASE)),
+            TLDA_ERR_ARG,
             "batch is NULL and no refresh or reset was requested");
   if (b) {
     tlda_status st = check_batch(c, b);
@@ -402,8 +404,11 @@ tlda_status tlda_update_moments(tlda_ctx* c, const tlda_csr_batch* b, uint32_t f
     st = validate_content(c, b);
     if (st != TLDA_OK) return st;
   }
-  tlda_status st = ensure_s2(c);
-  if (st != TLDA_OK) return st;
+  tlda_status st = TLDA_OK;
+  if (b || (flags & (TLDA_REFRESH_W | TLDA_RESET))) {
+    st = ensure_s2(c);
+    if (st != TLDA_OK) return st;
+  }
   const size_t V = c->cfg.V;
   if (flags & TLDA_RESET) {
     HIP_OK(c, launch_zero(c->mom.counts, 2 * sizeof(unsigned long long), c->stream));
@@ -418,7 +423,18 @@ tlda_status tlda_update_moments(tlda_ctx* c, const tlda_csr_batch* b, uint32_t f
     st = end_use(c, b);
     if (st != TLDA_OK) return st;
   }
-  if (flags & TLDA_REFRESH_W) return refresh(c);
+  if (flags & TLDA_REFRESH_W) {
+    st = refresh(c);
+    if (st != TLDA_OK) return st;
+  }
+  if (flags & TLDA_RELEASE) {
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    dfree(c->mom.S2);
+    HIP_OK(c, launch_zero(c->mom.counts, 2 * sizeof(unsigned long long), c->stream));
+    HIP_OK(c, launch_zero(c->mom.totals, V * sizeof(unsigned long long), c->stream));
+    HIP_OK(c, launch_zero(c->mom.fsum, V * sizeof(double), c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+  }
   return TLDA_OK;
 }
 

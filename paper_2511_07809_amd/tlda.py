@@ -24,6 +24,7 @@ TLDA_VALIDATE_CSR = 0x1
 TLDA_BF16 = 0x2
 TLDA_REFRESH_W = 0x1
 TLDA_RESET = 0x2
+TLDA_RELEASE = 0x4
 TLDA_PROJECT_SIMPLEX = 0x1
 TLDA_MAX_D = 256
 TLDA_MAX_K = 256

@@ -7,7 +7,7 @@ of the method's arithmetic (no moments, whitening, gradients or recovery), so
 both the FP64 oracle and the HIP path can be fed from it without sharing code.
 """
 from .lda_corpus import (Corpus, CorpusSpec, SPECS, generate, iter_batches,
-                         init_phi, make_csr_rows)
+                         init_phi, make_csr_rows, slice_specs)
 
 __all__ = ["Corpus", "CorpusSpec", "SPECS", "generate", "iter_batches",
-           "init_phi", "make_csr_rows"]
+           "init_phi", "make_csr_rows", "slice_specs"]

@@ -61,6 +61,22 @@ SPECS = {
 }
 
 
+def slice_specs(n_slices: int = 64, seed: int = 1004, median: float = 150_000.0,
+                sigma: float = 1.0, lo: int = 10_000, hi: int = 2_000_000,
+                scale: float = 1.0) -> list:
+    """The batched-time-slice workload: independent corpora sharing V = 20 000,
+    sizes clip(round(exp(N(ln median, sigma))), lo, hi) (times `scale`, for
+    smaller runs), K drawn uniformly from {10, 20, 50}, tweet-shaped documents
+    and topics as in c2, each slice with its own seed and planted topics."""
+    rng = np.random.default_rng(seed)
+    sizes = np.clip(np.round(np.exp(rng.normal(np.log(median), sigma, n_slices))), lo, hi)
+    ks = rng.choice([10, 20, 50], size=n_slices)
+    return [CorpusSpec(f"c4.{i}", V=20000, K=int(ks[i]), N=max(1, int(sizes[i] * scale)),
+                       doc_len_lambda=20.0, alpha0=1.0, topic_conc=0.01, zipf_s=1.1,
+                       zipf_mix=0.3, batch=131072, seed=seed * 1000 + i)
+            for i in range(n_slices)]
+
+
 @dataclasses.dataclass
 class Corpus:
     spec: CorpusSpec

@@ -187,3 +187,25 @@ def test_multi_rejects_bad_plans(side_stream):
     with pytest.raises(tl.TldaError) as e:
         tl.tlda_graph_capture([plan])
     assert e.value.status == 1
+
+
+def test_release_frees_the_accumulator_and_keeps_the_whitening(side_stream):
+    rp, ci, va = _rows(2000, 77)
+    b = tl.CsrBatch.from_numpy(rp, ci, va)
+    ctx = tl.tlda_create(V, 12, 12, 1.0, bf16=True, stream=side_stream)
+    torch.cuda.synchronize()
+    tl.tlda_update_moments(ctx, b)
+    tl.tlda_update_moments(ctx, None, tl.TLDA_REFRESH_W | tl.TLDA_RELEASE)
+    W, eig, m = tl.tlda_get_whitening(ctx)
+    N, skipped, totals = tl.tlda_get_stats(ctx)
+    assert N == 0 and skipped == 0 and not totals.any()
+    X1, _ = tl.tlda_whiten_batch(ctx, b)
+    side_stream.synchronize()
+    # a fresh accumulation after the release gives the same whitening
+    tl.tlda_update_moments(ctx, b)
+    tl.tlda_update_moments(ctx, None, tl.TLDA_REFRESH_W)
+    W2, _, _ = tl.tlda_get_whitening(ctx)
+    assert rel(W2, W) < 1e-9
+    X2, _ = tl.tlda_whiten_batch(ctx, b)
+    side_stream.synchronize()
+    assert rel(X1.cpu().numpy(), X2.cpu().numpy()) < 1e-6
