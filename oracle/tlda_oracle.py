@@ -37,6 +37,13 @@ Readings
   R9  Appendix cumulants: per-document pair and triple sums are normalised by
       L(L-1) and L(L-1)(L-2) (ordered distinct tokens), and the alpha0 term of
       M3 multiplies the pair moment by M1 (the form the theorem's proof uses).
+  R14 Classic rung: the SGD of the batched section run on the appendix's
+      alpha0-corrected moments (R9) instead of the centred ones.  W whitens
+      M2 = (alpha0+1) mean P2 - alpha0 M1 M1^T; the data term of the gradient
+      is the per-document piece of M3 contracted implicitly with (W, phi, phi);
+      recovery is the orthogonal one of the post-processing section:
+      lambda_i = (1+theta)|phi_i|^3, mu_i = lambda_i (W^T)^+ phi_i/|phi_i|,
+      alpha_i proportional to lambda_i^-2.
 """
 from __future__ import annotations
 
@@ -51,7 +58,8 @@ __all__ = [
     "whiten", "cp_gradient", "cp_gradient_explicit", "cp_loss", "cp_step",
     "unwhiten", "simplex_project", "infer_doc_topics", "match_topics",
     "uncentered_cumulants", "whitened_tensor", "tensor_power_method",
-    "classic_recover", "fit_batched",
+    "classic_recover", "fit_batched", "classic_second_moment", "classic_data_term",
+    "classic_cp_gradient", "classic_unwhiten", "fit_batched_classic",
 ]
 
 
@@ -408,6 +416,102 @@ def classic_recover(M2: np.ndarray, M3: np.ndarray, K: int, seed: int = 0):
     mu = (U * np.sqrt(lam2)[None, :]) @ v * lam[None, :]
     a = lam ** -2.0
     return {"mu": mu, "alpha": a / a.sum(), "lambda": lam}
+
+
+# --------------------------------------------------------------------------
+# Estimator rung with the classic alpha0-corrected moments (appendix, R9), run
+# through the same batched SGD: the whitened third moment is contracted
+# implicitly, per document, from the unbiased pair and triple pieces.
+# --------------------------------------------------------------------------
+def classic_second_moment(batches, m: np.ndarray, N: int, alpha0: float) -> np.ndarray:
+    """M2 = (alpha0 + 1) mean_d P2_d - alpha0 M1 M1^T with the unbiased pair
+    piece P2_d = (c c^T - diag c) / (L (L - 1)), summed over kept documents."""
+    V = m.shape[0]
+    P2 = np.zeros((V, V))
+    for rp, ci, va in batches:
+        st = batch_stats(rp, ci, va, V)
+        for d in np.nonzero(st["keep"])[0]:
+            a, b = int(rp[d]), int(rp[d + 1])
+            c = np.zeros(V)
+            np.add.at(c, ci[a:b], va[a:b].astype(np.float64))
+            L = float(st["L"][d])
+            P2 += (np.outer(c, c) - np.diag(c)) / (L * (L - 1.0))
+    return (alpha0 + 1.0) * P2 / N - alpha0 * np.outer(m, m)
+
+
+def classic_data_term(row_ptr, col_idx, val, V: int, m: np.ndarray, W: np.ndarray,
+                      Phi: np.ndarray, alpha0: float) -> tuple:
+    """Sum over the batch's kept documents of M3_d(W, W, W)(I, phi_k, phi_k),
+    column k, with M3_d = c3 P3_d - c2 (P2_d x M1 + its two permutations) +
+    alpha0^2 M1^3 the per-document piece of the appendix's M3 (c2 =
+    alpha0 (alpha0 + 1) / 2).  Written out per document with y = W^T c,
+    z = W Phi, s = y.phi, g = W^T (c z), q = c.z^2, h = W^T (c z^2),
+    r = (W^T M1).phi, l2 = 1/(L(L-1)), l3 = 1/(L(L-1)(L-2)):
+      c3 l3 (y s^2 - 2 s g - y q + 2 h) - c2 l2 (2 r (y s - g) + m_w (s^2 - q))
+      + alpha0^2 m_w r^2.
+    Returns (D x K sum, number of kept documents)."""
+    st = batch_stats(row_ptr, col_idx, val, V)
+    c3 = _c3(alpha0)
+    c2 = alpha0 * (alpha0 + 1.0) / 2.0
+    Z = W @ Phi
+    mw = W.T @ m
+    r = mw @ Phi
+    out = np.zeros(Phi.shape)
+    for d in np.nonzero(st["keep"])[0]:
+        a, b = int(row_ptr[d]), int(row_ptr[d + 1])
+        cols = col_idx[a:b].astype(np.int64)
+        cnt = val[a:b].astype(np.float64)
+        L = float(st["L"][d])
+        l2 = 1.0 / (L * (L - 1.0))
+        l3 = l2 / (L - 2.0)
+        Wd, Zd = W[cols], Z[cols]                 # rows of the document's words
+        y = Wd.T @ cnt
+        s = y @ Phi
+        g = Wd.T @ (cnt[:, None] * Zd)
+        q = cnt @ (Zd * Zd)
+        h = Wd.T @ (cnt[:, None] * Zd * Zd)
+        out += c3 * l3 * (np.outer(y, s * s) - 2.0 * s[None, :] * g - np.outer(y, q) + 2.0 * h)
+        out -= c2 * l2 * (2.0 * r[None, :] * (np.outer(y, s) - g) + np.outer(mw, s * s - q))
+        out += alpha0 ** 2 * np.outer(mw, r * r)
+    return out, int(st["n_kept"])
+
+
+def classic_cp_gradient(row_ptr, col_idx, val, V, m, W, Phi, alpha0, theta):
+    """3(1+theta) Phi (Phi^T Phi * Phi^T Phi) - (3/n) sum_d M3_d(W,W,W)(I, phi, phi)."""
+    data, n = classic_data_term(row_ptr, col_idx, val, V, m, W, Phi, alpha0)
+    G = Phi.T @ Phi
+    return 3.0 * (1.0 + theta) * Phi @ (G * G) - 3.0 / max(n, 1) * data
+
+
+def classic_unwhiten(Phi: np.ndarray, U: np.ndarray, lam: np.ndarray, theta: float) -> dict:
+    """Classic recovery (R14, the relation of the post-processing section in
+    the orthonormal case): lambda_i = (1+theta)
+    |phi_i|^3, mu_i = lambda_i (W^T)^+ phi_i / |phi_i| = lambda_i U diag(l)^1/2
+    phi_i / |phi_i|, alpha_i proportional to lambda_i^-2; mu clipped and
+    renormalised onto the simplex."""
+    nrm = np.linalg.norm(Phi, axis=0)
+    lamb = (1.0 + theta) * nrm ** 3
+    mu = (U * np.sqrt(lam)[None, :]) @ (Phi / nrm[None, :]) * lamb[None, :]
+    a = lamb ** -2.0
+    mu_s = np.maximum(mu, 0.0)
+    mu_s = mu_s / mu_s.sum(axis=0, keepdims=True)
+    return {"mu": mu, "mu_simplex": mu_s, "alpha": a / a.sum(), "lambda": lamb}
+
+
+def fit_batched_classic(batches: list, V: int, K: int, D: int, alpha0: float, theta: float,
+                        beta: float, passes: int, Phi0: np.ndarray) -> dict:
+    m, N = first_moment(batches, V)
+    M2 = classic_second_moment(batches, m, N, alpha0)
+    W, lam, U = whitening(M2, D)
+    Phi = Phi0.copy()
+    for _ in range(passes):
+        for rp, ci, va in batches:
+            G = classic_cp_gradient(rp, ci, va, V, m, W, Phi, alpha0, theta)
+            if batch_stats(rp, ci, va, V)["n_kept"] > 0:
+                Phi = Phi - beta * G
+    out = classic_unwhiten(Phi, U, lam, theta)
+    out.update({"Phi": Phi, "W": W, "eig": lam, "U": U, "m": m, "N": N, "M2": M2})
+    return out
 
 
 # --------------------------------------------------------------------------

@@ -352,3 +352,90 @@ def test_batched_fit_config1_runs_and_reports_recovery():
     base = np.mean(np.abs(c.mu - out["m"][:, None]).sum(axis=0))
     np.testing.assert_allclose(out["mu_simplex"].sum(axis=0), 1.0, atol=1e-12)
     assert err < base
+
+
+# ----------------------------------------------------------------------------
+# the classic alpha0-corrected rung
+# ----------------------------------------------------------------------------
+def test_classic_second_moment_matches_the_explicit_cumulants_over_batches():
+    c, spec = _small_lda(N=900, seed=31)
+    batches = [(rp, ci, va) for rp, ci, va, _ in iter_batches(c, 250)]
+    m, N = O.first_moment(batches, spec.V)
+    M1, M2, _ = O.uncentered_cumulants(c.indptr, c.indices, c.data, spec.V, spec.alpha0)
+    np.testing.assert_allclose(m, M1, atol=1e-15)
+    np.testing.assert_allclose(O.classic_second_moment(batches, m, N, spec.alpha0), M2,
+                               atol=1e-15)
+
+
+def test_classic_data_term_equals_the_explicit_whitened_contraction():
+    """The implicit per-document form (y s^2, g, q, h terms) against the
+    explicit M3 tensor contracted with (W, phi_k, phi_k)."""
+    c, spec = _small_lda(N=300, seed=32)
+    rng = np.random.default_rng(3)
+    D, K = 4, 3
+    W = rng.standard_normal((spec.V, D))
+    Phi = rng.standard_normal((D, K))
+    M1, _, M3 = O.uncentered_cumulants(c.indptr, c.indices, c.data, spec.V, spec.alpha0)
+    data, n = O.classic_data_term(c.indptr, c.indices, c.data, spec.V, M1, W, Phi, spec.alpha0)
+    T = np.einsum("abc,ai,bj,ck->ijk", M3, W, W, W)
+    expl = n * np.stack([np.einsum("ijk,j,k->i", T, Phi[:, k], Phi[:, k]) for k in range(K)],
+                        axis=1)
+    np.testing.assert_allclose(data, expl, rtol=1e-11, atol=1e-11 * np.abs(expl).max())
+
+
+def test_classic_gradient_is_the_derivative_of_its_objective():
+    c, spec = _small_lda(N=200, seed=33)
+    rng = np.random.default_rng(4)
+    D, K, theta = 3, 3, 0.5
+    W = rng.standard_normal((spec.V, D)) * 2
+    Phi = rng.standard_normal((D, K))
+    M1, _, M3 = O.uncentered_cumulants(c.indptr, c.indices, c.data, spec.V, spec.alpha0)
+    T = np.einsum("abc,ai,bj,ck->ijk", M3, W, W, W)
+
+    def loss(P):
+        G = P.T @ P
+        return (1 + theta) / 2 * (G ** 3).sum() - np.einsum("ijk,il,jl,kl->", T, P, P, P)
+
+    g = O.classic_cp_gradient(c.indptr, c.indices, c.data, spec.V, M1, W, Phi, spec.alpha0, theta)
+    h = 1e-6
+    fd = np.zeros_like(Phi)
+    for idx in np.ndindex(Phi.shape):
+        e = np.zeros_like(Phi)
+        e[idx] = h
+        fd[idx] = (loss(Phi + e) - loss(Phi - e)) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-8)
+
+
+@pytest.mark.parametrize("theta", [0.0, 1.0])
+def test_classic_unwhiten_recovers_population_topics(theta):
+    """Population moments M2 = sum a mu mu^T, M3 = sum a mu^3: the whitened
+    factors sqrt(a_i) W^T mu_i are orthonormal, T = sum a_i^(-1/2) v_i^3, the
+    CP fixed point is ((a_i^(-1/2)) / (1 + theta))^(1/3) v_i, and the classic
+    recovery returns mu and a exactly."""
+    rng = np.random.default_rng(5)
+    V, K = 30, 4
+    mu = rng.dirichlet(np.full(V, 0.3), size=K).T
+    a = rng.dirichlet(np.ones(K) * 2)
+    M2 = (mu * a) @ mu.T
+    W, lam, U = O.whitening(M2, K)
+    v = np.sqrt(a)[None, :] * (W.T @ mu)
+    np.testing.assert_allclose(v.T @ v, np.eye(K), atol=1e-10)
+    Phi = v * np.cbrt(a ** -0.5 / (1 + theta))[None, :]
+    out = O.classic_unwhiten(Phi, U, lam, theta)
+    np.testing.assert_allclose(out["mu"], mu, atol=1e-10)
+    np.testing.assert_allclose(out["alpha"], a, atol=1e-10)
+
+
+def test_classic_fit_from_the_planted_start_stays_near_the_truth():
+    """On the 500-word workload the classic rung keeps a start at the planted
+    factors within 0.1 mean L1 of the planted topics (it is the estimator, not
+    the start, that is checked here)."""
+    spec = SPECS["c1"]
+    c = generate(spec)
+    batches = [(rp, ci, va) for rp, ci, va, _ in iter_batches(c)]
+    m, N = O.first_moment(batches, spec.V)
+    W, lam, U = O.whitening(O.classic_second_moment(batches, m, N, spec.alpha0), spec.K)
+    a = c.alpha / c.alpha.sum()
+    Phi0 = (np.sqrt(a)[None, :] * (W.T @ c.mu)) * np.cbrt(a ** -0.5)[None, :]
+    fit = O.fit_batched_classic(batches, spec.V, spec.K, spec.K, spec.alpha0, 0.0, 0.03, 5, Phi0)
+    assert O.match_topics(fit["mu_simplex"], c.mu)["mean_l1"] < 0.1
