@@ -72,12 +72,33 @@ typedef enum {
  * the update, unwhitening and inference stay FP64/FP32.  tlda_whiten_batch,
  * tlda_cp_step and tlda_whiten_cp_step switch; their interfaces do not. */
 #define TLDA_BF16 0x2u
+/* Classic moments (the appendix's alpha0-corrected cumulants, used as an
+ * estimator rung of the same batched SGD; FP32, requires D, K <= 128, else
+ * TLDA_ERR_SHAPE; not combinable with TLDA_BF16, TLDA_ERR_ARG).
+ *  - tlda_update_moments accumulates the unbiased pair piece
+ *    P2 = (c c^T - diag c) / (L (L - 1)) per kept document in place of f f^T,
+ *    and a refresh whitens M2 = (alpha0 + 1) sum P2 / N - alpha0 M1 M1^T.
+ *  - tlda_whiten_cp_step takes the data term of the gradient from the
+ *    per-document piece of the appendix's third moment,
+ *    M3_d = c3 P3_d - c2 (P2_d x M1 + its two permutations) + alpha0^2 M1^3
+ *    (P3_d: ordered distinct token triples over L (L - 1) (L - 2);
+ *    c2 = alpha0 (alpha0 + 1) / 2, c3 = (alpha0 + 1)(alpha0 + 2) / 2),
+ *    contracted with (W, phi_k, phi_k) per document without forming it:
+ *      G = 3(1+theta) Phi (Phi^T Phi * Phi^T Phi)
+ *          - (3 / n) sum_d M3_d(W, W, W)(I, phi_k, phi_k).
+ *    tlda_cp_step (which sees only X) returns TLDA_ERR_STATE.
+ *  - tlda_unwhiten returns the orthogonal recovery: lambda_i =
+ *    (1+theta)|phi_i|^3, mu_i = lambda_i (W^T)^+ phi_i / |phi_i|, alpha_i
+ *    proportional to lambda_i^-2 (a zero column gets mu 0 and weight 0).
+ *  - tlda_whiten_batch and inference keep their definitions (X = W^T (f - M1)
+ *    with this W). */
+#define TLDA_CLASSIC 0x4u
 
 typedef struct {
   int32_t V;            /* vocabulary size, 3 <= V <= 131072                       */
   int32_t K;            /* number of topics, 1 <= K <= TLDA_MAX_K                   */
   int32_t D;            /* whitening size, 1 <= D <= min(V, TLDA_MAX_D), D*K bound  */
-  int32_t flags;        /* TLDA_VALIDATE_CSR | TLDA_BF16                           */
+  int32_t flags;        /* TLDA_VALIDATE_CSR | TLDA_BF16 | TLDA_CLASSIC            */
   double alpha0;        /* topic mixing parameter, > 0                             */
   double theta;         /* orthogonality penalty of eq. full_vec_pb, >= 0          */
   int32_t eig_iters;    /* subspace iterations of a refresh, 0 = default (60)      */

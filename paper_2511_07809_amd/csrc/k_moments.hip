@@ -51,8 +51,12 @@ __global__ void __launch_bounds__(256) k_validate_csr(const int32_t* __restrict_
 // nnz positions; as columns are strictly increasing, col_j <= col_k and the
 // pair lands in the upper triangle of S2.  Kept/dropped document counts are
 // kept per block and added by k_add_counts, so no address is hit by every row.
+// CLASSIC: the pair sum takes the unbiased piece of the appendix's second
+// moment, c_j c_k / (L (L - 1)) off the diagonal and c_j (c_j - 1) / (L (L - 1))
+// on it, in place of f_j f_k.
 constexpr int kAccMaxBlocks = kWhitenBlockCounts;
 
+template <bool CLASSIC>
 __global__ void __launch_bounds__(256) k_accumulate(const int32_t* __restrict__ row_ptr,
                                                     const int32_t* __restrict__ col_idx,
                                                     const float* __restrict__ val, int n_rows,
@@ -76,6 +80,7 @@ __global__ void __launch_bounds__(256) k_accumulate(const int32_t* __restrict__ 
     }
     ++kept;
     const double invL = 1.0 / (double)L;
+    const double l2 = 1.0 / ((double)L * (double)(L - 1));
     for (int j = lane; j < n; j += kWave) {
       const int c = col_idx[b + j];
       const float v = val[b + j];
@@ -94,8 +99,14 @@ __global__ void __launch_bounds__(256) k_accumulate(const int32_t* __restrict__ 
       const long long base = (long long)j * n - (long long)j * (j - 1) / 2;
       const int k = j + (int)(p - base);
       const int cj = col_idx[b + j], ck = col_idx[b + k];
-      const double fj = (double)val[b + j] * invL, fk = (double)val[b + k] * invL;
-      unsafeAtomicAdd(&S2[(size_t)cj * V + ck], fj * fk);
+      double prod;
+      if (CLASSIC) {
+        const double vj = (double)val[b + j], vk = (double)val[b + k];
+        prod = (j == k ? vj * (vj - 1.0) : vj * vk) * l2;
+      } else {
+        prod = ((double)val[b + j] * invL) * ((double)val[b + k] * invL);
+      }
+      unsafeAtomicAdd(&S2[(size_t)cj * V + ck], prod);
     }
   }
   if (lane == 0) {
@@ -172,12 +183,16 @@ hipError_t launch_validate_csr(const tlda_csr_batch& b, int V, int* err, hipStre
 }
 
 hipError_t launch_accumulate(const tlda_csr_batch& b, int V, const Moments& m, int* block_counts,
-                             hipStream_t s) {
+                             bool classic, hipStream_t s) {
   const int rows_per_block = 256 / kWave;
   int grid = (b.n_rows + rows_per_block - 1) / rows_per_block;
   if (grid > kAccMaxBlocks) grid = kAccMaxBlocks;
-  hipLaunchKernelGGL(k_accumulate, dim3(grid), dim3(256), 0, s, b.row_ptr, b.col_idx, b.val,
-                     b.n_rows, V, block_counts, m.totals, m.fsum, m.S2);
+  if (classic)
+    hipLaunchKernelGGL(k_accumulate<true>, dim3(grid), dim3(256), 0, s, b.row_ptr, b.col_idx,
+                       b.val, b.n_rows, V, block_counts, m.totals, m.fsum, m.S2);
+  else
+    hipLaunchKernelGGL(k_accumulate<false>, dim3(grid), dim3(256), 0, s, b.row_ptr, b.col_idx,
+                       b.val, b.n_rows, V, block_counts, m.totals, m.fsum, m.S2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_add_counts, dim3(1), dim3(256), 0, s, block_counts, grid, m.counts);

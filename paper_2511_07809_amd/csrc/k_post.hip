@@ -49,7 +49,38 @@ __global__ void __launch_bounds__(256) k_frame_weights(const float* __restrict__
   }
 }
 
-// mu[i][k] = sum_d U[i][d] sqrt(eig[d]) phi[d][k] scale[k] + m[i]
+// Classic recovery: lambda_k = (1+theta)|phi_k|^3, scale[k] = lambda_k / |phi_k|
+// (so that mu_k = lambda_k (W^T)^+ phi_k / |phi_k|), alpha_k proportional to
+// lambda_k^-2; a zero column gets scale 0 and weight 0.  One block; K <= 256.
+__global__ void __launch_bounds__(256) k_classic_weights(const float* __restrict__ Phi, int D,
+                                                         int K, double theta,
+                                                         double* __restrict__ scale,
+                                                         double* __restrict__ alpha,
+                                                         double* __restrict__ lambda) {
+  __shared__ double w_sh[256];
+  const int k = threadIdx.x;
+  double w = 0.0;
+  if (k < K) {
+    double n2 = 0.0;
+    for (int d = 0; d < D; ++d) {
+      const double v = (double)Phi[d * K + k];
+      n2 += v * v;
+    }
+    const double lam = (1.0 + theta) * n2 * sqrt(n2);
+    scale[k] = (1.0 + theta) * n2;
+    w = lam > 0.0 ? 1.0 / (lam * lam) : 0.0;
+    if (lambda != nullptr) lambda[k] = lam;
+  }
+  w_sh[k] = w;
+  __syncthreads();
+  if (k < K) {
+    double s = 0.0;
+    for (int j = 0; j < K; ++j) s += w_sh[j];
+    alpha[k] = s > 0.0 ? w / s : 0.0;
+  }
+}
+
+// mu[i][k] = sum_d U[i][d] sqrt(eig[d]) phi[d][k] scale[k] + m[i] (m may be NULL)
 __global__ void k_mu(const float* __restrict__ Phi, const double* __restrict__ U,
                      const double* __restrict__ eig, const double* __restrict__ m,
                      const double* __restrict__ scale, int V, int D, int K,
@@ -59,7 +90,7 @@ __global__ void k_mu(const float* __restrict__ Phi, const double* __restrict__ U
   const int i = (int)(e / K), k = (int)(e % K);
   double s = 0.0;
   for (int d = 0; d < D; ++d) s += U[(size_t)i * D + d] * sqrt(eig[d]) * (double)Phi[d * K + k];
-  mu[e] = s * scale[k] + m[i];
+  mu[e] = s * scale[k] + (m != nullptr ? m[i] : 0.0);
 }
 
 // Clip negative entries and renormalise every column to sum one (a column
@@ -251,6 +282,25 @@ hipError_t launch_unwhiten(const float* Phi, const double* U, const double* eig,
   const size_t n = (size_t)V * K;
   hipLaunchKernelGGL(k_mu, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Phi, U, eig, m,
                      scratch, V, D, K, mu);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (flags & TLDA_PROJECT_SIMPLEX) {
+    hipLaunchKernelGGL(k_simplex_columns, dim3(K), dim3(256), 0, s, mu, V, K);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_unwhiten_classic(const float* Phi, const double* U, const double* eig, int V,
+                                   int D, int K, double theta, uint32_t flags, double* mu,
+                                   double* alpha, double* lambda, double* scratch, hipStream_t s) {
+  hipLaunchKernelGGL(k_classic_weights, dim3(1), dim3(256), 0, s, Phi, D, K, theta, scratch,
+                     alpha, lambda);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t n = (size_t)V * K;
+  hipLaunchKernelGGL(k_mu, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Phi, U, eig,
+                     static_cast<const double*>(nullptr), scratch, V, D, K, mu);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (flags & TLDA_PROJECT_SIMPLEX) {

@@ -63,6 +63,7 @@ thread_local KernelTimer g_main_timer;
 namespace {
 
 bool is_bf16(const tlda_ctx* c) { return (c->cfg.flags & TLDA_BF16) != 0; }
+bool is_classic(const tlda_ctx* c) { return (c->cfg.flags & TLDA_CLASSIC) != 0; }
 
 // FP32 (and, in BF16 contexts, BF16) gather copies of W and their mean
 // projections, from U, eig and M1.
@@ -206,13 +207,15 @@ tlda_status orthonormalise(tlda_ctx* c, const double* in, double* tmp, double* o
   return TLDA_OK;
 }
 
-// M2~ Q = (alpha0+1)(S2 Q / N - M1 (M1^T Q)) into Y.
+// M2~ Q = (alpha0+1)(S2 Q / N - M1 (M1^T Q)) into Y; for classic-moment
+// contexts M2 Q = (alpha0+1) S2 Q / N - alpha0 M1 (M1^T Q).
 tlda_status apply_m2(tlda_ctx* c, const double* Q, double* Y, double N) {
   tlda::EigScratch& e = c->eig;
   const int V = c->cfg.V, p = e.p;
   const double a1 = c->cfg.alpha0 + 1.0;
+  const double am = is_classic(c) ? c->cfg.alpha0 : a1;
   HIP_OK(c, tlda::launch_vecT_mat(e.mcand, Q, e.t, V, p, c->stream));
-  HIP_OK(c, tlda::launch_m2_apply(c->mom.S2, e.mcand, e.t, Q, Y, V, p, a1 / N, a1, c->stream));
+  HIP_OK(c, tlda::launch_m2_apply(c->mom.S2, e.mcand, e.t, Q, Y, V, p, a1 / N, am, c->stream));
   return TLDA_OK;
 }
 
@@ -272,6 +275,56 @@ tlda_status refresh(tlda_ctx* c) {
   return TLDA_OK;
 }
 
+// The CP step of a classic-moment context (the batch is already checked):
+// Z = W Phi and r, the per-block data-term partials over the batch, then the
+// shared finish kernel.  X_out, if given, receives the whitened batch first.
+tlda_status classic_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float* Phi, float* grad,
+                         float* X_out, int32_t* n_kept_out) {
+  tlda_status st = validate_content(c, b);
+  if (st != TLDA_OK) return st;
+  if (X_out != nullptr) {
+    st = tlda_whiten_batch(c, b, X_out, nullptr);
+    if (st != TLDA_OK) return st;
+  }
+  if (b->n_rows == 0) {
+    if (n_kept_out) HIP_OK(c, launch_zero(n_kept_out, sizeof(int32_t), c->stream));
+    return TLDA_OK;
+  }
+  const int V = c->cfg.V, D = c->cfg.D, K = c->cfg.K;
+  const int Kp = tlda::padded_d(K);
+  if (c->cp.Z == nullptr) {
+    HIP_OK(c, dalloc(&c->cp.Z, (size_t)V * Kp));
+    HIP_OK(c, dalloc(&c->cp.rz, (size_t)Kp));
+  }
+  if (c->tune.classic_resident <= 0) {
+    int per_cu = 0;
+    HIP_OK(c, tlda::launch_classic_cp(*b, c->wh.W32, c->Dp, c->cp.Z, Kp, c->wh.mw32, c->cp.rz, D,
+                                      K, c->cfg.alpha0, 0, nullptr, &per_cu, c->stream));
+    c->tune.classic_resident = (per_cu > 0 ? per_cu : 1) * c->num_cu;
+  }
+  const int ntiles = (b->n_rows + 15) / 16;
+  int nblk = ntiles < c->tune.classic_resident ? ntiles : c->tune.classic_resident;
+  if (nblk > 2 * tlda::kWhitenBlockCounts) nblk = 2 * tlda::kWhitenBlockCounts;
+  st = ensure_partial(c, (size_t)nblk * D * K);
+  if (st != TLDA_OK) return st;
+  float* g = grad ? grad : c->cp.grad;
+  HIP_OK(c, tlda::launch_classic_z(c->wh.W32, V, D, c->Dp, Phi, K, Kp, c->wh.mw32, c->cp.Z,
+                                   c->cp.rz, c->cp.phi0, c->num_cu, c->stream));
+  st = begin_use(c, b);
+  if (st != TLDA_OK) return st;
+  HIP_OK(c, timing_start(c));
+  HIP_OK(c, tlda::launch_classic_cp(*b, c->wh.W32, c->Dp, c->cp.Z, Kp, c->wh.mw32, c->cp.rz, D, K,
+                                    c->cfg.alpha0, nblk, c->cp.partial, c->block_counts,
+                                    c->stream));
+  HIP_OK(c, timing_stop(c));
+  st = end_use(c, b);
+  if (st != TLDA_OK) return st;
+  HIP_OK(c, tlda::launch_cp_finish(c->cp.partial, nblk, c->block_counts, nblk, 0, c->cp.phi0, D, K,
+                                   c->cfg.alpha0, c->cfg.theta, beta, Phi, g, c->cp.R1, n_kept_out,
+                                   c->stream));
+  return TLDA_OK;
+}
+
 void destroy_all(tlda_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
@@ -284,6 +337,7 @@ void destroy_all(tlda_ctx* c) {
   dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
   dfree(e.sel); dfree(e.mcand); dfree(e.info);
   dfree(c->cp.partial); dfree(c->cp.R1); dfree(c->cp.phi0); dfree(c->cp.grad); dfree(c->cp.X);
+  dfree(c->cp.Z); dfree(c->cp.rz);
   dfree(c->post); dfree(c->postA); dfree(c->postG); dfree(c->postZ); dfree(c->postEv);
   dfree(c->A32); dfree(c->G32); dfree(c->step32); dfree(c->dev_flags); dfree(c->block_counts);
   for (auto& s : c->slots) {
@@ -322,16 +376,18 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
   const tlda_config& c = *cfg;
   if (!(c.alpha0 > 0.0) || !std::isfinite(c.alpha0)) return TLDA_ERR_ARG;
   if (!(c.theta >= 0.0) || !std::isfinite(c.theta)) return TLDA_ERR_ARG;
-  if (c.flags & ~(TLDA_VALIDATE_CSR | TLDA_BF16)) return TLDA_ERR_ARG;
+  if (c.flags & ~(TLDA_VALIDATE_CSR | TLDA_BF16 | TLDA_CLASSIC)) return TLDA_ERR_ARG;
+  if ((c.flags & TLDA_BF16) && (c.flags & TLDA_CLASSIC)) return TLDA_ERR_ARG;
   if (c.eig_iters < 0 || c.eig_block < 0) return TLDA_ERR_ARG;
   if (c.V < 3 || c.V > 131072) return TLDA_ERR_SHAPE;
   if (c.K < 1 || c.K > TLDA_MAX_K || c.D < 1 || c.D > TLDA_MAX_D || c.D > c.V) return TLDA_ERR_SHAPE;
   if (c.D * c.K > TLDA_MAX_DK) return TLDA_ERR_SHAPE;
-  if (!(c.flags & TLDA_BF16) &&
+  if (!(c.flags & (TLDA_BF16 | TLDA_CLASSIC)) &&
       (((c.D + 3) / 4) * ((c.K + 3) / 4) > 1024 || tlda::cp_tile_rows(c.D, c.K) == 0))
-    return TLDA_ERR_SHAPE;   // the FP32 reduction's shape limits
+    return TLDA_ERR_SHAPE;   // the FP32 reduction's shape limits (unused by BF16 and classic)
   if (c.eig_block != 0 && (c.eig_block < c.D || c.eig_block > c.V)) return TLDA_ERR_SHAPE;
   if ((c.flags & TLDA_BF16) && !tlda::bf16_supported(c.D, c.K)) return TLDA_ERR_SHAPE;
+  if ((c.flags & TLDA_CLASSIC) && !tlda::classic_supported(c.D, c.K)) return TLDA_ERR_SHAPE;
   tlda_ctx* ctx = new (std::nothrow) tlda_ctx();
   if (!ctx) return TLDA_ERR_OOM;
   ctx->cfg = c;
@@ -419,7 +475,8 @@ tlda_status tlda_update_moments(tlda_ctx* c, const tlda_csr_batch* b, uint32_t f
   if (b && b->n_rows > 0) {
     st = begin_use(c, b);
     if (st != TLDA_OK) return st;
-    HIP_OK(c, tlda::launch_accumulate(*b, c->cfg.V, c->mom, c->block_counts, c->stream));
+    HIP_OK(c, tlda::launch_accumulate(*b, c->cfg.V, c->mom, c->block_counts, is_classic(c),
+                                      c->stream));
     st = end_use(c, b);
     if (st != TLDA_OK) return st;
   }
@@ -468,6 +525,8 @@ tlda_status tlda_whiten_batch(tlda_ctx* c, const tlda_csr_batch* b, float* X, in
 tlda_status tlda_cp_step(tlda_ctx* c, const float* X, int32_t n_rows, const int32_t* n_kept,
                          float beta, float* Phi, float* grad) {
   if (!c) return TLDA_ERR_ARG;
+  CHECK_ARG(c, !is_classic(c), TLDA_ERR_STATE,
+            "classic-moment contexts step from the batch (tlda_whiten_cp_step), not from X");
   CHECK_ARG(c, n_rows >= 0, TLDA_ERR_SHAPE, "negative n_rows");
   CHECK_ARG(c, Phi != nullptr, TLDA_ERR_ARG, "Phi is NULL");
   CHECK_ARG(c, X != nullptr || n_rows == 0, TLDA_ERR_ARG, "X is NULL");
@@ -508,6 +567,7 @@ tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta
   CHECK_ARG(c, Phi != nullptr, TLDA_ERR_ARG, "Phi is NULL");
   CHECK_ARG(c, std::isfinite(beta), TLDA_ERR_ARG, "beta is not finite");
   const int D = c->cfg.D, K = c->cfg.K;
+  if (is_classic(c)) return classic_step(c, b, beta, Phi, grad, X_out, n_kept_out);
   if (!is_bf16(c) && !tlda::fused_supported(D, K, c->Dp)) {
     // two calls in sequence through the context's own X buffer
     const size_t need = (size_t)b->n_rows * D;
@@ -585,6 +645,12 @@ tlda_status tlda_unwhiten(tlda_ctx* c, const float* Phi, double* mu, double* alp
   CHECK_ARG(c, Phi && mu && alpha, TLDA_ERR_ARG, "Phi, mu or alpha is NULL");
   CHECK_ARG(c, (flags & ~TLDA_PROJECT_SIMPLEX) == 0, TLDA_ERR_ARG, "unknown flags");
   CHECK_ARG(c, c->wh.ready, TLDA_ERR_STATE, "no whitening matrix yet");
+  if (is_classic(c)) {
+    HIP_OK(c, tlda::launch_unwhiten_classic(Phi, c->wh.U, c->wh.eig, c->cfg.V, c->cfg.D, c->cfg.K,
+                                            c->cfg.theta, flags, mu, alpha, lambda, c->post,
+                                            c->stream));
+    return TLDA_OK;
+  }
   HIP_OK(c, tlda::launch_unwhiten(Phi, c->wh.U, c->wh.eig, c->wh.m, c->cfg.V, c->cfg.D, c->cfg.K,
                                   c->cfg.theta, flags, mu, alpha, lambda, c->post, c->stream));
   return TLDA_OK;

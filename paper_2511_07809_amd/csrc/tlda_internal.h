@@ -82,6 +82,7 @@ struct Tuning {
   int fused_blocks = 0;
   int bf16_blocks = 0;
   int bf16_resident[3] = {0, 0, 0};   // cached occupancy rounds of the BF16 kernels
+  int classic_resident = 0;           // the same for the classic-moment kernel
   int whiten_v4 = 0;
   int whiten_chunks = 0;
 };
@@ -94,6 +95,8 @@ struct CpScratch {
   float* grad = nullptr;      // [D][K] used when the caller passes no gradient buffer
   float* X = nullptr;         // [cap_x] whitened batch for the unfused fallback
   size_t cap_x = 0;
+  float* Z = nullptr;         // [V][Kp] W Phi of the classic-moment step
+  float* rz = nullptr;        // [Kp]    Phi^T W^T M1 of the classic-moment step
 };
 
 }  // namespace tlda
@@ -205,8 +208,10 @@ hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s);
 // moments
 hipError_t launch_validate_csr(const tlda_csr_batch& b, int V, int* err, hipStream_t s);
 // block_counts: scratch for 2 * kWhitenBlockCounts ints
+// classic: S2 takes the unbiased pair piece (c c^T - diag c) / (L (L - 1))
+// instead of f f^T
 hipError_t launch_accumulate(const tlda_csr_batch& b, int V, const Moments& m, int* block_counts,
-                             hipStream_t s);
+                             bool classic, hipStream_t s);
 hipError_t launch_mirror_upper(double* S2, int V, hipStream_t s);
 hipError_t launch_mean(const double* fsum, const unsigned long long* counts, double* m, int V,
                        hipStream_t s);
@@ -281,6 +286,18 @@ hipError_t launch_whiten_bf16(const tlda_csr_batch& b, const uint16_t* W16, cons
                               int Dh, int D, int nblk, float* X, int* block_counts, hipStream_t s);
 // One full round of resident CP-reduction blocks on this device.
 int cp_resident_blocks(int D, int K, int num_cu);
+// classic-moment CP step (FP32, D, K <= 128): Z = W Phi, r = Phi^T mw32 and
+// phi_copy = Phi, then the per-block data-term partials divided by c3 and the
+// kept counts (block_counts[0 .. nblk)).  With partial == nullptr,
+// launch_classic_cp only stores in *block_counts the resident blocks per CU.
+bool classic_supported(int D, int K);
+hipError_t launch_classic_z(const float* W32, int V, int D, int Dp, const float* Phi, int K,
+                            int Kp, const float* mw32, float* Z, float* r, float* phi_copy,
+                            int num_cu, hipStream_t s);
+hipError_t launch_classic_cp(const tlda_csr_batch& b, const float* W32, int Dp, const float* Z,
+                             int Kp, const float* mw32, const float* r, int D, int K,
+                             double alpha0, int nblk, float* partial, int* block_counts,
+                             hipStream_t s);
 // document-topic encoder (MLP)
 size_t mlp_param_count(int d_in, int hidden, int k_out);
 // offsets of W1, b1, W2, b2, W3, b3 in the packed parameter vector
@@ -297,6 +314,11 @@ hipError_t mlp_refresh_bf16(tlda_mlp& m);
 hipError_t launch_unwhiten(const float* Phi, const double* U, const double* eig, const double* m,
                            int V, int D, int K, double theta, uint32_t flags, double* mu,
                            double* alpha, double* lambda, double* scratch, hipStream_t s);
+// classic recovery: lambda_k = (1+theta)|phi_k|^3, mu_k = lambda_k U diag(eig)^(1/2)
+// phi_k / |phi_k|, alpha proportional to lambda^-2
+hipError_t launch_unwhiten_classic(const float* Phi, const double* U, const double* eig, int V,
+                                   int D, int K, double theta, uint32_t flags, double* mu,
+                                   double* alpha, double* lambda, double* scratch, hipStream_t s);
 hipError_t launch_inference_setup(const double* W, const double* m, const double* mu, int V,
                                   int D, int K, double* A, double* G, double* Z, double* ev,
                                   float* A32, float* G32, float* step32, int* info,

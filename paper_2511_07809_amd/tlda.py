@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "TLDA_OK", 1: "TLDA_ERR_ARG", 2: "TLDA_ERR_SHAPE", 3: "TLDA_E
                 7: "TLDA_ERR_DEVICE"}
 TLDA_VALIDATE_CSR = 0x1
 TLDA_BF16 = 0x2
+TLDA_CLASSIC = 0x4
 TLDA_REFRESH_W = 0x1
 TLDA_RESET = 0x2
 TLDA_RELEASE = 0x4
@@ -203,13 +204,15 @@ class _StagedBatch(CsrBatch):
 # The C ABI, one Python function per C function.
 # ---------------------------------------------------------------------------
 def tlda_create(V: int, K: int, D: int, alpha0: float, theta: float = 0.0, *,
-                validate_csr: bool = False, bf16: bool = False, eig_iters: int = 0,
+                validate_csr: bool = False, bf16: bool = False, classic: bool = False,
+                eig_iters: int = 0,
                 eig_block: int = 0, eig_seed: int = 0,
                 stream: Optional[torch.cuda.Stream] = None) -> Context:
     if not torch.cuda.is_available():
         raise RuntimeError("libtlda needs a ROCm GPU; none is visible")
     stream = stream or torch.cuda.current_stream()
-    flags = (TLDA_VALIDATE_CSR if validate_csr else 0) | (TLDA_BF16 if bf16 else 0)
+    flags = ((TLDA_VALIDATE_CSR if validate_csr else 0) | (TLDA_BF16 if bf16 else 0)
+             | (TLDA_CLASSIC if classic else 0))
     cfg = tlda_config(V, K, D, flags, float(alpha0), float(theta), eig_iters, eig_block, eig_seed)
     h = ctypes.c_void_p()
     _check(None, _LIB.tlda_create(ctypes.byref(cfg), ctypes.c_void_p(stream.cuda_stream),

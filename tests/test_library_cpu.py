@@ -64,7 +64,8 @@ def test_create_validates_config_before_touching_a_device(lib):
         cfg = tlda.tlda_config(V, K, D, flags, alpha0, theta, 0, 0, 0)
         return lib.tlda_create(ctypes.byref(cfg), None, ctypes.byref(out))
 
-    assert create(100, 10, 10, 0x4) == 1                       # unknown flag
+    assert create(100, 10, 10, 0x8) == 1                       # unknown flag
+    assert create(100, 10, 10, tlda.TLDA_BF16 | tlda.TLDA_CLASSIC) == 1   # not combinable
     assert create(100, 10, 10, 0, alpha0=0.0) == 1             # alpha0 must be > 0
     assert create(100, 10, 10, 0, theta=-1.0) == 1             # theta must be >= 0
     assert create(2, 1, 1, 0) == 2                             # V < 3
@@ -72,6 +73,8 @@ def test_create_validates_config_before_touching_a_device(lib):
     assert create(300, 257, 10, 0) == 2                        # K above the limit
     assert create(300, 10, 129, tlda.TLDA_BF16) == 2           # BF16 path: D <= 128
     assert create(300, 129, 10, tlda.TLDA_BF16) == 2           # BF16 path: K <= 128
+    assert create(300, 10, 129, tlda.TLDA_CLASSIC) == 2        # classic rung: D <= 128
+    assert create(300, 129, 10, tlda.TLDA_CLASSIC) == 2        # classic rung: K <= 128
     assert out.value is None
     lib.tlda_set_timing_events.restype = ctypes.c_int
     lib.tlda_set_timing_events.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
