@@ -62,6 +62,9 @@ def parse():
                          "the two precisions")
     ap.add_argument("--fit-beta", type=float, default=None,
                     help="step size of that fit (default 0.03 for c1, 0.01 for c2, 0.001 for c3)")
+    ap.add_argument("--estimator", default="centred", choices=["centred", "classic"],
+                    help="classic: the alpha0-corrected moments (FP32 classic-moment context) "
+                         "on c1, c2 or c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -108,6 +111,135 @@ def cpu_baseline(corpus, spec, batches, seconds: float) -> dict:
     return {"value": docs / dt, "unit": "docs/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{docs} documents of batch 0 ({spec.name}) in 1024-document slices, "
                       f"{dt:.1f} s: dense FP64 whitening plus the eq. vec_deriv gradient"}
+
+
+def classic_cpu_baseline(corpus, spec, batches, seconds: float) -> dict:
+    """The FP64 oracle of the classic rung on a bounded sample of batch 0:
+    the implicit per-document data term and gradient on 256-document slices."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import tlda_oracle as O
+    from synth import init_phi
+
+    rng = np.random.default_rng(0)
+    D, K = spec.K, spec.K
+    Q, _ = np.linalg.qr(rng.standard_normal((spec.V, D)))
+    W = Q * 30.0
+    m = np.bincount(corpus.indices[: corpus.indptr[min(corpus.n_docs, 65536)]],
+                    minlength=spec.V).astype(np.float64)
+    m /= m.sum()
+    Phi = init_phi(D, K, 1) * 0.3
+    rp, ci, va, _ = batches[0]
+    step, docs, s = 256, 0, 0
+    t0 = time.perf_counter()
+    while True:
+        e = min(s + step, rp.shape[0] - 1)
+        a, b = int(rp[s]), int(rp[e])
+        sub_rp = (rp[s:e + 1] - a).astype(np.int64)
+        G = O.classic_cp_gradient(sub_rp, ci[a:b], va[a:b], spec.V, m, W, Phi, spec.alpha0, 0.0)
+        Phi = Phi - 1e-6 * G
+        docs += e - s
+        s = e if e < rp.shape[0] - 1 else 0
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": docs / dt, "unit": "docs/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{docs} documents of batch 0 ({spec.name}) in 256-document slices, "
+                      f"{dt:.1f} s: the classic rung's FP64 per-document data term and gradient"}
+
+
+def run_classic(args) -> None:
+    """The classic alpha0-corrected rung: moment pass, refresh and CP steps of
+    an FP32 classic-moment context on the same corpus and batches."""
+    import numpy as np
+    import torch
+
+    from paper_2511_07809_amd import tlda as tl
+    from synth import SPECS, generate, init_phi, iter_batches
+
+    spec = SPECS[args.workload]
+    D = K = spec.K
+    corpus = generate(spec, n_docs=args.docs or None)
+    batches = list(iter_batches(corpus))
+    log(f"[bench] generated {spec.name}: {corpus.n_docs} docs, {corpus.nnz} nnz")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    ctx = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, classic=True, eig_iters=60)
+    dev = [tl.CsrBatch.from_numpy(rp, ci, va) for rp, ci, va, _ in batches]
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for b in dev:
+        tl.tlda_update_moments(ctx, b)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter()
+    tl.tlda_update_moments(ctx, None, tl.TLDA_REFRESH_W)
+    refresh_ms = (time.perf_counter() - t_ref) * 1e3
+    moments_ms = ev[0].elapsed_time(ev[1])
+    log(f"[bench] classic moment pass {moments_ms:.2f} ms, refresh {refresh_ms:.1f} ms")
+    beta = args.beta if args.beta is not None else 1e-3
+    nk = torch.empty(1, dtype=torch.int32, device="cuda")
+    Phi = torch.from_numpy((init_phi(D, K, 1) * 0.3).astype(np.float32)).cuda()
+    r = run_steps(tl, ctx, lambda i: dev[i % len(dev)], True, beta, Phi, None, nk, args.steps,
+                  args.warmup, stream)
+    docs_per_s = r["docs"] / (r["total_ms"] / 1e3)
+    kern_us = r["kern_ms"].mean(axis=0) * 1e3
+    log(f"[bench] classic: {args.steps} steps {r['total_ms']:.3f} ms, step "
+        f"{r['step_ms'].mean() * 1e3:.1f} us, k_classic_cp {kern_us[0]:.1f} us, "
+        f"{docs_per_s:.4g} docs/s")
+    # roofline of k_classic_cp: reduction rows = nonzeros + documents, each a
+    # D x K outer product on FP32 matrix cores; bytes = CSR + W + Z, once
+    per = args.steps
+    rows = (r["nnz"] + r["docs"]) / per
+    flops = 2.0 * rows * D * K
+    byts = (4 * (r["docs"] + per) + 8 * r["nnz"]) / per + 4 * spec.V * (D + K)
+    t_k = kern_us[0] / 1e6
+    mm_frac = flops / t_k / 1e12 / FP32_VALU_PEAK_TFLOPS
+    hbm_frac = byts / t_k / 1e9 / HBM_PEAK_GBS
+    if mm_frac >= hbm_frac:
+        roof = {"kernel": "k_classic_cp", "bound": "mfma", "achieved": flops / t_k / 1e12,
+                "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": mm_frac}
+    else:
+        roof = {"kernel": "k_classic_cp", "bound": "hbm", "achieved": byts / t_k / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_frac}
+    roof.update({"traffic": measured_traffic("k_classic_cp", spec.name),
+                 "algorithmic_flops": flops, "algorithmic_bytes": byts,
+                 "mfma_frac": mm_frac, "hbm_frac": hbm_frac, "avg_launch_us": float(kern_us[0])})
+    fit_beta = args.fit_beta
+    if fit_beta is None:
+        fit_beta = {"c1": 0.03, "c2": 0.01}.get(spec.name, 1e-3)
+    Phi = torch.from_numpy((init_phi(D, K, 1) * 0.3).astype(np.float32)).cuda()
+    for _ in range(args.fit_passes):
+        for b in dev:
+            tl.tlda_whiten_cp_step(ctx, b, fit_beta, Phi)
+    l1, _ = topic_error(tl, ctx, Phi, corpus.mu)
+    out = {
+        "metric": "docs/sec (whiten+CP step) at fixed topic-recovery error; % HBM roofline",
+        "value": docs_per_s, "unit": "docs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["total_ms"] / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{spec.name} classic rung: V={spec.V}, K=D={K}, "
+                               f"alpha0={spec.alpha0}, {corpus.n_docs} docs of length "
+                               f"1+Poisson({spec.doc_len_lambda:g}), batch {spec.batch}, "
+                               "resident in HBM",
+                   "estimator": "classic", "global_batch": spec.batch, "beta": beta},
+        "roofline": roof,
+        "breakdown": {"step_us": float(r["step_ms"].mean()) * 1e3,
+                      "main_kernel_us": [float(x) for x in kern_us],
+                      "moment_pass_ms": moments_ms,
+                      "moments_docs_per_s": corpus.n_docs / (moments_ms / 1e3),
+                      "refresh_ms": refresh_ms},
+        "accuracy": {"passes": args.fit_passes, "beta": fit_beta,
+                     "classic_topic_l1_to_planted": l1},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle of the classic rung on a bounded sample")
+        out["cpu_baseline"] = classic_cpu_baseline(corpus, spec, batches, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -504,6 +636,9 @@ def main():
         return
     if args.workload == "c4":
         run_slices(args)
+        return
+    if args.estimator == "classic":
+        run_classic(args)
         return
     import numpy as np
     import torch
