@@ -44,6 +44,13 @@ Readings
       recovery is the orthogonal one of the post-processing section:
       lambda_i = (1+theta)|phi_i|^3, mu_i = lambda_i (W^T)^+ phi_i/|phi_i|,
       alpha_i proportional to lambda_i^-2.
+  R15 Fully online mode: the paper keeps Phi across batches while W changes
+      and does not say how Phi is carried over.  Phi is re-based as
+      Phi_new = W_new^T (W_old^T)^+ Phi_old (the factors' centred word-space
+      vectors seen through the new whitening; the shift of M1 between batches
+      is not carried, it is O(batch / N)).  The incremental PCA is read as the
+      top-D eigenpairs of the running M2~ over every batch seen so far, which
+      is what an incremental PCA of the centred data tracks.
 """
 from __future__ import annotations
 
@@ -59,7 +66,8 @@ __all__ = [
     "unwhiten", "simplex_project", "infer_doc_topics", "match_topics",
     "uncentered_cumulants", "whitened_tensor", "tensor_power_method",
     "classic_recover", "fit_batched", "classic_second_moment", "classic_data_term",
-    "classic_cp_gradient", "classic_unwhiten", "fit_batched_classic",
+    "classic_cp_gradient", "classic_unwhiten", "fit_batched_classic", "rebase_phi",
+    "fit_online",
 ]
 
 
@@ -534,4 +542,42 @@ def fit_batched(batches: list, V: int, K: int, D: int, alpha0: float, theta: flo
                 Phi = cp_step(X, Phi, n, alpha0, theta, beta)
     out = unwhiten(Phi, U, lam, m, theta)
     out.update({"Phi": Phi, "W": W, "eig": lam, "U": U, "m": m, "N": N, "M2": M2})
+    return out
+
+
+# --------------------------------------------------------------------------
+# The fully online method (fully-online section, R15): factors from a batched
+# run on an initial portion, then per new batch: the moments, a new whitening
+# of the running M2~, Phi carried into the new whitened space, the whitened
+# batch and one gradient step.  No earlier batch is revisited.
+# --------------------------------------------------------------------------
+def rebase_phi(Phi: np.ndarray, W_old: np.ndarray, W_new: np.ndarray) -> np.ndarray:
+    """Phi_new = W_new^T (W_old^T)^+ Phi_old (R15): the factors' centred
+    word-space vectors (W_old^T)^+ phi, seen through the new whitening."""
+    return W_new.T @ np.linalg.pinv(W_old.T) @ Phi
+
+
+def fit_online(init_batches: list, stream_batches: list, V: int, K: int, D: int, alpha0: float,
+               theta: float, beta: float, init_passes: int, Phi0: np.ndarray) -> dict:
+    """R15: Phi from fit_batched on init_batches; then for each batch of
+    stream_batches the running M1 and M2~ over every batch seen so far, W from
+    them (R4), Phi rebased from the previous W, X with the new M1 and W, and
+    one gradient step (skipped when the batch keeps no document)."""
+    fit = fit_batched(init_batches, V, K, D, alpha0, theta, beta, init_passes, Phi0)
+    Phi, W = fit["Phi"], fit["W"]
+    seen = list(init_batches)
+    trace = []
+    for rp, ci, va in stream_batches:
+        seen.append((rp, ci, va))
+        m, N = first_moment(seen, V)
+        W_new, lam, U = whitening(centered_second_moment(seen, m, N, alpha0), D)
+        Phi = rebase_phi(Phi, W, W_new)
+        W = W_new
+        n = batch_stats(rp, ci, va, V)["n_kept"]
+        if n > 0:
+            Phi = cp_step(whiten(rp, ci, va, V, m, W), Phi, n, alpha0, theta, beta)
+        trace.append(Phi.copy())
+    out = unwhiten(Phi, U, lam, m, theta)
+    out.update({"Phi": Phi, "W": W, "eig": lam, "U": U, "m": m, "N": N, "trace": trace,
+                "Phi_init": fit["Phi"], "W_init": fit["W"]})
     return out

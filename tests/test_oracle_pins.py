@@ -439,3 +439,50 @@ def test_classic_fit_from_the_planted_start_stays_near_the_truth():
     Phi0 = (np.sqrt(a)[None, :] * (W.T @ c.mu)) * np.cbrt(a ** -0.5)[None, :]
     fit = O.fit_batched_classic(batches, spec.V, spec.K, spec.K, spec.alpha0, 0.0, 0.03, 5, Phi0)
     assert O.match_topics(fit["mu_simplex"], c.mu)["mean_l1"] < 0.1
+
+
+# ----------------------------------------------------------------------------
+# the fully online mode (R15)
+# ----------------------------------------------------------------------------
+def test_rebase_transports_whitened_topic_vectors_between_whitenings():
+    """Any two whitenings of the same population M2~ see the centred topics
+    nu_i as W^T nu_i; rebasing the old view gives the new one exactly (here
+    the new whitening is the old one rotated and rescaled), and the planted CP
+    fixed point goes to the fixed point of the rotated problem."""
+    mu, alpha, a0, a, m, nu = _planted_population()
+    K = mu.shape[1]
+    M2 = (nu * a) @ nu.T
+    W_old, lam, U = O.whitening(M2, K - 1)
+    R, _ = np.linalg.qr(np.random.default_rng(2).standard_normal((K - 1, K - 1)))
+    for s in (1.0, 2.5):
+        W_new = W_old @ R / np.sqrt(s)
+        np.testing.assert_allclose(O.rebase_phi(W_old.T @ nu, W_old, W_new), W_new.T @ nu,
+                                   atol=1e-12)
+    Phi_star = (a / 2.0) ** (1 / 3) * (W_old.T @ nu)
+    np.testing.assert_allclose(O.rebase_phi(Phi_star, W_old, W_old @ R), R.T @ Phi_star,
+                               atol=1e-12)
+    np.testing.assert_allclose(O.rebase_phi(Phi_star, W_old, W_old), Phi_star, atol=1e-12)
+
+
+def test_online_over_copies_of_one_batch_reduces_to_plain_steps():
+    """Streaming copies of the initial batch leaves M1 and M2~ (so W) unchanged,
+    so the online fit equals the batched fit with one more pass per copy."""
+    c, spec = _small_lda(N=400, seed=41)
+    B = [(rp, ci, va) for rp, ci, va, _ in iter_batches(c, 400)][0]
+    Phi0 = init_phi(spec.K, spec.K, 3)
+    on = O.fit_online([B], [B, B, B], spec.V, spec.K, spec.K, spec.alpha0, 0.0, 0.05, 4, Phi0)
+    ref = O.fit_batched([B], spec.V, spec.K, spec.K, spec.alpha0, 0.0, 0.05, 7, Phi0)
+    np.testing.assert_allclose(on["Phi"], ref["Phi"], atol=1e-10)
+    assert len(on["trace"]) == 3
+
+
+def test_online_whitening_covers_every_batch_seen():
+    c, spec = _small_lda(N=900, seed=42)
+    bs = [(rp, ci, va) for rp, ci, va, _ in iter_batches(c, 300)]
+    Phi0 = init_phi(spec.K, spec.K, 4)
+    on = O.fit_online(bs[:1], bs[1:], spec.V, spec.K, spec.K, spec.alpha0, 0.0, 0.02, 2, Phi0)
+    full = O.fit_batched(bs, spec.V, spec.K, spec.K, spec.alpha0, 0.0, 0.02, 0, Phi0)
+    np.testing.assert_allclose(on["W"], full["W"], atol=1e-12)
+    np.testing.assert_allclose(on["m"], full["m"], atol=1e-15)
+    init = O.fit_batched(bs[:1], spec.V, spec.K, spec.K, spec.alpha0, 0.0, 0.02, 2, Phi0)
+    np.testing.assert_allclose(on["Phi_init"], init["Phi"], atol=1e-15)
