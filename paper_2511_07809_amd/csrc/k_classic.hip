@@ -8,20 +8,20 @@
 //   + alpha0^2 m_w r^2,        g = sum_w c_w W_w z_w,  h = sum_w c_w W_w z_w^2,
 // column k taking the k-th entries of s, q, r, z (c2 = alpha0(alpha0+1)/2,
 // c3 = (alpha0+1)(alpha0+2)/2, m_w = W^T M1).  Grouped by what multiplies W
-// rows, the batch sum divided by c3 is one reduction over rows:
-//   sum over nonzeros (d, w):  W_w  (x)  c_w (b_d * z_w + g_d z_w^2)
-//   sum over documents d:      y_d  (x)  a_d
+// rows (y_d = sum_w c_w W_w), the batch sum divided by c3 is one reduction
+// with a row per nonzero (d, w),
+//   sum over nonzeros (d, w):  W_w  (x)  c_w (a_d + b_d * z_w + g_d z_w^2)
 //   plus m_w (x) sum_d e_d,
 // with a = l3 (s^2 - q) - 2 (c2/c3) l2 r s, b = -2 l3 s + 2 (c2/c3) l2 r,
 // g_d = 2 l3 and e = -(c2/c3) l2 (s^2 - q) + (alpha0^2/c3) r^2 (zero for
 // dropped documents).
 //
 // k_classic_z forms Z (FP32, V x Kp) and r once per step.  k_classic_cp runs
-// over tiles of 16 documents: phase 1 (a wave per document) gathers the W and
-// Z rows of the document's words for y, s, q and the coefficients; phase 2
-// stages 32 reduction rows at a time in LDS (W rows with their scaled Z rows,
-// then the tile's y rows with a) and accumulates the D x K outer products on
-// FP32 matrix cores.  Each block writes its partial sum and its kept-document
+// over tiles of 16 documents: phase 1 (a wave per document) gathers the Z rows
+// of the document's words for s, q and the coefficients; phase 2 stages the
+// tile's nonzero rows (W rows with their scaled Z rows) in LDS, kRows at a
+// time and double-buffered, and accumulates the D x K outer products on FP32
+// matrix cores.  Each block writes its partial sum and its kept-document
 // count; the shared finish kernel adds them in block order, forms the
 // gradient with the penalty term and updates Phi.
 #include "tlda_internal.h"
@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kDocs = 16;    // documents per tile
-constexpr int kRows = 32;    // reduction rows per staged chunk
+constexpr int kRows = 16;    // reduction rows per staged chunk (two buffers)
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // Z[w][k] = sum_d W32[w][d] Phi[d][k] (zero for K <= k < Kp); block 0 also
@@ -79,12 +79,14 @@ __global__ void __launch_bounds__(kThreads, 2) k_classic_cp(
   constexpr int LDA = DQ + 4, LDB = KQ + 4;
   constexpr int NCT = KQ / 16, NDT = DQ / 16, NRT = NDT * NCT;
   constexpr int RT = (NRT + 3) / 4;
-  constexpr int ND = (DQ + 63) / 64, NK = (KQ + 63) / 64;   // phase-1 columns per lane
+  constexpr int NK = (KQ + 63) / 64;                        // phase-1 columns per lane
   constexpr int GA = DQ / 4, GB = KQ / 4;                   // float4 groups per staged row
+  constexpr int TPR = kThreads / kRows;                     // threads per staged row
+  constexpr int UA = (GA + TPR - 1) / TPR, UB = (GB + TPR - 1) / TPR;
   constexpr int NB = 8;                                     // nonzeros per gather step
-  __shared__ __attribute__((aligned(16))) float As[kRows * LDA];
-  __shared__ __attribute__((aligned(16))) float Bs[kRows * LDB];
-  __shared__ __attribute__((aligned(16))) float Ys[kDocs * LDA];
+  static_assert(kThreads % kRows == 0, "staging maps whole rows to threads");
+  __shared__ __attribute__((aligned(16))) float As[2][kRows * LDA];
+  __shared__ __attribute__((aligned(16))) float Bs[2][kRows * LDB];
   __shared__ __attribute__((aligned(16))) float Al[kDocs * LDB];
   __shared__ __attribute__((aligned(16))) float Be[kDocs * LDB];
   __shared__ float gam[kDocs];
@@ -94,6 +96,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_classic_cp(
   __shared__ int wave_kept[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
+  const int srow = tid / TPR, ssub = tid % TPR;   // staged row and column-group lane
 
   for (int k = tid; k < KQ; k += kThreads) rsh[k] = k < K ? r_g[k] : 0.f;
   float dl[NK];
@@ -103,6 +106,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_classic_cp(
 #pragma unroll
   for (int q = 0; q < RT; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
   int kept_total = 0;
+  int buf = 0;
 
   const int ntiles = (n_rows + kDocs - 1) / kDocs;
   for (int tile = blockIdx.x; tile < ntiles; tile += nblk) {
@@ -111,11 +115,9 @@ __global__ void __launch_bounds__(kThreads, 2) k_classic_cp(
     __syncthreads();   // the previous tile's LDS reads are done
     if (tid <= kDocs) rps[tid] = row_ptr[t0 + (tid < nd ? tid : nd)];
     __syncthreads();
-    // ---- phase 1: per-document y, s, q and coefficients (a wave per document) ----
+    // ---- phase 1: per-document s, q, L and coefficients (a wave per document) ----
     for (int ld = wave; ld < kDocs; ld += 4) {
-      float y[ND], s[NK], q[NK];
-#pragma unroll
-      for (int u = 0; u < ND; ++u) y[u] = 0.f;
+      float s[NK], q[NK];
 #pragma unroll
       for (int u = 0; u < NK; ++u) s[u] = q[u] = 0.f;
       float L = 0.f;
@@ -128,15 +130,10 @@ __global__ void __launch_bounds__(kThreads, 2) k_classic_cp(
             mc = col_idx[jb + lane];
             mv = val[jb + lane];
           }
-          float wv[NB][ND], zv[NB][NK];
+          float zv[NB][NK];
 #pragma unroll
           for (int t = 0; t < NB; ++t) {
             const int c = __shfl(mc, t, 64);   // 0 (a valid row) past the document's end
-#pragma unroll
-            for (int u = 0; u < ND; ++u) {
-              const int d = lane + 64 * u;
-              wv[t][u] = d < Dp ? W32[(size_t)c * Dp + d] : 0.f;
-            }
 #pragma unroll
             for (int u = 0; u < NK; ++u) {
               const int k = lane + 64 * u;
@@ -148,8 +145,6 @@ __global__ void __launch_bounds__(kThreads, 2) k_classic_cp(
             const float v = __shfl(mv, t, 64);   // 0 past the document's end
             L += v;
 #pragma unroll
-            for (int u = 0; u < ND; ++u) y[u] = fmaf(v, wv[t][u], y[u]);
-#pragma unroll
             for (int u = 0; u < NK; ++u) {
               s[u] = fmaf(v, zv[t][u], s[u]);
               q[u] = fmaf(v * zv[t][u], zv[t][u], q[u]);
@@ -160,11 +155,6 @@ __global__ void __launch_bounds__(kThreads, 2) k_classic_cp(
       const bool keep = ld < nd && L >= 3.f;   // L is the same on every lane
       const float l2 = keep ? 1.0f / (L * (L - 1.0f)) : 0.f;
       const float l3 = keep ? l2 / (L - 2.0f) : 0.f;
-#pragma unroll
-      for (int u = 0; u < ND; ++u) {
-        const int d = lane + 64 * u;
-        if (d < DQ) Ys[ld * LDA + d] = keep ? y[u] : 0.f;
-      }
 #pragma unroll
       for (int u = 0; u < NK; ++u) {
         const int k = lane + 64 * u;
@@ -179,59 +169,72 @@ __global__ void __launch_bounds__(kThreads, 2) k_classic_cp(
       kept_total += keep ? 1 : 0;
     }
     __syncthreads();
-    // ---- phase 2: the tile's nonzero rows, then its document rows ----
+    // ---- phase 2: one reduction row per nonzero, staged kRows at a time
+    // (double-buffered: the gathers of chunk i+1 are in flight during the
+    // matrix-core work on chunk i) ----
     const int nb0 = rps[0];
     const int nnz = rps[nd] - nb0;
-    const int nrow = nnz + kDocs;
-    for (int cs = 0; cs < nrow; cs += kRows) {
-      const int i = tid >> 3, sub = tid & 7;
-      const int gi = cs + i;
-      if (gi < nnz) {
-        const int j = nb0 + gi;
-        const int col = col_idx[j];
-        const float v = val[j];
-        int lo = 0, hi = nd;   // rps[lo] <= j < rps[hi]
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (rps[mid] <= j) lo = mid;
-          else hi = mid;
-        }
-        const float g = gam[lo];
-        for (int u = sub; u < GA; u += 8) {
-          float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (4 * u < Dp) w = *reinterpret_cast<const float4*>(W32 + (size_t)col * Dp + 4 * u);
-          *reinterpret_cast<float4*>(As + i * LDA + 4 * u) = w;
-        }
-        for (int u = sub; u < GB; u += 8) {
-          float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (4 * u < Kp) z = *reinterpret_cast<const float4*>(Z + (size_t)col * Kp + 4 * u);
-          const float4 be = *reinterpret_cast<const float4*>(Be + lo * LDB + 4 * u);
+    float4 wr[UA], zr[UB];
+    float pv = 0.f;
+    int pdoc = 0;
+    auto fetch = [&](int cs) {
+      const int gi = cs + srow;
+      const bool in = gi < nnz;
+      const int j = nb0 + (in ? gi : 0);
+      const int col = col_idx[j];
+      pv = in ? val[j] : 0.f;            // rows past the tile's end add zero
+      int lo = 0, hi = nd;               // rps[lo] <= j < rps[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rps[mid] <= j) lo = mid;
+        else hi = mid;
+      }
+      pdoc = lo;
+#pragma unroll
+      for (int u = 0; u < UA; ++u) {
+        const int g = ssub + TPR * u;
+        wr[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (g < GA && 4 * g < Dp) wr[u] = *reinterpret_cast<const float4*>(W32 + (size_t)col * Dp + 4 * g);
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int g = ssub + TPR * u;
+        zr[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (g < GB && 4 * g < Kp) zr[u] = *reinterpret_cast<const float4*>(Z + (size_t)col * Kp + 4 * g);
+      }
+    };
+    if (nnz > 0) fetch(0);
+    for (int cs = 0; cs < nnz; cs += kRows) {
+      // B row = c (a_d + b_d * z + g_d z^2); A row = W row
+      const float g = gam[pdoc];
+#pragma unroll
+      for (int u = 0; u < UA; ++u) {
+        const int gg = ssub + TPR * u;
+        if (gg < GA) *reinterpret_cast<float4*>(&As[buf][srow * LDA + 4 * gg]) = wr[u];
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int gg = ssub + TPR * u;
+        if (gg < GB) {
+          const float4 al = *reinterpret_cast<const float4*>(Al + pdoc * LDB + 4 * gg);
+          const float4 be = *reinterpret_cast<const float4*>(Be + pdoc * LDB + 4 * gg);
+          const float4 z = zr[u];
           float4 o;
-          o.x = v * fmaf(g * z.x, z.x, be.x * z.x);
-          o.y = v * fmaf(g * z.y, z.y, be.y * z.y);
-          o.z = v * fmaf(g * z.z, z.z, be.z * z.z);
-          o.w = v * fmaf(g * z.w, z.w, be.w * z.w);
-          *reinterpret_cast<float4*>(Bs + i * LDB + 4 * u) = o;
+          o.x = pv * fmaf(g * z.x + be.x, z.x, al.x);
+          o.y = pv * fmaf(g * z.y + be.y, z.y, al.y);
+          o.z = pv * fmaf(g * z.z + be.z, z.z, al.z);
+          o.w = pv * fmaf(g * z.w + be.w, z.w, al.w);
+          *reinterpret_cast<float4*>(&Bs[buf][srow * LDB + 4 * gg]) = o;
         }
-      } else if (gi < nrow) {
-        const int ld = gi - nnz;
-        for (int u = sub; u < GA; u += 8)
-          *reinterpret_cast<float4*>(As + i * LDA + 4 * u) =
-              *reinterpret_cast<const float4*>(Ys + ld * LDA + 4 * u);
-        for (int u = sub; u < GB; u += 8)
-          *reinterpret_cast<float4*>(Bs + i * LDB + 4 * u) =
-              *reinterpret_cast<const float4*>(Al + ld * LDB + 4 * u);
-      } else {
-        for (int u = sub; u < GA; u += 8)
-          *reinterpret_cast<float4*>(As + i * LDA + 4 * u) = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int u = sub; u < GB; u += 8)
-          *reinterpret_cast<float4*>(Bs + i * LDB + 4 * u) = make_float4(0.f, 0.f, 0.f, 0.f);
       }
       __syncthreads();
+      if (cs + kRows < nnz) fetch(cs + kRows);
+      const float* Ab = As[buf];
+      const float* Bb = Bs[buf];
 #pragma unroll
       for (int rs = 0; rs < kRows / 4; ++rs) {
-        const float* xa = As + (rs * 4 + l4) * LDA + l16;
-        const float* sb = Bs + (rs * 4 + l4) * LDB + l16;
+        const float* xa = Ab + (rs * 4 + l4) * LDA + l16;
+        const float* sb = Bb + (rs * 4 + l4) * LDB + l16;
 #pragma unroll
         for (int q = 0; q < RT; ++q) {
           const int t = wave + 4 * q;
@@ -240,7 +243,7 @@ __global__ void __launch_bounds__(kThreads, 2) k_classic_cp(
                                                           acc[q], 0, 0, 0);
         }
       }
-      __syncthreads();
+      buf ^= 1;
     }
   }
   // ---- m_w (x) sum e, then the block's partial and kept count ----
