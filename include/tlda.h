@@ -104,6 +104,7 @@ typedef struct {
   int32_t eig_iters;    /* subspace iterations of a refresh, 0 = default (60)      */
   int32_t eig_block;    /* subspace width p >= D, 0 = default                      */
   uint64_t eig_seed;    /* seed of the refresh's start block                       */
+  int32_t eig_warm_iters; /* subspace iterations of a warm refresh, 0 = default (4) */
 } tlda_config;
 
 /* One CSR batch of documents (rows) over the vocabulary (columns).  Counts are
@@ -134,6 +135,7 @@ const char* tlda_last_error(const tlda_ctx* ctx);
 #define TLDA_REFRESH_W 0x1u   /* after accumulating, recompute M1, M2~ and W       */
 #define TLDA_RESET 0x2u       /* clear the accumulators before accumulating        */
 #define TLDA_RELEASE 0x4u     /* last: free the V x V accumulator, clear the counts */
+#define TLDA_REFRESH_WARM 0x8u  /* refresh W starting from the previous refresh    */
 
 /* Section "Computing the Centered Cumulants" and the batched implementation:
  * accumulates, over the kept documents of `batch` (may be NULL when only
@@ -153,6 +155,25 @@ const char* tlda_last_error(const tlda_ctx* ctx);
  * resident).  A later update allocates the accumulator again.
  * Accumulation uses FP64 atomics: sums are exact up to FP64 rounding order. */
 tlda_status tlda_update_moments(tlda_ctx* ctx, const tlda_csr_batch* batch, uint32_t flags);
+
+/* TLDA_REFRESH_WARM (fully online mode, section "Fully Online, Incremental
+ * Tensor LDA": the incremental PCA update after each new batch) refreshes W
+ * like TLDA_REFRESH_W but starts the block subspace iteration from the
+ * orthonormal block that the previous refresh of this context converged to,
+ * and runs cfg.eig_warm_iters iterations (default 4) before the Rayleigh-Ritz
+ * step: the running M2~ changes little per batch, so its dominant subspace is
+ * tracked at a fraction of a cold refresh's cost.  Without a previous refresh
+ * (or after tlda_load_state) it is a cold refresh.  Every refresh and every
+ * tlda_set_whitening keeps the whitening it replaces for tlda_rebase_phi. */
+
+/* Fully online mode: carry Phi [D][K] (device float, in place) from the
+ * whitened space of the previous whitening W_old into that of the current W,
+ * Phi <- W^T (W_old^T)^+ Phi = diag(eig)^(-1/2) U^T U_old diag(eig_old)^(1/2) Phi
+ * (the paper keeps Phi across whitening updates without saying how; this maps
+ * the factors' centred word-space vectors (W_old^T)^+ phi into the new
+ * whitened coordinates).  FP64 arithmetic; TLDA_ERR_STATE when the context
+ * has not replaced a whitening since it was created or loaded. */
+tlda_status tlda_rebase_phi(tlda_ctx* ctx, float* Phi);
 
 /* Whitened counts of the centred data (online second-moment section):
  * X[d, :] = W^T (f_d - M1) for kept rows, 0 for dropped rows.

@@ -80,6 +80,23 @@ __global__ void __launch_bounds__(256) k_classic_weights(const float* __restrict
   }
 }
 
+// One block per column k of Phi (D <= 256): the column is read into LDS,
+// then Phi[d][k] = eig[d]^(-1/2) sum_e C[d][e] eig_prev[e]^(1/2) phi[e].
+__global__ void __launch_bounds__(256) k_rebase(const double* __restrict__ C,
+                                                const double* __restrict__ eig,
+                                                const double* __restrict__ eig_prev, int D, int K,
+                                                float* __restrict__ Phi) {
+  __shared__ double col[256];
+  const int k = blockIdx.x, d = threadIdx.x;
+  if (d < D) col[d] = (double)Phi[d * K + k] * sqrt(eig_prev[d]);
+  __syncthreads();
+  if (d < D) {
+    double s = 0.0;
+    for (int e = 0; e < D; ++e) s += C[d * D + e] * col[e];
+    Phi[d * K + k] = (float)(s / sqrt(eig[d]));
+  }
+}
+
 // mu[i][k] = sum_d U[i][d] sqrt(eig[d]) phi[d][k] scale[k] + m[i] (m may be NULL)
 __global__ void k_mu(const float* __restrict__ Phi, const double* __restrict__ U,
                      const double* __restrict__ eig, const double* __restrict__ m,
@@ -289,6 +306,12 @@ hipError_t launch_unwhiten(const float* Phi, const double* U, const double* eig,
     e = hipGetLastError();
   }
   return e;
+}
+
+hipError_t launch_rebase(const double* C, const double* eig, const double* eig_prev, int D, int K,
+                         float* Phi, hipStream_t s) {
+  hipLaunchKernelGGL(k_rebase, dim3(K), dim3(256), 0, s, C, eig, eig_prev, D, K, Phi);
+  return hipGetLastError();
 }
 
 hipError_t launch_unwhiten_classic(const float* Phi, const double* U, const double* eig, int V,

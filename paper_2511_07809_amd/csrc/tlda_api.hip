@@ -219,28 +219,54 @@ tlda_status apply_m2(tlda_ctx* c, const double* Q, double* Y, double N) {
   return TLDA_OK;
 }
 
-tlda_status refresh(tlda_ctx* c) {
+// Keeps the current whitening (if any) as the one tlda_rebase_phi maps from.
+tlda_status save_prev(tlda_ctx* c) {
+  if (!c->wh.ready) return TLDA_OK;
+  const size_t V = c->cfg.V, D = c->cfg.D;
+  if (c->wh.Uprev == nullptr) {
+    HIP_OK(c, dalloc(&c->wh.Uprev, V * D));
+    HIP_OK(c, dalloc(&c->wh.eigprev, D));
+    HIP_OK(c, dalloc(&c->wh.C, D * D));
+  }
+  HIP_OK(c, hipMemcpyAsync(c->wh.Uprev, c->wh.U, sizeof(double) * V * D, hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIP_OK(c, hipMemcpyAsync(c->wh.eigprev, c->wh.eig, sizeof(double) * D, hipMemcpyDeviceToDevice,
+                           c->stream));
+  c->wh.prev_ready = true;
+  return TLDA_OK;
+}
+
+// warm: start from the block the previous refresh converged to (if any) and
+// run cfg.eig_warm_iters iterations instead of a seeded cold start.
+tlda_status refresh(tlda_ctx* c, bool warm) {
   const int V = c->cfg.V, D = c->cfg.D;
   unsigned long long counts[2] = {0, 0};
   HIP_OK(c, hipMemcpyAsync(counts, c->mom.counts, sizeof(counts), hipMemcpyDeviceToHost, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   CHECK_ARG(c, counts[0] > 0, TLDA_ERR_NUMERIC, "no kept documents: M1 and M2 are undefined");
   const int p = c->cfg.eig_block > 0 ? c->cfg.eig_block : default_block(c->cfg);
-  const int iters = c->cfg.eig_iters > 0 ? c->cfg.eig_iters : 60;
   tlda_status st = ensure_eig(c, p);
   if (st != TLDA_OK) return st;
   tlda::EigScratch& e = c->eig;
+  warm = warm && e.warm != nullptr;
+  const int iters = warm ? (c->cfg.eig_warm_iters > 0 ? c->cfg.eig_warm_iters : 4)
+                         : (c->cfg.eig_iters > 0 ? c->cfg.eig_iters : 60);
   const double N = (double)counts[0];
   HIP_OK(c, launch_zero(e.info, 4 * sizeof(int), c->stream));
   HIP_OK(c, tlda::launch_mean(c->mom.fsum, c->mom.counts, e.mcand, V, c->stream));
   HIP_OK(c, tlda::launch_mirror_upper(c->mom.S2, V, c->stream));
-  // start block: seeded uniform entries, orthonormalised (y -> tmp q -> y)
   double* q = e.Q;
   double* y = e.Y;
-  HIP_OK(c, tlda::launch_random_block(y, V, p, c->cfg.eig_seed, c->stream));
-  st = orthonormalise(c, y, q, y);
-  if (st != TLDA_OK) return st;
-  std::swap(q, y);   // q: orthonormal block
+  if (warm) {
+    // start block: the orthonormal block of the previous refresh
+    if (e.warm != q) std::swap(q, y);
+  } else {
+    // start block: seeded uniform entries, orthonormalised (y -> tmp q -> y)
+    HIP_OK(c, tlda::launch_random_block(y, V, p, c->cfg.eig_seed, c->stream));
+    st = orthonormalise(c, y, q, y);
+    if (st != TLDA_OK) return st;
+    std::swap(q, y);   // q: orthonormal block
+  }
   for (int it = 0; it < iters; ++it) {
     st = apply_m2(c, q, y, N);
     if (st != TLDA_OK) return st;
@@ -265,7 +291,10 @@ tlda_status refresh(tlda_ctx* c) {
   for (int d = 0; d < D; ++d)
     CHECK_ARG(c, std::isfinite(eigD[d]) && eigD[d] > 0.0, TLDA_ERR_NUMERIC,
               "M2~ has fewer than D positive eigenvalues; lower D");
-  // commit
+  // commit (q, the converged orthonormal block, is the next warm start)
+  st = save_prev(c);
+  if (st != TLDA_OK) return st;
+  e.warm = q;
   HIP_OK(c, hipMemcpyAsync(c->wh.U, y, sizeof(double) * (size_t)V * D, hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(c, hipMemcpyAsync(c->wh.eig, e.sel, sizeof(double) * D, hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(c, hipMemcpyAsync(c->wh.m, e.mcand, sizeof(double) * V, hipMemcpyDeviceToDevice, c->stream));
@@ -331,6 +360,7 @@ void destroy_all(tlda_ctx* c) {
   dfree(c->mom.counts); dfree(c->mom.totals); dfree(c->mom.fsum); dfree(c->mom.S2);
   dfree(c->wh.W); dfree(c->wh.U); dfree(c->wh.eig); dfree(c->wh.m); dfree(c->wh.W32);
   dfree(c->wh.mw32); dfree(c->wh.W16); dfree(c->wh.mw16);
+  dfree(c->wh.Uprev); dfree(c->wh.eigprev); dfree(c->wh.C);
   delete[] c->t_start;
   delete[] c->t_stop;
   tlda::EigScratch& e = c->eig;
@@ -449,8 +479,10 @@ void tlda_destroy(tlda_ctx* ctx) { destroy_all(ctx); }
 
 tlda_status tlda_update_moments(tlda_ctx* c, const tlda_csr_batch* b, uint32_t flags) {
   if (!c) return TLDA_ERR_ARG;
-  CHECK_ARG(c, (flags & ~(TLDA_REFRESH_W | TLDA_RESET | TLDA_RELEASE)) == 0, TLDA_ERR_ARG,
-            "unknown flags");
+  CHECK_ARG(c,
+            (flags & ~(TLDA_REFRESH_W | TLDA_RESET | TLDA_RELEASE | TLDA_REFRESH_WARM)) == 0,
+            TLDA_ERR_ARG, "unknown flags");
+  if (flags & TLDA_REFRESH_WARM) flags |= TLDA_REFRESH_W;
   CHECK_ARG(c, b != nullptr || (flags & (TLDA_REFRESH_W | TLDA_RESET | TLDA_RELEASE)),
             TLDA_ERR_ARG,
             "batch is NULL and no refresh or reset was requested");
@@ -481,7 +513,7 @@ tlda_status tlda_update_moments(tlda_ctx* c, const tlda_csr_batch* b, uint32_t f
     if (st != TLDA_OK) return st;
   }
   if (flags & TLDA_REFRESH_W) {
-    st = refresh(c);
+    st = refresh(c, (flags & TLDA_REFRESH_WARM) != 0);
     if (st != TLDA_OK) return st;
   }
   if (flags & TLDA_RELEASE) {
@@ -753,12 +785,25 @@ tlda_status tlda_set_whitening(tlda_ctx* c, const double* W, const double* M1) {
     for (int i = 0; i < V; ++i) s += W[(size_t)i * D + d] * W[(size_t)i * D + d];
     CHECK_ARG(c, s > 0.0, TLDA_ERR_NUMERIC, "W has a zero column");
   }
+  tlda_status st = save_prev(c);
+  if (st != TLDA_OK) return st;
   HIP_OK(c, hipMemcpyAsync(c->wh.W, W, sizeof(double) * (size_t)V * D, hipMemcpyHostToDevice, c->stream));
   HIP_OK(c, hipMemcpyAsync(c->wh.m, M1, sizeof(double) * V, hipMemcpyHostToDevice, c->stream));
   HIP_OK(c, tlda::launch_from_injected(c->wh.W, V, D, c->wh.U, c->wh.eig, c->stream));
   HIP_OK(c, form_whitening(c));
   HIP_OK(c, hipStreamSynchronize(c->stream));
   c->wh.ready = true;
+  return TLDA_OK;
+}
+
+tlda_status tlda_rebase_phi(tlda_ctx* c, float* Phi) {
+  if (!c) return TLDA_ERR_ARG;
+  CHECK_ARG(c, Phi != nullptr, TLDA_ERR_ARG, "Phi is NULL");
+  CHECK_ARG(c, c->wh.ready && c->wh.prev_ready, TLDA_ERR_STATE,
+            "no previous whitening to rebase from");
+  const int V = c->cfg.V, D = c->cfg.D, K = c->cfg.K;
+  HIP_OK(c, tlda::launch_gram(c->wh.U, c->wh.Uprev, c->wh.C, V, D, c->stream));
+  HIP_OK(c, tlda::launch_rebase(c->wh.C, c->wh.eig, c->wh.eigprev, D, K, Phi, c->stream));
   return TLDA_OK;
 }
 
@@ -1367,6 +1412,8 @@ tlda_status tlda_load_state(tlda_ctx* c, const void* buf, size_t len) {
   }
   HIP_OK(c, hipStreamSynchronize(c->stream));
   c->wh.ready = h.ready != 0;
+  c->wh.prev_ready = false;
+  c->eig.warm = nullptr;
   return TLDA_OK;
 }
 

@@ -53,6 +53,11 @@ struct Whitening {
   float* mw32 = nullptr;   // [Dp], W^T M1
   uint16_t* W16 = nullptr; // [V][Dh] BF16 bits of fp32(W) (BF16 contexts only)
   float* mw16 = nullptr;   // [Dh], W16^T M1 from the rounded values
+  // the whitening this one replaced (for tlda_rebase_phi)
+  bool prev_ready = false;
+  double* Uprev = nullptr;   // [V][D]
+  double* eigprev = nullptr; // [D]
+  double* C = nullptr;       // [D][D] U^T Uprev
 };
 
 struct EigScratch {
@@ -67,6 +72,7 @@ struct EigScratch {
   double* sel = nullptr;   // [D + p*D] selected Ritz values and vectors
   double* mcand = nullptr; // [V]     M1 of the refresh in progress
   int* info = nullptr;     // [4]     device status words
+  double* warm = nullptr;  // Q or Y: the orthonormal block the last refresh converged to
 };
 
 // Launch-shape knobs (0 = built-in choice).  Initialised from the
@@ -319,6 +325,9 @@ hipError_t launch_unwhiten(const float* Phi, const double* U, const double* eig,
 hipError_t launch_unwhiten_classic(const float* Phi, const double* U, const double* eig, int V,
                                    int D, int K, double theta, uint32_t flags, double* mu,
                                    double* alpha, double* lambda, double* scratch, hipStream_t s);
+// Phi[:, k] <- diag(eig)^(-1/2) C diag(eig_prev)^(1/2) Phi[:, k] (FP64 sums)
+hipError_t launch_rebase(const double* C, const double* eig, const double* eig_prev, int D, int K,
+                         float* Phi, hipStream_t s);
 hipError_t launch_inference_setup(const double* W, const double* m, const double* mu, int V,
                                   int D, int K, double* A, double* G, double* Z, double* ev,
                                   float* A32, float* G32, float* step32, int* info,

@@ -26,6 +26,7 @@ TLDA_CLASSIC = 0x4
 TLDA_REFRESH_W = 0x1
 TLDA_RESET = 0x2
 TLDA_RELEASE = 0x4
+TLDA_REFRESH_WARM = 0x8
 TLDA_PROJECT_SIMPLEX = 0x1
 TLDA_MAX_D = 256
 TLDA_MAX_K = 256
@@ -36,7 +37,8 @@ EXPORTED = ("tlda_create", "tlda_destroy", "tlda_status_str", "tlda_last_error",
             "tlda_update_moments", "tlda_whiten_batch", "tlda_cp_step", "tlda_whiten_cp_step",
             "tlda_unwhiten",
             "tlda_infer_doc_topics", "tlda_stage_batch", "tlda_get_stats",
-            "tlda_get_whitening", "tlda_set_whitening", "tlda_set_timing_events",
+            "tlda_get_whitening", "tlda_set_whitening", "tlda_rebase_phi",
+            "tlda_set_timing_events",
             "tlda_save_state", "tlda_load_state",
             "tlda_mlp_param_count", "tlda_mlp_create", "tlda_mlp_destroy", "tlda_mlp_last_error",
             "tlda_mlp_set_params", "tlda_mlp_get_params", "tlda_mlp_forward",
@@ -51,7 +53,8 @@ class tlda_config(ctypes.Structure):
     _fields_ = [("V", ctypes.c_int32), ("K", ctypes.c_int32), ("D", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("alpha0", ctypes.c_double),
                 ("theta", ctypes.c_double), ("eig_iters", ctypes.c_int32),
-                ("eig_block", ctypes.c_int32), ("eig_seed", ctypes.c_uint64)]
+                ("eig_block", ctypes.c_int32), ("eig_seed", ctypes.c_uint64),
+                ("eig_warm_iters", ctypes.c_int32)]
 
 
 class tlda_csr_batch(ctypes.Structure):
@@ -83,6 +86,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tlda_get_stats": ([vp, vp, vp, vp], i32),
         "tlda_get_whitening": ([vp, vp, vp, vp], i32),
         "tlda_set_whitening": ([vp, vp, vp], i32),
+        "tlda_rebase_phi": ([vp, vp], i32),
         "tlda_set_timing_events": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32], i32),
         "tlda_save_state": ([vp, vp, ctypes.POINTER(ctypes.c_size_t)], i32),
         "tlda_mlp_param_count": ([i32, i32, i32], ctypes.c_int64),
@@ -205,7 +209,7 @@ class _StagedBatch(CsrBatch):
 # ---------------------------------------------------------------------------
 def tlda_create(V: int, K: int, D: int, alpha0: float, theta: float = 0.0, *,
                 validate_csr: bool = False, bf16: bool = False, classic: bool = False,
-                eig_iters: int = 0,
+                eig_iters: int = 0, eig_warm_iters: int = 0,
                 eig_block: int = 0, eig_seed: int = 0,
                 stream: Optional[torch.cuda.Stream] = None) -> Context:
     if not torch.cuda.is_available():
@@ -213,7 +217,8 @@ def tlda_create(V: int, K: int, D: int, alpha0: float, theta: float = 0.0, *,
     stream = stream or torch.cuda.current_stream()
     flags = ((TLDA_VALIDATE_CSR if validate_csr else 0) | (TLDA_BF16 if bf16 else 0)
              | (TLDA_CLASSIC if classic else 0))
-    cfg = tlda_config(V, K, D, flags, float(alpha0), float(theta), eig_iters, eig_block, eig_seed)
+    cfg = tlda_config(V, K, D, flags, float(alpha0), float(theta), eig_iters, eig_block, eig_seed,
+                      eig_warm_iters)
     h = ctypes.c_void_p()
     _check(None, _LIB.tlda_create(ctypes.byref(cfg), ctypes.c_void_p(stream.cuda_stream),
                                   ctypes.byref(h)))
@@ -308,6 +313,11 @@ def tlda_set_whitening(ctx: Context, W, M1) -> None:
     M1 = np.ascontiguousarray(M1, dtype=np.float64)
     assert W.shape == (ctx.V, ctx.D) and M1.shape == (ctx.V,)
     _check(ctx, _LIB.tlda_set_whitening(ctx.handle, W.ctypes.data, M1.ctypes.data))
+
+
+def tlda_rebase_phi(ctx: Context, Phi: torch.Tensor) -> None:
+    assert Phi.dtype == torch.float32 and Phi.is_contiguous() and Phi.numel() == ctx.D * ctx.K
+    _check(ctx, _LIB.tlda_rebase_phi(ctx.handle, _ptr(Phi)))
 
 
 def tlda_set_timing_events(ctx: Context, starts, stops) -> None:

@@ -61,7 +61,7 @@ def test_create_validates_config_before_touching_a_device(lib):
     out = ctypes.c_void_p()
 
     def create(V, K, D, flags, alpha0=1.0, theta=0.0):
-        cfg = tlda.tlda_config(V, K, D, flags, alpha0, theta, 0, 0, 0)
+        cfg = tlda.tlda_config(V, K, D, flags, alpha0, theta, 0, 0, 0, 0)
         return lib.tlda_create(ctypes.byref(cfg), None, ctypes.byref(out))
 
     assert create(100, 10, 10, 0x8) == 1                       # unknown flag
@@ -86,9 +86,10 @@ def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "tlda.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(tlda_config),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(tlda_config),"
         " offsetof(tlda_config, alpha0), offsetof(tlda_config, eig_iters),"
-        " offsetof(tlda_config, eig_seed), sizeof(tlda_csr_batch),"
+        " offsetof(tlda_config, eig_seed), offsetof(tlda_config, eig_warm_iters),"
+        " sizeof(tlda_csr_batch),"
         " offsetof(tlda_csr_batch, row_ptr), offsetof(tlda_csr_batch, slot));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
@@ -98,7 +99,8 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_2511_07809_amd import tlda
     cfg, b = tlda.tlda_config, tlda.tlda_csr_batch
     assert got == [ctypes.sizeof(cfg), cfg.alpha0.offset, cfg.eig_iters.offset,
-                   cfg.eig_seed.offset, ctypes.sizeof(b), b.row_ptr.offset, b.slot.offset]
+                   cfg.eig_seed.offset, cfg.eig_warm_iters.offset, ctypes.sizeof(b),
+                   b.row_ptr.offset, b.slot.offset]
 
 
 def test_header_compiles_as_c_and_cxx(tmp_path):
