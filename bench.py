@@ -9,8 +9,13 @@ arithmetic; the other precision is timed beside it on the same whitening.
 The moment pass and the whitening refresh that precede the CP passes are run
 and timed in the same process and reported beside the steps.  Inputs are
 resident in HBM before timing starts (--streamed: staged from pinned host
-memory inside the timed region).  An untimed fit of both precisions from the
-same start reports their topic-recovery errors after the same passes.
+memory inside the timed region).  The K timed steps run twice: eagerly, one
+library call per step, with events attached to each main kernel's dispatch
+(the kernel times of the roofline), and as one captured HIP graph of the same
+K steps (tlda_graph_capture_steps), whose time gives `value` for the fused
+path over resident batches (eager otherwise).  An untimed fit of both
+precisions from the same start reports their topic-recovery errors after the
+same passes.
 
 Prints one JSON line (see the keys below).  --gpus > 1 is not supported: this
 build runs on one GPU.
@@ -65,6 +70,12 @@ def parse():
     ap.add_argument("--estimator", default="centred", choices=["centred", "classic"],
                     help="classic: the alpha0-corrected moments (FP32 classic-moment context) "
                          "on c1, c2 or c3")
+    ap.add_argument("--online", action="store_true",
+                    help="fully online mode on c1, c2 or c3: after a batched start on the first "
+                         "batch, every step is moments + warm whitening refresh + Phi rebase + "
+                         "whitening and CP step of a new batch")
+    ap.add_argument("--warm-iters", type=int, default=4,
+                    help="subspace iterations of each warm refresh in --online")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -239,6 +250,81 @@ def run_classic(args) -> None:
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle of the classic rung on a bounded sample")
         out["cpu_baseline"] = classic_cpu_baseline(corpus, spec, batches, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def run_online(args) -> None:
+    """Fully online mode: moments, warm-started whitening refresh, Phi rebase
+    and one whitening + CP step per new batch, timed per stage."""
+    import numpy as np
+    import torch
+
+    from paper_2511_07809_amd import tlda as tl
+    from synth import SPECS, generate, init_phi, iter_batches
+
+    spec = SPECS[args.workload]
+    D = K = spec.K
+    corpus = generate(spec, n_docs=args.docs or None)
+    batches = list(iter_batches(corpus))
+    log(f"[bench] generated {spec.name}: {corpus.n_docs} docs, {len(batches)} batches")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    bf16 = args.precision == "bf16"
+    ctx = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, bf16=bf16, eig_iters=60,
+                         eig_warm_iters=args.warm_iters)
+    dev = [tl.CsrBatch.from_numpy(rp, ci, va) for rp, ci, va, _ in batches]
+    beta = args.beta if args.beta is not None else (0.03 if spec.name == "c1" else 1e-3)
+    # batched start on the first batch
+    tl.tlda_update_moments(ctx, dev[0], tl.TLDA_REFRESH_W)
+    Phi = torch.from_numpy(init_phi(D, K, 1).astype(np.float32)).cuda()
+    for _ in range(3):
+        tl.tlda_whiten_cp_step(ctx, dev[0], beta, Phi)
+    torch.cuda.synchronize()
+
+    def one(i, ev=None):
+        b = dev[1 + i % (len(dev) - 1)] if len(dev) > 1 else dev[0]
+        if ev:
+            ev[0].record(stream)
+        tl.tlda_update_moments(ctx, b, tl.TLDA_REFRESH_WARM)
+        if ev:
+            ev[1].record(stream)
+        tl.tlda_rebase_phi(ctx, Phi)
+        if ev:
+            ev[2].record(stream)
+        tl.tlda_whiten_cp_step(ctx, b, beta, Phi)
+        if ev:
+            ev[3].record(stream)
+        return b
+
+    for i in range(args.warmup):
+        one(i)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    docs = 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        docs += one(args.warmup + i, evs[i]).n_rows
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = evs[0][0].elapsed_time(evs[-1][3])
+    stage = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(3)] for e in evs]).mean(axis=0)
+    out = {
+        "metric": "docs/sec (whiten+CP step) at fixed topic-recovery error; % HBM roofline",
+        "value": docs / (total_ms / 1e3), "unit": "docs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total_ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if bf16 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{spec.name} fully online: V={spec.V}, K=D={K}, "
+                               f"alpha0={spec.alpha0}, batch {spec.batch}, per step moments + "
+                               f"warm refresh ({args.warm_iters} iterations) + rebase + "
+                               "whitening and CP step, resident in HBM",
+                   "mode": "online", "global_batch": spec.batch, "beta": beta},
+        "roofline": None,
+        "breakdown": {"moments_and_warm_refresh_ms": float(stage[0]),
+                      "rebase_ms": float(stage[1]), "whiten_cp_step_ms": float(stage[2]),
+                      "wall_ms": wall * 1e3},
+    }
+    log(f"[bench] online: {out['breakdown']}")
     print(json.dumps(out), flush=True)
 
 
@@ -640,6 +726,9 @@ def main():
     if args.estimator == "classic":
         run_classic(args)
         return
+    if args.online:
+        run_online(args)
+        return
     import numpy as np
     import torch
 
@@ -655,9 +744,11 @@ def main():
         f"{len(batches)} batches in {time.time() - t:.1f}s")
 
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
+    # a stream of its own (default priority): the null stream cannot be captured
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
     bf16 = args.precision == "bf16"
-    ctx = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, bf16=bf16, eig_iters=60)
+    ctx = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, bf16=bf16, eig_iters=60, stream=stream)
     dev = [tl.CsrBatch.from_numpy(rp, ci, va) for rp, ci, va, _ in batches]
     torch.cuda.synchronize()
 
@@ -675,7 +766,7 @@ def main():
     log(f"[bench] moment pass {moments_ms:.2f} ms, refresh {refresh_ms:.1f} ms")
     # the other precision on the same whitening, for the side-by-side figures
     W, _, m = tl.tlda_get_whitening(ctx)
-    other = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, bf16=not bf16)
+    other = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, bf16=not bf16, stream=stream)
     tl.tlda_set_whitening(other, W, m)
     del W
 
@@ -714,8 +805,31 @@ def main():
         log(f"[bench] {name} {args.path}: {args.steps} steps {r['total_ms']:.3f} ms "
             f"(wall {r['wall_ms']:.1f} ms), step {r['step_ms'].mean() * 1e3:.1f} us, main "
             f"kernel(s) {' + '.join(f'{x:.1f}' for x in km)} us, {r['docs_per_s']:.4g} docs/s")
+    # the same K steps as one captured HIP graph (no host launch gaps); the
+    # kernels and their launch shapes are those of the eager steps above
+    graph_runs = {}
+    if fused and not args.streamed:
+        for name, cx in ((args.precision, ctx), ("fp32" if bf16 else "bf16", other)):
+            steps_b = [dev[(args.warmup + i) % len(dev)] for i in range(args.steps)]
+            Phi = torch.from_numpy(init_phi(D, K, 1).astype(np.float32)).cuda()
+            torch.cuda.synchronize()
+            g = tl.tlda_graph_capture_steps(cx, steps_b, beta, Phi)
+            tl.tlda_graph_launch(g)                  # untimed replay
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            tl.tlda_graph_launch(g)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            graph_runs[name] = {"total_ms": ms,
+                                "docs_per_s": sum(b.n_rows for b in steps_b) / (ms / 1e3)}
+            log(f"[bench] {name} graph of {args.steps} steps: {ms:.3f} ms, "
+                f"{graph_runs[name]['docs_per_s']:.4g} docs/s")
+            del g
     main_run = runs[args.precision]
     K_steps = args.steps
+    main_graph = graph_runs.get(args.precision)
 
     # ---- roofline of the dominant kernel, on its own launch duration ----
     docs, nnz_tot = main_run["docs"], main_run["nnz"]
@@ -783,8 +897,9 @@ def main():
     other_name = "fp32" if bf16 else "bf16"
     out = {
         "metric": "docs/sec (whiten+CP step) at fixed topic-recovery error; % HBM roofline",
-        "value": main_run["docs_per_s"], "unit": "docs/s", "n_gpus": 1, "steps": K_steps,
-        "warmup": args.warmup, "ms_per_step": main_run["total_ms"] / K_steps,
+        "value": (main_graph or main_run)["docs_per_s"], "unit": "docs/s", "n_gpus": 1,
+        "steps": K_steps, "warmup": args.warmup,
+        "ms_per_step": (main_graph or main_run)["total_ms"] / K_steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16" if bf16 else "f32", "data": "synthetic",
         "config": {"workload": f"{spec.name}: V={spec.V}, K=D={K}, alpha0={spec.alpha0}, "
@@ -793,9 +908,15 @@ def main():
                                + ("streamed from pinned host memory" if args.streamed
                                   else "resident in HBM"),
                    "streamed": bool(args.streamed), "precision": args.precision,
-                   "global_batch": spec.batch, "beta": beta, "path": args.path},
+                   "global_batch": spec.batch, "beta": beta, "path": args.path,
+                   "launch": "hip_graph" if main_graph else "eager"},
         "roofline": roof,
-        "breakdown": {"path": args.path, "step_us": float(main_run["step_ms"].mean()) * 1e3,
+        "breakdown": {"path": args.path,
+                      "eager_docs_per_s": main_run["docs_per_s"],
+                      "graph_docs_per_s": main_graph["docs_per_s"] if main_graph else None,
+                      f"{other_name}_graph_docs_per_s":
+                          graph_runs[other_name]["docs_per_s"] if other_name in graph_runs else None,
+                      "step_us": float(main_run["step_ms"].mean()) * 1e3,
                       "main_kernel_us": [float(x) for x in kern_us],
                       f"{other_name}_docs_per_s": runs[other_name]["docs_per_s"],
                       f"{other_name}_step_us": float(runs[other_name]["step_ms"].mean()) * 1e3,

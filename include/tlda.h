@@ -355,6 +355,18 @@ tlda_status tlda_multi_autotune(tlda_multi* plan, int32_t reps, int32_t* total_b
  * shared stream; tlda_graph_launch replays it (asynchronous).  A plan's
  * launch shape is frozen into the graph when it is captured. */
 tlda_status tlda_graph_capture(tlda_multi* const* plans, int32_t n_plans, tlda_graph** out);
+/* Capture n fused steps of one context, tlda_whiten_cp_step(ctx,
+ * &batches[i], beta, Phi, NULL, NULL, NULL) for i = 0 .. n-1 in order, as one
+ * HIP graph on the context's stream (a launch-bound pass over resident
+ * batches then costs one launch).  The batches must be device batches
+ * (slot < 0) that stay allocated while the graph lives; with
+ * TLDA_VALIDATE_CSR they are validated once, before the capture.  Supported
+ * for BF16 contexts and FP32 contexts within the fused kernel's shapes (D, K
+ * <= 64), not classic ones (TLDA_ERR_SHAPE / TLDA_ERR_ARG); TLDA_ERR_ARG for a
+ * context on the null stream.  Synchronous; the timing hook does not apply
+ * to the captured launches. */
+tlda_status tlda_graph_capture_steps(tlda_ctx* ctx, const tlda_csr_batch* batches, int32_t n,
+                                     float beta, float* Phi, tlda_graph** out);
 tlda_status tlda_graph_launch(tlda_graph* graph);
 void tlda_graph_destroy(tlda_graph* graph);
 

@@ -78,7 +78,7 @@ hipError_t form_whitening(tlda_ctx* c) {
 // The next event pair of the timing hook goes to the next main-kernel launch.
 hipError_t timing_start(tlda_ctx* c) {
   tlda::g_main_timer = tlda::KernelTimer{};
-  if (c->t_n <= 0) return hipSuccess;
+  if (c->t_n <= 0 || c->in_capture) return hipSuccess;
   tlda::g_main_timer.start = c->t_start[c->t_next];
   tlda::g_main_timer.stop = c->t_stop[c->t_next];
   return hipSuccess;
@@ -86,7 +86,7 @@ hipError_t timing_start(tlda_ctx* c) {
 
 hipError_t timing_stop(tlda_ctx* c) {
   tlda::g_main_timer = tlda::KernelTimer{};
-  if (c->t_n <= 0) return hipSuccess;
+  if (c->t_n <= 0 || c->in_capture) return hipSuccess;
   c->t_next = (c->t_next + 1) % c->t_n;
   return hipSuccess;
 }
@@ -143,7 +143,7 @@ tlda_status check_batch(tlda_ctx* c, const tlda_csr_batch* b) {
 
 // Optional CSR content validation: synchronous, before any state changes.
 tlda_status validate_content(tlda_ctx* c, const tlda_csr_batch* b) {
-  if (!(c->cfg.flags & TLDA_VALIDATE_CSR) || b->n_rows == 0) return TLDA_OK;
+  if (!(c->cfg.flags & TLDA_VALIDATE_CSR) || b->n_rows == 0 || c->in_capture) return TLDA_OK;
   if (b->slot >= 0) HIP_OK(c, hipStreamWaitEvent(c->stream, c->slots[b->slot].ready, 0));
   HIP_OK(c, launch_zero(c->dev_flags, sizeof(int), c->stream));
   HIP_OK(c, tlda::launch_validate_csr(*b, c->cfg.V, c->dev_flags, c->stream));
@@ -1311,6 +1311,70 @@ tlda_status tlda_graph_capture(tlda_multi* const* plans, int32_t n_plans, tlda_g
     if (g->graph) hipGraphDestroy(g->graph);
     delete g;
     return st != TLDA_OK ? st : TLDA_ERR_DEVICE;
+  }
+  *out = g;
+  return TLDA_OK;
+}
+
+tlda_status tlda_graph_capture_steps(tlda_ctx* c, const tlda_csr_batch* batches, int32_t n,
+                                     float beta, float* Phi, tlda_graph** out) {
+  if (!out) return TLDA_ERR_ARG;
+  *out = nullptr;
+  if (!c) return TLDA_ERR_ARG;
+  CHECK_ARG(c, n >= 1 && batches != nullptr && Phi != nullptr, TLDA_ERR_ARG,
+            "need at least one batch, and Phi");
+  CHECK_ARG(c, c->stream != nullptr, TLDA_ERR_ARG, "the null stream cannot be captured");
+  CHECK_ARG(c, !is_classic(c), TLDA_ERR_ARG, "classic-moment steps are not captured");
+  const int D = c->cfg.D, K = c->cfg.K;
+  CHECK_ARG(c, is_bf16(c) || tlda::fused_supported(D, K, c->Dp), TLDA_ERR_SHAPE,
+            "FP32 steps above the fused kernel's shapes are not captured");
+  CHECK_ARG(c, c->wh.ready, TLDA_ERR_STATE, "no whitening matrix yet");
+  CHECK_ARG(c, std::isfinite(beta), TLDA_ERR_ARG, "beta is not finite");
+  // everything that may synchronise or allocate happens before the capture:
+  // argument and content checks, and the largest partial buffer
+  int max_rows = 0;
+  for (int i = 0; i < n; ++i) {
+    tlda_status st = check_batch(c, &batches[i]);
+    if (st != TLDA_OK) return st;
+    CHECK_ARG(c, batches[i].slot < 0, TLDA_ERR_ARG, "staged batches are not captured");
+    st = validate_content(c, &batches[i]);
+    if (st != TLDA_OK) return st;
+    max_rows = std::max(max_rows, (int)batches[i].n_rows);
+  }
+  size_t need = 0;
+  if (is_bf16(c)) {
+    need = (size_t)bf16_grid(c, 0, max_rows) * D * K;
+  } else {
+    if (c->tune.fused_blocks <= 0) {
+      int per_cu = 0;
+      HIP_OK(c, tlda::launch_whiten_cp(batches[0], c->wh.W32, c->wh.mw32, D, c->Dp, Phi, K, 0,
+                                       nullptr, &per_cu, nullptr, nullptr, c->stream));
+      c->tune.fused_blocks = (per_cu > 0 ? per_cu : 1) * c->num_cu;
+    }
+    int nblk = std::min(c->tune.fused_blocks, 2 * tlda::kWhitenBlockCounts);
+    need = (size_t)nblk * D * K;
+  }
+  tlda_status st = ensure_partial(c, need);
+  if (st != TLDA_OK) return st;
+  HIP_OK(c, hipStreamSynchronize(c->stream));
+  tlda_graph* g = new (std::nothrow) tlda_graph();
+  if (!g) return TLDA_ERR_OOM;
+  g->stream = c->stream;
+  if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    delete g;
+    CHECK_ARG(c, false, TLDA_ERR_DEVICE, "could not begin a capture on the context's stream");
+  }
+  c->in_capture = true;
+  for (int i = 0; i < n && st == TLDA_OK; ++i)
+    st = tlda_whiten_cp_step(c, &batches[i], beta, Phi, nullptr, nullptr, nullptr);
+  c->in_capture = false;
+  hipError_t e = hipStreamEndCapture(c->stream, &g->graph);
+  if (st != TLDA_OK || e != hipSuccess ||
+      hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+    if (g->graph) hipGraphDestroy(g->graph);
+    delete g;
+    if (st != TLDA_OK) return st;
+    CHECK_ARG(c, false, TLDA_ERR_DEVICE, "graph capture or instantiation failed");
   }
   *out = g;
   return TLDA_OK;

@@ -135,6 +135,7 @@ struct tlda_ctx {
   hipEvent_t* t_start = nullptr;
   hipEvent_t* t_stop = nullptr;
   int t_n = 0, t_next = 0;
+  bool in_capture = false;    // capturing a graph of steps: no validation, no timing hook
   std::string last_error;
 };
 

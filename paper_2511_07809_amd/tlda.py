@@ -45,7 +45,8 @@ EXPORTED = ("tlda_create", "tlda_destroy", "tlda_status_str", "tlda_last_error",
             "tlda_mlp_gradients", "tlda_mlp_train_step", "tlda_infer_doc_topics_mlp",
             "tlda_multi_create", "tlda_multi_destroy", "tlda_multi_last_error",
             "tlda_multi_set_blocks", "tlda_multi_get_blocks", "tlda_multi_step",
-            "tlda_multi_autotune", "tlda_graph_capture", "tlda_graph_launch",
+            "tlda_multi_autotune", "tlda_graph_capture", "tlda_graph_capture_steps",
+            "tlda_graph_launch",
             "tlda_graph_destroy")
 
 
@@ -100,6 +101,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tlda_multi_step": ([vp], i32),
         "tlda_multi_autotune": ([vp, i32, ctypes.POINTER(i32)], i32),
         "tlda_graph_capture": ([ctypes.POINTER(vp), i32, ctypes.POINTER(vp)], i32),
+        "tlda_graph_capture_steps": ([vp, vp, i32, ctypes.c_float, vp, ctypes.POINTER(vp)], i32),
         "tlda_graph_launch": ([vp], i32),
         "tlda_graph_destroy": ([vp], None),
         "tlda_mlp_create": ([i32, i32, i32, i32, vp, ctypes.POINTER(vp)], i32),
@@ -519,6 +521,17 @@ def tlda_graph_capture(plans) -> Graph:
     if st != TLDA_OK:
         raise TldaError(st, _LIB.tlda_status_str(st).decode())
     return Graph(h.value, list(plans))
+
+
+def tlda_graph_capture_steps(ctx: Context, batches, beta: float, Phi: torch.Tensor) -> Graph:
+    """One HIP graph of len(batches) fused steps of ctx (device batches)."""
+    assert Phi.dtype == torch.float32 and Phi.is_contiguous() and Phi.numel() == ctx.D * ctx.K
+    n = len(batches)
+    arr = (tlda_csr_batch * n)(*[b.struct() for b in batches])
+    h = ctypes.c_void_p()
+    _check(ctx, _LIB.tlda_graph_capture_steps(ctx.handle, arr, n, float(beta), _ptr(Phi),
+                                              ctypes.byref(h)))
+    return Graph(h.value, [ctx, list(batches), Phi])
 
 
 def tlda_graph_launch(g: Graph) -> None:

@@ -209,3 +209,60 @@ def test_release_frees_the_accumulator_and_keeps_the_whitening(side_stream):
     X2, _ = tl.tlda_whiten_batch(ctx, b)
     side_stream.synchronize()
     assert rel(X1.cpu().numpy(), X2.cpu().numpy()) < 1e-6
+
+
+@pytest.mark.parametrize("bf16,D,K", [(True, 50, 50), (True, 20, 10), (False, 50, 50),
+                                      (False, 7, 5)])
+def test_captured_steps_of_one_context_match_eager(side_stream, bf16, D, K):
+    rng = np.random.default_rng(D + K)
+    Q, _ = np.linalg.qr(rng.standard_normal((V, D)))
+    W = Q * rng.uniform(5, 30, size=D)[None, :]
+    m = rng.dirichlet(np.ones(V))
+    ctx = tl.tlda_create(V, K, D, 1.0, 0.5, bf16=bf16, validate_csr=True, stream=side_stream)
+    tl.tlda_set_whitening(ctx, W, m)
+    batches = [tl.CsrBatch.from_numpy(*_rows(n, 900 + n)) for n in (2500, 1, 777)]
+    Phi0 = (init_phi(D, K, 3) * 0.9).astype(np.float32)
+    beta = 2e-3
+    Pe = torch.from_numpy(Phi0).cuda()
+    torch.cuda.synchronize()
+    eager = []
+    for _ in range(3):
+        for b in batches:
+            tl.tlda_whiten_cp_step(ctx, b, beta, Pe)
+        side_stream.synchronize()
+        eager.append(Pe.cpu().numpy().copy())
+    Pg = torch.from_numpy(Phi0).cuda()
+    torch.cuda.synchronize()
+    g = tl.tlda_graph_capture_steps(ctx, batches, beta, Pg)
+    for r in range(3):
+        tl.tlda_graph_launch(g)
+        side_stream.synchronize()
+        junk = torch.randn(4096, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        assert np.array_equal(Pg.cpu().numpy(), eager[r]), r
+
+
+def test_captured_steps_reject_unsupported_contexts(side_stream):
+    rp, ci, va = _rows(100, 5)
+    b = tl.CsrBatch.from_numpy(rp, ci, va)
+    rng = np.random.default_rng(1)
+    P = torch.zeros((100, 100), dtype=torch.float32, device="cuda")
+    big = tl.tlda_create(V, 100, 100, 1.0, stream=side_stream)    # FP32, beyond fused shapes
+    Q, _ = np.linalg.qr(rng.standard_normal((V, 100)))
+    tl.tlda_set_whitening(big, Q * 10, rng.dirichlet(np.ones(V)))
+    with pytest.raises(tl.TldaError) as e:
+        tl.tlda_graph_capture_steps(big, [b], 1e-3, P)
+    assert e.value.status == 2
+    cl = tl.tlda_create(V, 8, 8, 1.0, classic=True, stream=side_stream)
+    with pytest.raises(tl.TldaError) as e:
+        tl.tlda_graph_capture_steps(cl, [b], 1e-3, P[:8, :8].contiguous())
+    assert e.value.status == 1
+    nul = tl.tlda_create(V, 8, 8, 1.0, bf16=True, stream=torch.cuda.default_stream())
+    with pytest.raises(tl.TldaError) as e:
+        tl.tlda_graph_capture_steps(nul, [b], 1e-3, P[:8, :8].contiguous())
+    assert e.value.status == 1
+    nw = tl.tlda_create(V, 8, 8, 1.0, bf16=True, stream=side_stream)   # no whitening yet
+    with pytest.raises(tl.TldaError) as e:
+        tl.tlda_graph_capture_steps(nw, [b], 1e-3, P[:8, :8].contiguous())
+    assert e.value.status == 4
