@@ -296,7 +296,7 @@ __device__ __forceinline__ void cp_finish_block(
   __shared__ double red[kFinGroups][kFinEntries + 1];
   __shared__ double pen_s[kFinEntries];
   __shared__ int nred[kFinThreads / 64];
-  const int tid = threadIdx.x, el = tid & 15, grp = tid >> 4;
+  const int tid = threadIdx.x, el = tid % kFinEntries, grp = tid / kFinEntries;
   const int lane = tid & 63, wave = tid >> 6;
   const int DK = D * K;
   const int e = blk * kFinEntries + el;
@@ -319,23 +319,37 @@ __device__ __forceinline__ void cp_finish_block(
   for (int i = tid; i < DK; i += kFinThreads) ph[i] = Phi0[i];
   red[grp][el] = (r0 + r1) + (r2 + r3);
   __syncthreads();
-  const int me = blk * kFinEntries + wave;   // wave w: penalty of entry w
-  if (me < DK) {
+  // wave w: penalty of entries w, w + 16, ... of the block
+  for (int wi = wave; wi < kFinEntries; wi += kFinThreads / 64) {
+    const int me = blk * kFinEntries + wi;
+    if (me >= DK) break;
     const int d = me / K, k = me % K;
     double pen = 0.0;
     for (int j = lane; j < K; j += 64) {
-      double dot0 = 0.0, dot1 = 0.0;
+      // (Phi^T Phi)[j][k] in four independent chains
+      double dot0 = 0.0, dot1 = 0.0, dot2 = 0.0, dot3 = 0.0;
       int i = 0;
-      for (; i + 1 < D; i += 2) {
-        dot0 += (double)ph[i * K + j] * (double)ph[i * K + k];
-        dot1 += (double)ph[(i + 1) * K + j] * (double)ph[(i + 1) * K + k];
+      for (; i + 3 < D; i += 4) {
+        const float a0 = ph[i * K + j], a1 = ph[(i + 1) * K + j];
+        const float a2 = ph[(i + 2) * K + j], a3 = ph[(i + 3) * K + j];
+        const float b0 = ph[i * K + k], b1 = ph[(i + 1) * K + k];
+        const float b2 = ph[(i + 2) * K + k], b3 = ph[(i + 3) * K + k];
+        dot0 += (double)a0 * (double)b0;
+        dot1 += (double)a1 * (double)b1;
+        dot2 += (double)a2 * (double)b2;
+        dot3 += (double)a3 * (double)b3;
       }
-      if (i < D) dot0 += (double)ph[i * K + j] * (double)ph[i * K + k];
-      const double dot = dot0 + dot1;
+      for (; i < D; ++i) dot0 += (double)ph[i * K + j] * (double)ph[i * K + k];
+      const double dot = (dot0 + dot1) + (dot2 + dot3);
       pen += (double)ph[d * K + j] * (dot * dot);
     }
     for (int off = 32; off > 0; off >>= 1) pen += __shfl_xor(pen, off, 64);
-    if (lane == 0) pen_s[wave] = pen;
+    if (lane == 0) pen_s[wi] = pen;
+  }
+  // the groups' sums, added pairwise in a fixed tree (bit-reproducible)
+  for (int h = kFinGroups / 2; h > 0; h >>= 1) {
+    __syncthreads();
+    if (grp < h) red[grp][el] += red[grp + h][el];
   }
   __syncthreads();
   int n = n_default;
@@ -344,8 +358,7 @@ __device__ __forceinline__ void cp_finish_block(
     for (int w = 0; w < kFinThreads / 64; ++w) n += nred[w];
   }
   if (tid < kFinEntries && e < DK) {
-    double tot = 0.0;
-    for (int g = 0; g < kFinGroups; ++g) tot += red[g][el];
+    const double tot = red[0][el];
     R1[e] = tot;
     if (n <= 0) {
       grad[e] = 0.f;
