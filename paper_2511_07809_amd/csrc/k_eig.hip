@@ -3,9 +3,15 @@
 // Cholesky-QR orthonormalisation and a final Rayleigh-Ritz step solved by
 // parallel-order cyclic Jacobi (section "Online Decomposition of the Second
 // Moment": W = U diag(lambda)^(-1/2) so that W^T M2~ W = I).
+#include <rocblas/rocblas.h>
+
 #include "tlda_internal.h"
 
 namespace tlda {
+
+thread_local void* g_blas = nullptr;
+thread_local EigEnv g_eig_env;
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -16,11 +22,13 @@ namespace {
 // K step 16 staged through LDS.  grid.z splits Kd into chunks of k_chunk
 // rows; with more than one chunk the tile is added to C with FP64 atomics.
 // ---------------------------------------------------------------------------
+// (c_stride_z != 0: chunk z writes its own tile to C + z * c_stride_z.)
 template <bool TRANS_A>
 __global__ void __launch_bounds__(256) k_gemm64(int M, int N, int Kd, const double* __restrict__ A,
                                                 int lda, const double* __restrict__ B, int ldb,
                                                 double* __restrict__ C, int ldc, double alpha,
-                                                int k_chunk, int atomic_out) {
+                                                int k_chunk, int atomic_out, size_t c_stride_z) {
+  C += blockIdx.z * c_stride_z;
   __shared__ double As[16][64 + 2];
   __shared__ double Bs[16][64 + 2];
   const int tid = threadIdx.x;
@@ -84,8 +92,47 @@ __global__ void __launch_bounds__(256) k_gemm64(int M, int N, int Kd, const doub
   }
 }
 
+// Out[e] = alpha * sum_z part[z][e] over nz chunks, in chunk order.
+__global__ void k_sum_partials(const double* __restrict__ part, int nz, size_t mn, int N, int ldc,
+                               double alpha, double* __restrict__ C) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mn) return;
+  double s = 0.0;
+  for (int z = 0; z < nz; ++z) s += part[(size_t)z * mn + e];
+  C[(e / N) * ldc + e % N] = alpha * s;
+}
+
 hipError_t gemm(bool transA, int M, int N, int Kd, const double* A, int lda, const double* B,
                 int ldb, double* C, int ldc, double alpha, int splits, hipStream_t s) {
+  if (transA && g_eig_env.part != nullptr && (size_t)M * N <= g_eig_env.part_mn) {
+    // A^T B over many rows: row chunks of at least 256 write their own
+    // partials, then one pass adds them in order (no atomics)
+    int nz = (Kd + 255) / 256;
+    if (nz > kSplitMax) nz = kSplitMax;
+    if (nz < 1) nz = 1;
+    const int chunk = ((Kd + nz - 1) / nz + 15) / 16 * 16;
+    nz = (Kd + chunk - 1) / chunk;
+    const size_t mn = (size_t)M * N;
+    dim3 grid((N + 63) / 64, (M + 63) / 64, nz);
+    hipLaunchKernelGGL(k_gemm64<true>, grid, dim3(256), 0, s, M, N, Kd, A, lda, B, ldb,
+                       g_eig_env.part, N, 1.0, chunk, 0, mn);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s,
+                       g_eig_env.part, nz, mn, N, ldc, alpha, C);
+    return hipGetLastError();
+  }
+  if (g_blas != nullptr) {
+    // row-major C = op(A) B is column-major C^T = B^T op(A)^T
+    rocblas_handle h = static_cast<rocblas_handle>(g_blas);
+    if (rocblas_set_stream(h, s) != rocblas_status_success) return hipErrorUnknown;
+    const double beta = 0.0;
+    const rocblas_status st =
+        rocblas_dgemm(h, rocblas_operation_none,
+                      transA ? rocblas_operation_transpose : rocblas_operation_none, N, M, Kd,
+                      &alpha, B, ldb, A, lda, &beta, C, ldc);
+    return st == rocblas_status_success ? hipSuccess : hipErrorUnknown;
+  }
   if (splits < 1) splits = 1;
   int chunk = (Kd + splits - 1) / splits;
   chunk = (chunk + 15) / 16 * 16;
@@ -98,10 +145,10 @@ hipError_t gemm(bool transA, int M, int N, int Kd, const double* A, int lda, con
   }
   if (transA)
     hipLaunchKernelGGL(k_gemm64<true>, grid, dim3(256), 0, s, M, N, Kd, A, lda, B, ldb, C, ldc,
-                       alpha, chunk, atomic_out);
+                       alpha, chunk, atomic_out, (size_t)0);
   else
     hipLaunchKernelGGL(k_gemm64<false>, grid, dim3(256), 0, s, M, N, Kd, A, lda, B, ldb, C, ldc,
-                       alpha, chunk, atomic_out);
+                       alpha, chunk, atomic_out, (size_t)0);
   return hipGetLastError();
 }
 
@@ -172,6 +219,78 @@ __global__ void __launch_bounds__(1024) k_cholesky(double* __restrict__ G, int p
     __syncthreads();
   }
   if (tid == 0 && sh_fail) atomicOr(info, 1);
+}
+
+// The same factorisation with the matrix held in LDS (p <= kLdsP): two
+// barriers per column instead of round trips through global memory.
+constexpr int kLdsP = 128;
+__global__ void __launch_bounds__(1024) k_cholesky_lds(double* __restrict__ G, int p,
+                                                       double shift_rel, int* __restrict__ info) {
+  __shared__ double A[kLdsP * kLdsP];
+  __shared__ double red[1024];
+  __shared__ int sh_fail;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double mx = 0.0;
+  for (int idx = tid; idx < p * p; idx += nt) {
+    const double v = G[idx];
+    A[idx] = v;
+    if (idx / p == idx % p) mx = fmax(mx, v);
+  }
+  red[tid] = mx;
+  if (tid == 0) sh_fail = 0;
+  __syncthreads();
+  for (int w = nt / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const double shift = shift_rel * red[0];
+  for (int i = tid; i < p; i += nt) A[i * p + i] += shift;
+  __syncthreads();
+  for (int j = 0; j < p; ++j) {
+    const double d = A[j * p + j];
+    const double sq = d > 0.0 ? sqrt(d) : 1.0;
+    for (int i = j + 1 + tid; i < p; i += nt) A[i * p + j] /= sq;
+    __syncthreads();
+    if (tid == 0) {
+      if (!(d > 0.0)) sh_fail = 1;
+      A[j * p + j] = sq;
+    }
+    const int rem = p - j - 1;
+    for (int idx = tid; idx < rem * rem; idx += nt) {
+      const int i = j + 1 + idx / rem, k = j + 1 + idx % rem;
+      if (k <= i) A[i * p + k] -= A[i * p + j] * A[k * p + j];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < p * p; idx += nt) G[idx] = A[idx];
+  if (tid == 0 && sh_fail) atomicOr(info, 1);
+}
+
+// Binv = (L^-1)^T for p <= kLdsP: thread c computes column c of X = L^-1 by
+// forward substitution, X held in LDS (X[k][c]: conflict-free across
+// threads), the rows of L read from global memory as broadcasts; four
+// partial sums shorten the dependency chain.
+__global__ void __launch_bounds__(kLdsP) k_tri_inverse_lds(const double* __restrict__ G, int p,
+                                                           double* __restrict__ Binv) {
+  __shared__ double X[kLdsP * kLdsP];
+  const int c = threadIdx.x;
+  if (c < p) {
+    for (int i = 0; i < c; ++i) X[i * p + c] = 0.0;
+    for (int i = c; i < p; ++i) {
+      const double* Li = G + (size_t)i * p;
+      double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int k = c;
+      for (; k + 3 < i; k += 4) {
+        s0 -= Li[k] * X[k * p + c];
+        s1 -= Li[k + 1] * X[(k + 1) * p + c];
+        s2 -= Li[k + 2] * X[(k + 2) * p + c];
+        s3 -= Li[k + 3] * X[(k + 3) * p + c];
+      }
+      for (; k < i; ++k) s0 -= Li[k] * X[k * p + c];
+      X[i * p + c] = ((s0 + s1) + (s2 + s3)) / Li[i];
+    }
+    for (int i = 0; i < p; ++i) Binv[(size_t)c * p + i] = X[i * p + c];
+  }
 }
 
 // Binv = (L^-1)^T for the lower-triangular L held in G; thread c solves
@@ -443,14 +562,20 @@ hipError_t launch_gram(const double* A, const double* B, double* G, int V, int p
 }
 
 hipError_t launch_cholesky(double* G, int p, double shift_rel, int* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, G, p, shift_rel, info);
+  if (p <= kLdsP)
+    hipLaunchKernelGGL(k_cholesky_lds, dim3(1), dim3(1024), 0, s, G, p, shift_rel, info);
+  else
+    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), 0, s, G, p, shift_rel, info);
   return hipGetLastError();
 }
 
 // Y (V x p) <- Y L^-T, written to Out; Binv is p x p scratch.
 hipError_t launch_trsm_right_into(const double* Y, const double* G, double* Binv, double* Out, int V,
                                   int p, hipStream_t s) {
-  hipLaunchKernelGGL(k_tri_inverse_t, dim3(1), dim3(256), 0, s, G, p, Binv);
+  if (p <= kLdsP)
+    hipLaunchKernelGGL(k_tri_inverse_lds, dim3(1), dim3(kLdsP), 0, s, G, p, Binv);
+  else
+    hipLaunchKernelGGL(k_tri_inverse_t, dim3(1), dim3(256), 0, s, G, p, Binv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return gemm(false, V, p, p, Y, p, Binv, p, Out, p, 1.0, 1, s);
@@ -462,6 +587,11 @@ hipError_t launch_jacobi(double* A, double* Z, double* ev, int p, int* info, hip
   const size_t shmem = sizeof(double) * (3 * (m / 2) + 2 * nt) + sizeof(int) * m;
   hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(nt), shmem, s, A, Z, ev, p, info);
   return hipGetLastError();
+}
+
+hipError_t launch_block_product(const double* Q, const double* Z, double* Out, int V, int p,
+                                hipStream_t s) {
+  return gemm(false, V, p, p, Q, p, Z, p, Out, p, 1.0, 1, s);
 }
 
 hipError_t launch_ritz_vectors(const double* Q, const double* Z, const double* ev, int V, int p,

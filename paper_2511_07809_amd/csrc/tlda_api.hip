@@ -7,6 +7,8 @@
 #include <new>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "tlda_internal.h"
 
 #include <algorithm>
@@ -176,8 +178,9 @@ tlda_status ensure_eig(tlda_ctx* c, int p) {
   tlda::EigScratch& e = c->eig;
   if (e.p == p && e.Q) return TLDA_OK;
   dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
-  dfree(e.sel); dfree(e.mcand); dfree(e.info);
+  dfree(e.sel); dfree(e.mcand); dfree(e.info); dfree(e.part);
   e.p = 0;
+  e.warm = nullptr;
   const size_t V = c->cfg.V, D = c->cfg.D;
   HIP_OK(c, dalloc(&e.Q, V * p));
   HIP_OK(c, dalloc(&e.Y, V * p));
@@ -189,6 +192,7 @@ tlda_status ensure_eig(tlda_ctx* c, int p) {
   HIP_OK(c, dalloc(&e.sel, D + (size_t)p * D));
   HIP_OK(c, dalloc(&e.mcand, V));
   HIP_OK(c, dalloc(&e.info, 4));
+  HIP_OK(c, dalloc(&e.part, (size_t)tlda::kSplitMax * p * p));
   e.p = p;
   return TLDA_OK;
 }
@@ -236,10 +240,23 @@ tlda_status save_prev(tlda_ctx* c) {
   return TLDA_OK;
 }
 
+tlda_status ensure_blas(tlda_ctx* c) {
+  if (c->blas != nullptr) return TLDA_OK;
+  rocblas_handle h = nullptr;
+  CHECK_ARG(c, rocblas_create_handle(&h) == rocblas_status_success, TLDA_ERR_DEVICE,
+            "rocBLAS handle creation failed");
+  c->blas = h;
+  return TLDA_OK;
+}
+
 // warm: start from the block the previous refresh converged to (if any) and
 // run cfg.eig_warm_iters iterations instead of a seeded cold start.
 tlda_status refresh(tlda_ctx* c, bool warm) {
   const int V = c->cfg.V, D = c->cfg.D;
+  {
+    tlda_status bs = ensure_blas(c);
+    if (bs != TLDA_OK) return bs;
+  }
   unsigned long long counts[2] = {0, 0};
   HIP_OK(c, hipMemcpyAsync(counts, c->mom.counts, sizeof(counts), hipMemcpyDeviceToHost, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
@@ -248,6 +265,7 @@ tlda_status refresh(tlda_ctx* c, bool warm) {
   tlda_status st = ensure_eig(c, p);
   if (st != TLDA_OK) return st;
   tlda::EigScratch& e = c->eig;
+  tlda::BlasScope blas_scope(c->blas, e.part, (size_t)p * p);
   warm = warm && e.warm != nullptr;
   const int iters = warm ? (c->cfg.eig_warm_iters > 0 ? c->cfg.eig_warm_iters : 4)
                          : (c->cfg.eig_iters > 0 ? c->cfg.eig_iters : 60);
@@ -260,7 +278,9 @@ tlda_status refresh(tlda_ctx* c, bool warm) {
   if (warm) {
     // start block: the orthonormal block of the previous refresh
     if (e.warm != q) std::swap(q, y);
-  } else {
+  }
+  e.warm = nullptr;   // both buffers are overwritten below; set again on success
+  if (!warm) {
     // start block: seeded uniform entries, orthonormalised (y -> tmp q -> y)
     HIP_OK(c, tlda::launch_random_block(y, V, p, c->cfg.eig_seed, c->stream));
     st = orthonormalise(c, y, q, y);
@@ -291,11 +311,14 @@ tlda_status refresh(tlda_ctx* c, bool warm) {
   for (int d = 0; d < D; ++d)
     CHECK_ARG(c, std::isfinite(eigD[d]) && eigD[d] > 0.0, TLDA_ERR_NUMERIC,
               "M2~ has fewer than D positive eigenvalues; lower D");
-  // commit (q, the converged orthonormal block, is the next warm start)
+  // commit
   st = save_prev(c);
   if (st != TLDA_OK) return st;
-  e.warm = q;
   HIP_OK(c, hipMemcpyAsync(c->wh.U, y, sizeof(double) * (size_t)V * D, hipMemcpyDeviceToDevice, c->stream));
+  // the next warm start: the full Ritz basis Q Z (p columns), so that the
+  // projected matrix of the next refresh starts close to diagonal
+  HIP_OK(c, tlda::launch_block_product(q, e.Z, y, V, p, c->stream));
+  e.warm = y;
   HIP_OK(c, hipMemcpyAsync(c->wh.eig, e.sel, sizeof(double) * D, hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(c, hipMemcpyAsync(c->wh.m, e.mcand, sizeof(double) * V, hipMemcpyDeviceToDevice, c->stream));
   HIP_OK(c, form_whitening(c));
@@ -365,7 +388,7 @@ void destroy_all(tlda_ctx* c) {
   delete[] c->t_stop;
   tlda::EigScratch& e = c->eig;
   dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
-  dfree(e.sel); dfree(e.mcand); dfree(e.info);
+  dfree(e.sel); dfree(e.mcand); dfree(e.info); dfree(e.part);
   dfree(c->cp.partial); dfree(c->cp.R1); dfree(c->cp.phi0); dfree(c->cp.grad); dfree(c->cp.X);
   dfree(c->cp.Z); dfree(c->cp.rz);
   dfree(c->post); dfree(c->postA); dfree(c->postG); dfree(c->postZ); dfree(c->postEv);
@@ -377,6 +400,7 @@ void destroy_all(tlda_ctx* c) {
     if (s.free_) (void)hipEventDestroy(s.free_);
   }
   if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+  if (c->blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c->blas));
   delete c;
 }
 
@@ -802,6 +826,9 @@ tlda_status tlda_rebase_phi(tlda_ctx* c, float* Phi) {
   CHECK_ARG(c, c->wh.ready && c->wh.prev_ready, TLDA_ERR_STATE,
             "no previous whitening to rebase from");
   const int V = c->cfg.V, D = c->cfg.D, K = c->cfg.K;
+  tlda_status st = ensure_blas(c);
+  if (st != TLDA_OK) return st;
+  tlda::BlasScope blas_scope(c->blas, c->eig.part, c->eig.part ? (size_t)c->eig.p * c->eig.p : 0);
   HIP_OK(c, tlda::launch_gram(c->wh.U, c->wh.Uprev, c->wh.C, V, D, c->stream));
   HIP_OK(c, tlda::launch_rebase(c->wh.C, c->wh.eig, c->wh.eigprev, D, K, Phi, c->stream));
   return TLDA_OK;

@@ -73,6 +73,7 @@ struct EigScratch {
   double* mcand = nullptr; // [V]     M1 of the refresh in progress
   int* info = nullptr;     // [4]     device status words
   double* warm = nullptr;  // Q or Y: the orthonormal block the last refresh converged to
+  double* part = nullptr;  // [kSplitMax][p][p] partial sums of the Gram products
 };
 
 // Launch-shape knobs (0 = built-in choice).  Initialised from the
@@ -136,6 +137,7 @@ struct tlda_ctx {
   hipEvent_t* t_stop = nullptr;
   int t_n = 0, t_next = 0;
   bool in_capture = false;    // capturing a graph of steps: no validation, no timing hook
+  void* blas = nullptr;       // rocblas_handle of the refresh's FP64 products (created lazily)
   std::string last_error;
 };
 
@@ -200,6 +202,35 @@ struct KernelTimer {
 };
 extern thread_local KernelTimer g_main_timer;
 
+// rocBLAS handle (a rocblas_handle) for the dense FP64 products of the
+// whitening refresh, set by the API around a refresh or rebase; while it is
+// null those products run on the library's own GEMM kernel.
+// Partial-sum scratch of the transposed products A^T B over many rows (the
+// refresh's Gram products): up to kSplitMax row chunks each write their own
+// M x N partial, added in chunk order afterwards (deterministic).
+constexpr int kSplitMax = 64;
+struct EigEnv {
+  void* blas = nullptr;
+  double* part = nullptr;     // kSplitMax * part_mn doubles
+  size_t part_mn = 0;         // largest M * N the scratch serves
+};
+extern thread_local void* g_blas;
+extern thread_local EigEnv g_eig_env;
+struct BlasScope {
+  EigEnv prev;
+  void* prev_blas;
+  BlasScope(void* h, double* part, size_t part_mn) : prev(g_eig_env), prev_blas(g_blas) {
+    g_blas = h;
+    g_eig_env.blas = h;
+    g_eig_env.part = part;
+    g_eig_env.part_mn = part_mn;
+  }
+  ~BlasScope() {
+    g_blas = prev_blas;
+    g_eig_env = prev;
+  }
+};
+
 template <typename... Params, typename... Args>
 inline void launch_main(void (*kernel)(Params...), dim3 grid, dim3 block, unsigned shmem,
                         hipStream_t s, Args... args) {
@@ -234,6 +265,9 @@ hipError_t launch_cholesky(double* G, int p, double shift_rel, int* info, hipStr
 hipError_t launch_trsm_right_into(const double* Y, const double* G, double* Binv, double* Out, int V,
                                   int p, hipStream_t s);
 hipError_t launch_jacobi(double* A, double* Z, double* ev, int p, int* info, hipStream_t s);
+// Out (V x p) = Q (V x p) Z (p x p)
+hipError_t launch_block_product(const double* Q, const double* Z, double* Out, int V, int p,
+                                hipStream_t s);
 hipError_t launch_ritz_vectors(const double* Q, const double* Z, const double* ev, int V, int p,
                                int D, double* U, double* eigD, hipStream_t s);
 hipError_t launch_form_whitening(const double* U, const double* eig, const double* m, int V, int D,
