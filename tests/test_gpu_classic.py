@@ -205,3 +205,27 @@ def test_classic_config_errors():
     with pytest.raises(tl.TldaError) as e:
         tl.tlda_cp_step(ctx, X, 8, None, 0.1, Pd)
     assert e.value.status == 4
+
+
+def test_classic_step_full_size_tweet_batch():
+    """One full 131 072-document batch of the tweet-shaped workload (V = 20 000,
+    K = D = 50), the launch configuration the benchmark times, against the
+    oracle's per-document gradient over the same batch."""
+    spec = SPECS["c2"]
+    c = generate(spec, n_docs=spec.batch)
+    rp, ci, va, _ = next(iter_batches(c))
+    D = K = spec.K
+    rng = np.random.default_rng(23)
+    Q, _ = np.linalg.qr(rng.standard_normal((spec.V, D)))
+    W = Q * rng.uniform(20, 200, size=D)[None, :]
+    m = np.bincount(ci, weights=va, minlength=spec.V) / va.sum()
+    Phi = (init_phi(D, K, 9) * 0.3).astype(np.float32)
+    ctx = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, classic=True)
+    tl.tlda_set_whitening(ctx, W, m)
+    Pd = torch.from_numpy(Phi).cuda()
+    g = torch.empty_like(Pd)
+    tl.tlda_whiten_cp_step(ctx, tl.CsrBatch.from_numpy(rp, ci, va), 1e-4, Pd, g)
+    torch.cuda.synchronize()
+    ref = O.classic_cp_gradient(rp, ci, va, spec.V, m, W, Phi.astype(np.float64), spec.alpha0,
+                                0.0)
+    assert rel(g.cpu().numpy(), ref) < 1e-5
