@@ -420,6 +420,119 @@ __global__ void __launch_bounds__(1024) k_jacobi(double* __restrict__ A, double*
   for (int i = tid; i < p; i += nt) ev[i] = A[(size_t)i * p + i];
 }
 
+// The same iteration with the p x p matrix in LDS (p <= kLdsP); the rotation
+// accumulator Z stays in global memory.
+__global__ void __launch_bounds__(1024) k_jacobi_lds(double* __restrict__ Ag, double* __restrict__ Z,
+                                                 double* __restrict__ ev, int p,
+                                                 int* __restrict__ info) {
+  __shared__ double A[kLdsP * kLdsP];
+  __shared__ double sh[3 * (kLdsP / 2) + 2 * 1024];   // c, s, pair indices, reduction scratch
+  __shared__ int sh_rot;
+  __shared__ double sh_norm;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int m = (p + 1) & ~1;
+  const int half = m / 2;
+  double* cs = sh;
+  double* sn = sh + half;
+  int* pi = reinterpret_cast<int*>(sh + 2 * half);
+  int* pj = pi + half;
+  double* red = sh + 3 * half;     // 2 * nt doubles
+  for (int idx = tid; idx < p * p; idx += nt) {
+    A[idx] = Ag[idx];
+    Z[idx] = (idx / p == idx % p) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // Frobenius norm (invariant under the rotations)
+  double tot = 0.0;
+  for (int idx = tid; idx < p * p; idx += nt) tot += A[idx] * A[idx];
+  red[tid] = tot;
+  __syncthreads();
+  for (int w = nt / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) sh_norm = sqrt(red[0]);
+  __threadfence_block();
+  __syncthreads();
+  const double tiny = 1e-20 * sh_norm;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) sh_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < m - 1; ++r) {
+      for (int k = tid; k < half; k += nt) {
+        int i, j;
+        if (k == 0) { i = 0; j = 1 + r; }
+        else {
+          i = 1 + (r + k) % (m - 1);
+          j = 1 + (r - k + (m - 1)) % (m - 1);
+        }
+        if (i > j) { const int t = i; i = j; j = t; }
+        double c = 1.0, s = 0.0;
+        if (j < p) {
+          const double aij = A[(size_t)i * p + j];
+          const double aii = A[(size_t)i * p + i], ajj = A[(size_t)j * p + j];
+          if (fabs(aij) > tiny && fabs(aij) > 1e-15 * sqrt(fabs(aii * ajj))) {
+            const double tau = (ajj - aii) / (2.0 * aij);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            sh_rot = 1;
+          }
+        }
+        pi[k] = i;
+        pj[k] = j;
+        cs[k] = c;
+        sn[k] = s;
+      }
+      __syncthreads();
+      // columns i, j of A and Z
+      for (int idx = tid; idx < half * p; idx += nt) {
+        const int k = idx / p, row = idx % p;
+        const int i = pi[k], j = pj[k];
+        const double s = sn[k];
+        if (j >= p || s == 0.0) continue;
+        const double c = cs[k];
+        const double ai = A[(size_t)row * p + i], aj = A[(size_t)row * p + j];
+        A[(size_t)row * p + i] = c * ai - s * aj;
+        A[(size_t)row * p + j] = s * ai + c * aj;
+        const double zi = Z[(size_t)row * p + i], zj = Z[(size_t)row * p + j];
+        Z[(size_t)row * p + i] = c * zi - s * zj;
+        Z[(size_t)row * p + j] = s * zi + c * zj;
+      }
+      __threadfence_block();
+      __syncthreads();
+      // rows i, j of A
+      for (int idx = tid; idx < half * p; idx += nt) {
+        const int k = idx / p, col = idx % p;
+        const int i = pi[k], j = pj[k];
+        const double s = sn[k];
+        if (j >= p || s == 0.0) continue;
+        const double c = cs[k];
+        const double ai = A[(size_t)i * p + col], aj = A[(size_t)j * p + col];
+        A[(size_t)i * p + col] = c * ai - s * aj;
+        A[(size_t)j * p + col] = s * ai + c * aj;
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+    if (sh_rot == 0) break;
+    __syncthreads();
+  }
+  // final check of the remaining off-diagonal mass
+  double off = 0.0;
+  for (int idx = tid; idx < p * p; idx += nt)
+    if (idx / p != idx % p) off += A[idx] * A[idx];
+  red[tid] = off;
+  __syncthreads();
+  for (int w = nt / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0 && sqrt(red[0]) > 1e-10 * sh_norm) atomicOr(info, 2);
+  for (int i = tid; i < p; i += nt) ev[i] = A[(size_t)i * p + i];
+  for (int idx = tid; idx < p * p; idx += nt) Ag[idx] = A[idx];
+}
+
 // Sorts the Ritz values in decreasing order (ties: lower index first), keeps
 // the top D, and gathers the matching eigenvector columns into Zs [p][D].
 __global__ void __launch_bounds__(256) k_select_top(const double* __restrict__ Z,
@@ -582,6 +695,10 @@ hipError_t launch_trsm_right_into(const double* Y, const double* G, double* Binv
 }
 
 hipError_t launch_jacobi(double* A, double* Z, double* ev, int p, int* info, hipStream_t s) {
+  if (p <= kLdsP) {
+    hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(1024), 0, s, A, Z, ev, p, info);
+    return hipGetLastError();
+  }
   const int m = (p + 1) & ~1;
   const int nt = 1024;
   const size_t shmem = sizeof(double) * (3 * (m / 2) + 2 * nt) + sizeof(int) * m;
