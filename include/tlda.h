@@ -102,7 +102,7 @@ typedef struct {
   double alpha0;        /* topic mixing parameter, > 0                             */
   double theta;         /* orthogonality penalty of eq. full_vec_pb, >= 0          */
   int32_t eig_iters;    /* subspace iterations of a refresh, 0 = default (60)      */
-  int32_t eig_block;    /* subspace width p >= D, 0 = default                      */
+  int32_t eig_block;    /* subspace width D <= p <= min(V, 512), 0 = default      */
   uint64_t eig_seed;    /* seed of the refresh's start block                       */
   int32_t eig_warm_iters; /* subspace iterations of a warm refresh, 0 = default (4) */
 } tlda_config;

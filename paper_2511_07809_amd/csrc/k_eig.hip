@@ -266,44 +266,32 @@ __global__ void __launch_bounds__(1024) k_cholesky_lds(double* __restrict__ G, i
   if (tid == 0 && sh_fail) atomicOr(info, 1);
 }
 
-// Binv = (L^-1)^T for p <= kLdsP: thread c computes column c of X = L^-1 by
-// forward substitution, X held in LDS (X[k][c]: conflict-free across
-// threads), the rows of L read from global memory as broadcasts; four
-// partial sums shorten the dependency chain.
-__global__ void __launch_bounds__(kLdsP) k_tri_inverse_lds(const double* __restrict__ G, int p,
-                                                           double* __restrict__ Binv) {
-  __shared__ double X[kLdsP * kLdsP];
-  const int c = threadIdx.x;
-  if (c < p) {
-    for (int i = 0; i < c; ++i) X[i * p + c] = 0.0;
+// Binv = (L^-1)^T: thread c computes column c of X = L^-1 by forward
+// substitution.  A block takes kInvCols columns, X[:, its columns] held in
+// LDS (X[k][c]: conflict-free across threads), the rows of L read from global
+// memory as broadcasts; four partial sums shorten the dependency chain.
+// Columns are independent, so any p <= 512 fits (p * kInvCols doubles).
+constexpr int kInvCols = 32;
+__global__ void __launch_bounds__(64) k_tri_inverse_cols(const double* __restrict__ G, int p,
+                                                         double* __restrict__ Binv) {
+  __shared__ double X[512 * kInvCols];
+  const int cl = threadIdx.x, c = blockIdx.x * kInvCols + cl;
+  if (cl < kInvCols && c < p) {
+    for (int i = 0; i < c; ++i) X[i * kInvCols + cl] = 0.0;
     for (int i = c; i < p; ++i) {
       const double* Li = G + (size_t)i * p;
       double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
       int k = c;
       for (; k + 3 < i; k += 4) {
-        s0 -= Li[k] * X[k * p + c];
-        s1 -= Li[k + 1] * X[(k + 1) * p + c];
-        s2 -= Li[k + 2] * X[(k + 2) * p + c];
-        s3 -= Li[k + 3] * X[(k + 3) * p + c];
+        s0 -= Li[k] * X[k * kInvCols + cl];
+        s1 -= Li[k + 1] * X[(k + 1) * kInvCols + cl];
+        s2 -= Li[k + 2] * X[(k + 2) * kInvCols + cl];
+        s3 -= Li[k + 3] * X[(k + 3) * kInvCols + cl];
       }
-      for (; k < i; ++k) s0 -= Li[k] * X[k * p + c];
-      X[i * p + c] = ((s0 + s1) + (s2 + s3)) / Li[i];
+      for (; k < i; ++k) s0 -= Li[k] * X[k * kInvCols + cl];
+      X[i * kInvCols + cl] = ((s0 + s1) + (s2 + s3)) / Li[i];
     }
-    for (int i = 0; i < p; ++i) Binv[(size_t)c * p + i] = X[i * p + c];
-  }
-}
-
-// Binv = (L^-1)^T for the lower-triangular L held in G; thread c solves
-// L x = e_c by forward substitution and stores x as row c of Binv.
-__global__ void __launch_bounds__(256) k_tri_inverse_t(const double* __restrict__ G, int p,
-                                                       double* __restrict__ Binv) {
-  for (int c = threadIdx.x; c < p; c += blockDim.x) {
-    double* x = Binv + (size_t)c * p;
-    for (int i = 0; i < p; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) s -= G[(size_t)i * p + k] * x[k];
-      x[i] = (i < c) ? 0.0 : s / G[(size_t)i * p + i];
-    }
+    for (int i = 0; i < p; ++i) Binv[(size_t)c * p + i] = X[i * kInvCols + cl];
   }
 }
 
@@ -685,10 +673,9 @@ hipError_t launch_cholesky(double* G, int p, double shift_rel, int* info, hipStr
 // Y (V x p) <- Y L^-T, written to Out; Binv is p x p scratch.
 hipError_t launch_trsm_right_into(const double* Y, const double* G, double* Binv, double* Out, int V,
                                   int p, hipStream_t s) {
-  if (p <= kLdsP)
-    hipLaunchKernelGGL(k_tri_inverse_lds, dim3(1), dim3(kLdsP), 0, s, G, p, Binv);
-  else
-    hipLaunchKernelGGL(k_tri_inverse_t, dim3(1), dim3(256), 0, s, G, p, Binv);
+  if (p > 512) return hipErrorInvalidValue;   // the kernel's LDS holds 512 rows
+  hipLaunchKernelGGL(k_tri_inverse_cols, dim3((p + kInvCols - 1) / kInvCols), dim3(64), 0, s, G,
+                     p, Binv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return gemm(false, V, p, p, Y, p, Binv, p, Out, p, 1.0, 1, s);

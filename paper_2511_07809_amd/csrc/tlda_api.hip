@@ -439,7 +439,8 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
   if (!(c.flags & (TLDA_BF16 | TLDA_CLASSIC)) &&
       (((c.D + 3) / 4) * ((c.K + 3) / 4) > 1024 || tlda::cp_tile_rows(c.D, c.K) == 0))
     return TLDA_ERR_SHAPE;   // the FP32 reduction's shape limits (unused by BF16 and classic)
-  if (c.eig_block != 0 && (c.eig_block < c.D || c.eig_block > c.V)) return TLDA_ERR_SHAPE;
+  if (c.eig_block != 0 && (c.eig_block < c.D || c.eig_block > c.V || c.eig_block > 512))
+    return TLDA_ERR_SHAPE;
   if ((c.flags & TLDA_BF16) && !tlda::bf16_supported(c.D, c.K)) return TLDA_ERR_SHAPE;
   if ((c.flags & TLDA_CLASSIC) && !tlda::classic_supported(c.D, c.K)) return TLDA_ERR_SHAPE;
   tlda_ctx* ctx = new (std::nothrow) tlda_ctx();

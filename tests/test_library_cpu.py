@@ -75,6 +75,8 @@ def test_create_validates_config_before_touching_a_device(lib):
     assert create(300, 129, 10, tlda.TLDA_BF16) == 2           # BF16 path: K <= 128
     assert create(300, 10, 129, tlda.TLDA_CLASSIC) == 2        # classic rung: D <= 128
     assert create(300, 129, 10, tlda.TLDA_CLASSIC) == 2        # classic rung: K <= 128
+    cfg = tlda.tlda_config(1000, 10, 10, 0, 1.0, 0.0, 0, 513, 0, 0)   # subspace width <= 512
+    assert lib.tlda_create(ctypes.byref(cfg), None, ctypes.byref(out)) == 2
     assert out.value is None
     lib.tlda_set_timing_events.restype = ctypes.c_int
     lib.tlda_set_timing_events.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
