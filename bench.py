@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--streamed", action="store_true",
                     help="stream every step's batch from pinned host memory (tlda_stage_batch, "
                          "copy of batch i+1 overlapping the compute of batch i)")
+    ap.add_argument("--stage-format", default="auto", choices=["auto", "f32", "u16"],
+                    help="--streamed host format: u16 = 16-bit column indices and counts "
+                         "(tlda_stage_batch_u16, half the PCIe bytes); auto: u16 for the BF16 "
+                         "step when V <= 65536, f32 for the FP32 step")
     ap.add_argument("--path", default="fused", choices=["fused", "split"],
                     help="fused: tlda_whiten_cp_step; split: tlda_whiten_batch + tlda_cp_step")
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"],
@@ -776,18 +780,31 @@ def main():
     nk = torch.empty(1, dtype=torch.int32, device="cuda")
     fused = args.path == "fused"
 
+    def stage_format_for(precision):
+        if args.stage_format != "auto":
+            return args.stage_format
+        return "u16" if precision == "bf16" and spec.V <= 65536 else "f32"
+    stage_format = stage_format_for(args.precision)
     if args.streamed:
-        host = [tl.CsrBatch.from_numpy(rp, ci, va, pin=True) for rp, ci, va, _ in batches]
+        hosts = {}
+        if "u16" in (stage_format_for("bf16"), stage_format_for("fp32")):
+            hosts["u16"] = [tl.CsrBatchU16(rp, ci, va) for rp, ci, va, _ in batches]
+        if "f32" in (stage_format_for("bf16"), stage_format_for("fp32")):
+            hosts["f32"] = [tl.CsrBatch.from_numpy(rp, ci, va, pin=True)
+                            for rp, ci, va, _ in batches]
 
         def make_batch_for(cx):
+            fmt = stage_format_for("bf16" if cx is (ctx if bf16 else other) else "fp32")
+            host = hosts[fmt]
+            stage = tl.tlda_stage_batch_u16 if fmt == "u16" else tl.tlda_stage_batch
             staged = {}
 
             def batch_for(i):
                 # stage batch i+1 before computing batch i, so the copy overlaps the compute
                 if i not in staged:
                     staged.clear()
-                    staged[i] = tl.tlda_stage_batch(cx, host[i % len(host)], i % 2)
-                staged[i + 1] = tl.tlda_stage_batch(cx, host[(i + 1) % len(host)], (i + 1) % 2)
+                    staged[i] = stage(cx, host[i % len(host)], i % 2)
+                staged[i + 1] = stage(cx, host[(i + 1) % len(host)], (i + 1) % 2)
                 return staged.pop(i)
             return batch_for
     else:
@@ -912,6 +929,7 @@ def main():
                                + ("streamed from pinned host memory" if args.streamed
                                   else "resident in HBM"),
                    "streamed": bool(args.streamed), "precision": args.precision,
+                   "stage_format": stage_format if args.streamed else None,
                    "global_batch": spec.batch, "beta": beta, "path": args.path,
                    "launch": "hip_graph" if main_graph else "eager"},
         "roofline": roof,

@@ -241,6 +241,24 @@ tlda_status tlda_infer_doc_topics(tlda_ctx* ctx, const float* X, int32_t n_rows,
 tlda_status tlda_stage_batch(tlda_ctx* ctx, const tlda_csr_batch* host_batch, int32_t slot,
                              tlda_csr_batch* dev_out);
 
+/* The compact staging format: the same CSR batch with 16-bit column indices
+ * (the context's V <= 65536) and 16-bit counts (1 .. 65535), about half the
+ * bytes of the 32-bit form over PCIe.  All arrays are pinned host memory. */
+typedef struct {
+  int32_t n_rows;
+  int32_t nnz;
+  const int32_t* row_ptr;   /* [n_rows + 1] */
+  const uint16_t* col_idx;  /* [nnz]        */
+  const uint16_t* val;      /* [nnz] counts */
+} tlda_csr_batch_u16;
+
+/* tlda_stage_batch for a compact host batch: the 16-bit arrays are copied
+ * and then widened on the device (on the copy stream, before the slot's ready
+ * event) into the slot's 32-bit arrays, so *dev_out is an ordinary staged
+ * batch.  TLDA_ERR_SHAPE when the context's V exceeds 65536. */
+tlda_status tlda_stage_batch_u16(tlda_ctx* ctx, const tlda_csr_batch_u16* host_batch,
+                                 int32_t slot, tlda_csr_batch* dev_out);
+
 /* Inspection and test hooks (all synchronous). */
 /* N, dropped documents and the int64 token totals [V] (token_totals may be NULL). */
 tlda_status tlda_get_stats(tlda_ctx* ctx, int64_t* N, int64_t* n_skipped, int64_t* token_totals);

@@ -300,25 +300,23 @@ __device__ __forceinline__ void cp_finish_block(
   const int lane = tid & 63, wave = tid >> 6;
   const int DK = D * K;
   const int e = blk * kFinEntries + el;
-  double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
-  if (e < DK) {
-    int b = grp;
-    for (; b + 3 * kFinGroups < nblk; b += 4 * kFinGroups) {
-      r0 += (double)partial[(size_t)b * DK + e];
-      r1 += (double)partial[(size_t)(b + kFinGroups) * DK + e];
-      r2 += (double)partial[(size_t)(b + 2 * kFinGroups) * DK + e];
-      r3 += (double)partial[(size_t)(b + 3 * kFinGroups) * DK + e];
-    }
-    for (; b < nblk; b += kFinGroups) r0 += (double)partial[(size_t)b * DK + e];
-  }
   int cnt = 0;
   if (counts != nullptr)
     for (int i = tid; i < ncounts; i += kFinThreads) cnt += counts[i];
-  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
-  if (lane == 0) nred[wave] = cnt;
   for (int i = tid; i < DK; i += kFinThreads) ph[i] = Phi0[i];
-  red[grp][el] = (r0 + r1) + (r2 + r3);
   __syncthreads();
+  // the first four partials of this thread are in flight while the penalty
+  // below works from LDS (a barrier would wait for them)
+  int b = grp;
+  const bool first4 = e < DK && b + 3 * kFinGroups < nblk;
+  float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
+  if (first4) {
+    f0 = partial[(size_t)b * DK + e];
+    f1 = partial[(size_t)(b + kFinGroups) * DK + e];
+    f2 = partial[(size_t)(b + 2 * kFinGroups) * DK + e];
+    f3 = partial[(size_t)(b + 3 * kFinGroups) * DK + e];
+    b += 4 * kFinGroups;
+  }
   // wave w: penalty of entries w, w + 16, ... of the block
   for (int wi = wave; wi < kFinEntries; wi += kFinThreads / 64) {
     const int me = blk * kFinEntries + wi;
@@ -346,6 +344,19 @@ __device__ __forceinline__ void cp_finish_block(
     for (int off = 32; off > 0; off >>= 1) pen += __shfl_xor(pen, off, 64);
     if (lane == 0) pen_s[wi] = pen;
   }
+  double r0 = f0, r1 = f1, r2 = f2, r3 = f3;
+  if (e < DK) {
+    for (; b + 3 * kFinGroups < nblk; b += 4 * kFinGroups) {
+      r0 += (double)partial[(size_t)b * DK + e];
+      r1 += (double)partial[(size_t)(b + kFinGroups) * DK + e];
+      r2 += (double)partial[(size_t)(b + 2 * kFinGroups) * DK + e];
+      r3 += (double)partial[(size_t)(b + 3 * kFinGroups) * DK + e];
+    }
+    for (; b < nblk; b += kFinGroups) r0 += (double)partial[(size_t)b * DK + e];
+  }
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+  if (lane == 0) nred[wave] = cnt;
+  red[grp][el] = (r0 + r1) + (r2 + r3);
   // the groups' sums, added pairwise in a fixed tree (bit-reproducible)
   for (int h = kFinGroups / 2; h > 0; h >>= 1) {
     __syncthreads();

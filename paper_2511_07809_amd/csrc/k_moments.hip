@@ -172,7 +172,32 @@ __global__ void k_mean(const double* __restrict__ fsum, const unsigned long long
   if (i < V) m[i] = fsum[i] / (double)counts[0];
 }
 
+// Widening of a compact staged batch, four entries per thread.
+__global__ void __launch_bounds__(256) k_widen_u16(const uint16_t* __restrict__ col16,
+                                                   const uint16_t* __restrict__ val16, size_t nnz,
+                                                   int32_t* __restrict__ col,
+                                                   float* __restrict__ val) {
+  const size_t base = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const size_t j = base + q;
+    if (j < nnz) {
+      col[j] = (int32_t)col16[j];
+      val[j] = (float)val16[j];
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_widen_u16(const uint16_t* col16, const uint16_t* val16, size_t nnz,
+                            int32_t* col, float* val, hipStream_t s) {
+  if (nnz == 0) return hipSuccess;
+  const size_t threads = (nnz + 3) / 4;
+  hipLaunchKernelGGL(k_widen_u16, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, col16,
+                     val16, nnz, col, val);
+  return hipGetLastError();
+}
 
 hipError_t launch_validate_csr(const tlda_csr_batch& b, int V, int* err, hipStream_t s) {
   const int rows_per_block = 256 / kWave;

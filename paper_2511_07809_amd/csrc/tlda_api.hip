@@ -395,7 +395,7 @@ void destroy_all(tlda_ctx* c) {
   dfree(c->A32); dfree(c->G32); dfree(c->step32); dfree(c->dev_flags); dfree(c->block_counts);
   for (auto& s : c->slots) {
     if (s.free_) (void)hipEventSynchronize(s.free_);
-    dfree(s.row_ptr); dfree(s.col_idx); dfree(s.val);
+    dfree(s.row_ptr); dfree(s.col_idx); dfree(s.val); dfree(s.col16); dfree(s.val16);
     if (s.ready) (void)hipEventDestroy(s.ready);
     if (s.free_) (void)hipEventDestroy(s.free_);
   }
@@ -764,6 +764,53 @@ tlda_status tlda_stage_batch(tlda_ctx* c, const tlda_csr_batch* h, int32_t slot,
   }
   HIP_OK(c, hipEventRecord(s.ready, c->copy_stream));
   // until a consumer records its own release, the slot is free once copied
+  HIP_OK(c, hipEventRecord(s.free_, c->copy_stream));
+  s.used = true;
+  dev_out->n_rows = h->n_rows;
+  dev_out->nnz = h->nnz;
+  dev_out->row_ptr = s.row_ptr;
+  dev_out->col_idx = s.col_idx;
+  dev_out->val = s.val;
+  dev_out->slot = slot;
+  return TLDA_OK;
+}
+
+tlda_status tlda_stage_batch_u16(tlda_ctx* c, const tlda_csr_batch_u16* h, int32_t slot,
+                                 tlda_csr_batch* dev_out) {
+  if (!c) return TLDA_ERR_ARG;
+  CHECK_ARG(c, h && dev_out, TLDA_ERR_ARG, "host batch or output is NULL");
+  CHECK_ARG(c, slot == 0 || slot == 1, TLDA_ERR_ARG, "slot must be 0 or 1");
+  CHECK_ARG(c, c->cfg.V <= 65536, TLDA_ERR_SHAPE, "16-bit column indices need V <= 65536");
+  CHECK_ARG(c, h->n_rows >= 0 && h->nnz >= 0, TLDA_ERR_SHAPE, "negative n_rows or nnz");
+  CHECK_ARG(c, h->row_ptr != nullptr, TLDA_ERR_ARG, "row_ptr is NULL");
+  if (h->nnz > 0) CHECK_ARG(c, h->col_idx && h->val, TLDA_ERR_ARG, "col_idx or val is NULL");
+  tlda::StageSlot& s = c->slots[slot];
+  const size_t rows = (size_t)h->n_rows + 1, nnz = (size_t)h->nnz;
+  if (s.cap_rows < rows || s.cap_nnz < nnz || s.cap16 < nnz) {
+    if (s.used) HIP_OK(c, hipEventSynchronize(s.free_));
+    dfree(s.row_ptr); dfree(s.col_idx); dfree(s.val); dfree(s.col16); dfree(s.val16);
+    s.cap_rows = s.cap_nnz = s.cap16 = 0;
+    s.used = false;
+    const size_t r = rows, z = std::max<size_t>(nnz, 1);
+    HIP_OK(c, dalloc(&s.row_ptr, r));
+    HIP_OK(c, dalloc(&s.col_idx, z));
+    HIP_OK(c, dalloc(&s.val, z));
+    HIP_OK(c, dalloc(&s.col16, z));
+    HIP_OK(c, dalloc(&s.val16, z));
+    s.cap_rows = r;
+    s.cap_nnz = s.cap16 = z;
+  }
+  if (s.used) HIP_OK(c, hipStreamWaitEvent(c->copy_stream, s.free_, 0));
+  HIP_OK(c, hipMemcpyAsync(s.row_ptr, h->row_ptr, rows * sizeof(int32_t), hipMemcpyHostToDevice,
+                           c->copy_stream));
+  if (nnz) {
+    HIP_OK(c, hipMemcpyAsync(s.col16, h->col_idx, nnz * sizeof(uint16_t), hipMemcpyHostToDevice,
+                             c->copy_stream));
+    HIP_OK(c, hipMemcpyAsync(s.val16, h->val, nnz * sizeof(uint16_t), hipMemcpyHostToDevice,
+                             c->copy_stream));
+    HIP_OK(c, tlda::launch_widen_u16(s.col16, s.val16, nnz, s.col_idx, s.val, c->copy_stream));
+  }
+  HIP_OK(c, hipEventRecord(s.ready, c->copy_stream));
   HIP_OK(c, hipEventRecord(s.free_, c->copy_stream));
   s.used = true;
   dev_out->n_rows = h->n_rows;

@@ -31,6 +31,9 @@ struct StageSlot {
   int32_t* col_idx = nullptr;
   float* val = nullptr;
   size_t cap_rows = 0, cap_nnz = 0;
+  uint16_t* col16 = nullptr;    // compact staging copies (tlda_stage_batch_u16)
+  uint16_t* val16 = nullptr;
+  size_t cap16 = 0;
   hipEvent_t ready = nullptr;   // recorded on the copy stream after the copy
   hipEvent_t free_ = nullptr;   // recorded on the compute stream after consumers
   bool used = false;
@@ -251,6 +254,9 @@ hipError_t launch_validate_csr(const tlda_csr_batch& b, int V, int* err, hipStre
 hipError_t launch_accumulate(const tlda_csr_batch& b, int V, const Moments& m, int* block_counts,
                              bool classic, hipStream_t s);
 hipError_t launch_mirror_upper(double* S2, int V, hipStream_t s);
+// col[j] = col16[j], val[j] = val16[j] for j < nnz (compact staging)
+hipError_t launch_widen_u16(const uint16_t* col16, const uint16_t* val16, size_t nnz,
+                            int32_t* col, float* val, hipStream_t s);
 hipError_t launch_mean(const double* fsum, const unsigned long long* counts, double* m, int V,
                        hipStream_t s);
 // eigen-solver building blocks (FP64)

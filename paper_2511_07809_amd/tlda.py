@@ -36,7 +36,7 @@ TLDA_MLP_MAX_WIDTH = 1024
 EXPORTED = ("tlda_create", "tlda_destroy", "tlda_status_str", "tlda_last_error",
             "tlda_update_moments", "tlda_whiten_batch", "tlda_cp_step", "tlda_whiten_cp_step",
             "tlda_unwhiten",
-            "tlda_infer_doc_topics", "tlda_stage_batch", "tlda_get_stats",
+            "tlda_infer_doc_topics", "tlda_stage_batch", "tlda_stage_batch_u16", "tlda_get_stats",
             "tlda_get_whitening", "tlda_set_whitening", "tlda_rebase_phi",
             "tlda_set_timing_events",
             "tlda_save_state", "tlda_load_state",
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tlda_infer_doc_topics": ([vp, vp, i32, vp, i32, ctypes.c_float, vp], i32),
         "tlda_stage_batch": ([vp, ctypes.POINTER(tlda_csr_batch), i32,
                               ctypes.POINTER(tlda_csr_batch)], i32),
+        "tlda_stage_batch_u16": ([vp, vp, i32, ctypes.POINTER(tlda_csr_batch)], i32),
         "tlda_get_stats": ([vp, vp, vp, vp], i32),
         "tlda_get_whitening": ([vp, vp, vp, vp], i32),
         "tlda_set_whitening": ([vp, vp, vp], i32),
@@ -196,6 +197,32 @@ class CsrBatch:
                               self.val.data_ptr() if self.nnz else None, self.slot)
 
 
+class tlda_csr_batch_u16(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("nnz", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("val", ctypes.c_void_p)]
+
+
+class CsrBatchU16:
+    """A CSR batch in the compact staging format (pinned host memory):
+    int32 row pointers, 16-bit column indices and counts."""
+
+    def __init__(self, row_ptr, col_idx, val):
+        import numpy as np
+        assert col_idx.size == 0 or int(col_idx.max()) < 65536
+        assert val.size == 0 or (float(val.min()) >= 1 and float(val.max()) <= 65535)
+        self.n_rows = int(row_ptr.shape[0]) - 1
+        self.nnz = int(col_idx.shape[0])
+        self.row_ptr = torch.from_numpy(row_ptr.astype("int32")).pin_memory()
+        self.col_idx = torch.from_numpy(col_idx.astype(np.uint16).view(np.int16)).pin_memory()
+        self.val = torch.from_numpy(val.astype(np.uint16).view(np.int16)).pin_memory()
+
+    def struct(self) -> tlda_csr_batch_u16:
+        return tlda_csr_batch_u16(self.n_rows, self.nnz, self.row_ptr.data_ptr(),
+                                  self.col_idx.data_ptr() if self.nnz else None,
+                                  self.val.data_ptr() if self.nnz else None)
+
+
 class _StagedBatch(CsrBatch):
     def __init__(self, s: tlda_csr_batch, owner: CsrBatch):
         self._s = s
@@ -287,6 +314,13 @@ def tlda_stage_batch(ctx: Context, host_batch: CsrBatch, slot: int) -> CsrBatch:
     h = host_batch.struct()
     out = tlda_csr_batch()
     _check(ctx, _LIB.tlda_stage_batch(ctx.handle, ctypes.byref(h), slot, ctypes.byref(out)))
+    return _StagedBatch(out, host_batch)
+
+
+def tlda_stage_batch_u16(ctx: Context, host_batch: CsrBatchU16, slot: int) -> CsrBatch:
+    h = host_batch.struct()
+    out = tlda_csr_batch()
+    _check(ctx, _LIB.tlda_stage_batch_u16(ctx.handle, ctypes.byref(h), slot, ctypes.byref(out)))
     return _StagedBatch(out, host_batch)
 
 

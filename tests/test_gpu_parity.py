@@ -425,6 +425,36 @@ def test_staged_batches_equal_device_batches(c1):
         assert torch.equal(X, Xr)
 
 
+def test_compact_staged_batches_equal_device_batches(c1):
+    """16-bit staging (column indices and counts widened on the device) gives
+    bit-identical whitened rows and steps; a batch whose nonzero count grows
+    between uses of a slot, and an empty batch, are staged too."""
+    spec = c1["spec"]
+    ctx = make_ctx(spec.V, spec.K, spec.K, bf16=True)
+    tl.tlda_set_whitening(ctx, c1["W"], c1["m"])
+    rp0, ci0, va0 = make_csr_rows([], spec.V)
+    batches = [c1["batches"][1][:3], (rp0, ci0, va0)] + list(c1["batches"])
+    host = [tl.CsrBatchU16(*b) for b in batches]
+    Pd = torch.from_numpy(init_phi(spec.K, spec.K, 2).astype(np.float32)).cuda()
+    Pr = Pd.clone()
+    staged = [tl.tlda_stage_batch_u16(ctx, host[0], 0)]
+    for i in range(len(host)):
+        if i + 1 < len(host):
+            staged.append(tl.tlda_stage_batch_u16(ctx, host[i + 1], (i + 1) % 2))
+        X, _ = tl.tlda_whiten_batch(ctx, staged[i])
+        tl.tlda_whiten_cp_step(ctx, staged[i], 0.03, Pd)
+        torch.cuda.synchronize()
+        Xr, _ = tl.tlda_whiten_batch(ctx, dev_batch(*batches[i]))
+        tl.tlda_whiten_cp_step(ctx, dev_batch(*batches[i]), 0.03, Pr)
+        torch.cuda.synchronize()
+        assert torch.equal(X, Xr), i
+        assert torch.equal(Pd, Pr), i
+    big = make_ctx(70000, 4, 4)
+    with pytest.raises(tl.TldaError) as e:
+        tl.tlda_stage_batch_u16(big, host[2], 0)
+    assert e.value.status == 2
+
+
 def test_checkpoint_resume_is_bit_identical(c1):
     """A context restored from a checkpoint continues exactly like the one it
     was saved from: same W, same whitened batches, bit-identical factors."""
