@@ -181,7 +181,8 @@ def run_classic(args) -> None:
     log(f"[bench] generated {spec.name}: {corpus.n_docs} docs, {corpus.nnz} nnz")
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    ctx = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, classic=True, eig_iters=60)
+    bf16 = args.precision == "bf16"
+    ctx = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, classic=True, bf16=bf16, eig_iters=60)
     dev = [tl.CsrBatch.from_numpy(rp, ci, va) for rp, ci, va, _ in batches]
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -203,24 +204,26 @@ def run_classic(args) -> None:
     docs_per_s = r["docs"] / (r["total_ms"] / 1e3)
     kern_us = r["kern_ms"].mean(axis=0) * 1e3
     log(f"[bench] classic: {args.steps} steps {r['total_ms']:.3f} ms, step "
-        f"{r['step_ms'].mean() * 1e3:.1f} us, k_classic_cp {kern_us[0]:.1f} us, "
+        f"{r['step_ms'].mean() * 1e3:.1f} us, data-term kernel {kern_us[0]:.1f} us, "
         f"{docs_per_s:.4g} docs/s")
-    # roofline of k_classic_cp: reduction rows = nonzeros + documents, each a
-    # D x K outer product on FP32 matrix cores; bytes = CSR + W + Z, once
+    # roofline of the data-term kernel: one reduction row per nonzero, a D x K
+    # outer product on the matrix cores; bytes = CSR + W + Z copies, once
     per = args.steps
-    rows = (r["nnz"] + r["docs"]) / per
-    flops = 2.0 * rows * D * K
-    byts = (4 * (r["docs"] + per) + 8 * r["nnz"]) / per + 4 * spec.V * (D + K)
+    kname = "k_classic_cp16" if bf16 else "k_classic_cp"
+    peak = BF16_MFMA_PEAK_TFLOPS if bf16 else FP32_VALU_PEAK_TFLOPS
+    flops = 2.0 * (r["nnz"] / per) * D * K
+    elem = 2 if bf16 else 4
+    byts = (4 * (r["docs"] + per) + 8 * r["nnz"]) / per + elem * spec.V * (D + K)
     t_k = kern_us[0] / 1e6
-    mm_frac = flops / t_k / 1e12 / FP32_VALU_PEAK_TFLOPS
+    mm_frac = flops / t_k / 1e12 / peak
     hbm_frac = byts / t_k / 1e9 / HBM_PEAK_GBS
     if mm_frac >= hbm_frac:
-        roof = {"kernel": "k_classic_cp", "bound": "mfma", "achieved": flops / t_k / 1e12,
-                "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": mm_frac}
+        roof = {"kernel": kname, "bound": "mfma", "achieved": flops / t_k / 1e12,
+                "peak": peak, "unit": "TFLOP/s", "frac": mm_frac}
     else:
-        roof = {"kernel": "k_classic_cp", "bound": "hbm", "achieved": byts / t_k / 1e9,
+        roof = {"kernel": kname, "bound": "hbm", "achieved": byts / t_k / 1e9,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_frac}
-    roof.update({"traffic": measured_traffic("k_classic_cp", spec.name),
+    roof.update({"traffic": measured_traffic(kname, spec.name),
                  "algorithmic_flops": flops, "algorithmic_bytes": byts,
                  "mfma_frac": mm_frac, "hbm_frac": hbm_frac, "avg_launch_us": float(kern_us[0])})
     fit_beta = args.fit_beta
@@ -235,13 +238,14 @@ def run_classic(args) -> None:
         "metric": "docs/sec (whiten+CP step) at fixed topic-recovery error; % HBM roofline",
         "value": docs_per_s, "unit": "docs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["total_ms"] / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if bf16 else "f32", "data": "synthetic",
         "config": {"workload": f"{spec.name} classic rung: V={spec.V}, K=D={K}, "
                                f"alpha0={spec.alpha0}, {corpus.n_docs} docs of length "
                                f"1+Poisson({spec.doc_len_lambda:g}), batch {spec.batch}, "
                                "resident in HBM",
-                   "estimator": "classic", "global_batch": spec.batch, "beta": beta},
+                   "estimator": "classic", "precision": args.precision,
+                   "global_batch": spec.batch, "beta": beta},
         "roofline": roof,
         "breakdown": {"step_us": float(r["step_ms"].mean()) * 1e3,
                       "main_kernel_us": [float(x) for x in kern_us],

@@ -73,8 +73,12 @@ typedef enum {
  * tlda_cp_step and tlda_whiten_cp_step switch; their interfaces do not. */
 #define TLDA_BF16 0x2u
 /* Classic moments (the appendix's alpha0-corrected cumulants, used as an
- * estimator rung of the same batched SGD; FP32, requires D, K <= 128, else
- * TLDA_ERR_SHAPE; not combinable with TLDA_BF16, TLDA_ERR_ARG).
+ * estimator rung of the same batched SGD; requires D, K <= 128, else
+ * TLDA_ERR_SHAPE).  FP32 per-document arithmetic, or with TLDA_BF16: the
+ * data term then reads the BF16 whitening copy W16 (and W16^T M1), Z16 =
+ * bf16(W16 Phi), and its reduction rows are rounded to BF16 for the matrix
+ * cores with FP32 accumulation; the per-document sums and coefficients, the
+ * refresh, the penalty and the update stay FP64/FP32.
  *  - tlda_update_moments accumulates the unbiased pair piece
  *    P2 = (c c^T - diag c) / (L (L - 1)) per kept document in place of f f^T,
  *    and a refresh whitens M2 = (alpha0 + 1) sum P2 / N - alpha0 M1 M1^T.

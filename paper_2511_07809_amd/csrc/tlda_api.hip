@@ -343,6 +343,41 @@ tlda_status classic_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float
     return TLDA_OK;
   }
   const int V = c->cfg.V, D = c->cfg.D, K = c->cfg.K;
+  if (is_bf16(c)) {
+    const int Kh = tlda::bf16_cols(K);
+    if (c->cp.Z16 == nullptr) {
+      HIP_OK(c, dalloc(&c->cp.Z16, (size_t)V * Kh));
+      if (c->cp.rz == nullptr) HIP_OK(c, dalloc(&c->cp.rz, (size_t)Kh));
+    }
+    if (c->tune.classic16_resident <= 0) {
+      int per_cu = 0;
+      HIP_OK(c, tlda::launch_classic_cp16(*b, c->wh.W16, c->Dh, c->cp.Z16, Kh, c->wh.mw16,
+                                          c->cp.rz, D, K, c->cfg.alpha0, 0, nullptr, &per_cu,
+                                          c->stream));
+      c->tune.classic16_resident = (per_cu > 0 ? per_cu : 1) * c->num_cu;
+    }
+    const int ntiles = (b->n_rows + 15) / 16;
+    int nblk = ntiles < c->tune.classic16_resident ? ntiles : c->tune.classic16_resident;
+    if (nblk > 2 * tlda::kWhitenBlockCounts) nblk = 2 * tlda::kWhitenBlockCounts;
+    st = ensure_partial(c, (size_t)nblk * D * K);
+    if (st != TLDA_OK) return st;
+    float* g = grad ? grad : c->cp.grad;
+    HIP_OK(c, tlda::launch_classic_z16(c->wh.W16, V, D, c->Dh, Phi, K, Kh, c->wh.mw16, c->cp.Z16,
+                                       c->cp.rz, c->cp.phi0, c->num_cu, c->stream));
+    st = begin_use(c, b);
+    if (st != TLDA_OK) return st;
+    HIP_OK(c, timing_start(c));
+    HIP_OK(c, tlda::launch_classic_cp16(*b, c->wh.W16, c->Dh, c->cp.Z16, Kh, c->wh.mw16, c->cp.rz,
+                                        D, K, c->cfg.alpha0, nblk, c->cp.partial, c->block_counts,
+                                        c->stream));
+    HIP_OK(c, timing_stop(c));
+    st = end_use(c, b);
+    if (st != TLDA_OK) return st;
+    HIP_OK(c, tlda::launch_cp_finish(c->cp.partial, nblk, c->block_counts, nblk, 0, c->cp.phi0, D,
+                                     K, c->cfg.alpha0, c->cfg.theta, beta, Phi, g, c->cp.R1,
+                                     n_kept_out, c->stream));
+    return TLDA_OK;
+  }
   const int Kp = tlda::padded_d(K);
   if (c->cp.Z == nullptr) {
     HIP_OK(c, dalloc(&c->cp.Z, (size_t)V * Kp));
@@ -390,7 +425,7 @@ void destroy_all(tlda_ctx* c) {
   dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
   dfree(e.sel); dfree(e.mcand); dfree(e.info); dfree(e.part);
   dfree(c->cp.partial); dfree(c->cp.R1); dfree(c->cp.phi0); dfree(c->cp.grad); dfree(c->cp.X);
-  dfree(c->cp.Z); dfree(c->cp.rz);
+  dfree(c->cp.Z); dfree(c->cp.rz); dfree(c->cp.Z16);
   dfree(c->post); dfree(c->postA); dfree(c->postG); dfree(c->postZ); dfree(c->postEv);
   dfree(c->A32); dfree(c->G32); dfree(c->step32); dfree(c->dev_flags); dfree(c->block_counts);
   for (auto& s : c->slots) {
@@ -431,7 +466,6 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
   if (!(c.alpha0 > 0.0) || !std::isfinite(c.alpha0)) return TLDA_ERR_ARG;
   if (!(c.theta >= 0.0) || !std::isfinite(c.theta)) return TLDA_ERR_ARG;
   if (c.flags & ~(TLDA_VALIDATE_CSR | TLDA_BF16 | TLDA_CLASSIC)) return TLDA_ERR_ARG;
-  if ((c.flags & TLDA_BF16) && (c.flags & TLDA_CLASSIC)) return TLDA_ERR_ARG;
   if (c.eig_iters < 0 || c.eig_block < 0) return TLDA_ERR_ARG;
   if (c.V < 3 || c.V > 131072) return TLDA_ERR_SHAPE;
   if (c.K < 1 || c.K > TLDA_MAX_K || c.D < 1 || c.D > TLDA_MAX_D || c.D > c.V) return TLDA_ERR_SHAPE;

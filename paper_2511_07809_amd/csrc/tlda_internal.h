@@ -93,6 +93,7 @@ struct Tuning {
   int bf16_blocks = 0;
   int bf16_resident[3] = {0, 0, 0};   // cached occupancy rounds of the BF16 kernels
   int classic_resident = 0;           // the same for the classic-moment kernel
+  int classic16_resident = 0;         // and its BF16 variant
   int whiten_v4 = 0;
   int whiten_chunks = 0;
 };
@@ -107,6 +108,7 @@ struct CpScratch {
   size_t cap_x = 0;
   float* Z = nullptr;         // [V][Kp] W Phi of the classic-moment step
   float* rz = nullptr;        // [Kp]    Phi^T W^T M1 of the classic-moment step
+  uint16_t* Z16 = nullptr;    // [V][Kh] bf16(W16 Phi) of the BF16 classic-moment step
 };
 
 }  // namespace tlda
@@ -341,6 +343,14 @@ bool classic_supported(int D, int K);
 hipError_t launch_classic_z(const float* W32, int V, int D, int Dp, const float* Phi, int K,
                             int Kp, const float* mw32, float* Z, float* r, float* phi_copy,
                             int num_cu, hipStream_t s);
+// BF16 variant: Z16 = bf16(W16 Phi) (V x Kh, Kh = bf16_cols(K)), r = Phi^T mw16
+hipError_t launch_classic_z16(const uint16_t* W16, int V, int D, int Dh, const float* Phi, int K,
+                              int Kh, const float* mw16, uint16_t* Z16, float* r, float* phi_copy,
+                              int num_cu, hipStream_t s);
+hipError_t launch_classic_cp16(const tlda_csr_batch& b, const uint16_t* W16, int Dh,
+                               const uint16_t* Z16, int Kh, const float* mw16, const float* r,
+                               int D, int K, double alpha0, int nblk, float* partial,
+                               int* block_counts, hipStream_t s);
 hipError_t launch_classic_cp(const tlda_csr_batch& b, const float* W32, int Dp, const float* Z,
                              int Kp, const float* mw32, const float* r, int D, int K,
                              double alpha0, int nblk, float* partial, int* block_counts,

@@ -76,6 +76,35 @@ def test_classic_gradient_and_step_match_oracle(D, K, n, theta):
     assert rel(Pd.cpu().numpy(), P64 - beta * ref_g) < 1e-5
 
 
+@pytest.mark.parametrize("D,K,n", [(5, 5, 1000), (20, 30, 777), (50, 50, 1203), (64, 64, 300),
+                                   (100, 100, 229), (128, 128, 130), (3, 12, 64), (1, 1, 37)])
+def test_classic_bf16_gradient_matches_oracle(D, K, n):
+    """BF16 classic rung: W16 = bf16(W) for the gathers, Z16 = bf16(W16 Phi),
+    reduction rows rounded to BF16 for the matrix cores.  Running the same
+    implicit formula with these roundings in numpy leaves 0.3-0.5% relative
+    error on the data term; the bar is 2e-2 on the data term recovered from
+    the gradient and on the gradient itself."""
+    rp, ci, va = _rows(n, D * 37 + K, long_rows=3)
+    W, m = _whitening(D, D * 11 + K)
+    a0, theta = 1.5, 0.5
+    Phi = (init_phi(D, K, D + K) * 0.3).astype(np.float32)
+    ctx = tl.tlda_create(V, K, D, a0, theta, classic=True, bf16=True)
+    tl.tlda_set_whitening(ctx, W, m)
+    Pd = torch.from_numpy(Phi).cuda()
+    g = torch.empty_like(Pd)
+    nk = torch.zeros(1, dtype=torch.int32, device="cuda")
+    tl.tlda_whiten_cp_step(ctx, tl.CsrBatch.from_numpy(rp, ci, va), 1e-3, Pd, g, None, nk)
+    torch.cuda.synchronize()
+    P64 = Phi.astype(np.float64)
+    data, n_kept = O.classic_data_term(rp, ci, va, V, m, W, P64, a0)
+    assert int(nk.item()) == n_kept
+    gg = g.cpu().numpy().astype(np.float64)
+    G = P64.T @ P64
+    pen = 3.0 * (1.0 + theta) * P64 @ (G * G)
+    assert rel((pen - gg) * n_kept / 3.0, data) < 2e-2
+    assert rel(gg, O.classic_cp_gradient(rp, ci, va, V, m, W, P64, a0, theta)) < 2e-2
+
+
 def test_classic_step_writes_whitened_rows_and_skips_empty_batches():
     D = K = 8
     rp, ci, va = _rows(300, 5)
@@ -192,9 +221,6 @@ def test_classic_fit_matches_oracle_fit(c1_classic):
 
 def test_classic_config_errors():
     with pytest.raises(tl.TldaError) as e:
-        tl.tlda_create(V, 10, 10, 1.0, bf16=True, classic=True)
-    assert e.value.status == 1
-    with pytest.raises(tl.TldaError) as e:
         tl.tlda_create(V, 10, 130, 1.0, classic=True)
     assert e.value.status == 2
     ctx = tl.tlda_create(V, 4, 4, 1.0, classic=True)
@@ -207,10 +233,12 @@ def test_classic_config_errors():
     assert e.value.status == 4
 
 
-def test_classic_step_full_size_tweet_batch():
+@pytest.mark.parametrize("bf16", [False, True])
+def test_classic_step_full_size_tweet_batch(bf16):
     """One full 131 072-document batch of the tweet-shaped workload (V = 20 000,
     K = D = 50), the launch configuration the benchmark times, against the
-    oracle's per-document gradient over the same batch."""
+    oracle's per-document gradient over the same batch (FP32 1e-5, BF16
+    2e-2)."""
     spec = SPECS["c2"]
     c = generate(spec, n_docs=spec.batch)
     rp, ci, va, _ = next(iter_batches(c))
@@ -220,7 +248,7 @@ def test_classic_step_full_size_tweet_batch():
     W = Q * rng.uniform(20, 200, size=D)[None, :]
     m = np.bincount(ci, weights=va, minlength=spec.V) / va.sum()
     Phi = (init_phi(D, K, 9) * 0.3).astype(np.float32)
-    ctx = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, classic=True)
+    ctx = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, classic=True, bf16=bf16)
     tl.tlda_set_whitening(ctx, W, m)
     Pd = torch.from_numpy(Phi).cuda()
     g = torch.empty_like(Pd)
@@ -228,4 +256,4 @@ def test_classic_step_full_size_tweet_batch():
     torch.cuda.synchronize()
     ref = O.classic_cp_gradient(rp, ci, va, spec.V, m, W, Phi.astype(np.float64), spec.alpha0,
                                 0.0)
-    assert rel(g.cpu().numpy(), ref) < 1e-5
+    assert rel(g.cpu().numpy(), ref) < (2e-2 if bf16 else 1e-5)

@@ -65,7 +65,6 @@ def test_create_validates_config_before_touching_a_device(lib):
         return lib.tlda_create(ctypes.byref(cfg), None, ctypes.byref(out))
 
     assert create(100, 10, 10, 0x8) == 1                       # unknown flag
-    assert create(100, 10, 10, tlda.TLDA_BF16 | tlda.TLDA_CLASSIC) == 1   # not combinable
     assert create(100, 10, 10, 0, alpha0=0.0) == 1             # alpha0 must be > 0
     assert create(100, 10, 10, 0, theta=-1.0) == 1             # theta must be >= 0
     assert create(2, 1, 1, 0) == 2                             # V < 3
