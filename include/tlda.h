@@ -356,8 +356,9 @@ typedef struct tlda_graph tlda_graph;
  * step sizes.  n_kept_out: device int32 [n_slices] or NULL, receives the
  * kept-row counts at each step.  Batches of contexts created with
  * TLDA_VALIDATE_CSR are validated once, here.  TLDA_ERR_SHAPE for a context
- * that is not BF16 or has D or K above 64; TLDA_ERR_STATE without a
- * whitening matrix. */
+ * that is not BF16 or has D or K above 64; TLDA_ERR_ARG for a classic-moment
+ * context (TLDA_CLASSIC: the multi-slice step is the centred one);
+ * TLDA_ERR_STATE without a whitening matrix. */
 tlda_status tlda_multi_create(int32_t n_slices, tlda_ctx* const* ctxs,
                               const tlda_csr_batch* batches, float* const* Phis,
                               const float* betas, int32_t* n_kept_out, tlda_multi** out);

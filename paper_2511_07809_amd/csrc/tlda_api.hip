@@ -1239,6 +1239,7 @@ tlda_status tlda_multi_create(int32_t n_slices, tlda_ctx* const* ctxs,
   for (int i = 0; i < n_slices; ++i) {
     tlda_ctx* c = ctxs[i];
     if (!c || !Phis[i] || !std::isfinite(betas[i])) return TLDA_ERR_ARG;
+    if (is_classic(c)) return TLDA_ERR_ARG;   // the multi-slice step is the centred one
     if (!is_bf16(c) || tlda::multi_shape(c->cfg.D, c->cfg.K) < 0) return TLDA_ERR_SHAPE;
     if (!c->wh.ready) return TLDA_ERR_STATE;
     if (c->stream != ctxs[0]->stream) return TLDA_ERR_ARG;

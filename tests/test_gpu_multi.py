@@ -173,6 +173,13 @@ def test_multi_rejects_bad_plans(side_stream):
     with pytest.raises(tl.TldaError) as e:
         tl.tlda_multi_create([ctxs[0], big], batches, Ps, [1e-3, 1e-3])
     assert e.value.status == 2
+    classic = tl.tlda_create(V, 20, 20, 1.0, bf16=True, classic=True, stream=side_stream)
+    rng0 = np.random.default_rng(3)
+    tl.tlda_set_whitening(classic, np.linalg.qr(rng0.standard_normal((V, 20)))[0] * 10,
+                          rng0.dirichlet(np.ones(V)))
+    with pytest.raises(tl.TldaError) as e:
+        tl.tlda_multi_create([ctxs[0], classic], batches, Ps, [1e-3, 1e-3])
+    assert e.value.status == 1
     nowhite = tl.tlda_create(V, 20, 20, 1.0, bf16=True, stream=side_stream)
     with pytest.raises(tl.TldaError) as e:
         tl.tlda_multi_create([ctxs[0], nowhite], batches, Ps, [1e-3, 1e-3])
