@@ -403,7 +403,10 @@ void tlda_graph_destroy(tlda_graph* graph);
  * (arrays may be NULL) turns the hook off.  Not synchronous. */
 tlda_status tlda_set_timing_events(tlda_ctx* ctx, void* const* start, void* const* stop,
                                    int32_t n);
-/* Checkpoint of the moment state and W.  buf == NULL: *len receives the size. */
+/* Checkpoint of the moment state and W.  buf == NULL: *len receives the size.
+ * The checkpoint records whether the moments are classic (TLDA_CLASSIC) or
+ * centred; loading into a context of the other kind, or of another V, K or
+ * D, is refused (TLDA_ERR_ARG / TLDA_ERR_SHAPE) with the context unchanged. */
 tlda_status tlda_save_state(tlda_ctx* ctx, void* buf, size_t* len);
 tlda_status tlda_load_state(tlda_ctx* ctx, const void* buf, size_t len);
 

@@ -1509,7 +1509,7 @@ namespace {
 constexpr uint32_t kMagic = 0x41444c54u;   // "TLDA"
 struct Header {
   uint32_t magic, version;
-  int32_t V, K, D, has_s2, ready, pad;
+  int32_t V, K, D, has_s2, ready, moments;   // moments: 1 = classic (TLDA_CLASSIC), 0 = centred
 };
 }  // namespace
 
@@ -1526,7 +1526,8 @@ tlda_status tlda_save_state(tlda_ctx* c, void* buf, size_t* len) {
   }
   CHECK_ARG(c, *len >= need, TLDA_ERR_SHAPE, "checkpoint buffer too small");
   char* p = static_cast<char*>(buf);
-  Header h{kMagic, 1u, (int32_t)V, c->cfg.K, (int32_t)D, has_s2 ? 1 : 0, c->wh.ready ? 1 : 0, 0};
+  Header h{kMagic, 1u, (int32_t)V, c->cfg.K, (int32_t)D, has_s2 ? 1 : 0, c->wh.ready ? 1 : 0,
+           is_classic(c) ? 1 : 0};
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
   auto d2h = [&](const void* src, size_t bytes) -> hipError_t {
@@ -1557,6 +1558,8 @@ tlda_status tlda_load_state(tlda_ctx* c, const void* buf, size_t len) {
   CHECK_ARG(c, h.magic == kMagic && h.version == 1u, TLDA_ERR_ARG, "not a checkpoint of this format");
   CHECK_ARG(c, h.V == c->cfg.V && h.K == c->cfg.K && h.D == c->cfg.D, TLDA_ERR_SHAPE,
             "checkpoint shape does not match the context");
+  CHECK_ARG(c, (h.moments == 1) == is_classic(c), TLDA_ERR_ARG,
+            "checkpoint moments (classic or centred) do not match the context");
   const size_t V = c->cfg.V, D = c->cfg.D;
   size_t need = sizeof(Header) + 16 + V * 16;
   if (h.has_s2) need += V * V * 8;

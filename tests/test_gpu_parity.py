@@ -470,6 +470,10 @@ def test_checkpoint_resume_is_bit_identical(c1):
     blob = tl.tlda_save_state(a)                # interrupted after the refresh
     b_ctx = make_ctx(spec.V, spec.K, spec.K, spec.alpha0)
     tl.tlda_load_state(b_ctx, blob)
+    classic = make_ctx(spec.V, spec.K, spec.K, spec.alpha0, classic=True)
+    with pytest.raises(tl.TldaError) as e:       # centred moments into a classic context
+        tl.tlda_load_state(classic, blob)
+    assert e.value.status == 1
     c_ctx = make_ctx(spec.V, spec.K, spec.K, spec.alpha0)
     tl.tlda_load_state(c_ctx, mid)
     for b in dbs[3:]:
