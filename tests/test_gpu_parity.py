@@ -344,6 +344,51 @@ def test_fused_step_equals_split_steps_at_full_size():
     assert rel(outs[0].numpy(), P2.cpu().numpy()) < REL32
 
 
+def _full_batch_reference(spec, rp, ci, va, W, m, Phi, theta, check_rows, rng):
+    """X of a full batch as the sparse product F W - 1 (W^T M1)^T (dropped rows
+    zero), tied to the oracle's whitening on sampled rows, and the oracle's
+    gradient on it."""
+    import scipy.sparse as sp
+    st = O.batch_stats(rp, ci, va, spec.V)
+    F = sp.csr_matrix((va.astype(np.float64), ci, rp), shape=(rp.size - 1, spec.V))
+    Ld = np.asarray(F.sum(axis=1)).ravel()
+    F = sp.diags(1.0 / np.maximum(Ld, 1.0)) @ F
+    X = F @ W - (W.T @ m)[None, :]
+    X[~st["keep"]] = 0.0
+    for r in rng.choice(rp.size - 1, check_rows, replace=False):
+        a, b = int(rp[r]), int(rp[r + 1])
+        one = O.whiten(np.array([0, b - a]), ci[a:b], va[a:b], spec.V, m, W)[0]
+        np.testing.assert_allclose(X[r], one, rtol=0, atol=1e-12 * max(1.0, np.abs(one).max()))
+    g = O.cp_gradient(X, Phi.astype(np.float64), st["n_kept"], spec.alpha0, theta)
+    return X, g, st["n_kept"]
+
+
+@pytest.mark.parametrize("theta", [0.0, 1.0])
+def test_fused_step_full_size_matches_oracle(theta):
+    """The fused FP32 step on one full 131 072-document batch of the
+    tweet-shaped workload, in the benchmark's launch configuration, against
+    the oracle's gradient of the same batch."""
+    spec = SPECS["c2"]
+    c = generate(spec, n_docs=spec.batch)
+    rp, ci, va, _ = next(iter_batches(c))
+    D = K = spec.K
+    rng = np.random.default_rng(31)
+    Q, _ = np.linalg.qr(rng.standard_normal((spec.V, D)))
+    W = Q * rng.uniform(20, 200, size=D)[None, :]
+    m = np.bincount(ci, weights=va, minlength=spec.V) / va.sum()
+    Phi = (init_phi(D, K, 3) * 0.5).astype(np.float32)
+    _, g_ref, n_kept = _full_batch_reference(spec, rp, ci, va, W, m, Phi, theta, 50, rng)
+    ctx = make_ctx(spec.V, K, D, spec.alpha0, theta)
+    tl.tlda_set_whitening(ctx, W, m)
+    Pd = torch.from_numpy(Phi).cuda()
+    g = torch.empty_like(Pd)
+    nk = torch.zeros(1, dtype=torch.int32, device="cuda")
+    tl.tlda_whiten_cp_step(ctx, dev_batch(rp, ci, va), 1e-4, Pd, g, None, nk)
+    torch.cuda.synchronize()
+    assert int(nk.item()) == n_kept
+    assert rel(g.cpu().numpy(), g_ref) < REL32
+
+
 # ----------------------------------------------------------------------------
 # boundary: unwhitening and inference
 # ----------------------------------------------------------------------------
