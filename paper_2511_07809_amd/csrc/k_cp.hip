@@ -389,7 +389,14 @@ __global__ void __launch_bounds__(kFinThreads) k_cp_finish(
     float beta, float* __restrict__ Phi, float* __restrict__ grad, double* __restrict__ R1,
     int* __restrict__ n_out) {
   extern __shared__ float ph[];                 // [D][K] copy of Phi0
-  cp_finish_block(blockIdx.x, partial, nblk, counts, ncounts, n_default, Phi0, D, K, alpha0, theta,
+  // Workgroups go to the 8 XCDs in turn; block b takes entry chunk
+  // (b % 8) per + b / 8, so each XCD reads one contiguous run of every
+  // partial row and no cache line of it is fetched by two XCDs.  The grid is
+  // 8 per blocks; those past the last chunk have nothing to do.
+  const int per = gridDim.x / 8;
+  const int chunk = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (chunk * kFinEntries >= D * K) return;
+  cp_finish_block(chunk, partial, nblk, counts, ncounts, n_default, Phi0, D, K, alpha0, theta,
                   beta, Phi, grad, R1, n_out, ph);
 }
 
@@ -513,7 +520,8 @@ hipError_t launch_cp_finish(const float* partial, int nblk, const int* counts, i
                             double theta, float beta, float* Phi, float* grad, double* R1,
                             int* n_out, hipStream_t s) {
   const int DK = D * K;
-  hipLaunchKernelGGL(k_cp_finish, dim3((DK + kFinEntries - 1) / kFinEntries), dim3(kFinThreads),
+  const int chunks = (DK + kFinEntries - 1) / kFinEntries;
+  hipLaunchKernelGGL(k_cp_finish, dim3(8 * ((chunks + 7) / 8)), dim3(kFinThreads),
                      sizeof(float) * DK, s, partial, nblk, counts, ncounts, n_default, Phi0, D, K,
                      alpha0, theta, beta, Phi, grad, R1, n_out);
   return hipGetLastError();
