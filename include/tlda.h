@@ -101,7 +101,11 @@ typedef enum {
 typedef struct {
   int32_t V;            /* vocabulary size, 3 <= V <= 131072                       */
   int32_t K;            /* number of topics, 1 <= K <= TLDA_MAX_K                   */
-  int32_t D;            /* whitening size, 1 <= D <= min(V, TLDA_MAX_D), D*K bound  */
+  int32_t D;            /* whitening size, 1 <= D <= min(V, TLDA_MAX_D), D*K bound;
+                         * an FP32 context (neither TLDA_BF16 nor TLDA_CLASSIC) also
+                         * needs Dq Kq + 4 (Dq + Kq) <= 16384 with Dq, Kq = D, K
+                         * rounded up to multiples of 4 (Phi and a 4-row tile in
+                         * 64 KiB of LDS): D = K = 120 passes, 128 x 128 does not */
   int32_t flags;        /* TLDA_VALIDATE_CSR | TLDA_BF16 | TLDA_CLASSIC            */
   double alpha0;        /* topic mixing parameter, > 0                             */
   double theta;         /* orthogonality penalty of eq. full_vec_pb, >= 0          */

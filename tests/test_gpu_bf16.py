@@ -220,6 +220,36 @@ def test_bf16_fused_step_matches_rounded_oracle(D, K):
     assert rel(Pd.cpu().numpy(), Phi0.astype(np.float64) - beta * got) < 1e-6
 
 
+def test_bf16_fused_step_at_the_largest_vocabulary():
+    """V = 131 072, the largest vocabulary a context takes, with column
+    indices over the whole range (0 and V - 1 included): the fused BF16 step
+    against the oracle on the rounded whitening, to the bound above."""
+    V, D, K = 131072, 50, 50
+    rng = np.random.default_rng(131)
+    rp, ci, va = make_csr_rows([{0: 2, V - 1: 1, V // 2: 1}, {V - 1: 3}] + [
+        {int(w): int(rng.integers(1, 4)) for w in rng.choice(V, size=rng.integers(1, 45),
+                                                              replace=False)}
+        for _ in range(600)], V)
+    W, m = _whitening(V, D, seed=132, lo=200.0, hi=2000.0)
+    a0, theta, beta = 1.0, 0.0, 1e-3
+    ctx = make_ctx(V, K, D, a0, theta)
+    tl.tlda_set_whitening(ctx, W, m)
+    Phi0 = (init_phi(D, K, 4) * 0.8).astype(np.float32)
+    Pd = torch.from_numpy(Phi0).cuda()
+    g = torch.empty_like(Pd)
+    n_rows = len(rp) - 1
+    Xo = torch.empty((n_rows, D), dtype=torch.float32, device="cuda")
+    nk = torch.empty(1, dtype=torch.int32, device="cuda")
+    tl.tlda_whiten_cp_step(ctx, dev_batch(rp, ci, va), beta, Pd, g, Xo, nk)
+    X_ref = O.whiten(rp, ci, va, V, m, bf16_round(W))
+    n_ref = O.batch_stats(rp, ci, va, V)["n_kept"]
+    assert int(nk.item()) == n_ref
+    assert rel(Xo.cpu().numpy(), X_ref) < REL32
+    ref, B, C = rounded_gradient(X_ref, Phi0, n_ref, a0, theta)
+    got = g.cpu().numpy().astype(np.float64)
+    _assert_within(got, ref, 4 * U_BF16 * (B + C) + 2.0 ** -22 * np.abs(ref), "fused gradient")
+
+
 def test_bf16_fused_step_full_size_matches_oracle():
     """The fused BF16 step on one full 131 072-document batch of the
     tweet-shaped workload (the benchmarked configuration) against the oracle's

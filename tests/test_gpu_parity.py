@@ -203,7 +203,8 @@ def _cp_case(n, D, K, seed, scale=1.0):
 
 @pytest.mark.parametrize("D,K,n", [(5, 5, 1000), (10, 10, 3001), (20, 20, 777), (50, 50, 4099),
                                    (64, 64, 2048), (100, 100, 1500), (128, 100, 515),
-                                   (7, 3, 999), (3, 12, 64), (1, 1, 5), (30, 60, 333)])
+                                   (7, 3, 999), (3, 12, 64), (1, 1, 5), (30, 60, 333),
+                                   (120, 120, 300), (256, 56, 257), (56, 256, 129)])
 @pytest.mark.parametrize("theta", [0.0, 1.0])
 def test_cp_gradient_and_step_match_oracle(D, K, n, theta):
     a0 = 1.0 if D != 100 else 2.0
@@ -218,6 +219,18 @@ def test_cp_gradient_and_step_match_oracle(D, K, n, theta):
     assert rel(g.cpu().numpy(), ref_g) < REL32
     ref_p = Phi.astype(np.float64) - beta * ref_g
     assert rel(Pd.cpu().numpy(), ref_p) < REL32
+
+
+@pytest.mark.parametrize("D,K", [(128, 128), (256, 64), (64, 256), (124, 128)])
+def test_fp32_context_beyond_the_lds_tile_is_rejected(D, K):
+    """Shapes within D*K <= TLDA_MAX_DK but over the FP32 reduction's LDS
+    tile (Phi plus a 4-row tile in 64 KiB) are refused at creation; the BF16
+    path takes 128 x 128."""
+    with pytest.raises(tl.TldaError) as e:
+        make_ctx(max(D, 3), K, D)
+    assert e.value.status == 2
+    if D <= 128 and K <= 128:
+        tl.tlda_create(max(D, 3), K, D, 1.0, 0.0, bf16=True)
 
 
 def test_cp_step_uses_kept_count_and_skips_empty_batches():
@@ -282,7 +295,7 @@ def test_cp_step_full_size_streaming_shape():
 # fused whitening + CP step
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("D,K", [(5, 5), (10, 7), (20, 20), (33, 40), (50, 50), (64, 64),
-                                 (100, 100), (128, 96), (150, 40)])
+                                 (100, 100), (128, 96), (150, 40), (256, 56), (56, 256)])
 def test_fused_step_matches_oracle(D, K):
     """tlda_whiten_cp_step against the oracle's whitening and gradient on the
     same batch (rows with dropped and empty documents included)."""
@@ -300,6 +313,38 @@ def test_fused_step_matches_oracle(D, K):
     ctx = make_ctx(V, K, D, a0, theta)
     tl.tlda_set_whitening(ctx, W, m)
     Phi0 = (init_phi(D, K, 2) * 0.8).astype(np.float32)
+    Pd = torch.from_numpy(Phi0).cuda()
+    g = torch.empty_like(Pd)
+    Xo = torch.empty((len(rows), D), dtype=torch.float32, device="cuda")
+    nk = torch.empty(1, dtype=torch.int32, device="cuda")
+    tl.tlda_whiten_cp_step(ctx, dev_batch(rp, ci, va), beta, Pd, g, Xo, nk)
+    X_ref = O.whiten(rp, ci, va, V, m, W)
+    n_ref = O.batch_stats(rp, ci, va, V)["n_kept"]
+    g_ref = O.cp_gradient(X_ref, Phi0.astype(np.float64), n_ref, a0, theta)
+    assert int(nk.item()) == n_ref
+    assert rel(Xo.cpu().numpy(), X_ref) < REL32
+    assert rel(g.cpu().numpy(), g_ref) < REL32
+    assert rel(Pd.cpu().numpy(), Phi0 - beta * g_ref) < REL32
+
+
+def test_fused_step_at_the_largest_vocabulary():
+    """V = 131 072, the largest vocabulary a context takes, with column
+    indices over the whole range (0 and V - 1 included): the fused step
+    against the oracle's whitening and gradient."""
+    V, D, K = 131072, 50, 50
+    rng = np.random.default_rng(131)
+    rows = [{0: 2, V - 1: 1, V // 2: 1}, {V - 1: 3}]
+    for _ in range(600):
+        words = rng.choice(V, size=rng.integers(1, 45), replace=False)
+        rows.append({int(w): int(rng.integers(1, 4)) for w in words})
+    rp, ci, va = make_csr_rows(rows, V)
+    Q, _ = np.linalg.qr(rng.standard_normal((V, D)))
+    W = Q * rng.uniform(200, 2000, size=D)[None, :]
+    m = rng.dirichlet(np.ones(V))
+    a0, theta, beta = 1.0, 0.0, 1e-3
+    ctx = make_ctx(V, K, D, a0, theta)
+    tl.tlda_set_whitening(ctx, W, m)
+    Phi0 = (init_phi(D, K, 4) * 0.8).astype(np.float32)
     Pd = torch.from_numpy(Phi0).cuda()
     g = torch.empty_like(Pd)
     Xo = torch.empty((len(rows), D), dtype=torch.float32, device="cuda")
