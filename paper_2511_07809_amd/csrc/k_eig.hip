@@ -473,32 +473,67 @@ __global__ void __launch_bounds__(1024) k_jacobi_lds(double* __restrict__ Ag, do
         sn[k] = s;
       }
       __syncthreads();
-      // columns i, j of A and Z
-      for (int idx = tid; idx < half * p; idx += nt) {
-        const int k = idx / p, row = idx % p;
-        const int i = pi[k], j = pj[k];
-        const double s = sn[k];
-        if (j >= p || s == 0.0) continue;
-        const double c = cs[k];
-        const double ai = A[(size_t)row * p + i], aj = A[(size_t)row * p + j];
-        A[(size_t)row * p + i] = c * ai - s * aj;
-        A[(size_t)row * p + j] = s * ai + c * aj;
-        const double zi = Z[(size_t)row * p + i], zj = Z[(size_t)row * p + j];
-        Z[(size_t)row * p + i] = c * zi - s * zj;
-        Z[(size_t)row * p + j] = s * zi + c * zj;
+      // A <- J^T A J in one pass: a thread owns the 2 x 2 block of A at the
+      // rows of pair a and the columns of pair b, rotated by b's columns and
+      // then by a's rows (the same operations, in the same order, as a column
+      // pass followed by a row pass).  Entries at the padding index p do not
+      // exist.
+      for (int idx = tid; idx < half * half; idx += nt) {
+        const int a = idx / half, b = idx % half;
+        const double sa = sn[a], sb = sn[b];
+        if (sa == 0.0 && sb == 0.0) continue;
+        const int ia = pi[a], ja = pj[a], ib = pi[b], jb = pj[b];
+        const bool ra = ja < p, rb = jb < p;
+        const double ca = cs[a], cb = cs[b];
+        double x00 = A[(size_t)ia * p + ib];
+        double x01 = rb ? A[(size_t)ia * p + jb] : 0.0;
+        double x10 = ra ? A[(size_t)ja * p + ib] : 0.0;
+        double x11 = ra && rb ? A[(size_t)ja * p + jb] : 0.0;
+        if (sb != 0.0) {
+          const double y00 = cb * x00 - sb * x01, y01 = sb * x00 + cb * x01;
+          const double y10 = cb * x10 - sb * x11, y11 = sb * x10 + cb * x11;
+          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+        }
+        if (sa != 0.0) {
+          const double y00 = ca * x00 - sa * x10, y10 = sa * x00 + ca * x10;
+          const double y01 = ca * x01 - sa * x11, y11 = sa * x01 + ca * x11;
+          x00 = y00; x01 = y01; x10 = y10; x11 = y11;
+        }
+        A[(size_t)ia * p + ib] = x00;
+        if (rb) A[(size_t)ia * p + jb] = x01;
+        if (ra) A[(size_t)ja * p + ib] = x10;
+        if (ra && rb) A[(size_t)ja * p + jb] = x11;
       }
-      __threadfence_block();
-      __syncthreads();
-      // rows i, j of A
-      for (int idx = tid; idx < half * p; idx += nt) {
-        const int k = idx / p, col = idx % p;
-        const int i = pi[k], j = pj[k];
-        const double s = sn[k];
-        if (j >= p || s == 0.0) continue;
-        const double c = cs[k];
-        const double ai = A[(size_t)i * p + col], aj = A[(size_t)j * p + col];
-        A[(size_t)i * p + col] = c * ai - s * aj;
-        A[(size_t)j * p + col] = s * ai + c * aj;
+      // Z <- Z J: consecutive threads take consecutive pairs of one row, and
+      // each thread issues all its loads before its stores
+      constexpr int kZ = 8;
+      for (int base = 0; base < half * p; base += kZ * nt) {
+        double zi[kZ], zj[kZ];
+#pragma unroll
+        for (int u = 0; u < kZ; ++u) {
+          const int idx = base + u * nt + tid;
+          zi[u] = zj[u] = 0.0;
+          if (idx < half * p) {
+            const int row = idx / half, k = idx % half;
+            if (pj[k] < p && sn[k] != 0.0) {
+              zi[u] = Z[(size_t)row * p + pi[k]];
+              zj[u] = Z[(size_t)row * p + pj[k]];
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kZ; ++u) {
+          const int idx = base + u * nt + tid;
+          if (idx < half * p) {
+            const int row = idx / half, k = idx % half;
+            const double s = sn[k];
+            if (pj[k] < p && s != 0.0) {
+              const double c = cs[k];
+              Z[(size_t)row * p + pi[k]] = c * zi[u] - s * zj[u];
+              Z[(size_t)row * p + pj[k]] = s * zi[u] + c * zj[u];
+            }
+          }
+        }
       }
       __threadfence_block();
       __syncthreads();
