@@ -278,7 +278,9 @@ __global__ void __launch_bounds__(kThreads) k_cp_reduce_mfma(const float* __rest
 //      order, giving R1 with a fixed summation order;
 //   2. with Phi0 in LDS, the 64 lanes of wave w form the penalty of entry w,
 //      P[d][k] = sum_j Phi0[d][j] (phi0_j . phi0_k)^2 (FP64), lane l taking
-//      j = l, l + 64, ...;
+//      j = l, l + 64, ...; the squared dot products come from gsq (K x K,
+//      formed once per step by k_gram_sq) when it is given, else each wave
+//      forms the ones it needs;
 //   3. grad = 3(1+theta) P - 3 c3 / n R1 and Phi = Phi0 - beta grad.
 // n is the sum of counts[0 .. ncounts) (per-block kept-row counts, or one
 // caller-supplied count) or n_default when counts is NULL; n <= 0 gives a
@@ -292,7 +294,8 @@ __device__ __forceinline__ void cp_finish_block(
     int blk, const float* __restrict__ partial, int nblk, const int* __restrict__ counts,
     int ncounts, int n_default, const float* __restrict__ Phi0, int D, int K, double alpha0,
     double theta, float beta, float* __restrict__ Phi, float* __restrict__ grad,
-    double* __restrict__ R1, int* __restrict__ n_out, float* __restrict__ ph) {
+    double* __restrict__ R1, int* __restrict__ n_out, float* __restrict__ ph,
+    const double* __restrict__ gsq) {
   __shared__ double red[kFinGroups][kFinEntries + 1];
   __shared__ double pen_s[kFinEntries];
   __shared__ int nred[kFinThreads / 64];
@@ -323,23 +326,27 @@ __device__ __forceinline__ void cp_finish_block(
     if (me >= DK) break;
     const int d = me / K, k = me % K;
     double pen = 0.0;
-    for (int j = lane; j < K; j += 64) {
-      // (Phi^T Phi)[j][k] in four independent chains
-      double dot0 = 0.0, dot1 = 0.0, dot2 = 0.0, dot3 = 0.0;
-      int i = 0;
-      for (; i + 3 < D; i += 4) {
-        const float a0 = ph[i * K + j], a1 = ph[(i + 1) * K + j];
-        const float a2 = ph[(i + 2) * K + j], a3 = ph[(i + 3) * K + j];
-        const float b0 = ph[i * K + k], b1 = ph[(i + 1) * K + k];
-        const float b2 = ph[(i + 2) * K + k], b3 = ph[(i + 3) * K + k];
-        dot0 += (double)a0 * (double)b0;
-        dot1 += (double)a1 * (double)b1;
-        dot2 += (double)a2 * (double)b2;
-        dot3 += (double)a3 * (double)b3;
+    if (gsq != nullptr) {
+      for (int j = lane; j < K; j += 64) pen += (double)ph[d * K + j] * gsq[(size_t)j * K + k];
+    } else {
+      for (int j = lane; j < K; j += 64) {
+        // (Phi^T Phi)[j][k] in four independent chains
+        double dot0 = 0.0, dot1 = 0.0, dot2 = 0.0, dot3 = 0.0;
+        int i = 0;
+        for (; i + 3 < D; i += 4) {
+          const float a0 = ph[i * K + j], a1 = ph[(i + 1) * K + j];
+          const float a2 = ph[(i + 2) * K + j], a3 = ph[(i + 3) * K + j];
+          const float b0 = ph[i * K + k], b1 = ph[(i + 1) * K + k];
+          const float b2 = ph[(i + 2) * K + k], b3 = ph[(i + 3) * K + k];
+          dot0 += (double)a0 * (double)b0;
+          dot1 += (double)a1 * (double)b1;
+          dot2 += (double)a2 * (double)b2;
+          dot3 += (double)a3 * (double)b3;
+        }
+        for (; i < D; ++i) dot0 += (double)ph[i * K + j] * (double)ph[i * K + k];
+        const double dot = (dot0 + dot1) + (dot2 + dot3);
+        pen += (double)ph[d * K + j] * (dot * dot);
       }
-      for (; i < D; ++i) dot0 += (double)ph[i * K + j] * (double)ph[i * K + k];
-      const double dot = (dot0 + dot1) + (dot2 + dot3);
-      pen += (double)ph[d * K + j] * (dot * dot);
     }
     for (int off = 32; off > 0; off >>= 1) pen += __shfl_xor(pen, off, 64);
     if (lane == 0) pen_s[wi] = pen;
@@ -383,11 +390,36 @@ __device__ __forceinline__ void cp_finish_block(
   if (blk == 0 && tid == 0 && n_out != nullptr) *n_out = n;
 }
 
+// gsq[j][k] = (phi_j . phi_k)^2 for the K columns of Phi (D x K), in FP64:
+// the squared Gram entries of the penalty, with the finish kernel's own
+// summation (four chains over d, added pairwise).  One thread per entry.
+__global__ void __launch_bounds__(256) k_gram_sq(const float* __restrict__ Phi, int D, int K,
+                                                 double* __restrict__ gsq) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= K * K) return;
+  const int j = e / K, k = e % K;
+  double dot0 = 0.0, dot1 = 0.0, dot2 = 0.0, dot3 = 0.0;
+  int i = 0;
+  for (; i + 3 < D; i += 4) {
+    const float a0 = Phi[i * K + j], a1 = Phi[(i + 1) * K + j];
+    const float a2 = Phi[(i + 2) * K + j], a3 = Phi[(i + 3) * K + j];
+    const float b0 = Phi[i * K + k], b1 = Phi[(i + 1) * K + k];
+    const float b2 = Phi[(i + 2) * K + k], b3 = Phi[(i + 3) * K + k];
+    dot0 += (double)a0 * (double)b0;
+    dot1 += (double)a1 * (double)b1;
+    dot2 += (double)a2 * (double)b2;
+    dot3 += (double)a3 * (double)b3;
+  }
+  for (; i < D; ++i) dot0 += (double)Phi[i * K + j] * (double)Phi[i * K + k];
+  const double dot = (dot0 + dot1) + (dot2 + dot3);
+  gsq[e] = dot * dot;
+}
+
 __global__ void __launch_bounds__(kFinThreads) k_cp_finish(
     const float* __restrict__ partial, int nblk, const int* __restrict__ counts, int ncounts,
     int n_default, const float* __restrict__ Phi0, int D, int K, double alpha0, double theta,
     float beta, float* __restrict__ Phi, float* __restrict__ grad, double* __restrict__ R1,
-    int* __restrict__ n_out) {
+    int* __restrict__ n_out, const double* __restrict__ gsq) {
   extern __shared__ float ph[];                 // [D][K] copy of Phi0
   // Workgroups go to the 8 XCDs in turn; block b takes entry chunk
   // (b % 8) per + b / 8, so each XCD reads one contiguous run of every
@@ -397,7 +429,7 @@ __global__ void __launch_bounds__(kFinThreads) k_cp_finish(
   const int chunk = (blockIdx.x % 8) * per + blockIdx.x / 8;
   if (chunk * kFinEntries >= D * K) return;
   cp_finish_block(chunk, partial, nblk, counts, ncounts, n_default, Phi0, D, K, alpha0, theta,
-                  beta, Phi, grad, R1, n_out, ph);
+                  beta, Phi, grad, R1, n_out, ph, gsq);
 }
 
 // The finish of every slice of a multi-slice step in one launch: block b
@@ -407,7 +439,8 @@ __global__ void __launch_bounds__(kFinThreads) k_cp_finish_multi(const SliceStep
   extern __shared__ float ph[];
   const SliceStep& d = sl[fin_slice[blockIdx.x]];
   cp_finish_block(blockIdx.x - d.fin0, d.partial, d.nblk, d.block_counts, d.nblk, 0, d.phi_copy,
-                  d.D, d.K, d.alpha0, d.theta, d.beta, d.Phi, d.grad, d.R1, d.n_kept_out, ph);
+                  d.D, d.K, d.alpha0, d.theta, d.beta, d.Phi, d.grad, d.R1, d.n_kept_out, ph,
+                  nullptr);
 }
 
 }  // namespace
@@ -515,15 +548,20 @@ hipError_t launch_cp_finish_multi(const SliceStep* sl, const int* fin_slice, int
   return hipGetLastError();
 }
 
+hipError_t launch_gram_sq(const float* Phi, int D, int K, double* gsq, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_sq, dim3((K * K + 255) / 256), dim3(256), 0, s, Phi, D, K, gsq);
+  return hipGetLastError();
+}
+
 hipError_t launch_cp_finish(const float* partial, int nblk, const int* counts, int ncounts,
                             int n_default, const float* Phi0, int D, int K, double alpha0,
                             double theta, float beta, float* Phi, float* grad, double* R1,
-                            int* n_out, hipStream_t s) {
+                            int* n_out, const double* gsq, hipStream_t s) {
   const int DK = D * K;
   const int chunks = (DK + kFinEntries - 1) / kFinEntries;
   hipLaunchKernelGGL(k_cp_finish, dim3(8 * ((chunks + 7) / 8)), dim3(kFinThreads),
                      sizeof(float) * DK, s, partial, nblk, counts, ncounts, n_default, Phi0, D, K,
-                     alpha0, theta, beta, Phi, grad, R1, n_out);
+                     alpha0, theta, beta, Phi, grad, R1, n_out, gsq);
   return hipGetLastError();
 }
 

@@ -120,6 +120,23 @@ tlda_status ensure_partial(tlda_ctx* c, size_t need) {
   return TLDA_OK;
 }
 
+// The finish of a step (gradient and update from the reduction's partials).
+// From kGramOnceDK entries of Phi on, the squared Gram entries of Phi0 are
+// formed once first rather than by every finish block.
+tlda_status finish_step(tlda_ctx* c, int nblk, const int* counts, int ncounts, int n_default,
+                        float beta, float* Phi, float* grad, int* n_out) {
+  const int D = c->cfg.D, K = c->cfg.K;
+  const double* gsq = nullptr;
+  if (D * K >= tlda::kGramOnceDK) {
+    HIP_OK(c, tlda::launch_gram_sq(c->cp.phi0, D, K, c->cp.gsq, c->stream));
+    gsq = c->cp.gsq;
+  }
+  HIP_OK(c, tlda::launch_cp_finish(c->cp.partial, nblk, counts, ncounts, n_default, c->cp.phi0, D,
+                                   K, c->cfg.alpha0, c->cfg.theta, beta, Phi, grad, c->cp.R1,
+                                   n_out, gsq, c->stream));
+  return TLDA_OK;
+}
+
 int default_block(const tlda_config& c) {
   int p = 2 * c.D;
   if (p < c.D + 16) p = c.D + 16;
@@ -373,10 +390,7 @@ tlda_status classic_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float
     HIP_OK(c, timing_stop(c));
     st = end_use(c, b);
     if (st != TLDA_OK) return st;
-    HIP_OK(c, tlda::launch_cp_finish(c->cp.partial, nblk, c->block_counts, nblk, 0, c->cp.phi0, D,
-                                     K, c->cfg.alpha0, c->cfg.theta, beta, Phi, g, c->cp.R1,
-                                     n_kept_out, c->stream));
-    return TLDA_OK;
+    return finish_step(c, nblk, c->block_counts, nblk, 0, beta, Phi, g, n_kept_out);
   }
   const int Kp = tlda::padded_d(K);
   if (c->cp.Z == nullptr) {
@@ -406,10 +420,7 @@ tlda_status classic_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float
   HIP_OK(c, timing_stop(c));
   st = end_use(c, b);
   if (st != TLDA_OK) return st;
-  HIP_OK(c, tlda::launch_cp_finish(c->cp.partial, nblk, c->block_counts, nblk, 0, c->cp.phi0, D, K,
-                                   c->cfg.alpha0, c->cfg.theta, beta, Phi, g, c->cp.R1, n_kept_out,
-                                   c->stream));
-  return TLDA_OK;
+  return finish_step(c, nblk, c->block_counts, nblk, 0, beta, Phi, g, n_kept_out);
 }
 
 void destroy_all(tlda_ctx* c) {
@@ -425,6 +436,7 @@ void destroy_all(tlda_ctx* c) {
   dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
   dfree(e.sel); dfree(e.mcand); dfree(e.info); dfree(e.part);
   dfree(c->cp.partial); dfree(c->cp.R1); dfree(c->cp.phi0); dfree(c->cp.grad); dfree(c->cp.X);
+  dfree(c->cp.gsq);
   dfree(c->cp.Z); dfree(c->cp.rz); dfree(c->cp.Z16);
   dfree(c->post); dfree(c->postA); dfree(c->postG); dfree(c->postZ); dfree(c->postEv);
   dfree(c->A32); dfree(c->G32); dfree(c->step32); dfree(c->dev_flags); dfree(c->block_counts);
@@ -515,6 +527,7 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
             dalloc(&ctx->wh.W32, V * (size_t)ctx->Dp) == hipSuccess &&
             dalloc(&ctx->wh.mw32, (size_t)ctx->Dp) == hipSuccess &&
             dalloc(&ctx->cp.R1, D * K) == hipSuccess && dalloc(&ctx->cp.phi0, D * K) == hipSuccess &&
+            dalloc(&ctx->cp.gsq, (size_t)K * K) == hipSuccess &&
             dalloc(&ctx->cp.grad, D * K) == hipSuccess && dalloc(&ctx->post, K) == hipSuccess &&
             dalloc(&ctx->postA, D * K) == hipSuccess && dalloc(&ctx->postG, K * K) == hipSuccess &&
             dalloc(&ctx->postZ, K * K) == hipSuccess && dalloc(&ctx->postEv, K) == hipSuccess &&
@@ -643,10 +656,7 @@ tlda_status tlda_cp_step(tlda_ctx* c, const float* X, int32_t n_rows, const int3
     HIP_OK(c, tlda::launch_cp_reduce(X, n_rows, Phi, D, K, nblk, c->cp.partial, c->cp.phi0,
                                      c->stream));
   HIP_OK(c, timing_stop(c));
-  HIP_OK(c, tlda::launch_cp_finish(c->cp.partial, nblk, n_kept, n_kept ? 1 : 0, n_rows,
-                                   c->cp.phi0, D, K, c->cfg.alpha0, c->cfg.theta, beta, Phi, g,
-                                   c->cp.R1, nullptr, c->stream));
-  return TLDA_OK;
+  return finish_step(c, nblk, n_kept, n_kept ? 1 : 0, n_rows, beta, Phi, g, nullptr);
 }
 
 tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float* Phi,
@@ -698,10 +708,7 @@ tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta
     HIP_OK(c, timing_stop(c));
     st = end_use(c, b);
     if (st != TLDA_OK) return st;
-    HIP_OK(c, tlda::launch_cp_finish(c->cp.partial, nblk, c->block_counts, nblk, 0, c->cp.phi0, D,
-                                     K, c->cfg.alpha0, c->cfg.theta, beta, Phi, g, c->cp.R1,
-                                     n_kept_out, c->stream));
-    return TLDA_OK;
+    return finish_step(c, nblk, c->block_counts, nblk, 0, beta, Phi, g, n_kept_out);
   }
   const int T = tlda::cp_mfma_tile_rows(D, K);
   const int ntiles = (b->n_rows + T - 1) / T;
@@ -724,10 +731,7 @@ tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta
   HIP_OK(c, timing_stop(c));
   st = end_use(c, b);
   if (st != TLDA_OK) return st;
-  HIP_OK(c, tlda::launch_cp_finish(c->cp.partial, nblk, c->block_counts, nblk, 0, c->cp.phi0, D, K,
-                                   c->cfg.alpha0, c->cfg.theta, beta, Phi, g, c->cp.R1,
-                                   n_kept_out, c->stream));
-  return TLDA_OK;
+  return finish_step(c, nblk, c->block_counts, nblk, 0, beta, Phi, g, n_kept_out);
 }
 
 tlda_status tlda_unwhiten(tlda_ctx* c, const float* Phi, double* mu, double* alpha, double* lambda,

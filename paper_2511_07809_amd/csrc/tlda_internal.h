@@ -109,6 +109,7 @@ struct CpScratch {
   float* Z = nullptr;         // [V][Kp] W Phi of the classic-moment step
   float* rz = nullptr;        // [Kp]    Phi^T W^T M1 of the classic-moment step
   uint16_t* Z16 = nullptr;    // [V][Kh] bf16(W16 Phi) of the BF16 classic-moment step
+  double* gsq = nullptr;      // [K][K] squared Gram entries of Phi (large D x K only)
 };
 
 }  // namespace tlda
@@ -293,11 +294,18 @@ int whiten_chunks(int V, int Dp);
 // finish kernel reads while it writes Phi.
 hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D, int K, int nblk,
                             float* partial, float* phi_copy, hipStream_t s);
-// n = sum of counts[0 .. ncounts), or n_default when counts is NULL
+// n = sum of counts[0 .. ncounts), or n_default when counts is NULL; gsq
+// (K x K squared Gram entries of Phi0 from launch_gram_sq) or NULL, in which
+// case the finish forms the ones it needs itself
 hipError_t launch_cp_finish(const float* partial, int nblk, const int* counts, int ncounts,
                             int n_default, const float* Phi0, int D, int K, double alpha0,
                             double theta, float beta, float* Phi, float* grad, double* R1,
-                            int* n_out, hipStream_t s);
+                            int* n_out, const double* gsq, hipStream_t s);
+// gsq[j][k] = (phi_j . phi_k)^2 in FP64 for Phi (D x K)
+hipError_t launch_gram_sq(const float* Phi, int D, int K, double* gsq, hipStream_t s);
+// From this many entries of Phi on, the squared Gram entries are formed once
+// per step instead of by every finish block
+constexpr int kGramOnceDK = 4096;
 int cp_tile_rows(int D, int K);
 int mfma_bucket(int n);
 int cp_mfma_tile_rows(int D, int K);
