@@ -12,8 +12,8 @@ resident in HBM before timing starts (--streamed: staged from pinned host
 memory inside the timed region).  The K timed steps run twice: eagerly, one
 library call per step, with events attached to each main kernel's dispatch
 (the kernel times of the roofline), and as one captured HIP graph of the same
-K steps (tlda_graph_capture_steps), whose time gives `value` for the fused
-path over resident batches (eager otherwise).  An untimed fit of both
+K steps (tlda_graph_capture_steps), replayed 5 times; the median replay gives
+`value` for the fused path over resident batches (eager otherwise).  An untimed fit of both
 precisions from the same start reports their topic-recovery errors after the
 same passes.
 
@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+GRAPH_REPLAYS = 5              # timed replays of the captured K steps (median reported)
 FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector / FP32 matrix, TFLOP/s
 BF16_MFMA_PEAK_TFLOPS = 2500.0 # MI355X dense BF16 matrix, TFLOP/s
 
@@ -841,15 +842,21 @@ def main():
                 continue
             tl.tlda_graph_launch(g)                  # untimed replay
             torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            tl.tlda_graph_launch(g)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            graph_runs[name] = {"total_ms": ms,
+            # GRAPH_REPLAYS timed replays of the K steps, each bracketed by
+            # events and a synchronisation; the median replay gives the rate
+            reps = []
+            for _ in range(GRAPH_REPLAYS):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                tl.tlda_graph_launch(g)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                reps.append(e0.elapsed_time(e1))
+            ms = float(np.median(reps))
+            graph_runs[name] = {"total_ms": ms, "replay_ms": reps,
                                 "docs_per_s": sum(b.n_rows for b in steps_b) / (ms / 1e3)}
-            log(f"[bench] {name} graph of {args.steps} steps: {ms:.3f} ms, "
+            log(f"[bench] {name} graph of {args.steps} steps: median {ms:.3f} ms of "
+                f"{GRAPH_REPLAYS} replays ({', '.join(f'{x:.3f}' for x in reps)}), "
                 f"{graph_runs[name]['docs_per_s']:.4g} docs/s")
             del g
     main_run = runs[args.precision]
@@ -940,6 +947,7 @@ def main():
         "breakdown": {"path": args.path,
                       "eager_docs_per_s": main_run["docs_per_s"],
                       "graph_docs_per_s": main_graph["docs_per_s"] if main_graph else None,
+                      "graph_replay_ms": main_graph["replay_ms"] if main_graph else None,
                       f"{other_name}_graph_docs_per_s":
                           graph_runs[other_name]["docs_per_s"] if other_name in graph_runs else None,
                       "step_us": float(main_run["step_ms"].mean()) * 1e3,

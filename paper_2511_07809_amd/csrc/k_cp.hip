@@ -392,27 +392,29 @@ __device__ __forceinline__ void cp_finish_block(
 
 // gsq[j][k] = (phi_j . phi_k)^2 for the K columns of Phi (D x K), in FP64:
 // the squared Gram entries of the penalty, with the finish kernel's own
-// summation (four chains over d, added pairwise).  One thread per entry.
-__global__ void __launch_bounds__(256) k_gram_sq(const float* __restrict__ Phi, int D, int K,
-                                                 double* __restrict__ gsq) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= K * K) return;
-  const int j = e / K, k = e % K;
-  double dot0 = 0.0, dot1 = 0.0, dot2 = 0.0, dot3 = 0.0;
-  int i = 0;
-  for (; i + 3 < D; i += 4) {
-    const float a0 = Phi[i * K + j], a1 = Phi[(i + 1) * K + j];
-    const float a2 = Phi[(i + 2) * K + j], a3 = Phi[(i + 3) * K + j];
-    const float b0 = Phi[i * K + k], b1 = Phi[(i + 1) * K + k];
-    const float b2 = Phi[(i + 2) * K + k], b3 = Phi[(i + 3) * K + k];
-    dot0 += (double)a0 * (double)b0;
-    dot1 += (double)a1 * (double)b1;
-    dot2 += (double)a2 * (double)b2;
-    dot3 += (double)a3 * (double)b3;
+// summation: four chains over d (chain c takes d = 4m + c, chain 0 also the
+// tail), added as (c0 + c1) + (c2 + c3).  Four lanes per entry, one per
+// chain; each block stages Phi in LDS and forms 256 entries.
+__global__ void __launch_bounds__(1024) k_gram_sq(const float* __restrict__ Phi, int D, int K,
+                                                  double* __restrict__ gsq) {
+  extern __shared__ float ph[];                 // [D][K]
+  for (int i = threadIdx.x; i < D * K; i += 1024) ph[i] = Phi[i];
+  __syncthreads();
+  const int t = blockIdx.x * 1024 + threadIdx.x;
+  const int e = t >> 2, c = t & 3;
+  const bool in = e < K * K;
+  const int j = in ? e / K : 0, k = in ? e % K : 0;
+  double acc = 0.0;
+  const int M = D / 4;
+  for (int m = 0; m < M; ++m) {
+    const int i = 4 * m + c;
+    acc += (double)ph[i * K + j] * (double)ph[i * K + k];
   }
-  for (; i < D; ++i) dot0 += (double)Phi[i * K + j] * (double)Phi[i * K + k];
-  const double dot = (dot0 + dot1) + (dot2 + dot3);
-  gsq[e] = dot * dot;
+  if (c == 0)
+    for (int i = 4 * M; i < D; ++i) acc += (double)ph[i * K + j] * (double)ph[i * K + k];
+  acc += __shfl_xor(acc, 1, 64);                // (c0 + c1), (c2 + c3)
+  acc += __shfl_xor(acc, 2, 64);                // (c0 + c1) + (c2 + c3)
+  if (in && c == 0) gsq[e] = acc * acc;
 }
 
 __global__ void __launch_bounds__(kFinThreads) k_cp_finish(
@@ -549,7 +551,8 @@ hipError_t launch_cp_finish_multi(const SliceStep* sl, const int* fin_slice, int
 }
 
 hipError_t launch_gram_sq(const float* Phi, int D, int K, double* gsq, hipStream_t s) {
-  hipLaunchKernelGGL(k_gram_sq, dim3((K * K + 255) / 256), dim3(256), 0, s, Phi, D, K, gsq);
+  hipLaunchKernelGGL(k_gram_sq, dim3((4 * K * K + 1023) / 1024), dim3(1024),
+                     sizeof(float) * D * K, s, Phi, D, K, gsq);
   return hipGetLastError();
 }
 
