@@ -408,13 +408,19 @@ __global__ void __launch_bounds__(1024) k_jacobi(double* __restrict__ A, double*
   for (int i = tid; i < p; i += nt) ev[i] = A[(size_t)i * p + i];
 }
 
-// The same iteration with the p x p matrix in LDS (p <= kLdsP); the rotation
-// accumulator Z stays in global memory.
-__global__ void __launch_bounds__(1024) k_jacobi_lds(double* __restrict__ Ag, double* __restrict__ Z,
+// The same iteration with the p x p matrix in LDS (p <= kLdsP).  ZL: the
+// rotation accumulator Z is in LDS as well (p <= kLdsPZ, the two matrices
+// fill the 160 KB), and Z's array doubles as the reduction scratch before Z
+// is formed and after it is written out; otherwise Z stays in global memory.
+constexpr int kLdsPZ = 100;
+template <bool ZL>
+__global__ void __launch_bounds__(1024) k_jacobi_lds(double* __restrict__ Ag, double* __restrict__ Zg,
                                                  double* __restrict__ ev, int p,
                                                  int* __restrict__ info) {
-  __shared__ double A[kLdsP * kLdsP];
-  __shared__ double sh[3 * (kLdsP / 2) + 2 * 1024];   // c, s, pair indices, reduction scratch
+  constexpr int PA = ZL ? kLdsPZ : kLdsP;
+  __shared__ double A[PA * PA];
+  __shared__ double Zl[ZL ? PA * PA : 1];
+  __shared__ double sh[3 * (PA / 2) + (ZL ? 0 : 2 * 1024)];   // c, s, pair indices (, scratch)
   __shared__ int sh_rot;
   __shared__ double sh_norm;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -424,10 +430,11 @@ __global__ void __launch_bounds__(1024) k_jacobi_lds(double* __restrict__ Ag, do
   double* sn = sh + half;
   int* pi = reinterpret_cast<int*>(sh + 2 * half);
   int* pj = pi + half;
-  double* red = sh + 3 * half;     // 2 * nt doubles
+  double* red = ZL ? Zl : sh + 3 * half;     // 2 * nt doubles
+  double* Z = ZL ? Zl : Zg;
   for (int idx = tid; idx < p * p; idx += nt) {
     A[idx] = Ag[idx];
-    Z[idx] = (idx / p == idx % p) ? 1.0 : 0.0;
+    if (!ZL) Z[idx] = (idx / p == idx % p) ? 1.0 : 0.0;
   }
   __syncthreads();
   // Frobenius norm (invariant under the rotations)
@@ -443,6 +450,10 @@ __global__ void __launch_bounds__(1024) k_jacobi_lds(double* __restrict__ Ag, do
   __threadfence_block();
   __syncthreads();
   const double tiny = 1e-20 * sh_norm;
+  if (ZL) {
+    for (int idx = tid; idx < p * p; idx += nt) Z[idx] = (idx / p == idx % p) ? 1.0 : 0.0;
+    __syncthreads();
+  }
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) sh_rot = 0;
     __syncthreads();
@@ -539,6 +550,10 @@ __global__ void __launch_bounds__(1024) k_jacobi_lds(double* __restrict__ Ag, do
       __syncthreads();
     }
     if (sh_rot == 0) break;
+    __syncthreads();
+  }
+  if (ZL) {
+    for (int idx = tid; idx < p * p; idx += nt) Zg[idx] = Z[idx];
     __syncthreads();
   }
   // final check of the remaining off-diagonal mass
@@ -717,8 +732,12 @@ hipError_t launch_trsm_right_into(const double* Y, const double* G, double* Binv
 }
 
 hipError_t launch_jacobi(double* A, double* Z, double* ev, int p, int* info, hipStream_t s) {
+  if (p <= kLdsPZ) {
+    hipLaunchKernelGGL(k_jacobi_lds<true>, dim3(1), dim3(1024), 0, s, A, Z, ev, p, info);
+    return hipGetLastError();
+  }
   if (p <= kLdsP) {
-    hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(1024), 0, s, A, Z, ev, p, info);
+    hipLaunchKernelGGL(k_jacobi_lds<false>, dim3(1), dim3(1024), 0, s, A, Z, ev, p, info);
     return hipGetLastError();
   }
   const int m = (p + 1) & ~1;

@@ -65,9 +65,13 @@ def test_stats_bit_exact_with_ragged_batches_and_dropped_docs(c1):
     assert np.array_equal(totals, ref["token_totals"] + extra["token_totals"])
 
 
-def test_refresh_matches_oracle_first_moment_and_whitening(c1):
+@pytest.mark.parametrize("eig_block", [0, 100, 120, 200])
+def test_refresh_matches_oracle_first_moment_and_whitening(c1, eig_block):
+    """The block width selects the Rayleigh-Ritz eigensolver: Jacobi with the
+    matrix and the rotations in LDS (p <= 100, the default p = 21 here), with
+    the rotations in global memory (p <= 128), or all in global memory."""
     spec = c1["spec"]
-    ctx = make_ctx(spec.V, spec.K, spec.K, spec.alpha0, eig_iters=100)
+    ctx = make_ctx(spec.V, spec.K, spec.K, spec.alpha0, eig_iters=100, eig_block=eig_block)
     for b in c1["batches"]:
         tl.tlda_update_moments(ctx, dev_batch(*b))
     tl.tlda_update_moments(ctx, None, tl.TLDA_REFRESH_W)
