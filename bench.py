@@ -886,9 +886,13 @@ def main():
             ach = cp_flops / t_k / 1e12
             roof = {"kernel": name, "bound": "mfma", "achieved": ach, "peak": mm_peak,
                     "unit": "TFLOP/s", "frac": ach / mm_peak}
+        # beside the HBM figure: the whitening-row gathers, one row of D
+        # elements of the whitening copy per nonzero, served from the caches
+        gather_bytes = nnz_tot / K_steps * D * w_elem
         roof.update({"traffic": measured_traffic(key, spec.name),
                      "algorithmic_bytes": csr_bytes + w_bytes, "algorithmic_flops": cp_flops,
                      "hbm_frac": hbm_frac, "mfma_frac": mm_frac,
+                     "gather_bytes": gather_bytes, "gather_TBps": gather_bytes / t_k / 1e12,
                      "avg_launch_us": float(kern_us[0])})
     else:
         wh_bytes = csr_bytes + 4 * D * rows_per + w_bytes
