@@ -110,3 +110,13 @@ def test_header_compiles_as_c_and_cxx(tmp_path):
         src.write_text('#include "tlda.h"\nint main(void){return TLDA_OK;}\n')
         subprocess.run([comp, "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
                         str(src), "-o", str(tmp_path / f"h_{ext}")], check=True)
+
+
+def test_bench_runs_on_one_gpu_only():
+    """bench.py --gpus N with N > 1 exits at once with a message (this build
+    measures one GPU's share; the sharding is a design note)."""
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU only" in r.stdout + r.stderr
