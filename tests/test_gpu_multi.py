@@ -219,8 +219,10 @@ def test_release_frees_the_accumulator_and_keeps_the_whitening(side_stream):
 
 
 @pytest.mark.parametrize("bf16,D,K", [(True, 50, 50), (True, 20, 10), (False, 50, 50),
-                                      (False, 7, 5)])
+                                      (False, 7, 5), (True, 100, 100), (False, 64, 64)])
 def test_captured_steps_of_one_context_match_eager(side_stream, bf16, D, K):
+    """Replays of the captured steps equal the eager steps bit for bit (the
+    two largest shapes also capture the once-per-step Gram kernel)."""
     rng = np.random.default_rng(D + K)
     Q, _ = np.linalg.qr(rng.standard_normal((V, D)))
     W = Q * rng.uniform(5, 30, size=D)[None, :]
