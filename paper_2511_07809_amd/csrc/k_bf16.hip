@@ -102,14 +102,20 @@ __global__ void __launch_bounds__(256) k_mw16(const uint16_t* __restrict__ W16,
   if (tid == 0) mw16[d] = (float)red[0];
 }
 
-template <int DQ, int KQ>
+// Waves per block: 16 when both D and K are padded past 64, so that the R1
+// accumulators (DQ x KQ per block) spread over four times the waves and each
+// wave keeps a quarter of them (4 waves per SIMD instead of 2; one 64-document
+// tile per pass); 4 otherwise.
+constexpr int bf16_waves(int DQ, int KQ) { return (DQ > 64 && KQ > 64) ? 16 : 4; }
+
+template <int DQ, int KQ, int NW = 4>
 struct Bf16Shape {
   static constexpr int LDA = DQ + 8;        // row-major X tile stride (bf16)
   static constexpr int LDT = kTile + 8;     // column-major tiles stride (bf16)
   static constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = DQ / 32;
-  static constexpr int ST = (NCT + 3) / 4;  // column tiles of S per wave
+  static constexpr int ST = (NCT + NW - 1) / NW;       // column tiles of S per wave
   static constexpr int WD = NDT >= 4 ? 4 : NDT;
-  static constexpr int WK = 4 / WD;
+  static constexpr int WK = NW / WD;
   static constexpr int TDW = NDT / WD;                 // R1 row tiles per wave
   static constexpr int TKW = (NCT + WK - 1) / WK;      // R1 column tiles per wave
 };
@@ -117,7 +123,7 @@ struct Bf16Shape {
 // The work of one block: block `blk` of `nblk` blocks that share one batch.
 // LDS comes from the caller (Xs: kTile x LDA, XsT: DQ x LDT, SsT: KQ x LDT
 // BF16 values, wave_kept: 4 ints), so one kernel can serve several shapes.
-template <int DQ, int KQ, int G, int MODE>
+template <int DQ, int KQ, int G, int MODE, int NW>
 __device__ __forceinline__ void cp_bf16_block(
     int blk, int nblk, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const float* __restrict__ val, int n_rows, const uint16_t* __restrict__ W16,
@@ -126,10 +132,11 @@ __device__ __forceinline__ void cp_bf16_block(
     int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy,
     uint16_t* __restrict__ Xs, uint16_t* __restrict__ XsT, uint16_t* __restrict__ SsT,
     int* __restrict__ wave_kept) {
-  typedef Bf16Shape<DQ, KQ> Sh;
+  typedef Bf16Shape<DQ, KQ, NW> Sh;
   constexpr bool kCp = MODE != kWhitenOnly;
+  constexpr int kThreads = NW * 64;
   constexpr int RPW = 64 / G;
-  constexpr int RPB = 4 * RPW;
+  constexpr int RPB = NW * RPW;
   constexpr int PASSES = (kTile + RPB - 1) / RPB;
   constexpr int SLOTS = G >= kNB ? 1 : kNB / G;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -149,7 +156,7 @@ __device__ __forceinline__ void cp_bf16_block(
   u32x4 bphi[Sh::ST][Sh::NKS];
 #pragma unroll
   for (int q = 0; q < Sh::ST; ++q) {
-    const int ct = wave + 4 * q;
+    const int ct = wave + NW * q;
     const int k = 16 * ct + l16;
 #pragma unroll
     for (int ks = 0; ks < Sh::NKS; ++ks) {
@@ -308,7 +315,7 @@ __device__ __forceinline__ void cp_bf16_block(
     // ---- 2. S = X Phi; S^2 to LDS, column-major ----
 #pragma unroll
     for (int q = 0; q < Sh::ST; ++q) {
-      const int ct = wave + 4 * q;
+      const int ct = wave + NW * q;
       if (ct < Sh::NCT) {
 #pragma unroll
         for (int rt = 0; rt < kTile / 16; ++rt) {
@@ -367,26 +374,32 @@ __device__ __forceinline__ void cp_bf16_block(
   if (MODE != kFromX) {
     if (lane == 0) wave_kept[wave] = kept_total;
     __syncthreads();
-    if (tid == 0)
-      block_counts[blk] = wave_kept[0] + wave_kept[1] + wave_kept[2] + wave_kept[3];
+    if (tid == 0) {
+      int n = 0;
+      for (int w = 0; w < NW; ++w) n += wave_kept[w];
+      block_counts[blk] = n;
+    }
   }
 }
 
 
 template <int DQ, int KQ, int G, int MODE>
-__global__ void __launch_bounds__(kThreads, (DQ <= 64 && KQ <= 64) ? 3 : 2) k_cp_bf16(
+__global__ void __launch_bounds__(64 * (MODE == kWhitenOnly ? 4 : bf16_waves(DQ, KQ)),
+                                  (DQ <= 64 && KQ <= 64) ? 3 : (DQ > 64 && KQ > 64) ? 4 : 2)
+    k_cp_bf16(
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const float* __restrict__ val, int n_rows, const uint16_t* __restrict__ W16,
     const float* __restrict__ mw16, int Dh, const float* __restrict__ Xin, int D,
     const float* __restrict__ Phi, int K, int nblk, float* __restrict__ partial,
     int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy) {
-  typedef Bf16Shape<DQ, KQ> Sh;
+  constexpr int NW = MODE == kWhitenOnly ? 4 : bf16_waves(DQ, KQ);
+  typedef Bf16Shape<DQ, KQ, NW> Sh;
   constexpr bool kCp = MODE != kWhitenOnly;
   __shared__ __attribute__((aligned(16))) uint16_t Xs[kCp ? kTile * Sh::LDA : 8];
   __shared__ __attribute__((aligned(16))) uint16_t XsT[kCp ? DQ * Sh::LDT : 8];
   __shared__ __attribute__((aligned(16))) uint16_t SsT[kCp ? KQ * Sh::LDT : 8];
-  __shared__ int wave_kept[4];
-  cp_bf16_block<DQ, KQ, G, MODE>(blockIdx.x, nblk, row_ptr, col_idx, val, n_rows, W16, mw16, Dh,
+  __shared__ int wave_kept[NW];
+  cp_bf16_block<DQ, KQ, G, MODE, NW>(blockIdx.x, nblk, row_ptr, col_idx, val, n_rows, W16, mw16, Dh,
                                  Xin, D, Phi, K, partial, block_counts, Xout, phi_copy, Xs, XsT,
                                  SsT, wave_kept);
 }
@@ -406,7 +419,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_cp_bf16_multi(const SliceStep* 
   const int blk = blockIdx.x - d.blk0;
 #define TLDA_MULTI(DQ_, KQ_, G_)                                                               \
   case multi_shape_id(DQ_, KQ_, G_):                                                           \
-    cp_bf16_block<DQ_, KQ_, G_, kFused>(blk, d.nblk, d.row_ptr, d.col_idx, d.val, d.n_rows,    \
+    cp_bf16_block<DQ_, KQ_, G_, kFused, 4>(blk, d.nblk, d.row_ptr, d.col_idx, d.val, d.n_rows,    \
                                         d.W16, d.mw16, d.Dh, nullptr, d.D, d.Phi, d.K,         \
                                         d.partial, d.block_counts, nullptr, d.phi_copy, Xs,    \
                                         XsT, SsT, wave_kept);                                  \
@@ -440,13 +453,14 @@ struct Bf16Args {
 
 template <int DQ, int KQ, int G, int MODE>
 hipError_t launch_t(const Bf16Args& a, int* per_cu, hipStream_t s) {
+  constexpr int kBlock = 64 * (MODE == kWhitenOnly ? 4 : bf16_waves(DQ, KQ));
   if (per_cu != nullptr)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_cp_bf16<DQ, KQ, G, MODE>,
-                                                        kThreads, 0);
+                                                        kBlock, 0);
   const int32_t* rp = a.b ? a.b->row_ptr : nullptr;
   const int32_t* ci = a.b ? a.b->col_idx : nullptr;
   const float* va = a.b ? a.b->val : nullptr;
-  launch_main(k_cp_bf16<DQ, KQ, G, MODE>, dim3(a.nblk), dim3(kThreads), 0, s, rp, ci, va,
+  launch_main(k_cp_bf16<DQ, KQ, G, MODE>, dim3(a.nblk), dim3(kBlock), 0, s, rp, ci, va,
               a.n_rows, a.W16, a.mw16, a.Dh, a.Xin, a.D, a.Phi, a.K, a.nblk, a.partial,
               a.block_counts, a.Xout, a.phi_copy);
   return hipGetLastError();
