@@ -102,11 +102,13 @@ __global__ void __launch_bounds__(256) k_mw16(const uint16_t* __restrict__ W16,
   if (tid == 0) mw16[d] = (float)red[0];
 }
 
-// Waves per block: 16 when both D and K are padded past 64, so that the R1
-// accumulators (DQ x KQ per block) spread over four times the waves and each
-// wave keeps a quarter of them (4 waves per SIMD instead of 2; one 64-document
-// tile per pass); 4 otherwise.
-constexpr int bf16_waves(int DQ, int KQ) { return (DQ > 64 && KQ > 64) ? 16 : 4; }
+// Waves per block: 16 when both D and K are padded past 64 and 8 when one is,
+// so that the R1 accumulators (DQ x KQ per block) spread over more waves and
+// each keeps few enough registers for 4 waves per SIMD (with 4-wave blocks
+// these shapes ran at 2 or 3); 4 otherwise.
+constexpr int bf16_waves(int DQ, int KQ) {
+  return (DQ > 64 && KQ > 64) ? 16 : (DQ > 64 || KQ > 64) ? 8 : 4;
+}
 
 template <int DQ, int KQ, int NW = 4>
 struct Bf16Shape {
@@ -385,7 +387,7 @@ __device__ __forceinline__ void cp_bf16_block(
 
 template <int DQ, int KQ, int G, int MODE>
 __global__ void __launch_bounds__(64 * (MODE == kWhitenOnly ? 4 : bf16_waves(DQ, KQ)),
-                                  (DQ <= 64 && KQ <= 64) ? 3 : (DQ > 64 && KQ > 64) ? 4 : 2)
+                                  (DQ <= 64 && KQ <= 64) ? 3 : 4)
     k_cp_bf16(
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const float* __restrict__ val, int n_rows, const uint16_t* __restrict__ W16,
