@@ -149,18 +149,26 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // compile-time constants, so every loop is fully unrolled, accumulators stay
 // in place across the matrix instructions and only the row bound is checked
 // at run time.
+// Waves per block of the matrix-core reduction: 16 when D is padded past 64,
+// so that the R1 tiles (and the Phi fragments and staged rows) spread over
+// four times the waves and the kernel keeps several waves per SIMD instead of
+// one; 4 otherwise.
+constexpr int cp_waves(int DQ) { return DQ > 64 ? 16 : 4; }
+
 template <int DQ, int KQ, int T>
-__global__ void __launch_bounds__(kThreads) k_cp_reduce_mfma(const float* __restrict__ X,
+__global__ void __launch_bounds__(64 * cp_waves(DQ)) k_cp_reduce_mfma(const float* __restrict__ X,
                                                              int n_rows,
                                                              const float* __restrict__ Phi,
                                                              int D, int K, int nblk,
                                                              float* __restrict__ partial,
                                                              float* __restrict__ phi_copy) {
+  constexpr int NW = cp_waves(DQ);
+  constexpr int kThreads = NW * 64;
   constexpr int LDX = DQ + 4, LDS = KQ + 4;
   constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = DQ / 4;
   constexpr int NRT = NDT * NCT;
-  constexpr int ST = (NCT + 3) / 4;              // S column tiles per wave (max)
-  constexpr int RT = (NRT + 3) / 4;              // R1 tiles per wave (max)
+  constexpr int ST = (NCT + NW - 1) / NW;        // S column tiles per wave (max)
+  constexpr int RT = (NRT + NW - 1) / NW;        // R1 tiles per wave (max)
   // X tile staging: thread t owns column t % CP of rows t / CP + i * RPI,
   // CP = DQ rounded up to a power of two; rows past the batch and padding
   // columns load a clamped, in-bounds address and are zeroed by a select.
@@ -178,7 +186,7 @@ __global__ void __launch_bounds__(kThreads) k_cp_reduce_mfma(const float* __rest
   float bf[ST][NKS];
 #pragma unroll
   for (int q = 0; q < ST; ++q) {
-    const int ct = wave + 4 * q;
+    const int ct = wave + NW * q;
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) {
       const int d = 4 * ks + l4, k = 16 * ct + l16;
@@ -215,7 +223,7 @@ __global__ void __launch_bounds__(kThreads) k_cp_reduce_mfma(const float* __rest
     // S = X_t Phi, squared into LDS (four independent 16-row chains at a time)
 #pragma unroll
     for (int q = 0; q < ST; ++q) {
-      const int ct = wave + 4 * q;
+      const int ct = wave + NW * q;
       if (ct < NCT) {
 #pragma unroll
         for (int rt0 = 0; rt0 < T / 16; rt0 += 4) {
@@ -247,7 +255,7 @@ __global__ void __launch_bounds__(kThreads) k_cp_reduce_mfma(const float* __rest
       const float* sb = Ss + (rs * 4 + l4) * LDS + l16;
 #pragma unroll
       for (int q = 0; q < RT; ++q) {
-        const int t = wave + 4 * q;
+        const int t = wave + NW * q;
         if (t < NRT)
           acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[(t / NCT) * 16], sb[(t % NCT) * 16],
                                                         acc[q], 0, 0, 0);
@@ -257,7 +265,7 @@ __global__ void __launch_bounds__(kThreads) k_cp_reduce_mfma(const float* __rest
   float* out = partial + (size_t)blockIdx.x * D * K;
 #pragma unroll
   for (int q = 0; q < RT; ++q) {
-    const int t = wave + 4 * q;
+    const int t = wave + NW * q;
     if (t < NRT) {
       const int k = (t % NCT) * 16 + l16;
 #pragma unroll
@@ -492,9 +500,9 @@ int cp_resident_blocks(int D, int K, int num_cu) {
 #define TLDA_OCC(DQ_, KQ_)                                                                      \
   if (dq == DQ_ && kq == KQ_)                                                                   \
     e = Tm == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
-                       &per_cu, k_cp_reduce_mfma<DQ_, KQ_, 64>, kThreads, 0)                    \
+                       &per_cu, k_cp_reduce_mfma<DQ_, KQ_, 64>, 64 * cp_waves(DQ_), 0)         \
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
-                       &per_cu, k_cp_reduce_mfma<DQ_, KQ_, 32>, kThreads, 0);
+                       &per_cu, k_cp_reduce_mfma<DQ_, KQ_, 32>, 64 * cp_waves(DQ_), 0);
 #define TLDA_OCC_ROW(DQ_) \
   TLDA_OCC(DQ_, 16) TLDA_OCC(DQ_, 32) TLDA_OCC(DQ_, 64) TLDA_OCC(DQ_, 112) TLDA_OCC(DQ_, 128)
     TLDA_OCC_ROW(16) TLDA_OCC_ROW(32) TLDA_OCC_ROW(64) TLDA_OCC_ROW(112) TLDA_OCC_ROW(128)
@@ -524,11 +532,11 @@ hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D,
 #define TLDA_MFMA(DQ_, KQ_)                                                                   \
   if (dq == DQ_ && kq == KQ_) {                                                               \
     if (Tm == 64)                                                                             \
-      launch_main(k_cp_reduce_mfma<DQ_, KQ_, 64>, dim3(nblk), dim3(kThreads), 0, s, X, n_rows, \
-                  Phi, D, K, nblk, partial, phi_copy);                                        \
+      launch_main(k_cp_reduce_mfma<DQ_, KQ_, 64>, dim3(nblk), dim3(64 * cp_waves(DQ_)), 0, s, X, \
+                  n_rows, Phi, D, K, nblk, partial, phi_copy);                                \
     else                                                                                      \
-      launch_main(k_cp_reduce_mfma<DQ_, KQ_, 32>, dim3(nblk), dim3(kThreads), 0, s, X, n_rows, \
-                  Phi, D, K, nblk, partial, phi_copy);                                        \
+      launch_main(k_cp_reduce_mfma<DQ_, KQ_, 32>, dim3(nblk), dim3(64 * cp_waves(DQ_)), 0, s, X, \
+                  n_rows, Phi, D, K, nblk, partial, phi_copy);                                \
   }
 #define TLDA_MFMA_ROW(DQ_) \
   TLDA_MFMA(DQ_, 16) TLDA_MFMA(DQ_, 32) TLDA_MFMA(DQ_, 64) TLDA_MFMA(DQ_, 112) TLDA_MFMA(DQ_, 128)
