@@ -255,10 +255,10 @@ __global__ void __launch_bounds__(1024) k_cholesky_lds(double* __restrict__ G, i
       if (!(d > 0.0)) sh_fail = 1;
       A[j * p + j] = sq;
     }
-    const int rem = p - j - 1;
-    for (int idx = tid; idx < rem * rem; idx += nt) {
-      const int i = j + 1 + idx / rem, k = j + 1 + idx % rem;
-      if (k <= i) A[i * p + k] -= A[i * p + j] * A[k * p + j];
+    // trailing lower triangle (j < k <= i < p), threads as a 32 x 32 grid
+    for (int i = j + 1 + (tid >> 5); i < p; i += 32) {
+      const double aij = A[i * p + j];
+      for (int k = j + 1 + (tid & 31); k <= i; k += 32) A[i * p + k] -= aij * A[k * p + j];
     }
     __syncthreads();
   }
@@ -266,32 +266,55 @@ __global__ void __launch_bounds__(1024) k_cholesky_lds(double* __restrict__ G, i
   if (tid == 0 && sh_fail) atomicOr(info, 1);
 }
 
-// Binv = (L^-1)^T: thread c computes column c of X = L^-1 by forward
-// substitution.  A block takes kInvCols columns, X[:, its columns] held in
-// LDS (X[k][c]: conflict-free across threads), the rows of L read from global
-// memory as broadcasts; four partial sums shorten the dependency chain.
-// Columns are independent, so any p <= 512 fits (p * kInvCols doubles).
-constexpr int kInvCols = 32;
-__global__ void __launch_bounds__(64) k_tri_inverse_cols(const double* __restrict__ G, int p,
-                                                         double* __restrict__ Binv) {
-  __shared__ double X[512 * kInvCols];
-  const int cl = threadIdx.x, c = blockIdx.x * kInvCols + cl;
-  if (cl < kInvCols && c < p) {
-    for (int i = 0; i < c; ++i) X[i * kInvCols + cl] = 0.0;
-    for (int i = c; i < p; ++i) {
-      const double* Li = G + (size_t)i * p;
-      double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int k = c;
-      for (; k + 3 < i; k += 4) {
-        s0 -= Li[k] * X[k * kInvCols + cl];
-        s1 -= Li[k + 1] * X[(k + 1) * kInvCols + cl];
-        s2 -= Li[k + 2] * X[(k + 2) * kInvCols + cl];
-        s3 -= Li[k + 3] * X[(k + 3) * kInvCols + cl];
-      }
-      for (; k < i; ++k) s0 -= Li[k] * X[k * kInvCols + cl];
-      X[i * kInvCols + cl] = ((s0 + s1) + (s2 + s3)) / Li[i];
+// Binv = (L^-1)^T: wave c computes column c of X = L^-1 by forward
+// substitution, x_i = (delta_ic - sum_{c <= k < i} L[i][k] x_k) / L[i][i].
+// Lane l keeps x_k for k = c + l + 64 j in registers; each row's sum is
+// split over the lanes and added by a butterfly (every lane gets the same
+// value), and row i + 1 of L is loaded while row i is reduced (staging L
+// in LDS measured no faster).  p <= 512.
+constexpr int kInvJ = 8;
+__global__ void __launch_bounds__(256) k_tri_inverse_waves(const double* __restrict__ G, int p,
+                                                           double* __restrict__ Binv) {
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= p) return;                          // the whole wave
+  double xr[kInvJ], ln[kInvJ];
+#pragma unroll
+  for (int j = 0; j < kInvJ; ++j) xr[j] = 0.0;
+  auto load_row = [&](int i, double (&l)[kInvJ]) {
+#pragma unroll
+    for (int j = 0; j < kInvJ; ++j) {
+      const int k = c + lane + 64 * j;
+      l[j] = k < i ? G[(size_t)i * p + k] : 0.0;
     }
-    for (int i = 0; i < p; ++i) Binv[(size_t)c * p + i] = X[i * kInvCols + cl];
+  };
+  load_row(c, ln);
+  double diag = G[(size_t)c * p + c];
+  for (int i = c; i < p; ++i) {
+    double lc[kInvJ];
+#pragma unroll
+    for (int j = 0; j < kInvJ; ++j) lc[j] = ln[j];
+    const double dg = diag;
+    if (i + 1 < p) {
+      load_row(i + 1, ln);
+      diag = G[(size_t)(i + 1) * p + i + 1];
+    }
+    double part = 0.0;
+#pragma unroll
+    for (int j = 0; j < kInvJ; ++j) part += lc[j] * xr[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+    const double xi = ((i == c ? 1.0 : 0.0) - part) / dg;
+    const int t = i - c;
+#pragma unroll
+    for (int j = 0; j < kInvJ; ++j)
+      if (lane == (t & 63) && j == (t >> 6)) xr[j] = xi;
+  }
+  for (int k = lane; k < c; k += 64) Binv[(size_t)c * p + k] = 0.0;
+#pragma unroll
+  for (int j = 0; j < kInvJ; ++j) {
+    const int k = c + lane + 64 * j;
+    if (k < p) Binv[(size_t)c * p + k] = xr[j];
   }
 }
 
@@ -723,9 +746,8 @@ hipError_t launch_cholesky(double* G, int p, double shift_rel, int* info, hipStr
 // Y (V x p) <- Y L^-T, written to Out; Binv is p x p scratch.
 hipError_t launch_trsm_right_into(const double* Y, const double* G, double* Binv, double* Out, int V,
                                   int p, hipStream_t s) {
-  if (p > 512) return hipErrorInvalidValue;   // the kernel's LDS holds 512 rows
-  hipLaunchKernelGGL(k_tri_inverse_cols, dim3((p + kInvCols - 1) / kInvCols), dim3(64), 0, s, G,
-                     p, Binv);
+  if (p > 64 * kInvJ) return hipErrorInvalidValue;   // a lane keeps kInvJ entries of a column
+  hipLaunchKernelGGL(k_tri_inverse_waves, dim3((p + 3) / 4), dim3(256), 0, s, G, p, Binv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return gemm(false, V, p, p, Y, p, Binv, p, Out, p, 1.0, 1, s);
