@@ -150,19 +150,19 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 // in place across the matrix instructions and only the row bound is checked
 // at run time.
 // Waves per block of the matrix-core reduction: 16 when D is padded past 64,
-// so that the R1 tiles (and the Phi fragments and staged rows) spread over
-// four times the waves and the kernel keeps several waves per SIMD instead of
-// one; 4 otherwise.
-constexpr int cp_waves(int DQ) { return DQ > 64 ? 16 : 4; }
+// or K is and D is at least 32, so that the R1 tiles (and the Phi fragments
+// and staged rows) spread over four times the waves and the kernel keeps
+// several waves per SIMD instead of one or two; 4 otherwise.
+constexpr int cp_waves(int DQ, int KQ) { return (DQ > 64 || (KQ > 64 && DQ >= 32)) ? 16 : 4; }
 
 template <int DQ, int KQ, int T>
-__global__ void __launch_bounds__(64 * cp_waves(DQ)) k_cp_reduce_mfma(const float* __restrict__ X,
+__global__ void __launch_bounds__(64 * cp_waves(DQ, KQ)) k_cp_reduce_mfma(const float* __restrict__ X,
                                                              int n_rows,
                                                              const float* __restrict__ Phi,
                                                              int D, int K, int nblk,
                                                              float* __restrict__ partial,
                                                              float* __restrict__ phi_copy) {
-  constexpr int NW = cp_waves(DQ);
+  constexpr int NW = cp_waves(DQ, KQ);
   constexpr int kThreads = NW * 64;
   constexpr int LDX = DQ + 4, LDS = KQ + 4;
   constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = DQ / 4;
@@ -500,9 +500,9 @@ int cp_resident_blocks(int D, int K, int num_cu) {
 #define TLDA_OCC(DQ_, KQ_)                                                                      \
   if (dq == DQ_ && kq == KQ_)                                                                   \
     e = Tm == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
-                       &per_cu, k_cp_reduce_mfma<DQ_, KQ_, 64>, 64 * cp_waves(DQ_), 0)         \
+                       &per_cu, k_cp_reduce_mfma<DQ_, KQ_, 64>, 64 * cp_waves(DQ_, KQ_), 0)         \
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
-                       &per_cu, k_cp_reduce_mfma<DQ_, KQ_, 32>, 64 * cp_waves(DQ_), 0);
+                       &per_cu, k_cp_reduce_mfma<DQ_, KQ_, 32>, 64 * cp_waves(DQ_, KQ_), 0);
 #define TLDA_OCC_ROW(DQ_) \
   TLDA_OCC(DQ_, 16) TLDA_OCC(DQ_, 32) TLDA_OCC(DQ_, 64) TLDA_OCC(DQ_, 112) TLDA_OCC(DQ_, 128)
     TLDA_OCC_ROW(16) TLDA_OCC_ROW(32) TLDA_OCC_ROW(64) TLDA_OCC_ROW(112) TLDA_OCC_ROW(128)
@@ -532,10 +532,10 @@ hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D,
 #define TLDA_MFMA(DQ_, KQ_)                                                                   \
   if (dq == DQ_ && kq == KQ_) {                                                               \
     if (Tm == 64)                                                                             \
-      launch_main(k_cp_reduce_mfma<DQ_, KQ_, 64>, dim3(nblk), dim3(64 * cp_waves(DQ_)), 0, s, X, \
+      launch_main(k_cp_reduce_mfma<DQ_, KQ_, 64>, dim3(nblk), dim3(64 * cp_waves(DQ_, KQ_)), 0, s, X, \
                   n_rows, Phi, D, K, nblk, partial, phi_copy);                                \
     else                                                                                      \
-      launch_main(k_cp_reduce_mfma<DQ_, KQ_, 32>, dim3(nblk), dim3(64 * cp_waves(DQ_)), 0, s, X, \
+      launch_main(k_cp_reduce_mfma<DQ_, KQ_, 32>, dim3(nblk), dim3(64 * cp_waves(DQ_, KQ_)), 0, s, X, \
                   n_rows, Phi, D, K, nblk, partial, phi_copy);                                \
   }
 #define TLDA_MFMA_ROW(DQ_) \

@@ -208,7 +208,8 @@ def _cp_case(n, D, K, seed, scale=1.0):
 @pytest.mark.parametrize("D,K,n", [(5, 5, 1000), (10, 10, 3001), (20, 20, 777), (50, 50, 4099),
                                    (64, 64, 2048), (100, 100, 1500), (128, 100, 515),
                                    (7, 3, 999), (3, 12, 64), (1, 1, 5), (30, 60, 333),
-                                   (120, 120, 300), (256, 56, 257), (56, 256, 129)])
+                                   (120, 120, 300), (256, 56, 257), (56, 256, 129),
+                                   (50, 100, 600), (20, 120, 300)])
 @pytest.mark.parametrize("theta", [0.0, 1.0])
 def test_cp_gradient_and_step_match_oracle(D, K, n, theta):
     a0 = 1.0 if D != 100 else 2.0
