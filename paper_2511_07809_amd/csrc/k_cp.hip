@@ -297,6 +297,8 @@ __global__ void __launch_bounds__(64 * cp_waves(DQ, KQ)) k_cp_reduce_mfma(const 
 constexpr int kFinEntries = kFinishEntries;
 constexpr int kFinThreads = 1024;
 constexpr int kFinGroups = kFinThreads / kFinEntries;   // 64
+constexpr int kFinPre = 4;        // quads of partials issued before the penalty
+constexpr int kFinStage = 4;      // Phi0 entries per thread per staging round
 
 __device__ __forceinline__ void cp_finish_block(
     int blk, const float* __restrict__ partial, int nblk, const int* __restrict__ counts,
@@ -311,22 +313,53 @@ __device__ __forceinline__ void cp_finish_block(
   const int lane = tid & 63, wave = tid >> 6;
   const int DK = D * K;
   const int e = blk * kFinEntries + el;
+  // Phi0 into LDS and the kept-row counts, with the loads of a round issued
+  // together (clamped indexes, unconditional) so that one memory round trip
+  // serves up to kFinStage * kFinThreads entries.
   int cnt = 0;
-  if (counts != nullptr)
-    for (int i = tid; i < ncounts; i += kFinThreads) cnt += counts[i];
-  for (int i = tid; i < DK; i += kFinThreads) ph[i] = Phi0[i];
+  const bool have_counts = counts != nullptr && ncounts > 0;
+  int c_first = 0;
+  if (DK <= kFinStage * kFinThreads) {
+    // one round, straight-line; lanes past the end store the last entry's
+    // own value again
+    float v[kFinStage];
+#pragma unroll
+    for (int u = 0; u < kFinStage; ++u) v[u] = Phi0[min(tid + u * kFinThreads, DK - 1)];
+    if (have_counts) c_first = counts[min(tid, ncounts - 1)];
+#pragma unroll
+    for (int u = 0; u < kFinStage; ++u) ph[min(tid + u * kFinThreads, DK - 1)] = v[u];
+  } else {
+    if (have_counts) c_first = counts[min(tid, ncounts - 1)];
+    for (int i = tid; i < DK; i += kFinThreads) ph[i] = Phi0[i];
+  }
+  if (have_counts) {
+    cnt = tid < ncounts ? c_first : 0;
+    for (int i = tid + kFinThreads; i < ncounts; i += kFinThreads) cnt += counts[i];
+  }
   __syncthreads();
-  // the first four partials of this thread are in flight while the penalty
-  // below works from LDS (a barrier would wait for them)
-  int b = grp;
-  const bool first4 = e < DK && b + 3 * kFinGroups < nblk;
-  float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
-  if (first4) {
-    f0 = partial[(size_t)b * DK + e];
-    f1 = partial[(size_t)(b + kFinGroups) * DK + e];
-    f2 = partial[(size_t)(b + 2 * kFinGroups) * DK + e];
-    f3 = partial[(size_t)(b + 3 * kFinGroups) * DK + e];
-    b += 4 * kFinGroups;
+  // The first kFinPre quads of this thread's partials (four partials each,
+  // kFinGroups apart) are all in flight while the penalty below works from
+  // LDS (a barrier would wait for them); the first nq of them are added
+  // afterwards in the same order as the loop that takes the rest.  The loads
+  // are unconditional, from indexes clamped into the buffer: a load under a
+  // lane condition is followed by a wait for it where the branches join.
+  constexpr int kQuad = 4 * kFinGroups;
+  float f[4 * kFinPre] = {};
+  int nq = 0;
+#pragma unroll
+  for (int q = 0; q < kFinPre; ++q)
+    nq += (e < DK && grp + q * kQuad + 3 * kFinGroups < nblk) ? 1 : 0;
+  const int ec = e < DK ? e : DK - 1;
+  if (nblk >= kFinPre * kQuad) {
+    // every prefetched row exists: rows grp + kFinGroups t, one stride apart
+    const float* pr = partial + (size_t)grp * DK + ec;
+    const size_t stride = (size_t)kFinGroups * DK;
+#pragma unroll
+    for (int t = 0; t < 4 * kFinPre; ++t) f[t] = pr[t * stride];
+  } else if (nblk > 0) {
+#pragma unroll
+    for (int t = 0; t < 4 * kFinPre; ++t)
+      f[t] = partial[(size_t)min(grp + t * kFinGroups, nblk - 1) * DK + ec];
   }
   // wave w: penalty of entries w, w + 16, ... of the block
   for (int wi = wave; wi < kFinEntries; wi += kFinThreads / 64) {
@@ -359,7 +392,16 @@ __device__ __forceinline__ void cp_finish_block(
     for (int off = 32; off > 0; off >>= 1) pen += __shfl_xor(pen, off, 64);
     if (lane == 0) pen_s[wi] = pen;
   }
-  double r0 = f0, r1 = f1, r2 = f2, r3 = f3;
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+#pragma unroll
+  for (int q = 0; q < kFinPre; ++q)
+    if (q < nq) {
+      r0 += (double)f[4 * q];
+      r1 += (double)f[4 * q + 1];
+      r2 += (double)f[4 * q + 2];
+      r3 += (double)f[4 * q + 3];
+    }
+  int b = grp + nq * kQuad;
   if (e < DK) {
     for (; b + 3 * kFinGroups < nblk; b += 4 * kFinGroups) {
       r0 += (double)partial[(size_t)b * DK + e];

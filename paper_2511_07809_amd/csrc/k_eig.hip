@@ -512,13 +512,19 @@ __global__ void __launch_bounds__(1024) k_jacobi_lds(double* __restrict__ Ag, do
       // then by a's rows (the same operations, in the same order, as a column
       // pass followed by a row pass).  Entries at the padding index p do not
       // exist.
-      for (int idx = tid; idx < half * half; idx += nt) {
-        const int a = idx / half, b = idx % half;
-        const double sa = sn[a], sb = sn[b];
+      // Lane l of every wave owns column pair b = l (half <= 64), the waves
+      // take the row pairs a in turn.
+      const int lb = tid & 63, nw = nt >> 6;
+      const bool own = lb < half;
+      const double sb = own ? sn[lb] : 0.0, cb = own ? cs[lb] : 1.0;
+      const int ib = own ? pi[lb] : 0, jb = own ? pj[lb] : p;
+      const bool rb = jb < p;
+      for (int a = own ? (tid >> 6) : half; a < half; a += nw) {
+        const double sa = sn[a];
         if (sa == 0.0 && sb == 0.0) continue;
-        const int ia = pi[a], ja = pj[a], ib = pi[b], jb = pj[b];
-        const bool ra = ja < p, rb = jb < p;
-        const double ca = cs[a], cb = cs[b];
+        const int ia = pi[a], ja = pj[a];
+        const bool ra = ja < p;
+        const double ca = cs[a];
         double x00 = A[(size_t)ia * p + ib];
         double x01 = rb ? A[(size_t)ia * p + jb] : 0.0;
         double x10 = ra ? A[(size_t)ja * p + ib] : 0.0;
@@ -538,33 +544,28 @@ __global__ void __launch_bounds__(1024) k_jacobi_lds(double* __restrict__ Ag, do
         if (ra) A[(size_t)ja * p + ib] = x10;
         if (ra && rb) A[(size_t)ja * p + jb] = x11;
       }
-      // Z <- Z J: consecutive threads take consecutive pairs of one row, and
-      // each thread issues all its loads before its stores
+      // Z <- Z J: the same lane owns the same pair b in every row, the waves
+      // take the rows in turn, and each thread issues kZ rows' loads before
+      // its stores
       constexpr int kZ = 8;
-      for (int base = 0; base < half * p; base += kZ * nt) {
-        double zi[kZ], zj[kZ];
+      if (rb && sb != 0.0) {
+        for (int r0 = tid >> 6; r0 < p; r0 += kZ * nw) {
+          double zi[kZ], zj[kZ];
 #pragma unroll
-        for (int u = 0; u < kZ; ++u) {
-          const int idx = base + u * nt + tid;
-          zi[u] = zj[u] = 0.0;
-          if (idx < half * p) {
-            const int row = idx / half, k = idx % half;
-            if (pj[k] < p && sn[k] != 0.0) {
-              zi[u] = Z[(size_t)row * p + pi[k]];
-              zj[u] = Z[(size_t)row * p + pj[k]];
+          for (int u = 0; u < kZ; ++u) {
+            const int row = r0 + u * nw;
+            zi[u] = zj[u] = 0.0;
+            if (row < p) {
+              zi[u] = Z[(size_t)row * p + ib];
+              zj[u] = Z[(size_t)row * p + jb];
             }
           }
-        }
 #pragma unroll
-        for (int u = 0; u < kZ; ++u) {
-          const int idx = base + u * nt + tid;
-          if (idx < half * p) {
-            const int row = idx / half, k = idx % half;
-            const double s = sn[k];
-            if (pj[k] < p && s != 0.0) {
-              const double c = cs[k];
-              Z[(size_t)row * p + pi[k]] = c * zi[u] - s * zj[u];
-              Z[(size_t)row * p + pj[k]] = s * zi[u] + c * zj[u];
+          for (int u = 0; u < kZ; ++u) {
+            const int row = r0 + u * nw;
+            if (row < p) {
+              Z[(size_t)row * p + ib] = cb * zi[u] - sb * zj[u];
+              Z[(size_t)row * p + jb] = sb * zi[u] + cb * zj[u];
             }
           }
         }
