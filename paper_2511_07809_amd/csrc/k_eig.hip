@@ -97,17 +97,27 @@ __global__ void k_sum_partials(const double* __restrict__ part, int nz, size_t m
                                double alpha, double* __restrict__ C) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= mn) return;
+  // the loads of 16 chunks are issued together, then added in chunk order
+  constexpr int kU = 16;
   double s = 0.0;
-  for (int z = 0; z < nz; ++z) s += part[(size_t)z * mn + e];
+  int z = 0;
+  for (; z + kU <= nz; z += kU) {
+    double v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = part[(size_t)(z + u) * mn + e];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) s += v[u];
+  }
+  for (; z < nz; ++z) s += part[(size_t)z * mn + e];
   C[(e / N) * ldc + e % N] = alpha * s;
 }
 
 hipError_t gemm(bool transA, int M, int N, int Kd, const double* A, int lda, const double* B,
                 int ldb, double* C, int ldc, double alpha, int splits, hipStream_t s) {
   if (transA && g_eig_env.part != nullptr && (size_t)M * N <= g_eig_env.part_mn) {
-    // A^T B over many rows: row chunks of at least 256 write their own
+    // A^T B over many rows: row chunks of at least 64 write their own
     // partials, then one pass adds them in order (no atomics)
-    int nz = (Kd + 255) / 256;
+    int nz = (Kd + 63) / 64;
     if (nz > kSplitMax) nz = kSplitMax;
     if (nz < 1) nz = 1;
     const int chunk = ((Kd + nz - 1) / nz + 15) / 16 * 16;

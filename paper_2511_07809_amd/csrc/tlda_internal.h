@@ -214,7 +214,7 @@ extern thread_local KernelTimer g_main_timer;
 // Partial-sum scratch of the transposed products A^T B over many rows (the
 // refresh's Gram products): up to kSplitMax row chunks each write their own
 // M x N partial, added in chunk order afterwards (deterministic).
-constexpr int kSplitMax = 64;
+constexpr int kSplitMax = 256;
 struct EigEnv {
   void* blas = nullptr;
   double* part = nullptr;     // kSplitMax * part_mn doubles
