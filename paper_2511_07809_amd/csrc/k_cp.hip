@@ -299,6 +299,7 @@ constexpr int kFinThreads = 1024;
 constexpr int kFinGroups = kFinThreads / kFinEntries;   // 64
 constexpr int kFinPre = 4;        // quads of partials issued before the penalty
 constexpr int kFinStage = 4;      // Phi0 entries per thread per staging round
+constexpr int kFinPad = 64;       // LDS floats after the copy of Phi0 (staging pad)
 
 __device__ __forceinline__ void cp_finish_block(
     int blk, const float* __restrict__ partial, int nblk, const int* __restrict__ counts,
@@ -320,14 +321,18 @@ __device__ __forceinline__ void cp_finish_block(
   const bool have_counts = counts != nullptr && ncounts > 0;
   int c_first = 0;
   if (DK <= kFinStage * kFinThreads) {
-    // one round, straight-line; lanes past the end store the last entry's
-    // own value again
+    // one round, straight-line; lanes past the end store into the
+    // kFinPad-float pad after Phi0's copy, one slot per lane (no two lanes
+    // of a wave on one LDS address)
     float v[kFinStage];
 #pragma unroll
     for (int u = 0; u < kFinStage; ++u) v[u] = Phi0[min(tid + u * kFinThreads, DK - 1)];
     if (have_counts) c_first = counts[min(tid, ncounts - 1)];
 #pragma unroll
-    for (int u = 0; u < kFinStage; ++u) ph[min(tid + u * kFinThreads, DK - 1)] = v[u];
+    for (int u = 0; u < kFinStage; ++u) {
+      const int i = tid + u * kFinThreads;
+      ph[i < DK ? i : DK + lane] = v[u];
+    }
   } else {
     if (have_counts) c_first = counts[min(tid, ncounts - 1)];
     for (int i = tid; i < DK; i += kFinThreads) ph[i] = Phi0[i];
@@ -356,7 +361,10 @@ __device__ __forceinline__ void cp_finish_block(
     const size_t stride = (size_t)kFinGroups * DK;
 #pragma unroll
     for (int t = 0; t < 4 * kFinPre; ++t) f[t] = pr[t * stride];
-  } else if (nblk > 0) {
+  } else if (nblk > 3 * kFinGroups) {
+    // some lanes have a full quad (exactly those counted in nq: a lane's
+    // first quad is full once nblk > grp + 3 kFinGroups); the others load
+    // rows they then drop.  Below that no lane has one and nq is 0.
 #pragma unroll
     for (int t = 0; t < 4 * kFinPre; ++t)
       f[t] = partial[(size_t)min(grp + t * kFinGroups, nblk - 1) * DK + ec];
@@ -467,7 +475,7 @@ __global__ void __launch_bounds__(1024) k_gram_sq(const float* __restrict__ Phi,
   if (in && c == 0) gsq[e] = acc * acc;
 }
 
-__global__ void __launch_bounds__(kFinThreads) k_cp_finish(
+__global__ void __launch_bounds__(kFinThreads, 8) k_cp_finish(
     const float* __restrict__ partial, int nblk, const int* __restrict__ counts, int ncounts,
     int n_default, const float* __restrict__ Phi0, int D, int K, double alpha0, double theta,
     float beta, float* __restrict__ Phi, float* __restrict__ grad, double* __restrict__ R1,
@@ -486,7 +494,7 @@ __global__ void __launch_bounds__(kFinThreads) k_cp_finish(
 
 // The finish of every slice of a multi-slice step in one launch: block b
 // serves slice fin_slice[b] as its finish block b - fin0.
-__global__ void __launch_bounds__(kFinThreads) k_cp_finish_multi(const SliceStep* __restrict__ sl,
+__global__ void __launch_bounds__(kFinThreads, 8) k_cp_finish_multi(const SliceStep* __restrict__ sl,
                                                                  const int* __restrict__ fin_slice) {
   extern __shared__ float ph[];
   const SliceStep& d = sl[fin_slice[blockIdx.x]];
@@ -595,7 +603,8 @@ hipError_t launch_cp_reduce(const float* X, int n_rows, const float* Phi, int D,
 
 hipError_t launch_cp_finish_multi(const SliceStep* sl, const int* fin_slice, int n_fin,
                                   int max_dk, hipStream_t s) {
-  hipLaunchKernelGGL(k_cp_finish_multi, dim3(n_fin), dim3(kFinThreads), sizeof(float) * max_dk, s,
+  hipLaunchKernelGGL(k_cp_finish_multi, dim3(n_fin), dim3(kFinThreads),
+                     sizeof(float) * (max_dk + kFinPad), s,
                      sl, fin_slice);
   return hipGetLastError();
 }
@@ -613,7 +622,8 @@ hipError_t launch_cp_finish(const float* partial, int nblk, const int* counts, i
   const int DK = D * K;
   const int chunks = (DK + kFinEntries - 1) / kFinEntries;
   hipLaunchKernelGGL(k_cp_finish, dim3(8 * ((chunks + 7) / 8)), dim3(kFinThreads),
-                     sizeof(float) * DK, s, partial, nblk, counts, ncounts, n_default, Phi0, D, K,
+                     sizeof(float) * (DK + kFinPad), s, partial, nblk, counts, ncounts, n_default,
+                     Phi0, D, K,
                      alpha0, theta, beta, Phi, grad, R1, n_out, gsq);
   return hipGetLastError();
 }

@@ -226,6 +226,27 @@ def test_cp_gradient_and_step_match_oracle(D, K, n, theta):
     assert rel(Pd.cpu().numpy(), ref_p) < REL32
 
 
+@pytest.mark.parametrize("cap", [1, 200, 256, 300, 700, 1023, 1024, 1100, 1500])
+def test_cp_finish_at_every_partial_count(cap, monkeypatch):
+    """The finish adds the reduction's per-block partials, nblk of them, and
+    prefetches them by three routes (nblk below 256, 256 to 1023, 1024 and
+    more, each with its own tail); the block-count cap fixes nblk for a batch
+    with more row tiles than any cap here."""
+    monkeypatch.setenv("TLDA_TUNE_CP_BLOCKS", str(cap))
+    D = K = 50
+    n = 150_000
+    X, Phi = _cp_case(n, D, K, seed=cap)
+    ctx = make_ctx(D, K, D, 1.0, 0.5)
+    Xd = torch.from_numpy(X).cuda()
+    Pd = torch.from_numpy(Phi).cuda()
+    g = torch.empty_like(Pd)
+    beta = 1e-3
+    tl.tlda_cp_step(ctx, Xd, n, None, beta, Pd, g)
+    ref_g = O.cp_gradient(X.astype(np.float64), Phi.astype(np.float64), n, 1.0, 0.5)
+    assert rel(g.cpu().numpy(), ref_g) < REL32
+    assert rel(Pd.cpu().numpy(), Phi.astype(np.float64) - beta * ref_g) < REL32
+
+
 @pytest.mark.parametrize("D,K", [(128, 128), (256, 64), (64, 256), (124, 128)])
 def test_fp32_context_beyond_the_lds_tile_is_rejected(D, K):
     """Shapes within D*K <= TLDA_MAX_DK but over the FP32 reduction's LDS
