@@ -92,24 +92,34 @@ __global__ void __launch_bounds__(256) k_gemm64(int M, int N, int Kd, const doub
   }
 }
 
-// Out[e] = alpha * sum_z part[z][e] over nz chunks, in chunk order.
+// Out[e] = alpha * sum_z part[z][e] over nz chunks: four lanes per entry,
+// lane c adding the c-th quarter of the chunks in chunk order, the quarters
+// then combined as (q0 + q1) + (q2 + q3) (a fixed order, so the sum is
+// deterministic).  A lane issues the loads of 16 chunks before adding them;
+// the last batch loads from chunk indexes clamped into its quarter and adds
+// only the chunks that exist.
 __global__ void k_sum_partials(const double* __restrict__ part, int nz, size_t mn, int N, int ldc,
                                double alpha, double* __restrict__ C) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= mn) return;
-  // the loads of 16 chunks are issued together, then added in chunk order
   constexpr int kU = 16;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t e = t >> 2;
+  const int c = (int)(t & 3);
+  const bool in = e < mn;
+  const size_t ec = in ? e : mn - 1;
+  const int per = (nz + 3) / 4;
+  const int z0 = min(c * per, nz), z1 = min(z0 + per, nz);
   double s = 0.0;
-  int z = 0;
-  for (; z + kU <= nz; z += kU) {
+  for (int z = z0; z < z1; z += kU) {
     double v[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) v[u] = part[(size_t)(z + u) * mn + e];
+    for (int u = 0; u < kU; ++u) v[u] = part[(size_t)min(z + u, z1 - 1) * mn + ec];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) s += v[u];
+    for (int u = 0; u < kU; ++u)
+      if (z + u < z1) s += v[u];
   }
-  for (; z < nz; ++z) s += part[(size_t)z * mn + e];
-  C[(e / N) * ldc + e % N] = alpha * s;
+  s += __shfl_xor(s, 1, 64);                    // (q0 + q1), (q2 + q3)
+  s += __shfl_xor(s, 2, 64);                    // (q0 + q1) + (q2 + q3)
+  if (in && c == 0) C[(e / N) * ldc + e % N] = alpha * s;
 }
 
 hipError_t gemm(bool transA, int M, int N, int Kd, const double* A, int lda, const double* B,
@@ -128,7 +138,7 @@ hipError_t gemm(bool transA, int M, int N, int Kd, const double* A, int lda, con
                        g_eig_env.part, N, 1.0, chunk, 0, mn);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)((4 * mn + 255) / 256)), dim3(256), 0, s,
                        g_eig_env.part, nz, mn, N, ldc, alpha, C);
     return hipGetLastError();
   }
