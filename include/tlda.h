@@ -62,7 +62,9 @@ typedef enum {
 #define TLDA_MAX_DK 16384   /* D * K: Phi must fit in a 64 KiB LDS tile */
 
 /* tlda_config.flags */
-#define TLDA_VALIDATE_CSR 0x1u  /* check every batch's CSR content (synchronous) */
+#define TLDA_VALIDATE_CSR 0x1u  /* check every batch's CSR content (synchronous);
+                                 * a rejection (TLDA_ERR_CSR) names the global
+                                 * index first_doc + row of the first bad row */
 /* BF16 precision for the per-document work (requires D, K <= 128, else
  * TLDA_ERR_SHAPE): the whitening gathers read a BF16 copy W16 = bf16(fp32(W))
  * with its own mean projection W16^T M1 (FP64), so X = (F - 1 M1^T) W16 is
@@ -115,12 +117,19 @@ typedef struct {
   int32_t eig_warm_iters; /* subspace iterations of a warm refresh, 0 = default (4) */
 } tlda_config;
 
-/* One CSR batch of documents (rows) over the vocabulary (columns).  Counts are
- * positive integer-valued floats <= 2^24; column indices are strictly
- * increasing within a row.  row_ptr[0] == 0, row_ptr[n_rows] == nnz.
+/* One CSR batch of documents (rows) over the vocabulary (columns): the rows
+ * of the paper's N x V input matrix (package section "Input and Output") for
+ * documents first_doc .. first_doc + n_rows - 1.  Counts are positive
+ * integer-valued floats <= 2^24; column indices are strictly increasing
+ * within a row.  row_ptr[0] == 0, row_ptr[n_rows] == nnz.
  * slot < 0: the arrays are caller-owned device memory.  slot >= 0: the arrays
  * are a staging slot filled by tlda_stage_batch; consuming calls then wait for
- * that copy and release the slot when their work is done. */
+ * that copy and release the slot when their work is done.  (Host batches are
+ * only read by the staging calls, which return the device view; no other
+ * call reads host memory, so the batch carries no memory-kind field.)
+ * first_doc: global index of row 0 in the corpus (>= 0); the library uses it
+ * only to name documents in its messages (a CSR rejection names the global
+ * index of the first rejected row), and the staging calls carry it over. */
 typedef struct {
   int32_t n_rows;
   int32_t nnz;
@@ -128,6 +137,7 @@ typedef struct {
   const int32_t* col_idx;   /* [nnz]        */
   const float* val;         /* [nnz]        */
   int32_t slot;
+  int64_t first_doc;
 } tlda_csr_batch;
 
 /* Create a context whose work runs on `hip_stream` (a hipStream_t; NULL = the
@@ -229,15 +239,25 @@ tlda_status tlda_whiten_cp_step(tlda_ctx* ctx, const tlda_csr_batch* batch, floa
 tlda_status tlda_unwhiten(tlda_ctx* ctx, const float* Phi, double* mu, double* alpha,
                           double* lambda, uint32_t flags);
 
-/* Document-topic proportions (the package's document-topic output), as the
- * minimiser over the probability simplex of |x_d - A theta|^2 with
+/* Document-topic proportions (package section "Input and Output": the N x K
+ * document-topic output), as the minimiser over the probability simplex of
+ * |x_d - A theta|^2 with x_d = W^T (f_d - M1) the whitened document and
  * A = W^T (mu - M1 1^T): projected gradient from theta = 1/K with step
  * 1 / lambda_max(A^T A), at most max_iter steps, stopping early when the L1
  * change of an iterate is below tol (tol = 0: exactly max_iter steps).
- * X: device float [n_rows][D] from tlda_whiten_batch.  mu: device double
- * [V][K].  theta_out: device float [n_rows][K], rows on the simplex. */
-tlda_status tlda_infer_doc_topics(tlda_ctx* ctx, const float* X, int32_t n_rows, const double* mu,
+ * batch: the documents (device or staged); each is whitened as by
+ * tlda_whiten_batch into the context's own buffer (grown on demand, which
+ * synchronises the stream), then solved.  Dropped documents (fewer than
+ * three tokens) have x_d = 0 and get the solve's value at x = 0.
+ * mu: device double [V][K], e.g. from tlda_unwhiten.  theta_out: device float
+ * [n_rows][K], rows on the simplex.  TLDA_ERR_STATE without a W. */
+tlda_status tlda_infer_doc_topics(tlda_ctx* ctx, const tlda_csr_batch* batch, const double* mu,
                                   int32_t max_iter, float tol, float* theta_out);
+/* The same solve for rows already whitened: X device float [n_rows][D] from
+ * tlda_whiten_batch (or tlda_whiten_cp_step's X_out). */
+tlda_status tlda_infer_doc_topics_whitened(tlda_ctx* ctx, const float* X, int32_t n_rows,
+                                           const double* mu, int32_t max_iter, float tol,
+                                           float* theta_out);
 
 /* Streaming (batched implementation over data larger than device memory):
  * copy a CSR batch from pinned host memory (hipHostMalloc) into staging slot
@@ -258,6 +278,7 @@ typedef struct {
   const int32_t* row_ptr;   /* [n_rows + 1] */
   const uint16_t* col_idx;  /* [nnz]        */
   const uint16_t* val;      /* [nnz] counts */
+  int64_t first_doc;        /* as in tlda_csr_batch, carried to the device view */
 } tlda_csr_batch_u16;
 
 /* tlda_stage_batch for a compact host batch: the 16-bit arrays are copied
@@ -267,11 +288,13 @@ typedef struct {
 tlda_status tlda_stage_batch_u16(tlda_ctx* ctx, const tlda_csr_batch_u16* host_batch,
                                  int32_t slot, tlda_csr_batch* dev_out);
 
-/* Inspection and test hooks (all synchronous). */
+/* Inspection and test hooks (all synchronous; they change nothing but the
+ * context's last-error message). */
 /* N, dropped documents and the int64 token totals [V] (token_totals may be NULL). */
-tlda_status tlda_get_stats(tlda_ctx* ctx, int64_t* N, int64_t* n_skipped, int64_t* token_totals);
+tlda_status tlda_get_stats(const tlda_ctx* ctx, int64_t* N, int64_t* n_skipped,
+                           int64_t* token_totals);
 /* Host copies: W [V][D], eigenvalues [D], M1 [V]; any may be NULL. */
-tlda_status tlda_get_whitening(tlda_ctx* ctx, double* W, double* eig, double* M1);
+tlda_status tlda_get_whitening(const tlda_ctx* ctx, double* W, double* eig, double* M1);
 /* Install a whitening matrix W [V][D] (mutually orthogonal columns, as any
  * U diag(lambda)^(-1/2) has) and M1 [V] from host memory, e.g. computed by an
  * independent implementation; the eigenvalues are taken as 1/|w_d|^2. */
@@ -411,7 +434,7 @@ tlda_status tlda_set_timing_events(tlda_ctx* ctx, void* const* start, void* cons
  * The checkpoint records whether the moments are classic (TLDA_CLASSIC) or
  * centred; loading into a context of the other kind, or of another V, K or
  * D, is refused (TLDA_ERR_ARG / TLDA_ERR_SHAPE) with the context unchanged. */
-tlda_status tlda_save_state(tlda_ctx* ctx, void* buf, size_t* len);
+tlda_status tlda_save_state(const tlda_ctx* ctx, void* buf, size_t* len);
 tlda_status tlda_load_state(tlda_ctx* ctx, const void* buf, size_t len);
 
 #ifdef __cplusplus

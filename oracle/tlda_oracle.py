@@ -187,6 +187,63 @@ def whiten(row_ptr, col_idx, val, V: int, m: np.ndarray, W: np.ndarray) -> np.nd
     return X
 
 
+def _frequency_csr(row_ptr, col_idx, val, V: int):
+    """Sparse n x V matrix of the frequency rows f_d = c_d / L_d (R1), rows of
+    dropped documents (R2) emptied, and the keep mask."""
+    import scipy.sparse as sp
+    L = doc_lengths(row_ptr, val)
+    keep = L >= 3
+    C = sp.csr_matrix((np.asarray(val, dtype=np.float64), np.asarray(col_idx),
+                       np.asarray(row_ptr)), shape=(L.shape[0], V))
+    scale = np.where(keep, 1.0 / np.maximum(L, 1), 0.0)
+    return sp.diags(scale) @ C, keep
+
+
+def whiten_csr(row_ptr, col_idx, val, V: int, m: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """The same X as `whiten` without the dense n x V frequency matrix: the
+    centred product (F - 1 M1^T) W split as F W - 1 (W^T M1)^T, with F a
+    sparse (CSR) matrix, dropped rows zero (R2, R5).  A regrouping of the
+    definition, for full-size batches."""
+    F, keep = _frequency_csr(row_ptr, col_idx, val, V)
+    X = np.asarray(F @ W) - (W.T @ m)[None, :]
+    X[~keep] = 0.0
+    return X
+
+
+def whitening_operator(batches, V: int, D: int, alpha0: float, extra: int = 10):
+    """W with W^T M2~ W = I_D (R3, R4) for a vocabulary too large for a dense
+    V x V matrix: M2~ v = (alpha0 + 1)/N (F^T (F v) - N M1 (M1^T v)) is applied
+    as an operator over the sparse frequency rows of every batch, and its top
+    D + extra eigenpairs come from Lanczos iteration (ARPACK, to machine
+    precision); the top D are kept, ordered and signed as in `whitening`.
+    Returns (W, top-D eigenvalues, U, M1, N)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    parts = [_frequency_csr(rp, ci, va, V) for rp, ci, va in batches]
+    F = sp.vstack([p[0] for p in parts]).tocsr()
+    N = int(sum(int(p[1].sum()) for p in parts))
+    m = np.asarray(F.sum(axis=0)).ravel() / N
+    a1 = alpha0 + 1.0
+
+    def apply(v):
+        v = np.asarray(v).reshape(V, -1)
+        return a1 / N * np.asarray(F.T @ (F @ v)) - a1 * np.outer(m, m @ v)
+
+    op = sla.LinearOperator((V, V), matvec=apply, matmat=apply, dtype=np.float64)
+    k = min(D + extra, V - 1)
+    evals, evecs = sla.eigsh(op, k=k, which="LA", tol=0.0)
+    order = np.argsort(evals)[::-1][:D]
+    lam = evals[order]
+    U = evecs[:, order].copy()
+    for j in range(D):
+        i = int(np.argmax(np.abs(U[:, j])))
+        if U[i, j] < 0:
+            U[:, j] = -U[:, j]
+    if np.any(lam <= 0):
+        raise ValueError("second moment has fewer than D positive eigenvalues")
+    return U / np.sqrt(lam)[None, :], lam, U, m, N
+
+
 # --------------------------------------------------------------------------
 # Third-moment CP decomposition (section "Online Learning of the Third Moment").
 # --------------------------------------------------------------------------

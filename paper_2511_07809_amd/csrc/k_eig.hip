@@ -124,11 +124,12 @@ __global__ void k_sum_partials(const double* __restrict__ part, int nz, size_t m
 
 hipError_t gemm(bool transA, int M, int N, int Kd, const double* A, int lda, const double* B,
                 int ldb, double* C, int ldc, double alpha, int splits, hipStream_t s) {
-  if (transA && g_eig_env.part != nullptr && (size_t)M * N <= g_eig_env.part_mn) {
+  if (transA && g_eig_env.part != nullptr && (size_t)M * N <= g_eig_env.part_mn &&
+      g_eig_env.part_chunks > 0) {
     // A^T B over many rows: row chunks of at least 64 write their own
     // partials, then one pass adds them in order (no atomics)
     int nz = (Kd + 63) / 64;
-    if (nz > kSplitMax) nz = kSplitMax;
+    if (nz > g_eig_env.part_chunks) nz = g_eig_env.part_chunks;
     if (nz < 1) nz = 1;
     const int chunk = ((Kd + nz - 1) / nz + 15) / 16 * 16;
     nz = (Kd + chunk - 1) / chunk;

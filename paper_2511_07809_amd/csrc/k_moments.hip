@@ -42,7 +42,10 @@ __global__ void __launch_bounds__(256) k_validate_csr(const int32_t* __restrict_
       if (!(v >= 1.0f) || v > 16777216.0f || v != rintf(v)) bad = 1;
     }
   }
-  if (wave_sum_i(bad) != 0 && lane == 0) atomicOr(err, 1);
+  if (wave_sum_i(bad) != 0 && lane == 0) {
+    atomicOr(err, 1);
+    atomicMax(err + 1, n_rows - row);   // the first rejected row has the largest n_rows - row
+  }
 }
 
 // One wave per document, grid-stride over the batch.  Token totals use 64-bit

@@ -22,7 +22,7 @@ struct Fail {
   tlda_status code;
 };
 
-void set_err(tlda_ctx* c, const std::string& msg) {
+void set_err(const tlda_ctx* c, const std::string& msg) {
   if (c) c->last_error = msg;
 }
 
@@ -120,6 +120,18 @@ tlda_status ensure_partial(tlda_ctx* c, size_t need) {
   return TLDA_OK;
 }
 
+// The context's own whitened-batch buffer, at least `need` floats.
+tlda_status ensure_x(tlda_ctx* c, size_t need) {
+  if (c->cp.cap_x < need) {
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    dfree(c->cp.X);
+    c->cp.cap_x = 0;
+    HIP_OK(c, dalloc(&c->cp.X, need));
+    c->cp.cap_x = need;
+  }
+  return TLDA_OK;
+}
+
 // The finish of a step (gradient and update from the reduction's partials).
 // From kGramOnceDK entries of Phi on, the squared Gram entries of Phi0 are
 // formed once first rather than by every finish block.
@@ -148,6 +160,7 @@ tlda_status check_batch(tlda_ctx* c, const tlda_csr_batch* b) {
   CHECK_ARG(c, b != nullptr, TLDA_ERR_ARG, "batch is NULL");
   CHECK_ARG(c, b->n_rows >= 0 && b->nnz >= 0, TLDA_ERR_SHAPE, "negative n_rows or nnz");
   CHECK_ARG(c, b->slot >= -1 && b->slot <= 1, TLDA_ERR_ARG, "slot must be -1, 0 or 1");
+  CHECK_ARG(c, b->first_doc >= 0, TLDA_ERR_ARG, "first_doc must be >= 0");
   if (b->n_rows > 0) CHECK_ARG(c, b->row_ptr != nullptr, TLDA_ERR_ARG, "row_ptr is NULL");
   if (b->nnz > 0)
     CHECK_ARG(c, b->col_idx != nullptr && b->val != nullptr, TLDA_ERR_ARG,
@@ -164,12 +177,18 @@ tlda_status check_batch(tlda_ctx* c, const tlda_csr_batch* b) {
 tlda_status validate_content(tlda_ctx* c, const tlda_csr_batch* b) {
   if (!(c->cfg.flags & TLDA_VALIDATE_CSR) || b->n_rows == 0 || c->in_capture) return TLDA_OK;
   if (b->slot >= 0) HIP_OK(c, hipStreamWaitEvent(c->stream, c->slots[b->slot].ready, 0));
-  HIP_OK(c, launch_zero(c->dev_flags, sizeof(int), c->stream));
+  HIP_OK(c, launch_zero(c->dev_flags, 2 * sizeof(int), c->stream));
   HIP_OK(c, tlda::launch_validate_csr(*b, c->cfg.V, c->dev_flags, c->stream));
-  int bad = 0;
-  HIP_OK(c, hipMemcpyAsync(&bad, c->dev_flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  int bad[2] = {0, 0};
+  HIP_OK(c, hipMemcpyAsync(bad, c->dev_flags, sizeof(bad), hipMemcpyDeviceToHost, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
-  CHECK_ARG(c, bad == 0, TLDA_ERR_CSR, "CSR content rejected (row_ptr, column order/range or counts)");
+  if (bad[0] != 0) {
+    const int row = b->n_rows - bad[1];
+    set_err(c, "CSR content rejected at document " + std::to_string(b->first_doc + row) +
+                   " (row " + std::to_string(row) +
+                   " of the batch): row_ptr, column order/range or counts");
+    return TLDA_ERR_CSR;
+  }
   return TLDA_OK;
 }
 
@@ -197,6 +216,7 @@ tlda_status ensure_eig(tlda_ctx* c, int p) {
   dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
   dfree(e.sel); dfree(e.mcand); dfree(e.info); dfree(e.part);
   e.p = 0;
+  e.part_chunks = 0;
   e.warm = nullptr;
   const size_t V = c->cfg.V, D = c->cfg.D;
   HIP_OK(c, dalloc(&e.Q, V * p));
@@ -209,7 +229,10 @@ tlda_status ensure_eig(tlda_ctx* c, int p) {
   HIP_OK(c, dalloc(&e.sel, D + (size_t)p * D));
   HIP_OK(c, dalloc(&e.mcand, V));
   HIP_OK(c, dalloc(&e.info, 4));
-  HIP_OK(c, dalloc(&e.part, (size_t)tlda::kSplitMax * p * p));
+  // the Gram products split their V rows into chunks of at least 64 rows
+  const int chunks = (int)std::min<size_t>(tlda::kSplitMax, (V + 63) / 64);
+  HIP_OK(c, dalloc(&e.part, (size_t)chunks * p * p));
+  e.part_chunks = chunks;
   e.p = p;
   return TLDA_OK;
 }
@@ -282,7 +305,8 @@ tlda_status refresh(tlda_ctx* c, bool warm) {
   tlda_status st = ensure_eig(c, p);
   if (st != TLDA_OK) return st;
   tlda::EigScratch& e = c->eig;
-  tlda::BlasScope blas_scope(c->blas, e.part, (size_t)p * p);
+  tlda::BlasScope blas_scope(c->tune.gemm_route == 1 ? nullptr : c->blas, e.part, (size_t)p * p,
+                             e.part_chunks);
   warm = warm && e.warm != nullptr;
   const int iters = warm ? (c->cfg.eig_warm_iters > 0 ? c->cfg.eig_warm_iters : 4)
                          : (c->cfg.eig_iters > 0 ? c->cfg.eig_iters : 60);
@@ -503,6 +527,7 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
   ctx->tune.whiten_chunks = env_int("TLDA_TUNE_WHITEN_CHUNKS");
   ctx->tune.fused_blocks = env_int("TLDA_TUNE_FUSED_BLOCKS");
   ctx->tune.bf16_blocks = env_int("TLDA_TUNE_BF16_BLOCKS");
+  ctx->tune.gemm_route = env_int("TLDA_TUNE_GEMM");
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   auto fail = [&](tlda_status s) {
     destroy_all(ctx);
@@ -674,13 +699,8 @@ tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta
     const size_t need = (size_t)b->n_rows * D;
     float* X = X_out;
     if (X == nullptr) {
-      if (c->cp.cap_x < need) {
-        HIP_OK(c, hipStreamSynchronize(c->stream));
-        dfree(c->cp.X);
-        c->cp.cap_x = 0;
-        HIP_OK(c, dalloc(&c->cp.X, need));
-        c->cp.cap_x = need;
-      }
+      st = ensure_x(c, need);
+      if (st != TLDA_OK) return st;
       X = c->cp.X;
     }
     int32_t* nk = n_kept_out ? n_kept_out : c->dev_flags + 2;
@@ -751,8 +771,27 @@ tlda_status tlda_unwhiten(tlda_ctx* c, const float* Phi, double* mu, double* alp
   return TLDA_OK;
 }
 
-tlda_status tlda_infer_doc_topics(tlda_ctx* c, const float* X, int32_t n_rows, const double* mu,
+tlda_status tlda_infer_doc_topics(tlda_ctx* c, const tlda_csr_batch* b, const double* mu,
                                   int32_t max_iter, float tol, float* theta_out) {
+  if (!c) return TLDA_ERR_ARG;
+  tlda_status st = check_batch(c, b);
+  if (st != TLDA_OK) return st;
+  CHECK_ARG(c, max_iter >= 0, TLDA_ERR_ARG, "negative max_iter");
+  CHECK_ARG(c, tol >= 0.0f && std::isfinite(tol), TLDA_ERR_ARG, "tol must be finite and >= 0");
+  CHECK_ARG(c, mu != nullptr, TLDA_ERR_ARG, "mu is NULL");
+  CHECK_ARG(c, theta_out != nullptr || b->n_rows == 0, TLDA_ERR_ARG, "theta is NULL");
+  CHECK_ARG(c, c->wh.ready, TLDA_ERR_STATE, "no whitening matrix yet");
+  if (b->n_rows == 0) return TLDA_OK;
+  st = ensure_x(c, (size_t)b->n_rows * c->cfg.D);
+  if (st != TLDA_OK) return st;
+  st = tlda_whiten_batch(c, b, c->cp.X, nullptr);
+  if (st != TLDA_OK) return st;
+  return tlda_infer_doc_topics_whitened(c, c->cp.X, b->n_rows, mu, max_iter, tol, theta_out);
+}
+
+tlda_status tlda_infer_doc_topics_whitened(tlda_ctx* c, const float* X, int32_t n_rows,
+                                           const double* mu, int32_t max_iter, float tol,
+                                           float* theta_out) {
   if (!c) return TLDA_ERR_ARG;
   CHECK_ARG(c, n_rows >= 0 && max_iter >= 0, TLDA_ERR_ARG, "negative n_rows or max_iter");
   CHECK_ARG(c, tol >= 0.0f && std::isfinite(tol), TLDA_ERR_ARG, "tol must be finite and >= 0");
@@ -778,6 +817,7 @@ tlda_status tlda_stage_batch(tlda_ctx* c, const tlda_csr_batch* h, int32_t slot,
   CHECK_ARG(c, h->n_rows >= 0 && h->nnz >= 0, TLDA_ERR_SHAPE, "negative n_rows or nnz");
   CHECK_ARG(c, h->row_ptr != nullptr, TLDA_ERR_ARG, "row_ptr is NULL");
   if (h->nnz > 0) CHECK_ARG(c, h->col_idx && h->val, TLDA_ERR_ARG, "col_idx or val is NULL");
+  CHECK_ARG(c, h->first_doc >= 0, TLDA_ERR_ARG, "first_doc must be >= 0");
   tlda::StageSlot& s = c->slots[slot];
   const size_t rows = (size_t)h->n_rows + 1, nnz = (size_t)h->nnz;
   if (s.cap_rows < rows || s.cap_nnz < nnz) {
@@ -810,6 +850,7 @@ tlda_status tlda_stage_batch(tlda_ctx* c, const tlda_csr_batch* h, int32_t slot,
   dev_out->col_idx = s.col_idx;
   dev_out->val = s.val;
   dev_out->slot = slot;
+  dev_out->first_doc = h->first_doc;
   return TLDA_OK;
 }
 
@@ -822,6 +863,7 @@ tlda_status tlda_stage_batch_u16(tlda_ctx* c, const tlda_csr_batch_u16* h, int32
   CHECK_ARG(c, h->n_rows >= 0 && h->nnz >= 0, TLDA_ERR_SHAPE, "negative n_rows or nnz");
   CHECK_ARG(c, h->row_ptr != nullptr, TLDA_ERR_ARG, "row_ptr is NULL");
   if (h->nnz > 0) CHECK_ARG(c, h->col_idx && h->val, TLDA_ERR_ARG, "col_idx or val is NULL");
+  CHECK_ARG(c, h->first_doc >= 0, TLDA_ERR_ARG, "first_doc must be >= 0");
   tlda::StageSlot& s = c->slots[slot];
   const size_t rows = (size_t)h->n_rows + 1, nnz = (size_t)h->nnz;
   if (s.cap_rows < rows || s.cap_nnz < nnz || s.cap16 < nnz) {
@@ -857,10 +899,11 @@ tlda_status tlda_stage_batch_u16(tlda_ctx* c, const tlda_csr_batch_u16* h, int32
   dev_out->col_idx = s.col_idx;
   dev_out->val = s.val;
   dev_out->slot = slot;
+  dev_out->first_doc = h->first_doc;
   return TLDA_OK;
 }
 
-tlda_status tlda_get_stats(tlda_ctx* c, int64_t* N, int64_t* n_skipped, int64_t* totals) {
+tlda_status tlda_get_stats(const tlda_ctx* c, int64_t* N, int64_t* n_skipped, int64_t* totals) {
   if (!c) return TLDA_ERR_ARG;
   unsigned long long counts[2];
   HIP_OK(c, hipMemcpyAsync(counts, c->mom.counts, sizeof(counts), hipMemcpyDeviceToHost, c->stream));
@@ -873,7 +916,7 @@ tlda_status tlda_get_stats(tlda_ctx* c, int64_t* N, int64_t* n_skipped, int64_t*
   return TLDA_OK;
 }
 
-tlda_status tlda_get_whitening(tlda_ctx* c, double* W, double* eig, double* M1) {
+tlda_status tlda_get_whitening(const tlda_ctx* c, double* W, double* eig, double* M1) {
   if (!c) return TLDA_ERR_ARG;
   CHECK_ARG(c, c->wh.ready, TLDA_ERR_STATE, "no whitening matrix yet");
   const size_t V = c->cfg.V, D = c->cfg.D;
@@ -914,7 +957,8 @@ tlda_status tlda_rebase_phi(tlda_ctx* c, float* Phi) {
   const int V = c->cfg.V, D = c->cfg.D, K = c->cfg.K;
   tlda_status st = ensure_blas(c);
   if (st != TLDA_OK) return st;
-  tlda::BlasScope blas_scope(c->blas, c->eig.part, c->eig.part ? (size_t)c->eig.p * c->eig.p : 0);
+  tlda::BlasScope blas_scope(c->tune.gemm_route == 1 ? nullptr : c->blas, c->eig.part,
+                             c->eig.part ? (size_t)c->eig.p * c->eig.p : 0, c->eig.part_chunks);
   HIP_OK(c, tlda::launch_gram(c->wh.U, c->wh.Uprev, c->wh.C, V, D, c->stream));
   HIP_OK(c, tlda::launch_rebase(c->wh.C, c->wh.eig, c->wh.eigprev, D, K, Phi, c->stream));
   return TLDA_OK;
@@ -1517,7 +1561,7 @@ struct Header {
 };
 }  // namespace
 
-tlda_status tlda_save_state(tlda_ctx* c, void* buf, size_t* len) {
+tlda_status tlda_save_state(const tlda_ctx* c, void* buf, size_t* len) {
   if (!c || !len) return TLDA_ERR_ARG;
   const size_t V = c->cfg.V, D = c->cfg.D;
   const bool has_s2 = c->mom.S2 != nullptr;

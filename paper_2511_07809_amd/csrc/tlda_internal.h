@@ -76,7 +76,8 @@ struct EigScratch {
   double* mcand = nullptr; // [V]     M1 of the refresh in progress
   int* info = nullptr;     // [4]     device status words
   double* warm = nullptr;  // Q or Y: the orthonormal block the last refresh converged to
-  double* part = nullptr;  // [kSplitMax][p][p] partial sums of the Gram products
+  double* part = nullptr;  // [part_chunks][p][p] partial sums of the Gram products
+  int part_chunks = 0;     // min(kSplitMax, ceil(V / 64)): the most row chunks gemm() uses
 };
 
 // Launch-shape knobs (0 = built-in choice).  Initialised from the
@@ -86,7 +87,8 @@ struct EigScratch {
 // TLDA_TUNE_BF16_BLOCKS: the same for the BF16 kernels).  cp_max_blocks: grid of the CP reduction
 // (default: one full round of resident blocks); whiten_v4: float4 columns
 // per lane (1 or 2); whiten_chunks: XCD column chunks (1, 2, 4, 8; -1 = by
-// W size).
+// W size); gemm_route (TLDA_TUNE_GEMM): 1 runs the refresh's dense products
+// on the library's vector-ALU tile kernel instead of the default route.
 struct Tuning {
   int cp_max_blocks = 0;
   int fused_blocks = 0;
@@ -96,6 +98,7 @@ struct Tuning {
   int classic16_resident = 0;         // and its BF16 variant
   int whiten_v4 = 0;
   int whiten_chunks = 0;
+  int gemm_route = 0;                 // refresh products: 0 built-in choice, 1 the vector kernel
 };
 
 struct CpScratch {
@@ -144,7 +147,7 @@ struct tlda_ctx {
   int t_n = 0, t_next = 0;
   bool in_capture = false;    // capturing a graph of steps: no validation, no timing hook
   void* blas = nullptr;       // rocblas_handle of the refresh's FP64 products (created lazily)
-  std::string last_error;
+  mutable std::string last_error;   // also set by the const inspection calls
 };
 
 // Document-topic encoder: d_in -> hidden -> hidden -> k_out MLP (GELU,
@@ -217,19 +220,22 @@ extern thread_local KernelTimer g_main_timer;
 constexpr int kSplitMax = 256;
 struct EigEnv {
   void* blas = nullptr;
-  double* part = nullptr;     // kSplitMax * part_mn doubles
+  double* part = nullptr;     // part_chunks * part_mn doubles
   size_t part_mn = 0;         // largest M * N the scratch serves
+  int part_chunks = 0;        // row chunks the scratch holds (at most kSplitMax)
 };
 extern thread_local void* g_blas;
 extern thread_local EigEnv g_eig_env;
 struct BlasScope {
   EigEnv prev;
   void* prev_blas;
-  BlasScope(void* h, double* part, size_t part_mn) : prev(g_eig_env), prev_blas(g_blas) {
+  BlasScope(void* h, double* part, size_t part_mn, int part_chunks)
+      : prev(g_eig_env), prev_blas(g_blas) {
     g_blas = h;
     g_eig_env.blas = h;
     g_eig_env.part = part;
     g_eig_env.part_mn = part_mn;
+    g_eig_env.part_chunks = part_chunks;
   }
   ~BlasScope() {
     g_blas = prev_blas;
@@ -250,6 +256,8 @@ inline void launch_main(void (*kernel)(Params...), dim3 grid, dim3 block, unsign
 // zero-fill with a kernel (no memset nodes, so callers may capture the work)
 hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s);
 // moments
+// err[0] != 0 when some row is rejected; err[1] = n_rows - (first rejected
+// row) then (err[0..1] zeroed by the caller)
 hipError_t launch_validate_csr(const tlda_csr_batch& b, int V, int* err, hipStream_t s);
 // block_counts: scratch for 2 * kWhitenBlockCounts ints
 // classic: S2 takes the unbiased pair piece (c c^T - diag c) / (L (L - 1))

@@ -36,7 +36,7 @@ TLDA_MLP_MAX_WIDTH = 1024
 EXPORTED = ("tlda_create", "tlda_destroy", "tlda_status_str", "tlda_last_error",
             "tlda_update_moments", "tlda_whiten_batch", "tlda_cp_step", "tlda_whiten_cp_step",
             "tlda_unwhiten",
-            "tlda_infer_doc_topics", "tlda_stage_batch", "tlda_stage_batch_u16", "tlda_get_stats",
+            "tlda_infer_doc_topics", "tlda_infer_doc_topics_whitened", "tlda_stage_batch", "tlda_stage_batch_u16", "tlda_get_stats",
             "tlda_get_whitening", "tlda_set_whitening", "tlda_rebase_phi",
             "tlda_set_timing_events",
             "tlda_save_state", "tlda_load_state",
@@ -61,7 +61,8 @@ class tlda_config(ctypes.Structure):
 class tlda_csr_batch(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int32), ("nnz", ctypes.c_int32),
                 ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
-                ("val", ctypes.c_void_p), ("slot", ctypes.c_int32)]
+                ("val", ctypes.c_void_p), ("slot", ctypes.c_int32),
+                ("first_doc", ctypes.c_int64)]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -81,7 +82,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tlda_whiten_cp_step": ([vp, ctypes.POINTER(tlda_csr_batch), ctypes.c_float, vp, vp, vp,
                                  vp], i32),
         "tlda_unwhiten": ([vp, vp, vp, vp, vp, u32], i32),
-        "tlda_infer_doc_topics": ([vp, vp, i32, vp, i32, ctypes.c_float, vp], i32),
+        "tlda_infer_doc_topics": ([vp, ctypes.POINTER(tlda_csr_batch), vp, i32, ctypes.c_float,
+                                   vp], i32),
+        "tlda_infer_doc_topics_whitened": ([vp, vp, i32, vp, i32, ctypes.c_float, vp], i32),
         "tlda_stage_batch": ([vp, ctypes.POINTER(tlda_csr_batch), i32,
                               ctypes.POINTER(tlda_csr_batch)], i32),
         "tlda_stage_batch_u16": ([vp, vp, i32, ctypes.POINTER(tlda_csr_batch)], i32),
@@ -173,7 +176,7 @@ class CsrBatch:
     """A CSR batch whose arrays live in device (or pinned host) memory."""
 
     def __init__(self, row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor,
-                 slot: int = -1):
+                 slot: int = -1, first_doc: int = 0):
         assert row_ptr.dtype == torch.int32 and col_idx.dtype == torch.int32
         assert val.dtype == torch.float32
         assert row_ptr.is_contiguous() and col_idx.is_contiguous() and val.is_contiguous()
@@ -181,34 +184,37 @@ class CsrBatch:
         self.n_rows = row_ptr.numel() - 1
         self.nnz = col_idx.numel()
         self.slot = slot
+        self.first_doc = int(first_doc)
 
     @classmethod
-    def from_numpy(cls, row_ptr, col_idx, val, device="cuda", pin=False):
+    def from_numpy(cls, row_ptr, col_idx, val, device="cuda", pin=False, first_doc=0):
         rp = torch.from_numpy(row_ptr.astype("int32", copy=False))
         ci = torch.from_numpy(col_idx.astype("int32", copy=False))
         va = torch.from_numpy(val.astype("float32", copy=False))
         if pin:
-            return cls(rp.pin_memory(), ci.pin_memory(), va.pin_memory())
-        return cls(rp.to(device), ci.to(device), va.to(device))
+            return cls(rp.pin_memory(), ci.pin_memory(), va.pin_memory(), first_doc=first_doc)
+        return cls(rp.to(device), ci.to(device), va.to(device), first_doc=first_doc)
 
     def struct(self) -> tlda_csr_batch:
         return tlda_csr_batch(self.n_rows, self.nnz, self.row_ptr.data_ptr(),
                               self.col_idx.data_ptr() if self.nnz else None,
-                              self.val.data_ptr() if self.nnz else None, self.slot)
+                              self.val.data_ptr() if self.nnz else None, self.slot,
+                              self.first_doc)
 
 
 class tlda_csr_batch_u16(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int32), ("nnz", ctypes.c_int32),
                 ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
-                ("val", ctypes.c_void_p)]
+                ("val", ctypes.c_void_p), ("first_doc", ctypes.c_int64)]
 
 
 class CsrBatchU16:
     """A CSR batch in the compact staging format (pinned host memory):
     int32 row pointers, 16-bit column indices and counts."""
 
-    def __init__(self, row_ptr, col_idx, val):
+    def __init__(self, row_ptr, col_idx, val, first_doc: int = 0):
         import numpy as np
+        self.first_doc = int(first_doc)
         assert col_idx.size == 0 or int(col_idx.max()) < 65536
         assert val.size == 0 or (float(val.min()) >= 1 and float(val.max()) <= 65535)
         self.n_rows = int(row_ptr.shape[0]) - 1
@@ -220,14 +226,14 @@ class CsrBatchU16:
     def struct(self) -> tlda_csr_batch_u16:
         return tlda_csr_batch_u16(self.n_rows, self.nnz, self.row_ptr.data_ptr(),
                                   self.col_idx.data_ptr() if self.nnz else None,
-                                  self.val.data_ptr() if self.nnz else None)
+                                  self.val.data_ptr() if self.nnz else None, self.first_doc)
 
 
 class _StagedBatch(CsrBatch):
     def __init__(self, s: tlda_csr_batch, owner: CsrBatch):
         self._s = s
         self._owner = owner          # keeps the pinned host arrays alive
-        self.n_rows, self.nnz, self.slot = s.n_rows, s.nnz, s.slot
+        self.n_rows, self.nnz, self.slot, self.first_doc = s.n_rows, s.nnz, s.slot, s.first_doc
 
     def struct(self) -> tlda_csr_batch:
         return self._s
@@ -299,14 +305,25 @@ def tlda_unwhiten(ctx: Context, Phi: torch.Tensor, flags: int = 0):
     return mu, alpha, lam
 
 
-def tlda_infer_doc_topics(ctx: Context, X: torch.Tensor, n_rows: int, mu: torch.Tensor,
-                          max_iter: int, tol: float = 0.0,
-                          theta: Optional[torch.Tensor] = None) -> torch.Tensor:
+def tlda_infer_doc_topics(ctx: Context, batch: CsrBatch, mu: torch.Tensor, max_iter: int,
+                          tol: float = 0.0, theta: Optional[torch.Tensor] = None) -> torch.Tensor:
+    if theta is None:
+        theta = torch.empty((batch.n_rows, ctx.K), dtype=torch.float32, device="cuda")
+    assert mu.dtype == torch.float64 and mu.is_contiguous()
+    s = batch.struct()
+    _check(ctx, _LIB.tlda_infer_doc_topics(ctx.handle, ctypes.byref(s), _ptr(mu), max_iter,
+                                           float(tol), _ptr(theta)))
+    return theta
+
+
+def tlda_infer_doc_topics_whitened(ctx: Context, X: torch.Tensor, n_rows: int, mu: torch.Tensor,
+                                   max_iter: int, tol: float = 0.0,
+                                   theta: Optional[torch.Tensor] = None) -> torch.Tensor:
     if theta is None:
         theta = torch.empty((n_rows, ctx.K), dtype=torch.float32, device="cuda")
     assert mu.dtype == torch.float64 and mu.is_contiguous()
-    _check(ctx, _LIB.tlda_infer_doc_topics(ctx.handle, _ptr(X), n_rows, _ptr(mu), max_iter,
-                                           float(tol), _ptr(theta)))
+    _check(ctx, _LIB.tlda_infer_doc_topics_whitened(ctx.handle, _ptr(X), n_rows, _ptr(mu),
+                                                    max_iter, float(tol), _ptr(theta)))
     return theta
 
 

@@ -27,12 +27,13 @@ import torch
 from oracle import tlda_oracle as O
 from synth import SPECS, generate, init_phi, iter_batches, make_csr_rows
 
+from bf16_ref import U_BF16, assert_within, bf16_round, fused_bound, rounded_gradient
+
 pytestmark = pytest.mark.gpu
 
 tl = pytest.importorskip("paper_2511_07809_amd.tlda")
 
 REL32 = 1e-5
-U_BF16 = 2.0 ** -8
 
 
 def rel(a, b):
@@ -41,36 +42,12 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def bf16_round(a):
-    """Nearest BF16 value of fp32(a), ties to even (the format's definition:
-    keep the upper 16 bits of the FP32 pattern after adding half an ulp)."""
-    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
-    u = f.view(np.uint32).astype(np.uint64)
-    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
-    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
-
-
 def dev_batch(rp, ci, va):
     return tl.CsrBatch.from_numpy(rp, ci, va)
 
 
 def make_ctx(V, K, D, alpha0=1.0, theta=0.0, **kw):
     return tl.tlda_create(V, K, D, alpha0, theta, bf16=True, **kw)
-
-
-def rounded_gradient(X, Phi, n, alpha0, theta):
-    """Oracle gradient with the data term on BF16-rounded X and Phi and the
-    penalty term on the FP32 Phi; plus the magnitude sums B and C."""
-    Xh, Ph = bf16_round(X), bf16_round(Phi)
-    Phi64 = np.asarray(Phi, dtype=np.float64)
-    zero = np.zeros((1, Phi.shape[0]))
-    pen = O.cp_gradient(zero, Phi64, n, alpha0, theta)
-    data = O.cp_gradient(Xh, Ph, n, alpha0, theta) - O.cp_gradient(zero, Ph, n, alpha0, theta)
-    S = Xh @ Ph
-    B = np.abs(Xh).T @ (S * S)
-    C = np.abs(Xh).T @ (np.abs(S) * (np.abs(Xh) @ np.abs(Ph)))
-    scale = 3.0 * (alpha0 + 1.0) * (alpha0 + 2.0) / 2.0 / n
-    return pen + data, scale * B, scale * C
 
 
 def _rows(V, n, seed, max_len=45):
@@ -119,12 +96,6 @@ def _cp_case(n, D, K, seed, scale=1.0):
     return X.astype(np.float32), Phi.astype(np.float32)
 
 
-def _assert_within(got, ref, bound, what):
-    excess = np.abs(got - ref) - bound
-    worst = float(excess.max())
-    assert worst <= 0.0, f"{what}: exceeds the rounding bound by {worst:g}"
-
-
 @pytest.mark.parametrize("D,K,n", [(5, 5, 1000), (10, 10, 3001), (20, 20, 777), (50, 50, 4099),
                                    (64, 64, 2048), (100, 100, 1500), (128, 100, 515),
                                    (128, 128, 700), (7, 3, 999), (3, 12, 64), (1, 1, 5),
@@ -141,7 +112,7 @@ def test_bf16_cp_gradient_within_rounding_bound(D, K, n, theta):
     ref, B, C = rounded_gradient(X, Phi, n, a0, theta)
     got = g.cpu().numpy().astype(np.float64)
     bound = 2 * U_BF16 * B + D * 2.0 ** -23 * C + 2.0 ** -22 * np.abs(ref)
-    _assert_within(got, ref, bound, "gradient")
+    assert_within(got, ref, bound, "gradient")
     upd = Phi.astype(np.float64) - beta * got
     assert rel(Pd.cpu().numpy(), upd) < 1e-6
     # error against the unrounded FP64 gradient, reported with a loose bound
@@ -160,7 +131,7 @@ def test_bf16_cp_step_kept_count_empty_batch_and_reproducibility():
     g = torch.empty_like(Pd)
     tl.tlda_cp_step(ctx, Xd, 300, nk, 0.01, Pd, g)
     ref, B, C = rounded_gradient(X, Phi, 200, 1.0, 0.0)
-    _assert_within(g.cpu().numpy(), ref, 2 * U_BF16 * B + D * 2.0 ** -23 * C + 1e-7 * np.abs(ref),
+    assert_within(g.cpu().numpy(), ref, 2 * U_BF16 * B + D * 2.0 ** -23 * C + 1e-7 * np.abs(ref),
                    "gradient with kept count")
     P0 = Pd.clone()
     tl.tlda_cp_step(ctx, Xd, 300, torch.zeros(1, dtype=torch.int32, device="cuda"), 0.01, Pd, g)
@@ -187,7 +158,7 @@ def test_bf16_cp_step_full_batch_shapes(n, D, K, V, a0):
     tl.tlda_cp_step(ctx, torch.from_numpy(X).cuda(), n, None, 1e-4, Pd, g)
     ref, B, C = rounded_gradient(X, Phi, n, a0, 0.0)
     got = g.cpu().numpy().astype(np.float64)
-    _assert_within(got, ref, 2 * U_BF16 * B + D * 2.0 ** -23 * C + 2.0 ** -22 * np.abs(ref),
+    assert_within(got, ref, 2 * U_BF16 * B + D * 2.0 ** -23 * C + 2.0 ** -22 * np.abs(ref),
                    "full-size gradient")
 
 
@@ -216,7 +187,7 @@ def test_bf16_fused_step_matches_rounded_oracle(D, K):
     assert rel(Xo.cpu().numpy(), X_ref) < REL32
     ref, B, C = rounded_gradient(X_ref, Phi0, n_ref, a0, theta)
     got = g.cpu().numpy().astype(np.float64)
-    _assert_within(got, ref, 4 * U_BF16 * (B + C) + 2.0 ** -22 * np.abs(ref), "fused gradient")
+    assert_within(got, ref, 4 * U_BF16 * (B + C) + 2.0 ** -22 * np.abs(ref), "fused gradient")
     assert rel(Pd.cpu().numpy(), Phi0.astype(np.float64) - beta * got) < 1e-6
 
 
@@ -247,18 +218,20 @@ def test_bf16_fused_step_at_the_largest_vocabulary():
     assert rel(Xo.cpu().numpy(), X_ref) < REL32
     ref, B, C = rounded_gradient(X_ref, Phi0, n_ref, a0, theta)
     got = g.cpu().numpy().astype(np.float64)
-    _assert_within(got, ref, 4 * U_BF16 * (B + C) + 2.0 ** -22 * np.abs(ref), "fused gradient")
+    assert_within(got, ref, 4 * U_BF16 * (B + C) + 2.0 ** -22 * np.abs(ref), "fused gradient")
 
 
-def test_bf16_fused_step_full_size_matches_oracle():
-    """The fused BF16 step on one full 131 072-document batch of the
-    tweet-shaped workload (the benchmarked configuration) against the oracle's
-    gradient of the same batch whitened by W16 = bf16(W): X from the sparse
-    product F W16 - 1 (W16^T M1)^T, tied to the oracle's whitening on sampled
-    rows.  The step's remaining roundings (X, Phi and S^2 to BF16) are
-    bounded as in the rest of this file's unrounded comparisons: 5e-2."""
-    import scipy.sparse as sp
-    spec = SPECS["c2"]
+@pytest.mark.parametrize("workload", ["c2", "c3"])
+def test_bf16_fused_step_full_size_within_rounding_bound(workload):
+    """The fused BF16 step on one full batch of the tweet-shaped workload
+    (131 072 x 50) and of the streaming workload (262 144 x 100, V = 50 000),
+    in the launch configuration the benchmark times, against the oracle's
+    gradient of the same batch whitened by W16 = bf16(W), element by element
+    within the derived bound 4u (B + C) + 2^-22 |ref|.  X is the oracle's
+    sparse whitening (tied to the dense definition on sampled rows); the
+    kept-row count is exact.  The streaming batch is also staged through the
+    compact 16-bit host format and must give the same gradient bit for bit."""
+    spec = SPECS[workload]
     c = generate(spec, n_docs=spec.batch)
     rp, ci, va, _ = next(iter_batches(c))
     D = K = spec.K
@@ -267,24 +240,33 @@ def test_bf16_fused_step_full_size_matches_oracle():
     W = Q * rng.uniform(20, 200, size=D)[None, :]
     m = np.bincount(ci, weights=va, minlength=spec.V) / va.sum()
     Wh = bf16_round(W)
-    st = O.batch_stats(rp, ci, va, spec.V)
-    F = sp.csr_matrix((va.astype(np.float64), ci, rp), shape=(rp.size - 1, spec.V))
-    F = sp.diags(1.0 / np.maximum(np.asarray(F.sum(axis=1)).ravel(), 1.0)) @ F
-    X = F @ Wh - (Wh.T @ m)[None, :]
-    X[~st["keep"]] = 0.0
-    for r in rng.choice(rp.size - 1, 50, replace=False):
+    X = O.whiten_csr(rp, ci, va, spec.V, m, Wh)
+    for r in np.concatenate([rng.choice(rp.size - 1, 40, replace=False), [0, rp.size - 2]]):
         a_, b_ = int(rp[r]), int(rp[r + 1])
         one = O.whiten(np.array([0, b_ - a_]), ci[a_:b_], va[a_:b_], spec.V, m, Wh)[0]
         np.testing.assert_allclose(X[r], one, rtol=0, atol=1e-12 * max(1.0, np.abs(one).max()))
+    n_ref = int(O.batch_stats(rp, ci, va, spec.V)["n_kept"])
     Phi = (init_phi(D, K, 3) * 0.5).astype(np.float32)
-    g_ref = O.cp_gradient(X, Phi.astype(np.float64), st["n_kept"], spec.alpha0, 0.0)
+    ref, B, C = rounded_gradient(X, Phi, n_ref, spec.alpha0, 0.0)
     ctx = make_ctx(spec.V, K, D, spec.alpha0)
     tl.tlda_set_whitening(ctx, W, m)
     Pd = torch.from_numpy(Phi).cuda()
     g = torch.empty_like(Pd)
-    tl.tlda_whiten_cp_step(ctx, dev_batch(rp, ci, va), 1e-4, Pd, g)
+    nk = torch.zeros(1, dtype=torch.int32, device="cuda")
+    tl.tlda_whiten_cp_step(ctx, dev_batch(rp, ci, va), 1e-4, Pd, g, None, nk)
     torch.cuda.synchronize()
-    assert rel(g.cpu().numpy(), g_ref) < 5e-2
+    assert int(nk.item()) == n_ref
+    got = g.cpu().numpy().astype(np.float64)
+    assert_within(got, ref, fused_bound(ref, B, C), f"{workload} full-size fused gradient")
+    assert rel(Pd.cpu().numpy(), Phi.astype(np.float64) - 1e-4 * got) < 1e-6
+    if workload == "c3":
+        host = tl.CsrBatchU16(rp, ci, va)
+        staged = tl.tlda_stage_batch_u16(ctx, host, 1)
+        P2 = torch.from_numpy(Phi).cuda()
+        g2 = torch.empty_like(P2)
+        tl.tlda_whiten_cp_step(ctx, staged, 1e-4, P2, g2)
+        torch.cuda.synchronize()
+        assert torch.equal(g2, g) and torch.equal(P2, Pd)
 
 
 def test_bf16_fused_equals_split_at_full_size_and_is_reproducible():

@@ -97,6 +97,61 @@ def test_multi_step_matches_single_slice_steps(side_stream):
             assert int(nk[i].item()) == int(n1.item())
 
 
+# One slice per shape class of the multi-slice kernel: D in {5, 12, 30, 50}
+# (8-column groups G = 1, 2, 4, 8 of the BF16 whitening copy; padded D 32 or
+# 64) times K in {10, 20, 50} (padded K 16, 32, 64), with uneven row counts.
+SHAPE_CLASSES = [(D, K) for D in (5, 12, 30, 50) for K in (10, 20, 50)]
+
+
+def test_multi_step_matches_oracle_in_every_shape_class(side_stream):
+    """One multi-slice step over twelve slices (every shape class the
+    persistent kernel dispatches on) plus an empty slice, each against the
+    oracle's gradient of its own batch whitened by its own W16 = bf16(W),
+    within the derived element-wise bound of a fused BF16 step.  The gradient
+    is recovered from the update, (Phi0 - Phi1) / beta, which adds at most
+    2^-24 |Phi1| / beta; the kept-row counts must be exact."""
+    from bf16_ref import assert_within, bf16_round, fused_bound, rounded_gradient
+    from oracle import tlda_oracle as O
+    ctxs, batches, phis0, host, whit, params = [], [], [], [], [], []
+    slices = [(D, K, 97 + 331 * i) for i, (D, K) in enumerate(SHAPE_CLASSES)] + [(20, 20, 0)]
+    for i, (D, K, n) in enumerate(slices):
+        seed = 50 + i
+        rng = np.random.default_rng(seed)
+        Q, _ = np.linalg.qr(rng.standard_normal((V, D)))
+        W = Q * rng.uniform(5, 30, size=D)[None, :]
+        m = rng.dirichlet(np.ones(V))
+        a0, theta = 1.0 + 0.5 * (i % 3), 0.25 * (i % 2)
+        ctx = tl.tlda_create(V, K, D, a0, theta, bf16=True, stream=side_stream)
+        tl.tlda_set_whitening(ctx, W, m)
+        rp, ci, va = _rows(n, seed + 100)
+        ctxs.append(ctx)
+        batches.append(tl.CsrBatch.from_numpy(rp, ci, va))
+        phis0.append((init_phi(D, K, seed) * 0.9).astype(np.float32))
+        host.append((rp, ci, va))
+        whit.append((W, m))
+        params.append((a0, theta))
+    betas = [2e-3 * (1 + i % 4) for i in range(len(ctxs))]
+    Ps = [torch.from_numpy(p).cuda() for p in phis0]
+    nk = torch.full((len(ctxs),), -1, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    plan = tl.tlda_multi_create(ctxs, batches, Ps, betas, nk)
+    tl.tlda_multi_step(plan)
+    side_stream.synchronize()
+    for i, ((D, K, n), (rp, ci, va), (W, m), (a0, theta)) in enumerate(
+            zip(slices, host, whit, params)):
+        st = O.batch_stats(rp, ci, va, V)
+        assert int(nk[i].item()) == st["n_kept"], slices[i]
+        P1 = Ps[i].cpu().numpy().astype(np.float64)
+        if st["n_kept"] == 0:
+            assert np.array_equal(P1, phis0[i]), slices[i]
+            continue
+        X_ref = O.whiten(rp, ci, va, V, m, bf16_round(W))
+        ref, B, C = rounded_gradient(X_ref, phis0[i], st["n_kept"], a0, theta)
+        got = (phis0[i].astype(np.float64) - P1) / betas[i]
+        bound = fused_bound(ref, B, C) + 2.0 ** -24 * np.abs(P1) / betas[i]
+        assert_within(got, ref, bound, f"slice {i} (D={D}, K={K}, n={n})")
+
+
 def test_autotune_restores_phi_and_chooses_a_valid_shape(side_stream):
     ctxs, batches, phis0 = _build(side_stream, seed0=11)
     Ps = [torch.from_numpy(p).cuda() for p in phis0]

@@ -226,12 +226,15 @@ def test_cp_gradient_and_step_match_oracle(D, K, n, theta):
     assert rel(Pd.cpu().numpy(), ref_p) < REL32
 
 
-@pytest.mark.parametrize("cap", [1, 200, 256, 300, 700, 1023, 1024, 1100, 1500])
+@pytest.mark.parametrize("cap", [1, 191, 192, 193, 200, 256, 300, 700, 1023, 1024, 1100, 1500])
 def test_cp_finish_at_every_partial_count(cap, monkeypatch):
     """The finish adds the reduction's per-block partials, nblk of them, and
-    prefetches them by three routes (nblk below 256, 256 to 1023, 1024 and
-    more, each with its own tail); the block-count cap fixes nblk for a batch
-    with more row tiles than any cap here."""
+    prefetches them by three routes: none up to nblk = 192 (no lane has a
+    full quad of four partials 64 apart), clamped loads from 193 to 1023
+    (the lanes whose first quad exists add it, the others drop theirs), and
+    every prefetched row present from 1024 on; each route has its own tail.
+    The block-count cap fixes nblk for a batch with more row tiles than any
+    cap here."""
     monkeypatch.setenv("TLDA_TUNE_CP_BLOCKS", str(cap))
     D = K = 50
     n = 150_000
@@ -416,16 +419,11 @@ def test_fused_step_equals_split_steps_at_full_size():
 
 
 def _full_batch_reference(spec, rp, ci, va, W, m, Phi, theta, check_rows, rng):
-    """X of a full batch as the sparse product F W - 1 (W^T M1)^T (dropped rows
-    zero), tied to the oracle's whitening on sampled rows, and the oracle's
+    """X of a full batch from the oracle's sparse whitening (dropped rows
+    zero), tied to its dense definition on sampled rows, and the oracle's
     gradient on it."""
-    import scipy.sparse as sp
     st = O.batch_stats(rp, ci, va, spec.V)
-    F = sp.csr_matrix((va.astype(np.float64), ci, rp), shape=(rp.size - 1, spec.V))
-    Ld = np.asarray(F.sum(axis=1)).ravel()
-    F = sp.diags(1.0 / np.maximum(Ld, 1.0)) @ F
-    X = F @ W - (W.T @ m)[None, :]
-    X[~st["keep"]] = 0.0
+    X = O.whiten_csr(rp, ci, va, spec.V, m, W)
     for r in rng.choice(rp.size - 1, check_rows, replace=False):
         a, b = int(rp[r]), int(rp[r + 1])
         one = O.whiten(np.array([0, b - a]), ci[a:b], va[a:b], spec.V, m, W)[0]
@@ -434,12 +432,13 @@ def _full_batch_reference(spec, rp, ci, va, W, m, Phi, theta, check_rows, rng):
     return X, g, st["n_kept"]
 
 
-@pytest.mark.parametrize("theta", [0.0, 1.0])
-def test_fused_step_full_size_matches_oracle(theta):
-    """The fused FP32 step on one full 131 072-document batch of the
-    tweet-shaped workload, in the benchmark's launch configuration, against
-    the oracle's gradient of the same batch."""
-    spec = SPECS["c2"]
+@pytest.mark.parametrize("workload,theta", [("c2", 0.0), ("c2", 1.0), ("c3", 0.0)])
+def test_fused_step_full_size_matches_oracle(workload, theta):
+    """The fused FP32 step on one full batch, in the benchmark's launch
+    configuration, against the oracle's gradient of the same batch: 131 072
+    documents of the tweet-shaped workload (D = K = 50) and 262 144 of the
+    streaming workload (V = 50 000, D = K = 100)."""
+    spec = SPECS[workload]
     c = generate(spec, n_docs=spec.batch)
     rp, ci, va, _ = next(iter_batches(c))
     D = K = spec.K
@@ -479,20 +478,58 @@ def test_unwhiten_matches_oracle(c1, theta):
 
 
 def test_infer_doc_topics_matches_oracle(c1):
+    """Document-topic proportions from a CSR batch (whitened inside the call)
+    and from already whitened rows, against the oracle's projected-gradient
+    solve on the oracle's whitening; a batch with empty and dropped rows
+    gives those rows the solve's value at x = 0."""
     spec = c1["spec"]
     ctx = make_ctx(spec.V, spec.K, spec.K, spec.alpha0)
     tl.tlda_set_whitening(ctx, c1["W"], c1["m"])
     mu = np.ascontiguousarray(c1["corpus"].mu)
+    mud = torch.from_numpy(mu).cuda()
+    A = O.inference_matrix(mu, c1["m"], c1["W"])
     rp, ci, va = c1["batches"][0]
     X, nk = tl.tlda_whiten_batch(ctx, dev_batch(rp, ci, va))
     Xo = O.whiten(rp, ci, va, spec.V, c1["m"], c1["W"])
-    A = O.inference_matrix(mu, c1["m"], c1["W"])
-    th = tl.tlda_infer_doc_topics(ctx, X, 200, torch.from_numpy(mu).cuda(), 100)
+    th = tl.tlda_infer_doc_topics_whitened(ctx, X, 200, mud, 100)
     ref = O.infer_doc_topics(Xo[:200], A, 100)
     got = th.cpu().numpy()
     np.testing.assert_allclose(got.sum(axis=1), 1.0, atol=1e-5)
     assert got.min() >= 0
     assert np.abs(got - ref).sum(axis=1).max() < 1e-3
+    rows = [{}, {4: 1}, {1: 2, 8: 1}] + [
+        {int(w): int(c) for w, c in zip(ci[rp[d]:rp[d + 1]], va[rp[d]:rp[d + 1]])}
+        for d in range(300)]
+    rp2, ci2, va2 = make_csr_rows(rows, spec.V)
+    b = tl.CsrBatch.from_numpy(rp2, ci2, va2, first_doc=123456)
+    th2 = tl.tlda_infer_doc_topics(ctx, b, mud, 100).cpu().numpy()
+    ref2 = O.infer_doc_topics(O.whiten(rp2, ci2, va2, spec.V, c1["m"], c1["W"]), A, 100)
+    np.testing.assert_allclose(th2.sum(axis=1), 1.0, atol=1e-5)
+    assert th2.min() >= 0
+    assert np.abs(th2 - ref2).sum(axis=1).max() < 1e-3
+    assert np.abs(th2[3:3 + 200] - got).max() < 1e-5    # the same documents either way
+
+
+def test_csr_rejection_names_the_global_document():
+    """With validation on, a rejected batch reports the global index
+    first_doc + row of its first bad row, and the context is unchanged."""
+    V = 20
+    ctx = make_ctx(V, 2, 2, validate_csr=True)
+    rows = [{0: 2, 3: 1}, {1: 1, 2: 2, 5: 1}, {4: 1, 6: 2}, {7: 3, 9: 1}]
+    rp, ci, va = make_csr_rows(rows, V)
+    ci2, va2 = ci.copy(), va.copy()
+    va2[rp[2]] = 0.5                           # row 2: a count that is not a positive integer
+    ci2[rp[3]] = V                             # row 3: a column out of range
+    with pytest.raises(tl.TldaError) as e:
+        tl.tlda_update_moments(ctx, tl.CsrBatch.from_numpy(rp, ci2, va2, first_doc=1_000_000))
+    assert e.value.status == 3
+    assert "document 1000002 " in str(e.value) and "row 2 " in str(e.value)
+    assert tl.tlda_get_stats(ctx)[0] == 0
+    with pytest.raises(tl.TldaError) as e:
+        tl.tlda_update_moments(ctx, tl.CsrBatch.from_numpy(rp, ci, va, first_doc=-1))
+    assert e.value.status == 1
+    tl.tlda_update_moments(ctx, tl.CsrBatch.from_numpy(rp, ci, va, first_doc=7))
+    assert tl.tlda_get_stats(ctx)[0] == 4
 
 
 # ----------------------------------------------------------------------------
@@ -539,6 +576,59 @@ def test_staged_batches_equal_device_batches(c1):
     for X, b in zip(outs, c1["batches"]):
         Xr, _ = tl.tlda_whiten_batch(ctx, dev_batch(*b))
         assert torch.equal(X, Xr)
+
+
+@pytest.mark.parametrize("fmt,bf16", [("f32", False), ("u16", False), ("u16", True)])
+def test_staged_batches_match_oracle(c1, fmt, bf16):
+    """Batches staged from pinned host memory (32-bit, or the compact 16-bit
+    format widened on the device), consumed in the order a streamed pass uses
+    them (batch i + 1 staged before batch i is stepped, the two slots
+    alternating), against the oracle directly: the whitened rows (FP32 bar, or
+    for BF16 the whitening by W16 = bf16(W)), the kept-row counts, and the
+    gradient of a fused step from a fresh Phi on every batch (FP32: 1e-5;
+    BF16: the derived element-wise bound).  Batches include a ragged one with
+    empty and dropped rows, and one without rows."""
+    from bf16_ref import assert_within, bf16_round, fused_bound, rounded_gradient
+    spec = c1["spec"]
+    ctx = make_ctx(spec.V, spec.K, spec.K, spec.alpha0, 0.5, bf16=bf16)
+    tl.tlda_set_whitening(ctx, c1["W"], c1["m"])
+    rp0, ci0, va0 = make_csr_rows([{}, {1: 1}, {2: 2, 7: 1}, {3: 1, 4: 1, 499: 1}], spec.V)
+    empty = make_csr_rows([], spec.V)
+    batches = [c1["batches"][0], (rp0, ci0, va0), empty] + list(c1["batches"][1:4])
+    make = tl.CsrBatchU16 if fmt == "u16" else (lambda *b: tl.CsrBatch.from_numpy(*b, pin=True))
+    stage = tl.tlda_stage_batch_u16 if fmt == "u16" else tl.tlda_stage_batch
+    host = [make(*b) for b in batches]
+    Wr = bf16_round(c1["W"]) if bf16 else c1["W"]
+    Phi0 = (init_phi(spec.K, spec.K, 6) * 0.9).astype(np.float32)
+    staged = [stage(ctx, host[0], 0)]
+    for i, (rp, ci, va) in enumerate(batches):
+        if i + 1 < len(host):
+            staged.append(stage(ctx, host[i + 1], (i + 1) % 2))
+        n = rp.size - 1
+        X, nk = tl.tlda_whiten_batch(ctx, staged[i], X=torch.empty((max(n, 1), spec.K),
+                                                                  device="cuda"))
+        Pd = torch.from_numpy(Phi0).cuda()
+        g = torch.zeros_like(Pd)
+        nk2 = torch.empty(1, dtype=torch.int32, device="cuda")
+        tl.tlda_whiten_cp_step(ctx, staged[i], 1e-3, Pd, g, None, nk2)
+        torch.cuda.synchronize()
+        st = O.batch_stats(rp, ci, va, spec.V)
+        assert int(nk.item()) == int(nk2.item()) == st["n_kept"], i
+        if n == 0:
+            assert torch.equal(Pd.cpu(), torch.from_numpy(Phi0))
+            continue
+        X_ref = O.whiten(rp, ci, va, spec.V, c1["m"], Wr)
+        assert rel(X.cpu().numpy()[:n], X_ref) < REL32, i
+        if st["n_kept"] == 0:
+            assert torch.equal(Pd.cpu(), torch.from_numpy(Phi0)), i
+            continue
+        got = g.cpu().numpy().astype(np.float64)
+        if bf16:
+            ref, B, C = rounded_gradient(X_ref, Phi0, st["n_kept"], spec.alpha0, 0.5)
+            assert_within(got, ref, fused_bound(ref, B, C), f"staged batch {i}")
+        else:
+            ref = O.cp_gradient(X_ref, Phi0.astype(np.float64), st["n_kept"], spec.alpha0, 0.5)
+            assert rel(got, ref) < REL32, i
 
 
 def test_compact_staged_batches_equal_device_batches(c1):

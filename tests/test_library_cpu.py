@@ -87,21 +87,25 @@ def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "tlda.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(tlda_config),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
+        " sizeof(tlda_config),"
         " offsetof(tlda_config, alpha0), offsetof(tlda_config, eig_iters),"
         " offsetof(tlda_config, eig_seed), offsetof(tlda_config, eig_warm_iters),"
         " sizeof(tlda_csr_batch),"
-        " offsetof(tlda_csr_batch, row_ptr), offsetof(tlda_csr_batch, slot));return 0;}\n")
+        " offsetof(tlda_csr_batch, row_ptr), offsetof(tlda_csr_batch, slot),"
+        " offsetof(tlda_csr_batch, first_doc), sizeof(tlda_csr_batch_u16),"
+        " offsetof(tlda_csr_batch_u16, first_doc));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
                     str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
     from paper_2511_07809_amd import tlda
-    cfg, b = tlda.tlda_config, tlda.tlda_csr_batch
+    cfg, b, h = tlda.tlda_config, tlda.tlda_csr_batch, tlda.tlda_csr_batch_u16
     assert got == [ctypes.sizeof(cfg), cfg.alpha0.offset, cfg.eig_iters.offset,
                    cfg.eig_seed.offset, cfg.eig_warm_iters.offset, ctypes.sizeof(b),
-                   b.row_ptr.offset, b.slot.offset]
+                   b.row_ptr.offset, b.slot.offset, b.first_doc.offset, ctypes.sizeof(h),
+                   h.first_doc.offset]
 
 
 def test_header_compiles_as_c_and_cxx(tmp_path):

@@ -112,6 +112,43 @@ def test_whitening_identity_and_whitened_corpus():
     np.testing.assert_allclose((a0 + 1) / N * X.T @ X, np.eye(K), atol=1e-10)
 
 
+def test_sparse_whitening_equals_the_dense_definition():
+    """whiten_csr regroups (F - 1 M1^T) W as F W - 1 (W^T M1)^T over a sparse
+    F: it must equal the dense definition row for row, dropped rows zero."""
+    c, batches = _c1_batches()
+    V = c.spec.V
+    rng = np.random.default_rng(3)
+    W = rng.standard_normal((V, 7)) * 20.0
+    m = rng.dirichlet(np.ones(V))
+    extra = make_csr_rows([{}, {4: 1, 9: 1}, {0: 5}, {2: 1, 499: 2}], V)
+    for rp, ci, va in list(batches[:2]) + [extra]:
+        X = O.whiten_csr(rp, ci, va, V, m, W)
+        ref = O.whiten(rp, ci, va, V, m, W)
+        assert np.abs(X - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    assert np.all(O.whiten_csr(*extra, V, m, W)[[0, 1]] == 0.0)
+
+
+@pytest.mark.parametrize("D", [5, 30])
+def test_operator_whitening_equals_the_dense_eigendecomposition(D):
+    """The Lanczos whitening of M2~ applied as an operator against the dense
+    M2~ and LAPACK's symmetric eigensolver: same M1, N, eigenvalues, columns
+    (same order and sign rule) and the identity W^T M2~ W = I."""
+    c, batches = _c1_batches()
+    V, a0 = c.spec.V, c.spec.alpha0
+    m, N = O.first_moment(batches, V)
+    M2 = O.centered_second_moment(batches, m, N, a0)
+    W_ref, lam_ref, U_ref = O.whitening(M2, D)
+    W, lam, U, m2, N2 = O.whitening_operator(batches, V, D, a0)
+    assert N2 == N
+    np.testing.assert_allclose(m2, m, rtol=0, atol=1e-15)
+    assert np.abs(lam - lam_ref).max() <= 1e-12 * lam_ref[0]
+    gaps = np.minimum(np.r_[np.inf, -np.diff(lam_ref)], np.r_[-np.diff(lam_ref), np.inf])
+    wide = gaps > 1e-4 * lam_ref[0]
+    assert wide.sum() >= min(D, 5)
+    assert np.abs(U[:, wide] - U_ref[:, wide]).max() < 1e-8
+    np.testing.assert_allclose(W.T @ M2 @ W, np.eye(D), atol=1e-9)
+
+
 def test_dropped_rows_are_zero_and_excluded():
     V = 6
     rp, ci, va = make_csr_rows([{0: 2, 1: 1}, {2: 1}, {}, {3: 1, 4: 1, 5: 3}, {1: 1, 5: 1}], V)
