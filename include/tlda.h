@@ -225,6 +225,25 @@ tlda_status tlda_cp_step(tlda_ctx* ctx, const float* X, int32_t n_rows, const in
 tlda_status tlda_whiten_cp_step(tlda_ctx* ctx, const tlda_csr_batch* batch, float beta, float* Phi,
                                 float* grad, float* X_out, int32_t* n_kept_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same step as
+ * tlda_whiten_cp_step, same arguments and results up to the order of the FP32
+ * partial sums, calling no allocating routine.  The reduction's per-block
+ * partials go to one 16 MiB device array per GPU (4 Mi floats), held by the
+ * library until the process ends, instead of the context's buffer that
+ * tlda_whiten_cp_step grows on demand; the grid is capped at
+ * floor(4 Mi / (D K)) blocks so that they fit (every block writes its whole
+ * partial, so nothing needs clearing between calls).  Every call on one GPU
+ * shares that array: calls that overlap on one GPU (contexts on different
+ * streams) race and must be ordered by the caller.  Covers BF16 contexts and
+ * FP32 contexts with D, K <= 64 (other FP32 shapes run two calls through a
+ * whitened-batch buffer: TLDA_ERR_SHAPE); TLDA_ERR_ARG for classic-moment
+ * contexts; TLDA_ERR_DEVICE if the array's device address could not be
+ * found (it is looked up once per device by tlda_create). */
+tlda_status tlda_whiten_cp_step_noalloc(tlda_ctx* ctx, const tlda_csr_batch* batch, float beta,
+                                        float* Phi, float* grad, float* X_out,
+                                        int32_t* n_kept_out);
+
 /* tlda_unwhiten flags */
 #define TLDA_PROJECT_SIMPLEX 0x1u  /* clip negative entries of mu and renormalise */
 

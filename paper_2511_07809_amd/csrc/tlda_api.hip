@@ -4,15 +4,13 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include <rocblas/rocblas.h>
 
 #include "tlda_internal.h"
-
-#include <algorithm>
-#include <cmath>
 
 using tlda::launch_zero;
 
@@ -61,6 +59,39 @@ void dfree(T*& p) {
 namespace tlda {
 thread_local KernelTimer g_main_timer;
 }  // namespace tlda
+
+namespace {
+
+// Per-block partials of tlda_whiten_cp_step_noalloc: one array on every
+// device the library runs on, held until the process ends.  Host code never
+// passes this name to a kernel (on the host it is a stand-in, not a device
+// address): it uses the address hipGetSymbolAddress returns for the device.
+__device__ __align__(256) float scratch[tlda::kNoAllocFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_addr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_looked_up[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current; looked up
+// once per device.
+hipError_t scratch_address(int device, float** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_looked_up[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_addr[device] = e == hipSuccess ? static_cast<float*>(p) : nullptr;
+    g_scratch_looked_up[device] = true;
+  }
+  *out = g_scratch_addr[device];
+  return g_scratch_err[device];
+}
+
+}  // namespace
 
 namespace {
 
@@ -135,15 +166,16 @@ tlda_status ensure_x(tlda_ctx* c, size_t need) {
 // The finish of a step (gradient and update from the reduction's partials).
 // From kGramOnceDK entries of Phi on, the squared Gram entries of Phi0 are
 // formed once first rather than by every finish block.
-tlda_status finish_step(tlda_ctx* c, int nblk, const int* counts, int ncounts, int n_default,
-                        float beta, float* Phi, float* grad, int* n_out) {
+tlda_status finish_step(tlda_ctx* c, const float* partial, int nblk, const int* counts,
+                        int ncounts, int n_default, float beta, float* Phi, float* grad,
+                        int* n_out) {
   const int D = c->cfg.D, K = c->cfg.K;
   const double* gsq = nullptr;
   if (D * K >= tlda::kGramOnceDK) {
     HIP_OK(c, tlda::launch_gram_sq(c->cp.phi0, D, K, c->cp.gsq, c->stream));
     gsq = c->cp.gsq;
   }
-  HIP_OK(c, tlda::launch_cp_finish(c->cp.partial, nblk, counts, ncounts, n_default, c->cp.phi0, D,
+  HIP_OK(c, tlda::launch_cp_finish(partial, nblk, counts, ncounts, n_default, c->cp.phi0, D,
                                    K, c->cfg.alpha0, c->cfg.theta, beta, Phi, grad, c->cp.R1,
                                    n_out, gsq, c->stream));
   return TLDA_OK;
@@ -368,6 +400,61 @@ tlda_status refresh(tlda_ctx* c, bool warm) {
   return TLDA_OK;
 }
 
+// The fused whitening + CP step of a BF16 context or of an FP32 context
+// within the fused kernel's shapes (the batch is already checked).  The
+// reduction's per-block partials go to `partial`, which holds part_cap
+// floats: the grid is capped so that they fit (fewer blocks, each taking more
+// row tiles).  partial == nullptr: the context's own buffer, grown to the
+// grid's need.
+tlda_status fused_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float* Phi, float* grad,
+                       float* X_out, int32_t* n_kept_out, float* partial, size_t part_cap) {
+  tlda_status st = validate_content(c, b);
+  if (st != TLDA_OK) return st;
+  if (b->n_rows == 0) {
+    if (n_kept_out) HIP_OK(c, launch_zero(n_kept_out, sizeof(int32_t), c->stream));
+    return TLDA_OK;
+  }
+  const int D = c->cfg.D, K = c->cfg.K;
+  int nblk;
+  if (is_bf16(c)) {
+    nblk = bf16_grid(c, 0, b->n_rows);
+  } else {
+    const int T = tlda::cp_mfma_tile_rows(D, K);
+    const int ntiles = (b->n_rows + T - 1) / T;
+    if (c->tune.fused_blocks <= 0) {
+      int per_cu = 0;
+      HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, Phi, K, 0, nullptr,
+                                       &per_cu, nullptr, nullptr, c->stream));
+      c->tune.fused_blocks = (per_cu > 0 ? per_cu : 1) * c->num_cu;
+    }
+    nblk = ntiles < c->tune.fused_blocks ? ntiles : c->tune.fused_blocks;
+    if (nblk > 2 * tlda::kWhitenBlockCounts) nblk = 2 * tlda::kWhitenBlockCounts;
+  }
+  if (partial != nullptr) {
+    const size_t fit = part_cap / ((size_t)D * K);
+    if ((size_t)nblk > fit) nblk = (int)fit;
+  } else {
+    st = ensure_partial(c, (size_t)nblk * D * K);
+    if (st != TLDA_OK) return st;
+    partial = c->cp.partial;
+  }
+  float* g = grad ? grad : c->cp.grad;
+  st = begin_use(c, b);
+  if (st != TLDA_OK) return st;
+  HIP_OK(c, timing_start(c));
+  if (is_bf16(c))
+    HIP_OK(c, tlda::launch_whiten_cp_bf16(*b, c->wh.W16, c->wh.mw16, c->Dh, D, Phi, K, nblk,
+                                          partial, c->block_counts, X_out, c->cp.phi0,
+                                          c->stream));
+  else
+    HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, Phi, K, nblk, partial,
+                                     c->block_counts, X_out, c->cp.phi0, c->stream));
+  HIP_OK(c, timing_stop(c));
+  st = end_use(c, b);
+  if (st != TLDA_OK) return st;
+  return finish_step(c, partial, nblk, c->block_counts, nblk, 0, beta, Phi, g, n_kept_out);
+}
+
 // The CP step of a classic-moment context (the batch is already checked):
 // Z = W Phi and r, the per-block data-term partials over the batch, then the
 // shared finish kernel.  X_out, if given, receives the whitened batch first.
@@ -414,7 +501,8 @@ tlda_status classic_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float
     HIP_OK(c, timing_stop(c));
     st = end_use(c, b);
     if (st != TLDA_OK) return st;
-    return finish_step(c, nblk, c->block_counts, nblk, 0, beta, Phi, g, n_kept_out);
+    return finish_step(c, c->cp.partial, nblk, c->block_counts, nblk, 0, beta, Phi, g,
+                     n_kept_out);
   }
   const int Kp = tlda::padded_d(K);
   if (c->cp.Z == nullptr) {
@@ -444,7 +532,8 @@ tlda_status classic_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float
   HIP_OK(c, timing_stop(c));
   st = end_use(c, b);
   if (st != TLDA_OK) return st;
-  return finish_step(c, nblk, c->block_counts, nblk, 0, beta, Phi, g, n_kept_out);
+  return finish_step(c, c->cp.partial, nblk, c->block_counts, nblk, 0, beta, Phi, g,
+                     n_kept_out);
 }
 
 void destroy_all(tlda_ctx* c) {
@@ -539,6 +628,12 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
     return fail(TLDA_ERR_DEVICE);
   if (hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking) != hipSuccess)
     return fail(TLDA_ERR_DEVICE);
+  {
+    // the allocation-free step's buffer on this device (its calls fail with
+    // this message if the lookup did; every other call works without it)
+    const hipError_t e = scratch_address(ctx->device, &ctx->noalloc);
+    if (e != hipSuccess) ctx->noalloc_error = hipGetErrorString(e);
+  }
   for (auto& s : ctx->slots) {
     if (hipEventCreateWithFlags(&s.ready, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&s.free_, hipEventDisableTiming) != hipSuccess)
@@ -681,7 +776,8 @@ tlda_status tlda_cp_step(tlda_ctx* c, const float* X, int32_t n_rows, const int3
     HIP_OK(c, tlda::launch_cp_reduce(X, n_rows, Phi, D, K, nblk, c->cp.partial, c->cp.phi0,
                                      c->stream));
   HIP_OK(c, timing_stop(c));
-  return finish_step(c, nblk, n_kept, n_kept ? 1 : 0, n_rows, beta, Phi, g, nullptr);
+  return finish_step(c, c->cp.partial, nblk, n_kept, n_kept ? 1 : 0, n_rows, beta, Phi, g,
+                     nullptr);
 }
 
 tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float* Phi,
@@ -708,50 +804,31 @@ tlda_status tlda_whiten_cp_step(tlda_ctx* c, const tlda_csr_batch* b, float beta
     if (st != TLDA_OK) return st;
     return tlda_cp_step(c, X, b->n_rows, nk, beta, Phi, grad);
   }
-  st = validate_content(c, b);
+  return fused_step(c, b, beta, Phi, grad, X_out, n_kept_out, nullptr, 0);
+}
+
+tlda_status tlda_whiten_cp_step_noalloc(tlda_ctx* c, const tlda_csr_batch* b, float beta,
+                                        float* Phi, float* grad, float* X_out,
+                                        int32_t* n_kept_out) {
+  if (!c) return TLDA_ERR_ARG;
+  tlda_status st = check_batch(c, b);
   if (st != TLDA_OK) return st;
-  if (b->n_rows == 0) {
-    if (n_kept_out) HIP_OK(c, launch_zero(n_kept_out, sizeof(int32_t), c->stream));
-    return TLDA_OK;
-  }
-  if (is_bf16(c)) {
-    const int nblk = bf16_grid(c, 0, b->n_rows);
-    st = ensure_partial(c, (size_t)nblk * D * K);
-    if (st != TLDA_OK) return st;
-    float* g = grad ? grad : c->cp.grad;
-    st = begin_use(c, b);
-    if (st != TLDA_OK) return st;
-    HIP_OK(c, timing_start(c));
-    HIP_OK(c, tlda::launch_whiten_cp_bf16(*b, c->wh.W16, c->wh.mw16, c->Dh, D, Phi, K, nblk,
-                                          c->cp.partial, c->block_counts, X_out, c->cp.phi0,
-                                          c->stream));
-    HIP_OK(c, timing_stop(c));
-    st = end_use(c, b);
-    if (st != TLDA_OK) return st;
-    return finish_step(c, nblk, c->block_counts, nblk, 0, beta, Phi, g, n_kept_out);
-  }
-  const int T = tlda::cp_mfma_tile_rows(D, K);
-  const int ntiles = (b->n_rows + T - 1) / T;
-  if (c->tune.fused_blocks <= 0) {
-    int per_cu = 0;
-    HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, Phi, K, 0, nullptr,
-                                     &per_cu, nullptr, nullptr, c->stream));
-    c->tune.fused_blocks = (per_cu > 0 ? per_cu : 1) * c->num_cu;
-  }
-  int nblk = ntiles < c->tune.fused_blocks ? ntiles : c->tune.fused_blocks;
-  if (nblk > 2 * tlda::kWhitenBlockCounts) nblk = 2 * tlda::kWhitenBlockCounts;
-  st = ensure_partial(c, (size_t)nblk * D * K);
-  if (st != TLDA_OK) return st;
-  float* g = grad ? grad : c->cp.grad;
-  st = begin_use(c, b);
-  if (st != TLDA_OK) return st;
-  HIP_OK(c, timing_start(c));
-  HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, Phi, K, nblk,
-                                   c->cp.partial, c->block_counts, X_out, c->cp.phi0, c->stream));
-  HIP_OK(c, timing_stop(c));
-  st = end_use(c, b);
-  if (st != TLDA_OK) return st;
-  return finish_step(c, nblk, c->block_counts, nblk, 0, beta, Phi, g, n_kept_out);
+  CHECK_ARG(c, c->wh.ready, TLDA_ERR_STATE, "no whitening matrix yet: refresh or set one first");
+  CHECK_ARG(c, Phi != nullptr, TLDA_ERR_ARG, "Phi is NULL");
+  CHECK_ARG(c, std::isfinite(beta), TLDA_ERR_ARG, "beta is not finite");
+  const int D = c->cfg.D, K = c->cfg.K;
+  CHECK_ARG(c, !is_classic(c), TLDA_ERR_ARG,
+            "classic-moment steps have no allocation-free variant (their Z buffers grow on "
+            "first use)");
+  CHECK_ARG(c, is_bf16(c) || tlda::fused_supported(D, K, c->Dp), TLDA_ERR_SHAPE,
+            "this FP32 shape runs as two calls through a whitened-batch buffer; the "
+            "allocation-free step covers BF16 contexts and FP32 contexts with D, K <= 64");
+  CHECK_ARG(c, (size_t)D * K <= tlda::kNoAllocFloats, TLDA_ERR_SHAPE,
+            "D * K exceeds the allocation-free step's partial buffer");
+  CHECK_ARG(c, c->noalloc != nullptr, TLDA_ERR_DEVICE,
+            "the allocation-free step's device buffer was not found on this device: " +
+                c->noalloc_error);
+  return fused_step(c, b, beta, Phi, grad, X_out, n_kept_out, c->noalloc, tlda::kNoAllocFloats);
 }
 
 tlda_status tlda_unwhiten(tlda_ctx* c, const float* Phi, double* mu, double* alpha, double* lambda,

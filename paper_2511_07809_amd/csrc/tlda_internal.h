@@ -12,6 +12,9 @@
 
 namespace tlda {
 
+// Floats of the allocation-free step's partial buffer (16 MiB per device).
+constexpr size_t kNoAllocFloats = size_t(4) << 20;
+
 // Per-block count scratch: the whitening and the moment kernels cap their
 // grids at this many blocks (the moment kernel stores two counts per block).
 constexpr int kWhitenBlockCounts = 2048;
@@ -148,6 +151,10 @@ struct tlda_ctx {
   bool in_capture = false;    // capturing a graph of steps: no validation, no timing hook
   void* blas = nullptr;       // rocblas_handle of the refresh's FP64 products (created lazily)
   mutable std::string last_error;   // also set by the const inspection calls
+  // device address of the allocation-free step's partial buffer on this
+  // context's device (null, with the runtime's message, if the lookup failed)
+  float* noalloc = nullptr;
+  std::string noalloc_error;
 };
 
 // Document-topic encoder: d_in -> hidden -> hidden -> k_out MLP (GELU,

@@ -35,6 +35,7 @@ TLDA_MLP_MAX_WIDTH = 1024
 
 EXPORTED = ("tlda_create", "tlda_destroy", "tlda_status_str", "tlda_last_error",
             "tlda_update_moments", "tlda_whiten_batch", "tlda_cp_step", "tlda_whiten_cp_step",
+            "tlda_whiten_cp_step_noalloc",
             "tlda_unwhiten",
             "tlda_infer_doc_topics", "tlda_infer_doc_topics_whitened", "tlda_stage_batch", "tlda_stage_batch_u16", "tlda_get_stats",
             "tlda_get_whitening", "tlda_set_whitening", "tlda_rebase_phi",
@@ -81,6 +82,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tlda_cp_step": ([vp, vp, i32, vp, ctypes.c_float, vp, vp], i32),
         "tlda_whiten_cp_step": ([vp, ctypes.POINTER(tlda_csr_batch), ctypes.c_float, vp, vp, vp,
                                  vp], i32),
+        "tlda_whiten_cp_step_noalloc": ([vp, ctypes.POINTER(tlda_csr_batch), ctypes.c_float, vp,
+                                         vp, vp, vp], i32),
         "tlda_unwhiten": ([vp, vp, vp, vp, vp, u32], i32),
         "tlda_infer_doc_topics": ([vp, ctypes.POINTER(tlda_csr_batch), vp, i32, ctypes.c_float,
                                    vp], i32),
@@ -294,6 +297,19 @@ def tlda_whiten_cp_step(ctx: Context, batch: CsrBatch, beta: float, Phi: torch.T
     s = batch.struct()
     _check(ctx, _LIB.tlda_whiten_cp_step(ctx.handle, ctypes.byref(s), float(beta), _ptr(Phi),
                                          _ptr(grad), _ptr(X_out), _ptr(n_kept)))
+
+
+def tlda_whiten_cp_step_noalloc(ctx: Context, batch: CsrBatch, beta: float, Phi: torch.Tensor,
+                                grad: Optional[torch.Tensor] = None,
+                                X_out: Optional[torch.Tensor] = None,
+                                n_kept: Optional[torch.Tensor] = None) -> None:
+    assert Phi.dtype == torch.float32 and Phi.is_contiguous() and Phi.numel() == ctx.D * ctx.K
+    if X_out is not None:
+        assert X_out.dtype == torch.float32 and X_out.numel() >= batch.n_rows * ctx.D
+    s = batch.struct()
+    _check(ctx, _LIB.tlda_whiten_cp_step_noalloc(ctx.handle, ctypes.byref(s), float(beta),
+                                                 _ptr(Phi), _ptr(grad), _ptr(X_out),
+                                                 _ptr(n_kept)))
 
 
 def tlda_unwhiten(ctx: Context, Phi: torch.Tensor, flags: int = 0):
