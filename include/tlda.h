@@ -219,9 +219,9 @@ tlda_status tlda_cp_step(tlda_ctx* ctx, const float* X, int32_t n_rows, const in
  * count), so X does not travel through HBM.  Phi: device float [D][K],
  * updated in place.  grad: device float [D][K] or NULL.  X_out: device float
  * [n_rows][D] or NULL (written only if given).  n_kept_out: device int32 or
- * NULL.  Requires a W (TLDA_ERR_STATE).  Shapes outside the fused kernel's
- * range (D or K above 64, where its registers would spill) run the two
- * calls in sequence. */
+ * NULL.  Requires a W (TLDA_ERR_STATE).  FP32 shapes outside the fused
+ * kernel's range (D or K above 128) run the two calls in sequence through a
+ * whitened-batch buffer of the context. */
 tlda_status tlda_whiten_cp_step(tlda_ctx* ctx, const tlda_csr_batch* batch, float beta, float* Phi,
                                 float* grad, float* X_out, int32_t* n_kept_out);
 
@@ -236,8 +236,8 @@ tlda_status tlda_whiten_cp_step(tlda_ctx* ctx, const tlda_csr_batch* batch, floa
  * partial, so nothing needs clearing between calls).  Every call on one GPU
  * shares that array: calls that overlap on one GPU (contexts on different
  * streams) race and must be ordered by the caller.  Covers BF16 contexts and
- * FP32 contexts with D, K <= 64 (other FP32 shapes run two calls through a
- * whitened-batch buffer: TLDA_ERR_SHAPE); TLDA_ERR_ARG for classic-moment
+ * FP32 contexts with D, K <= 128 (FP32 shapes with D or K above 128 run two
+ * calls through a whitened-batch buffer: TLDA_ERR_SHAPE); TLDA_ERR_ARG for classic-moment
  * contexts; TLDA_ERR_DEVICE if the array's device address could not be
  * found (it is looked up once per device by tlda_create). */
 tlda_status tlda_whiten_cp_step_noalloc(tlda_ctx* ctx, const tlda_csr_batch* batch, float beta,
@@ -431,7 +431,7 @@ tlda_status tlda_graph_capture(tlda_multi* const* plans, int32_t n_plans, tlda_g
  * (slot < 0) that stay allocated while the graph lives; with
  * TLDA_VALIDATE_CSR they are validated once, before the capture.  Supported
  * for BF16 contexts and FP32 contexts within the fused kernel's shapes (D, K
- * <= 64), not classic ones (TLDA_ERR_SHAPE / TLDA_ERR_ARG); TLDA_ERR_ARG for a
+ * <= 128), not classic ones (TLDA_ERR_SHAPE / TLDA_ERR_ARG); TLDA_ERR_ARG for a
  * context on the null stream.  Synchronous; the timing hook does not apply
  * to the captured launches. */
 tlda_status tlda_graph_capture_steps(tlda_ctx* ctx, const tlda_csr_batch* batches, int32_t n,

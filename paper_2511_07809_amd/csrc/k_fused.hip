@@ -3,10 +3,10 @@
 // the data term of eq. vec_deriv, R1 = X^T (X Phi)^2, so X never travels
 // through HBM (it is written out only when the caller asks for it).
 //
-// Per block (256 threads), for each of its row tiles of T documents:
+// Per block (NW waves), for each of its row tiles of T documents:
 //   1. whitening: a group of G lanes owns a document (one float4 of columns
-//      per lane); 16 nonzeros per step are fetched in one round trip, shared
-//      by lane shuffles, and all 16 W-row gathers are issued before use; the
+//      per lane); 8 nonzeros per step are fetched in one round trip, shared
+//      by lane shuffles, and all 8 W-row gathers are issued before use; the
 //      row x = (1/L) sum c W[col] - W^T M1 (zero for dropped documents) goes to
 //      LDS;
 //   2. S = X_t Phi on FP32 matrix cores, squared into LDS;
@@ -15,39 +15,58 @@
 // block's matrix work.  Each block writes its R1 partial and its kept-row
 // count (and its share of a copy of Phi); the finish kernel adds them in
 // block order, forms the gradient and updates Phi.
+//
+// Two families of instances: D, K <= 64 (padded 16, 32 or 64) take 4-wave
+// blocks, G = Dp / 4 <= 16 lanes per document and 64- or 32-row tiles;
+// shapes with D or K padded to 112 or 128 take 8-wave blocks, 32 lanes per
+// document (one float4 of the up to 128 columns each) and 64-row tiles, so
+// that two blocks fit on a CU (LDS and 128 registers per lane) and one
+// block's gathers overlap the other's matrix work.
 #include "tlda_internal.h"
 
 namespace tlda {
 namespace {
 
-constexpr int kThreads = 256;
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Waves per block of the fused kernel and its resident waves per SIMD.
+constexpr int fused_waves(int DQ, int KQ) { return (DQ > 64 || KQ > 64) ? 8 : 4; }
+constexpr int fused_min_waves(int DQ, int KQ) { return (DQ > 64 || KQ > 64) ? 4 : 3; }
+
 template <int DQ, int KQ, int T, int G>
-__global__ void __launch_bounds__(kThreads, 3) k_whiten_cp(
+__global__ void __launch_bounds__(64 * fused_waves(DQ, KQ), fused_min_waves(DQ, KQ)) k_whiten_cp(
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const float* __restrict__ val, int n_rows, const float* __restrict__ W32,
     const float* __restrict__ mw32, int D, int Dp, const float* __restrict__ Phi, int K,
     int nblk, float* __restrict__ partial, int* __restrict__ block_counts,
     float* __restrict__ Xout, float* __restrict__ phi_copy) {
+  constexpr int NW = fused_waves(DQ, KQ);
+  constexpr int kThreads = 64 * NW;
   constexpr int LDX = DQ + 4, LDS = KQ + 4;
   constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = DQ / 4;
   constexpr int NRT = NDT * NCT;
-  constexpr int ST = (NCT + 3) / 4;
-  constexpr int RT = (NRT + 3) / 4;
+  constexpr int ST = (NCT + NW - 1) / NW;  // S column tiles per wave (max)
+  // R1 tiles of a wave: wide instances with at least NW / 2 column tiles give
+  // wave w column tile w, every row tile (LDS offsets known at compile time;
+  // a runtime tile index t / NCT, t % NCT kept an address register per tile
+  // live through the gathers and spilled); otherwise tiles w, w + NW, ...
+  constexpr bool kColOwner = NW > 4 && 2 * NCT > NW;
+  constexpr int RT = kColOwner ? NDT : (NRT + NW - 1) / NW;
   constexpr int RPW = 64 / G;              // documents per wave per whitening pass
-  constexpr int RPB = 4 * RPW;             // documents per block per pass
-  constexpr int NB = 8;                    // nonzeros per gather step
+  constexpr int RPB = NW * RPW;            // documents per block per pass
+  constexpr int NB = NW > 4 ? 4 : 8;       // nonzeros per gather step (wide instances: 4,
+                                           // so that their 128 registers hold the rest)
   constexpr int SLOTS = G >= NB ? 1 : NB / G;
   constexpr int PASSES = (T + RPB - 1) / RPB;
   __shared__ __attribute__((aligned(16))) float Xs[T * LDX];
   __shared__ __attribute__((aligned(16))) float Ss[T * LDS];
-  __shared__ int wave_kept[4];
+  __shared__ int wave_kept[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
   const int gl = lane % G;
   const int c4 = gl * 4;
-  const bool active = c4 < Dp;             // lane holds real (or zero-padded) W columns
+  const bool active = c4 < D;              // lane's float4 holds real W columns (the rest
+                                           // of a row past D is zero padding)
   const bool in_lds = c4 < DQ;             // its columns exist in the LDS tile
 
   for (int e = blockIdx.x * kThreads + tid; e < D * K; e += nblk * kThreads) phi_copy[e] = Phi[e];
@@ -55,7 +74,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_whiten_cp(
   float bf[ST][NKS];
 #pragma unroll
   for (int q = 0; q < ST; ++q) {
-    const int ct = wave + 4 * q;
+    const int ct = wave + NW * q;
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) {
       const int d = 4 * ks + l4, k = 16 * ct + l16;
@@ -100,8 +119,10 @@ __global__ void __launch_bounds__(kThreads, 3) k_whiten_cp(
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
           const int c = __shfl(cidx[t / G < SLOTS ? t / G : 0], t % G, G);
+          // 32-bit element offset from the kernel's (uniform) base: V Dp < 2^31
+          const uint32_t off = (uint32_t)c * (uint32_t)Dp + (uint32_t)c4;
           w[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (active && jb + t < e) w[t] = *reinterpret_cast<const float4*>(W32 + (size_t)c * Dp + c4);
+          if (active && jb + t < e) w[t] = *reinterpret_cast<const float4*>(W32 + off);
         }
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
@@ -138,7 +159,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_whiten_cp(
     // ---- 2. S = X_t Phi, squared into LDS ----
 #pragma unroll
     for (int q = 0; q < ST; ++q) {
-      const int ct = wave + 4 * q;
+      const int ct = wave + NW * q;
       if (ct < NCT) {
 #pragma unroll
         for (int rt0 = 0; rt0 < T / 16; rt0 += 4) {
@@ -147,12 +168,17 @@ __global__ void __launch_bounds__(kThreads, 3) k_whiten_cp(
           for (int u = 0; u < 4; ++u) sacc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
           const float* xa = Xs + (rt0 * 16 + l16) * LDX + l4;
 #pragma unroll
-          for (int ks = 0; ks < NKS; ++ks)
+          for (int ks = 0; ks < NKS; ++ks) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
               if (rt0 + u < T / 16)
                 sacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u * 16 * LDX + 4 * ks],
                                                                bf[q][ks], sacc[u], 0, 0, 0);
+            // wide instances: keep the operand loads of a few k steps in
+            // flight, not all of them (their registers would spill)
+            if constexpr (NW > 4)
+              if (ks % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+          }
 #pragma unroll
           for (int u = 0; u < 4; ++u)
             if (rt0 + u < T / 16)
@@ -170,18 +196,26 @@ __global__ void __launch_bounds__(kThreads, 3) k_whiten_cp(
       const float* sb = Ss + (rs * 4 + l4) * LDS + l16;
 #pragma unroll
       for (int q = 0; q < RT; ++q) {
-        const int t = wave + 4 * q;
-        if (t < NRT)
-          acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[(t / NCT) * 16], sb[(t % NCT) * 16],
-                                                        acc[q], 0, 0, 0);
+        if constexpr (kColOwner) {
+          if (wave < NCT)
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[q * 16], sb[wave * 16], acc[q], 0,
+                                                          0, 0);
+        } else {
+          const int t = wave + NW * q;
+          if (t < NRT)
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[(t / NCT) * 16], sb[(t % NCT) * 16],
+                                                          acc[q], 0, 0, 0);
+        }
       }
+      if constexpr (NW > 4)
+        if (rs % 2 == 1) __builtin_amdgcn_sched_barrier(0);
     }
   }
   float* out = partial + (size_t)blockIdx.x * D * K;
 #pragma unroll
   for (int q = 0; q < RT; ++q) {
-    const int t = wave + 4 * q;
-    if (t < NRT) {
+    const int t = kColOwner ? q * NCT + wave : wave + NW * q;
+    if ((kColOwner && wave < NCT) || (!kColOwner && t < NRT)) {
       const int k = (t % NCT) * 16 + l16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -192,7 +226,257 @@ __global__ void __launch_bounds__(kThreads, 3) k_whiten_cp(
   }
   if (lane == 0) wave_kept[wave] = kept_total;
   __syncthreads();
-  if (tid == 0) block_counts[blockIdx.x] = wave_kept[0] + wave_kept[1] + wave_kept[2] + wave_kept[3];
+  if (tid == 0) {
+    int n = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) n += wave_kept[w];
+    block_counts[blockIdx.x] = n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wide shapes (D or K padded to 112 or 128): 8-wave blocks, 32-row tiles,
+// 32 lanes per document (one float4 of the up to 128 columns each), two
+// documents per wave and pass, two passes per tile.  The whitening phase is
+// latency-bound on chains of dependent memory round trips, so it is
+// pipelined across documents: a wave's row pointers are loaded two
+// documents ahead and its CSR entries (up to 32, one per lane, in one round
+// trip) one document ahead, so a document's own chain is only its W-row
+// gather steps (8 nonzeros per step; a document of up to 16 distinct words
+// takes two).  The loads for the next tile's first document are in flight
+// while the tile's matrix work runs.  Phi lives in LDS (the B operand of
+// S = X_t Phi), which leaves the registers to the gathers; each wave owns
+// one column tile of S and of R1 (every row tile), so all LDS offsets are
+// known at compile time.  Two blocks fit on a CU at 112 x 112 (LDS and 128
+// registers per lane), one block's gathers overlapping the other's matrix
+// work.
+// ---------------------------------------------------------------------------
+// LDS of a wide block (Phi, X and S tiles, counts) and its waves per SIMD:
+// two blocks per CU while they fit in the 160 KB, else one.
+constexpr int wide_lds_bytes(int DQ, int KQ) {
+  return (DQ * KQ + 32 * (DQ + 4) + 32 * (KQ + 4)) * 4 + 32;
+}
+constexpr int wide_min_waves(int DQ, int KQ) { return 2 * wide_lds_bytes(DQ, KQ) <= 163840 ? 4 : 2; }
+
+template <int DQ, int KQ>
+__global__ void __launch_bounds__(512, wide_min_waves(DQ, KQ)) k_whiten_cp_wide(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+    const float* __restrict__ val, int n_rows, const float* __restrict__ W32,
+    const float* __restrict__ mw32, int D, int Dp, const float* __restrict__ Phi, int K,
+    int nblk, float* __restrict__ partial, int* __restrict__ block_counts,
+    float* __restrict__ Xout, float* __restrict__ phi_copy) {
+  constexpr int NW = 8, kThreads = 512;
+  constexpr int T = 32, G = 32, RPW = 2, RPB = NW * RPW, PASSES = T / RPB;
+  constexpr int NB = 8;                    // nonzeros per gather step
+  constexpr int LDX = DQ + 4, LDS = KQ + 4, LDP = KQ;   // Phi unpadded: 78 KB per block at 112
+                                                         // x 112, so two blocks fit on a CU
+  constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = DQ / 4;
+  static_assert(NCT <= NW && T % RPB == 0, "wide fused shape");
+  __shared__ __attribute__((aligned(16))) float Ps[DQ * LDP];
+  __shared__ __attribute__((aligned(16))) float Xs[T * LDX];
+  __shared__ __attribute__((aligned(16))) float Ss[T * LDS];
+  __shared__ int wave_kept[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int gl = lane & (G - 1), half = lane >> 5;
+  const int c4 = gl * 4;
+  const bool active = c4 < D;              // lane's float4 holds real W columns
+  const bool in_lds = c4 < DQ;             // its columns exist in the LDS tile
+  const bool owner = wave < NCT;           // wave owns column tile `wave` of S and R1
+
+  for (int e = blockIdx.x * kThreads + tid; e < D * K; e += nblk * kThreads) phi_copy[e] = Phi[e];
+  // Phi into LDS, zero padded (first read after the first tile's barrier).
+  // Xs needs no clearing: every pass writes all DQ columns of its rows.
+  for (int e = tid; e < DQ * LDP; e += kThreads) {
+    const int d = e / LDP, k = e % LDP;
+    Ps[e] = (d < D && k < K) ? Phi[d * K + k] : 0.f;
+  }
+  floatx4 acc[NDT];
+#pragma unroll
+  for (int q = 0; q < NDT; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  int kept_total = 0;
+
+  // The documents this lane group whitens, in order: pass g of the block is
+  // pass g % PASSES of tile blockIdx.x + (g / PASSES) nblk.
+  const int ntiles = (n_rows + T - 1) / T;
+  const int my_tiles = blockIdx.x < ntiles ? (ntiles - 1 - blockIdx.x) / nblk + 1 : 0;
+  const int n_pass = my_tiles * PASSES;
+  auto doc_row = [&](int g) -> int {     // -1: no document
+    if (g >= n_pass) return -1;
+    const int tile = blockIdx.x + (g / PASSES) * nblk;
+    const int row = tile * T + (g % PASSES) * RPB + wave * RPW + half;
+    return row < n_rows ? row : -1;
+  };
+  // row pointers of documents g + 1 and g + 2, CSR entries of document g + 1
+  auto load_rp = [&](int g, int& b, int& e) {
+    const int r = doc_row(g);
+    const int rc = r < 0 ? 0 : r;
+    const int b_ = row_ptr[rc], e_ = row_ptr[rc + 1];
+    b = r < 0 ? 0 : b_;
+    e = r < 0 ? 0 : e_;
+  };
+  // Unconditional loads from clamped indexes (the launcher passes valid
+  // arrays even for a batch without nonzeros): a load under a lane condition
+  // sits in a branch whose join waits for every load in flight.
+  auto load_csr = [&](int b, int e, int& c, float& v) {
+    const int j = b + gl;
+    const bool in = j < e;
+    const int jc = in ? j : 0;
+    const int c_ = col_idx[jc];
+    const float v_ = val[jc];
+    c = in ? c_ : 0;
+    v = in ? v_ : 0.f;
+  };
+  int b0 = 0, e0 = 0, b1 = 0, e1 = 0;
+  load_rp(0, b0, e0);
+  load_rp(1, b1, e1);
+  int cc = 0;
+  float cv = 0.f;
+  if (n_pass > 0) load_csr(b0, e0, cc, cv);
+
+#pragma unroll 1
+  for (int g = 0; g < n_pass; ++g) {
+    const int pass = g % PASSES;
+    const int lr = pass * RPB + wave * RPW + half;   // row within the tile
+    const int row = doc_row(g);
+    const int b = b0, e = e0;
+    int c_cur = cc;
+    float v_cur = cv;
+    // start the next documents' loads: CSR of g + 1, row pointers of g + 2
+    load_csr(b1, e1, cc, cv);
+    b0 = b1;
+    e0 = e1;
+    load_rp(g + 2, b1, e1);
+    // ---- 1. whitening of this pass's documents into LDS ----
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    float Lp = 0.f;
+    for (int base = b; base < e; base += G) {
+      if (base != b) load_csr(base, e, c_cur, v_cur);   // documents with more than G words
+      Lp += v_cur;
+      const int n_here = min(G, e - base);
+      for (int t0 = 0; t0 < n_here; t0 += NB) {
+        // Branch-free gathers, all NB in flight together: steps past the
+        // document's end read a valid row (their count is zeroed below) and
+        // lanes past D read column 0 of it (their sums are never used).
+        float4 w[NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+          const int c = __shfl(c_cur, (t0 + t) & (G - 1), G);
+          // 32-bit element offset from the kernel's (uniform) base: V Dp < 2^31
+          const uint32_t off = (uint32_t)c * (uint32_t)Dp + (uint32_t)(active ? c4 : 0);
+          w[t] = *reinterpret_cast<const float4*>(W32 + off);
+        }
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+          const float vs = __shfl(v_cur, (t0 + t) & (G - 1), G);
+          const float v = t0 + t < n_here ? vs : 0.f;
+          a.x = fmaf(v, w[t].x, a.x);
+          a.y = fmaf(v, w[t].y, a.y);
+          a.z = fmaf(v, w[t].z, a.z);
+          a.w = fmaf(v, w[t].w, a.w);
+        }
+      }
+    }
+    float L = Lp;
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) L += __shfl_xor(L, off, G);
+    const int kept = (row >= 0 && L >= 3.f) ? 1 : 0;
+    float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (kept && active) {
+      const float4 mw = *reinterpret_cast<const float4*>(mw32 + c4);
+      const float invL = 1.0f / L;
+      x.x = fmaf(a.x, invL, -mw.x);
+      x.y = fmaf(a.y, invL, -mw.y);
+      x.z = fmaf(a.z, invL, -mw.z);
+      x.w = fmaf(a.w, invL, -mw.w);
+    }
+    if (in_lds) *reinterpret_cast<float4*>(Xs + lr * LDX + c4) = x;
+    if (Xout != nullptr && row >= 0 && active) {
+      float* out = Xout + (size_t)row * D;
+      if (c4 + 0 < D) out[c4 + 0] = x.x;
+      if (c4 + 1 < D) out[c4 + 1] = x.y;
+      if (c4 + 2 < D) out[c4 + 2] = x.z;
+      if (c4 + 3 < D) out[c4 + 3] = x.w;
+    }
+    kept_total += __popcll(__ballot(kept && gl == 0));
+    if (pass != PASSES - 1) continue;
+    __syncthreads();
+    // ---- 2. S = X_t Phi (column tile `wave`), squared into LDS ----
+    if (owner) {
+      floatx4 sacc[T / 16];
+#pragma unroll
+      for (int u = 0; u < T / 16; ++u) sacc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const float* xa = Xs + l16 * LDX + l4;
+      const float* pb = Ps + l4 * LDP + wave * 16 + l16;
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        const float bv = pb[4 * ks * LDP];
+#pragma unroll
+        for (int u = 0; u < T / 16; ++u)
+          sacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u * 16 * LDX + 4 * ks], bv, sacc[u],
+                                                         0, 0, 0);
+        if (ks % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int u = 0; u < T / 16; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          Ss[(u * 16 + 4 * l4 + r) * LDS + wave * 16 + l16] = sacc[u][r] * sacc[u][r];
+    }
+    __syncthreads();
+    // ---- 3. R1 += X_t^T S^2 (column tile `wave`, every row tile) ----
+    if (owner) {
+#pragma unroll
+      for (int rs = 0; rs < T / 4; ++rs) {
+        const float* xa = Xs + (rs * 4 + l4) * LDX + l16;
+        const float sv = Ss[(rs * 4 + l4) * LDS + wave * 16 + l16];
+#pragma unroll
+        for (int q = 0; q < NDT; ++q)
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[q * 16], sv, acc[q], 0, 0, 0);
+        if (rs % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    __syncthreads();
+  }
+  float* out = partial + (size_t)blockIdx.x * D * K;
+  if (owner) {
+    const int k = wave * 16 + l16;
+#pragma unroll
+    for (int q = 0; q < NDT; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int d = q * 16 + 4 * l4 + r;
+        if (d < D && k < K) out[d * K + k] = acc[q][r];
+      }
+  }
+  if (lane == 0) wave_kept[wave] = kept_total;
+  __syncthreads();
+  if (tid == 0) {
+    int n = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) n += wave_kept[w];
+    block_counts[blockIdx.x] = n;
+  }
+}
+
+template <int DQ, int KQ>
+hipError_t launch_wide(const tlda_csr_batch& b, const float* W32, const float* mw32, int D, int Dp,
+                       const float* Phi, int K, int nblk, float* partial, int* block_counts,
+                       float* Xout, float* phi_copy, hipStream_t s) {
+  if (partial == nullptr) {   // occupancy query: resident blocks per CU in nblk's place
+    int per_cu = 0;
+    hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_whiten_cp_wide<DQ, KQ>, 512, 0);
+    *block_counts = per_cu;
+    return e;
+  }
+  // without nonzeros the CSR arrays may be absent: the kernel's clamped loads
+  // then read the row pointers instead (the values are discarded)
+  const int32_t* ci = b.nnz > 0 ? b.col_idx : b.row_ptr;
+  const float* va = b.nnz > 0 ? b.val : reinterpret_cast<const float*>(b.row_ptr);
+  launch_main(k_whiten_cp_wide<DQ, KQ>, dim3(nblk), dim3(512), 0, s, b.row_ptr, ci, va, b.n_rows,
+              W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout, phi_copy);
+  return hipGetLastError();
 }
 
 template <int DQ, int KQ, int T, int G>
@@ -201,12 +485,13 @@ hipError_t launch_fused_t(const tlda_csr_batch& b, const float* W32, const float
                           int* block_counts, float* Xout, float* phi_copy, hipStream_t s) {
   if (partial == nullptr) {   // occupancy query: resident blocks per CU in nblk's place
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_whiten_cp<DQ, KQ, T, G>,
-                                                                 kThreads, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, k_whiten_cp<DQ, KQ, T, G>, 64 * fused_waves(DQ, KQ), 0);
     *block_counts = per_cu;
     return e;
   }
-  launch_main(k_whiten_cp<DQ, KQ, T, G>, dim3(nblk), dim3(kThreads), 0, s, b.row_ptr, b.col_idx,
+  launch_main(k_whiten_cp<DQ, KQ, T, G>, dim3(nblk), dim3(64 * fused_waves(DQ, KQ)), 0, s,
+              b.row_ptr, b.col_idx,
               b.val, b.n_rows, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout,
               phi_copy);
   return hipGetLastError();
@@ -227,16 +512,15 @@ hipError_t launch_fused_g(int G, const tlda_csr_batch& b, const float* W32, cons
 
 }  // namespace
 
-// Shapes the fused kernel covers: D, K <= 64 (padded to 16, 32 or 64).  Above
-// that its registers spill (measured at D = K = 100: 708 us per batch against
-// 540 us for the two separate kernels), so larger shapes run the two calls.
+// Shapes the fused kernel covers: D, K <= 128 (each padded to 16, 32, 64,
+// 112 or 128); the X and S tiles of the wide (8-wave) instances take up to
+// 2 x 64 x 132 floats (67.6 KB) of LDS.
 bool fused_supported(int D, int K, int Dp) {
-  return mfma_bucket(D) > 0 && mfma_bucket(D) <= 64 && mfma_bucket(K) > 0 &&
-         mfma_bucket(K) <= 64 && Dp <= 64;
+  return mfma_bucket(D) > 0 && mfma_bucket(K) > 0 && Dp <= 128;
 }
 
 int fused_tile_rows(int D, int K) {
-  return cp_mfma_tile_rows(D, K);
+  return (mfma_bucket(D) > 64 || mfma_bucket(K) > 64) ? 32 : cp_mfma_tile_rows(D, K);   // wide: T
 }
 
 hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
@@ -257,6 +541,17 @@ hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const flo
   TLDA_FUSED_ROW(16) TLDA_FUSED_ROW(32) TLDA_FUSED_ROW(64)
 #undef TLDA_FUSED_ROW
 #undef TLDA_FUSED
+  // wide shapes: 32 lanes per document (one float4 of up to 128 columns each)
+#define TLDA_WIDE(DQ_, KQ_)                                                                    \
+  if (dq == DQ_ && kq == KQ_)                                                                  \
+    return launch_wide<DQ_, KQ_>(b, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts,     \
+                                 Xout, phi_copy, s);
+#define TLDA_WIDE_ROW(DQ_) \
+  TLDA_WIDE(DQ_, 16) TLDA_WIDE(DQ_, 32) TLDA_WIDE(DQ_, 64) TLDA_WIDE(DQ_, 112) TLDA_WIDE(DQ_, 128)
+  TLDA_WIDE(16, 112) TLDA_WIDE(16, 128) TLDA_WIDE(32, 112) TLDA_WIDE(32, 128)
+  TLDA_WIDE(64, 112) TLDA_WIDE(64, 128) TLDA_WIDE_ROW(112) TLDA_WIDE_ROW(128)
+#undef TLDA_WIDE_ROW
+#undef TLDA_WIDE
   return hipErrorInvalidValue;
 }
 

@@ -419,7 +419,7 @@ tlda_status fused_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float* 
   if (is_bf16(c)) {
     nblk = bf16_grid(c, 0, b->n_rows);
   } else {
-    const int T = tlda::cp_mfma_tile_rows(D, K);
+    const int T = tlda::fused_tile_rows(D, K);
     const int ntiles = (b->n_rows + T - 1) / T;
     if (c->tune.fused_blocks <= 0) {
       int per_cu = 0;
@@ -822,7 +822,7 @@ tlda_status tlda_whiten_cp_step_noalloc(tlda_ctx* c, const tlda_csr_batch* b, fl
             "first use)");
   CHECK_ARG(c, is_bf16(c) || tlda::fused_supported(D, K, c->Dp), TLDA_ERR_SHAPE,
             "this FP32 shape runs as two calls through a whitened-batch buffer; the "
-            "allocation-free step covers BF16 contexts and FP32 contexts with D, K <= 64");
+            "allocation-free step covers BF16 contexts and FP32 contexts with D, K <= 128");
   CHECK_ARG(c, (size_t)D * K <= tlda::kNoAllocFloats, TLDA_ERR_SHAPE,
             "D * K exceeds the allocation-free step's partial buffer");
   CHECK_ARG(c, c->noalloc != nullptr, TLDA_ERR_DEVICE,

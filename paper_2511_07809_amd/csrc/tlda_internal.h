@@ -326,6 +326,7 @@ int mfma_bucket(int n);
 int cp_mfma_tile_rows(int D, int K);
 // fused whitening + CP reduction
 bool fused_supported(int D, int K, int Dp);
+int fused_tile_rows(int D, int K);        // row tile of the fused kernel for this shape
 // With partial == nullptr, launch_whiten_cp only stores in *block_counts how
 // many blocks of the kernel it would launch can be resident on one CU.
 hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,

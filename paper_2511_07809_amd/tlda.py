@@ -165,7 +165,7 @@ class Context:
 
     def __del__(self):
         h, self.handle = getattr(self, "handle", None), None
-        if h:
+        if h and _LIB is not None:          # (None while the interpreter shuts down)
             _LIB.tlda_destroy(h)
 
 

@@ -274,7 +274,8 @@ def test_release_frees_the_accumulator_and_keeps_the_whitening(side_stream):
 
 
 @pytest.mark.parametrize("bf16,D,K", [(True, 50, 50), (True, 20, 10), (False, 50, 50),
-                                      (False, 7, 5), (True, 100, 100), (False, 64, 64)])
+                                      (False, 7, 5), (True, 100, 100), (False, 64, 64),
+                                      (False, 100, 100), (False, 120, 40)])
 def test_captured_steps_of_one_context_match_eager(side_stream, bf16, D, K):
     """Replays of the captured steps equal the eager steps bit for bit (the
     two largest shapes also capture the once-per-step Gram kernel)."""
@@ -311,9 +312,9 @@ def test_captured_steps_reject_unsupported_contexts(side_stream):
     rp, ci, va = _rows(100, 5)
     b = tl.CsrBatch.from_numpy(rp, ci, va)
     rng = np.random.default_rng(1)
-    P = torch.zeros((100, 100), dtype=torch.float32, device="cuda")
-    big = tl.tlda_create(V, 100, 100, 1.0, stream=side_stream)    # FP32, beyond fused shapes
-    Q, _ = np.linalg.qr(rng.standard_normal((V, 100)))
+    P = torch.zeros((150, 40), dtype=torch.float32, device="cuda")
+    big = tl.tlda_create(V, 40, 150, 1.0, stream=side_stream)      # FP32, beyond fused shapes
+    Q, _ = np.linalg.qr(rng.standard_normal((V, 150)))
     tl.tlda_set_whitening(big, Q * 10, rng.dirichlet(np.ones(V)))
     with pytest.raises(tl.TldaError) as e:
         tl.tlda_graph_capture_steps(big, [b], 1e-3, P)

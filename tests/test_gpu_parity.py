@@ -356,6 +356,29 @@ def test_fused_step_matches_oracle(D, K):
     assert rel(Pd.cpu().numpy(), Phi0 - beta * g_ref) < REL32
 
 
+@pytest.mark.parametrize("D,K,bf16", [(100, 100, False), (50, 50, False), (100, 100, True)])
+def test_fused_step_on_rows_without_words(D, K, bf16):
+    """A batch whose rows are all empty (no nonzeros, no column or count
+    arrays): every row is dropped, the kept count is 0 and Phi is unchanged."""
+    V = 300
+    rng = np.random.default_rng(D)
+    Q, _ = np.linalg.qr(rng.standard_normal((V, D)))
+    ctx = make_ctx(V, K, D, bf16=bf16)
+    tl.tlda_set_whitening(ctx, Q * 10.0, rng.dirichlet(np.ones(V)))
+    b = tl.CsrBatch(torch.zeros(6, dtype=torch.int32, device="cuda"),
+                    torch.zeros(0, dtype=torch.int32, device="cuda"),
+                    torch.zeros(0, dtype=torch.float32, device="cuda"))
+    P0 = torch.from_numpy(init_phi(D, K, 3).astype(np.float32)).cuda()
+    P = P0.clone()
+    nk = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    Xo = torch.full((5, D), float("nan"), device="cuda")
+    tl.tlda_whiten_cp_step(ctx, b, 1e-3, P, None, Xo, nk)
+    torch.cuda.synchronize()
+    assert int(nk.item()) == 0
+    assert torch.equal(P, P0)
+    assert torch.all(Xo == 0)
+
+
 def test_fused_step_at_the_largest_vocabulary():
     """V = 131 072, the largest vocabulary a context takes, with column
     indices over the whole range (0 and V - 1 included): the fused step

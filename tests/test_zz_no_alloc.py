@@ -42,7 +42,8 @@ def _whitening(V, D, seed):
 
 
 @pytest.mark.parametrize("D,K,bf16,tuned_blocks", [(50, 50, True, 0), (100, 100, True, 2048),
-                                                   (50, 50, False, 0), (20, 30, False, 0)])
+                                                   (50, 50, False, 0), (20, 30, False, 0),
+                                                   (100, 100, False, 0)])
 def test_noalloc_step_matches_the_allocating_step(tweet, D, K, bf16, tuned_blocks, monkeypatch):
     """tuned_blocks = 2048 makes the allocating step use 2048 blocks, where
     the allocation-free grid is capped at floor(4 Mi / (D K)) = 419."""
@@ -74,10 +75,10 @@ def test_noalloc_step_matches_the_allocating_step(tweet, D, K, bf16, tuned_block
 def test_noalloc_step_refuses_what_it_does_not_cover(tweet):
     spec, big, _ = tweet
     b = tl.CsrBatch.from_numpy(*big)
-    W, m = _whitening(spec.V, 100, 1)
-    ctx = tl.tlda_create(spec.V, 100, 100, spec.alpha0)            # FP32 above the fused shapes
+    W, m = _whitening(spec.V, 150, 1)
+    ctx = tl.tlda_create(spec.V, 40, 150, spec.alpha0)             # FP32 above the fused shapes
     tl.tlda_set_whitening(ctx, W, m)
-    P = torch.from_numpy(init_phi(100, 100, 1).astype(np.float32)).cuda()
+    P = torch.from_numpy(init_phi(150, 40, 1).astype(np.float32)).cuda()
     with pytest.raises(tl.TldaError) as e:
         tl.tlda_whiten_cp_step_noalloc(ctx, b, 1e-4, P)
     assert e.value.status == 2
