@@ -4,18 +4,22 @@
 A step is one batch through the hot path of the batched method: the whitened
 batch X = (F_B - 1 M1^T) W and one CP gradient step on Phi, either fused in
 one call (tlda_whiten_cp_step, the default) or as tlda_whiten_batch followed
-by tlda_cp_step (--path split), in BF16 (default) or FP32 per-document
-arithmetic; the other precision is timed beside it on the same whitening.
-The moment pass and the whitening refresh that precede the CP passes are run
-and timed in the same process and reported beside the steps.  Inputs are
-resident in HBM before timing starts (--streamed: staged from pinned host
-memory inside the timed region).  The K timed steps run twice: eagerly, one
-library call per step, with events attached to each main kernel's dispatch
-(the kernel times of the roofline), and as one captured HIP graph of the same
-K steps (tlda_graph_capture_steps), replayed 5 times; the median replay gives
-`value` for the fused path over resident batches (eager otherwise).  An untimed fit of both
-precisions from the same start reports their topic-recovery errors after the
-same passes.
+by tlda_cp_step (--path split).  The default workload is the streaming-scale
+batch shape (V = 50 000, K = D = 100, alpha0 = 2, batches of 262 144
+documents of length 1 + Poisson(15)): 16 distinct batches (4 194 304
+documents) resident in HBM, stepped in FP32 (the paper's arithmetic; `value`)
+and, beside it on the same whitening, in BF16 (`breakdown`).  The moment pass
+and the whitening refresh that precede the CP passes are run and timed in the
+same process and reported beside the steps.  The K timed steps run twice:
+eagerly, one library call per step, with events attached to each main
+kernel's dispatch (the kernel times of the roofline), and as one captured HIP
+graph of the same K steps (tlda_graph_capture_steps), replayed 5 times; the
+median replay gives `value` for the fused path over resident batches (eager
+otherwise; --streamed stages every batch from pinned host memory inside the
+timed region).  An untimed fit of both precisions from the same start
+reports their topic-recovery errors after the same passes.  The
+tweet-shaped workload (V = 20 000, K = D = 50, 1 000 000 documents) is then
+measured the same way and summarised in `breakdown.c2` (--no-c2 skips it).
 
 Prints one JSON line (see the keys below).  --gpus > 1 is not supported: this
 build runs on one GPU.
@@ -48,13 +52,16 @@ def parse():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--slice-scale", type=float, default=1.0,
                     help="c4: scale factor on every slice's size")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"],
                     help="c5: the document-topic encoder on the tweet-shaped corpus (trained on "
                          "--train-docs solve outputs, timed on --infer-docs fresh documents)")
     ap.add_argument("--train-docs", type=int, default=2_000_000)
     ap.add_argument("--infer-docs", type=int, default=10_000_000)
     ap.add_argument("--epochs", type=int, default=12)
-    ap.add_argument("--docs", type=int, default=0, help="limit the corpus size (0 = full)")
+    ap.add_argument("--docs", type=int, default=0,
+                    help="corpus size (0: 16 batches for c3, the full corpus otherwise)")
+    ap.add_argument("--no-c2", action="store_true",
+                    help="skip the tweet-shaped summary measured after the main workload")
     ap.add_argument("--beta", type=float, default=None)
     ap.add_argument("--streamed", action="store_true",
                     help="stream every step's batch from pinned host memory (tlda_stage_batch, "
@@ -65,7 +72,7 @@ def parse():
                          "step when V <= 65536, f32 for the FP32 step")
     ap.add_argument("--path", default="fused", choices=["fused", "split"],
                     help="fused: tlda_whiten_cp_step; split: tlda_whiten_batch + tlda_cp_step")
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"],
+    ap.add_argument("--precision", default="fp32", choices=["bf16", "fp32"],
                     help="precision of the timed path (the other one is timed beside it)")
     ap.add_argument("--fit-passes", type=int, default=20,
                     help="passes of the untimed fit that compares the topic-recovery error of "
@@ -82,51 +89,77 @@ def parse():
     ap.add_argument("--warm-iters", type=int, default=4,
                     help="subspace iterations of each warm refresh in --online")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU budget of the classic-rung and encoder baselines")
+    ap.add_argument("--cpu-reps", type=int, default=3,
+                    help="timed oracle runs per thread setting (median reported)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy a device buffer of this many MiB (a plain copy "
                          "kernel of known size that scales the HBM byte counters)")
     return ap.parse_args()
 
 
-def cpu_baseline(corpus, spec, batches, seconds: float) -> dict:
-    """The FP64 oracle (as it stands) on a bounded sample of the same batches:
-    whiten 1024-document slices and take a gradient on each."""
+def _cpu_model() -> str:
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except Exception:                     # lscpu missing: leave the model unnamed
+        return "unknown"
+    for line in out.splitlines():
+        if line.startswith("Model name:"):
+            return line.split(":", 1)[1].strip()
+    return "unknown"
+
+
+def _host_cores() -> int:
+    """Cores this process may use: the box's share when OMP_NUM_THREADS fixes
+    it, else the affinity mask."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(spec, batch, W, m, reps: int) -> dict:
+    """The FP64 oracle's sparse path as it stands, on one full batch of the
+    same workload: `whiten_csr` (SciPy CSR times W, the 1/L scale and the
+    rank-one mean correction) and `cp_gradient` (NumPy BLAS contractions),
+    then the update.  `reps` timed runs single-threaded and `reps` with every
+    host core of this process; the median of each."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import tlda_oracle as O
     from synth import init_phi
 
-    rng = np.random.default_rng(0)
-    D, K = spec.K, spec.K
-    Q, _ = np.linalg.qr(rng.standard_normal((spec.V, D)))
-    W = Q * 30.0
-    m = np.bincount(corpus.indices[: corpus.indptr[min(corpus.n_docs, 65536)]],
-                    minlength=spec.V).astype(np.float64)
-    m /= m.sum()
+    rp, ci, va = batch
+    D, K = W.shape[1], spec.K
     Phi = init_phi(D, K, 1)
-    rp, ci, va, _ = batches[0]
-    step = 1024
-    docs = 0
-    t0 = time.perf_counter()
-    s = 0
-    while True:
-        e = min(s + step, rp.shape[0] - 1)
-        a, b = int(rp[s]), int(rp[e])
-        sub_rp = (rp[s:e + 1] - a).astype(np.int64)
-        X = O.whiten(sub_rp, ci[a:b], va[a:b], spec.V, m, W)
-        n = O.batch_stats(sub_rp, ci[a:b], va[a:b], spec.V)["n_kept"]
-        Phi = O.cp_step(X, Phi, max(n, 1), spec.alpha0, 0.0, 1e-6)
-        docs += e - s
-        s = e if e < rp.shape[0] - 1 else 0
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    return {"value": docs / dt, "unit": "docs/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{docs} documents of batch 0 ({spec.name}) in 1024-document slices, "
-                      f"{dt:.1f} s: dense FP64 whitening plus the eq. vec_deriv gradient"}
+
+    def once() -> float:
+        t0 = time.perf_counter()
+        X = O.whiten_csr(rp, ci, va, spec.V, m, W)
+        n = int((O.doc_lengths(rp, va) >= 3).sum())
+        G = O.cp_gradient(X, Phi, max(n, 1), spec.alpha0, 0.0)
+        _ = Phi - 1e-6 * G
+        return time.perf_counter() - t0
+
+    docs = rp.size - 1
+    res = {}
+    for label, threads in (("single", 1), ("all", _host_cores())):
+        with threadpool_limits(limits=threads):
+            used = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+            secs = [once() for _ in range(reps)]
+        res[label] = {"docs_per_s": docs / float(np.median(secs)), "threads": int(used),
+                      "runs_s": secs}
+    return {"value": res["all"]["docs_per_s"], "unit": "docs/s", "cores": res["all"]["threads"],
+            "kind": "oracle",
+            "sample": f"one {docs}-document batch ({spec.name}), median of {reps} runs per "
+                      "thread setting: the oracle's sparse FP64 whitening (CSR times W, "
+                      "rank-one mean correction) plus the eq. vec_deriv gradient and update",
+            "single_thread_docs_per_s": res["single"]["docs_per_s"],
+            "runs_s": {"single": res["single"]["runs_s"], "all": res["all"]["runs_s"]},
+            "cpu_model": _cpu_model()}
 
 
 def classic_cpu_baseline(corpus, spec, batches, seconds: float) -> dict:
@@ -720,45 +753,25 @@ def run_slices(args) -> None:
     print(json.dumps(out), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of this path is described in DESIGN.md but not built", file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "c5":
-        run_encoder(args)
-        return
-    if args.workload == "c4":
-        run_slices(args)
-        return
-    if args.estimator == "classic":
-        run_classic(args)
-        return
-    if args.online:
-        run_online(args)
-        return
+def measure(tl, spec, args, precision: str, n_docs: int, stream) -> dict:
+    """One workload: corpus, moment pass and refresh, the timed steps of both
+    precisions (eager and graph), the roofline of the main precision's
+    kernel and the topic error of both precisions after the same passes."""
     import numpy as np
     import torch
 
-    from paper_2511_07809_amd import tlda as tl
-    from synth import SPECS, generate, init_phi, iter_batches
+    from synth import generate, init_phi, iter_batches
 
-    spec = SPECS[args.workload]
     D = K = spec.K
     t = time.time()
-    corpus = generate(spec, n_docs=args.docs or None)
+    corpus = generate(spec, n_docs=n_docs or None)
     batches = list(iter_batches(corpus))
     log(f"[bench] generated {spec.name}: {corpus.n_docs} docs, {corpus.nnz} nnz, "
         f"{len(batches)} batches in {time.time() - t:.1f}s")
-
-    torch.cuda.set_device(0)
-    # a stream of its own (default priority): the null stream cannot be captured
-    stream = torch.cuda.Stream()
-    torch.cuda.set_stream(stream)
-    bf16 = args.precision == "bf16"
+    bf16 = precision == "bf16"
     ctx = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, bf16=bf16, eig_iters=60, stream=stream)
-    dev = [tl.CsrBatch.from_numpy(rp, ci, va) for rp, ci, va, _ in batches]
+    dev = [tl.CsrBatch.from_numpy(rp, ci, va, first_doc=int(i * spec.batch))
+           for i, (rp, ci, va, _) in enumerate(batches)]
     torch.cuda.synchronize()
 
     # ---- moment pass (a1) and refresh, timed on the context's stream ----
@@ -772,12 +785,13 @@ def main():
     tl.tlda_update_moments(ctx, None, tl.TLDA_REFRESH_W)
     refresh_ms = (time.perf_counter() - t_ref) * 1e3
     moments_ms = ev[0].elapsed_time(ev[1])
-    log(f"[bench] moment pass {moments_ms:.2f} ms, refresh {refresh_ms:.1f} ms")
+    log(f"[bench] {spec.name} moment pass {moments_ms:.2f} ms, refresh {refresh_ms:.1f} ms")
+    # free the V x V accumulator (20 GB at V = 50 000) now that W exists
+    tl.tlda_update_moments(ctx, None, tl.TLDA_RELEASE)
     # the other precision on the same whitening, for the side-by-side figures
     W, _, m = tl.tlda_get_whitening(ctx)
     other = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, bf16=not bf16, stream=stream)
     tl.tlda_set_whitening(other, W, m)
-    del W
 
     # ---- CP steps (a2 + a3) ----
     beta = args.beta if args.beta is not None else (0.03 if spec.name == "c1" else 1e-3)
@@ -785,11 +799,11 @@ def main():
     nk = torch.empty(1, dtype=torch.int32, device="cuda")
     fused = args.path == "fused"
 
-    def stage_format_for(precision):
+    def stage_format_for(prec):
         if args.stage_format != "auto":
             return args.stage_format
-        return "u16" if precision == "bf16" and spec.V <= 65536 else "f32"
-    stage_format = stage_format_for(args.precision)
+        return "u16" if prec == "bf16" and spec.V <= 65536 else "f32"
+    stage_format = stage_format_for(precision)
     if args.streamed:
         hosts = {}
         if "u16" in (stage_format_for("bf16"), stage_format_for("fp32")):
@@ -816,22 +830,23 @@ def main():
         def make_batch_for(cx):
             return lambda i: dev[i % len(dev)]
 
+    other_name = "fp32" if bf16 else "bf16"
     runs = {}
-    for name, cx in ((args.precision, ctx), ("fp32" if bf16 else "bf16", other)):
+    for name, cx in ((precision, ctx), (other_name, other)):
         Phi = torch.from_numpy(init_phi(D, K, 1).astype(np.float32)).cuda()
         r = run_steps(tl, cx, make_batch_for(cx), fused, beta, Phi, Xbuf, nk, args.steps,
                       args.warmup, stream)
         r["docs_per_s"] = r["docs"] / (r["total_ms"] / 1e3)
         runs[name] = r
         km = r["kern_ms"].mean(axis=0) * 1e3
-        log(f"[bench] {name} {args.path}: {args.steps} steps {r['total_ms']:.3f} ms "
+        log(f"[bench] {spec.name} {name} {args.path}: {args.steps} steps {r['total_ms']:.3f} ms "
             f"(wall {r['wall_ms']:.1f} ms), step {r['step_ms'].mean() * 1e3:.1f} us, main "
             f"kernel(s) {' + '.join(f'{x:.1f}' for x in km)} us, {r['docs_per_s']:.4g} docs/s")
     # the same K steps as one captured HIP graph (no host launch gaps); the
     # kernels and their launch shapes are those of the eager steps above
     graph_runs = {}
     if fused and not args.streamed:
-        for name, cx in ((args.precision, ctx), ("fp32" if bf16 else "bf16", other)):
+        for name, cx in ((precision, ctx), (other_name, other)):
             steps_b = [dev[(args.warmup + i) % len(dev)] for i in range(args.steps)]
             Phi = torch.from_numpy(init_phi(D, K, 1).astype(np.float32)).cuda()
             torch.cuda.synchronize()
@@ -855,13 +870,12 @@ def main():
             ms = float(np.median(reps))
             graph_runs[name] = {"total_ms": ms, "replay_ms": reps,
                                 "docs_per_s": sum(b.n_rows for b in steps_b) / (ms / 1e3)}
-            log(f"[bench] {name} graph of {args.steps} steps: median {ms:.3f} ms of "
+            log(f"[bench] {spec.name} {name} graph of {args.steps} steps: median {ms:.3f} ms of "
                 f"{GRAPH_REPLAYS} replays ({', '.join(f'{x:.3f}' for x in reps)}), "
                 f"{graph_runs[name]['docs_per_s']:.4g} docs/s")
             del g
-    main_run = runs[args.precision]
+    main_run = runs[precision]
     K_steps = args.steps
-    main_graph = graph_runs.get(args.precision)
 
     # ---- roofline of the dominant kernel, on its own launch duration ----
     docs, nnz_tot = main_run["docs"], main_run["nnz"]
@@ -872,10 +886,13 @@ def main():
     cp_flops = rows_per * (4.0 * D * K + K)
     mm_peak = BF16_MFMA_PEAK_TFLOPS if bf16 else FP32_VALU_PEAK_TFLOPS
     kern_us = main_run["kern_ms"].mean(axis=0) * 1e3
+    wide = D > 64 or K > 64
     if fused:
         t_k = kern_us[0] / 1e6
-        name = "k_cp_bf16 (fused mode)" if bf16 else "k_whiten_cp"
-        key = "k_cp_bf16/fused" if bf16 else "k_whiten_cp"
+        if bf16:
+            name, key = "k_cp_bf16 (fused mode)", "k_cp_bf16/fused"
+        else:
+            name = key = "k_whiten_cp_wide" if wide else "k_whiten_cp"
         hbm_frac = (csr_bytes + w_bytes) / t_k / 1e9 / HBM_PEAK_GBS
         mm_frac = cp_flops / t_k / 1e12 / mm_peak
         if hbm_frac >= mm_frac:
@@ -886,8 +903,8 @@ def main():
             ach = cp_flops / t_k / 1e12
             roof = {"kernel": name, "bound": "mfma", "achieved": ach, "peak": mm_peak,
                     "unit": "TFLOP/s", "frac": ach / mm_peak}
-        # beside the HBM figure: the whitening-row gathers, one row of D
-        # elements of the whitening copy per nonzero, served from the caches
+        # beside it: the whitening-row gathers, one row of D elements of the
+        # whitening copy per nonzero, served by the caches
         gather_bytes = nnz_tot / K_steps * D * w_elem
         roof.update({"traffic": measured_traffic(key, spec.name),
                      "algorithmic_bytes": csr_bytes + w_bytes, "algorithmic_flops": cp_flops,
@@ -920,34 +937,73 @@ def main():
         fit_beta = {"c1": 0.03, "c2": 0.01}.get(spec.name, 1e-3)
     acc = {"passes": args.fit_passes, "beta": fit_beta}
     mus = {}
-    for name, cx in ((args.precision, ctx), ("fp32" if bf16 else "bf16", other)):
+    for name, cx in ((precision, ctx), (other_name, other)):
         Phi = torch.from_numpy(init_phi(D, K, 1).astype(np.float32)).cuda()
         for _ in range(args.fit_passes):
             for b in dev:
                 tl.tlda_whiten_cp_step(cx, b, fit_beta, Phi)
         acc[f"{name}_topic_l1_to_planted"], mus[name] = topic_error(tl, cx, Phi, corpus.mu)
     acc["fp32_vs_bf16_topic_l1"] = float(np.abs(mus["fp32"] - mus["bf16"]).sum(axis=0).mean())
-    log(f"[bench] topic error after {args.fit_passes} passes: {acc}")
+    log(f"[bench] {spec.name} topic error after {args.fit_passes} passes: {acc}")
+    return {"corpus": corpus, "batches": batches, "runs": runs, "graph_runs": graph_runs,
+            "roof": roof, "acc": acc, "moments_ms": moments_ms, "refresh_ms": refresh_ms,
+            "W": W, "m": m, "stage_format": stage_format, "beta": beta, "kern_us": kern_us,
+            "other_name": other_name}
 
-    mom_docs_s = corpus.n_docs / (moments_ms / 1e3)
-    other_name = "fp32" if bf16 else "bf16"
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of this path is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "c5":
+        run_encoder(args)
+        return
+    if args.workload == "c4":
+        run_slices(args)
+        return
+    if args.estimator == "classic":
+        run_classic(args)
+        return
+    if args.online:
+        run_online(args)
+        return
+    import torch
+
+    from paper_2511_07809_amd import tlda as tl
+    from synth import SPECS
+
+    spec = SPECS[args.workload]
+    n_docs = args.docs or (16 * spec.batch if spec.name == "c3" else 0)
+    torch.cuda.set_device(0)
+    # a stream of its own (default priority): the null stream cannot be captured
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    res = measure(tl, spec, args, args.precision, n_docs, stream)
+    corpus, runs, graph_runs = res["corpus"], res["runs"], res["graph_runs"]
+    main_run, main_graph = runs[args.precision], graph_runs.get(args.precision)
+    other_name = res["other_name"]
+    K = spec.K
+    mom_docs_s = corpus.n_docs / (res["moments_ms"] / 1e3)
+    bf16 = args.precision == "bf16"
     out = {
         "metric": "docs/sec (whiten+CP step) at fixed topic-recovery error; % HBM roofline",
         "value": (main_graph or main_run)["docs_per_s"], "unit": "docs/s", "n_gpus": 1,
-        "steps": K_steps, "warmup": args.warmup,
-        "ms_per_step": (main_graph or main_run)["total_ms"] / K_steps,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": (main_graph or main_run)["total_ms"] / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16" if bf16 else "f32", "data": "synthetic",
         "config": {"workload": f"{spec.name}: V={spec.V}, K=D={K}, alpha0={spec.alpha0}, "
-                               f"{corpus.n_docs} docs of length 1+Poisson({spec.doc_len_lambda:g}), "
-                               f"batch {spec.batch}, "
+                               f"{corpus.n_docs} docs ({len(res['batches'])} distinct batches of "
+                               f"{spec.batch}) of length 1+Poisson({spec.doc_len_lambda:g}), "
                                + ("streamed from pinned host memory" if args.streamed
                                   else "resident in HBM"),
                    "streamed": bool(args.streamed), "precision": args.precision,
-                   "stage_format": stage_format if args.streamed else None,
-                   "global_batch": spec.batch, "beta": beta, "path": args.path,
+                   "stage_format": res["stage_format"] if args.streamed else None,
+                   "global_batch": spec.batch, "beta": res["beta"], "path": args.path,
                    "launch": "hip_graph" if main_graph else "eager"},
-        "roofline": roof,
+        "roofline": res["roof"],
         "breakdown": {"path": args.path,
                       "eager_docs_per_s": main_run["docs_per_s"],
                       "graph_docs_per_s": main_graph["docs_per_s"] if main_graph else None,
@@ -955,16 +1011,34 @@ def main():
                       f"{other_name}_graph_docs_per_s":
                           graph_runs[other_name]["docs_per_s"] if other_name in graph_runs else None,
                       "step_us": float(main_run["step_ms"].mean()) * 1e3,
-                      "main_kernel_us": [float(x) for x in kern_us],
+                      "main_kernel_us": [float(x) for x in res["kern_us"]],
                       f"{other_name}_docs_per_s": runs[other_name]["docs_per_s"],
                       f"{other_name}_step_us": float(runs[other_name]["step_ms"].mean()) * 1e3,
-                      "moment_pass_ms": moments_ms, "moments_docs_per_s": mom_docs_s,
-                      "refresh_ms": refresh_ms},
-        "accuracy": acc,
+                      f"{other_name}_main_kernel_us":
+                          [float(x) for x in runs[other_name]["kern_ms"].mean(axis=0) * 1e3],
+                      "moment_pass_ms": res["moments_ms"], "moments_docs_per_s": mom_docs_s,
+                      "refresh_ms": res["refresh_ms"]},
+        "accuracy": res["acc"],
     }
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(corpus, spec, batches, args.cpu_seconds)
+        log("[bench] timing the CPU oracle on one batch (single-thread and all cores)")
+        rp, ci, va, _ = res["batches"][0]
+        out["cpu_baseline"] = cpu_baseline(spec, (rp, ci, va), res["W"], res["m"], args.cpu_reps)
+        log(f"[bench] cpu baseline: {out['cpu_baseline']['value']:.4g} docs/s "
+            f"({out['cpu_baseline']['cores']} threads), single thread "
+            f"{out['cpu_baseline']['single_thread_docs_per_s']:.4g}")
+    if spec.name == "c3" and not args.no_c2 and not args.streamed and not args.docs:
+        del res
+        c2 = measure(tl, SPECS["c2"], args, args.precision, 0, stream)
+        out["breakdown"]["c2"] = {
+            "workload": f"c2: V=20000, K=D=50, {c2['corpus'].n_docs} docs, batch "
+                        f"{SPECS['c2'].batch}, resident in HBM",
+            **{f"{n}_graph_docs_per_s": g["docs_per_s"] for n, g in c2["graph_runs"].items()},
+            **{f"{n}_main_kernel_us": float(r["kern_ms"].mean() * 1e3)
+               for n, r in c2["runs"].items()},
+            "roofline": {k: c2["roof"][k] for k in ("kernel", "bound", "frac", "hbm_frac",
+                                                   "mfma_frac", "avg_launch_us")},
+            "accuracy": c2["acc"]}
     if args.copy_probe_mb:
         n = args.copy_probe_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
