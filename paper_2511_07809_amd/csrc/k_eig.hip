@@ -3,13 +3,12 @@
 // Cholesky-QR orthonormalisation and a final Rayleigh-Ritz step solved by
 // parallel-order cyclic Jacobi (section "Online Decomposition of the Second
 // Moment": W = U diag(lambda)^(-1/2) so that W^T M2~ W = I).
-#include <rocblas/rocblas.h>
+#include <algorithm>
 
 #include "tlda_internal.h"
 
 namespace tlda {
 
-thread_local void* g_blas = nullptr;
 thread_local EigEnv g_eig_env;
 
 namespace {
@@ -92,6 +91,175 @@ __global__ void __launch_bounds__(256) k_gemm64(int M, int N, int Kd, const doub
   }
 }
 
+// ---------------------------------------------------------------------------
+// Dense FP64 GEMM on the matrix cores: C = alpha * A * B (row-major; A is
+// M x K, B is K x N), v_mfma_f64_16x16x4f64 with FP64 accumulation.
+// Block: 8 waves over a 128-row x 16 NT-column tile of C (NT 16-column
+// tiles, at most 8: wider products take several column blocks, and two
+// blocks fit on a CU); wave (wr, wc) owns rows 32 wr .. 32 wr + 31 (two
+// 16-row MFMA tiles) and column half wc (tiles 0 .. NT0 - 1 or NT0 .. NT - 1).
+// K advances 16 at a time through double-buffered LDS: the next K tile is
+// loaded into registers while the current one is multiplied (loads are
+// unconditional, from clamped addresses, with out-of-range entries zeroed by
+// selects, so none of them waits on another).  For the tall products (C = S2
+// times the subspace block, V rows) the 128-row tile reads each row block of
+// B once per 128 rows of A: B's traffic is N / 128 of A's.  grid.z splits K
+// into chunks whose C tiles go to their own slice of a workspace
+// (c_stride_z apart); k_sum_splits adds the slices in order.
+// Operand layout of the instruction: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; accumulator register r of lane l is D[4 r + l / 16][l % 16].
+// ---------------------------------------------------------------------------
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+constexpr int kDgBM = 128, kDgBK = 16, kDgThreads = 512;
+
+template <int NT>
+__global__ void __launch_bounds__(kDgThreads, 4) k_dgemm_mfma(
+    int M, int N, int K, int k_chunk, const double* __restrict__ A, int lda,
+    const double* __restrict__ B, int ldb, double* __restrict__ C, int ldc, size_t c_stride_z,
+    double alpha) {
+  constexpr int BNC = 16 * NT, LDA_S = kDgBK + 1, LDB_S = BNC + 2;
+  constexpr int NT0 = (NT + 1) / 2;
+  constexpr int A_PER = kDgBM * kDgBK / kDgThreads;
+  constexpr int B_PER = (kDgBK * BNC + kDgThreads - 1) / kDgThreads;
+  __shared__ double As[2][kDgBM * LDA_S];
+  __shared__ double Bs[2][kDgBK * LDB_S];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 3, wc = wave >> 2;
+  const int ct0 = wc ? NT0 : 0;
+  const int nct = wc ? NT - NT0 : NT0;
+  const int row0 = blockIdx.y * kDgBM, col0 = blockIdx.x * BNC;
+  const int kbeg = blockIdx.z * k_chunk;
+  const int kend = min(K, kbeg + k_chunk);
+  C += blockIdx.z * c_stride_z;
+  doublex4 acc[2][NT0];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int j = 0; j < NT0; ++j) acc[t][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+  // raw loaded values and which of them are in range: the selects happen
+  // when the tile is stored to LDS, after the matrix work, so nothing waits
+  // for the loads before then
+  double ra[A_PER], rb[B_PER];
+  unsigned am = 0, bm = 0;
+  auto load = [&](int k0) {
+    am = bm = 0;
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) {
+      const int e = tid + i * kDgThreads;
+      const int gr = row0 + e / kDgBK, gk = k0 + e % kDgBK;
+      const bool in = gr < M && gk < kend;
+      ra[i] = A[in ? (size_t)gr * lda + gk : 0];
+      am |= (in ? 1u : 0u) << i;
+    }
+#pragma unroll
+    for (int i = 0; i < B_PER; ++i) {
+      const int e = tid + i * kDgThreads;
+      const int gk = k0 + e / BNC, gc = col0 + e % BNC;
+      const bool in = e < kDgBK * BNC && gk < kend && gc < N;
+      rb[i] = B[in ? (size_t)gk * ldb + gc : 0];
+      bm |= (in ? 1u : 0u) << i;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) {
+      const int e = tid + i * kDgThreads;
+      As[buf][(e / kDgBK) * LDA_S + e % kDgBK] = ((am >> i) & 1u) ? ra[i] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < B_PER; ++i) {
+      const int e = tid + i * kDgThreads;
+      if (e < kDgBK * BNC) Bs[buf][(e / BNC) * LDB_S + e % BNC] = ((bm >> i) & 1u) ? rb[i] : 0.0;
+    }
+  };
+  const int nk = (kend - kbeg + kDgBK - 1) / kDgBK;
+  load(kbeg);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load(kbeg + (kt + 1) * kDgBK);
+    const double* as = As[cur] + (wr * 32 + (lane & 15)) * LDA_S + (lane >> 4);
+    const double* bs = Bs[cur] + (lane >> 4) * LDB_S + ct0 * 16 + (lane & 15);
+#pragma unroll
+    for (int ks = 0; ks < kDgBK / 4; ++ks) {
+      const double a0 = as[4 * ks], a1 = as[16 * LDA_S + 4 * ks];
+#pragma unroll
+      for (int j = 0; j < NT0; ++j)
+        if (j < nct) {
+          const double b = bs[4 * ks * LDB_S + j * 16];
+          acc[0][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][j], 0, 0, 0);
+          acc[1][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int j = 0; j < NT0; ++j) {
+      if (j >= nct) continue;
+      const int col = col0 + (ct0 + j) * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wr * 32 + t * 16 + 4 * r + (lane >> 4);
+        if (row < M && col < N) C[(size_t)row * ldc + col] = alpha * acc[t][j][r];
+      }
+    }
+}
+
+// C[r][c] = alpha * sum_z ws[z][r][c] in order z = 0 .. nz - 1 (ws slices M x N).
+__global__ void k_sum_splits(const double* __restrict__ ws, int nz, int M, int N,
+                             double* __restrict__ C, int ldc, double alpha) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t mn = (size_t)M * N;
+  if (e >= mn) return;
+  double s = 0.0;
+  for (int z = 0; z < nz; ++z) s += ws[(size_t)z * mn + e];
+  C[(e / N) * ldc + e % N] = alpha * s;
+}
+
+template <int NT>
+hipError_t launch_dgemm_nt(dim3 grid, int M, int N, int K, int chunk, const double* A, int lda,
+                           const double* B, int ldb, double* C, int ldc, size_t cz, double alpha,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_dgemm_mfma<NT>, grid, dim3(kDgThreads), 0, s, M, N, K, chunk, A, lda, B,
+                     ldb, C, ldc, cz, alpha);
+  return hipGetLastError();
+}
+
+hipError_t dgemm_mfma(int M, int N, int K, const double* A, int lda, const double* B, int ldb,
+                      double* C, int ldc, double alpha, hipStream_t s) {
+  const int gx = (N + 127) / 128;                     // column blocks of at most 8 tiles
+  const int NT = ((N + gx - 1) / gx + 15) / 16;
+  const int BNC = 16 * NT;
+  const int gy = (M + kDgBM - 1) / kDgBM;
+  int splits = dgemm_splits(M, N, K, g_eig_env.num_cu);
+  if (splits > 1 && (g_eig_env.ws == nullptr || (size_t)splits * M * N > g_eig_env.ws_doubles))
+    splits = 1;
+  int chunk = ((K + splits - 1) / splits + kDgBK - 1) / kDgBK * kDgBK;
+  splits = (K + chunk - 1) / chunk;
+  double* out = splits > 1 ? g_eig_env.ws : C;
+  const int ldo = splits > 1 ? N : ldc;
+  const size_t cz = splits > 1 ? (size_t)M * N : 0;
+  const double al = splits > 1 ? 1.0 : alpha;
+  const dim3 grid(gx, gy, splits);
+  hipError_t e = hipErrorInvalidValue;
+  switch (NT) {
+#define TLDA_DG(n) \
+  case n: e = launch_dgemm_nt<n>(grid, M, N, K, chunk, A, lda, B, ldb, out, ldo, cz, al, s); break;
+    TLDA_DG(1) TLDA_DG(2) TLDA_DG(3) TLDA_DG(4) TLDA_DG(5) TLDA_DG(6) TLDA_DG(7) TLDA_DG(8)
+#undef TLDA_DG
+    default: break;
+  }
+  if (e != hipSuccess || splits == 1) return e;
+  const size_t mn = (size_t)M * N;
+  hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s,
+                     g_eig_env.ws, splits, M, N, C, ldc, alpha);
+  return hipGetLastError();
+}
+
 // Out[e] = alpha * sum_z part[z][e] over nz chunks: four lanes per entry,
 // lane c adding the c-th quarter of the chunks in chunk order, the quarters
 // then combined as (q0 + q1) + (q2 + q3) (a fixed order, so the sum is
@@ -143,17 +311,7 @@ hipError_t gemm(bool transA, int M, int N, int Kd, const double* A, int lda, con
                        g_eig_env.part, nz, mn, N, ldc, alpha, C);
     return hipGetLastError();
   }
-  if (g_blas != nullptr) {
-    // row-major C = op(A) B is column-major C^T = B^T op(A)^T
-    rocblas_handle h = static_cast<rocblas_handle>(g_blas);
-    if (rocblas_set_stream(h, s) != rocblas_status_success) return hipErrorUnknown;
-    const double beta = 0.0;
-    const rocblas_status st =
-        rocblas_dgemm(h, rocblas_operation_none,
-                      transA ? rocblas_operation_transpose : rocblas_operation_none, N, M, Kd,
-                      &alpha, B, ldb, A, lda, &beta, C, ldc);
-    return st == rocblas_status_success ? hipSuccess : hipErrorUnknown;
-  }
+  if (!transA && g_eig_env.route == 0) return dgemm_mfma(M, N, Kd, A, lda, B, ldb, C, ldc, alpha, s);
   if (splits < 1) splits = 1;
   int chunk = (Kd + splits - 1) / splits;
   chunk = (chunk + 15) / 16 * 16;
@@ -823,6 +981,26 @@ hipError_t launch_from_injected(const double* W, int V, int D, double* U, double
                                 hipStream_t s) {
   hipLaunchKernelGGL(k_from_injected, dim3(D), dim3(256), 0, s, W, V, D, U, eig);
   return hipGetLastError();
+}
+
+int dgemm_splits(int M, int N, int K, int num_cu) {
+  // blocks resident at once: two 8-wave blocks per CU; the time of a product
+  // goes as (rounds of resident blocks) / splits, so pick the split count in
+  // 1 .. 8 (chunks of at least 1024) with the fewest rounds per split,
+  // the smallest count on ties
+  const long long blocks = (long long)((N + 127) / 128) * ((M + kDgBM - 1) / kDgBM);
+  const long long slots = 2LL * num_cu;
+  if (K < 2048 || blocks <= 0) return 1;
+  int best = 1;
+  double best_t = (double)((blocks + slots - 1) / slots);
+  for (int sp = 2; sp <= 8 && K / sp >= 1024; ++sp) {
+    const double t = (double)((blocks * sp + slots - 1) / slots) / sp;
+    if (t < best_t - 1e-9) {
+      best_t = t;
+      best = sp;
+    }
+  }
+  return best;
 }
 
 }  // namespace tlda

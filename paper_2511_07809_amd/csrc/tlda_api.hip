@@ -8,8 +8,6 @@
 #include <new>
 #include <vector>
 
-#include <rocblas/rocblas.h>
-
 #include "tlda_internal.h"
 
 using tlda::launch_zero;
@@ -246,9 +244,10 @@ tlda_status ensure_eig(tlda_ctx* c, int p) {
   tlda::EigScratch& e = c->eig;
   if (e.p == p && e.Q) return TLDA_OK;
   dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
-  dfree(e.sel); dfree(e.mcand); dfree(e.info); dfree(e.part);
+  dfree(e.sel); dfree(e.mcand); dfree(e.info); dfree(e.part); dfree(e.ws);
   e.p = 0;
   e.part_chunks = 0;
+  e.ws_doubles = 0;
   e.warm = nullptr;
   const size_t V = c->cfg.V, D = c->cfg.D;
   HIP_OK(c, dalloc(&e.Q, V * p));
@@ -265,6 +264,12 @@ tlda_status ensure_eig(tlda_ctx* c, int p) {
   const int chunks = (int)std::min<size_t>(tlda::kSplitMax, (V + 63) / 64);
   HIP_OK(c, dalloc(&e.part, (size_t)chunks * p * p));
   e.part_chunks = chunks;
+  // K-split partials of the S2 product on the matrix cores (V x p each)
+  const int splits = tlda::dgemm_splits((int)V, p, (int)V, c->num_cu > 0 ? c->num_cu : 256);
+  if (splits > 1) {
+    HIP_OK(c, dalloc(&e.ws, (size_t)splits * V * p));
+    e.ws_doubles = (size_t)splits * V * p;
+  }
   e.p = p;
   return TLDA_OK;
 }
@@ -312,23 +317,24 @@ tlda_status save_prev(tlda_ctx* c) {
   return TLDA_OK;
 }
 
-tlda_status ensure_blas(tlda_ctx* c) {
-  if (c->blas != nullptr) return TLDA_OK;
-  rocblas_handle h = nullptr;
-  CHECK_ARG(c, rocblas_create_handle(&h) == rocblas_status_success, TLDA_ERR_DEVICE,
-            "rocBLAS handle creation failed");
-  c->blas = h;
-  return TLDA_OK;
+// The refresh's product environment: its matrix-core or vector route, the
+// Gram-split and K-split scratch of this context.
+tlda::EigEnv eig_env(const tlda_ctx* c) {
+  tlda::EigEnv env;
+  env.route = c->tune.gemm_route == 1 ? 1 : 0;
+  env.part = c->eig.part;
+  env.part_mn = c->eig.part ? (size_t)c->eig.p * c->eig.p : 0;
+  env.part_chunks = c->eig.part_chunks;
+  env.ws = c->eig.ws;
+  env.ws_doubles = c->eig.ws_doubles;
+  env.num_cu = c->num_cu > 0 ? c->num_cu : 256;
+  return env;
 }
 
 // warm: start from the block the previous refresh converged to (if any) and
 // run cfg.eig_warm_iters iterations instead of a seeded cold start.
 tlda_status refresh(tlda_ctx* c, bool warm) {
   const int V = c->cfg.V, D = c->cfg.D;
-  {
-    tlda_status bs = ensure_blas(c);
-    if (bs != TLDA_OK) return bs;
-  }
   unsigned long long counts[2] = {0, 0};
   HIP_OK(c, hipMemcpyAsync(counts, c->mom.counts, sizeof(counts), hipMemcpyDeviceToHost, c->stream));
   HIP_OK(c, hipStreamSynchronize(c->stream));
@@ -337,8 +343,7 @@ tlda_status refresh(tlda_ctx* c, bool warm) {
   tlda_status st = ensure_eig(c, p);
   if (st != TLDA_OK) return st;
   tlda::EigScratch& e = c->eig;
-  tlda::BlasScope blas_scope(c->tune.gemm_route == 1 ? nullptr : c->blas, e.part, (size_t)p * p,
-                             e.part_chunks);
+  tlda::EigScope scope(eig_env(c));
   warm = warm && e.warm != nullptr;
   const int iters = warm ? (c->cfg.eig_warm_iters > 0 ? c->cfg.eig_warm_iters : 4)
                          : (c->cfg.eig_iters > 0 ? c->cfg.eig_iters : 60);
@@ -547,7 +552,7 @@ void destroy_all(tlda_ctx* c) {
   delete[] c->t_stop;
   tlda::EigScratch& e = c->eig;
   dfree(e.Q); dfree(e.Y); dfree(e.G); dfree(e.Z); dfree(e.ev); dfree(e.t); dfree(e.Binv);
-  dfree(e.sel); dfree(e.mcand); dfree(e.info); dfree(e.part);
+  dfree(e.sel); dfree(e.mcand); dfree(e.info); dfree(e.part); dfree(e.ws);
   dfree(c->cp.partial); dfree(c->cp.R1); dfree(c->cp.phi0); dfree(c->cp.grad); dfree(c->cp.X);
   dfree(c->cp.gsq);
   dfree(c->cp.Z); dfree(c->cp.rz); dfree(c->cp.Z16);
@@ -560,7 +565,6 @@ void destroy_all(tlda_ctx* c) {
     if (s.free_) (void)hipEventDestroy(s.free_);
   }
   if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
-  if (c->blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(c->blas));
   delete c;
 }
 
@@ -1032,10 +1036,7 @@ tlda_status tlda_rebase_phi(tlda_ctx* c, float* Phi) {
   CHECK_ARG(c, c->wh.ready && c->wh.prev_ready, TLDA_ERR_STATE,
             "no previous whitening to rebase from");
   const int V = c->cfg.V, D = c->cfg.D, K = c->cfg.K;
-  tlda_status st = ensure_blas(c);
-  if (st != TLDA_OK) return st;
-  tlda::BlasScope blas_scope(c->tune.gemm_route == 1 ? nullptr : c->blas, c->eig.part,
-                             c->eig.part ? (size_t)c->eig.p * c->eig.p : 0, c->eig.part_chunks);
+  tlda::EigScope scope(eig_env(c));
   HIP_OK(c, tlda::launch_gram(c->wh.U, c->wh.Uprev, c->wh.C, V, D, c->stream));
   HIP_OK(c, tlda::launch_rebase(c->wh.C, c->wh.eig, c->wh.eigprev, D, K, Phi, c->stream));
   return TLDA_OK;

@@ -81,6 +81,8 @@ struct EigScratch {
   double* warm = nullptr;  // Q or Y: the orthonormal block the last refresh converged to
   double* part = nullptr;  // [part_chunks][p][p] partial sums of the Gram products
   int part_chunks = 0;     // min(kSplitMax, ceil(V / 64)): the most row chunks gemm() uses
+  double* ws = nullptr;    // [splits][V][p] K-split partials of the S2 product
+  size_t ws_doubles = 0;
 };
 
 // Launch-shape knobs (0 = built-in choice).  Initialised from the
@@ -91,7 +93,7 @@ struct EigScratch {
 // (default: one full round of resident blocks); whiten_v4: float4 columns
 // per lane (1 or 2); whiten_chunks: XCD column chunks (1, 2, 4, 8; -1 = by
 // W size); gemm_route (TLDA_TUNE_GEMM): 1 runs the refresh's dense products
-// on the library's vector-ALU tile kernel instead of the default route.
+// on the library's vector-ALU tile kernel instead of the FP64 matrix cores.
 struct Tuning {
   int cp_max_blocks = 0;
   int fused_blocks = 0;
@@ -149,7 +151,6 @@ struct tlda_ctx {
   hipEvent_t* t_stop = nullptr;
   int t_n = 0, t_next = 0;
   bool in_capture = false;    // capturing a graph of steps: no validation, no timing hook
-  void* blas = nullptr;       // rocblas_handle of the refresh's FP64 products (created lazily)
   mutable std::string last_error;   // also set by the const inspection calls
   // device address of the allocation-free step's partial buffer on this
   // context's device (null, with the runtime's message, if the lookup failed)
@@ -218,37 +219,33 @@ struct KernelTimer {
 };
 extern thread_local KernelTimer g_main_timer;
 
-// rocBLAS handle (a rocblas_handle) for the dense FP64 products of the
-// whitening refresh, set by the API around a refresh or rebase; while it is
-// null those products run on the library's own GEMM kernel.
-// Partial-sum scratch of the transposed products A^T B over many rows (the
-// refresh's Gram products): up to kSplitMax row chunks each write their own
-// M x N partial, added in chunk order afterwards (deterministic).
+// Environment of the refresh's dense FP64 products, set by the API around a
+// refresh or rebase (EigScope).  route 0: C = A B on the FP64 matrix cores
+// (k_dgemm_mfma), with a K split over ws (splits x M x N doubles) when the
+// grid would not fill the device; route 1: the vector-ALU tile kernel.
+// The transposed products A^T B over many rows (the refresh's Gram products)
+// split their rows into up to kSplitMax chunks, each writing its own M x N
+// partial to `part`, added in chunk order afterwards (deterministic).
 constexpr int kSplitMax = 256;
 struct EigEnv {
-  void* blas = nullptr;
+  int route = 0;
   double* part = nullptr;     // part_chunks * part_mn doubles
   size_t part_mn = 0;         // largest M * N the scratch serves
   int part_chunks = 0;        // row chunks the scratch holds (at most kSplitMax)
+  double* ws = nullptr;       // K-split workspace of the matrix-core product
+  size_t ws_doubles = 0;
+  int num_cu = 256;
 };
-extern thread_local void* g_blas;
 extern thread_local EigEnv g_eig_env;
-struct BlasScope {
+struct EigScope {
   EigEnv prev;
-  void* prev_blas;
-  BlasScope(void* h, double* part, size_t part_mn, int part_chunks)
-      : prev(g_eig_env), prev_blas(g_blas) {
-    g_blas = h;
-    g_eig_env.blas = h;
-    g_eig_env.part = part;
-    g_eig_env.part_mn = part_mn;
-    g_eig_env.part_chunks = part_chunks;
-  }
-  ~BlasScope() {
-    g_blas = prev_blas;
-    g_eig_env = prev;
-  }
+  explicit EigScope(const EigEnv& e) : prev(g_eig_env) { g_eig_env = e; }
+  ~EigScope() { g_eig_env = prev; }
 };
+// K-split count of the matrix-core product C (M x N) = A (M x K) B: the count
+// in 1 .. 8 (chunks of at least 1024) that fills the rounds of resident
+// blocks best.
+int dgemm_splits(int M, int N, int K, int num_cu);
 
 template <typename... Params, typename... Args>
 inline void launch_main(void (*kernel)(Params...), dim3 grid, dim3 block, unsigned shmem,
