@@ -142,8 +142,11 @@ typedef struct {
 
 /* Create a context whose work runs on `hip_stream` (a hipStream_t; NULL = the
  * null stream).  Validates the configuration (TLDA_ERR_ARG / TLDA_ERR_SHAPE).
- * Device memory for the second moment (V*V doubles) is allocated on the first
- * tlda_update_moments call. */
+ * Device memory for the second moment is allocated on the first
+ * tlda_update_moments call: the exact accumulator of its upper triangle
+ * (8 V (V + 1) bytes) and, at the first refresh, the FP64 V x V matrix the
+ * refresh multiplies (8 V^2 bytes); about 16 V^2 bytes in all (40 GB at
+ * V = 50 000; TLDA_ERR_OOM when the device cannot hold them). */
 tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out);
 void tlda_destroy(tlda_ctx* ctx);
 const char* tlda_status_str(tlda_status s);
@@ -171,7 +174,10 @@ const char* tlda_last_error(const tlda_ctx* ctx);
  * the totals and sum f, keeping W: for contexts that only step after their
  * refresh (e.g. many time slices, whose accumulators could not all stay
  * resident).  A later update allocates the accumulator again.
- * Accumulation uses FP64 atomics: sums are exact up to FP64 rounding order. */
+ * The sums of f and of the pairs are accumulated exactly in 128-bit fixed
+ * point (each FP64 term truncated to a multiple of 2^-64), so the moments,
+ * and every W refreshed from them, are the same bits whatever the order or
+ * the batching of the documents. */
 tlda_status tlda_update_moments(tlda_ctx* ctx, const tlda_csr_batch* batch, uint32_t flags);
 
 /* TLDA_REFRESH_WARM (fully online mode, section "Fully Online, Incremental

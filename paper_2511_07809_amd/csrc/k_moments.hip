@@ -48,12 +48,42 @@ __global__ void __launch_bounds__(256) k_validate_csr(const int32_t* __restrict_
   }
 }
 
+// Exact, order-independent accumulation of FP64 terms in [0, 2^63): every
+// term t becomes the integer floor(t 2^64) (fixed point with 2^-64
+// resolution; the truncation loses less than 2^-64 per term) and is added to
+// a 128-bit accumulator {lo, hi} with 64-bit integer atomics: lo takes the
+// low word, and when that add wraps (seen from the value the atomic returns)
+// the carry goes to hi with the integer part.  Integer addition is
+// associative, so the final {hi, lo} is the same bits for any order of the
+// terms: the moments, and the W computed from them, are bit-reproducible.
+__device__ __forceinline__ void fx_add(unsigned long long* __restrict__ acc, double t) {
+  const double ip = floor(t);
+  unsigned long long hi = (unsigned long long)ip;
+  const unsigned long long lo = (unsigned long long)ldexp(t - ip, 64);
+  if (lo != 0ull) {
+    const unsigned long long old = atomicAdd(acc, lo);
+    if (old + lo < old) ++hi;
+  }
+  if (hi != 0ull) atomicAdd(acc + 1, hi);
+}
+
+__device__ __forceinline__ double fx_value(const unsigned long long* __restrict__ acc) {
+  return (double)acc[1] + ldexp((double)acc[0], -64);
+}
+
+// Entry (j, k), j <= k, of the packed upper triangle of a V x V matrix: row
+// j holds columns j .. V - 1 and starts at j V - j (j - 1) / 2.
+__device__ __forceinline__ size_t tri_index(int j, int k, int V) {
+  return (size_t)j * V - (size_t)j * (j - 1) / 2 + (size_t)(k - j);
+}
+
 // One wave per document, grid-stride over the batch.  Token totals use 64-bit
-// integer atomics (exact, order-independent) and the frequency sums FP64
-// atomics.  The pair loop enumerates the upper triangle (j <= k) of the row's
-// nnz positions; as columns are strictly increasing, col_j <= col_k and the
-// pair lands in the upper triangle of S2.  Kept/dropped document counts are
-// kept per block and added by k_add_counts, so no address is hit by every row.
+// integer atomics and the frequency sums and pair sums the exact fixed-point
+// accumulation above.  The pair loop enumerates the upper triangle (j <= k)
+// of the row's nnz positions; as columns are strictly increasing,
+// col_j <= col_k and the pair lands in the packed upper triangle of the
+// accumulator.  Kept/dropped document counts are kept per block and added by
+// k_add_counts, so no address is hit by every row.
 // CLASSIC: the pair sum takes the unbiased piece of the appendix's second
 // moment, c_j c_k / (L (L - 1)) off the diagonal and c_j (c_j - 1) / (L (L - 1))
 // on it, in place of f_j f_k.
@@ -65,8 +95,8 @@ __global__ void __launch_bounds__(256) k_accumulate(const int32_t* __restrict__ 
                                                     const float* __restrict__ val, int n_rows,
                                                     int V, int* __restrict__ block_counts,
                                                     unsigned long long* __restrict__ totals,
-                                                    double* __restrict__ fsum,
-                                                    double* __restrict__ S2) {
+                                                    unsigned long long* __restrict__ fsum,
+                                                    unsigned long long* __restrict__ S2) {
   __shared__ int kept_s[4], drop_s[4];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -88,7 +118,7 @@ __global__ void __launch_bounds__(256) k_accumulate(const int32_t* __restrict__ 
       const int c = col_idx[b + j];
       const float v = val[b + j];
       atomicAdd(&totals[c], (unsigned long long)v);
-      unsafeAtomicAdd(&fsum[c], (double)v * invL);
+      fx_add(fsum + 2 * (size_t)c, (double)v * invL);
     }
     const long long P = (long long)n * (n + 1) / 2;
     const double tn = 2.0 * n + 1.0;
@@ -109,7 +139,7 @@ __global__ void __launch_bounds__(256) k_accumulate(const int32_t* __restrict__ 
       } else {
         prod = ((double)val[b + j] * invL) * ((double)val[b + k] * invL);
       }
-      unsafeAtomicAdd(&S2[(size_t)cj * V + ck], prod);
+      fx_add(S2 + 2 * tri_index(cj, ck, V), prod);
     }
   }
   if (lane == 0) {
@@ -148,31 +178,37 @@ __global__ void __launch_bounds__(256) k_add_counts(const int* __restrict__ bloc
   }
 }
 
-// Copies the upper triangle onto the lower one, so S2 is a full symmetric
-// matrix for the eigen-solver's products.  A 32 x 32 tile of the upper
-// triangle is read row-wise into LDS and written transposed, so both the read
-// and the write are coalesced.
-__global__ void __launch_bounds__(256) k_mirror_upper(double* __restrict__ S2, int V) {
+// The FP64 symmetric S2 of the refresh's products from the packed upper
+// triangle of the fixed-point accumulator: a 32 x 32 tile of the upper
+// triangle is converted row-wise, written in place and, through LDS,
+// transposed into the lower triangle, so reads and writes are coalesced.
+__global__ void __launch_bounds__(256) k_fx_symmetric(const unsigned long long* __restrict__ acc,
+                                                      int V, double* __restrict__ S2) {
   __shared__ double tile[32][33];
-  const int bi = blockIdx.y, bj = blockIdx.x;     // destination tile (bi, bj), bi >= bj
-  if (bj > bi) return;
+  const int bi = blockIdx.y, bj = blockIdx.x;     // source tile (bi, bj) of the upper triangle
+  if (bi > bj) return;
   const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8
-  // source tile (bj, bi) of the upper triangle
   for (int r = ty; r < 32; r += 8) {
-    const int gi = bj * 32 + r, gj = bi * 32 + tx;
-    tile[r][tx] = (gi < V && gj < V) ? S2[(size_t)gi * V + gj] : 0.0;
+    const int gi = bi * 32 + r, gj = bj * 32 + tx;
+    double v = 0.0;
+    if (gi < V && gj < V && gi <= gj) {
+      v = fx_value(acc + 2 * tri_index(gi, gj, V));
+      S2[(size_t)gi * V + gj] = v;
+    }
+    tile[r][tx] = v;
   }
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {
-    const int gi = bi * 32 + r, gj = bj * 32 + tx;   // destination (gi, gj), gi > gj
+    const int gi = bj * 32 + r, gj = bi * 32 + tx;   // destination (gi, gj), gi > gj
     if (gi < V && gj < V && gj < gi) S2[(size_t)gi * V + gj] = tile[tx][r];
   }
 }
 
-__global__ void k_mean(const double* __restrict__ fsum, const unsigned long long* __restrict__ counts,
-                       double* __restrict__ m, int V) {
+__global__ void k_mean(const unsigned long long* __restrict__ fsum,
+                       const unsigned long long* __restrict__ counts, double* __restrict__ m,
+                       int V) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < V) m[i] = fsum[i] / (double)counts[0];
+  if (i < V) m[i] = fx_value(fsum + 2 * (size_t)i) / (double)counts[0];
 }
 
 // Widening of a compact staged batch, four entries per thread.
@@ -217,24 +253,24 @@ hipError_t launch_accumulate(const tlda_csr_batch& b, int V, const Moments& m, i
   if (grid > kAccMaxBlocks) grid = kAccMaxBlocks;
   if (classic)
     hipLaunchKernelGGL(k_accumulate<true>, dim3(grid), dim3(256), 0, s, b.row_ptr, b.col_idx,
-                       b.val, b.n_rows, V, block_counts, m.totals, m.fsum, m.S2);
+                       b.val, b.n_rows, V, block_counts, m.totals, m.fsum, m.acc);
   else
     hipLaunchKernelGGL(k_accumulate<false>, dim3(grid), dim3(256), 0, s, b.row_ptr, b.col_idx,
-                       b.val, b.n_rows, V, block_counts, m.totals, m.fsum, m.S2);
+                       b.val, b.n_rows, V, block_counts, m.totals, m.fsum, m.acc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_add_counts, dim3(1), dim3(256), 0, s, block_counts, grid, m.counts);
   return hipGetLastError();
 }
 
-hipError_t launch_mirror_upper(double* S2, int V, hipStream_t s) {
+hipError_t launch_fx_symmetric(const unsigned long long* acc, int V, double* S2, hipStream_t s) {
   const int nt = (V + 31) / 32;
-  hipLaunchKernelGGL(k_mirror_upper, dim3(nt, nt), dim3(32, 8), 0, s, S2, V);
+  hipLaunchKernelGGL(k_fx_symmetric, dim3(nt, nt), dim3(32, 8), 0, s, acc, V, S2);
   return hipGetLastError();
 }
 
-hipError_t launch_mean(const double* fsum, const unsigned long long* counts, double* m, int V,
-                       hipStream_t s) {
+hipError_t launch_mean(const unsigned long long* fsum, const unsigned long long* counts, double* m,
+                       int V, hipStream_t s) {
   hipLaunchKernelGGL(k_mean, dim3((V + 255) / 256), dim3(256), 0, s, fsum, counts, m, V);
   return hipGetLastError();
 }

@@ -232,11 +232,12 @@ tlda_status end_use(tlda_ctx* c, const tlda_csr_batch* b) {
   return TLDA_OK;
 }
 
-tlda_status ensure_s2(tlda_ctx* c) {
-  if (c->mom.S2) return TLDA_OK;
-  const size_t n = (size_t)c->cfg.V * c->cfg.V;
-  HIP_OK(c, dalloc(&c->mom.S2, n));
-  HIP_OK(c, launch_zero(c->mom.S2, n * sizeof(double), c->stream));
+// The exact pair-sum accumulator (packed upper triangle, zeroed when made).
+tlda_status ensure_acc(tlda_ctx* c) {
+  if (c->mom.acc) return TLDA_OK;
+  const size_t n = tlda::tri_words(c->cfg.V);
+  HIP_OK(c, dalloc(&c->mom.acc, n));
+  HIP_OK(c, launch_zero(c->mom.acc, n * sizeof(unsigned long long), c->stream));
   return TLDA_OK;
 }
 
@@ -349,8 +350,9 @@ tlda_status refresh(tlda_ctx* c, bool warm) {
                          : (c->cfg.eig_iters > 0 ? c->cfg.eig_iters : 60);
   const double N = (double)counts[0];
   HIP_OK(c, launch_zero(e.info, 4 * sizeof(int), c->stream));
+  if (c->mom.S2 == nullptr) HIP_OK(c, dalloc(&c->mom.S2, (size_t)V * V));
   HIP_OK(c, tlda::launch_mean(c->mom.fsum, c->mom.counts, e.mcand, V, c->stream));
-  HIP_OK(c, tlda::launch_mirror_upper(c->mom.S2, V, c->stream));
+  HIP_OK(c, tlda::launch_fx_symmetric(c->mom.acc, V, c->mom.S2, c->stream));
   double* q = e.Q;
   double* y = e.Y;
   if (warm) {
@@ -544,7 +546,8 @@ tlda_status classic_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float
 void destroy_all(tlda_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  dfree(c->mom.counts); dfree(c->mom.totals); dfree(c->mom.fsum); dfree(c->mom.S2);
+  dfree(c->mom.counts); dfree(c->mom.totals); dfree(c->mom.fsum); dfree(c->mom.acc);
+  dfree(c->mom.S2);
   dfree(c->wh.W); dfree(c->wh.U); dfree(c->wh.eig); dfree(c->wh.m); dfree(c->wh.W32);
   dfree(c->wh.mw32); dfree(c->wh.W16); dfree(c->wh.mw16);
   dfree(c->wh.Uprev); dfree(c->wh.eigprev); dfree(c->wh.C);
@@ -645,7 +648,7 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
   }
   const size_t V = c.V, D = c.D, K = c.K;
   bool ok = dalloc(&ctx->mom.counts, 2) == hipSuccess && dalloc(&ctx->mom.totals, V) == hipSuccess &&
-            dalloc(&ctx->mom.fsum, V) == hipSuccess && dalloc(&ctx->wh.W, V * D) == hipSuccess &&
+            dalloc(&ctx->mom.fsum, 2 * V) == hipSuccess && dalloc(&ctx->wh.W, V * D) == hipSuccess &&
             dalloc(&ctx->wh.U, V * D) == hipSuccess && dalloc(&ctx->wh.eig, D) == hipSuccess &&
             dalloc(&ctx->wh.m, V) == hipSuccess &&
             dalloc(&ctx->wh.W32, V * (size_t)ctx->Dp) == hipSuccess &&
@@ -664,7 +667,7 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
   if (!ok) return fail(TLDA_ERR_OOM);
   if (launch_zero(ctx->mom.counts, 2 * sizeof(unsigned long long), ctx->stream) != hipSuccess ||
       launch_zero(ctx->mom.totals, V * sizeof(unsigned long long), ctx->stream) != hipSuccess ||
-      launch_zero(ctx->mom.fsum, V * sizeof(double), ctx->stream) != hipSuccess ||
+      launch_zero(ctx->mom.fsum, 2 * V * sizeof(unsigned long long), ctx->stream) != hipSuccess ||
       hipStreamSynchronize(ctx->stream) != hipSuccess)
     return fail(TLDA_ERR_DEVICE);
   *out = ctx;
@@ -690,15 +693,16 @@ tlda_status tlda_update_moments(tlda_ctx* c, const tlda_csr_batch* b, uint32_t f
   }
   tlda_status st = TLDA_OK;
   if (b || (flags & (TLDA_REFRESH_W | TLDA_RESET))) {
-    st = ensure_s2(c);
+    st = ensure_acc(c);
     if (st != TLDA_OK) return st;
   }
   const size_t V = c->cfg.V;
   if (flags & TLDA_RESET) {
     HIP_OK(c, launch_zero(c->mom.counts, 2 * sizeof(unsigned long long), c->stream));
     HIP_OK(c, launch_zero(c->mom.totals, V * sizeof(unsigned long long), c->stream));
-    HIP_OK(c, launch_zero(c->mom.fsum, V * sizeof(double), c->stream));
-    HIP_OK(c, launch_zero(c->mom.S2, V * V * sizeof(double), c->stream));
+    HIP_OK(c, launch_zero(c->mom.fsum, 2 * V * sizeof(unsigned long long), c->stream));
+    HIP_OK(c, launch_zero(c->mom.acc, tlda::tri_words((int)V) * sizeof(unsigned long long),
+                          c->stream));
   }
   if (b && b->n_rows > 0) {
     st = begin_use(c, b);
@@ -715,9 +719,10 @@ tlda_status tlda_update_moments(tlda_ctx* c, const tlda_csr_batch* b, uint32_t f
   if (flags & TLDA_RELEASE) {
     HIP_OK(c, hipStreamSynchronize(c->stream));
     dfree(c->mom.S2);
+    dfree(c->mom.acc);
     HIP_OK(c, launch_zero(c->mom.counts, 2 * sizeof(unsigned long long), c->stream));
     HIP_OK(c, launch_zero(c->mom.totals, V * sizeof(unsigned long long), c->stream));
-    HIP_OK(c, launch_zero(c->mom.fsum, V * sizeof(double), c->stream));
+    HIP_OK(c, launch_zero(c->mom.fsum, 2 * V * sizeof(unsigned long long), c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
   }
   return TLDA_OK;
@@ -1630,21 +1635,24 @@ void tlda_graph_destroy(tlda_graph* g) {
 }
 
 // Checkpoint layout: header (magic, version, V, K, D, flags), the counts,
-// token totals, sum f, S2 (when allocated), then W, U, eig and M1 (when ready).
+// token totals, the exact sum f, the exact pair-sum accumulator (when
+// allocated), then W, U, eig and M1 (when ready).
 namespace {
 constexpr uint32_t kMagic = 0x41444c54u;   // "TLDA"
 struct Header {
   uint32_t magic, version;
-  int32_t V, K, D, has_s2, ready, moments;   // moments: 1 = classic (TLDA_CLASSIC), 0 = centred
+  int32_t V, K, D, has_acc, ready, moments;  // moments: 1 = classic (TLDA_CLASSIC), 0 = centred
 };
+constexpr uint32_t kVersion = 2u;           // 2: fixed-point moment accumulators
 }  // namespace
 
 tlda_status tlda_save_state(const tlda_ctx* c, void* buf, size_t* len) {
   if (!c || !len) return TLDA_ERR_ARG;
   const size_t V = c->cfg.V, D = c->cfg.D;
-  const bool has_s2 = c->mom.S2 != nullptr;
-  size_t need = sizeof(Header) + 2 * 8 + V * 8 + V * 8;
-  if (has_s2) need += V * V * 8;
+  const bool has_acc = c->mom.acc != nullptr;
+  const size_t acc_bytes = tlda::tri_words((int)V) * 8;
+  size_t need = sizeof(Header) + 2 * 8 + V * 8 + V * 16;
+  if (has_acc) need += acc_bytes;
   if (c->wh.ready) need += 2 * V * D * 8 + D * 8 + V * 8;
   if (!buf) {
     *len = need;
@@ -1652,7 +1660,7 @@ tlda_status tlda_save_state(const tlda_ctx* c, void* buf, size_t* len) {
   }
   CHECK_ARG(c, *len >= need, TLDA_ERR_SHAPE, "checkpoint buffer too small");
   char* p = static_cast<char*>(buf);
-  Header h{kMagic, 1u, (int32_t)V, c->cfg.K, (int32_t)D, has_s2 ? 1 : 0, c->wh.ready ? 1 : 0,
+  Header h{kMagic, kVersion, (int32_t)V, c->cfg.K, (int32_t)D, has_acc ? 1 : 0, c->wh.ready ? 1 : 0,
            is_classic(c) ? 1 : 0};
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
@@ -1663,8 +1671,8 @@ tlda_status tlda_save_state(const tlda_ctx* c, void* buf, size_t* len) {
   };
   HIP_OK(c, d2h(c->mom.counts, 16));
   HIP_OK(c, d2h(c->mom.totals, V * 8));
-  HIP_OK(c, d2h(c->mom.fsum, V * 8));
-  if (has_s2) HIP_OK(c, d2h(c->mom.S2, V * V * 8));
+  HIP_OK(c, d2h(c->mom.fsum, V * 16));
+  if (has_acc) HIP_OK(c, d2h(c->mom.acc, acc_bytes));
   if (c->wh.ready) {
     HIP_OK(c, d2h(c->wh.W, V * D * 8));
     HIP_OK(c, d2h(c->wh.U, V * D * 8));
@@ -1681,18 +1689,20 @@ tlda_status tlda_load_state(tlda_ctx* c, const void* buf, size_t len) {
   CHECK_ARG(c, len >= sizeof(Header), TLDA_ERR_SHAPE, "checkpoint too short");
   Header h;
   std::memcpy(&h, buf, sizeof(h));
-  CHECK_ARG(c, h.magic == kMagic && h.version == 1u, TLDA_ERR_ARG, "not a checkpoint of this format");
+  CHECK_ARG(c, h.magic == kMagic && h.version == kVersion, TLDA_ERR_ARG,
+            "not a checkpoint of this format");
   CHECK_ARG(c, h.V == c->cfg.V && h.K == c->cfg.K && h.D == c->cfg.D, TLDA_ERR_SHAPE,
             "checkpoint shape does not match the context");
   CHECK_ARG(c, (h.moments == 1) == is_classic(c), TLDA_ERR_ARG,
             "checkpoint moments (classic or centred) do not match the context");
   const size_t V = c->cfg.V, D = c->cfg.D;
-  size_t need = sizeof(Header) + 16 + V * 16;
-  if (h.has_s2) need += V * V * 8;
+  const size_t acc_bytes = tlda::tri_words((int)V) * 8;
+  size_t need = sizeof(Header) + 16 + V * 8 + V * 16;
+  if (h.has_acc) need += acc_bytes;
   if (h.ready) need += 2 * V * D * 8 + D * 8 + V * 8;
   CHECK_ARG(c, len >= need, TLDA_ERR_SHAPE, "checkpoint truncated");
-  if (h.has_s2) {
-    tlda_status st = ensure_s2(c);
+  if (h.has_acc) {
+    tlda_status st = ensure_acc(c);
     if (st != TLDA_OK) return st;
   }
   const char* p = static_cast<const char*>(buf) + sizeof(Header);
@@ -1703,9 +1713,9 @@ tlda_status tlda_load_state(tlda_ctx* c, const void* buf, size_t len) {
   };
   HIP_OK(c, h2d(c->mom.counts, 16));
   HIP_OK(c, h2d(c->mom.totals, V * 8));
-  HIP_OK(c, h2d(c->mom.fsum, V * 8));
-  if (h.has_s2) HIP_OK(c, h2d(c->mom.S2, V * V * 8));
-  else if (c->mom.S2) HIP_OK(c, launch_zero(c->mom.S2, V * V * 8, c->stream));
+  HIP_OK(c, h2d(c->mom.fsum, V * 16));
+  if (h.has_acc) HIP_OK(c, h2d(c->mom.acc, acc_bytes));
+  else if (c->mom.acc) HIP_OK(c, launch_zero(c->mom.acc, acc_bytes, c->stream));
   if (h.ready) {
     HIP_OK(c, h2d(c->wh.W, V * D * 8));
     HIP_OK(c, h2d(c->wh.U, V * D * 8));

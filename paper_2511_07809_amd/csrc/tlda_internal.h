@@ -42,12 +42,19 @@ struct StageSlot {
   bool used = false;
 };
 
+// Moment accumulators.  fsum and acc hold exact 128-bit fixed-point sums
+// ({lo, hi} pairs of 64-bit words, value hi + lo 2^-64), so the moments do
+// not depend on the order documents are added in; S2 is the FP64 symmetric
+// matrix the refresh forms from acc (k_fx_symmetric) for its products.
 struct Moments {
   unsigned long long* counts = nullptr;  // [0] N kept, [1] dropped
   unsigned long long* totals = nullptr;  // [V] token totals of kept documents
-  double* fsum = nullptr;                // [V] sum of f over kept documents
-  double* S2 = nullptr;                  // [V][V] upper triangle of sum f f^T
+  unsigned long long* fsum = nullptr;    // [V][2] sum of f over kept documents
+  unsigned long long* acc = nullptr;     // [V (V + 1) / 2][2] packed upper triangle of sum f f^T
+  double* S2 = nullptr;                  // [V][V] FP64 symmetric copy, formed at each refresh
 };
+// 64-bit words of the packed fixed-point accumulator of a V-word vocabulary
+inline size_t tri_words(int V) { return (size_t)V * (V + 1); }
 
 struct Whitening {
   bool ready = false;
@@ -267,12 +274,14 @@ hipError_t launch_validate_csr(const tlda_csr_batch& b, int V, int* err, hipStre
 // classic: S2 takes the unbiased pair piece (c c^T - diag c) / (L (L - 1))
 // instead of f f^T
 hipError_t launch_accumulate(const tlda_csr_batch& b, int V, const Moments& m, int* block_counts,
-                             bool classic, hipStream_t s);
-hipError_t launch_mirror_upper(double* S2, int V, hipStream_t s);
+                             bool classic, hipStream_t s);   // adds into m.acc, m.fsum, m.totals
+// S2 (V x V, FP64, symmetric) from the packed fixed-point accumulator
+hipError_t launch_fx_symmetric(const unsigned long long* acc, int V, double* S2, hipStream_t s);
 // col[j] = col16[j], val[j] = val16[j] for j < nnz (compact staging)
 hipError_t launch_widen_u16(const uint16_t* col16, const uint16_t* val16, size_t nnz,
                             int32_t* col, float* val, hipStream_t s);
-hipError_t launch_mean(const double* fsum, const unsigned long long* counts, double* m, int V,
+hipError_t launch_mean(const unsigned long long* fsum, const unsigned long long* counts, double* m,
+                       int V,
                        hipStream_t s);
 // eigen-solver building blocks (FP64)
 hipError_t launch_random_block(double* Q, int V, int p, uint64_t seed, hipStream_t s);

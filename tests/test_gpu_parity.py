@@ -65,6 +65,30 @@ def test_stats_bit_exact_with_ragged_batches_and_dropped_docs(c1):
     assert np.array_equal(totals, ref["token_totals"] + extra["token_totals"])
 
 
+@pytest.mark.parametrize("classic", [False, True])
+def test_moments_and_whitening_are_order_independent(c1, classic):
+    """The exact fixed-point accumulation makes the moments independent of
+    the order and batching of the documents: the same corpus fed forward in
+    batches of 1 000 and backward in ragged batches of 777 gives bit-identical
+    counts, M1, eigenvalues and W."""
+    spec = c1["spec"]
+    c = c1["corpus"]
+    outs = []
+    for order in ("forward", "backward"):
+        ctx = make_ctx(spec.V, spec.K, spec.K, spec.alpha0, classic=classic, eig_iters=60)
+        bs = [b[:3] for b in iter_batches(c, 1000 if order == "forward" else 777)]
+        if order == "backward":
+            bs = bs[::-1]
+        for rp, ci, va in bs:
+            tl.tlda_update_moments(ctx, dev_batch(rp, ci, va))
+        tl.tlda_update_moments(ctx, None, tl.TLDA_REFRESH_W)
+        outs.append((tl.tlda_get_stats(ctx), tl.tlda_get_whitening(ctx)))
+    (sa, wa), (sb, wb) = outs
+    assert sa[0] == sb[0] and sa[1] == sb[1] and np.array_equal(sa[2], sb[2])
+    for x, y in zip(wa, wb):
+        assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("eig_block", [0, 100, 120, 200])
 def test_refresh_matches_oracle_first_moment_and_whitening(c1, eig_block):
     """The block width selects the Rayleigh-Ritz eigensolver: Jacobi with the
