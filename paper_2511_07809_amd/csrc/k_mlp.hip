@@ -15,6 +15,7 @@
 //             db = column sums of dZ
 // gelu(z) = z Phi(z), Phi(z) = (1 + erf(z / sqrt 2)) / 2, from the device
 // math library's erff and expf.
+#include <algorithm>
 #include <cmath>
 
 #include "tlda_internal.h"
@@ -53,12 +54,16 @@ __device__ __forceinline__ float gelu_grad(float z) {
 // quarter (2 x 2 matrix-core tiles).  Operand tiles go through LDS with the
 // reduction index contiguous, which is what the matrix core's A and B
 // fragments need.
+// grid.z splits the reduction (kEpiStore only): block z takes rows
+// z k_chunk .. of the reduction index and writes its partial to
+// Cf + z c_stride_z (k_sum_slices then adds the partials in order).
 template <bool TA, bool TB, bool AF32, int EPI>
 __global__ void __launch_bounds__(kThreads) k_gemm(int M, int N, int Kd, const void* __restrict__ Av,
                                                   int lda, const uint16_t* __restrict__ B, int ldb,
                                                   const float* __restrict__ bias,
                                                   float* __restrict__ Cf, uint16_t* __restrict__ Cb,
-                                                  int ldc, const float* __restrict__ Zaux) {
+                                                  int ldc, const float* __restrict__ Zaux,
+                                                  int k_chunk, size_t c_stride_z) {
   __shared__ __attribute__((aligned(16))) uint16_t As[kTileM * kLdsK];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[kTileN * kLdsK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -73,7 +78,10 @@ __global__ void __launch_bounds__(kThreads) k_gemm(int M, int N, int Kd, const v
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < Kd; k0 += kTileK) {
+  const int kbeg = blockIdx.z * k_chunk;
+  Kd = min(Kd, kbeg + k_chunk);              // this block's end of the reduction index
+  if (EPI == kEpiStore) Cf += blockIdx.z * c_stride_z;
+  for (int k0 = kbeg; k0 < Kd; k0 += kTileK) {
     __syncthreads();
     // ---- A tile: As[m][k] = op(A)[m0 + m][k0 + k] ----
     if (!TA) {
@@ -210,19 +218,34 @@ __global__ void __launch_bounds__(kThreads) k_softmax(const float* __restrict__ 
   }
 }
 
-// out[c] = sum over rows r of M[r][c] (BF16 input, FP32 sum in a fixed
-// order): one block per 64 columns, 4 row phases per column, combined in LDS.
+// part[y][c] = sum over rows r of chunk y (rows y rchunk ..) of M[r][c] (BF16
+// input, FP32 sum in a fixed order): block (x, y) takes 64 columns of row
+// chunk y, 4 row phases per column combined in LDS; k_sum_slices then adds
+// the chunks in order (the bias gradients: column sums of dZ).
 __global__ void __launch_bounds__(kThreads) k_colsum(const uint16_t* __restrict__ Mx, int rows,
-                                                     int cols, float* __restrict__ out) {
+                                                     int cols, int rchunk,
+                                                     float* __restrict__ part) {
   __shared__ float red[4][64];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63), ph = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * rchunk, r1 = min(rows, r0 + rchunk);
   float s = 0.f;
   if (c < cols)
-    for (int r = ph; r < rows; r += 4) s += from_bf16(Mx[(size_t)r * cols + c]);
+    for (int r = r0 + ph; r < r1; r += 4) s += from_bf16(Mx[(size_t)r * cols + c]);
   red[ph][threadIdx.x & 63] = s;
   __syncthreads();
-  if (ph == 0 && c < cols) out[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
-                                    (red[2][threadIdx.x] + red[3][threadIdx.x]);
+  if (ph == 0 && c < cols)
+    part[(size_t)blockIdx.y * cols + c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                          (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+// out[e] = sum_z ws[z][e] for z = 0 .. nz - 1 in order (e < n)
+__global__ void k_sum_slices(const float* __restrict__ ws, int nz, size_t n,
+                             float* __restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < nz; ++z) s += ws[(size_t)z * n + e];
+  out[e] = s;
 }
 
 // loss = sum of the row losses / n (fixed order, one block)
@@ -270,11 +293,56 @@ hipError_t gemm(int M, int N, int Kd, const void* A, int lda, const uint16_t* B,
   if (M <= 0 || N <= 0) return hipSuccess;
   const dim3 grid((N + kTileN - 1) / kTileN, (M + kTileM - 1) / kTileM);
   hipLaunchKernelGGL((k_gemm<TA, TB, AF32, EPI>), grid, dim3(kThreads), 0, s, M, N, Kd, A, lda, B,
-                     ldb, bias, Cf, Cb, ldc, Zaux);
+                     ldb, bias, Cf, Cb, ldc, Zaux, Kd, (size_t)0);
+  return hipGetLastError();
+}
+
+// Weight gradient C (M x N, FP32, ldc = N) = op(A) B over Kd rows, the rows
+// split into chunks of at least kGradChunk so that the grid has up to
+// kGradSplits times the output tiles; the chunk partials (in the encoder's
+// workspace) are added in chunk order.
+constexpr int kGradChunk = 128, kGradSplits = 32;
+template <bool AF32>
+hipError_t grad_gemm(tlda_mlp& m, int M, int N, int Kd, const void* A, int lda, const uint16_t* B,
+                     int ldb, float* C) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  int splits = std::min(kGradSplits, std::max(1, Kd / kGradChunk));
+  const int chunk = (Kd + splits - 1) / splits;
+  splits = (Kd + chunk - 1) / chunk;
+  const size_t mn = (size_t)M * N;
+  float* out = splits > 1 ? m.ws : C;
+  const dim3 grid((N + kTileN - 1) / kTileN, (M + kTileM - 1) / kTileM, splits);
+  hipLaunchKernelGGL((k_gemm<true, false, AF32, kEpiStore>), grid, dim3(kThreads), 0, m.stream, M,
+                     N, Kd, A, lda, B, ldb, nullptr, out, nullptr, N, nullptr, chunk, mn);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || splits == 1) return e;
+  hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, m.stream,
+                     m.ws, splits, mn, C);
+  return hipGetLastError();
+}
+
+// Bias gradient out[c] = sum over the n rows of dZ[r][c]: row chunks of 64
+// in parallel, then their sums in chunk order.
+hipError_t bias_grad(tlda_mlp& m, const uint16_t* dZ, int n, int cols, float* out) {
+  const int rchunk = 64;
+  const int nch = (n + rchunk - 1) / rchunk;
+  hipLaunchKernelGGL(k_colsum, dim3((cols + 63) / 64, nch), dim3(kThreads), 0, m.stream, dZ, n,
+                     cols, rchunk, m.ws);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_slices, dim3((cols + 255) / 256), dim3(256), 0, m.stream, m.ws, nch,
+                     (size_t)cols, out);
   return hipGetLastError();
 }
 
 }  // namespace
+
+size_t mlp_workspace_floats(int d_in, int hidden, int k_out, int max_batch) {
+  const size_t mn = std::max({(size_t)d_in * hidden, (size_t)hidden * hidden,
+                              (size_t)hidden * k_out});
+  const size_t chunks = ((size_t)max_batch + 63) / 64;
+  return std::max((size_t)kGradSplits * mn, chunks * (size_t)std::max(hidden, k_out));
+}
 
 size_t mlp_param_count(int d_in, int hidden, int k_out) {
   return (size_t)d_in * hidden + hidden + (size_t)hidden * hidden + hidden +
@@ -326,32 +394,20 @@ hipError_t mlp_backward(tlda_mlp& m, const float* X, const float* T, int n, floa
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   // layer 3
-  if ((e = gemm<true, false, false, kEpiStore>(H, K, n, m.H2, H, m.dZ3, K, nullptr, g + o[4],
-                                               nullptr, K, nullptr, m.stream)) != hipSuccess)
-    return e;
-  hipLaunchKernelGGL(k_colsum, dim3((K + 63) / 64), dim3(kThreads), 0, m.stream, m.dZ3, n, K,
-                     g + o[5]);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = grad_gemm<false>(m, H, K, n, m.H2, H, m.dZ3, K, g + o[4])) != hipSuccess) return e;
+  if ((e = bias_grad(m, m.dZ3, n, K, g + o[5])) != hipSuccess) return e;
   if ((e = gemm<false, true, false, kEpiDGelu>(n, H, K, m.dZ3, K, m.wb + o[4], K, nullptr, nullptr,
                                                m.dZa, H, m.Z2, m.stream)) != hipSuccess)
     return e;
   // layer 2
-  if ((e = gemm<true, false, false, kEpiStore>(H, H, n, m.H1, H, m.dZa, H, nullptr, g + o[2],
-                                               nullptr, H, nullptr, m.stream)) != hipSuccess)
-    return e;
-  hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64), dim3(kThreads), 0, m.stream, m.dZa, n, H,
-                     g + o[3]);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = grad_gemm<false>(m, H, H, n, m.H1, H, m.dZa, H, g + o[2])) != hipSuccess) return e;
+  if ((e = bias_grad(m, m.dZa, n, H, g + o[3])) != hipSuccess) return e;
   if ((e = gemm<false, true, false, kEpiDGelu>(n, H, H, m.dZa, H, m.wb + o[2], H, nullptr, nullptr,
                                                m.dZb, H, m.Z1, m.stream)) != hipSuccess)
     return e;
   // layer 1
-  if ((e = gemm<true, false, true, kEpiStore>(Din, H, n, X, Din, m.dZb, H, nullptr, g + o[0],
-                                              nullptr, H, nullptr, m.stream)) != hipSuccess)
-    return e;
-  hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64), dim3(kThreads), 0, m.stream, m.dZb, n, H,
-                     g + o[1]);
-  return hipGetLastError();
+  if ((e = grad_gemm<true>(m, Din, H, n, X, Din, m.dZb, H, g + o[0])) != hipSuccess) return e;
+  return bias_grad(m, m.dZb, n, H, g + o[1]);
 }
 
 hipError_t mlp_adam(tlda_mlp& m, float lr, float beta1, float beta2, float eps) {

@@ -1085,7 +1085,7 @@ void mlp_free(tlda_mlp* m) {
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   dfree(m->params); dfree(m->wb); dfree(m->grads); dfree(m->adam_m); dfree(m->adam_v);
   dfree(m->Z1); dfree(m->Z2); dfree(m->H1); dfree(m->H2); dfree(m->logits); dfree(m->dZ3);
-  dfree(m->dZa); dfree(m->dZb); dfree(m->row_loss);
+  dfree(m->dZa); dfree(m->dZb); dfree(m->row_loss); dfree(m->ws);
   delete m;
 }
 
@@ -1135,7 +1135,9 @@ tlda_status tlda_mlp_create(int32_t d_in, int32_t hidden, int32_t k_out, int32_t
             dalloc(&m->Z2, B * H) == hipSuccess && dalloc(&m->H1, B * H) == hipSuccess &&
             dalloc(&m->H2, B * H) == hipSuccess && dalloc(&m->logits, B * K) == hipSuccess &&
             dalloc(&m->dZ3, B * K) == hipSuccess && dalloc(&m->dZa, B * H) == hipSuccess &&
-            dalloc(&m->dZb, B * H) == hipSuccess && dalloc(&m->row_loss, B) == hipSuccess;
+            dalloc(&m->dZb, B * H) == hipSuccess && dalloc(&m->row_loss, B) == hipSuccess &&
+            dalloc(&m->ws, tlda::mlp_workspace_floats(d_in, hidden, k_out, max_batch)) ==
+                hipSuccess;
   if (!ok) {
     mlp_free(m);
     return TLDA_ERR_OOM;

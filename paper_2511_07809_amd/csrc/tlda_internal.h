@@ -186,6 +186,7 @@ struct tlda_mlp {
   uint16_t* dZa = nullptr;     // [max_batch][hidden] BF16 (dZ2, then dZ1)
   uint16_t* dZb = nullptr;
   float* row_loss = nullptr;   // [max_batch]
+  float* ws = nullptr;         // split partials of the weight and bias gradients
   std::string last_error;
 };
 
@@ -387,6 +388,8 @@ hipError_t launch_classic_cp(const tlda_csr_batch& b, const float* W32, int Dp, 
                              hipStream_t s);
 // document-topic encoder (MLP)
 size_t mlp_param_count(int d_in, int hidden, int k_out);
+// floats of the encoder's gradient workspace (split partials)
+size_t mlp_workspace_floats(int d_in, int hidden, int k_out, int max_batch);
 // offsets of W1, b1, W2, b2, W3, b3 in the packed parameter vector
 void mlp_offsets(int d_in, int hidden, int k_out, size_t off[6]);
 // forward pass of n <= max_batch rows: theta = softmax(...) (FP32 [n][k_out]);

@@ -62,7 +62,8 @@ def make_mlp(d_in, hidden, k_out, max_batch, params):
     return m
 
 
-SHAPES = [(50, 256, 50, 1000), (7, 33, 5, 130), (100, 256, 100, 300), (3, 64, 2, 64)]
+SHAPES = [(50, 256, 50, 1000), (7, 33, 5, 130), (100, 256, 100, 300), (3, 64, 2, 64),
+          (50, 256, 50, 4096)]
 
 
 @pytest.mark.parametrize("d_in,hidden,k_out,n", SHAPES)
