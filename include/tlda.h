@@ -420,11 +420,21 @@ const char* tlda_multi_last_error(const tlda_multi* plan);
  * resident blocks on the device, the default).  Synchronous. */
 tlda_status tlda_multi_set_blocks(tlda_multi* plan, int32_t total_blocks);
 tlda_status tlda_multi_get_blocks(const tlda_multi* plan, int32_t* total_blocks);
-/* One step of every slice (asynchronous on the contexts' stream). */
+/* Tile shape of the reduction launch: documents per row tile x waves per
+ * block, one of 64 x 4 (the default), 32 x 4 and 64 x 8 (TLDA_ERR_ARG
+ * otherwise).  Setting it lays the blocks out again with one round of
+ * resident blocks of that shape.  Synchronous. */
+tlda_status tlda_multi_set_tile(tlda_multi* plan, int32_t rows_per_tile, int32_t waves_per_block);
+tlda_status tlda_multi_get_tile(const tlda_multi* plan, int32_t* rows_per_tile,
+                                int32_t* waves_per_block);
+/* One step of every slice: two launches, the reduction over every slice's
+ * batch and the finish (asynchronous on the contexts' stream). */
 tlda_status tlda_multi_step(tlda_multi* plan);
-/* Autotuner: times `reps` steps for each candidate launch shape (1, 2, ...
- * resident blocks per CU, and two rounds), keeps the fastest and restores
- * every Phi to its value at entry.  Synchronous. */
+/* Autotuner: times `reps` steps for every tile shape with each candidate
+ * launch size (1, 2, ... resident blocks per CU of that shape, and two
+ * rounds), keeps the fastest pair (read it back with tlda_multi_get_tile and
+ * tlda_multi_get_blocks) and restores every Phi to its value at entry.
+ * Synchronous. */
 tlda_status tlda_multi_autotune(tlda_multi* plan, int32_t reps, int32_t* total_blocks_out);
 /* Capture the steps of n_plans plans, in order, as one HIP graph on their
  * shared stream; tlda_graph_launch replays it (asynchronous).  A plan's

@@ -110,10 +110,10 @@ constexpr int bf16_waves(int DQ, int KQ) {
   return (DQ > 64 && KQ > 64) ? 16 : (DQ > 64 || KQ > 64) ? 8 : 4;
 }
 
-template <int DQ, int KQ, int NW = 4>
+template <int DQ, int KQ, int NW = 4, int TR = kTile>
 struct Bf16Shape {
   static constexpr int LDA = DQ + 8;        // row-major X tile stride (bf16)
-  static constexpr int LDT = kTile + 8;     // column-major tiles stride (bf16)
+  static constexpr int LDT = TR + 8;        // column-major tiles stride (bf16)
   static constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = DQ / 32;
   static constexpr int ST = (NCT + NW - 1) / NW;       // column tiles of S per wave
   static constexpr int WD = NDT >= 4 ? 4 : NDT;
@@ -122,10 +122,12 @@ struct Bf16Shape {
   static constexpr int TKW = (NCT + WK - 1) / WK;      // R1 column tiles per wave
 };
 
-// The work of one block: block `blk` of `nblk` blocks that share one batch.
-// LDS comes from the caller (Xs: kTile x LDA, XsT: DQ x LDT, SsT: KQ x LDT
-// BF16 values, wave_kept: 4 ints), so one kernel can serve several shapes.
-template <int DQ, int KQ, int G, int MODE, int NW>
+// The work of one block: block `blk` of `nblk` blocks that share one batch,
+// in row tiles of TR documents (64 for the single-batch kernels; the
+// multi-slice kernels also take 32).  LDS comes from the caller (Xs: TR x LDA,
+// XsT: DQ x LDT, SsT: KQ x LDT BF16 values, wave_kept: NW ints), so one kernel
+// can serve several shapes.
+template <int DQ, int KQ, int G, int MODE, int NW, int TR = kTile>
 __device__ __forceinline__ void cp_bf16_block(
     int blk, int nblk, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const float* __restrict__ val, int n_rows, const uint16_t* __restrict__ W16,
@@ -134,12 +136,13 @@ __device__ __forceinline__ void cp_bf16_block(
     int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy,
     uint16_t* __restrict__ Xs, uint16_t* __restrict__ XsT, uint16_t* __restrict__ SsT,
     int* __restrict__ wave_kept) {
-  typedef Bf16Shape<DQ, KQ, NW> Sh;
+  typedef Bf16Shape<DQ, KQ, NW, TR> Sh;
+  static_assert(TR % 32 == 0, "tile rows: a multiple of the 32-row MFMA step");
   constexpr bool kCp = MODE != kWhitenOnly;
   constexpr int kThreads = NW * 64;
   constexpr int RPW = 64 / G;
   constexpr int RPB = NW * RPW;
-  constexpr int PASSES = (kTile + RPB - 1) / RPB;
+  constexpr int PASSES = (TR + RPB - 1) / RPB;
   constexpr int SLOTS = G >= kNB ? 1 : kNB / G;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
@@ -151,7 +154,7 @@ __device__ __forceinline__ void cp_bf16_block(
   if (kCp) {
     for (int e = blk * kThreads + tid; e < D * K; e += nblk * kThreads)
       phi_copy[e] = Phi[e];
-    for (int e = tid; e < kTile * Sh::LDA; e += kThreads) Xs[e] = 0;
+    for (int e = tid; e < TR * Sh::LDA; e += kThreads) Xs[e] = 0;
     for (int e = tid; e < DQ * Sh::LDT; e += kThreads) XsT[e] = 0;
   }
   // Phi fragments: bphi[q][ks] holds Phi[32 ks + 8 l4 + i][16 ct + l16], i = 0..7
@@ -182,15 +185,15 @@ __device__ __forceinline__ void cp_bf16_block(
   for (int i = 0; i < 8; ++i) mw[i] = MODE == kFromX ? 0.f : mw16[c8 + i];
   int kept_total = 0;
 
-  const int ntiles = (n_rows + kTile - 1) / kTile;
+  const int ntiles = (n_rows + TR - 1) / TR;
   for (int tile = blk; tile < ntiles; tile += nblk) {
     if (kCp) __syncthreads();
     // ---- 1. rows of the tile ----
 #pragma unroll 1
     for (int pass = 0; pass < PASSES; ++pass) {
       const int lr = pass * RPB + wave * RPW + lane / G;
-      const int row = tile * kTile + lr;
-      const bool valid = lr < kTile && row < n_rows;
+      const int row = tile * TR + lr;
+      const bool valid = lr < TR && row < n_rows;
       float x[8];
       int kept = 0;
       if (MODE == kFromX) {
@@ -296,14 +299,14 @@ __device__ __forceinline__ void cp_bf16_block(
       if (kCp) {
         const u32x4 hp = u32x4{pack_bf16(x[0], x[1]), pack_bf16(x[2], x[3]),
                                pack_bf16(x[4], x[5]), pack_bf16(x[6], x[7])};
-        if (lr < kTile) *reinterpret_cast<u32x4*>(Xs + lr * Sh::LDA + c8) = hp;
+        if (lr < TR) *reinterpret_cast<u32x4*>(Xs + lr * Sh::LDA + c8) = hp;
         // column-major copy: the even document of each pair writes both
         // documents' values of a column as one 32-bit word
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const uint32_t mine = hp[i];
           const uint32_t other = __shfl_down(mine, G, 64);
-          if (pair_lo && lr < kTile) {
+          if (pair_lo && lr < TR) {
             *reinterpret_cast<uint32_t*>(XsT + (c8 + 2 * i) * Sh::LDT + lr) =
                 (mine & 0xffffu) | (other << 16);
             *reinterpret_cast<uint32_t*>(XsT + (c8 + 2 * i + 1) * Sh::LDT + lr) =
@@ -320,7 +323,7 @@ __device__ __forceinline__ void cp_bf16_block(
       const int ct = wave + NW * q;
       if (ct < Sh::NCT) {
 #pragma unroll
-        for (int rt = 0; rt < kTile / 16; ++rt) {
+        for (int rt = 0; rt < TR / 16; ++rt) {
           floatx4 s = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int ks = 0; ks < Sh::NKS; ++ks) {
@@ -337,7 +340,7 @@ __device__ __forceinline__ void cp_bf16_block(
     // ---- 3. R1 += X^T S^2 ----
     const int wd = wave % Sh::WD, wk = wave / Sh::WD;
 #pragma unroll
-    for (int kk = 0; kk < kTile / 32; ++kk) {
+    for (int kk = 0; kk < TR / 32; ++kk) {
       u32x4 av[Sh::TDW];
 #pragma unroll
       for (int a = 0; a < Sh::TDW; ++a)
@@ -409,22 +412,25 @@ __global__ void __launch_bounds__(64 * (MODE == kWhitenOnly ? 4 : bf16_waves(DQ,
 // Several batches (the slices of a batched run, each with its own
 // whitening, D, K and Phi) in one launch: block b serves slice blk_slice[b],
 // as block b - blk0 of that slice's nblk blocks.  One LDS allocation of the
-// largest shape (D, K <= 64) serves every slice.
-__global__ void __launch_bounds__(kThreads, 3) k_cp_bf16_multi(const SliceStep* __restrict__ sl,
-                                                               const int* __restrict__ blk_slice) {
-  constexpr int LDA = 64 + 8, LDT = kTile + 8;
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[kTile * LDA];
+// largest shape (D, K <= 64) serves every slice.  Tile shape: TR documents
+// per row tile, NW waves per block (the plan's autotuner picks among the
+// instances below).
+template <int TR, int NW>
+__global__ void __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) k_cp_bf16_multi(
+    const SliceStep* __restrict__ sl, const int* __restrict__ blk_slice) {
+  constexpr int LDA = 64 + 8, LDT = TR + 8;
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[TR * LDA];
   __shared__ __attribute__((aligned(16))) uint16_t XsT[64 * LDT];
   __shared__ __attribute__((aligned(16))) uint16_t SsT[64 * LDT];
-  __shared__ int wave_kept[4];
+  __shared__ int wave_kept[NW];
   const SliceStep& d = sl[blk_slice[blockIdx.x]];
   const int blk = blockIdx.x - d.blk0;
 #define TLDA_MULTI(DQ_, KQ_, G_)                                                               \
   case multi_shape_id(DQ_, KQ_, G_):                                                           \
-    cp_bf16_block<DQ_, KQ_, G_, kFused, 4>(blk, d.nblk, d.row_ptr, d.col_idx, d.val, d.n_rows,    \
-                                        d.W16, d.mw16, d.Dh, nullptr, d.D, d.Phi, d.K,         \
-                                        d.partial, d.block_counts, nullptr, d.phi_copy, Xs,    \
-                                        XsT, SsT, wave_kept);                                  \
+    cp_bf16_block<DQ_, KQ_, G_, kFused, NW, TR>(blk, d.nblk, d.row_ptr, d.col_idx, d.val,       \
+                                               d.n_rows, d.W16, d.mw16, d.Dh, nullptr, d.D,    \
+                                               d.Phi, d.K, d.partial, d.block_counts, nullptr, \
+                                               d.phi_copy, Xs, XsT, SsT, wave_kept);            \
     break;
   switch (d.shape) {
     TLDA_MULTI(32, 16, 1) TLDA_MULTI(32, 16, 2) TLDA_MULTI(32, 16, 4)
@@ -507,14 +513,14 @@ hipError_t dispatch(int mode, const Bf16Args& a, int* per_cu, hipStream_t s) {
       default: return launch_t<32, 16, 16, kWhitenOnly>(a, per_cu, s);
     }
   }
-#define TLDA_BF16(DQ_, KQ_)                                                        \
+#define TLDA_BF16_SHAPE(DQ_, KQ_)                                                        \
   if (dq == DQ_ && kq == KQ_)                                                      \
     return mode == kFused ? launch_g<DQ_, KQ_, kFused>(G, a, per_cu, s)            \
                           : launch_g<DQ_, KQ_, kFromX>(G, a, per_cu, s);
-#define TLDA_BF16_ROW(DQ_) TLDA_BF16(DQ_, 16) TLDA_BF16(DQ_, 32) TLDA_BF16(DQ_, 64) TLDA_BF16(DQ_, 128)
+#define TLDA_BF16_ROW(DQ_) TLDA_BF16_SHAPE(DQ_, 16) TLDA_BF16_SHAPE(DQ_, 32) TLDA_BF16_SHAPE(DQ_, 64) TLDA_BF16_SHAPE(DQ_, 128)
   TLDA_BF16_ROW(32) TLDA_BF16_ROW(64) TLDA_BF16_ROW(128)
 #undef TLDA_BF16_ROW
-#undef TLDA_BF16
+#undef TLDA_BF16_SHAPE
   return hipErrorInvalidValue;
 }
 
@@ -528,19 +534,34 @@ int multi_shape(int D, int K) {
   return multi_shape_id(dq, kq, bf16_cols_(D) / 8);
 }
 
-int cp_bf16_multi_per_cu() {
+// Tile shapes of the multi-slice kernel: (rows per tile, waves per block).
+constexpr int kMultiShapes[kMultiTiles][2] = {{64, 4}, {32, 4}, {64, 8}};
+
+int multi_tile_rows(int v) { return kMultiShapes[v][0]; }
+int multi_tile_waves(int v) { return kMultiShapes[v][1]; }
+
+int cp_bf16_multi_per_cu(int v) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cp_bf16_multi, kThreads, 0) !=
-          hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
+  hipError_t e = hipErrorInvalidValue;
+  switch (v) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cp_bf16_multi<64, 4>, 256, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cp_bf16_multi<32, 4>, 256, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cp_bf16_multi<64, 8>, 512, 0); break;
+    default: break;
+  }
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
   return per_cu;
 }
 
-hipError_t launch_cp_bf16_multi(const SliceStep* sl, const int* blk_slice, int n_blocks,
+hipError_t launch_cp_bf16_multi(const SliceStep* sl, const int* blk_slice, int n_blocks, int v,
                                 hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cp_bf16_multi, dim3(n_blocks), dim3(kThreads), 0, s, sl, blk_slice);
+  switch (v) {
+    case 0: hipLaunchKernelGGL((k_cp_bf16_multi<64, 4>), dim3(n_blocks), dim3(256), 0, s, sl, blk_slice); break;
+    case 1: hipLaunchKernelGGL((k_cp_bf16_multi<32, 4>), dim3(n_blocks), dim3(256), 0, s, sl, blk_slice); break;
+    case 2: hipLaunchKernelGGL((k_cp_bf16_multi<64, 8>), dim3(n_blocks), dim3(512), 0, s, sl, blk_slice); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "tlda_internal.h"
@@ -1264,7 +1265,8 @@ struct tlda_multi {
   int num_cu = 0;
   std::vector<tlda_ctx*> ctxs;
   std::vector<tlda::SliceStep> host;   // table without the block layout
-  std::vector<int> tiles;
+  std::vector<int> rows;               // documents of each slice's batch
+  int tile = 0;                        // tile shape of the reduction (0 .. kMultiTiles - 1)
   tlda::SliceStep* d_table = nullptr;
   int* d_blk_slice = nullptr;
   int* d_fin_slice = nullptr;
@@ -1292,20 +1294,26 @@ void multi_free(tlda_multi* m) {
 }
 
 // Lay out total_blocks reduction blocks over the slices in proportion to
-// their row tiles (at least one each, at most one per tile), and the finish
-// blocks; upload the tables (synchronous, never inside a capture).
+// their row tiles of the plan's tile shape (at least one each, at most one
+// per tile), and the finish blocks; upload the tables (synchronous, never
+// inside a capture).
 tlda_status multi_layout(tlda_multi* m, int total_blocks) {
+  const int tr = tlda::multi_tile_rows(m->tile);
+  std::vector<int> tiles(m->n);
   long long all_tiles = 0;
-  for (int t : m->tiles) all_tiles += t;
-  if (total_blocks <= 0) total_blocks = tlda::cp_bf16_multi_per_cu() * m->num_cu;
+  for (int i = 0; i < m->n; ++i) {
+    tiles[i] = (m->rows[i] + tr - 1) / tr;
+    all_tiles += tiles[i];
+  }
+  if (total_blocks <= 0) total_blocks = tlda::cp_bf16_multi_per_cu(m->tile) * m->num_cu;
   std::vector<tlda::SliceStep> tab = m->host;
   std::vector<int> blk_slice, fin_slice;
   size_t need_p = 0, need_c = 0;
   int max_dk = 1;
   for (int i = 0; i < m->n; ++i) {
     tlda::SliceStep& d = tab[i];
-    long long want = all_tiles > 0 ? (long long)((double)total_blocks * m->tiles[i] / all_tiles + 0.5) : 1;
-    int nb = (int)std::max<long long>(1, std::min<long long>(want, std::max(1, m->tiles[i])));
+    long long want = all_tiles > 0 ? (long long)((double)total_blocks * tiles[i] / all_tiles + 0.5) : 1;
+    int nb = (int)std::max<long long>(1, std::min<long long>(want, std::max(1, tiles[i])));
     d.nblk = nb;
     d.blk0 = (int)blk_slice.size();
     for (int b = 0; b < nb; ++b) blk_slice.push_back(i);
@@ -1417,7 +1425,7 @@ tlda_status tlda_multi_create(int32_t n_slices, tlda_ctx* const* ctxs,
     d.theta = c->cfg.theta;
     d.beta = betas[i];
     m->host.push_back(d);
-    m->tiles.push_back((b.n_rows + 63) / 64);
+    m->rows.push_back(b.n_rows);
   }
   if (dalloc(&m->d_table, (size_t)n_slices) != hipSuccess) {
     multi_free(m);
@@ -1445,6 +1453,28 @@ tlda_status tlda_multi_set_blocks(tlda_multi* m, int32_t total_blocks) {
   return multi_layout(m, total_blocks);
 }
 
+tlda_status tlda_multi_set_tile(tlda_multi* m, int32_t rows_per_tile, int32_t waves_per_block) {
+  if (!m) return TLDA_ERR_ARG;
+  int v = -1;
+  for (int i = 0; i < tlda::kMultiTiles; ++i)
+    if (tlda::multi_tile_rows(i) == rows_per_tile && tlda::multi_tile_waves(i) == waves_per_block)
+      v = i;
+  MLP_CHECK(m, v >= 0, TLDA_ERR_ARG, "tile shape must be 64 x 4, 32 x 4 or 64 x 8");
+  const int prev = m->tile;
+  m->tile = v;
+  tlda_status st = multi_layout(m, 0);
+  if (st != TLDA_OK) m->tile = prev;
+  return st;
+}
+
+tlda_status tlda_multi_get_tile(const tlda_multi* m, int32_t* rows_per_tile,
+                                int32_t* waves_per_block) {
+  if (!m || !rows_per_tile || !waves_per_block) return TLDA_ERR_ARG;
+  *rows_per_tile = tlda::multi_tile_rows(m->tile);
+  *waves_per_block = tlda::multi_tile_waves(m->tile);
+  return TLDA_OK;
+}
+
 tlda_status tlda_multi_get_blocks(const tlda_multi* m, int32_t* total_blocks) {
   if (!m || !total_blocks) return TLDA_ERR_ARG;
   *total_blocks = m->total_blocks;
@@ -1453,7 +1483,8 @@ tlda_status tlda_multi_get_blocks(const tlda_multi* m, int32_t* total_blocks) {
 
 tlda_status tlda_multi_step(tlda_multi* m) {
   if (!m) return TLDA_ERR_ARG;
-  MLP_OK(m, tlda::launch_cp_bf16_multi(m->d_table, m->d_blk_slice, m->n_blocks, m->stream));
+  MLP_OK(m, tlda::launch_cp_bf16_multi(m->d_table, m->d_blk_slice, m->n_blocks, m->tile,
+                                       m->stream));
   MLP_OK(m, tlda::launch_cp_finish_multi(m->d_table, m->d_fin_slice, m->n_fin, m->max_dk,
                                          m->stream));
   return TLDA_OK;
@@ -1486,19 +1517,25 @@ tlda_status tlda_multi_autotune(tlda_multi* m, int32_t reps, int32_t* total_bloc
     }
     return hipSuccess;
   };
-  const int per_cu = tlda::cp_bf16_multi_per_cu();
-  std::vector<int> cands;
-  for (int b = 1; b <= per_cu; ++b) cands.push_back(b * m->num_cu);
-  cands.push_back(2 * per_cu * m->num_cu);
+  // candidates: every tile shape with 1, 2, ... resident blocks per CU and
+  // two full rounds
+  std::vector<std::pair<int, int>> cands;   // (tile shape, total blocks)
+  for (int v = 0; v < tlda::kMultiTiles; ++v) {
+    const int per_cu = tlda::cp_bf16_multi_per_cu(v);
+    for (int b = 1; b <= per_cu; ++b) cands.push_back({v, b * m->num_cu});
+    cands.push_back({v, 2 * per_cu * m->num_cu});
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   tlda_status st = TLDA_OK;
-  int best = cands.back();
+  std::pair<int, int> best = cands.front();
   float best_ms = 0.f;
+  const int tile_entry = m->tile;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     st = TLDA_ERR_DEVICE;
   } else {
-    for (int cand : cands) {
-      st = multi_layout(m, cand);
+    for (const auto& cand : cands) {
+      m->tile = cand.first;
+      st = multi_layout(m, cand.second);
       if (st != TLDA_OK) break;
       if ((st = tlda_multi_step(m)) != TLDA_OK) break;   // warm-up
       hipEventRecord(e0, m->stream);
@@ -1522,11 +1559,12 @@ tlda_status tlda_multi_autotune(tlda_multi* m, int32_t reps, int32_t* total_bloc
   }
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);
-  if (st == TLDA_OK) st = multi_layout(m, best);
+  m->tile = st == TLDA_OK ? best.first : tile_entry;
+  if (st == TLDA_OK) st = multi_layout(m, best.second);
   if (restore() != hipSuccess || hipStreamSynchronize(m->stream) != hipSuccess)
     st = st == TLDA_OK ? TLDA_ERR_DEVICE : st;
   release();
-  if (st == TLDA_OK && total_blocks_out) *total_blocks_out = best;
+  if (st == TLDA_OK && total_blocks_out) *total_blocks_out = best.second;
   return st;
 }
 

@@ -343,12 +343,17 @@ int cp_num_blocks(int n_rows, int D, int K, int max_blocks);
 hipError_t launch_sum_counts(const int* block_counts, int n, int* out, hipStream_t s);
 // multi-slice step: reduction over every slice's batch, then every slice's finish
 // (sl: device table; blk_slice [n_blocks], fin_slice [n_fin]: slice of each block)
-hipError_t launch_cp_bf16_multi(const SliceStep* sl, const int* blk_slice, int n_blocks,
+// v: tile shape of the multi-slice kernel, 0 .. kMultiTiles - 1 (rows per
+// tile multi_tile_rows(v), waves per block multi_tile_waves(v))
+constexpr int kMultiTiles = 3;
+int multi_tile_rows(int v);
+int multi_tile_waves(int v);
+hipError_t launch_cp_bf16_multi(const SliceStep* sl, const int* blk_slice, int n_blocks, int v,
                                 hipStream_t s);
 hipError_t launch_cp_finish_multi(const SliceStep* sl, const int* fin_slice, int n_fin,
                                   int max_dk, hipStream_t s);
 int multi_shape(int D, int K);            // shape id of the multi kernel for D, K <= 64, else -1
-int cp_bf16_multi_per_cu();               // resident blocks of the multi kernel per CU
+int cp_bf16_multi_per_cu(int v);          // resident blocks of the multi kernel per CU
 constexpr int kFinishEntries = 16;        // entries of D x K per finish block
 // BF16 path (D, K <= 128)
 int bf16_cols(int D);

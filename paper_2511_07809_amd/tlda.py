@@ -45,7 +45,8 @@ EXPORTED = ("tlda_create", "tlda_destroy", "tlda_status_str", "tlda_last_error",
             "tlda_mlp_set_params", "tlda_mlp_get_params", "tlda_mlp_forward",
             "tlda_mlp_gradients", "tlda_mlp_train_step", "tlda_infer_doc_topics_mlp",
             "tlda_multi_create", "tlda_multi_destroy", "tlda_multi_last_error",
-            "tlda_multi_set_blocks", "tlda_multi_get_blocks", "tlda_multi_step",
+            "tlda_multi_set_blocks", "tlda_multi_get_blocks", "tlda_multi_set_tile",
+            "tlda_multi_get_tile", "tlda_multi_step",
             "tlda_multi_autotune", "tlda_graph_capture", "tlda_graph_capture_steps",
             "tlda_graph_launch",
             "tlda_graph_destroy")
@@ -105,6 +106,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tlda_multi_last_error": ([vp], ctypes.c_char_p),
         "tlda_multi_set_blocks": ([vp, i32], i32),
         "tlda_multi_get_blocks": ([vp, ctypes.POINTER(i32)], i32),
+        "tlda_multi_set_tile": ([vp, i32, i32], i32),
+        "tlda_multi_get_tile": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "tlda_multi_step": ([vp], i32),
         "tlda_multi_autotune": ([vp, i32, ctypes.POINTER(i32)], i32),
         "tlda_graph_capture": ([ctypes.POINTER(vp), i32, ctypes.POINTER(vp)], i32),
@@ -568,6 +571,16 @@ def tlda_multi_get_blocks(p: Multi) -> int:
     v = ctypes.c_int32(0)
     _check_multi(p, _LIB.tlda_multi_get_blocks(p.handle, ctypes.byref(v)))
     return int(v.value)
+
+
+def tlda_multi_set_tile(p: Multi, rows_per_tile: int, waves_per_block: int) -> None:
+    _check_multi(p, _LIB.tlda_multi_set_tile(p.handle, rows_per_tile, waves_per_block))
+
+
+def tlda_multi_get_tile(p: Multi):
+    r, w = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check_multi(p, _LIB.tlda_multi_get_tile(p.handle, ctypes.byref(r), ctypes.byref(w)))
+    return int(r.value), int(w.value)
 
 
 def tlda_multi_step(p: Multi) -> None:

@@ -103,7 +103,8 @@ def test_multi_step_matches_single_slice_steps(side_stream):
 SHAPE_CLASSES = [(D, K) for D in (5, 12, 30, 50) for K in (10, 20, 50)]
 
 
-def test_multi_step_matches_oracle_in_every_shape_class(side_stream):
+@pytest.mark.parametrize("tile", [(64, 4), (32, 4), (64, 8)])
+def test_multi_step_matches_oracle_in_every_shape_class(side_stream, tile):
     """One multi-slice step over twelve slices (every shape class the
     persistent kernel dispatches on) plus an empty slice, each against the
     oracle's gradient of its own batch whitened by its own W16 = bf16(W),
@@ -135,6 +136,8 @@ def test_multi_step_matches_oracle_in_every_shape_class(side_stream):
     nk = torch.full((len(ctxs),), -1, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
     plan = tl.tlda_multi_create(ctxs, batches, Ps, betas, nk)
+    tl.tlda_multi_set_tile(plan, *tile)
+    assert tl.tlda_multi_get_tile(plan) == tile
     tl.tlda_multi_step(plan)
     side_stream.synchronize()
     for i, ((D, K, n), (rp, ci, va), (W, m), (a0, theta)) in enumerate(
@@ -158,16 +161,24 @@ def test_autotune_restores_phi_and_chooses_a_valid_shape(side_stream):
     torch.cuda.synchronize()
     plan = tl.tlda_multi_create(ctxs, batches, Ps, [2e-3] * len(ctxs))
     default = tl.tlda_multi_get_blocks(plan)
+    assert tl.tlda_multi_get_tile(plan) == (64, 4)
     best = tl.tlda_multi_autotune(plan, 2)
     assert best > 0 and tl.tlda_multi_get_blocks(plan) == best
+    best_tile = tl.tlda_multi_get_tile(plan)
+    assert best_tile in ((64, 4), (32, 4), (64, 8))
+    with pytest.raises(tl.TldaError) as e:
+        tl.tlda_multi_set_tile(plan, 48, 4)
+    assert e.value.status == 1
+    assert tl.tlda_multi_get_tile(plan) == best_tile
     for P, p0 in zip(Ps, phis0):
         assert torch.equal(P.cpu(), torch.from_numpy(p0))
-    # every launch shape gives the same step up to the partial-sum order
+    # every tile and launch shape gives the same step up to the partial-sum order
     outs = []
-    for blocks in (default, best, 37):
+    for tile, blocks in (((64, 4), default), (best_tile, best), ((32, 4), 37), ((64, 8), 37)):
         for P, p0 in zip(Ps, phis0):
             P.copy_(torch.from_numpy(p0).cuda())
         torch.cuda.synchronize()
+        tl.tlda_multi_set_tile(plan, *tile)
         tl.tlda_multi_set_blocks(plan, blocks)
         tl.tlda_multi_step(plan)
         side_stream.synchronize()
