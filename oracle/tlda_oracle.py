@@ -505,7 +505,7 @@ def classic_second_moment(batches, m: np.ndarray, N: int, alpha0: float) -> np.n
 
 
 def classic_data_term(row_ptr, col_idx, val, V: int, m: np.ndarray, W: np.ndarray,
-                      Phi: np.ndarray, alpha0: float) -> tuple:
+                      Phi: np.ndarray, alpha0: float, Z: np.ndarray = None) -> tuple:
     """Sum over the batch's kept documents of M3_d(W, W, W)(I, phi_k, phi_k),
     column k, with M3_d = c3 P3_d - c2 (P2_d x M1 + its two permutations) +
     alpha0^2 M1^3 the per-document piece of the appendix's M3 (c2 =
@@ -514,11 +514,16 @@ def classic_data_term(row_ptr, col_idx, val, V: int, m: np.ndarray, W: np.ndarra
     r = (W^T M1).phi, l2 = 1/(L(L-1)), l3 = 1/(L(L-1)(L-2)):
       c3 l3 (y s^2 - 2 s g - y q + 2 h) - c2 l2 (2 r (y s - g) + m_w (s^2 - q))
       + alpha0^2 m_w r^2.
+    Z, if given, replaces the per-word scores W Phi (V x K) wherever a word's
+    score enters: in g, q, h and in s = sum_w c_w z_w (equal to y.phi when
+    Z = W Phi); a test evaluates the term on rounded scores this way.
     Returns (D x K sum, number of kept documents)."""
     st = batch_stats(row_ptr, col_idx, val, V)
     c3 = _c3(alpha0)
     c2 = alpha0 * (alpha0 + 1.0) / 2.0
-    Z = W @ Phi
+    given = Z is not None
+    if not given:
+        Z = W @ Phi
     mw = W.T @ m
     r = mw @ Phi
     out = np.zeros(Phi.shape)
@@ -531,7 +536,7 @@ def classic_data_term(row_ptr, col_idx, val, V: int, m: np.ndarray, W: np.ndarra
         l3 = l2 / (L - 2.0)
         Wd, Zd = W[cols], Z[cols]                 # rows of the document's words
         y = Wd.T @ cnt
-        s = y @ Phi
+        s = cnt @ Zd if given else y @ Phi
         g = Wd.T @ (cnt[:, None] * Zd)
         q = cnt @ (Zd * Zd)
         h = Wd.T @ (cnt[:, None] * Zd * Zd)

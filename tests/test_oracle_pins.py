@@ -418,6 +418,11 @@ def test_classic_data_term_equals_the_explicit_whitened_contraction():
     expl = n * np.stack([np.einsum("ijk,j,k->i", T, Phi[:, k], Phi[:, k]) for k in range(K)],
                         axis=1)
     np.testing.assert_allclose(data, expl, rtol=1e-11, atol=1e-11 * np.abs(expl).max())
+    # the same with the word scores passed in (s summed from the scores)
+    data_z, n_z = O.classic_data_term(c.indptr, c.indices, c.data, spec.V, M1, W, Phi,
+                                      spec.alpha0, Z=W @ Phi)
+    assert n_z == n
+    np.testing.assert_allclose(data_z, expl, rtol=1e-11, atol=1e-11 * np.abs(expl).max())
 
 
 def test_classic_gradient_is_the_derivative_of_its_objective():
