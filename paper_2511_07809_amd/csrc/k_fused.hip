@@ -262,9 +262,9 @@ template <int DQ, int KQ>
 __global__ void __launch_bounds__(512, wide_min_waves(DQ, KQ)) k_whiten_cp_wide(
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const float* __restrict__ val, int n_rows, const float* __restrict__ W32,
-    const float* __restrict__ mw32, int D, int Dp, const float* __restrict__ Phi, int K,
-    int nblk, float* __restrict__ partial, int* __restrict__ block_counts,
-    float* __restrict__ Xout, float* __restrict__ phi_copy) {
+    const float* __restrict__ mw32, int D, int Dp, int Dt, uint32_t tail_base,
+    const float* __restrict__ Phi, int K, int nblk, float* __restrict__ partial,
+    int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy) {
   constexpr int NW = 8, kThreads = 512;
   constexpr int T = 32, G = 32, RPW = 2, RPB = NW * RPW, PASSES = T / RPB;
   constexpr int NB = 8;                    // nonzeros per gather step
@@ -283,6 +283,14 @@ __global__ void __launch_bounds__(512, wide_min_waves(DQ, KQ)) k_whiten_cp_wide(
   const bool active = c4 < D;              // lane's float4 holds real W columns
   const bool in_lds = c4 < DQ;             // its columns exist in the LDS tile
   const bool owner = wave < NCT;           // wave owns column tile `wave` of S and R1
+  // A row's gather reads its whole 128-byte lines from the row itself and
+  // the rest (Dt columns) from the compact tail copy, so that a row of
+  // D = 100 costs three lines and a sixteenth of a shared one instead of
+  // four; lanes past D read the row's first float4 (a line already read).
+  const int Dm = Dt > 0 ? D / 32 * 32 : Dp;
+  const bool tail_lane = active && c4 >= Dm;
+  const uint32_t gmul = tail_lane ? (uint32_t)Dt : (uint32_t)Dp;
+  const uint32_t gadd = !active ? 0u : tail_lane ? tail_base + (uint32_t)(c4 - Dm) : (uint32_t)c4;
 
   for (int e = blockIdx.x * kThreads + tid; e < D * K; e += nblk * kThreads) phi_copy[e] = Phi[e];
   // Phi into LDS, zero padded (first read after the first tile's barrier).
@@ -362,8 +370,9 @@ __global__ void __launch_bounds__(512, wide_min_waves(DQ, KQ)) k_whiten_cp_wide(
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
           const int c = __shfl(c_cur, (t0 + t) & (G - 1), G);
-          // 32-bit element offset from the kernel's (uniform) base: V Dp < 2^31
-          const uint32_t off = (uint32_t)c * (uint32_t)Dp + (uint32_t)(active ? c4 : 0);
+          // 32-bit element offset from the kernel's (uniform) base:
+          // V (Dp + Dt) < 2^31
+          const uint32_t off = (uint32_t)c * gmul + gadd;
           w[t] = *reinterpret_cast<const float4*>(W32 + off);
         }
 #pragma unroll
@@ -461,8 +470,9 @@ __global__ void __launch_bounds__(512, wide_min_waves(DQ, KQ)) k_whiten_cp_wide(
 
 template <int DQ, int KQ>
 hipError_t launch_wide(const tlda_csr_batch& b, const float* W32, const float* mw32, int D, int Dp,
-                       const float* Phi, int K, int nblk, float* partial, int* block_counts,
-                       float* Xout, float* phi_copy, hipStream_t s) {
+                       int Dt, uint32_t tail_base, const float* Phi, int K, int nblk,
+                       float* partial, int* block_counts, float* Xout, float* phi_copy,
+                       hipStream_t s) {
   if (partial == nullptr) {   // occupancy query: resident blocks per CU in nblk's place
     int per_cu = 0;
     hipError_t e =
@@ -475,7 +485,8 @@ hipError_t launch_wide(const tlda_csr_batch& b, const float* W32, const float* m
   const int32_t* ci = b.nnz > 0 ? b.col_idx : b.row_ptr;
   const float* va = b.nnz > 0 ? b.val : reinterpret_cast<const float*>(b.row_ptr);
   launch_main(k_whiten_cp_wide<DQ, KQ>, dim3(nblk), dim3(512), 0, s, b.row_ptr, ci, va, b.n_rows,
-              W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts, Xout, phi_copy);
+              W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial, block_counts, Xout,
+              phi_copy);
   return hipGetLastError();
 }
 
@@ -523,9 +534,38 @@ int fused_tile_rows(int D, int K) {
   return (mfma_bucket(D) > 64 || mfma_bucket(K) > 64) ? 32 : cp_mfma_tile_rows(D, K);   // wide: T
 }
 
+int w32_tail_cols(int D, int K) {
+  if (fused_tile_rows(D, K) != 32 || D < 32) return 0;   // only the wide kernel reads it
+  const int rem = D % 32;
+  return rem >= 1 && rem <= 8 ? (rem + 3) / 4 * 4 : 0;
+}
+
+namespace {
+__global__ void k_w32_tail(float* __restrict__ W32, int V, int Dm, int Dp, int Dt,
+                           uint32_t tail_base) {
+  const size_t n = (size_t)V * Dt;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t w = e / Dt, j = e % Dt;
+    W32[tail_base + e] = W32[w * Dp + Dm + j];
+  }
+}
+}  // namespace
+
+hipError_t launch_w32_tail(float* W32, int V, int D, int Dp, int Dt, uint32_t tail_base,
+                           hipStream_t s) {
+  if (Dt <= 0) return hipSuccess;
+  const size_t n = (size_t)V * Dt;
+  const int grid = (int)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_w32_tail, dim3(grid), dim3(256), 0, s, W32, V, D / 32 * 32, Dp, Dt,
+                     tail_base);
+  return hipGetLastError();
+}
+
 hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
-                            int Dp, const float* Phi, int K, int nblk, float* partial,
-                            int* block_counts, float* Xout, float* phi_copy, hipStream_t s) {
+                            int Dp, int Dt, uint32_t tail_base, const float* Phi, int K,
+                            int nblk, float* partial, int* block_counts, float* Xout,
+                            float* phi_copy, hipStream_t s) {
   const int dq = mfma_bucket(D), kq = mfma_bucket(K);
   const int T = fused_tile_rows(D, K);
   int G = Dp / 4;   // lanes per document: Dp is 4, 8, 16, 32 or 64 here
@@ -544,8 +584,8 @@ hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const flo
   // wide shapes: 32 lanes per document (one float4 of up to 128 columns each)
 #define TLDA_WIDE(DQ_, KQ_)                                                                    \
   if (dq == DQ_ && kq == KQ_)                                                                  \
-    return launch_wide<DQ_, KQ_>(b, W32, mw32, D, Dp, Phi, K, nblk, partial, block_counts,     \
-                                 Xout, phi_copy, s);
+    return launch_wide<DQ_, KQ_>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,   \
+                                 block_counts, Xout, phi_copy, s);
 #define TLDA_WIDE_ROW(DQ_) \
   TLDA_WIDE(DQ_, 16) TLDA_WIDE(DQ_, 32) TLDA_WIDE(DQ_, 64) TLDA_WIDE(DQ_, 112) TLDA_WIDE(DQ_, 128)
   TLDA_WIDE(16, 112) TLDA_WIDE(16, 128) TLDA_WIDE(32, 112) TLDA_WIDE(32, 128)

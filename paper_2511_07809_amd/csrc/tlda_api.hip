@@ -96,6 +96,8 @@ namespace {
 
 bool is_bf16(const tlda_ctx* c) { return (c->cfg.flags & TLDA_BF16) != 0; }
 bool is_classic(const tlda_ctx* c) { return (c->cfg.flags & TLDA_CLASSIC) != 0; }
+// W32's tail copy starts right after its V x Dp rows.
+uint32_t w32_tail_base(const tlda_ctx* c) { return (uint32_t)((size_t)c->cfg.V * c->Dp); }
 
 // FP32 (and, in BF16 contexts, BF16) gather copies of W and their mean
 // projections, from U, eig and M1.
@@ -103,6 +105,8 @@ hipError_t form_whitening(tlda_ctx* c) {
   const int V = c->cfg.V, D = c->cfg.D;
   hipError_t e = tlda::launch_form_whitening(c->wh.U, c->wh.eig, c->wh.m, V, D, c->Dp, c->wh.W,
                                              c->wh.W32, c->wh.mw32, c->stream);
+  if (e == hipSuccess)
+    e = tlda::launch_w32_tail(c->wh.W32, V, D, c->Dp, c->Dt, w32_tail_base(c), c->stream);
   if (e != hipSuccess || !is_bf16(c)) return e;
   return tlda::launch_form_w16(c->wh.W, c->wh.m, V, D, c->Dh, c->wh.W16, c->wh.mw16, c->stream);
 }
@@ -431,7 +435,8 @@ tlda_status fused_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float* 
     const int ntiles = (b->n_rows + T - 1) / T;
     if (c->tune.fused_blocks <= 0) {
       int per_cu = 0;
-      HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, Phi, K, 0, nullptr,
+      HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, c->Dt,
+                                       w32_tail_base(c), Phi, K, 0, nullptr,
                                        &per_cu, nullptr, nullptr, c->stream));
       c->tune.fused_blocks = (per_cu > 0 ? per_cu : 1) * c->num_cu;
     }
@@ -455,8 +460,9 @@ tlda_status fused_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float* 
                                           partial, c->block_counts, X_out, c->cp.phi0,
                                           c->stream));
   else
-    HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, Phi, K, nblk, partial,
-                                     c->block_counts, X_out, c->cp.phi0, c->stream));
+    HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, c->Dt, w32_tail_base(c),
+                                     Phi, K, nblk, partial, c->block_counts, X_out, c->cp.phi0,
+                                     c->stream));
   HIP_OK(c, timing_stop(c));
   st = end_use(c, b);
   if (st != TLDA_OK) return st;
@@ -615,6 +621,8 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
   ctx->cfg = c;
   ctx->Dp = tlda::padded_d(c.D);
   ctx->Dh = tlda::bf16_cols(c.D);
+  if (!(c.flags & (TLDA_BF16 | TLDA_CLASSIC)) && std::getenv("TLDA_TUNE_NO_W32_TAIL") == nullptr)
+    ctx->Dt = tlda::w32_tail_cols(c.D, c.K);
   auto env_int = [](const char* name) {
     const char* v = std::getenv(name);
     return v ? std::atoi(v) : 0;
@@ -652,7 +660,7 @@ tlda_status tlda_create(const tlda_config* cfg, void* hip_stream, tlda_ctx** out
             dalloc(&ctx->mom.fsum, 2 * V) == hipSuccess && dalloc(&ctx->wh.W, V * D) == hipSuccess &&
             dalloc(&ctx->wh.U, V * D) == hipSuccess && dalloc(&ctx->wh.eig, D) == hipSuccess &&
             dalloc(&ctx->wh.m, V) == hipSuccess &&
-            dalloc(&ctx->wh.W32, V * (size_t)ctx->Dp) == hipSuccess &&
+            dalloc(&ctx->wh.W32, V * (size_t)(ctx->Dp + ctx->Dt)) == hipSuccess &&
             dalloc(&ctx->wh.mw32, (size_t)ctx->Dp) == hipSuccess &&
             dalloc(&ctx->cp.R1, D * K) == hipSuccess && dalloc(&ctx->cp.phi0, D * K) == hipSuccess &&
             dalloc(&ctx->cp.gsq, (size_t)K * K) == hipSuccess &&
@@ -1628,7 +1636,8 @@ tlda_status tlda_graph_capture_steps(tlda_ctx* c, const tlda_csr_batch* batches,
   } else {
     if (c->tune.fused_blocks <= 0) {
       int per_cu = 0;
-      HIP_OK(c, tlda::launch_whiten_cp(batches[0], c->wh.W32, c->wh.mw32, D, c->Dp, Phi, K, 0,
+      HIP_OK(c, tlda::launch_whiten_cp(batches[0], c->wh.W32, c->wh.mw32, D, c->Dp, c->Dt,
+                                       w32_tail_base(c), Phi, K, 0,
                                        nullptr, &per_cu, nullptr, nullptr, c->stream));
       c->tune.fused_blocks = (per_cu > 0 ? per_cu : 1) * c->num_cu;
     }

@@ -132,6 +132,7 @@ struct CpScratch {
 struct tlda_ctx {
   tlda_config cfg;
   int Dp = 0;
+  int Dt = 0;                 // columns of W32's tail copy (0: none)
   int Dh = 0;                 // row stride of the BF16 whitening copy
   hipStream_t stream = nullptr;
   hipStream_t copy_stream = nullptr;
@@ -336,9 +337,19 @@ bool fused_supported(int D, int K, int Dp);
 int fused_tile_rows(int D, int K);        // row tile of the fused kernel for this shape
 // With partial == nullptr, launch_whiten_cp only stores in *block_counts how
 // many blocks of the kernel it would launch can be resident on one CU.
+// Dt > 0: W32 also holds, from element tail_base on, a [V][Dt] copy of the
+// columns past the last whole 128-byte line of each row (w32_tail_cols).
 hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
-                            int Dp, const float* Phi, int K, int nblk, float* partial,
-                            int* block_counts, float* Xout, float* phi_copy, hipStream_t s);
+                            int Dp, int Dt, uint32_t tail_base, const float* Phi, int K,
+                            int nblk, float* partial, int* block_counts, float* Xout,
+                            float* phi_copy, hipStream_t s);
+// Columns of the tail copy that the wide FP32 fused kernel reads instead of a
+// row's last, mostly empty 128-byte line: D mod 32 rounded up to 4 when that
+// is 1 to 8 and the shape takes the wide kernel, else 0 (no tail copy).
+int w32_tail_cols(int D, int K);
+// W32[tail_base + w Dt + j] = W32[w Dp + 32 floor(D / 32) + j], j < Dt.
+hipError_t launch_w32_tail(float* W32, int V, int D, int Dp, int Dt, uint32_t tail_base,
+                           hipStream_t s);
 int cp_num_blocks(int n_rows, int D, int K, int max_blocks);
 hipError_t launch_sum_counts(const int* block_counts, int n, int* out, hipStream_t s);
 // multi-slice step: reduction over every slice's batch, then every slice's finish
