@@ -264,7 +264,8 @@ __global__ void __launch_bounds__(512, wide_min_waves(DQ, KQ)) k_whiten_cp_wide(
     const float* __restrict__ val, int n_rows, const float* __restrict__ W32,
     const float* __restrict__ mw32, int D, int Dp, int Dt, uint32_t tail_base,
     const float* __restrict__ Phi, int K, int nblk, float* __restrict__ partial,
-    int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy) {
+    int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy,
+    double* __restrict__ gsq) {
   constexpr int NW = 8, kThreads = 512;
   constexpr int T = 32, G = 32, RPW = 2, RPB = NW * RPW, PASSES = T / RPB;
   constexpr int NB = 8;                    // nonzeros per gather step
@@ -447,6 +448,31 @@ __global__ void __launch_bounds__(512, wide_min_waves(DQ, KQ)) k_whiten_cp_wide(
     }
     __syncthreads();
   }
+  // The squared Gram entries (phi_j . phi_k)^2 of the finish, FP64, from the
+  // copy of Phi in LDS: the blocks share the K x K entries, four lanes per
+  // entry, each summing one chain of d (d = 4m + c, chain 0 also the tail),
+  // combined as (c0 + c1) + (c2 + c3) -- the summation of k_gram_sq, which
+  // the step then does not launch.  An entry's four lanes are adjacent and
+  // 4 K^2 is a multiple of four, so they enter and leave the loop together.
+  // (The barrier makes Ps visible also in a block that had no tile.)
+  __syncthreads();
+  if (gsq != nullptr) {
+    for (int e4 = blockIdx.x * kThreads + tid; e4 < 4 * K * K; e4 += nblk * kThreads) {
+      const int e = e4 >> 2, c = e4 & 3;
+      const int j = e / K, k = e % K;
+      double accg = 0.0;
+      const int M = D / 4;
+      for (int m = 0; m < M; ++m) {
+        const int i = 4 * m + c;
+        accg += (double)Ps[i * LDP + j] * (double)Ps[i * LDP + k];
+      }
+      if (c == 0)
+        for (int i = 4 * M; i < D; ++i) accg += (double)Ps[i * LDP + j] * (double)Ps[i * LDP + k];
+      accg += __shfl_xor(accg, 1, 64);
+      accg += __shfl_xor(accg, 2, 64);
+      if (c == 0) gsq[e] = accg * accg;
+    }
+  }
   float* out = partial + (size_t)blockIdx.x * D * K;
   if (owner) {
     const int k = wave * 16 + l16;
@@ -472,7 +498,7 @@ template <int DQ, int KQ>
 hipError_t launch_wide(const tlda_csr_batch& b, const float* W32, const float* mw32, int D, int Dp,
                        int Dt, uint32_t tail_base, const float* Phi, int K, int nblk,
                        float* partial, int* block_counts, float* Xout, float* phi_copy,
-                       hipStream_t s) {
+                       double* gsq, hipStream_t s) {
   if (partial == nullptr) {   // occupancy query: resident blocks per CU in nblk's place
     int per_cu = 0;
     hipError_t e =
@@ -486,7 +512,7 @@ hipError_t launch_wide(const tlda_csr_batch& b, const float* W32, const float* m
   const float* va = b.nnz > 0 ? b.val : reinterpret_cast<const float*>(b.row_ptr);
   launch_main(k_whiten_cp_wide<DQ, KQ>, dim3(nblk), dim3(512), 0, s, b.row_ptr, ci, va, b.n_rows,
               W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial, block_counts, Xout,
-              phi_copy);
+              phi_copy, gsq);
   return hipGetLastError();
 }
 
@@ -562,10 +588,12 @@ hipError_t launch_w32_tail(float* W32, int V, int D, int Dp, int Dt, uint32_t ta
   return hipGetLastError();
 }
 
+bool fused_forms_gram(int D, int K) { return fused_tile_rows(D, K) == 32; }
+
 hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
                             int Dp, int Dt, uint32_t tail_base, const float* Phi, int K,
                             int nblk, float* partial, int* block_counts, float* Xout,
-                            float* phi_copy, hipStream_t s) {
+                            float* phi_copy, double* gsq, hipStream_t s) {
   const int dq = mfma_bucket(D), kq = mfma_bucket(K);
   const int T = fused_tile_rows(D, K);
   int G = Dp / 4;   // lanes per document: Dp is 4, 8, 16, 32 or 64 here
@@ -585,7 +613,7 @@ hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const flo
 #define TLDA_WIDE(DQ_, KQ_)                                                                    \
   if (dq == DQ_ && kq == KQ_)                                                                  \
     return launch_wide<DQ_, KQ_>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,   \
-                                 block_counts, Xout, phi_copy, s);
+                                 block_counts, Xout, phi_copy, gsq, s);
 #define TLDA_WIDE_ROW(DQ_) \
   TLDA_WIDE(DQ_, 16) TLDA_WIDE(DQ_, 32) TLDA_WIDE(DQ_, 64) TLDA_WIDE(DQ_, 112) TLDA_WIDE(DQ_, 128)
   TLDA_WIDE(16, 112) TLDA_WIDE(16, 128) TLDA_WIDE(32, 112) TLDA_WIDE(32, 128)

@@ -169,13 +169,14 @@ tlda_status ensure_x(tlda_ctx* c, size_t need) {
 // The finish of a step (gradient and update from the reduction's partials).
 // From kGramOnceDK entries of Phi on, the squared Gram entries of Phi0 are
 // formed once first rather than by every finish block.
+// gram_ready: the reduction kernel already formed the squared Gram entries.
 tlda_status finish_step(tlda_ctx* c, const float* partial, int nblk, const int* counts,
                         int ncounts, int n_default, float beta, float* Phi, float* grad,
-                        int* n_out) {
+                        int* n_out, bool gram_ready = false) {
   const int D = c->cfg.D, K = c->cfg.K;
   const double* gsq = nullptr;
   if (D * K >= tlda::kGramOnceDK) {
-    HIP_OK(c, tlda::launch_gram_sq(c->cp.phi0, D, K, c->cp.gsq, c->stream));
+    if (!gram_ready) HIP_OK(c, tlda::launch_gram_sq(c->cp.phi0, D, K, c->cp.gsq, c->stream));
     gsq = c->cp.gsq;
   }
   HIP_OK(c, tlda::launch_cp_finish(partial, nblk, counts, ncounts, n_default, c->cp.phi0, D,
@@ -437,7 +438,7 @@ tlda_status fused_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float* 
       int per_cu = 0;
       HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, c->Dt,
                                        w32_tail_base(c), Phi, K, 0, nullptr,
-                                       &per_cu, nullptr, nullptr, c->stream));
+                                       &per_cu, nullptr, nullptr, nullptr, c->stream));
       c->tune.fused_blocks = (per_cu > 0 ? per_cu : 1) * c->num_cu;
     }
     nblk = ntiles < c->tune.fused_blocks ? ntiles : c->tune.fused_blocks;
@@ -452,6 +453,9 @@ tlda_status fused_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float* 
     partial = c->cp.partial;
   }
   float* g = grad ? grad : c->cp.grad;
+  // the FP32 wide kernel forms the finish's squared Gram entries itself
+  const bool gram_in_kernel =
+      !is_bf16(c) && D * K >= tlda::kGramOnceDK && tlda::fused_forms_gram(D, K);
   st = begin_use(c, b);
   if (st != TLDA_OK) return st;
   HIP_OK(c, timing_start(c));
@@ -462,11 +466,12 @@ tlda_status fused_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float* 
   else
     HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, c->Dt, w32_tail_base(c),
                                      Phi, K, nblk, partial, c->block_counts, X_out, c->cp.phi0,
-                                     c->stream));
+                                     gram_in_kernel ? c->cp.gsq : nullptr, c->stream));
   HIP_OK(c, timing_stop(c));
   st = end_use(c, b);
   if (st != TLDA_OK) return st;
-  return finish_step(c, partial, nblk, c->block_counts, nblk, 0, beta, Phi, g, n_kept_out);
+  return finish_step(c, partial, nblk, c->block_counts, nblk, 0, beta, Phi, g, n_kept_out,
+                     gram_in_kernel);
 }
 
 // The CP step of a classic-moment context (the batch is already checked):
@@ -1638,7 +1643,7 @@ tlda_status tlda_graph_capture_steps(tlda_ctx* c, const tlda_csr_batch* batches,
       int per_cu = 0;
       HIP_OK(c, tlda::launch_whiten_cp(batches[0], c->wh.W32, c->wh.mw32, D, c->Dp, c->Dt,
                                        w32_tail_base(c), Phi, K, 0,
-                                       nullptr, &per_cu, nullptr, nullptr, c->stream));
+                                       nullptr, &per_cu, nullptr, nullptr, nullptr, c->stream));
       c->tune.fused_blocks = (per_cu > 0 ? per_cu : 1) * c->num_cu;
     }
     int nblk = std::min(c->tune.fused_blocks, 2 * tlda::kWhitenBlockCounts);

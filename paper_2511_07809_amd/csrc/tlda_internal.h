@@ -339,10 +339,13 @@ int fused_tile_rows(int D, int K);        // row tile of the fused kernel for th
 // many blocks of the kernel it would launch can be resident on one CU.
 // Dt > 0: W32 also holds, from element tail_base on, a [V][Dt] copy of the
 // columns past the last whole 128-byte line of each row (w32_tail_cols).
+// gsq != nullptr: the kernel also forms the K x K squared Gram entries of
+// Phi for the finish (shapes where fused_forms_gram holds; others ignore it).
 hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
                             int Dp, int Dt, uint32_t tail_base, const float* Phi, int K,
                             int nblk, float* partial, int* block_counts, float* Xout,
-                            float* phi_copy, hipStream_t s);
+                            float* phi_copy, double* gsq, hipStream_t s);
+bool fused_forms_gram(int D, int K);
 // Columns of the tail copy that the wide FP32 fused kernel reads instead of a
 // row's last, mostly empty 128-byte line: D mod 32 rounded up to 4 when that
 // is 1 to 8 and the shape takes the wide kernel, else 0 (no tail copy).
