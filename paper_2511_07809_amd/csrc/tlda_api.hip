@@ -112,6 +112,8 @@ hipError_t form_whitening(tlda_ctx* c) {
 }
 
 // The next event pair of the timing hook goes to the next main-kernel launch.
+// (Not while a graph is captured: events attached to a launch are not
+// recorded in captured graphs.)
 hipError_t timing_start(tlda_ctx* c) {
   tlda::g_main_timer = tlda::KernelTimer{};
   if (c->t_n <= 0 || c->in_capture) return hipSuccess;

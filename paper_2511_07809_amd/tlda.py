@@ -432,7 +432,7 @@ class Mlp:
         self.n_params = int(_LIB.tlda_mlp_param_count(d_in, hidden, k_out))
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _LIB is not None:
             _LIB.tlda_mlp_destroy(self.handle)
             self.handle = None
 
@@ -527,7 +527,7 @@ class Multi:
         self._refs = refs
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _LIB is not None:
             _LIB.tlda_multi_destroy(self.handle)
             self.handle = None
 
@@ -538,7 +538,7 @@ class Graph:
         self._refs = refs
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _LIB is not None:
             _LIB.tlda_graph_destroy(self.handle)
             self.handle = None
 
