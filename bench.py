@@ -49,7 +49,10 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=24)
-    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default 64 for the step workloads: the "
+                    "streaming-scale kernel settles at its steady duration after a few tens "
+                    "of milliseconds of steps; 1 for --online)")
     ap.add_argument("--slice-scale", type=float, default=1.0,
                     help="c4: scale factor on every slice's size")
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"],
@@ -963,6 +966,8 @@ def measure(tl, spec, args, precision: str, n_docs: int, stream) -> dict:
 
 def main():
     args = parse()
+    if args.warmup is None:
+        args.warmup = 1 if args.online else 64
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is described in DESIGN.md but not built", file=sys.stderr)
