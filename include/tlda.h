@@ -161,8 +161,8 @@ const char* tlda_last_error(const tlda_ctx* ctx);
 /* Section "Computing the Centered Cumulants" and the batched implementation:
  * accumulates, over the kept documents of `batch` (may be NULL when only
  * refreshing), the document count N, the dropped-document count, exact int64
- * token totals per word, sum f (FP64) and the upper triangle of sum f f^T
- * (FP64).  With TLDA_REFRESH_W it then forms M1 = sum f / N and
+ * token totals per word, sum f and the upper triangle of sum f f^T (exact,
+ * see below).  With TLDA_REFRESH_W it then forms M1 = sum f / N and
  * M2~ = (alpha0 + 1)(sum f f^T / N - M1 M1^T) and recomputes
  * W = U diag(lambda)^(-1/2) from the top-D eigenpairs of M2~ by FP64 block
  * subspace iteration with Rayleigh-Ritz (section "Online Decomposition of the

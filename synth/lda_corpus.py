@@ -155,8 +155,19 @@ def _chunk_docs(spec: CorpusSpec, cum_mu: np.ndarray, alpha: np.ndarray,
     return indptr, cols, counts.astype(np.float32)
 
 
-def generate(spec: CorpusSpec, n_docs: Optional[int] = None) -> Corpus:
-    """Generate the first ``n_docs`` documents (default: all) of the workload."""
+_POOL_STATE = {}
+
+
+def _pool_chunk(job):
+    spec, cum_mu, alpha = _POOL_STATE["args"]
+    child, n = job
+    return _chunk_docs(spec, cum_mu, alpha, np.random.default_rng(child), n)
+
+
+def generate(spec: CorpusSpec, n_docs: Optional[int] = None, workers: int = 1) -> Corpus:
+    """Generate the first ``n_docs`` documents (default: all) of the workload.
+    Chunks are independent (each has its own child seed), so ``workers`` > 1
+    generates them in forked processes; the corpus is the same either way."""
     n_docs = spec.N if n_docs is None else int(n_docs)
     n_chunks = max(1, -(-n_docs // CHUNK))
     ss = np.random.SeedSequence(spec.seed)
@@ -166,11 +177,20 @@ def generate(spec: CorpusSpec, n_docs: Optional[int] = None) -> Corpus:
     cum_mu = np.cumsum(mu.T, axis=1)
     cum_mu[:, -1] = 1.0
     alpha = spec.alpha
+    jobs = [(children[c + 1], min(CHUNK, n_docs - c * CHUNK)) for c in range(n_chunks)]
+    if workers > 1 and n_chunks > 1:
+        import multiprocessing as mp
+        _POOL_STATE["args"] = (spec, cum_mu, alpha)
+        try:
+            with mp.get_context("fork").Pool(min(workers, n_chunks)) as pool:
+                chunks = pool.map(_pool_chunk, jobs)
+        finally:
+            _POOL_STATE.clear()
+    else:
+        chunks = [_chunk_docs(spec, cum_mu, alpha, np.random.default_rng(ch), n) for ch, n in jobs]
     ptrs, cols, vals = [], [], []
     offset = 0
-    for c in range(n_chunks):
-        n = min(CHUNK, n_docs - c * CHUNK)
-        ip, ci, va = _chunk_docs(spec, cum_mu, alpha, np.random.default_rng(children[c + 1]), n)
+    for ip, ci, va in chunks:
         ptrs.append(ip[1:] + offset)
         cols.append(ci)
         vals.append(va)
