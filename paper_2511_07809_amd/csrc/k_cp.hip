@@ -316,11 +316,24 @@ __device__ __forceinline__ void cp_finish_block(
   const int e = blk * kFinEntries + el;
   // Phi0 into LDS and the kept-row counts, with the loads of a round issued
   // together (clamped indexes, unconditional) so that one memory round trip
-  // serves up to kFinStage * kFinThreads entries.
+  // serves up to kFinStage * kFinThreads entries.  With the squared Gram
+  // entries given, the block needs only the rows of Phi0 its entries lie in
+  // (at most two: D K >= 4096 and D <= 256 make K >= 16): ph then holds
+  // Phi0[base .. base + n_ph).
   int cnt = 0;
   const bool have_counts = counts != nullptr && ncounts > 0;
   int c_first = 0;
-  if (DK <= kFinStage * kFinThreads) {
+  const bool rows_only = gsq != nullptr;
+  const int e_first = min(blk * kFinEntries, DK - 1);
+  const int e_last = min(blk * kFinEntries + kFinEntries - 1, DK - 1);
+  const int base = rows_only ? e_first / K * K : 0;
+  const int n_ph = rows_only ? (e_last / K + 1) * K - base : DK;
+  if (rows_only) {
+    // one straight-line round: n_ph <= 2 K <= 512 < kFinThreads
+    const float v = Phi0[base + min(tid, n_ph - 1)];
+    if (have_counts) c_first = counts[min(tid, ncounts - 1)];
+    ph[tid < n_ph ? tid : n_ph + lane] = v;
+  } else if (DK <= kFinStage * kFinThreads) {
     // one round, straight-line; lanes past the end store into the
     // kFinPad-float pad after Phi0's copy, one slot per lane (no two lanes
     // of a wave on one LDS address)
@@ -376,7 +389,8 @@ __device__ __forceinline__ void cp_finish_block(
     const int d = me / K, k = me % K;
     double pen = 0.0;
     if (gsq != nullptr) {
-      for (int j = lane; j < K; j += 64) pen += (double)ph[d * K + j] * gsq[(size_t)j * K + k];
+      for (int j = lane; j < K; j += 64)
+        pen += (double)ph[d * K + j - base] * gsq[(size_t)j * K + k];
     } else {
       for (int j = lane; j < K; j += 64) {
         // (Phi^T Phi)[j][k] in four independent chains
@@ -442,7 +456,7 @@ __device__ __forceinline__ void cp_finish_block(
       const double c3 = (alpha0 + 1.0) * (alpha0 + 2.0) / 2.0;
       const float g = (float)(3.0 * (1.0 + theta) * pen_s[el] - 3.0 * c3 / (double)n * tot);
       grad[e] = g;
-      Phi[e] = fmaf(-beta, g, ph[e]);
+      Phi[e] = fmaf(-beta, g, ph[e - base]);
     }
   }
   if (blk == 0 && tid == 0 && n_out != nullptr) *n_out = n;
