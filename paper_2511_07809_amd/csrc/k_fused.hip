@@ -258,7 +258,9 @@ constexpr int wide_lds_bytes(int DQ, int KQ) {
 }
 constexpr int wide_min_waves(int DQ, int KQ) { return 2 * wide_lds_bytes(DQ, KQ) <= 163840 ? 4 : 2; }
 
-template <int DQ, int KQ>
+// NK2: k-steps of S = X_t Phi, DQ / 4 unless the real D ends earlier (the
+// columns of X past D are zero): 25 for D <= 100 in the 112 bucket.
+template <int DQ, int KQ, int NK2 = DQ / 4>
 __global__ void __launch_bounds__(512, wide_min_waves(DQ, KQ)) k_whiten_cp_wide(
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const float* __restrict__ val, int n_rows, const float* __restrict__ W32,
@@ -271,8 +273,8 @@ __global__ void __launch_bounds__(512, wide_min_waves(DQ, KQ)) k_whiten_cp_wide(
   constexpr int NB = 8;                    // nonzeros per gather step
   constexpr int LDX = DQ + 4, LDS = KQ + 4, LDP = KQ;   // Phi unpadded: 78 KB per block at 112
                                                          // x 112, so two blocks fit on a CU
-  constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = DQ / 4;
-  static_assert(NCT <= NW && T % RPB == 0, "wide fused shape");
+  constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = NK2;
+  static_assert(NCT <= NW && T % RPB == 0 && NK2 <= DQ / 4, "wide fused shape");
   __shared__ __attribute__((aligned(16))) float Ps[DQ * LDP];
   __shared__ __attribute__((aligned(16))) float Xs[T * LDX];
   __shared__ __attribute__((aligned(16))) float Ss[T * LDS];
@@ -494,15 +496,20 @@ __global__ void __launch_bounds__(512, wide_min_waves(DQ, KQ)) k_whiten_cp_wide(
   }
 }
 
-template <int DQ, int KQ>
+template <int DQ, int KQ, int NK2 = DQ / 4>
 hipError_t launch_wide(const tlda_csr_batch& b, const float* W32, const float* mw32, int D, int Dp,
                        int Dt, uint32_t tail_base, const float* Phi, int K, int nblk,
                        float* partial, int* block_counts, float* Xout, float* phi_copy,
                        double* gsq, hipStream_t s) {
+  if constexpr (DQ == 112 && NK2 == DQ / 4) {
+    if (D <= 100)
+      return launch_wide<DQ, KQ, 25>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,
+                                     block_counts, Xout, phi_copy, gsq, s);
+  }
   if (partial == nullptr) {   // occupancy query: resident blocks per CU in nblk's place
     int per_cu = 0;
-    hipError_t e =
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_whiten_cp_wide<DQ, KQ>, 512, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, k_whiten_cp_wide<DQ, KQ, NK2>, 512, 0);
     *block_counts = per_cu;
     return e;
   }
@@ -510,9 +517,9 @@ hipError_t launch_wide(const tlda_csr_batch& b, const float* W32, const float* m
   // then read the row pointers instead (the values are discarded)
   const int32_t* ci = b.nnz > 0 ? b.col_idx : b.row_ptr;
   const float* va = b.nnz > 0 ? b.val : reinterpret_cast<const float*>(b.row_ptr);
-  launch_main(k_whiten_cp_wide<DQ, KQ>, dim3(nblk), dim3(512), 0, s, b.row_ptr, ci, va, b.n_rows,
-              W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial, block_counts, Xout,
-              phi_copy, gsq);
+  launch_main(k_whiten_cp_wide<DQ, KQ, NK2>, dim3(nblk), dim3(512), 0, s, b.row_ptr, ci, va,
+              b.n_rows, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial, block_counts,
+              Xout, phi_copy, gsq);
   return hipGetLastError();
 }
 
