@@ -348,10 +348,14 @@ def test_cp_step_full_size_streaming_shape():
 # fused whitening + CP step
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("D,K", [(5, 5), (10, 7), (20, 20), (33, 40), (50, 50), (64, 64),
-                                 (100, 100), (128, 96), (150, 40), (256, 56), (56, 256)])
+                                 (100, 100), (128, 96), (150, 40), (256, 56), (56, 256),
+                                 (97, 100), (104, 110), (36, 100), (65, 70)])
 def test_fused_step_matches_oracle(D, K):
     """tlda_whiten_cp_step against the oracle's whitening and gradient on the
-    same batch (rows with dropped and empty documents included)."""
+    same batch (rows with dropped and empty documents included).  The last
+    four shapes take the wide FP32 kernel with a W32 tail copy of 4 or 8
+    columns (D mod 32 = 1, 4, 8) and its S phase of 25 k-steps (D <= 100 in
+    the 112 bucket) or of the full 28 (D = 104)."""
     V = 400
     rng = np.random.default_rng(D * 7 + K)
     rows = [{}, {3: 1, 9: 1}]
