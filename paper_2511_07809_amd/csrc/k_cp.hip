@@ -301,31 +301,35 @@ constexpr int kFinPre = 4;        // quads of partials issued before the penalty
 constexpr int kFinStage = 4;      // Phi0 entries per thread per staging round
 constexpr int kFinPad = 64;       // LDS floats after the copy of Phi0 (staging pad)
 
+template <int FE>
 __device__ __forceinline__ void cp_finish_block(
     int blk, const float* __restrict__ partial, int nblk, const int* __restrict__ counts,
     int ncounts, int n_default, const float* __restrict__ Phi0, int D, int K, double alpha0,
     double theta, float beta, float* __restrict__ Phi, float* __restrict__ grad,
     double* __restrict__ R1, int* __restrict__ n_out, float* __restrict__ ph,
     const double* __restrict__ gsq) {
-  __shared__ double red[kFinGroups][kFinEntries + 1];
-  __shared__ double pen_s[kFinEntries];
+  // FE entries of D x K per block, FG = kFinThreads / FE groups of partials
+  constexpr int FG = kFinThreads / FE;
+  __shared__ double red[FG][FE + 1];
+  __shared__ double pen_s[FE];
   __shared__ int nred[kFinThreads / 64];
-  const int tid = threadIdx.x, el = tid % kFinEntries, grp = tid / kFinEntries;
+  const int tid = threadIdx.x, el = tid % FE, grp = tid / FE;
   const int lane = tid & 63, wave = tid >> 6;
   const int DK = D * K;
-  const int e = blk * kFinEntries + el;
+  const int e = blk * FE + el;
   // Phi0 into LDS and the kept-row counts, with the loads of a round issued
   // together (clamped indexes, unconditional) so that one memory round trip
   // serves up to kFinStage * kFinThreads entries.  With the squared Gram
   // entries given, the block needs only the rows of Phi0 its entries lie in
-  // (at most two: D K >= 4096 and D <= 256 make K >= 16): ph then holds
+  // (at most two: FE <= K, since D <= 256 makes K >= 16 from D K >= 4096 on and
+  // K >= 32 from D K >= 8192 on, where FE = 32): ph then holds
   // Phi0[base .. base + n_ph).
   int cnt = 0;
   const bool have_counts = counts != nullptr && ncounts > 0;
   int c_first = 0;
   const bool rows_only = gsq != nullptr;
-  const int e_first = min(blk * kFinEntries, DK - 1);
-  const int e_last = min(blk * kFinEntries + kFinEntries - 1, DK - 1);
+  const int e_first = min(blk * FE, DK - 1);
+  const int e_last = min(blk * FE + FE - 1, DK - 1);
   const int base = rows_only ? e_first / K * K : 0;
   const int n_ph = rows_only ? (e_last / K + 1) * K - base : DK;
   if (rows_only) {
@@ -356,41 +360,43 @@ __device__ __forceinline__ void cp_finish_block(
   }
   __syncthreads();
   // The first kFinPre quads of this thread's partials (four partials each,
-  // kFinGroups apart) are all in flight while the penalty below works from
+  // FG apart) are all in flight while the penalty below works from
   // LDS (a barrier would wait for them); the first nq of them are added
   // afterwards in the same order as the loop that takes the rest.  The loads
   // are unconditional, from indexes clamped into the buffer: a load under a
   // lane condition is followed by a wait for it where the branches join.
-  constexpr int kQuad = 4 * kFinGroups;
+  constexpr int kQuad = 4 * FG;
   float f[4 * kFinPre] = {};
   int nq = 0;
 #pragma unroll
   for (int q = 0; q < kFinPre; ++q)
-    nq += (e < DK && grp + q * kQuad + 3 * kFinGroups < nblk) ? 1 : 0;
+    nq += (e < DK && grp + q * kQuad + 3 * FG < nblk) ? 1 : 0;
   const int ec = e < DK ? e : DK - 1;
   if (nblk >= kFinPre * kQuad) {
-    // every prefetched row exists: rows grp + kFinGroups t, one stride apart
+    // every prefetched row exists: rows grp + FG t, one stride apart
     const float* pr = partial + (size_t)grp * DK + ec;
-    const size_t stride = (size_t)kFinGroups * DK;
+    const size_t stride = (size_t)FG * DK;
 #pragma unroll
     for (int t = 0; t < 4 * kFinPre; ++t) f[t] = pr[t * stride];
-  } else if (nblk > 3 * kFinGroups) {
+  } else if (nblk > 3 * FG) {
     // some lanes have a full quad (exactly those counted in nq: a lane's
-    // first quad is full once nblk > grp + 3 kFinGroups); the others load
+    // first quad is full once nblk > grp + 3 FG); the others load
     // rows they then drop.  Below that no lane has one and nq is 0.
 #pragma unroll
     for (int t = 0; t < 4 * kFinPre; ++t)
-      f[t] = partial[(size_t)min(grp + t * kFinGroups, nblk - 1) * DK + ec];
+      f[t] = partial[(size_t)min(grp + t * FG, nblk - 1) * DK + ec];
   }
   // wave w: penalty of entries w, w + 16, ... of the block
-  for (int wi = wave; wi < kFinEntries; wi += kFinThreads / 64) {
-    const int me = blk * kFinEntries + wi;
+  for (int wi = wave; wi < FE; wi += kFinThreads / 64) {
+    const int me = blk * FE + wi;
     if (me >= DK) break;
     const int d = me / K, k = me % K;
     double pen = 0.0;
     if (gsq != nullptr) {
+      // gsq is symmetric bit for bit (the same products in the same chains),
+      // so row k is read: consecutive lanes, consecutive addresses
       for (int j = lane; j < K; j += 64)
-        pen += (double)ph[d * K + j - base] * gsq[(size_t)j * K + k];
+        pen += (double)ph[d * K + j - base] * gsq[(size_t)k * K + j];
     } else {
       for (int j = lane; j < K; j += 64) {
         // (Phi^T Phi)[j][k] in four independent chains
@@ -425,19 +431,19 @@ __device__ __forceinline__ void cp_finish_block(
     }
   int b = grp + nq * kQuad;
   if (e < DK) {
-    for (; b + 3 * kFinGroups < nblk; b += 4 * kFinGroups) {
+    for (; b + 3 * FG < nblk; b += 4 * FG) {
       r0 += (double)partial[(size_t)b * DK + e];
-      r1 += (double)partial[(size_t)(b + kFinGroups) * DK + e];
-      r2 += (double)partial[(size_t)(b + 2 * kFinGroups) * DK + e];
-      r3 += (double)partial[(size_t)(b + 3 * kFinGroups) * DK + e];
+      r1 += (double)partial[(size_t)(b + FG) * DK + e];
+      r2 += (double)partial[(size_t)(b + 2 * FG) * DK + e];
+      r3 += (double)partial[(size_t)(b + 3 * FG) * DK + e];
     }
-    for (; b < nblk; b += kFinGroups) r0 += (double)partial[(size_t)b * DK + e];
+    for (; b < nblk; b += FG) r0 += (double)partial[(size_t)b * DK + e];
   }
   for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
   if (lane == 0) nred[wave] = cnt;
   red[grp][el] = (r0 + r1) + (r2 + r3);
   // the groups' sums, added pairwise in a fixed tree (bit-reproducible)
-  for (int h = kFinGroups / 2; h > 0; h >>= 1) {
+  for (int h = FG / 2; h > 0; h >>= 1) {
     __syncthreads();
     if (grp < h) red[grp][el] += red[grp + h][el];
   }
@@ -447,7 +453,7 @@ __device__ __forceinline__ void cp_finish_block(
     n = 0;
     for (int w = 0; w < kFinThreads / 64; ++w) n += nred[w];
   }
-  if (tid < kFinEntries && e < DK) {
+  if (tid < FE && e < DK) {
     const double tot = red[0][el];
     R1[e] = tot;
     if (n <= 0) {
@@ -489,6 +495,7 @@ __global__ void __launch_bounds__(1024) k_gram_sq(const float* __restrict__ Phi,
   if (in && c == 0) gsq[e] = acc * acc;
 }
 
+template <int FE>
 __global__ void __launch_bounds__(kFinThreads, 8) k_cp_finish(
     const float* __restrict__ partial, int nblk, const int* __restrict__ counts, int ncounts,
     int n_default, const float* __restrict__ Phi0, int D, int K, double alpha0, double theta,
@@ -501,9 +508,9 @@ __global__ void __launch_bounds__(kFinThreads, 8) k_cp_finish(
   // 8 per blocks; those past the last chunk have nothing to do.
   const int per = gridDim.x / 8;
   const int chunk = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (chunk * kFinEntries >= D * K) return;
-  cp_finish_block(chunk, partial, nblk, counts, ncounts, n_default, Phi0, D, K, alpha0, theta,
-                  beta, Phi, grad, R1, n_out, ph, gsq);
+  if (chunk * FE >= D * K) return;
+  cp_finish_block<FE>(chunk, partial, nblk, counts, ncounts, n_default, Phi0, D, K, alpha0, theta,
+                      beta, Phi, grad, R1, n_out, ph, gsq);
 }
 
 // The finish of every slice of a multi-slice step in one launch: block b
@@ -512,9 +519,9 @@ __global__ void __launch_bounds__(kFinThreads, 8) k_cp_finish_multi(const SliceS
                                                                  const int* __restrict__ fin_slice) {
   extern __shared__ float ph[];
   const SliceStep& d = sl[fin_slice[blockIdx.x]];
-  cp_finish_block(blockIdx.x - d.fin0, d.partial, d.nblk, d.block_counts, d.nblk, 0, d.phi_copy,
-                  d.D, d.K, d.alpha0, d.theta, d.beta, d.Phi, d.grad, d.R1, d.n_kept_out, ph,
-                  nullptr);
+  cp_finish_block<kFinEntries>(blockIdx.x - d.fin0, d.partial, d.nblk, d.block_counts, d.nblk, 0,
+                               d.phi_copy, d.D, d.K, d.alpha0, d.theta, d.beta, d.Phi, d.grad,
+                               d.R1, d.n_kept_out, ph, nullptr);
 }
 
 }  // namespace
@@ -634,11 +641,21 @@ hipError_t launch_cp_finish(const float* partial, int nblk, const int* counts, i
                             double theta, float beta, float* Phi, float* grad, double* R1,
                             int* n_out, const double* gsq, hipStream_t s) {
   const int DK = D * K;
-  const int chunks = (DK + kFinEntries - 1) / kFinEntries;
-  hipLaunchKernelGGL(k_cp_finish, dim3(8 * ((chunks + 7) / 8)), dim3(kFinThreads),
-                     sizeof(float) * (DK + kFinPad), s, partial, nblk, counts, ncounts, n_default,
-                     Phi0, D, K,
-                     alpha0, theta, beta, Phi, grad, R1, n_out, gsq);
+  // 16 entries per block, or 32 from D K = 8192 on: 64 (32) groups of 16
+  // lanes (32) need DK waves (DK / 2), and 32 entries keep a large D x K
+  // within one round of resident blocks while still giving every CU a block.
+  const bool wide = DK >= 8192;
+  const int fe = wide ? 32 : kFinEntries;
+  const int chunks = (DK + fe - 1) / fe;
+  const dim3 grid(8 * ((chunks + 7) / 8));
+  if (wide)
+    hipLaunchKernelGGL(k_cp_finish<32>, grid, dim3(kFinThreads), sizeof(float) * (DK + kFinPad), s,
+                       partial, nblk, counts, ncounts, n_default, Phi0, D, K, alpha0, theta, beta,
+                       Phi, grad, R1, n_out, gsq);
+  else
+    hipLaunchKernelGGL(k_cp_finish<kFinEntries>, grid, dim3(kFinThreads),
+                       sizeof(float) * (DK + kFinPad), s, partial, nblk, counts, ncounts,
+                       n_default, Phi0, D, K, alpha0, theta, beta, Phi, grad, R1, n_out, gsq);
   return hipGetLastError();
 }
 
