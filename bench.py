@@ -771,21 +771,28 @@ def run_slices(args) -> None:
     print(json.dumps(out), flush=True)
 
 
-def measure(tl, spec, args, precision: str, n_docs: int, stream) -> dict:
-    """One workload: corpus, moment pass and refresh, the timed steps of both
-    precisions (eager and graph), the roofline of the main precision's
+def make_corpus(spec, n_docs: int):
+    """The workload's corpus, generated by forked workers: call it before the
+    process first uses the GPU."""
+    from synth import generate
+    t = time.time()
+    corpus = generate(spec, n_docs=n_docs or None, workers=min(16, os.cpu_count() or 1))
+    log(f"[bench] generated {spec.name}: {corpus.n_docs} docs, {corpus.nnz} nnz in "
+        f"{time.time() - t:.1f}s")
+    return corpus
+
+
+def measure(tl, spec, args, precision: str, corpus, stream) -> dict:
+    """One workload: moment pass and refresh over `corpus`, the timed steps of
+    both precisions (eager and graph), the roofline of the main precision's
     kernel and the topic error of both precisions after the same passes."""
     import numpy as np
     import torch
 
-    from synth import generate, init_phi, iter_batches
+    from synth import init_phi, iter_batches
 
     D = K = spec.K
-    t = time.time()
-    corpus = generate(spec, n_docs=n_docs or None)
     batches = list(iter_batches(corpus))
-    log(f"[bench] generated {spec.name}: {corpus.n_docs} docs, {corpus.nnz} nnz, "
-        f"{len(batches)} batches in {time.time() - t:.1f}s")
     bf16 = precision == "bf16"
     ctx = tl.tlda_create(spec.V, K, D, spec.alpha0, 0.0, bf16=bf16, eig_iters=60, stream=stream)
     dev = [tl.CsrBatch.from_numpy(rp, ci, va, first_doc=int(i * spec.batch))
@@ -1106,11 +1113,17 @@ def main():
 
     spec = SPECS[args.workload]
     n_docs = args.docs or (16 * spec.batch if spec.name == "c3" else 0)
+    with_c2 = spec.name == "c3" and not args.no_c2 and not args.streamed and not args.docs
+    # corpora first: their generation forks worker processes, which must
+    # happen before this process touches the GPU
+    corpus_main = make_corpus(spec, n_docs)
+    corpus_c2 = make_corpus(SPECS["c2"], 0) if with_c2 else None
     torch.cuda.set_device(0)
     # a stream of its own (default priority): the null stream cannot be captured
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
-    res = measure(tl, spec, args, args.precision, n_docs, stream)
+    res = measure(tl, spec, args, args.precision, corpus_main, stream)
+    del corpus_main
     corpus, runs, graph_runs = res["corpus"], res["runs"], res["graph_runs"]
     main_run, main_graph = runs[args.precision], graph_runs.get(args.precision)
     other_name = res["other_name"]
@@ -1157,9 +1170,9 @@ def main():
         log(f"[bench] cpu baseline: {out['cpu_baseline']['value']:.4g} docs/s "
             f"({out['cpu_baseline']['cores']} threads), single thread "
             f"{out['cpu_baseline']['single_thread_docs_per_s']:.4g}")
-    if spec.name == "c3" and not args.no_c2 and not args.streamed and not args.docs:
+    if with_c2:
         del res
-        c2 = measure(tl, SPECS["c2"], args, args.precision, 0, stream)
+        c2 = measure(tl, SPECS["c2"], args, args.precision, corpus_c2, stream)
         out["breakdown"]["c2"] = {
             "workload": f"c2: V=20000, K=D=50, {c2['corpus'].n_docs} docs, batch "
                         f"{SPECS['c2'].batch}, resident in HBM",
