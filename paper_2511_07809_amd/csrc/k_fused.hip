@@ -496,12 +496,290 @@ __global__ void __launch_bounds__(512, wide_min_waves(DQ, KQ)) k_whiten_cp_wide(
   }
 }
 
+// ---------------------------------------------------------------------------
+// 112 x 112 (D and K in 65..112, the streaming-scale K = D = 100): one
+// 16-wave block per CU with the waves split by role.  Waves 0-11 (three per
+// SIMD) whiten 48-row tiles, exactly as the wide kernel's waves do (same
+// pipelined CSR loads, gathers, tail addressing and per-row arithmetic),
+// into one of two X buffers; waves 12-15 (one per SIMD) run S = X_t Phi and
+// R1 += X_t^T S^2 on the other buffer, each owning column tiles c and c + 4
+// of S and of R1.  One barrier per tile hands a buffer over.  In the wide
+// kernel a CU alternates between gathers and matrix work and the two phases
+// add up; here the matrix waves' work hides under the next tile's gathers,
+// and the gathers have 12 waves in flight per CU instead of 8 to 16 that
+// stop at every tile for the matrix phases.  The per-row results are those
+// of the wide kernel bit for bit; R1's partials sum the same products in
+// the same order within a tile, over 48-row instead of 32-row tiles.
+// Registers: 116 per lane, no spills (the 112 x 128 and 128 x 128 instances
+// would spill, so they stay on the wide kernel); LDS 114 KB.
+// ---------------------------------------------------------------------------
+template <int DQ, int KQ, int NK2>
+__global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+    const float* __restrict__ val, int n_rows, const float* __restrict__ W32,
+    const float* __restrict__ mw32, int D, int Dp, int Dt, uint32_t tail_base,
+    const float* __restrict__ Phi, int K, int nblk, float* __restrict__ partial,
+    int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy,
+    double* __restrict__ gsq) {
+  constexpr int NP = 12, NC = 4, kThreads = 1024;   // whitening and matrix waves
+  constexpr int T = 48, G = 32, RPW = 2, RPB = NP * RPW, PASSES = T / RPB;
+  constexpr int NB = 8;                              // nonzeros per gather step
+  constexpr int LDX = DQ + 4, LDS = KQ + 4, LDP = KQ;
+  constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = NK2;
+  constexpr int CT = (NCT + NC - 1) / NC;        // column tiles per consumer
+  static_assert(T % RPB == 0 && T % 16 == 0 && NKS <= DQ / 4, "hybrid fused shape");
+  __shared__ __attribute__((aligned(16))) float Ps[DQ * LDP];
+  __shared__ __attribute__((aligned(16))) float Xs[2][T * LDX];
+  __shared__ __attribute__((aligned(16))) float Ss[T * LDS];
+  __shared__ int wave_kept[NP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+
+  for (int e = blockIdx.x * kThreads + tid; e < D * K; e += nblk * kThreads) phi_copy[e] = Phi[e];
+  for (int e = tid; e < DQ * LDP; e += kThreads) {
+    const int d = e / LDP, k = e % LDP;
+    Ps[e] = (d < D && k < K) ? Phi[d * K + k] : 0.f;
+  }
+  const int ntiles = (n_rows + T - 1) / T;
+  const int my_tiles = blockIdx.x < ntiles ? (ntiles - 1 - blockIdx.x) / nblk + 1 : 0;
+  __syncthreads();
+
+  if (wave < NP) {
+    const int gl = lane & (G - 1), half = lane >> 5;
+    const int c4 = gl * 4;
+    const bool active = c4 < D;
+    const bool in_lds = c4 < DQ;
+    const int Dm = Dt > 0 ? D / 32 * 32 : Dp;
+    const bool tail_lane = active && c4 >= Dm;
+    const uint32_t gmul = tail_lane ? (uint32_t)Dt : (uint32_t)Dp;
+    const uint32_t gadd = !active ? 0u : tail_lane ? tail_base + (uint32_t)(c4 - Dm) : (uint32_t)c4;
+    const int n_pass = my_tiles * PASSES;
+    auto doc_row = [&](int g) -> int {
+      if (g >= n_pass) return -1;
+      const int tile = blockIdx.x + (g / PASSES) * nblk;
+      const int row = tile * T + (g % PASSES) * RPB + wave * RPW + half;
+      return row < n_rows ? row : -1;
+    };
+    auto load_rp = [&](int g, int& b, int& e) {
+      const int r = doc_row(g);
+      const int rc = r < 0 ? 0 : r;
+      const int b_ = row_ptr[rc], e_ = row_ptr[rc + 1];
+      b = r < 0 ? 0 : b_;
+      e = r < 0 ? 0 : e_;
+    };
+    auto load_csr = [&](int b, int e, int& c, float& v) {
+      const int j = b + gl;
+      const bool in = j < e;
+      const int jc = in ? j : 0;
+      const int c_ = col_idx[jc];
+      const float v_ = val[jc];
+      c = in ? c_ : 0;
+      v = in ? v_ : 0.f;
+    };
+    int b0 = 0, e0 = 0, b1 = 0, e1 = 0;
+    load_rp(0, b0, e0);
+    load_rp(1, b1, e1);
+    int cc = 0;
+    float cv = 0.f;
+    if (n_pass > 0) load_csr(b0, e0, cc, cv);
+    int kept_total = 0;
+    int g = 0;
+    // step s: tile s into buffer s & 1 (the matrix waves meanwhile read
+    // tile s - 1 from the other); one step more than tiles, so that the
+    // barriers pair up with the matrix waves' loop
+#pragma unroll 1
+    for (int s = 0; s <= my_tiles; ++s) {
+      if (s < my_tiles) {
+        float* X = Xs[s & 1];
+#pragma unroll 1
+        for (int pass = 0; pass < PASSES; ++pass, ++g) {
+          const int lr = pass * RPB + wave * RPW + half;
+          const int row = doc_row(g);
+          const int b = b0, e = e0;
+          int c_cur = cc;
+          float v_cur = cv;
+          load_csr(b1, e1, cc, cv);
+          b0 = b1;
+          e0 = e1;
+          load_rp(g + 2, b1, e1);
+          float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+          float Lp = 0.f;
+          for (int base = b; base < e; base += G) {
+            if (base != b) load_csr(base, e, c_cur, v_cur);
+            Lp += v_cur;
+            const int n_here = min(G, e - base);
+            for (int t0 = 0; t0 < n_here; t0 += NB) {
+              float4 w[NB];
+#pragma unroll
+              for (int t = 0; t < NB; ++t) {
+                const int c = __shfl(c_cur, (t0 + t) & (G - 1), G);
+                const uint32_t off = (uint32_t)c * gmul + gadd;
+                w[t] = *reinterpret_cast<const float4*>(W32 + off);
+              }
+#pragma unroll
+              for (int t = 0; t < NB; ++t) {
+                const float vs = __shfl(v_cur, (t0 + t) & (G - 1), G);
+                const float v = t0 + t < n_here ? vs : 0.f;
+                a.x = fmaf(v, w[t].x, a.x);
+                a.y = fmaf(v, w[t].y, a.y);
+                a.z = fmaf(v, w[t].z, a.z);
+                a.w = fmaf(v, w[t].w, a.w);
+              }
+            }
+          }
+          float L = Lp;
+#pragma unroll
+          for (int off = 1; off < G; off <<= 1) L += __shfl_xor(L, off, G);
+          const int kept = (row >= 0 && L >= 3.f) ? 1 : 0;
+          float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (kept && active) {
+            const float4 mw = *reinterpret_cast<const float4*>(mw32 + c4);
+            const float invL = 1.0f / L;
+            x.x = fmaf(a.x, invL, -mw.x);
+            x.y = fmaf(a.y, invL, -mw.y);
+            x.z = fmaf(a.z, invL, -mw.z);
+            x.w = fmaf(a.w, invL, -mw.w);
+          }
+          if (in_lds) *reinterpret_cast<float4*>(X + lr * LDX + c4) = x;
+          if (Xout != nullptr && row >= 0 && active) {
+            float* out = Xout + (size_t)row * D;
+            if (c4 + 0 < D) out[c4 + 0] = x.x;
+            if (c4 + 1 < D) out[c4 + 1] = x.y;
+            if (c4 + 2 < D) out[c4 + 2] = x.z;
+            if (c4 + 3 < D) out[c4 + 3] = x.w;
+          }
+          kept_total += __popcll(__ballot(kept && gl == 0));
+        }
+      }
+      __syncthreads();
+    }
+    if (lane == 0) wave_kept[wave] = kept_total;
+  } else {
+    // matrix wave cw: column tiles cw and cw + NC of S and R1 (K = 112 has
+    // seven: waves 12-14 take two, wave 15 one)
+    const int cw = wave - NP;
+    floatx4 acc[CT][NDT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+      for (int q = 0; q < NDT; ++q) acc[c][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int s = 0; s <= my_tiles; ++s) {
+      if (s >= 1) {   // tile s - 1, whitened in the previous step
+        const float* X = Xs[(s - 1) & 1];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          const int ct = cw + NC * c;
+          if (ct < NCT) {
+            floatx4 sacc[T / 16];
+#pragma unroll
+            for (int u = 0; u < T / 16; ++u) sacc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+            const float* xa = X + l16 * LDX + l4;
+            const float* pb = Ps + l4 * LDP + ct * 16 + l16;
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) {
+              const float bv = pb[4 * ks * LDP];
+#pragma unroll
+              for (int u = 0; u < T / 16; ++u)
+                sacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u * 16 * LDX + 4 * ks], bv,
+                                                               sacc[u], 0, 0, 0);
+            }
+            // S^2 through LDS into the B operand layout: only this wave
+            // writes and reads these columns, so no barrier is needed
+#pragma unroll
+            for (int u = 0; u < T / 16; ++u)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                Ss[(u * 16 + 4 * l4 + r) * LDS + ct * 16 + l16] = sacc[u][r] * sacc[u][r];
+#pragma unroll
+            for (int rs = 0; rs < T / 4; ++rs) {
+              const float* xr = X + (rs * 4 + l4) * LDX + l16;
+              const float sv = Ss[(rs * 4 + l4) * LDS + ct * 16 + l16];
+#pragma unroll
+              for (int q = 0; q < NDT; ++q)
+                acc[c][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[q * 16], sv, acc[c][q], 0, 0, 0);
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    float* out = partial + (size_t)blockIdx.x * D * K;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const int ct = cw + NC * c;
+      if (ct < NCT) {
+        const int k = ct * 16 + l16;
+#pragma unroll
+        for (int q = 0; q < NDT; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int d = q * 16 + 4 * l4 + r;
+            if (d < D && k < K) out[d * K + k] = acc[c][q][r];
+          }
+      }
+    }
+  }
+  // the squared Gram entries of the finish, as in the wide kernel
+  __syncthreads();
+  if (gsq != nullptr) {
+    for (int e4 = blockIdx.x * kThreads + tid; e4 < 4 * K * K; e4 += nblk * kThreads) {
+      const int e = e4 >> 2, c = e4 & 3;
+      const int j = e / K, k = e % K;
+      double accg = 0.0;
+      const int M = D / 4;
+      for (int m = 0; m < M; ++m) {
+        const int i = 4 * m + c;
+        accg += (double)Ps[i * LDP + j] * (double)Ps[i * LDP + k];
+      }
+      if (c == 0)
+        for (int i = 4 * M; i < D; ++i) accg += (double)Ps[i * LDP + j] * (double)Ps[i * LDP + k];
+      accg += __shfl_xor(accg, 1, 64);
+      accg += __shfl_xor(accg, 2, 64);
+      if (c == 0) gsq[e] = accg * accg;
+    }
+  }
+  if (tid == 0) {
+    int n = 0;
+#pragma unroll
+    for (int w = 0; w < NP; ++w) n += wave_kept[w];
+    block_counts[blockIdx.x] = n;
+  }
+}
+
+template <int NK2>
+hipError_t launch_hyb(const tlda_csr_batch& b, const float* W32, const float* mw32, int D, int Dp,
+                      int Dt, uint32_t tail_base, const float* Phi, int K, int nblk,
+                      float* partial, int* block_counts, float* Xout, float* phi_copy,
+                      double* gsq, hipStream_t s) {
+  if (partial == nullptr) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, k_whiten_cp_hyb<112, 112, NK2>, 1024, 0);
+    *block_counts = per_cu;
+    return e;
+  }
+  // as in launch_wide: clamped loads read the row pointers when there are no nonzeros
+  const int32_t* ci = b.nnz > 0 ? b.col_idx : b.row_ptr;
+  const float* va = b.nnz > 0 ? b.val : reinterpret_cast<const float*>(b.row_ptr);
+  launch_main(k_whiten_cp_hyb<112, 112, NK2>, dim3(nblk), dim3(1024), 0, s, b.row_ptr, ci, va,
+              b.n_rows, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial, block_counts,
+              Xout, phi_copy, gsq);
+  return hipGetLastError();
+}
+
 template <int DQ, int KQ, int NK2 = DQ / 4>
 hipError_t launch_wide(const tlda_csr_batch& b, const float* W32, const float* mw32, int D, int Dp,
                        int Dt, uint32_t tail_base, const float* Phi, int K, int nblk,
                        float* partial, int* block_counts, float* Xout, float* phi_copy,
                        double* gsq, hipStream_t s) {
-  if constexpr (DQ == 112 && NK2 == DQ / 4) {
+  if constexpr (DQ == 112 && KQ == 112) {   // the hybrid kernel (no spills at this shape)
+    if (D <= 100)
+      return launch_hyb<25>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,
+                            block_counts, Xout, phi_copy, gsq, s);
+    return launch_hyb<28>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,
+                          block_counts, Xout, phi_copy, gsq, s);
+  } else if constexpr (DQ == 112 && NK2 == DQ / 4) {
     if (D <= 100)
       return launch_wide<DQ, KQ, 25>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,
                                      block_counts, Xout, phi_copy, gsq, s);
@@ -557,18 +835,24 @@ hipError_t launch_fused_g(int G, const tlda_csr_batch& b, const float* W32, cons
 }  // namespace
 
 // Shapes the fused kernel covers: D, K <= 128 (each padded to 16, 32, 64,
-// 112 or 128); the X and S tiles of the wide (8-wave) instances take up to
-// 2 x 64 x 132 floats (67.6 KB) of LDS.
+// 112 or 128); the wide kernels keep Phi, X and S in LDS, at most 97 KB per
+// block for the 8-wave kernel (128 x 128) and 114 KB for the hybrid.
 bool fused_supported(int D, int K, int Dp) {
   return mfma_bucket(D) > 0 && mfma_bucket(K) > 0 && Dp <= 128;
 }
 
+namespace {
+// the wide kernels (k_whiten_cp_wide, k_whiten_cp_hyb): D or K past 64
+bool fused_wide(int D, int K) { return mfma_bucket(D) > 64 || mfma_bucket(K) > 64; }
+}  // namespace
+
 int fused_tile_rows(int D, int K) {
-  return (mfma_bucket(D) > 64 || mfma_bucket(K) > 64) ? 32 : cp_mfma_tile_rows(D, K);   // wide: T
+  if (!fused_wide(D, K)) return cp_mfma_tile_rows(D, K);
+  return mfma_bucket(D) == 112 && mfma_bucket(K) == 112 ? 48 : 32;   // hybrid : wide
 }
 
 int w32_tail_cols(int D, int K) {
-  if (fused_tile_rows(D, K) != 32 || D < 32) return 0;   // only the wide kernel reads it
+  if (!fused_wide(D, K) || D < 32) return 0;   // only the wide kernels read it
   const int rem = D % 32;
   return rem >= 1 && rem <= 8 ? (rem + 3) / 4 * 4 : 0;
 }
@@ -595,7 +879,7 @@ hipError_t launch_w32_tail(float* W32, int V, int D, int Dp, int Dt, uint32_t ta
   return hipGetLastError();
 }
 
-bool fused_forms_gram(int D, int K) { return fused_tile_rows(D, K) == 32; }
+bool fused_forms_gram(int D, int K) { return fused_wide(D, K); }
 
 hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
                             int Dp, int Dt, uint32_t tail_base, const float* Phi, int K,

@@ -346,9 +346,9 @@ hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const flo
                             int nblk, float* partial, int* block_counts, float* Xout,
                             float* phi_copy, double* gsq, hipStream_t s);
 bool fused_forms_gram(int D, int K);
-// Columns of the tail copy that the wide FP32 fused kernel reads instead of a
+// Columns of the tail copy that the wide FP32 fused kernels read instead of a
 // row's last, mostly empty 128-byte line: D mod 32 rounded up to 4 when that
-// is 1 to 8 and the shape takes the wide kernel, else 0 (no tail copy).
+// is 1 to 8 and the shape takes a wide kernel, else 0 (no tail copy).
 int w32_tail_cols(int D, int K);
 // W32[tail_base + w Dt + j] = W32[w Dp + 32 floor(D / 32) + j], j < Dt.
 hipError_t launch_w32_tail(float* W32, int V, int D, int Dp, int Dt, uint32_t tail_base,
