@@ -101,6 +101,10 @@ def parse():
                     help="CPU budget of the classic-rung and encoder baselines")
     ap.add_argument("--cpu-reps", type=int, default=3,
                     help="timed oracle runs per thread setting (median reported)")
+    ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="forked processes that generate the corpora before the GPU is first "
+                         "used (1: in this process, e.g. under a profiler that sets up the GPU "
+                         "before the program starts)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy a device buffer of this many MiB (a plain copy "
                          "kernel of known size that scales the HBM byte counters)")
@@ -378,6 +382,17 @@ def run_online(args) -> None:
     print(json.dumps(out), flush=True)
 
 
+def fp32_fused_kernel(D: int, K: int) -> str:
+    """The FP32 fused step's kernel for this shape (D and K are padded to 16,
+    32, 64, 112 or 128): the hybrid kernel when both pad to 112, the wide one
+    when either passes 64, else the small-shape kernel."""
+    def bucket(n):
+        return next(q for q in (16, 32, 64, 112, 128) if n <= q)
+    if bucket(D) == 112 and bucket(K) == 112:
+        return "k_whiten_cp_hyb"
+    return "k_whiten_cp_wide" if D > 64 or K > 64 else "k_whiten_cp"
+
+
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed counter summary,
     or None if there is none for this workload or the kernel's source has
@@ -620,6 +635,24 @@ def run_encoder(args) -> None:
     print(json.dumps(res), flush=True)
 
 
+def _fork_map(fn, items, workers: int) -> list:
+    """map over forked workers (before the process first uses the GPU), or
+    in this process when workers <= 1; the workers leave on their own."""
+    if workers <= 1 or len(items) <= 1:
+        return [fn(x) for x in items]
+    import multiprocessing as mp
+    pool = mp.get_context("fork").Pool(min(workers, len(items)))
+    try:
+        out = pool.map(fn, items)
+        pool.close()
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        pool.join()
+    return out
+
+
 def _gen_slice(spec):
     from synth import generate
     c = generate(spec)
@@ -632,15 +665,12 @@ def run_slices(args) -> None:
     over whole passes: one tlda_whiten_cp_step call per slice batch; one
     multi-slice plan step per batch index; the same captured in a HIP graph;
     and the graph after the autotuner picked each plan's launch shape."""
-    import multiprocessing as mp
-
     import numpy as np
 
     from synth import Corpus, init_phi, iter_batches, slice_specs
     specs = slice_specs(scale=args.slice_scale)
     t = time.time()
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        parts = pool.map(_gen_slice, specs)
+    parts = _fork_map(_gen_slice, specs, args.gen_workers)
     corpora = [Corpus(sp, ip, ix, dt, mu, sp.alpha) for sp, (ip, ix, dt, mu) in zip(specs, parts)]
     del parts
     n_docs = sum(c.n_docs for c in corpora)
@@ -771,12 +801,12 @@ def run_slices(args) -> None:
     print(json.dumps(out), flush=True)
 
 
-def make_corpus(spec, n_docs: int):
+def make_corpus(spec, n_docs: int, workers: int):
     """The workload's corpus, generated by forked workers: call it before the
     process first uses the GPU."""
     from synth import generate
     t = time.time()
-    corpus = generate(spec, n_docs=n_docs or None, workers=min(16, os.cpu_count() or 1))
+    corpus = generate(spec, n_docs=n_docs or None, workers=workers)
     log(f"[bench] generated {spec.name}: {corpus.n_docs} docs, {corpus.nnz} nnz in "
         f"{time.time() - t:.1f}s")
     return corpus
@@ -911,13 +941,12 @@ def measure(tl, spec, args, precision: str, corpus, stream) -> dict:
     cp_flops = rows_per * (4.0 * D * K + K)
     mm_peak = BF16_MFMA_PEAK_TFLOPS if bf16 else FP32_VALU_PEAK_TFLOPS
     kern_us = main_run["kern_ms"].mean(axis=0) * 1e3
-    wide = D > 64 or K > 64
     if fused:
         t_k = kern_us[0] / 1e6
         if bf16:
             name, key = "k_cp_bf16 (fused mode)", "k_cp_bf16/fused"
         else:
-            name = key = "k_whiten_cp_wide" if wide else "k_whiten_cp"
+            name = key = fp32_fused_kernel(D, K)
         hbm_frac = (csr_bytes + w_bytes) / t_k / 1e9 / HBM_PEAK_GBS
         mm_frac = cp_flops / t_k / 1e12 / mm_peak
         if hbm_frac >= mm_frac:
@@ -994,7 +1023,7 @@ def run_full_stream(args) -> None:
     n_docs = args.docs or spec.N
     D = K = spec.K
     t = time.time()
-    corpus = generate(spec, n_docs=n_docs, workers=min(16, os.cpu_count() or 1))
+    corpus = generate(spec, n_docs=n_docs, workers=args.gen_workers)
     batches = list(iter_batches(corpus))
     log(f"[bench] generated {spec.name}: {corpus.n_docs} docs, {corpus.nnz} nnz, "
         f"{len(batches)} batches in {time.time() - t:.1f}s")
@@ -1116,8 +1145,8 @@ def main():
     with_c2 = spec.name == "c3" and not args.no_c2 and not args.streamed and not args.docs
     # corpora first: their generation forks worker processes, which must
     # happen before this process touches the GPU
-    corpus_main = make_corpus(spec, n_docs)
-    corpus_c2 = make_corpus(SPECS["c2"], 0) if with_c2 else None
+    corpus_main = make_corpus(spec, n_docs, args.gen_workers)
+    corpus_c2 = make_corpus(SPECS["c2"], 0, args.gen_workers) if with_c2 else None
     torch.cuda.set_device(0)
     # a stream of its own (default priority): the null stream cannot be captured
     stream = torch.cuda.Stream()

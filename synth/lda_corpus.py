@@ -181,10 +181,15 @@ def generate(spec: CorpusSpec, n_docs: Optional[int] = None, workers: int = 1) -
     if workers > 1 and n_chunks > 1:
         import multiprocessing as mp
         _POOL_STATE["args"] = (spec, cum_mu, alpha)
+        pool = mp.get_context("fork").Pool(min(workers, n_chunks))
         try:
-            with mp.get_context("fork").Pool(min(workers, n_chunks)) as pool:
-                chunks = pool.map(_pool_chunk, jobs)
+            chunks = pool.map(_pool_chunk, jobs)
+            pool.close()   # the workers leave on their own, without a signal
+        except BaseException:
+            pool.terminate()
+            raise
         finally:
+            pool.join()
             _POOL_STATE.clear()
     else:
         chunks = [_chunk_docs(spec, cum_mu, alpha, np.random.default_rng(ch), n) for ch, n in jobs]
