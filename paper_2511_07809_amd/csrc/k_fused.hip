@@ -496,22 +496,45 @@ __global__ void __launch_bounds__(512, wide_min_waves(DQ, KQ)) k_whiten_cp_wide(
   }
 }
 
+// Sum over each 32-lane half of the wave, the result in all its lanes: DPP
+// within 16-lane rows, then the two rows of the half through a swizzle.
+__device__ __forceinline__ float half_sum32(float s) {
+  s += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, s), 0xB1, 0xF, 0xF, false));
+  s += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, s), 0x4E, 0xF, 0xF, false));
+  s += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, s), 0x141, 0xF, 0xF, false));
+  s += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, s), 0x140, 0xF, 0xF, false));
+  // lane ^ 16 within each group of 32 (swizzle bit mode: and 0x1f, or 0, xor 0x10)
+  return s + __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, s), 0x401F));
+}
+
 // ---------------------------------------------------------------------------
 // 112 x 112 (D and K in 65..112, the streaming-scale K = D = 100): one
 // 16-wave block per CU with the waves split by role.  Waves 0-11 (three per
-// SIMD) whiten 48-row tiles, exactly as the wide kernel's waves do (same
-// pipelined CSR loads, gathers, tail addressing and per-row arithmetic),
-// into one of two X buffers; waves 12-15 (one per SIMD) run S = X_t Phi and
-// R1 += X_t^T S^2 on the other buffer, each owning column tiles c and c + 4
-// of S and of R1.  One barrier per tile hands a buffer over.  In the wide
-// kernel a CU alternates between gathers and matrix work and the two phases
-// add up; here the matrix waves' work hides under the next tile's gathers,
-// and the gathers have 12 waves in flight per CU instead of 8 to 16 that
-// stop at every tile for the matrix phases.  The per-row results are those
-// of the wide kernel bit for bit; R1's partials sum the same products in
-// the same order within a tile, over 48-row instead of 32-row tiles.
-// Registers: 116 per lane, no spills (the 112 x 128 and 128 x 128 instances
-// would spill, so they stay on the wide kernel); LDS 114 KB.
+// SIMD) whiten 48-row tiles into one of two X buffers; waves 12-15 (one per
+// SIMD) run S = X_t Phi and R1 += X_t^T S^2 on the other buffer, each owning
+// column tiles c and c + 4 of S and of R1.  One barrier per tile hands a
+// buffer over.  In the 8-wave kernel a CU alternates between gathers and
+// matrix work and the two phases add up; here the matrix waves' work runs
+// beside the next tile's gathers.  What is left of the matrix phases' cost
+// is their issue slots on the whitening waves' SIMDs, so the whitening is
+// written for few instructions per nonzero:
+//  * the W-row gathers are buffer loads from a 32-bit byte offset, one
+//    24-bit multiply-add per nonzero (no 64-bit address arithmetic);
+//  * a document's CSR entries (up to 32, one per lane, loaded one document
+//    ahead) go to the wave's own LDS rows once, and every lane reads eight
+//    of them per step with two 16-byte LDS reads at fixed offsets (instead
+//    of two lane shuffles per nonzero);
+//  * the word count L is summed across the document's lanes with DPP and one
+//    swizzle as soon as its entries arrive, before its gathers.
+// Entries past a document's end are (column 0, count 0): they gather row 0
+// and add nothing.  S^2 never goes through LDS: the R1 product takes its
+// rows in the order the S accumulators hold them.  The per-row arithmetic
+// (the nonzeros of a row in CSR order, one FMA each) is the 8-wave kernel's;
+// L, a sum of the row's counts, is added in another order, which changes
+// nothing for integer counts.  Registers: 102 per lane, no spills (the
+// 112 x 128 and 128 x 128 instances would spill, so they stay on the 8-wave
+// kernel); LDS 99 KB.  The buffer descriptor needs the W32 copy below 4 GiB
+// and V below 2^24 (a 24-bit multiply); launch_wide checks both.
 // ---------------------------------------------------------------------------
 template <int DQ, int KQ, int NK2>
 __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
@@ -524,14 +547,14 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
   constexpr int NP = 12, NC = 4, kThreads = 1024;   // whitening and matrix waves
   constexpr int T = 48, G = 32, RPW = 2, RPB = NP * RPW, PASSES = T / RPB;
   constexpr int NB = 8;                              // nonzeros per gather step
-  constexpr int LDX = DQ + 4, LDS = KQ + 4, LDP = KQ;
+  constexpr int LDX = DQ + 4, LDP = KQ;
   constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = NK2;
   constexpr int CT = (NCT + NC - 1) / NC;        // column tiles per consumer
   static_assert(T % RPB == 0 && T % 16 == 0 && NKS <= DQ / 4, "hybrid fused shape");
   __shared__ __attribute__((aligned(16))) float Ps[DQ * LDP];
   __shared__ __attribute__((aligned(16))) float Xs[2][T * LDX];
-  __shared__ __attribute__((aligned(16))) float Ss[T * LDS];
   __shared__ int wave_kept[NP];
+  __shared__ __attribute__((aligned(16))) int2 ent[NP][2][G];   // (column, count) per document entry
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
 
@@ -553,6 +576,10 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
     const bool tail_lane = active && c4 >= Dm;
     const uint32_t gmul = tail_lane ? (uint32_t)Dt : (uint32_t)Dp;
     const uint32_t gadd = !active ? 0u : tail_lane ? tail_base + (uint32_t)(c4 - Dm) : (uint32_t)c4;
+    const uint32_t gmul4 = gmul * 4u, gadd4 = gadd * 4u;
+    const uint32_t w_bytes = (tail_base + tail_base / (uint32_t)Dp * (uint32_t)Dt) * 4u;
+    const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(W32), (short)0, (int)w_bytes, 0x00020000);
     const int n_pass = my_tiles * PASSES;
     auto doc_row = [&](int g) -> int {
       if (g >= n_pass) return -1;
@@ -603,23 +630,37 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
           e0 = e1;
           load_rp(g + 2, b1, e1);
           float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-          float Lp = 0.f;
+          float L = half_sum32(v_cur);   // the first chunk's counts, before its gathers
+          int2* my_ent = ent[wave][half];
           for (int base = b; base < e; base += G) {
-            if (base != b) load_csr(base, e, c_cur, v_cur);
-            Lp += v_cur;
+            if (base != b) {
+              load_csr(base, e, c_cur, v_cur);
+              L += half_sum32(v_cur);
+            }
+            // this chunk's entries into the wave's LDS rows (the previous
+            // chunk's reads were issued earlier by this same wave, and one
+            // wave's LDS operations complete in order)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            my_ent[gl] = make_int2(c_cur, __float_as_int(v_cur));
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
             const int n_here = min(G, e - base);
             for (int t0 = 0; t0 < n_here; t0 += NB) {
               float4 w[NB];
+              int2 en[NB];
+#pragma unroll
+              for (int t = 0; t < NB; ++t) en[t] = my_ent[t0 + t];
 #pragma unroll
               for (int t = 0; t < NB; ++t) {
-                const int c = __shfl(c_cur, (t0 + t) & (G - 1), G);
-                const uint32_t off = (uint32_t)c * gmul + gadd;
-                w[t] = *reinterpret_cast<const float4*>(W32 + off);
+                const int c = en[t].x;
+                const uint32_t off = __umul24((uint32_t)c, gmul4) + gadd4;
+                const auto r = __builtin_amdgcn_raw_buffer_load_b128(wrs, off, 0, 0);
+                w[t] = make_float4(__uint_as_float(r[0]), __uint_as_float(r[1]),
+                                   __uint_as_float(r[2]), __uint_as_float(r[3]));
               }
 #pragma unroll
               for (int t = 0; t < NB; ++t) {
-                const float vs = __shfl(v_cur, (t0 + t) & (G - 1), G);
-                const float v = t0 + t < n_here ? vs : 0.f;
+                const float v = __int_as_float(en[t].y);
                 a.x = fmaf(v, w[t].x, a.x);
                 a.y = fmaf(v, w[t].y, a.y);
                 a.z = fmaf(v, w[t].z, a.z);
@@ -627,9 +668,6 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
               }
             }
           }
-          float L = Lp;
-#pragma unroll
-          for (int off = 1; off < G; off <<= 1) L += __shfl_xor(L, off, G);
           const int kept = (row >= 0 && L >= 3.f) ? 1 : 0;
           float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
           if (kept && active) {
@@ -684,21 +722,20 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
                 sacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u * 16 * LDX + 4 * ks], bv,
                                                                sacc[u], 0, 0, 0);
             }
-            // S^2 through LDS into the B operand layout: only this wave
-            // writes and reads these columns, so no barrier is needed
+            // R1 += X_t^T S^2 with S^2 straight from the accumulators: k-step
+            // (u, r) sums rows u 16 + 4 k + r (k = l4), the rows this lane
+            // already holds, so S never goes through LDS
 #pragma unroll
             for (int u = 0; u < T / 16; ++u)
 #pragma unroll
-              for (int r = 0; r < 4; ++r)
-                Ss[(u * 16 + 4 * l4 + r) * LDS + ct * 16 + l16] = sacc[u][r] * sacc[u][r];
+              for (int r = 0; r < 4; ++r) {
+                const float sv = sacc[u][r] * sacc[u][r];
+                const float* xr = X + (u * 16 + 4 * l4 + r) * LDX + l16;
 #pragma unroll
-            for (int rs = 0; rs < T / 4; ++rs) {
-              const float* xr = X + (rs * 4 + l4) * LDX + l16;
-              const float sv = Ss[(rs * 4 + l4) * LDS + ct * 16 + l16];
-#pragma unroll
-              for (int q = 0; q < NDT; ++q)
-                acc[c][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[q * 16], sv, acc[c][q], 0, 0, 0);
-            }
+                for (int q = 0; q < NDT; ++q)
+                  acc[c][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[q * 16], sv, acc[c][q], 0, 0, 0);
+                if (r % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+              }
           }
         }
       }
@@ -747,6 +784,13 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
   }
 }
 
+// W32 (tail_base / Dp = V rows) below 4 GiB and V below 2^24.
+inline bool hyb_addressable(int Dp, int Dt, uint32_t tail_base) {
+  const uint64_t V = (uint64_t)tail_base / (uint64_t)Dp;
+  const uint64_t bytes = 4 * V * (uint64_t)(Dp + Dt);
+  return V < (1u << 24) && bytes < (1ull << 32);
+}
+
 template <int NK2>
 hipError_t launch_hyb(const tlda_csr_batch& b, const float* W32, const float* mw32, int D, int Dp,
                       int Dt, uint32_t tail_base, const float* Phi, int K, int nblk,
@@ -773,13 +817,19 @@ hipError_t launch_wide(const tlda_csr_batch& b, const float* W32, const float* m
                        int Dt, uint32_t tail_base, const float* Phi, int K, int nblk,
                        float* partial, int* block_counts, float* Xout, float* phi_copy,
                        double* gsq, hipStream_t s) {
-  if constexpr (DQ == 112 && KQ == 112) {   // the hybrid kernel (no spills at this shape)
-    if (D <= 100)
-      return launch_hyb<25>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,
+  if constexpr (DQ == 112 && KQ == 112) {
+    // the hybrid kernel, whose gathers address W32 (V rows of Dp floats from
+    // element 0, then V rows of Dt from tail_base = V Dp) with 32-bit byte
+    // offsets from 24-bit row numbers; past that, the 8-wave kernel
+    if (hyb_addressable(Dp, Dt, tail_base)) {
+      if (D <= 100)
+        return launch_hyb<25>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,
+                              block_counts, Xout, phi_copy, gsq, s);
+      return launch_hyb<28>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,
                             block_counts, Xout, phi_copy, gsq, s);
-    return launch_hyb<28>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,
-                          block_counts, Xout, phi_copy, gsq, s);
-  } else if constexpr (DQ == 112 && NK2 == DQ / 4) {
+    }
+  }
+  if constexpr (DQ == 112 && NK2 == DQ / 4) {
     if (D <= 100)
       return launch_wide<DQ, KQ, 25>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,
                                      block_counts, Xout, phi_copy, gsq, s);
@@ -836,7 +886,7 @@ hipError_t launch_fused_g(int G, const tlda_csr_batch& b, const float* W32, cons
 
 // Shapes the fused kernel covers: D, K <= 128 (each padded to 16, 32, 64,
 // 112 or 128); the wide kernels keep Phi, X and S in LDS, at most 97 KB per
-// block for the 8-wave kernel (128 x 128) and 114 KB for the hybrid.
+// block for the 8-wave kernel (128 x 128) and 99 KB for the hybrid.
 bool fused_supported(int D, int K, int Dp) {
   return mfma_bucket(D) > 0 && mfma_bucket(K) > 0 && Dp <= 128;
 }
