@@ -102,6 +102,24 @@ __global__ void __launch_bounds__(256) k_mw16(const uint16_t* __restrict__ W16,
   if (tid == 0) mw16[d] = (float)red[0];
 }
 
+// Sum over each group of G lanes (G <= 16, aligned), the result in all of
+// them: a DPP butterfly inside the 16-lane row (pairs, quads, mirrored halves
+// of 8, mirrored halves of 16), the same pairings as lane xors 1, 2, 4, 8.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF,
+                                                            0xF, false));
+}
+template <int G>
+__device__ __forceinline__ float group_sum(float s) {
+  static_assert(G >= 1 && G <= 16 && (G & (G - 1)) == 0, "group of 1 to 16 lanes");
+  if constexpr (G >= 2) s += dpp_mov<0xB1>(s);    // quad_perm [1, 0, 3, 2]
+  if constexpr (G >= 4) s += dpp_mov<0x4E>(s);    // quad_perm [2, 3, 0, 1]
+  if constexpr (G >= 8) s += dpp_mov<0x141>(s);   // row_half_mirror
+  if constexpr (G >= 16) s += dpp_mov<0x140>(s);  // row_mirror
+  return s;
+}
+
 // Waves per block: 16 when both D and K are padded past 64 and 8 when one is,
 // so that the R1 accumulators (DQ x KQ per block) spread over more waves and
 // each keeps few enough registers for 4 waves per SIMD (with 4-wave blocks
@@ -125,8 +143,8 @@ struct Bf16Shape {
 // The work of one block: block `blk` of `nblk` blocks that share one batch,
 // in row tiles of TR documents (64 for the single-batch kernels; the
 // multi-slice kernels also take 32).  LDS comes from the caller (Xs: TR x LDA,
-// XsT: DQ x LDT, SsT: KQ x LDT BF16 values, wave_kept: NW ints), so one kernel
-// can serve several shapes.
+// XsT: DQ x LDT, SsT: KQ x LDT BF16 values, wave_kept: NW ints, ent: 64 NW
+// entries), so one kernel can serve several shapes.
 template <int DQ, int KQ, int G, int MODE, int NW, int TR = kTile>
 __device__ __forceinline__ void cp_bf16_block(
     int blk, int nblk, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
@@ -135,7 +153,7 @@ __device__ __forceinline__ void cp_bf16_block(
     const float* __restrict__ Phi, int K, float* __restrict__ partial,
     int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy,
     uint16_t* __restrict__ Xs, uint16_t* __restrict__ XsT, uint16_t* __restrict__ SsT,
-    int* __restrict__ wave_kept) {
+    int* __restrict__ wave_kept, int2* __restrict__ ent) {
   typedef Bf16Shape<DQ, KQ, NW, TR> Sh;
   static_assert(TR % 32 == 0, "tile rows: a multiple of the 32-row MFMA step");
   constexpr bool kCp = MODE != kWhitenOnly;
@@ -144,12 +162,18 @@ __device__ __forceinline__ void cp_bf16_block(
   constexpr int RPB = NW * RPW;
   constexpr int PASSES = (TR + RPB - 1) / RPB;
   constexpr int SLOTS = G >= kNB ? 1 : kNB / G;
+  // G >= kNB: a step's entries sit in lanes 0 .. kNB - 1 of the group, which
+  // write them to the group's LDS row (G entries, one per lane); every lane
+  // then reads all kNB with 16-byte reads at fixed offsets
+  constexpr bool kStage = G >= kNB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
   const int gl = lane % G;
   const int c8 = gl * 8;               // first column of this lane (c8 < Dh <= DQ)
   const bool pair_lo = ((lane / G) & 1) == 0;
   const unsigned char* W16b = reinterpret_cast<const unsigned char*>(W16);
+  int2* my_ent = ent + (lane / G) * G + wave * 64;
+  const uint32_t row_bytes = (uint32_t)Dh * 2u, col_bytes = (uint32_t)c8 * 2u;
 
   if (kCp) {
     for (int e = blk * kThreads + tid; e < D * K; e += nblk * kThreads)
@@ -240,16 +264,36 @@ __device__ __forceinline__ void cp_bf16_block(
             inexact |= (__float_as_uint(cval[q]) & 0xffffu) != 0u;
           }
           if (jb + kNB < e) fetch(jb + kNB);      // next step's entries, in flight meanwhile
-          // all gathers first: 16 bytes of row c of W16 per lane, 32-bit offsets
+          uint32_t cs[kNB];
+          float v[kNB];
+          if constexpr (kStage) {
+            // the previous step's reads of the row were issued earlier by this
+            // wave, and one wave's LDS operations complete in order
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            my_ent[gl] = make_int2(cidx[0], __float_as_int(cval[0]));
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            int2 en[kNB];
+#pragma unroll
+            for (int t = 0; t < kNB; ++t) en[t] = my_ent[t];
+#pragma unroll
+            for (int t = 0; t < kNB; ++t) {
+              cs[t] = (uint32_t)en[t].x;
+              v[t] = __int_as_float(en[t].y);
+            }
+          } else {
+#pragma unroll
+            for (int t = 0; t < kNB; ++t) {
+              cs[t] = (uint32_t)__shfl(cidx[t / G < SLOTS ? t / G : 0], t % G, G);
+              v[t] = __shfl(cval[t / G < SLOTS ? t / G : 0], t % G, G);
+            }
+          }
+          // all gathers first: 16 bytes of row c of W16 per lane, 32-bit byte
+          // offsets from a 24-bit multiply (V < 2^24, V Dh 2 < 2^32)
           u32x4 w[kNB];
 #pragma unroll
-          for (int t = 0; t < kNB; ++t) {
-            const uint32_t c = (uint32_t)__shfl(cidx[t / G < SLOTS ? t / G : 0], t % G, G);
-            w[t] = *reinterpret_cast<const u32x4*>(W16b + (c * (uint32_t)Dh + (uint32_t)c8) * 2u);
-          }
-          float v[kNB];
-#pragma unroll
-          for (int t = 0; t < kNB; ++t) v[t] = __shfl(cval[t / G < SLOTS ? t / G : 0], t % G, G);
+          for (int t = 0; t < kNB; ++t)
+            w[t] = *reinterpret_cast<const u32x4*>(W16b + (__umul24(cs[t], row_bytes) + col_bytes));
           if (!__any(inexact)) {
             // every count of the step is exact in BF16 (integers <= 256): one
             // dot-2 per column, w.lo * v + w.hi * 0 + a (products exact in FP32)
@@ -281,9 +325,7 @@ __device__ __forceinline__ void cp_bf16_block(
               }
           }
         }
-        float L = Lp;
-#pragma unroll
-        for (int off = 1; off < G; off <<= 1) L += __shfl_xor(L, off, G);
+        const float L = group_sum<G>(Lp);
         kept = (valid && L >= 3.f) ? 1 : 0;
         const float invL = kept ? 1.0f / L : 0.f;
 #pragma unroll
@@ -404,9 +446,10 @@ __global__ void __launch_bounds__(64 * (MODE == kWhitenOnly ? 4 : bf16_waves(DQ,
   __shared__ __attribute__((aligned(16))) uint16_t XsT[kCp ? DQ * Sh::LDT : 8];
   __shared__ __attribute__((aligned(16))) uint16_t SsT[kCp ? KQ * Sh::LDT : 8];
   __shared__ int wave_kept[NW];
+  __shared__ __attribute__((aligned(16))) int2 ent[G >= kNB ? 64 * NW : 2];
   cp_bf16_block<DQ, KQ, G, MODE, NW>(blockIdx.x, nblk, row_ptr, col_idx, val, n_rows, W16, mw16, Dh,
                                  Xin, D, Phi, K, partial, block_counts, Xout, phi_copy, Xs, XsT,
-                                 SsT, wave_kept);
+                                 SsT, wave_kept, ent);
 }
 
 // Several batches (the slices of a batched run, each with its own
@@ -423,6 +466,7 @@ __global__ void __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) k_cp_bf16_multi(
   __shared__ __attribute__((aligned(16))) uint16_t XsT[64 * LDT];
   __shared__ __attribute__((aligned(16))) uint16_t SsT[64 * LDT];
   __shared__ int wave_kept[NW];
+  __shared__ __attribute__((aligned(16))) int2 ent[64 * NW];
   const SliceStep& d = sl[blk_slice[blockIdx.x]];
   const int blk = blockIdx.x - d.blk0;
 #define TLDA_MULTI(DQ_, KQ_, G_)                                                               \
@@ -430,7 +474,7 @@ __global__ void __launch_bounds__(64 * NW, NW == 4 ? 3 : 4) k_cp_bf16_multi(
     cp_bf16_block<DQ_, KQ_, G_, kFused, NW, TR>(blk, d.nblk, d.row_ptr, d.col_idx, d.val,       \
                                                d.n_rows, d.W16, d.mw16, d.Dh, nullptr, d.D,    \
                                                d.Phi, d.K, d.partial, d.block_counts, nullptr, \
-                                               d.phi_copy, Xs, XsT, SsT, wave_kept);            \
+                                               d.phi_copy, Xs, XsT, SsT, wave_kept, ent);       \
     break;
   switch (d.shape) {
     TLDA_MULTI(32, 16, 1) TLDA_MULTI(32, 16, 2) TLDA_MULTI(32, 16, 4)
