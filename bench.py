@@ -384,11 +384,11 @@ def run_online(args) -> None:
 
 def fp32_fused_kernel(D: int, K: int) -> str:
     """The FP32 fused step's kernel for this shape (D and K are padded to 16,
-    32, 64, 112 or 128): the hybrid kernel when both pad to 112, the wide one
-    when either passes 64, else the small-shape kernel."""
+    32, 64, 112 or 128): the hybrid kernel when both pad to 64 or both to
+    112, the wide one when either passes 64, else the small-shape kernel."""
     def bucket(n):
         return next(q for q in (16, 32, 64, 112, 128) if n <= q)
-    if bucket(D) == 112 and bucket(K) == 112:
+    if bucket(D) == bucket(K) and bucket(D) in (64, 112):
         return "k_whiten_cp_hyb"
     return "k_whiten_cp_wide" if D > 64 or K > 64 else "k_whiten_cp"
 

@@ -16,12 +16,14 @@
 // count (and its share of a copy of Phi); the finish kernel adds them in
 // block order, forms the gradient and updates Phi.
 //
-// Two families of instances: D, K <= 64 (padded 16, 32 or 64) take 4-wave
+// Three families of instances: D, K <= 64 (padded 16, 32 or 64) take 4-wave
 // blocks, G = Dp / 4 <= 16 lanes per document and 64- or 32-row tiles;
 // shapes with D or K padded to 112 or 128 take 8-wave blocks, 32 lanes per
-// document (one float4 of the up to 128 columns each) and 64-row tiles, so
+// document (one float4 of the up to 128 columns each) and 32-row tiles, so
 // that two blocks fit on a CU (LDS and 128 registers per lane) and one
-// block's gathers overlap the other's matrix work.
+// block's gathers overlap the other's matrix work; and the two shapes of the
+// hybrid kernel (64 x 64 and 112 x 112), one 16-wave block per CU whose
+// waves split into whitening and matrix roles.
 #include "tlda_internal.h"
 
 namespace tlda {
@@ -496,24 +498,35 @@ __global__ void __launch_bounds__(512, wide_min_waves(DQ, KQ)) k_whiten_cp_wide(
   }
 }
 
-// Sum over each 32-lane half of the wave, the result in all its lanes: DPP
-// within 16-lane rows, then the two rows of the half through a swizzle.
-__device__ __forceinline__ float half_sum32(float s) {
-  s += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, s), 0xB1, 0xF, 0xF, false));
-  s += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, s), 0x4E, 0xF, 0xF, false));
-  s += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, s), 0x141, 0xF, 0xF, false));
-  s += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, s), 0x140, 0xF, 0xF, false));
-  // lane ^ 16 within each group of 32 (swizzle bit mode: and 0x1f, or 0, xor 0x10)
-  return s + __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, s), 0x401F));
+// Sum over each aligned group of G lanes (16 or 32), the result in all of
+// them: DPP inside the 16-lane row (pairs, quads, mirrored halves of 8 and of
+// 16), then for G = 32 the two rows of the group through a swizzle.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF,
+                                                            0xF, false));
+}
+template <int G>
+__device__ __forceinline__ float doc_sum(float s) {
+  static_assert(G == 16 || G == 32, "documents of 16 or 32 lanes");
+  s += dpp_mov<0xB1>(s);    // quad_perm [1, 0, 3, 2]
+  s += dpp_mov<0x4E>(s);    // quad_perm [2, 3, 0, 1]
+  s += dpp_mov<0x141>(s);   // row_half_mirror
+  s += dpp_mov<0x140>(s);   // row_mirror
+  if constexpr (G == 32)    // lane ^ 16 (swizzle bit mode: and 0x1f, or 0, xor 0x10)
+    s += __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, s), 0x401F));
+  return s;
 }
 
 // ---------------------------------------------------------------------------
-// 112 x 112 (D and K in 65..112, the streaming-scale K = D = 100): one
-// 16-wave block per CU with the waves split by role.  Waves 0-11 (three per
-// SIMD) whiten 48-row tiles into one of two X buffers; waves 12-15 (one per
-// SIMD) run S = X_t Phi and R1 += X_t^T S^2 on the other buffer, each owning
-// column tiles c and c + 4 of S and of R1.  One barrier per tile hands a
-// buffer over.  In the 8-wave kernel a CU alternates between gathers and
+// 112 x 112 (D and K in 65..112, the streaming-scale K = D = 100; G = 32
+// lanes per document) and 64 x 64 (D and K in 33..64, the tweet-shaped
+// K = D = 50; G = 16): one 16-wave block per CU with the waves split by
+// role.  Waves 0-11 (three per SIMD) whiten 48-row tiles, 64 / G documents
+// per wave at a time, into one of two X buffers; waves 12-15 (one per SIMD)
+// run S = X_t Phi and R1 += X_t^T S^2 on the other buffer, each owning
+// column tiles c and c + 4 of S and of R1 (at 64 x 64 one tile each).  One
+// barrier per tile hands a buffer over.  In the 8-wave kernel a CU alternates between gathers and
 // matrix work and the two phases add up; here the matrix waves' work runs
 // beside the next tile's gathers.  What is left of the matrix phases' cost
 // is their issue slots on the whitening waves' SIMDs, so the whitening is
@@ -531,12 +544,13 @@ __device__ __forceinline__ float half_sum32(float s) {
 // rows in the order the S accumulators hold them.  The per-row arithmetic
 // (the nonzeros of a row in CSR order, one FMA each) is the 8-wave kernel's;
 // L, a sum of the row's counts, is added in another order, which changes
-// nothing for integer counts.  Registers: 102 per lane, no spills (the
-// 112 x 128 and 128 x 128 instances would spill, so they stay on the 8-wave
-// kernel); LDS 99 KB.  The buffer descriptor needs the W32 copy below 4 GiB
-// and V below 2^24 (a 24-bit multiply); launch_wide checks both.
+// nothing for integer counts.  Registers: 102 per lane at 112 x 112 and 84
+// at 64 x 64, no spills (the 112 x 128 and 128 x 128 instances would spill,
+// so they stay on the 8-wave kernel); LDS 99 KB and 48 KB.  The buffer
+// descriptor needs the W32 copy below 4 GiB and V below 2^24 (a 24-bit
+// multiply); the launchers check both.
 // ---------------------------------------------------------------------------
-template <int DQ, int KQ, int NK2>
+template <int DQ, int KQ, int NK2, int G>
 __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const float* __restrict__ val, int n_rows, const float* __restrict__ W32,
@@ -545,7 +559,7 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
     int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy,
     double* __restrict__ gsq) {
   constexpr int NP = 12, NC = 4, kThreads = 1024;   // whitening and matrix waves
-  constexpr int T = 48, G = 32, RPW = 2, RPB = NP * RPW, PASSES = T / RPB;
+  constexpr int T = 48, RPW = 64 / G, RPB = NP * RPW, PASSES = T / RPB;
   constexpr int NB = 8;                              // nonzeros per gather step
   constexpr int LDX = DQ + 4, LDP = KQ;
   constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = NK2;
@@ -554,7 +568,7 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
   __shared__ __attribute__((aligned(16))) float Ps[DQ * LDP];
   __shared__ __attribute__((aligned(16))) float Xs[2][T * LDX];
   __shared__ int wave_kept[NP];
-  __shared__ __attribute__((aligned(16))) int2 ent[NP][2][G];   // (column, count) per document entry
+  __shared__ __attribute__((aligned(16))) int2 ent[NP][64 / G][G];   // (column, count) per entry
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
 
@@ -568,7 +582,7 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
   __syncthreads();
 
   if (wave < NP) {
-    const int gl = lane & (G - 1), half = lane >> 5;
+    const int gl = lane & (G - 1), grp = lane / G;   // lane in its document, document in the wave
     const int c4 = gl * 4;
     const bool active = c4 < D;
     const bool in_lds = c4 < DQ;
@@ -584,7 +598,7 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
     auto doc_row = [&](int g) -> int {
       if (g >= n_pass) return -1;
       const int tile = blockIdx.x + (g / PASSES) * nblk;
-      const int row = tile * T + (g % PASSES) * RPB + wave * RPW + half;
+      const int row = tile * T + (g % PASSES) * RPB + wave * RPW + grp;
       return row < n_rows ? row : -1;
     };
     auto load_rp = [&](int g, int& b, int& e) {
@@ -620,7 +634,7 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
         float* X = Xs[s & 1];
 #pragma unroll 1
         for (int pass = 0; pass < PASSES; ++pass, ++g) {
-          const int lr = pass * RPB + wave * RPW + half;
+          const int lr = pass * RPB + wave * RPW + grp;
           const int row = doc_row(g);
           const int b = b0, e = e0;
           int c_cur = cc;
@@ -630,12 +644,12 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
           e0 = e1;
           load_rp(g + 2, b1, e1);
           float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-          float L = half_sum32(v_cur);   // the first chunk's counts, before its gathers
-          int2* my_ent = ent[wave][half];
+          float L = doc_sum<G>(v_cur);   // the first chunk's counts, before its gathers
+          int2* my_ent = ent[wave][grp];
           for (int base = b; base < e; base += G) {
             if (base != b) {
               load_csr(base, e, c_cur, v_cur);
-              L += half_sum32(v_cur);
+              L += doc_sum<G>(v_cur);
             }
             // this chunk's entries into the wave's LDS rows (the previous
             // chunk's reads were issued earlier by this same wave, and one
@@ -791,7 +805,7 @@ inline bool hyb_addressable(int Dp, int Dt, uint32_t tail_base) {
   return V < (1u << 24) && bytes < (1ull << 32);
 }
 
-template <int NK2>
+template <int DQ, int KQ, int NK2, int G>
 hipError_t launch_hyb(const tlda_csr_batch& b, const float* W32, const float* mw32, int D, int Dp,
                       int Dt, uint32_t tail_base, const float* Phi, int K, int nblk,
                       float* partial, int* block_counts, float* Xout, float* phi_copy,
@@ -799,14 +813,14 @@ hipError_t launch_hyb(const tlda_csr_batch& b, const float* W32, const float* mw
   if (partial == nullptr) {
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, k_whiten_cp_hyb<112, 112, NK2>, 1024, 0);
+        &per_cu, k_whiten_cp_hyb<DQ, KQ, NK2, G>, 1024, 0);
     *block_counts = per_cu;
     return e;
   }
   // as in launch_wide: clamped loads read the row pointers when there are no nonzeros
   const int32_t* ci = b.nnz > 0 ? b.col_idx : b.row_ptr;
   const float* va = b.nnz > 0 ? b.val : reinterpret_cast<const float*>(b.row_ptr);
-  launch_main(k_whiten_cp_hyb<112, 112, NK2>, dim3(nblk), dim3(1024), 0, s, b.row_ptr, ci, va,
+  launch_main(k_whiten_cp_hyb<DQ, KQ, NK2, G>, dim3(nblk), dim3(1024), 0, s, b.row_ptr, ci, va,
               b.n_rows, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial, block_counts,
               Xout, phi_copy, gsq);
   return hipGetLastError();
@@ -823,10 +837,10 @@ hipError_t launch_wide(const tlda_csr_batch& b, const float* W32, const float* m
     // offsets from 24-bit row numbers; past that, the 8-wave kernel
     if (hyb_addressable(Dp, Dt, tail_base)) {
       if (D <= 100)
-        return launch_hyb<25>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,
-                              block_counts, Xout, phi_copy, gsq, s);
-      return launch_hyb<28>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,
-                            block_counts, Xout, phi_copy, gsq, s);
+        return launch_hyb<112, 112, 25, 32>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk,
+                                            partial, block_counts, Xout, phi_copy, gsq, s);
+      return launch_hyb<112, 112, 28, 32>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk,
+                                          partial, block_counts, Xout, phi_copy, gsq, s);
     }
   }
   if constexpr (DQ == 112 && NK2 == DQ / 4) {
@@ -897,7 +911,8 @@ bool fused_wide(int D, int K) { return mfma_bucket(D) > 64 || mfma_bucket(K) > 6
 }  // namespace
 
 int fused_tile_rows(int D, int K) {
-  if (!fused_wide(D, K)) return cp_mfma_tile_rows(D, K);
+  if (!fused_wide(D, K))   // the hybrid kernel at 64 x 64, the 4-wave kernel below
+    return mfma_bucket(D) == 64 && mfma_bucket(K) == 64 ? 48 : cp_mfma_tile_rows(D, K);
   return mfma_bucket(D) == 112 && mfma_bucket(K) == 112 ? 48 : 32;   // hybrid : wide
 }
 
@@ -936,6 +951,15 @@ hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const flo
                             int nblk, float* partial, int* block_counts, float* Xout,
                             float* phi_copy, double* gsq, hipStream_t s) {
   const int dq = mfma_bucket(D), kq = mfma_bucket(K);
+  // D and K in 33..64: the hybrid kernel, 16 lanes per document (13 k-steps
+  // of S = X_t Phi up to D = 52)
+  if (dq == 64 && kq == 64 && hyb_addressable(Dp, Dt, tail_base)) {
+    if (D <= 52)
+      return launch_hyb<64, 64, 13, 16>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,
+                                        block_counts, Xout, phi_copy, gsq, s);
+    return launch_hyb<64, 64, 16, 16>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,
+                                      block_counts, Xout, phi_copy, gsq, s);
+  }
   const int T = fused_tile_rows(D, K);
   int G = Dp / 4;   // lanes per document: Dp is 4, 8, 16, 32 or 64 here
   if (G < 1) G = 1;
