@@ -172,7 +172,7 @@ __device__ __forceinline__ void cp_bf16_block(
   const int c8 = gl * 8;               // first column of this lane (c8 < Dh <= DQ)
   const bool pair_lo = ((lane / G) & 1) == 0;
   const unsigned char* W16b = reinterpret_cast<const unsigned char*>(W16);
-  int2* my_ent = ent + (lane / G) * G + wave * 64;
+  int2* my_ent = ent + (kStage ? (lane / G) * G + wave * 64 : 0);   // this group's LDS row
   const uint32_t row_bytes = (uint32_t)Dh * 2u, col_bytes = (uint32_t)c8 * 2u;
 
   if (kCp) {
