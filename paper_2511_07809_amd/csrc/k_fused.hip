@@ -16,14 +16,15 @@
 // count (and its share of a copy of Phi); the finish kernel adds them in
 // block order, forms the gradient and updates Phi.
 //
-// Three families of instances: D, K <= 64 (padded 16, 32 or 64) take 4-wave
-// blocks, G = Dp / 4 <= 16 lanes per document and 64- or 32-row tiles;
-// shapes with D or K padded to 112 or 128 take 8-wave blocks, 32 lanes per
+// Three families of instances: D and K both padded to 64, 112 or 128 take
+// the hybrid kernel, one 16-wave block per CU whose waves split into
+// whitening and matrix roles; the other shapes with D or K padded to 112 or
+// 128 (the other dimension 16 or 32) take 8-wave blocks, 32 lanes per
 // document (one float4 of the up to 128 columns each) and 32-row tiles, so
 // that two blocks fit on a CU (LDS and 128 registers per lane) and one
-// block's gathers overlap the other's matrix work; and the two shapes of the
-// hybrid kernel (64 x 64 and 112 x 112), one 16-wave block per CU whose
-// waves split into whitening and matrix roles.
+// block's gathers overlap the other's matrix work; the rest (D, K <= 64)
+// take 4-wave blocks, G = Dp / 4 <= 16 lanes per document and 64- or 32-row
+// tiles.
 #include "tlda_internal.h"
 
 namespace tlda {
@@ -519,14 +520,15 @@ __device__ __forceinline__ float doc_sum(float s) {
 }
 
 // ---------------------------------------------------------------------------
-// 112 x 112 (D and K in 65..112, the streaming-scale K = D = 100; G = 32
-// lanes per document) and 64 x 64 (D and K in 33..64, the tweet-shaped
-// K = D = 50; G = 16): one 16-wave block per CU with the waves split by
-// role.  Waves 0-11 (three per SIMD) whiten 48-row tiles, 64 / G documents
-// per wave at a time, into one of two X buffers; waves 12-15 (one per SIMD)
-// run S = X_t Phi and R1 += X_t^T S^2 on the other buffer, each owning
-// column tiles c and c + 4 of S and of R1 (at 64 x 64 one tile each).  One
-// barrier per tile hands a buffer over.  In the 8-wave kernel a CU alternates between gathers and
+// Every shape with D and K both padded to 64, 112 or 128 (the tweet-shaped
+// K = D = 50 at 64 x 64, the streaming-scale K = D = 100 at 112 x 112): one
+// 16-wave block per CU with the waves split by role.  G = 16 lanes per
+// document when D pads to 64, else 32.  Waves 0-11 (three per SIMD) whiten
+// 48-row tiles, 64 / G documents per wave at a time, into one of two X
+// buffers; waves 12-15 (one per SIMD) run S = X_t Phi and R1 += X_t^T S^2
+// on the other buffer, each owning column tiles c and c + 4 of S and of R1
+// (one tile each when K pads to 64, two each at 128).  One barrier per tile
+// hands a buffer over.  In the 8-wave kernel a CU alternates between gathers and
 // matrix work and the two phases add up; here the matrix waves' work runs
 // beside the next tile's gathers.  What is left of the matrix phases' cost
 // is their issue slots on the whitening waves' SIMDs, so the whitening is
@@ -544,11 +546,11 @@ __device__ __forceinline__ float doc_sum(float s) {
 // rows in the order the S accumulators hold them.  The per-row arithmetic
 // (the nonzeros of a row in CSR order, one FMA each) is the 8-wave kernel's;
 // L, a sum of the row's counts, is added in another order, which changes
-// nothing for integer counts.  Registers: 102 per lane at 112 x 112 and 84
-// at 64 x 64, no spills (the 112 x 128 and 128 x 128 instances would spill,
-// so they stay on the 8-wave kernel); LDS 99 KB and 48 KB.  The buffer
-// descriptor needs the W32 copy below 4 GiB and V below 2^24 (a 24-bit
-// multiply); the launchers check both.
+// nothing for integer counts.  Registers: 84 to 109 per lane, no spills
+// (102 at 112 x 112, 84 at 64 x 64, 109 at 128 x 128); LDS 48 KB at 64 x 64,
+// 99 KB at 112 x 112, 121 KB at 128 x 128.  The buffer descriptor needs the
+// W32 copy below 4 GiB and V below 2^24 (a 24-bit multiply); the launchers
+// check both.
 // ---------------------------------------------------------------------------
 template <int DQ, int KQ, int NK2, int G>
 __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
@@ -831,16 +833,18 @@ hipError_t launch_wide(const tlda_csr_batch& b, const float* W32, const float* m
                        int Dt, uint32_t tail_base, const float* Phi, int K, int nblk,
                        float* partial, int* block_counts, float* Xout, float* phi_copy,
                        double* gsq, hipStream_t s) {
-  if constexpr (DQ == 112 && KQ == 112) {
+  if constexpr (DQ >= 64 && KQ >= 64) {
     // the hybrid kernel, whose gathers address W32 (V rows of Dp floats from
     // element 0, then V rows of Dt from tail_base = V Dp) with 32-bit byte
     // offsets from 24-bit row numbers; past that, the 8-wave kernel
+    constexpr int G = DQ == 64 ? 16 : 32;
     if (hyb_addressable(Dp, Dt, tail_base)) {
-      if (D <= 100)
-        return launch_hyb<112, 112, 25, 32>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk,
-                                            partial, block_counts, Xout, phi_copy, gsq, s);
-      return launch_hyb<112, 112, 28, 32>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk,
-                                          partial, block_counts, Xout, phi_copy, gsq, s);
+      if (D <= (DQ == 64 ? 52 : DQ == 112 ? 100 : 116))
+        return launch_hyb<DQ, KQ, (DQ == 64 ? 13 : DQ == 112 ? 25 : 29), G>(
+            b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial, block_counts, Xout,
+            phi_copy, gsq, s);
+      return launch_hyb<DQ, KQ, DQ / 4, G>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk,
+                                           partial, block_counts, Xout, phi_copy, gsq, s);
     }
   }
   if constexpr (DQ == 112 && NK2 == DQ / 4) {
@@ -900,7 +904,7 @@ hipError_t launch_fused_g(int G, const tlda_csr_batch& b, const float* W32, cons
 
 // Shapes the fused kernel covers: D, K <= 128 (each padded to 16, 32, 64,
 // 112 or 128); the wide kernels keep Phi, X and S in LDS, at most 97 KB per
-// block for the 8-wave kernel (128 x 128) and 99 KB for the hybrid.
+// block for the 8-wave kernel and 121 KB for the hybrid (128 x 128).
 bool fused_supported(int D, int K, int Dp) {
   return mfma_bucket(D) > 0 && mfma_bucket(K) > 0 && Dp <= 128;
 }
@@ -911,9 +915,8 @@ bool fused_wide(int D, int K) { return mfma_bucket(D) > 64 || mfma_bucket(K) > 6
 }  // namespace
 
 int fused_tile_rows(int D, int K) {
-  if (!fused_wide(D, K))   // the hybrid kernel at 64 x 64, the 4-wave kernel below
-    return mfma_bucket(D) == 64 && mfma_bucket(K) == 64 ? 48 : cp_mfma_tile_rows(D, K);
-  return mfma_bucket(D) == 112 && mfma_bucket(K) == 112 ? 48 : 32;   // hybrid : wide
+  if (mfma_bucket(D) >= 64 && mfma_bucket(K) >= 64) return 48;   // the hybrid kernel
+  return fused_wide(D, K) ? 32 : cp_mfma_tile_rows(D, K);        // 8-wave : 4-wave
 }
 
 int w32_tail_cols(int D, int K) {
@@ -952,7 +955,7 @@ hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const flo
                             float* phi_copy, double* gsq, hipStream_t s) {
   const int dq = mfma_bucket(D), kq = mfma_bucket(K);
   // D and K in 33..64: the hybrid kernel, 16 lanes per document (13 k-steps
-  // of S = X_t Phi up to D = 52)
+  // of S = X_t Phi up to D = 52); wider hybrid shapes go through launch_wide
   if (dq == 64 && kq == 64 && hyb_addressable(Dp, Dt, tail_base)) {
     if (D <= 52)
       return launch_hyb<64, 64, 13, 16>(b, W32, mw32, D, Dp, Dt, tail_base, Phi, K, nblk, partial,

@@ -355,16 +355,17 @@ def test_cp_step_full_size_streaming_shape():
 @pytest.mark.parametrize("D,K", [(5, 5), (10, 7), (20, 20), (33, 40), (50, 50), (64, 64),
                                  (100, 100), (128, 96), (150, 40), (256, 56), (56, 256),
                                  (97, 100), (104, 110), (36, 100), (65, 70),
-                                 (52, 64), (53, 34), (112, 112), (101, 66)])
+                                 (52, 64), (53, 34), (112, 112), (101, 66),
+                                 (116, 128), (120, 120), (60, 128), (100, 50)])
 def test_fused_step_matches_oracle(D, K):
     """tlda_whiten_cp_step against the oracle's whitening and gradient on the
     same batch (rows with dropped and empty documents included).  D and K
-    both padded to 64 take the hybrid kernel with 16 lanes per document and
-    13 k-steps of S = X_t Phi (D <= 52: 33, 50, 52) or 16 (53, 64); both
-    padded to 112 take it with 32 lanes, 25 k-steps (D <= 100: 65, 97, 100)
-    or 28 (101, 104, 112), and a W32 tail copy of 4 or 8 columns where
-    D mod 32 is 1 to 8 (all of those but 112); (36, 100) and (128, 96) take
-    the 8-wave wide kernel, the small shapes the 4-wave kernel, and the
+    both padded to 64, 112 or 128 take the hybrid kernel: 16 lanes per
+    document when D pads to 64, with 13 k-steps of S = X_t Phi (D <= 52: 33,
+    36, 50, 52) or 16 (53, 60, 64); 32 lanes otherwise, with 25 k-steps
+    (D <= 100 at 112: 65, 97, 100) or 28 (101, 104, 112), 29 (D <= 116 at
+    128: 116) or 32 (120, 128), and a W32 tail copy of 4 or 8 columns where
+    D mod 32 is 1 to 8.  The small shapes take the 4-wave kernel, the
     shapes past 128 the split path."""
     V = 400
     rng = np.random.default_rng(D * 7 + K)
