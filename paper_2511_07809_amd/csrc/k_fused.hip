@@ -528,17 +528,17 @@ __device__ __forceinline__ float doc_sum(float s) {
 // buffers; waves 12-15 (one per SIMD) run S = X_t Phi and R1 += X_t^T S^2
 // on the other buffer, each owning column tiles c and c + 4 of S and of R1
 // (one tile each when K pads to 64, two each at 128).  One barrier per tile
-// hands a buffer over.  In the 8-wave kernel a CU alternates between gathers and
-// matrix work and the two phases add up; here the matrix waves' work runs
-// beside the next tile's gathers.  What is left of the matrix phases' cost
+// hands a buffer over.  In the 8-wave kernel a CU alternates between gathers
+// and matrix work and the two phases add up; here the matrix waves' work
+// runs beside the next tile's gathers.  What is left of the matrix phases' cost
 // is their issue slots on the whitening waves' SIMDs, so the whitening is
 // written for few instructions per nonzero:
 //  * the W-row gathers are buffer loads from a 32-bit byte offset, one
 //    24-bit multiply-add per nonzero (no 64-bit address arithmetic);
-//  * a document's CSR entries (up to 32, one per lane, loaded one document
-//    ahead) go to the wave's own LDS rows once, and every lane reads eight
-//    of them per step with two 16-byte LDS reads at fixed offsets (instead
-//    of two lane shuffles per nonzero);
+//  * a document's CSR entries (G at a time, one per lane, loaded one
+//    document ahead) go to the wave's own LDS rows once, and every lane
+//    reads eight of them per step with four 16-byte LDS reads at fixed
+//    offsets (instead of two lane shuffles per nonzero);
 //  * the word count L is summed across the document's lanes with DPP and one
 //    swizzle as soon as its entries arrive, before its gathers.
 // Entries past a document's end are (column 0, count 0): they gather row 0
