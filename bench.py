@@ -13,8 +13,9 @@ and the whitening refresh that precede the CP passes are run and timed in the
 same process and reported beside the steps.  The K timed steps run twice:
 eagerly, one library call per step, with events attached to each main
 kernel's dispatch (the kernel times of the roofline), and as one captured HIP
-graph of the same K steps (tlda_graph_capture_steps), replayed 5 times; the
-median replay gives `value` for the fused path over resident batches (eager
+graph of the same K steps (tlda_graph_capture_steps), replayed 3 times untimed
+and then 5 times timed; the median timed replay gives `value` for the fused
+path over resident batches (eager
 otherwise; --streamed stages every batch from pinned host memory inside the
 timed region).  An untimed fit of both precisions from the same start
 reports their topic-recovery errors after the same passes.  The
@@ -37,6 +38,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 GRAPH_REPLAYS = 5              # timed replays of the captured K steps (median reported)
+GRAPH_WARM_REPLAYS = 3         # untimed replays before them (the clocks settle over ~25 ms)
 FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector / FP32 matrix, TFLOP/s
 BF16_MFMA_PEAK_TFLOPS = 2500.0 # MI355X dense BF16 matrix, TFLOP/s
 
@@ -910,7 +912,8 @@ def measure(tl, spec, args, precision: str, corpus, stream) -> dict:
             except tl.TldaError as err:      # e.g. FP32 steps above the fused shapes
                 log(f"[bench] {name}: steps not captured ({err}); eager only")
                 continue
-            tl.tlda_graph_launch(g)                  # untimed replay
+            for _ in range(GRAPH_WARM_REPLAYS):      # untimed replays
+                tl.tlda_graph_launch(g)
             torch.cuda.synchronize()
             # GRAPH_REPLAYS timed replays of the K steps, each bracketed by
             # events and a synchronisation; the median replay gives the rate
