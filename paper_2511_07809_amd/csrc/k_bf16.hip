@@ -440,14 +440,18 @@ __global__ void __launch_bounds__(64 * (MODE == kWhitenOnly ? 4 : bf16_waves(DQ,
     const float* __restrict__ Phi, int K, int nblk, float* __restrict__ partial,
     int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy) {
   constexpr int NW = MODE == kWhitenOnly ? 4 : bf16_waves(DQ, KQ);
-  typedef Bf16Shape<DQ, KQ, NW> Sh;
   constexpr bool kCp = MODE != kWhitenOnly;
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[kCp ? kTile * Sh::LDA : 8];
+  // 16-wave blocks (D and K past 64) take 128-document tiles: half the
+  // barriers and matrix phases per document of 64-document tiles (118 against
+  // 125 us per streaming-scale batch), 104 KB of LDS at 128 x 128
+  constexpr int TRB = (kCp && NW == 16) ? 128 : kTile;
+  typedef Bf16Shape<DQ, KQ, NW, TRB> Sh;
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[kCp ? TRB * Sh::LDA : 8];
   __shared__ __attribute__((aligned(16))) uint16_t XsT[kCp ? DQ * Sh::LDT : 8];
   __shared__ __attribute__((aligned(16))) uint16_t SsT[kCp ? KQ * Sh::LDT : 8];
   __shared__ int wave_kept[NW];
   __shared__ __attribute__((aligned(16))) int2 ent[G >= kNB ? 64 * NW : 2];
-  cp_bf16_block<DQ, KQ, G, MODE, NW>(blockIdx.x, nblk, row_ptr, col_idx, val, n_rows, W16, mw16, Dh,
+  cp_bf16_block<DQ, KQ, G, MODE, NW, TRB>(blockIdx.x, nblk, row_ptr, col_idx, val, n_rows, W16, mw16, Dh,
                                  Xin, D, Phi, K, partial, block_counts, Xout, phi_copy, Xs, XsT,
                                  SsT, wave_kept, ent);
 }
