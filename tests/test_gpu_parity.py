@@ -356,7 +356,8 @@ def test_cp_step_full_size_streaming_shape():
                                  (100, 100), (128, 96), (150, 40), (256, 56), (56, 256),
                                  (97, 100), (104, 110), (36, 100), (65, 70),
                                  (52, 64), (53, 34), (112, 112), (101, 66),
-                                 (116, 128), (120, 120), (60, 128), (100, 50)])
+                                 (116, 128), (120, 120), (60, 128), (100, 50),
+                                 (20, 100), (100, 24)])
 def test_fused_step_matches_oracle(D, K):
     """tlda_whiten_cp_step against the oracle's whitening and gradient on the
     same batch (rows with dropped and empty documents included).  D and K
@@ -365,8 +366,10 @@ def test_fused_step_matches_oracle(D, K):
     36, 50, 52) or 16 (53, 60, 64); 32 lanes otherwise, with 25 k-steps
     (D <= 100 at 112: 65, 97, 100) or 28 (101, 104, 112), 29 (D <= 116 at
     128: 116) or 32 (120, 128), and a W32 tail copy of 4 or 8 columns where
-    D mod 32 is 1 to 8.  The small shapes take the 4-wave kernel, the
-    shapes past 128 the split path."""
+    D mod 32 is 1 to 8.  (20, 100) and (100, 24), one dimension padded to
+    32 and the other past 64, take the 8-wave wide kernel (the second with
+    the tail copy); the small shapes take the 4-wave kernel, the shapes past
+    128 the split path."""
     V = 400
     rng = np.random.default_rng(D * 7 + K)
     rows = [{}, {3: 1, 9: 1}]
