@@ -322,7 +322,8 @@ __device__ __forceinline__ void cp_finish_block(
   // serves up to kFinStage * kFinThreads entries.  With the squared Gram
   // entries given, the block needs only the rows of Phi0 its entries lie in
   // (at most two: FE <= K, since D <= 256 makes K >= 16 from D K >= 4096 on and
-  // K >= 32 from D K >= 8192 on, where FE = 32): ph then holds
+  // K >= 32 from D K >= 8192 on, where FE = 32, and FE = 64 only at K >= 64):
+  // ph then holds
   // Phi0[base .. base + n_ph).
   int cnt = 0;
   const bool have_counts = counts != nullptr && ncounts > 0;
@@ -641,14 +642,21 @@ hipError_t launch_cp_finish(const float* partial, int nblk, const int* counts, i
                             double theta, float beta, float* Phi, float* grad, double* R1,
                             int* n_out, const double* gsq, hipStream_t s) {
   const int DK = D * K;
-  // 16 entries per block, or 32 from D K = 8192 on: 64 (32) groups of 16
-  // lanes (32) need DK waves (DK / 2), and 32 entries keep a large D x K
-  // within one round of resident blocks while still giving every CU a block.
+  // 16 entries per block, or 32 from D K = 8192 on (64 when also K >= 64):
+  // 64 (32, 16) groups of 16 lanes (32, 64) need DK waves (DK / 2, DK / 4),
+  // and the wider blocks keep a large D x K within one round of resident
+  // blocks (at D = K = 100 with 256 partials, 64 entries per block take
+  // about 1 us less per step than 32).
   const bool wide = DK >= 8192;
-  const int fe = wide ? 32 : kFinEntries;
+  const bool wider = wide && K >= 64;
+  const int fe = wider ? 64 : wide ? 32 : kFinEntries;
   const int chunks = (DK + fe - 1) / fe;
   const dim3 grid(8 * ((chunks + 7) / 8));
-  if (wide)
+  if (wider)
+    hipLaunchKernelGGL(k_cp_finish<64>, grid, dim3(kFinThreads), sizeof(float) * (DK + kFinPad), s,
+                       partial, nblk, counts, ncounts, n_default, Phi0, D, K, alpha0, theta, beta,
+                       Phi, grad, R1, n_out, gsq);
+  else if (wide)
     hipLaunchKernelGGL(k_cp_finish<32>, grid, dim3(kFinThreads), sizeof(float) * (DK + kFinPad), s,
                        partial, nblk, counts, ncounts, n_default, Phi0, D, K, alpha0, theta, beta,
                        Phi, grad, R1, n_out, gsq);

@@ -250,22 +250,23 @@ def test_cp_gradient_and_step_match_oracle(D, K, n, theta):
     assert rel(Pd.cpu().numpy(), ref_p) < REL32
 
 
-@pytest.mark.parametrize("D,cap", [(50, c) for c in (1, 191, 192, 193, 200, 256, 300, 700, 1023,
-                                                     1024, 1100, 1500)]
-                         + [(100, c) for c in (1, 95, 96, 97, 128, 300, 511, 512, 513, 1024,
-                                               1500)])
-def test_cp_finish_at_every_partial_count(D, cap, monkeypatch):
+@pytest.mark.parametrize("D,K,cap", [(50, 50, c) for c in (1, 191, 192, 193, 200, 256, 300, 700,
+                                                           1023, 1024, 1100, 1500)]
+                         + [(100, 100, c) for c in (1, 47, 48, 49, 95, 96, 97, 128, 255, 256,
+                                                    257, 300, 511, 512, 513, 1024, 1500)]
+                         + [(256, 32, c) for c in (1, 96, 97, 511, 512, 700)])
+def test_cp_finish_at_every_partial_count(D, K, cap, monkeypatch):
     """The finish adds the reduction's per-block partials, nblk of them, and
     prefetches them by three routes.  At D = K = 50 (16 entries per block, 64
     groups of partials): none up to nblk = 192 (no lane has a full quad of
     four partials 64 apart), clamped loads from 193 to 1023 (the lanes whose
     first quad exists add it, the others drop theirs), and every prefetched
-    row present from 1024 on.  At D = K = 100 (32 entries per block, 32
-    groups): the same at 96, 97-511 and 512.  Each route has its own tail.
-    The block-count cap fixes nblk for a batch with more row tiles than any
-    cap here."""
+    row present from 1024 on.  At D = K = 100 (64 entries per block, 16
+    groups): the same at 48, 49-255 and 256; at D = 256, K = 32 (32 entries,
+    32 groups) at 96, 97-511 and 512.  Each route has its own tail.  The
+    block-count cap fixes nblk for a batch with more row tiles than any cap
+    here."""
     monkeypatch.setenv("TLDA_TUNE_CP_BLOCKS", str(cap))
-    K = D
     n = 150_000
     X, Phi = _cp_case(n, D, K, seed=cap)
     ctx = make_ctx(D, K, D, 1.0, 0.5)
