@@ -535,8 +535,9 @@ __device__ __forceinline__ float doc_sum(float s) {
 // written for few instructions per nonzero:
 //  * the W-row gathers are buffer loads from a 32-bit byte offset, one
 //    24-bit multiply-add per nonzero (no 64-bit address arithmetic);
-//  * a document's CSR entries (G at a time, one per lane, loaded one
-//    document ahead) go to the wave's own LDS rows once, and every lane
+//  * a document's CSR entries (32 at a time, 32 / G per lane, loaded one
+//    document ahead: a second chunk, a dependent round trip, is needed only
+//    past 32 nonzeros) go to the wave's own LDS rows once, and every lane
 //    reads eight of them per step with four 16-byte LDS reads at fixed
 //    offsets (instead of two lane shuffles per nonzero);
 //  * the word count L is summed across the document's lanes with DPP and one
@@ -546,8 +547,8 @@ __device__ __forceinline__ float doc_sum(float s) {
 // rows in the order the S accumulators hold them.  The per-row arithmetic
 // (the nonzeros of a row in CSR order, one FMA each) is the 8-wave kernel's;
 // L, a sum of the row's counts, is added in another order, which changes
-// nothing for integer counts.  Registers: 84 to 109 per lane, no spills
-// (102 at 112 x 112, 84 at 64 x 64, 109 at 128 x 128); LDS 48 KB at 64 x 64,
+// nothing for integer counts.  Registers: 90 to 109 per lane, no spills
+// (102 at 112 x 112, 90 at 64 x 64, 109 at 128 x 128); LDS 54 KB at 64 x 64,
 // 99 KB at 112 x 112, 121 KB at 128 x 128.  The buffer descriptor needs the
 // W32 copy below 4 GiB and V below 2^24 (a 24-bit multiply); the launchers
 // check both.
@@ -563,6 +564,7 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
   constexpr int NP = 12, NC = 4, kThreads = 1024;   // whitening and matrix waves
   constexpr int T = 48, RPW = 64 / G, RPB = NP * RPW, PASSES = T / RPB;
   constexpr int NB = 8;                              // nonzeros per gather step
+  constexpr int EPL = 32 / G, CH = G * EPL;          // CSR entries per lane, per chunk
   constexpr int LDX = DQ + 4, LDP = KQ;
   constexpr int NCT = KQ / 16, NDT = DQ / 16, NKS = NK2;
   constexpr int CT = (NCT + NC - 1) / NC;        // column tiles per consumer
@@ -570,7 +572,7 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
   __shared__ __attribute__((aligned(16))) float Ps[DQ * LDP];
   __shared__ __attribute__((aligned(16))) float Xs[2][T * LDX];
   __shared__ int wave_kept[NP];
-  __shared__ __attribute__((aligned(16))) int2 ent[NP][64 / G][G];   // (column, count) per entry
+  __shared__ __attribute__((aligned(16))) int2 ent[NP][64 / G][CH];   // (column, count) per entry
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
 
@@ -610,20 +612,29 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
       b = r < 0 ? 0 : b_;
       e = r < 0 ? 0 : e_;
     };
-    auto load_csr = [&](int b, int e, int& c, float& v) {
-      const int j = b + gl;
-      const bool in = j < e;
-      const int jc = in ? j : 0;
-      const int c_ = col_idx[jc];
-      const float v_ = val[jc];
-      c = in ? c_ : 0;
-      v = in ? v_ : 0.f;
+    auto load_csr = [&](int b, int e, int (&c)[EPL], float (&v)[EPL]) {
+#pragma unroll
+      for (int q = 0; q < EPL; ++q) {
+        const int j = b + gl + q * G;
+        const bool in = j < e;
+        const int jc = in ? j : 0;
+        const int c_ = col_idx[jc];
+        const float v_ = val[jc];
+        c[q] = in ? c_ : 0;
+        v[q] = in ? v_ : 0.f;
+      }
+    };
+    auto lane_sum = [](const float (&v)[EPL]) {
+      float x = v[0];
+#pragma unroll
+      for (int q = 1; q < EPL; ++q) x += v[q];
+      return x;
     };
     int b0 = 0, e0 = 0, b1 = 0, e1 = 0;
     load_rp(0, b0, e0);
     load_rp(1, b1, e1);
-    int cc = 0;
-    float cv = 0.f;
+    int cc[EPL] = {};
+    float cv[EPL] = {};
     if (n_pass > 0) load_csr(b0, e0, cc, cv);
     int kept_total = 0;
     int g = 0;
@@ -639,28 +650,34 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
           const int lr = pass * RPB + wave * RPW + grp;
           const int row = doc_row(g);
           const int b = b0, e = e0;
-          int c_cur = cc;
-          float v_cur = cv;
+          int c_cur[EPL];
+          float v_cur[EPL];
+#pragma unroll
+          for (int q = 0; q < EPL; ++q) {
+            c_cur[q] = cc[q];
+            v_cur[q] = cv[q];
+          }
           load_csr(b1, e1, cc, cv);
           b0 = b1;
           e0 = e1;
           load_rp(g + 2, b1, e1);
           float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-          float L = doc_sum<G>(v_cur);   // the first chunk's counts, before its gathers
+          float L = doc_sum<G>(lane_sum(v_cur));   // the first chunk's counts, before its gathers
           int2* my_ent = ent[wave][grp];
-          for (int base = b; base < e; base += G) {
+          for (int base = b; base < e; base += CH) {
             if (base != b) {
               load_csr(base, e, c_cur, v_cur);
-              L += doc_sum<G>(v_cur);
+              L += doc_sum<G>(lane_sum(v_cur));
             }
             // this chunk's entries into the wave's LDS rows (the previous
             // chunk's reads were issued earlier by this same wave, and one
             // wave's LDS operations complete in order)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            my_ent[gl] = make_int2(c_cur, __float_as_int(v_cur));
+#pragma unroll
+            for (int q = 0; q < EPL; ++q) my_ent[gl + q * G] = make_int2(c_cur[q], __float_as_int(v_cur[q]));
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            const int n_here = min(G, e - base);
+            const int n_here = min(CH, e - base);
             for (int t0 = 0; t0 < n_here; t0 += NB) {
               float4 w[NB];
               int2 en[NB];
