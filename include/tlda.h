@@ -56,7 +56,7 @@ typedef enum {
   TLDA_ERR_DEVICE = 7    /* a HIP runtime error                                    */
 } tlda_status;
 
-/* Limits of this build. */
+/* Limits of this library. */
 #define TLDA_MAX_D 256
 #define TLDA_MAX_K 256
 #define TLDA_MAX_DK 16384   /* D * K: Phi must fit in a 64 KiB LDS tile */

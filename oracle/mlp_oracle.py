@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
 benchmark's CPU-baseline leg, never by the product path.  It shares no code,
 constants or helpers with the HIP library.
 
-The encoder is this build's stand-in for the per-document simplex-constrained
+The encoder is this library's stand-in for the per-document simplex-constrained
 solve of the inference step (the package section's document-topic output,
 solved as in reading R8 of tlda_oracle): a multilayer perceptron maps a
 whitened document x (D values) to topic proportions on the simplex,

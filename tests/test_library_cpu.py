@@ -117,8 +117,8 @@ def test_header_compiles_as_c_and_cxx(tmp_path):
 
 
 def test_bench_runs_on_one_gpu_only():
-    """bench.py --gpus N with N > 1 exits at once with a message (this build
-    measures one GPU's share; the sharding is a design note)."""
+    """bench.py --gpus N with N > 1 exits at once with a message (the
+    benchmark measures one GPU's share; the sharding is a design note)."""
     import sys
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
