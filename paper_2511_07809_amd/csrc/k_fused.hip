@@ -528,7 +528,8 @@ __device__ __forceinline__ float doc_sum(float s) {
 // buffers; waves 12-15 (one per SIMD) run S = X_t Phi and R1 += X_t^T S^2
 // on the other buffer, each owning column tiles c and c + 4 of S and of R1
 // (one tile each when K pads to 64, two each at 128).  One barrier per tile
-// hands a buffer over.  In the 8-wave kernel a CU alternates between gathers
+// hands a buffer over.  Each block takes a contiguous run of the batch's
+// passes (RPB documents each), not of whole tiles.  In the 8-wave kernel a CU alternates between gathers
 // and matrix work and the two phases add up; here the matrix waves' work
 // runs beside the next tile's gathers.  What is left of the matrix phases' cost
 // is their issue slots on the whitening waves' SIMDs, so the whitening is
@@ -581,8 +582,15 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
     const int d = e / LDP, k = e % LDP;
     Ps[e] = (d < D && k < K) ? Phi[d * K + k] : 0.f;
   }
-  const int ntiles = (n_rows + T - 1) / T;
-  const int my_tiles = blockIdx.x < ntiles ? (ntiles - 1 - blockIdx.x) / nblk + 1 : 0;
+  // Work split: the batch in passes of RPB documents, each block a contiguous
+  // run of them.  At 262 144 documents on 256 blocks (112 x 112) that is 42
+  // or 43 passes per block, where whole 48-row tiles (two passes) dealt out
+  // one per block in turn gave 21 or 22.  With an odd count the block's last
+  // tile holds one pass of documents and one of empty rows.
+  const int n_pass_all = (n_rows + RPB - 1) / RPB;
+  const int pass0 = (int)((int64_t)blockIdx.x * n_pass_all / nblk);
+  const int my_pass = (int)((int64_t)(blockIdx.x + 1) * n_pass_all / nblk) - pass0;
+  const int my_tiles = (my_pass + PASSES - 1) / PASSES;
   __syncthreads();
 
   if (wave < NP) {
@@ -598,11 +606,9 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
     const uint32_t w_bytes = (tail_base + tail_base / (uint32_t)Dp * (uint32_t)Dt) * 4u;
     const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float*>(W32), (short)0, (int)w_bytes, 0x00020000);
-    const int n_pass = my_tiles * PASSES;
     auto doc_row = [&](int g) -> int {
-      if (g >= n_pass) return -1;
-      const int tile = blockIdx.x + (g / PASSES) * nblk;
-      const int row = tile * T + (g % PASSES) * RPB + wave * RPW + grp;
+      if (g >= my_pass) return -1;
+      const int row = (pass0 + g) * RPB + wave * RPW + grp;
       return row < n_rows ? row : -1;
     };
     auto load_rp = [&](int g, int& b, int& e) {
@@ -635,7 +641,7 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
     load_rp(1, b1, e1);
     int cc[EPL] = {};
     float cv[EPL] = {};
-    if (n_pass > 0) load_csr(b0, e0, cc, cv);
+    if (my_pass > 0) load_csr(b0, e0, cc, cv);
     int kept_total = 0;
     int g = 0;
     // step s: tile s into buffer s & 1 (the matrix waves meanwhile read
