@@ -388,17 +388,58 @@ __device__ __forceinline__ void cp_finish_block(
       f[t] = partial[(size_t)min(grp + t * FG, nblk - 1) * DK + ec];
   }
   // wave w: penalty of entries w, w + 16, ... of the block
-  for (int wi = wave; wi < FE; wi += kFinThreads / 64) {
-    const int me = blk * FE + wi;
-    if (me >= DK) break;
-    const int d = me / K, k = me % K;
-    double pen = 0.0;
-    if (gsq != nullptr) {
-      // gsq is symmetric bit for bit (the same products in the same chains),
-      // so row k is read: consecutive lanes, consecutive addresses
-      for (int j = lane; j < K; j += 64)
-        pen += (double)ph[d * K + j - base] * gsq[(size_t)k * K + j];
-    } else {
+  constexpr int kWaves = kFinThreads / 64;
+  constexpr int kEW = FE / kWaves;            // entries per wave
+  if (gsq != nullptr) {
+    // lane l of wave w adds Phi0[d][j] gsq[k][j] over j = l, l + 64, ...,
+    // for each of the wave's entries (d, k).  gsq is symmetric bit for bit
+    // (the same products in the same chains), so row k is read: consecutive
+    // lanes, consecutive addresses.  The loads of the first two 64-column
+    // chunks of all kEW entries are issued together (one round trip at
+    // K <= 128, where a loop over entries and columns waited for each load in
+    // turn), from clamped indexes.  A lane past K adds 0 x g, g a squared dot
+    // product (>= 0, finite for a finite Phi0): +0, which leaves the sum
+    // unchanged, so every sum takes its terms in the order j = l, l + 64, ...
+    // (only the Phi0 factor is selected: a select on g would let the compiler
+    // move its load under a lane condition, with a wait for it there).
+    double pen[kEW];
+    int drow[kEW], krow[kEW];
+#pragma unroll
+    for (int i = 0; i < kEW; ++i) {
+      const int me = min(blk * FE + wave + kWaves * i, DK - 1);
+      drow[i] = me / K;
+      krow[i] = me % K;
+      pen[i] = 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {             // K <= 256: four chunks of 64
+      if (t >= 2 && 64 * t >= K) break;
+      const int j = lane + 64 * t;
+      const int jc = min(j, K - 1);
+      double g[kEW];
+      float p[kEW];
+#pragma unroll
+      for (int i = 0; i < kEW; ++i) {
+        g[i] = gsq[(size_t)krow[i] * K + jc];
+        p[i] = ph[drow[i] * K + jc - base];
+      }
+#pragma unroll
+      for (int i = 0; i < kEW; ++i)
+        pen[i] = fma(j < K ? (double)p[i] : 0.0, g[i], pen[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kEW; ++i) {
+      double v = pen[i];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0 && blk * FE + wave + kWaves * i < DK) pen_s[wave + kWaves * i] = v;
+    }
+  } else {
+    // each wave forms the squared dot products it needs from Phi0 in LDS
+    for (int wi = wave; wi < FE; wi += kWaves) {
+      const int me = blk * FE + wi;
+      if (me >= DK) break;
+      const int d = me / K, k = me % K;
+      double pen = 0.0;
       for (int j = lane; j < K; j += 64) {
         // (Phi^T Phi)[j][k] in four independent chains
         double dot0 = 0.0, dot1 = 0.0, dot2 = 0.0, dot3 = 0.0;
@@ -417,9 +458,9 @@ __device__ __forceinline__ void cp_finish_block(
         const double dot = (dot0 + dot1) + (dot2 + dot3);
         pen += (double)ph[d * K + j] * (dot * dot);
       }
+      for (int off = 32; off > 0; off >>= 1) pen += __shfl_xor(pen, off, 64);
+      if (lane == 0) pen_s[wi] = pen;
     }
-    for (int off = 32; off > 0; off >>= 1) pen += __shfl_xor(pen, off, 64);
-    if (lane == 0) pen_s[wi] = pen;
   }
   double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
 #pragma unroll
@@ -496,8 +537,12 @@ __global__ void __launch_bounds__(1024) k_gram_sq(const float* __restrict__ Phi,
   if (in && c == 0) gsq[e] = acc * acc;
 }
 
+// Two blocks per CU (64 registers per lane) at 16 and 32 entries per block,
+// whose grids can exceed the CU count; one at 64 (D K / 64 <= 256 blocks, one
+// round), which leaves room for the penalty's squared-Gram loads of four
+// entries per wave in flight together.
 template <int FE>
-__global__ void __launch_bounds__(kFinThreads, 8) k_cp_finish(
+__global__ void __launch_bounds__(kFinThreads, FE == 64 ? 4 : 8) k_cp_finish(
     const float* __restrict__ partial, int nblk, const int* __restrict__ counts, int ncounts,
     int n_default, const float* __restrict__ Phi0, int D, int K, double alpha0, double theta,
     float beta, float* __restrict__ Phi, float* __restrict__ grad, double* __restrict__ R1,
