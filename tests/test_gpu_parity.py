@@ -399,6 +399,46 @@ def test_fused_step_matches_oracle(D, K):
     assert rel(Pd.cpu().numpy(), Phi0 - beta * g_ref) < REL32
 
 
+@pytest.mark.parametrize("D,K,n", [(100, 100, n) for n in (1, 23, 24, 25, 47, 48, 49, 73, 12288,
+                                                            12289, 12312, 12313, 24601)] +
+                         [(50, 50, n) for n in (1, 47, 48, 49, 12287, 12288, 12289, 24625)])
+def test_fused_step_at_work_split_boundaries(D, K, n):
+    """The hybrid kernel deals each of its blocks (min(ceil(n / 48), 256) of
+    them) a contiguous run of passes of 24 documents (D, K padded to 112) or
+    48 (padded to 64); a block whose run is odd ends on a tile holding one
+    pass of documents and one of empty rows.  Batch sizes at and around the
+    pass, tile and 256-tile boundaries (12 289 rows: one block with three
+    passes; 24 601: two blocks with five), each against the oracle."""
+    V = 400
+    rng = np.random.default_rng(n * 3 + D)
+    lens = rng.integers(0, 40, size=n)
+    lens[rng.random(n) < 0.05] = 2                    # dropped rows (L < 3)
+    rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    ci = np.concatenate([np.sort(rng.choice(V, size=int(l), replace=False)) for l in lens]
+                        + [np.zeros(0, dtype=np.int64)]).astype(np.int32)
+    va = rng.integers(1, 4, size=len(ci)).astype(np.float32)
+    Q, _ = np.linalg.qr(rng.standard_normal((V, D)))
+    W = Q * rng.uniform(5, 30, size=D)[None, :]
+    m = rng.dirichlet(np.ones(V))
+    a0, theta, beta = 1.5, 0.5, 2e-3
+    ctx = make_ctx(V, K, D, a0, theta)
+    tl.tlda_set_whitening(ctx, W, m)
+    Phi0 = (init_phi(D, K, 4) * 0.8).astype(np.float32)
+    Pd = torch.from_numpy(Phi0).cuda()
+    g = torch.empty_like(Pd)
+    nk = torch.empty(1, dtype=torch.int32, device="cuda")
+    tl.tlda_whiten_cp_step(ctx, dev_batch(rp, ci, va), beta, Pd, g, None, nk)
+    X_ref = O.whiten(rp, ci, va, V, m, W)
+    n_ref = O.batch_stats(rp, ci, va, V)["n_kept"]
+    assert int(nk.item()) == n_ref
+    if n_ref == 0:
+        assert torch.equal(Pd.cpu(), torch.from_numpy(Phi0))
+        return
+    g_ref = O.cp_gradient(X_ref, Phi0.astype(np.float64), n_ref, a0, theta)
+    assert rel(g.cpu().numpy(), g_ref) < REL32
+    assert rel(Pd.cpu().numpy(), Phi0 - beta * g_ref) < REL32
+
+
 @pytest.mark.parametrize("D,K,bf16", [(100, 100, False), (50, 50, False), (100, 100, True)])
 def test_fused_step_on_rows_without_words(D, K, bf16):
     """A batch whose rows are all empty (no nonzeros, no column or count
