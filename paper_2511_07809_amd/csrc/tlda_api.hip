@@ -590,7 +590,12 @@ void destroy_all(tlda_ctx* c) {
 extern "C" {
 
 const char* tlda_status_str(tlda_status s) {
-  switch (s) {
+  // a C caller may pass any int: its bits are read as one (loading a value
+  // outside the enumerators through the enum type is undefined in C++)
+  static_assert(sizeof(tlda_status) == sizeof(int), "tlda_status is an int");
+  int code;
+  std::memcpy(&code, &s, sizeof(code));
+  switch (code) {
     case TLDA_OK: return "ok";
     case TLDA_ERR_ARG: return "invalid argument";
     case TLDA_ERR_SHAPE: return "invalid shape";
