@@ -1,8 +1,9 @@
 // Host-layer checks of libtlda run under AddressSanitizer and
 // UndefinedBehaviorSanitizer (the library's host code is instrumented; device
 // code is not).  Covered: status strings, configuration checks of
-// tlda_create, argument checks of the batch, staging, step and checkpoint
-// calls, a short moments -> refresh -> step sequence through the staging
+// tlda_create, argument checks of the batch, staging, step, encoder, plan,
+// graph and checkpoint calls, the encoder's parameter round trip, a short
+// moments -> refresh -> step sequence through the staging
 // slots, and the checkpoint loader fed truncations of a valid checkpoint and
 // checkpoints with corrupted header fields.
 //
@@ -199,10 +200,62 @@ static void check_sequence(tlda_ctx* ctx, int V, int K, int D) {
   hipHostFree(hva);
 }
 
+// The encoder's host calls: shape checks, and a parameter round trip
+// through host buffers of exactly the parameter count.
+static void check_mlp(bool gpu) {
+  EXPECT(tlda_mlp_param_count(0, 32, 8) == 0);
+  tlda_mlp* m = reinterpret_cast<tlda_mlp*>(0x1);
+  EXPECT(tlda_mlp_create(16, 32, 8, 64, nullptr, nullptr) == TLDA_ERR_ARG);
+  EXPECT(tlda_mlp_create(0, 32, 8, 64, nullptr, &m) == TLDA_ERR_SHAPE);
+  EXPECT(m == nullptr);
+  EXPECT(tlda_mlp_create(16, TLDA_MLP_MAX_WIDTH + 1, 8, 64, nullptr, &m) == TLDA_ERR_SHAPE);
+  EXPECT(tlda_mlp_create(16, 32, TLDA_MAX_K + 1, 64, nullptr, &m) == TLDA_ERR_SHAPE);
+  EXPECT(tlda_mlp_create(16, 32, 8, 0, nullptr, &m) == TLDA_ERR_SHAPE);
+  if (!gpu) return;
+  EXPECT(tlda_mlp_create(16, 32, 8, 64, nullptr, &m) == TLDA_OK);
+  if (!m) return;
+  const int64_t np = tlda_mlp_param_count(16, 32, 8);
+  std::vector<float> p(np), q(np, -1.0f);
+  for (int64_t i = 0; i < np; ++i) p[i] = 0.001f * static_cast<float>(i % 997);
+  EXPECT(tlda_mlp_set_params(m, p.data()) == TLDA_OK);
+  EXPECT(tlda_mlp_get_params(m, q.data()) == TLDA_OK);
+  EXPECT(std::memcmp(p.data(), q.data(), np * sizeof(float)) == 0);
+  EXPECT(tlda_mlp_set_params(m, nullptr) != TLDA_OK);
+  EXPECT(tlda_mlp_forward(m, nullptr, 4, nullptr) != TLDA_OK);
+  EXPECT(std::strlen(tlda_mlp_last_error(m)) > 0);
+  tlda_mlp_destroy(m);
+  tlda_mlp_destroy(nullptr);
+}
+
+// Multi-slice plans and graph capture refuse malformed requests.
+static void check_plans(tlda_ctx* ctx) {
+  tlda_multi* plan = reinterpret_cast<tlda_multi*>(0x1);
+  EXPECT(tlda_multi_create(0, &ctx, nullptr, nullptr, nullptr, nullptr, &plan) == TLDA_ERR_ARG);
+  EXPECT(plan == nullptr);
+  tlda_csr_batch b;
+  std::memset(&b, 0, sizeof(b));
+  b.slot = -1;
+  float* phis[1] = {reinterpret_cast<float*>(0x100)};
+  const float betas[1] = {0.1f};
+  tlda_ctx* none[1] = {nullptr};
+  EXPECT(tlda_multi_create(1, none, &b, phis, betas, nullptr, &plan) == TLDA_ERR_ARG);
+  // an FP32 context is not a multi-slice shape (BF16 only)
+  EXPECT(tlda_multi_create(1, &ctx, &b, phis, betas, nullptr, &plan) != TLDA_OK);
+  EXPECT(plan == nullptr);
+  tlda_multi_destroy(nullptr);
+  tlda_graph* g = reinterpret_cast<tlda_graph*>(0x1);
+  EXPECT(tlda_graph_capture_steps(ctx, nullptr, 1, 0.1f, phis[0], &g) == TLDA_ERR_ARG);
+  EXPECT(g == nullptr);
+  EXPECT(tlda_graph_capture_steps(ctx, &b, 0, 0.1f, phis[0], &g) == TLDA_ERR_ARG);
+  EXPECT(tlda_graph_capture(nullptr, 1, &g) != TLDA_OK);
+  tlda_graph_destroy(nullptr);
+}
+
 int main(int argc, char** argv) {
   const bool gpu = argc > 1 && std::strcmp(argv[1], "gpu") == 0;
   check_status_strings();
   check_bad_configs();
+  check_mlp(gpu);
   const int V = 200, K = 8, D = 8;
   tlda_config c = base_config(V, K, D);
   tlda_ctx* ctx = nullptr;
@@ -215,6 +268,7 @@ int main(int argc, char** argv) {
     EXPECT(st == TLDA_OK);
     if (ctx) {
       check_bad_arguments(ctx);
+      check_plans(ctx);
       check_sequence(ctx, V, K, D);
       tlda_destroy(ctx);
     }
