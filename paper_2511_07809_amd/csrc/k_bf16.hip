@@ -143,9 +143,9 @@ struct Bf16Shape {
 // The work of one block: block `blk` of `nblk` blocks that share one batch,
 // in row tiles of TR documents (64 for the single-batch kernels; the
 // multi-slice kernels also take 32).  LDS comes from the caller (Xs: TR x LDA,
-// XsT: DQ x LDT, SsT: KQ x LDT BF16 values, wave_kept: NW ints, ent: 64 NW
-// entries), so one kernel can serve several shapes.
-template <int DQ, int KQ, int G, int MODE, int NW, int TR = kTile>
+// XsT: DQ x LDT, twice that with kDbl, SsT: KQ x LDT BF16 values, wave_kept:
+// NW ints, ent: 64 NW entries), so one kernel can serve several shapes.
+template <int DQ, int KQ, int G, int MODE, int NW, int TR = kTile, bool kDbl = false>
 __device__ __forceinline__ void cp_bf16_block(
     int blk, int nblk, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
     const float* __restrict__ val, int n_rows, const uint16_t* __restrict__ W16,
@@ -179,7 +179,7 @@ __device__ __forceinline__ void cp_bf16_block(
     for (int e = blk * kThreads + tid; e < D * K; e += nblk * kThreads)
       phi_copy[e] = Phi[e];
     for (int e = tid; e < TR * Sh::LDA; e += kThreads) Xs[e] = 0;
-    for (int e = tid; e < DQ * Sh::LDT; e += kThreads) XsT[e] = 0;
+    for (int e = tid; e < (kDbl ? 2 : 1) * DQ * Sh::LDT; e += kThreads) XsT[e] = 0;
   }
   // Phi fragments: bphi[q][ks] holds Phi[32 ks + 8 l4 + i][16 ct + l16], i = 0..7
   u32x4 bphi[Sh::ST][Sh::NKS];
@@ -210,8 +210,17 @@ __device__ __forceinline__ void cp_bf16_block(
   int kept_total = 0;
 
   const int ntiles = (n_rows + TR - 1) / TR;
-  for (int tile = blk; tile < ntiles; tile += nblk) {
-    if (kCp) __syncthreads();
+  // kDbl: two column-major tiles in turn, so a tile's rows can be written
+  // while other waves still read the previous tile's in the R1 phase (the
+  // row-major tile and S^2 are free by then: every wave has passed the
+  // barrier after the S phase, and the next S phase follows the barrier
+  // after the whitening); one barrier per tile fewer
+  if (kDbl) __syncthreads();
+  uint16_t* const XsT0 = XsT;
+  int parity = 0;
+  for (int tile = blk; tile < ntiles; tile += nblk, parity ^= 1) {
+    if (kCp && !kDbl) __syncthreads();
+    if (kDbl) XsT = XsT0 + parity * DQ * Sh::LDT;
     // ---- 1. rows of the tile ----
 #pragma unroll 1
     for (int pass = 0; pass < PASSES; ++pass) {
@@ -443,15 +452,18 @@ __global__ void __launch_bounds__(64 * (MODE == kWhitenOnly ? 4 : bf16_waves(DQ,
   constexpr bool kCp = MODE != kWhitenOnly;
   // 16-wave blocks (D and K past 64) take 128-document tiles: half the
   // barriers and matrix phases per document of 64-document tiles (118 against
-  // 125 us per streaming-scale batch), 104 KB of LDS at 128 x 128
+  // 125 us per streaming-scale batch), and two column-major tiles in turn
+  // (one barrier per tile fewer: 116.7 against 119.1 us); 144 KiB of LDS at
+  // 128 x 128
   constexpr int TRB = (kCp && NW == 16) ? 128 : kTile;
+  constexpr bool kDbl = kCp && NW == 16;
   typedef Bf16Shape<DQ, KQ, NW, TRB> Sh;
   __shared__ __attribute__((aligned(16))) uint16_t Xs[kCp ? TRB * Sh::LDA : 8];
-  __shared__ __attribute__((aligned(16))) uint16_t XsT[kCp ? DQ * Sh::LDT : 8];
+  __shared__ __attribute__((aligned(16))) uint16_t XsT[kCp ? (kDbl ? 2 : 1) * DQ * Sh::LDT : 8];
   __shared__ __attribute__((aligned(16))) uint16_t SsT[kCp ? KQ * Sh::LDT : 8];
   __shared__ int wave_kept[NW];
   __shared__ __attribute__((aligned(16))) int2 ent[G >= kNB ? 64 * NW : 2];
-  cp_bf16_block<DQ, KQ, G, MODE, NW, TRB>(blockIdx.x, nblk, row_ptr, col_idx, val, n_rows, W16, mw16, Dh,
+  cp_bf16_block<DQ, KQ, G, MODE, NW, TRB, kDbl>(blockIdx.x, nblk, row_ptr, col_idx, val, n_rows, W16, mw16, Dh,
                                  Xin, D, Phi, K, partial, block_counts, Xout, phi_copy, Xs, XsT,
                                  SsT, wave_kept, ent);
 }
