@@ -970,7 +970,9 @@ hipError_t launch_w32_tail(float* W32, int V, int D, int Dp, int Dt, uint32_t ta
   return hipGetLastError();
 }
 
-bool fused_forms_gram(int D, int K) { return fused_wide(D, K); }
+bool fused_forms_gram(int D, int K) {
+  return fused_wide(D, K) || (mfma_bucket(D) >= 64 && mfma_bucket(K) >= 64);
+}
 
 hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
                             int Dp, int Dt, uint32_t tail_base, const float* Phi, int K,

@@ -171,13 +171,17 @@ tlda_status ensure_x(tlda_ctx* c, size_t need) {
 // The finish of a step (gradient and update from the reduction's partials).
 // From kGramOnceDK entries of Phi on, the squared Gram entries of Phi0 are
 // formed once first rather than by every finish block.
-// gram_ready: the reduction kernel already formed the squared Gram entries.
+// gram_ready: the reduction kernel already formed the squared Gram entries
+// (also below kGramOnceDK: the FP32 hybrid kernel forms them at every shape
+// it serves, so that its finish reads them instead of forming a column of
+// Phi0^T Phi0 per entry from LDS; 62.0 against 64.2 us per tweet-shaped
+// step).
 tlda_status finish_step(tlda_ctx* c, const float* partial, int nblk, const int* counts,
                         int ncounts, int n_default, float beta, float* Phi, float* grad,
                         int* n_out, bool gram_ready = false) {
   const int D = c->cfg.D, K = c->cfg.K;
   const double* gsq = nullptr;
-  if (D * K >= tlda::kGramOnceDK) {
+  if (D * K >= tlda::kGramOnceDK || gram_ready) {
     if (!gram_ready) HIP_OK(c, tlda::launch_gram_sq(c->cp.phi0, D, K, c->cp.gsq, c->stream));
     gsq = c->cp.gsq;
   }
@@ -455,9 +459,11 @@ tlda_status fused_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float* 
     partial = c->cp.partial;
   }
   float* g = grad ? grad : c->cp.grad;
-  // the FP32 wide kernel forms the finish's squared Gram entries itself
+  // the FP32 wide and hybrid kernels form the finish's squared Gram entries
+  // themselves (the hybrid kernel also below kGramOnceDK entries)
   const bool gram_in_kernel =
-      !is_bf16(c) && D * K >= tlda::kGramOnceDK && tlda::fused_forms_gram(D, K);
+      !is_bf16(c) && tlda::fused_forms_gram(D, K) &&
+      (D * K >= tlda::kGramOnceDK || tlda::fused_tile_rows(D, K) == 48);
   st = begin_use(c, b);
   if (st != TLDA_OK) return st;
   HIP_OK(c, timing_start(c));

@@ -340,7 +340,8 @@ int fused_tile_rows(int D, int K);        // row tile of the fused kernel for th
 // Dt > 0: W32 also holds, from element tail_base on, a [V][Dt] copy of the
 // columns past the last whole 128-byte line of each row (w32_tail_cols).
 // gsq != nullptr: the kernel also forms the K x K squared Gram entries of
-// Phi for the finish (shapes where fused_forms_gram holds; others ignore it).
+// Phi for the finish (shapes where fused_forms_gram holds: the wide and the
+// hybrid kernels; others ignore it).
 hipError_t launch_whiten_cp(const tlda_csr_batch& b, const float* W32, const float* mw32, int D,
                             int Dp, int Dt, uint32_t tail_base, const float* Phi, int K,
                             int nblk, float* partial, int* block_counts, float* Xout,
