@@ -447,7 +447,8 @@ __global__ void __launch_bounds__(64 * (MODE == kWhitenOnly ? 4 : bf16_waves(DQ,
     const float* __restrict__ val, int n_rows, const uint16_t* __restrict__ W16,
     const float* __restrict__ mw16, int Dh, const float* __restrict__ Xin, int D,
     const float* __restrict__ Phi, int K, int nblk, float* __restrict__ partial,
-    int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy) {
+    int* __restrict__ block_counts, float* __restrict__ Xout, float* __restrict__ phi_copy,
+    double* __restrict__ gsq) {
   constexpr int NW = MODE == kWhitenOnly ? 4 : bf16_waves(DQ, KQ);
   constexpr bool kCp = MODE != kWhitenOnly;
   // 16-wave blocks (D and K past 64) take 128-document tiles: half the
@@ -466,6 +467,40 @@ __global__ void __launch_bounds__(64 * (MODE == kWhitenOnly ? 4 : bf16_waves(DQ,
   cp_bf16_block<DQ, KQ, G, MODE, NW, TRB, kDbl>(blockIdx.x, nblk, row_ptr, col_idx, val, n_rows, W16, mw16, Dh,
                                  Xin, D, Phi, K, partial, block_counts, Xout, phi_copy, Xs, XsT,
                                  SsT, wave_kept, ent);
+  // The fused step also forms the finish's squared Gram entries of Phi (still
+  // Phi0 here: the finish writes Phi after this kernel), with k_gram_sq's
+  // summation (four lanes per entry, chain c over d = 4m + c, chain 0 also
+  // the tail, added as (c0 + c1) + (c2 + c3)), so no launch of its own.
+  // 4 K^2 is a multiple of 4, so the four lanes of an entry leave the loop
+  // together.  The 16-wave blocks read Phi from an LDS copy in the space of
+  // the column-major tiles (free since the block's last barrier; 17 408
+  // floats >= D K), the others from global memory.
+  constexpr int kThr = 64 * NW;
+  if (MODE == kFused && gsq != nullptr && blockIdx.x * kThr < 4 * K * K) {
+    const float* P = Phi;
+    if constexpr (kDbl) {
+      static_assert(!kDbl || 2 * DQ * Sh::LDT / 2 >= TLDA_MAX_DK, "Phi fits the tiles' space");
+      float* Pf = reinterpret_cast<float*>(XsT);
+      for (int i = threadIdx.x; i < D * K; i += kThr) Pf[i] = Phi[i];
+      __syncthreads();
+      P = Pf;
+    }
+    for (int e4 = blockIdx.x * kThr + threadIdx.x; e4 < 4 * K * K; e4 += nblk * kThr) {
+      const int e = e4 >> 2, c = e4 & 3;
+      const int j = e / K, k = e % K;
+      double accg = 0.0;
+      const int M = D / 4;
+      for (int m = 0; m < M; ++m) {
+        const int i = 4 * m + c;
+        accg += (double)P[i * K + j] * (double)P[i * K + k];
+      }
+      if (c == 0)
+        for (int i = 4 * M; i < D; ++i) accg += (double)P[i * K + j] * (double)P[i * K + k];
+      accg += __shfl_xor(accg, 1, 64);
+      accg += __shfl_xor(accg, 2, 64);
+      if (c == 0) gsq[e] = accg * accg;
+    }
+  }
 }
 
 // Several batches (the slices of a batched run, each with its own
@@ -517,6 +552,7 @@ struct Bf16Args {
   int* block_counts;
   float* Xout;
   float* phi_copy;
+  double* gsq;
 };
 
 template <int DQ, int KQ, int G, int MODE>
@@ -530,7 +566,7 @@ hipError_t launch_t(const Bf16Args& a, int* per_cu, hipStream_t s) {
   const float* va = a.b ? a.b->val : nullptr;
   launch_main(k_cp_bf16<DQ, KQ, G, MODE>, dim3(a.nblk), dim3(kBlock), 0, s, rp, ci, va,
               a.n_rows, a.W16, a.mw16, a.Dh, a.Xin, a.D, a.Phi, a.K, a.nblk, a.partial,
-              a.block_counts, a.Xout, a.phi_copy);
+              a.block_counts, a.Xout, a.phi_copy, a.gsq);
   return hipGetLastError();
 }
 
@@ -650,16 +686,17 @@ int bf16_resident_blocks(int mode, int D, int K, int Dh, int num_cu) {
 
 hipError_t launch_whiten_cp_bf16(const tlda_csr_batch& b, const uint16_t* W16, const float* mw16,
                                  int Dh, int D, const float* Phi, int K, int nblk, float* partial,
-                                 int* block_counts, float* Xout, float* phi_copy, hipStream_t s) {
-  Bf16Args a{&b,   b.n_rows, W16,          mw16, Dh,  nullptr, D, Phi, K,
-             nblk, partial,  block_counts, Xout, phi_copy};
+                                 int* block_counts, float* Xout, float* phi_copy, double* gsq,
+                                 hipStream_t s) {
+  Bf16Args a{&b,   b.n_rows, W16,          mw16, Dh,       nullptr, D, Phi, K,
+             nblk, partial,  block_counts, Xout, phi_copy, gsq};
   return dispatch(kFused, a, nullptr, s);
 }
 
 hipError_t launch_cp_reduce_bf16(const float* X, int n_rows, const float* Phi, int D, int K,
                                  int nblk, float* partial, float* phi_copy, hipStream_t s) {
   Bf16Args a{nullptr, n_rows,  nullptr, nullptr, bf16_cols(D), X,       D,
-             Phi,     K,       nblk,    partial, nullptr,      nullptr, phi_copy};
+             Phi,     K,       nblk,    partial, nullptr,      nullptr, phi_copy, nullptr};
   return dispatch(kFromX, a, nullptr, s);
 }
 
@@ -667,7 +704,7 @@ hipError_t launch_whiten_bf16(const tlda_csr_batch& b, const uint16_t* W16, cons
                               int Dh, int D, int nblk, float* X, int* block_counts,
                               hipStream_t s) {
   Bf16Args a{&b,   b.n_rows, W16,          mw16, Dh,     nullptr, D, nullptr, 1,
-             nblk, nullptr,  block_counts, X,    nullptr};
+             nblk, nullptr,  block_counts, X,    nullptr, nullptr};
   return dispatch(kWhitenOnly, a, nullptr, s);
 }
 

@@ -321,10 +321,10 @@ __device__ __forceinline__ void cp_finish_block(
   // together (clamped indexes, unconditional) so that one memory round trip
   // serves up to kFinStage * kFinThreads entries.  With the squared Gram
   // entries given, the block needs only the rows of Phi0 its entries lie in
-  // (at most two: FE <= K, since D <= 256 makes K >= 16 from D K >= 4096 on and
-  // K >= 32 from D K >= 8192 on, where FE = 32, and FE = 64 only at K >= 64):
-  // ph then holds
-  // Phi0[base .. base + n_ph).
+  // (two at most where FE <= K: from D K >= 4096 on, where D <= 256 makes
+  // K >= 16, and always for the 32 and 64 entries per block; more at a small
+  // K, whose Gram entries the BF16 fused step also forms): ph then holds
+  // Phi0[base .. base + n_ph), n_ph <= FE + 2 K - 2 <= 574 <= D K.
   int cnt = 0;
   const bool have_counts = counts != nullptr && ncounts > 0;
   int c_first = 0;
@@ -334,7 +334,8 @@ __device__ __forceinline__ void cp_finish_block(
   const int base = rows_only ? e_first / K * K : 0;
   const int n_ph = rows_only ? (e_last / K + 1) * K - base : DK;
   if (rows_only) {
-    // one straight-line round: n_ph <= 2 K <= 512 < kFinThreads
+    // one straight-line round: n_ph < kFinThreads; a lane past n_ph stores
+    // into the pad after the copy (index n_ph + lane < D K + kFinPad)
     const float v = Phi0[base + min(tid, n_ph - 1)];
     if (have_counts) c_first = counts[min(tid, ncounts - 1)];
     ph[tid < n_ph ? tid : n_ph + lane] = v;

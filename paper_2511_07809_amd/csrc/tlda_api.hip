@@ -172,10 +172,10 @@ tlda_status ensure_x(tlda_ctx* c, size_t need) {
 // From kGramOnceDK entries of Phi on, the squared Gram entries of Phi0 are
 // formed once first rather than by every finish block.
 // gram_ready: the reduction kernel already formed the squared Gram entries
-// (also below kGramOnceDK: the FP32 hybrid kernel forms them at every shape
-// it serves, so that its finish reads them instead of forming a column of
-// Phi0^T Phi0 per entry from LDS; 62.0 against 64.2 us per tweet-shaped
-// step).
+// (also below kGramOnceDK: the BF16 fused kernel and the FP32 hybrid kernel
+// form them at every shape they serve, so that their finish reads them
+// instead of forming a column of Phi0^T Phi0 per entry from LDS; 62.0
+// against 64.2 us per tweet-shaped FP32 step).
 tlda_status finish_step(tlda_ctx* c, const float* partial, int nblk, const int* counts,
                         int ncounts, int n_default, float beta, float* Phi, float* grad,
                         int* n_out, bool gram_ready = false) {
@@ -459,18 +459,19 @@ tlda_status fused_step(tlda_ctx* c, const tlda_csr_batch* b, float beta, float* 
     partial = c->cp.partial;
   }
   float* g = grad ? grad : c->cp.grad;
-  // the FP32 wide and hybrid kernels form the finish's squared Gram entries
-  // themselves (the hybrid kernel also below kGramOnceDK entries)
+  // the BF16 kernel and the FP32 wide and hybrid kernels form the finish's
+  // squared Gram entries themselves (the BF16 and hybrid kernels also below
+  // kGramOnceDK entries)
   const bool gram_in_kernel =
-      !is_bf16(c) && tlda::fused_forms_gram(D, K) &&
-      (D * K >= tlda::kGramOnceDK || tlda::fused_tile_rows(D, K) == 48);
+      is_bf16(c) || (tlda::fused_forms_gram(D, K) &&
+                     (D * K >= tlda::kGramOnceDK || tlda::fused_tile_rows(D, K) == 48));
   st = begin_use(c, b);
   if (st != TLDA_OK) return st;
   HIP_OK(c, timing_start(c));
   if (is_bf16(c))
     HIP_OK(c, tlda::launch_whiten_cp_bf16(*b, c->wh.W16, c->wh.mw16, c->Dh, D, Phi, K, nblk,
                                           partial, c->block_counts, X_out, c->cp.phi0,
-                                          c->stream));
+                                          c->cp.gsq, c->stream));
   else
     HIP_OK(c, tlda::launch_whiten_cp(*b, c->wh.W32, c->wh.mw32, D, c->Dp, c->Dt, w32_tail_base(c),
                                      Phi, K, nblk, partial, c->block_counts, X_out, c->cp.phi0,

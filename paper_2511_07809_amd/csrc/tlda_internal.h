@@ -377,9 +377,12 @@ hipError_t launch_form_w16(const double* W, const double* m, int V, int D, int D
                            float* mw16, hipStream_t s);
 // resident blocks of one round on the device; mode 0 fused, 1 from X, 2 whitening only
 int bf16_resident_blocks(int mode, int D, int K, int Dh, int num_cu);
+// gsq != nullptr: the kernel also forms the K x K squared Gram entries of
+// Phi for the finish, as k_gram_sq does.
 hipError_t launch_whiten_cp_bf16(const tlda_csr_batch& b, const uint16_t* W16, const float* mw16,
                                  int Dh, int D, const float* Phi, int K, int nblk, float* partial,
-                                 int* block_counts, float* Xout, float* phi_copy, hipStream_t s);
+                                 int* block_counts, float* Xout, float* phi_copy, double* gsq,
+                                 hipStream_t s);
 hipError_t launch_cp_reduce_bf16(const float* X, int n_rows, const float* Phi, int D, int K,
                                  int nblk, float* partial, float* phi_copy, hipStream_t s);
 hipError_t launch_whiten_bf16(const tlda_csr_batch& b, const uint16_t* W16, const float* mw16,
