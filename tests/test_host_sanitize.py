@@ -29,7 +29,18 @@ def _run(mode):
 
 def test_host_layer_under_sanitizers_without_device():
     """Status strings (any int), configuration checks and a context request
-    that fails cleanly without a device (on a GPU host it succeeds)."""
+    that fails cleanly without a device (on a GPU host it succeeds).  Builds
+    the driver first if it is missing (on the CPU, like the library test)."""
+    if not os.path.exists(EXE):
+        import importlib.util
+
+        from paper_2511_07809_amd.build import build as lib_build
+        lib_build()
+        spec = importlib.util.spec_from_file_location(
+            "host_sanitize_build", os.path.join(HERE, "host_sanitize", "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build()
     _run("cpu")
 
 
