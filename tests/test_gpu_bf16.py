@@ -166,8 +166,12 @@ def test_bf16_cp_step_full_batch_shapes(n, D, K, V, a0):
 # fused whitening + CP step
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("D,K", [(5, 5), (10, 7), (20, 20), (33, 40), (50, 50), (64, 64),
-                                 (100, 100), (128, 96), (128, 128), (8, 100), (100, 8)])
+                                 (100, 100), (128, 96), (128, 128), (8, 100), (100, 8),
+                                 (1, 1), (7, 1), (16, 3), (33, 2)])
 def test_bf16_fused_step_matches_rounded_oracle(D, K):
+    """The fused BF16 step (which also forms the finish's squared Gram
+    entries) against the oracle on the rounded operands.  At K < 16 a finish
+    block's 16 entries span several rows of Phi (up to 16 at K = 1)."""
     V = 400
     rp, ci, va = _rows(V, 1500, seed=D * 7 + K)
     W, m = _whitening(V, D, seed=D * 7 + K + 1)
