@@ -796,10 +796,18 @@ __global__ void __launch_bounds__(1024, 1) k_whiten_cp_hyb(
       }
     }
   }
-  // the squared Gram entries of the finish, as in the wide kernel
+  // the squared Gram entries of the finish, as in the wide kernel, dealt
+  // first to the blocks with the shorter run of passes (they finish a pass
+  // earlier): block b has run floor((b+1) P / n) - floor(b P / n) of the P
+  // passes, floor(P / n) + 1 for the floor(b P / n) - b floor(P / n) longer
+  // runs before it
   __syncthreads();
   if (gsq != nullptr) {
-    for (int e4 = blockIdx.x * kThreads + tid; e4 < 4 * K * K; e4 += nblk * kThreads) {
+    const int q = n_pass_all / nblk;
+    const int n_short = nblk - (n_pass_all - q * nblk);
+    const int long_before = pass0 - (int)blockIdx.x * q;
+    const int slot = my_pass == q ? (int)blockIdx.x - long_before : n_short + long_before;
+    for (int e4 = slot * kThreads + tid; e4 < 4 * K * K; e4 += nblk * kThreads) {
       const int e = e4 >> 2, c = e4 & 3;
       const int j = e / K, k = e % K;
       double accg = 0.0;
