@@ -548,8 +548,8 @@ __device__ __forceinline__ float doc_sum(float s) {
 // rows in the order the S accumulators hold them.  The per-row arithmetic
 // (the nonzeros of a row in CSR order, one FMA each) is the 8-wave kernel's;
 // L, a sum of the row's counts, is added in another order, which changes
-// nothing for integer counts.  Registers: 90 to 109 per lane, no spills
-// (102 at 112 x 112, 90 at 64 x 64, 109 at 128 x 128); LDS 54 KB at 64 x 64,
+// nothing for integer counts.  Registers: 84 to 111 per lane, no spills
+// (101 at 112 x 112, 88 at 64 x 64, 108 to 111 at 128 x 128); LDS 54 KB at 64 x 64,
 // 99 KB at 112 x 112, 121 KB at 128 x 128.  The buffer descriptor needs the
 // W32 copy below 4 GiB and V below 2^24 (a 24-bit multiply); the launchers
 // check both.
